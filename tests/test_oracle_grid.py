@@ -1,0 +1,219 @@
+"""Grid-level pins of the oracle: the isotropic gradient (Eq. 20), normal and
+curvature (Eqs. 16-17), correction term (Eq. 65), conservation, and the
+physics the paper fixes (Laplace's law, the layered Poiseuille profile of
+Eqs. 69-70, the shear viscosity of Eq. 22)."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as WL
+
+CS2 = 1.0 / 3.0
+
+
+def params_of(box: WL.Box, **kw) -> O.Params:
+    d = dict(nx=box.nx, ny=box.ny, nz=box.nz, rho0_r=box.rho0_r, rho0_b=box.rho0_b,
+             alpha_r=box.alpha_r, alpha_b=box.alpha_b, nu_r=box.nu_r, nu_b=box.nu_b,
+             sigma=box.sigma, beta=box.beta, walls=box.walls, body_force=box.body_force,
+             omega=(1.0, 1.0, box.omega_bulk) + (1.0,) * 8)
+    d.update(kw)
+    return O.Params(**d)
+
+
+def test_gradient_is_exact_for_quadratic_fields():
+    P = O.Params(nx=11, ny=9, nz=7, rho0_r=1, rho0_b=1, alpha_r=8 / 27, alpha_b=8 / 27,
+                 nu_r=0.1, nu_b=0.1, sigma=0, beta=0)
+    z, y, x = np.meshgrid(np.arange(7.), np.arange(9.), np.arange(11.), indexing="ij")
+    chi = 0.3 + 0.2 * x - 0.7 * y + 0.05 * z + 0.01 * x * x - 0.02 * x * y + 0.03 * y * z + 0.015 * z * z
+    g = O.gradient(P, chi)
+    exp = [0.2 + 0.02 * x - 0.02 * y, -0.7 - 0.02 * x + 0.03 * z, 0.05 + 0.03 * y + 0.03 * z]
+    inner = (slice(1, -1), slice(1, -1), slice(1, -1))
+    for a in range(3):
+        np.testing.assert_allclose(g[a][inner], exp[a][inner], atol=1e-13)
+
+
+def test_gradient_wall_rule_uses_centre_value():
+    """Neighbours in solid layers take the centre value: a field varying only
+    along y gives, next to the wall, the one-sided smoothed difference."""
+    P = O.Params(nx=4, ny=8, nz=4, rho0_r=1, rho0_b=1, alpha_r=8 / 27, alpha_b=8 / 27,
+                 nu_r=0.1, nu_b=0.1, sigma=0, beta=0, walls=1)
+    chi = np.broadcast_to(np.arange(8.0)[None, :, None] ** 2, (4, 8, 4)).copy()
+    g = O.gradient(P, chi)
+    # at y = 1 the y-neighbour at y = 0 is solid -> replaced by chi(1) = 1:
+    # d/dy = (1/cs2) * sum_w(c_y=+1) * (chi(2) - chi(1)) = 3 * (1/6) * (4 - 1)
+    assert g[1][:, 1, :] == pytest.approx(np.full((4, 4), 0.5 * 3.0))
+    assert np.all(g[:, :, 0, :] == 0) and np.all(g[:, :, 7, :] == 0)
+
+
+def _tanh_field(shape, kind, R, W=2.0):
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    cx, cy, cz = (nx - 1) / 2, (ny - 1) / 2, (nz - 1) / 2
+    if kind == "sphere":
+        r = np.sqrt((x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2)
+    elif kind == "cylinder":
+        r = np.sqrt((x - cx) ** 2 + (y - cy) ** 2)
+    else:
+        r = np.abs(z - cz) + R
+    return np.tanh((R - r) / W), r
+
+
+def _curvature_at_interface(kind, R, n=48):
+    """Drive the oracle's field computation with a prescribed phase field."""
+    phi, r = _tanh_field((n, n, n), kind, R)
+    P = O.Params(nx=n, ny=n, nz=n, rho0_r=1.0, rho0_b=1.0, alpha_r=8 / 27, alpha_b=8 / 27,
+                 nu_r=0.1, nu_b=0.1, sigma=1.0, beta=0.7)
+    rho_r = (1 + phi) / 2
+    rho_b = (1 - phi) / 2
+    f = O.init(P, rho_r, rho_b, np.zeros((3, n, n, n)))
+    F = O.fields(P, f)
+    assert np.allclose(F["phi"], phi, atol=1e-13)
+    band = np.abs(r - R) < 0.75
+    return F["kappa"][band].mean(), F
+
+
+@pytest.mark.parametrize("kind,R,expect", [("sphere", 12.0, 2.0 / 12.0),
+                                           ("cylinder", 12.0, 1.0 / 12.0),
+                                           ("plane", 12.0, 0.0)])
+def test_curvature_of_simple_shapes(kind, R, expect):
+    k, F = _curvature_at_interface(kind, R)
+    if expect == 0.0:
+        assert abs(k) < 1e-12
+    else:
+        assert k == pytest.approx(expect, rel=0.03)
+    # the normal points from blue into red (towards +phi)
+    assert np.all(np.abs(np.sqrt(F["nx"] ** 2 + F["ny"] ** 2 + F["nz"] ** 2) - 1.0)[
+        np.abs(F["phi"]) < 0.9] < 1e-12)
+
+
+def test_sphere_curvature_converges_with_radius():
+    errs = []
+    for R in (6.0, 12.0):
+        k, _ = _curvature_at_interface("sphere", R)
+        errs.append(abs(k - 2.0 / R) / (2.0 / R))
+    assert errs[1] < errs[0]
+
+
+def _droplet(box_kw, n=16, R=4.0, u=(0.0, 0.0, 0.0), seed=11, amp=1e-4):
+    box = WL.two_phase_box((n, n, n), **box_kw)
+    c = ((n - 1) / 2.0,) * 3
+    rr, rb, uu = WL.droplet_fields(box, [c], [R], u_carrier=u)
+    P = params_of(box)
+    return P, O.init(P, rr, rb, uu, seed=seed, amp=amp)
+
+
+def test_correction_term_vanishes_at_unit_density_ratio():
+    P, f = _droplet(dict(gamma=1.0, rho_drop=1.0, tau=0.8, sigma=0.01, beta=0.7),
+                    u=(0.03, -0.01, 0.02))
+    O.step(P, f, 3)
+    F = O.fields(P, f)
+    # p - rho c_s^2 vanishes in exact arithmetic; what remains is the rounding
+    # of xi (1 - 8/27) against 1/3
+    for a in "xyz":
+        assert np.abs(F["Q" + a]).max() < 1e-16
+
+
+def test_correction_term_nonzero_with_density_ratio():
+    P, f = _droplet(dict(gamma=10.0, rho_drop=1.0, tau=0.8, sigma=0.01, beta=0.7),
+                    u=(0.03, 0.0, 0.0))
+    O.step(P, f, 2)
+    F = O.fields(P, f)
+    assert np.abs(F["Qx"]).max() > 1e-6
+
+
+@pytest.mark.parametrize("gamma,u", [(1.0, (0.02, 0.01, 0.0)), (10.0, (0.02, 0.01, 0.0)),
+                                     (100.0, (0.0, 0.0, 0.0))])
+def test_per_colour_mass_is_conserved(gamma, u):
+    """Collision keeps rho (k*_000 = rho), recolouring keeps each rho_k and
+    streaming permutes: per-colour mass is invariant up to rounding."""
+    P, f = _droplet(dict(gamma=gamma, rho_drop=1.0, tau=0.7, sigma=0.01, beta=0.7),
+                    u=u, amp=1e-5)
+    m0 = f.sum(axis=(1, 2, 3, 4))
+    O.step(P, f, 20)
+    m1 = f.sum(axis=(1, 2, 3, 4))
+    assert np.all(np.abs(m1 - m0) / m0 < 1e-13)
+
+
+def test_uniform_equilibrium_is_a_fixed_point_of_a_step():
+    n = 6
+    box = WL.two_phase_box((n, n, n), 10.0, 1.0, 0.7, 0.01, 0.7)
+    P = params_of(box)
+    rr = np.full((n, n, n), 1.0)
+    rb = np.zeros((n, n, n))
+    u = np.zeros((3, n, n, n))
+    u[0] = 0.04
+    u[2] = -0.02
+    f = O.init(P, rr, rb, u)
+    f0 = f.copy()
+    O.step(P, f, 3)
+    np.testing.assert_allclose(f, f0, atol=1e-15)
+
+
+def test_laplace_law_static_droplet():
+    """3D Laplace law dp = 2 sigma / R_eff (the 3D form of Eq. 68) for the
+    32^3 static droplet after 200 steps, within 10 %."""
+    w = WL.static_droplet()
+    P = params_of(w.box)
+    f = O.init(P, w.rho_r, w.rho_b, w.u)
+    m0 = f.sum(axis=(1, 2, 3, 4))
+    O.step(P, f, 200)
+    F = O.fields(P, f)
+    V = ((1 + F["phi"]) / 2).sum()
+    Reff = (3 * V / (4 * np.pi)) ** (1 / 3)
+    d = WL.periodic_distance((w.box.nx, w.box.ny, w.box.nz), w.centres[0])
+    dp = F["p"][d < Reff - 3].mean() - F["p"][d > Reff + 5].mean()
+    assert dp == pytest.approx(2 * w.box.sigma / Reff, rel=0.10)
+    m1 = f.sum(axis=(1, 2, 3, 4))
+    assert np.all(np.abs(m1 - m0) / m0 < 1e-13)
+
+
+def _layered(case, model, steps, a=12, b=24, nu=0.1):
+    w, M = WL.layered_channel(case, a=a, b=b, nu=nu)
+    box = w.box
+    P = params_of(box, model=model, use_q=int(model >= O.MODEL_C))
+    f = O.init(P, w.rho_r, w.rho_b, w.u)
+    O.step(P, f, steps)
+    F = O.fields(P, f)
+    ux = F["ux"][0, :, 0]
+    y = np.arange(box.ny) - (box.ny - 1) / 2.0
+    G = box.body_force[0]
+    d2 = ux[2:] - 2 * ux[1:-1] + ux[:-2]
+    yy = y[1:-1]
+    red = np.abs(yy) < a - 4
+    blue = (np.abs(yy) > a + 4) & (np.abs(yy) < b - 2)
+    mu_r, mu_b = box.nu_r * box.rho0_r, box.nu_b * box.rho0_b
+    return d2[red].mean() / (-G / mu_r), d2[blue].mean() / (-G / mu_b)
+
+
+@pytest.mark.parametrize("case,steps,tol_r,tol_b", [("A", 30000, 0.05, 0.02),
+                                                     ("B", 60000, 0.02, 0.10)])
+def test_layered_poiseuille_pure_layer_curvature(case, steps, tol_r, tol_b):
+    """Eqs. (69)-(70): inside each pure layer u_x'' = 2 A_k = -G/mu_k exactly.
+    Model D (with Q) reproduces it; Model A (standard equilibrium) does not."""
+    r, b = _layered(case, O.MODEL_D, steps)
+    assert r == pytest.approx(1.0, abs=tol_r)
+    assert b == pytest.approx(1.0, abs=tol_b)
+    ra, ba = _layered(case, O.MODEL_A, steps // 3)
+    assert max(abs(ra - 1.0), abs(ba - 1.0)) > 0.3
+
+
+def test_shear_wave_viscosity():
+    """Single-phase shear wave: amplitude decays as exp(-nu k^2 t) with
+    nu = (1/omega_1 - 1/2) c_s^2 from Eq. (22) in a pure phase."""
+    n = 32
+    nu = 0.05
+    box = WL.Box(nx=4, ny=n, nz=4, rho0_r=1.0, rho0_b=1.0, alpha_r=8 / 27, alpha_b=8 / 27,
+                 nu_r=nu, nu_b=nu, sigma=0.0, beta=0.7)
+    P = params_of(box)
+    y = np.arange(n)
+    u = np.zeros((3, 4, n, 4))
+    U = 1e-3
+    u[0] = U * np.sin(2 * np.pi * y / n)[None, :, None]
+    f = O.init(P, np.ones((4, n, 4)), np.zeros((4, n, 4)), u)
+    t = 400
+    O.step(P, f, t)
+    F = O.fields(P, f)
+    amp = (F["ux"][0, :, 0] * np.sin(2 * np.pi * y / n)).sum() * 2 / n
+    k = 2 * np.pi / n
+    nu_meas = -np.log(amp / U) / (k * k * t)
+    assert nu_meas == pytest.approx(nu, rel=0.01)

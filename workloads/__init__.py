@@ -1,0 +1,277 @@
+"""Seeded synthetic workloads for the colour-gradient LBM hot path.
+
+This module builds *inputs only*: parameter sets expressed in the paper's
+physical terms (reference densities, rest fractions alpha_k, kinematic
+viscosities, sigma, beta, relaxation rates) and initial colour-density and
+velocity fields (spheres of red fluid in blue fluid, uniform or sheared
+carrier velocity).  It holds none of the method's update arithmetic and is
+shared by the tests and the benchmark; the HIP path and the CPU oracle each
+receive the same arrays and parameters.
+
+Parameter conventions (readings of the paper where it leaves a choice):
+  * the lighter phase takes alpha = 8/27, so its squared sound speed is 1/3
+    (the bubble-rise set-up of Sec. IV uses this choice);
+  * the heavier phase of density ratio g takes alpha = 1 - (19/27)/g, which
+    makes the two ideal-gas pressures equal (Eq. 13 with xi = 9/19);
+  * a relaxation time tau prescribed for a pure phase k sets its kinematic
+    viscosity to (tau - 1/2) * xi * (1 - alpha_k) (Eq. 22 in a pure phase);
+  * droplets are sharp: red density rho_r^0 where |x - x_c| <= R (periodic
+    distance), blue density rho_b^0 elsewhere.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+XI = 9.0 / 19.0
+ALPHA_LIGHT = 8.0 / 27.0
+
+
+def alpha_heavy(gamma: float) -> float:
+    """Rest fraction of the heavier phase for density ratio gamma >= 1."""
+    return 1.0 - (19.0 / 27.0) / gamma
+
+
+def sound2(alpha: float) -> float:
+    return XI * (1.0 - alpha)
+
+
+@dataclasses.dataclass
+class Box:
+    """One periodic (or walled) box and its physical parameters."""
+    nx: int
+    ny: int
+    nz: int
+    rho0_r: float
+    rho0_b: float
+    alpha_r: float
+    alpha_b: float
+    nu_r: float
+    nu_b: float
+    sigma: float
+    beta: float
+    omega_bulk: float = 1.0
+    body_force: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    walls: int = 0
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    @property
+    def nodes(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def fluid_nodes(self) -> int:
+        ny = self.ny - 2 if (self.walls & 1) else self.ny
+        nz = self.nz - 2 if (self.walls & 2) else self.nz
+        return self.nx * ny * nz
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    box: Box
+    rho_r: np.ndarray      # float32 [nz, ny, nx]
+    rho_b: np.ndarray      # float32 [nz, ny, nx]
+    u: np.ndarray          # float32 [3, nz, ny, nx]
+    seed: int = 0
+    noise: float = 0.0
+    steps: int = 0
+    centres: Optional[List[Tuple[float, float, float]]] = None
+    radii: Optional[List[float]] = None
+
+
+def two_phase_box(n: Sequence[int], gamma: float, rho_drop: float, tau: float,
+                  sigma: float, beta: float, *, drop_is_heavy: bool = True,
+                  visc_ratio_kin: Optional[float] = None, walls: int = 0,
+                  omega_bulk: float = 1.0) -> Box:
+    """Box with red droplet phase of density rho_drop and density ratio gamma.
+
+    If ``visc_ratio_kin`` is None, tau is applied to both pure phases (equal
+    dynamic viscosities); otherwise nu_r = tau-derived value of the red phase
+    and nu_b = nu_r / visc_ratio_kin.
+    """
+    if gamma == 1.0:
+        a_r = a_b = ALPHA_LIGHT
+        rho_b = rho_drop
+    elif drop_is_heavy:
+        a_r, a_b = alpha_heavy(gamma), ALPHA_LIGHT
+        rho_b = rho_drop / gamma
+    else:
+        a_r, a_b = ALPHA_LIGHT, alpha_heavy(gamma)
+        rho_b = rho_drop * gamma
+    nu_r = (tau - 0.5) * sound2(a_r)
+    nu_b = (tau - 0.5) * sound2(a_b) if visc_ratio_kin is None else nu_r / visc_ratio_kin
+    return Box(nx=n[0], ny=n[1], nz=n[2], rho0_r=rho_drop, rho0_b=rho_b, alpha_r=a_r,
+               alpha_b=a_b, nu_r=nu_r, nu_b=nu_b, sigma=sigma, beta=beta,
+               omega_bulk=omega_bulk, walls=walls)
+
+
+def periodic_distance(shape_xyz, centre, walls=0):
+    """Distance of every node to ``centre`` with periodic wrap on open axes."""
+    nx, ny, nz = shape_xyz
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    d = []
+    for coord, c, n, periodic in ((x, centre[0], nx, True), (y, centre[1], ny, not (walls & 1)),
+                                   (z, centre[2], nz, not (walls & 2))):
+        dd = np.abs(coord - c)
+        if periodic:
+            dd = np.minimum(dd, n - dd)
+        d.append(dd)
+    return np.sqrt(d[0] ** 2 + d[1] ** 2 + d[2] ** 2)
+
+
+def droplet_fields(box: Box, centres, radii, u_drop=None, u_carrier=None):
+    """Sharp droplets of red fluid in blue fluid; returns float32 arrays."""
+    red = np.zeros(box.shape, dtype=bool)
+    for c, r in zip(centres, radii):
+        red |= periodic_distance((box.nx, box.ny, box.nz), c, box.walls) <= r
+    rho_r = np.where(red, box.rho0_r, 0.0).astype(np.float32)
+    rho_b = np.where(red, 0.0, box.rho0_b).astype(np.float32)
+    u = np.zeros((3,) + box.shape, dtype=np.float32)
+    if u_carrier is not None:
+        u[:] = np.asarray(u_carrier, dtype=np.float32).reshape(3, 1, 1, 1)
+    if u_drop is not None:
+        for c, r, ud in zip(centres, radii, u_drop):
+            m = periodic_distance((box.nx, box.ny, box.nz), c, box.walls) <= r
+            for a in range(3):
+                u[a][m] = ud[a]
+    return rho_r, rho_b, u
+
+
+# ---------------------------------------------------------------------------
+# The five benchmark workloads and their reduced parity versions
+# ---------------------------------------------------------------------------
+
+def static_droplet(n: int = 32, R: float = 8.0, sigma: float = 0.01, tau: float = 1.0,
+                   beta: float = 0.7, steps: int = 200) -> Workload:
+    """Static droplet, density ratio 1, viscosity ratio 1 (Laplace-law case)."""
+    box = two_phase_box((n, n, n), 1.0, 1.0, tau, sigma, beta)
+    c = ((n - 1) / 2.0,) * 3
+    rr, rb, u = droplet_fields(box, [c], [R])
+    return Workload("static_droplet_%d" % n, box, rr, rb, u, steps=steps, centres=[c], radii=[R])
+
+
+def translating_droplet(n: int = 256, R: float = 32.0, U: float = 0.05, gamma: float = 10.0,
+                        omega_shear: float = 1.6, sigma: float = 0.005, beta: float = 0.7,
+                        noise: float = 1e-6, seed: int = 2, steps: int = 5000) -> Workload:
+    """Droplet translating with a uniform velocity U along x (Galilean case).
+
+    Density ratio gamma (droplet heavier), equal dynamic viscosities, shear
+    rate omega_shear in both pure phases, bulk rate 1."""
+    tau = 1.0 / omega_shear
+    box = two_phase_box((n, n, n), gamma, 1.0, tau, sigma, beta)
+    c = ((n - 1) / 2.0,) * 3
+    rr, rb, u = droplet_fields(box, [c], [R], u_carrier=(U, 0.0, 0.0))
+    return Workload("translating_droplet_%d" % n, box, rr, rb, u, seed=seed, noise=noise,
+                    steps=steps, centres=[c], radii=[R])
+
+
+def place_droplets(n: int, count: int, rmin: float, rmax: float, gap: float, seed: int):
+    """Rejection-sample non-overlapping droplets in a periodic cube."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    centres, radii = [], []
+    tries = 0
+    while len(centres) < count:
+        tries += 1
+        if tries > 100000:
+            raise RuntimeError("could not place droplets")
+        r = rng.uniform(rmin, rmax)
+        c = rng.uniform(0, n, size=3)
+        ok = True
+        for c2, r2 in zip(centres, radii):
+            d = np.abs(c - np.asarray(c2))
+            d = np.minimum(d, n - d)
+            if np.sqrt((d ** 2).sum()) < r + r2 + gap:
+                ok = False
+                break
+        if ok:
+            centres.append(tuple(float(v) for v in c))
+            radii.append(float(r))
+    return centres, radii
+
+
+def sheared_droplets(n: int = 512, count: int = 8, rmin: float = 20.0, rmax: float = 48.0,
+                     gamma: float = 1000.0, U: float = 0.04, Re: float = 1000.0,
+                     visc_ratio_dyn: float = 10.0, sigma: float = 0.005, beta: float = 0.2,
+                     seed: int = 3, steps: int = 2000) -> Workload:
+    """Several heavy droplets in a light carrier with a sinusoidal shear."""
+    rho_r0, rho_b0 = 1.0, 1.0 / gamma
+    nu_b = U * n / Re
+    nu_r = visc_ratio_dyn * rho_b0 * nu_b / rho_r0
+    box = Box(nx=n, ny=n, nz=n, rho0_r=rho_r0, rho0_b=rho_b0, alpha_r=alpha_heavy(gamma),
+              alpha_b=ALPHA_LIGHT, nu_r=nu_r, nu_b=nu_b, sigma=sigma, beta=beta)
+    centres, radii = place_droplets(n, count, rmin, rmax, 4.0, seed)
+    rr, rb, u = droplet_fields(box, centres, radii)
+    y = np.arange(n, dtype=np.float64)
+    ux = U * np.sin(2.0 * np.pi * y / n)
+    carrier = (rb > 0)
+    u[0] = np.where(carrier, ux[None, :, None], 0.0).astype(np.float32)
+    return Workload("sheared_droplets_%d" % n, box, rr, rb, u, seed=seed, steps=steps,
+                    centres=centres, radii=radii)
+
+
+def batched_boxes(count: int = 96, lmin: int = 24, lmax: int = 128, seed: int = 4,
+                  steps: int = 1000) -> List[Workload]:
+    """Independent periodic boxes of uneven size and parameters."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for b in range(count):
+        L = rng.integers(lmin, lmax + 1, size=3)
+        gamma = float(rng.choice([1.0, 10.0, 100.0]))
+        sigma = float(rng.uniform(0.001, 0.02))
+        tau = float(rng.uniform(0.55, 1.2))
+        box = two_phase_box((int(L[0]), int(L[1]), int(L[2])), gamma, 1.0, tau, sigma, 0.7)
+        R = 0.25 * float(L.min())
+        c = tuple((float(v) - 1) / 2.0 for v in L)
+        rr, rb, u = droplet_fields(box, [c], [R])
+        out.append(Workload("box%02d" % b, box, rr, rb, u, seed=seed, steps=steps,
+                            centres=[c], radii=[R]))
+    return out
+
+
+def head_on_collision(nx: int = 768, ny: int = 384, nz: int = 384, R: float = 48.0,
+                      U: float = 0.05, gamma: float = 10.0, Re: float = 5000.0,
+                      We: float = 50.0, beta: float = 0.7, steps: int = 3000) -> Workload:
+    """Two droplets moving toward each other between bounce-back walls."""
+    rho_r0 = 1.0
+    nu_r = 2 * U * (2 * R) / Re
+    sigma = rho_r0 * (2 * U) ** 2 * (2 * R) / We
+    box = Box(nx=nx, ny=ny, nz=nz, rho0_r=rho_r0, rho0_b=rho_r0 / gamma,
+              alpha_r=alpha_heavy(gamma), alpha_b=ALPHA_LIGHT, nu_r=nu_r, nu_b=nu_r,
+              sigma=sigma, beta=beta, walls=3)
+    cy, cz = (ny - 1) / 2.0, (nz - 1) / 2.0
+    cs = [(nx / 2.0 - 2 * R, cy, cz), (nx / 2.0 + 2 * R, cy, cz)]
+    rr, rb, u = droplet_fields(box, cs, [R, R], u_drop=[(U, 0, 0), (-U, 0, 0)])
+    return Workload("head_on_collision", box, rr, rb, u, steps=steps, centres=cs, radii=[R, R])
+
+
+def layered_channel(case: str, a: int = 8, b: int = 16, nu: float = 0.02,
+                    G: float = 1.5e-8, sigma: float = 0.002 / 4.5, beta: float = 0.7):
+    """Layered two-phase channel flow between no-slip walls (Table III cases).
+
+    Red occupies |y| <= a, blue a < |y| <= b; walls at |y| = b (bounce-back
+    solid layers at y = 0 and y = 2b + 1).  The kinematic viscosities follow
+    from the dynamic ratio M of Table III with the given nu for blue."""
+    table = {"A": (0.1, 0.8, 0.9, 1.0 / 8.0),
+             "B": (0.8, 0.1, 0.2, 8.0),
+             "C": (0.008, 8.0, 0.9992, 1.0 / 40.0)}
+    rho_r0, rho_b0, alpha_b, M = table[case]
+    gamma = rho_r0 / rho_b0
+    alpha_r = 1.0 - (1.0 - alpha_b) / gamma
+    nu_b = nu
+    nu_r = M * rho_b0 * nu_b / rho_r0
+    ny = 2 * b + 2
+    box = Box(nx=1, ny=ny, nz=1, rho0_r=rho_r0, rho0_b=rho_b0, alpha_r=alpha_r, alpha_b=alpha_b,
+              nu_r=nu_r, nu_b=nu_b, sigma=sigma, beta=beta, body_force=(G, 0.0, 0.0), walls=1)
+    y = np.arange(ny) - (ny - 1) / 2.0
+    red = (np.abs(y) <= a)[None, :, None]
+    rho_r = np.where(red, rho_r0, 0.0).astype(np.float32) * np.ones(box.shape, np.float32)
+    rho_b = np.where(red, 0.0, rho_b0).astype(np.float32) * np.ones(box.shape, np.float32)
+    u = np.zeros((3,) + box.shape, dtype=np.float32)
+    return Workload("layered_%s" % case, box, rho_r, rho_b, u, centres=None, radii=None), M
+
