@@ -1,0 +1,165 @@
+/*
+ * cglbm.h -- C ABI of the MI355X (gfx950) hot path of the two-colour D3Q27
+ * colour-gradient lattice Boltzmann model with generalized equilibria
+ * (Saito, Takada, Baba, Someya, Ito, arXiv:2309.07801).
+ *
+ * One time step, per fluid node x (Sec. II, Sec. III.D-E):
+ *   1. pull-streaming of the red and blue populations, f^k_i(x,t) =
+ *      f^{k*}_i(x - c_i, t-1) (Eq. 5), full-way bounce-back at solid layers;
+ *   2. colour densities, momentum, ideal-gas pressure and order parameter
+ *      (Eqs. 10-14);
+ *   3. isotropic gradient stencil (Eq. 20) of the order parameter, unit
+ *      normal (Eq. 17), curvature (Eq. 16), CSF force (Eq. 15) and the
+ *      correction term Q (Eq. 65);
+ *   4. central-moment MRT collision of the total distribution with the
+ *      velocity-independent generalized equilibrium moments (Eqs. 57-63,
+ *      Eqs. 25 and 66-67), relaxation from the interpolated viscosity
+ *      (Eqs. 21-22);
+ *   5. recolouring (Eqs. 18-19).
+ *
+ * Conventions
+ *   - Velocities are ordered as the columns of the matrix of Eq. (1).
+ *   - Node index inside a box: x + nx*(y + ny*z); x fastest.  Boxes are
+ *     concatenated; box b starts at node offset cglbm_box_offset(h, b).
+ *   - The state at time t is the pre-collision distribution f(x,t).  The
+ *     library stores the post-collision distribution of step t-1 at x, so
+ *     that a pull reproduces f(x,t).
+ *   - All device pointers are caller-owned device memory (for instance torch
+ *     tensors).  The library never frees caller memory; it owns only the
+ *     handle, small parameter tables, a reduction scratch area and captured
+ *     graphs.
+ *   - `stream` is a hipStream_t passed as void*.  Every call enqueues its work
+ *     on that stream and returns without synchronizing, except where stated.
+ *   - Return codes: CGLBM_OK (0) or a negative CGLBM_E* code; a message for
+ *     the last failure on the calling thread is given by cglbm_last_error().
+ *     No exception crosses the ABI.
+ */
+#ifndef CGLBM_H
+#define CGLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CGLBM_OK 0
+#define CGLBM_EINVAL (-1)      /* bad sizes or parameters                     */
+#define CGLBM_EHIP (-2)        /* a HIP runtime call failed                   */
+#define CGLBM_EUNSUPPORTED (-3)/* valid by the paper, not built here          */
+#define CGLBM_EUNSTABLE (-4)   /* non-finite values found in the state        */
+#define CGLBM_ESTATE (-5)      /* call out of order / bad handle              */
+
+/* Per-colour parameters: reference density rho_k^0 (Eq. 14), rest fraction
+ * alpha_k with squared sound speed xi (1 - alpha_k), xi = 9/19 (Eq. 13), and
+ * kinematic viscosity nu_k (Eq. 21). */
+typedef struct {
+  double rho0;
+  double alpha;
+  double nu;
+} cglbm_phase;
+
+/* One box.  walls: bit0 = solid node layers at y = 0 and y = ny-1, bit1 =
+ * solid layers at z = 0 and z = nz-1 (full-way bounce-back); other axes are
+ * periodic.  sigma: interfacial tension of the CSF force (Eq. 15); beta:
+ * recolouring parameter (Eq. 19); omega_bulk: omega_2 of Eq. (25);
+ * omega_hi: omega_0 and omega_3..omega_10 of Eq. (25) -- only 1.0 is built
+ * (the choice of the paper, Sec. III.E), anything else gives
+ * CGLBM_EUNSUPPORTED; body_force: constant force density added to the CSF
+ * force. */
+typedef struct {
+  int32_t nx, ny, nz;
+  uint32_t walls;
+  cglbm_phase red, blue;
+  double sigma, beta;
+  double omega_bulk;
+  double omega_hi[9];
+  double body_force[3];
+} cglbm_box_params;
+
+/* Population storage formats.  Arithmetic is FP32 in all cases. */
+typedef enum {
+  CGLBM_FP32 = 0,       /* populations stored as float                        */
+  CGLBM_FP16_SHIFT = 1, /* half, stored as f - (colour fraction) * w_i-shift  */
+  CGLBM_BF16_SHIFT = 2  /* bfloat16, same shift                              */
+} cglbm_storage;
+
+typedef struct cglbm_handle cglbm_handle;
+
+/* Bytes the caller must provide: pop_bytes for EACH of the two population
+ * buffers, aux_bytes for the auxiliary field buffer.  Pure host computation;
+ * validates the parameters.  Returns CGLBM_EINVAL on bad parameters. */
+int cglbm_query_sizes(int32_t n_boxes, const cglbm_box_params *boxes, int32_t storage,
+                      size_t *pop_bytes, size_t *aux_bytes, int64_t *total_nodes);
+
+/* Create a handle and write the initial state.
+ * pop_a, pop_b: two device buffers of pop_bytes each; pop_b must not be NULL
+ *   (the in-place single-buffer layout is not built: CGLBM_EUNSUPPORTED).
+ * aux: device buffer of aux_bytes.
+ * init_rho_r, init_rho_b: device float arrays of total_nodes values (all
+ *   boxes concatenated as described above; values in alignment gaps are
+ *   ignored); init_u: device float array [3][total_nodes].  Each node gets
+ *   f^k = (rho_k/rho) (f^eq(rho, p, u) + eta), with the Model D equilibrium of
+ *   Eq. (56) (built from its central moments, Eqs. 57-63) and eta a
+ *   SplitMix64 counter noise of amplitude noise_amp (0 disables it).
+ *   rho = rho_r + rho_b must be > 0 everywhere (not checked on the device).
+ * The handle is returned in *out.  Enqueued on stream; the caller keeps all
+ * buffers alive until cglbm_destroy. */
+int cglbm_init(cglbm_handle **out, int32_t n_boxes, const cglbm_box_params *boxes,
+               int32_t storage, void *pop_a, void *pop_b, void *aux, const float *init_rho_r,
+               const float *init_rho_b, const float *init_u, uint64_t noise_seed,
+               double noise_amp, void *stream);
+
+/* Advance every box by n_steps time steps (steps 1-5 above).  Asynchronous. */
+int cglbm_step(cglbm_handle *h, int32_t n_steps, void *stream);
+
+/* Fields of the current state of box `box` into out_dev (device float,
+ * [count][nodes_of_box]) in the order of the set bits of field_mask:
+ *   bit 0 rho_r, 1 rho_b, 2 phi, 3 p, 4 ux, 5 uy, 6 uz (u includes F/2, Eq. 11),
+ *   bit 7 nx, 8 ny, 9 nz (Eq. 17), 10 kappa (Eq. 16), 11 Fx, 12 Fy, 13 Fz
+ *   (Eq. 15 plus body force), 14 Qx, 15 Qy, 16 Qz (Eq. 65).
+ * Solid nodes report zeros for the interface fields.  Asynchronous. */
+int cglbm_moments(cglbm_handle *h, int32_t box, uint32_t field_mask, float *out_dev,
+                  void *stream);
+
+/* Per-box diagnostics in FP64, deterministic (fixed summation order that
+ * depends only on the box).  centre: per box 3 doubles (droplet centre used
+ * for the Laplace measurement and the periodic centroid) or NULL (box
+ * centre).  out: per box CGLBM_NDIAG doubles:
+ *   0 M_r, 1 M_b (sums of rho_k over fluid nodes), 2-4 momentum sum rho*u,
+ *   5 p_in (mean p where |x-c| < R_eff-3), 6 p_out (mean p where
+ *   |x-c| > R_eff+5, periodic distance), 7 R_eff = (3V/4pi)^(1/3) with
+ *   V = sum (1+phi)/2, 8-10 red centroid relative to c, 11 kinetic energy
+ *   sum rho u^2/2, 12 count of non-finite populations.
+ * out_is_host != 0: out is host memory and the call synchronizes the stream;
+ * returns CGLBM_EUNSTABLE if any count of non-finite values is nonzero.
+ * Otherwise out is device memory and the call is asynchronous. */
+#define CGLBM_NDIAG 13
+int cglbm_reduce(cglbm_handle *h, const double *centre, double *out, int32_t out_is_host,
+                 void *stream);
+
+/* Node offset of box b in the concatenated arrays, or -1. */
+int64_t cglbm_box_offset(const cglbm_handle *h, int32_t box);
+
+/* Per-kernel timing with HIP events recorded on the caller's stream around
+ * every launch of the step.  begin: reserve room for max_launches launches;
+ * end: synchronize the events and return, per kernel kind
+ * (0 pull/moments, 1 interface, 2 collide), the total milliseconds and the
+ * number of launches timed.  Kinds beyond n_kinds are not reported. */
+int cglbm_profile_begin(cglbm_handle *h, int32_t max_launches);
+int cglbm_profile_end(cglbm_handle *h, double *total_ms, int64_t *launches, int32_t n_kinds);
+
+/* Release the handle and library-owned memory (never caller buffers). */
+void cglbm_destroy(cglbm_handle *h);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *cglbm_last_error(void);
+
+/* Library version string. */
+const char *cglbm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CGLBM_H */

@@ -110,8 +110,10 @@ def lib():
         L.orc_gradient.argtypes = [P, dp, dp]
         L.orc_fields.argtypes = [P, dp, dp]
         L.orc_init.argtypes = [P, dp, dp, dp, C.c_uint64, C.c_double, C.c_int32, dp]
+        L.orc_init_window.argtypes = [P, dp, dp, dp, C.c_uint64, C.c_double, C.c_int32,
+                                      C.POINTER(C.c_int32), C.POINTER(C.c_int32), dp]
         L.orc_step.argtypes = [P, dp, C.c_int32]
-        for fn in ("orc_gradient", "orc_fields", "orc_init", "orc_step"):
+        for fn in ("orc_gradient", "orc_fields", "orc_init", "orc_init_window", "orc_step"):
             getattr(L, fn).restype = C.c_int
         _lib = L
     return _lib
@@ -249,6 +251,24 @@ def init(P: Params, rho_r, rho_b, u, seed=0, amp=0.0, box=0) -> np.ndarray:
                         box, _dp(f))
     if rc != 0:
         raise ValueError("orc_init: non-positive total density")
+    return f
+
+
+def init_window(P: Params, rho_r, rho_b, u, global_dims, offset, seed=0, amp=0.0,
+                box=0) -> np.ndarray:
+    """Initial state of a window of a larger periodic box (noise keyed by the
+    larger box's node index).  global_dims, offset: (x, y, z)."""
+    rho_r = np.ascontiguousarray(rho_r, dtype=np.float64).reshape(P.shape)
+    rho_b = np.ascontiguousarray(rho_b, dtype=np.float64).reshape(P.shape)
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape((3,) + P.shape)
+    f = np.zeros((2, NQ) + P.shape)
+    cp = P.c()
+    gd = (C.c_int32 * 3)(*[int(v) for v in global_dims])
+    go = (C.c_int32 * 3)(*[int(v) for v in offset])
+    rc = lib().orc_init_window(C.byref(cp), _dp(rho_r), _dp(rho_b), _dp(u), C.c_uint64(seed),
+                               amp, box, gd, go, _dp(f))
+    if rc != 0:
+        raise ValueError("orc_init_window: non-positive total density")
     return f
 
 

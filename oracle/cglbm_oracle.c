@@ -708,6 +708,17 @@ int orc_step(const orc_params *P, double *f, int32_t nsteps) {
  * rho_k / rho so that pure phases stay pure. */
 int orc_init(const orc_params *P, const double *rho_r, const double *rho_b, const double *u,
              uint64_t seed, double amp, int32_t box, double *f) {
+  const int32_t dims[3] = {P->nx, P->ny, P->nz};
+  const int32_t zero[3] = {0, 0, 0};
+  return orc_init_window(P, rho_r, rho_b, u, seed, amp, box, dims, zero, f);
+}
+
+/* As orc_init for a window of a larger periodic box: node (x, y, z) of the
+ * window is node ((x+ox) mod Nx, (y+oy) mod Ny, (z+oz) mod Nz) of the larger
+ * box, whose index keys the noise. */
+int orc_init_window(const orc_params *P, const double *rho_r, const double *rho_b,
+                    const double *u, uint64_t seed, double amp, int32_t box,
+                    const int32_t *gdims, const int32_t *goff, double *f) {
   const int64_t N = (int64_t)P->nx * P->ny * P->nz;
   const double cs2r = orc_sound_speed2(P->alpha_r), cs2b = orc_sound_speed2(P->alpha_b);
   int bad = 0;
@@ -722,8 +733,12 @@ int orc_init(const orc_params *P, const double *rho_r, const double *rho_b, cons
     double uu[3] = {u[c], u[N + c], u[2 * N + c]};
     double feq[NQ];
     orc_feq(P->model, rho, p, uu, feq);
+    const int64_t x = c % P->nx, y = (c / P->nx) % P->ny, z = c / ((int64_t)P->nx * P->ny);
+    const int64_t gnode = (int64_t)wrap((int)(x + goff[0]), gdims[0]) +
+                          (int64_t)gdims[0] * ((int64_t)wrap((int)(y + goff[1]), gdims[1]) +
+                                               (int64_t)gdims[1] * wrap((int)(z + goff[2]), gdims[2]));
     for (int i = 0; i < NQ; ++i) {
-      double ft = feq[i] + (amp != 0.0 ? orc_noise(seed, box, c, i, amp) : 0.0);
+      double ft = feq[i] + (amp != 0.0 ? orc_noise(seed, box, gnode, i, amp) : 0.0);
       f[(int64_t)i * N + c] = rho_r[c] / rho * ft;
       f[(int64_t)(NQ + i) * N + c] = rho_b[c] / rho * ft;
     }

@@ -68,6 +68,9 @@ int orc_fields(const orc_params *P, const double *f, double *out);
 int orc_init(const orc_params *P, const double *rho_r, const double *rho_b,
              const double *u /* [3][N] */, uint64_t seed, double amp, int32_t box,
              double *f);
+int orc_init_window(const orc_params *P, const double *rho_r, const double *rho_b,
+                    const double *u, uint64_t seed, double amp, int32_t box,
+                    const int32_t *gdims, const int32_t *goff, double *f);
 int orc_step(const orc_params *P, double *f, int32_t nsteps);
 int orc_is_solid(const orc_params *P, int32_t x, int32_t y, int32_t z);
 

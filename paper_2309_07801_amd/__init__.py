@@ -1,0 +1,237 @@
+"""Python binding of the gfx950 colour-gradient LBM library (libcglbm.so).
+
+Argument marshalling only: every step of the time update runs in the HIP
+kernels behind the C ABI of ``include/cglbm.h``.  PyTorch provides device
+memory and the stream.  There is no fallback: if the library is missing or
+no GPU is present, the calls raise.
+
+Layout of the concatenated node arrays: box b occupies nodes
+``[offset(b), offset(b) + nx*ny*nz)`` with x fastest; gaps between boxes are
+ignored by the library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcglbm.so")
+
+CGLBM_OK = 0
+ERRORS = {-1: "CGLBM_EINVAL", -2: "CGLBM_EHIP", -3: "CGLBM_EUNSUPPORTED",
+          -4: "CGLBM_EUNSTABLE", -5: "CGLBM_ESTATE"}
+FP32, FP16_SHIFT, BF16_SHIFT = 0, 1, 2
+NDIAG = 13
+DIAG_NAMES = ("M_r", "M_b", "Px", "Py", "Pz", "p_in", "p_out", "R_eff", "cx", "cy", "cz",
+              "KE", "n_nonfinite")
+FIELDS = ("rho_r", "rho_b", "phi", "p", "ux", "uy", "uz", "nx", "ny", "nz", "kappa",
+          "Fx", "Fy", "Fz", "Qx", "Qy", "Qz")
+KERNEL_KINDS = ("pull", "interface", "collide")
+
+EXPORTED = ("cglbm_query_sizes", "cglbm_init", "cglbm_step", "cglbm_moments", "cglbm_reduce",
+            "cglbm_box_offset", "cglbm_profile_begin", "cglbm_profile_end", "cglbm_destroy",
+            "cglbm_last_error", "cglbm_version")
+
+
+class CglbmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s: %s" % (ERRORS.get(code, str(code)), msg))
+        self.code = code
+
+
+class Phase(C.Structure):
+    _fields_ = [("rho0", C.c_double), ("alpha", C.c_double), ("nu", C.c_double)]
+
+
+class BoxParams(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("walls", C.c_uint32),
+                ("red", Phase), ("blue", Phase), ("sigma", C.c_double), ("beta", C.c_double),
+                ("omega_bulk", C.c_double), ("omega_hi", C.c_double * 9),
+                ("body_force", C.c_double * 3)]
+
+
+def box_params(nx, ny, nz, rho0_r, rho0_b, alpha_r, alpha_b, nu_r, nu_b, sigma, beta,
+               omega_bulk=1.0, body_force=(0.0, 0.0, 0.0), walls=0, omega_hi=(1.0,) * 9):
+    p = BoxParams()
+    p.nx, p.ny, p.nz, p.walls = int(nx), int(ny), int(nz), int(walls)
+    p.red = Phase(float(rho0_r), float(alpha_r), float(nu_r))
+    p.blue = Phase(float(rho0_b), float(alpha_b), float(nu_b))
+    p.sigma, p.beta, p.omega_bulk = float(sigma), float(beta), float(omega_bulk)
+    p.omega_hi = (C.c_double * 9)(*[float(v) for v in omega_hi])
+    p.body_force = (C.c_double * 3)(*[float(v) for v in body_force])
+    return p
+
+
+def box_params_of(box) -> BoxParams:
+    """BoxParams from any object with the attributes of a box description."""
+    return box_params(box.nx, box.ny, box.nz, box.rho0_r, box.rho0_b, box.alpha_r, box.alpha_b,
+                      box.nu_r, box.nu_b, box.sigma, box.beta, getattr(box, "omega_bulk", 1.0),
+                      getattr(box, "body_force", (0.0, 0.0, 0.0)), getattr(box, "walls", 0))
+
+
+_lib = None
+
+
+def lib():
+    """Load libcglbm.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libcglbm.so is not built; run __graft_entry__.build() "
+                              "or python paper_2309_07801_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, u32 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32
+        BP = C.POINTER(BoxParams)
+        L.cglbm_query_sizes.argtypes = [i32, BP, i32, C.POINTER(C.c_size_t),
+                                        C.POINTER(C.c_size_t), C.POINTER(i64)]
+        L.cglbm_init.argtypes = [C.POINTER(vp), i32, BP, i32, vp, vp, vp, vp, vp, vp,
+                                 C.c_uint64, C.c_double, vp]
+        L.cglbm_step.argtypes = [vp, i32, vp]
+        L.cglbm_moments.argtypes = [vp, i32, u32, vp, vp]
+        L.cglbm_reduce.argtypes = [vp, C.POINTER(C.c_double), vp, i32, vp]
+        L.cglbm_box_offset.argtypes = [vp, i32]
+        L.cglbm_box_offset.restype = i64
+        L.cglbm_profile_begin.argtypes = [vp, i32]
+        L.cglbm_profile_end.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64), i32]
+        L.cglbm_destroy.argtypes = [vp]
+        L.cglbm_destroy.restype = None
+        L.cglbm_last_error.restype = C.c_char_p
+        L.cglbm_version.restype = C.c_char_p
+        for fn in ("cglbm_query_sizes", "cglbm_init", "cglbm_step", "cglbm_moments",
+                   "cglbm_reduce", "cglbm_profile_begin", "cglbm_profile_end"):
+            getattr(L, fn).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != CGLBM_OK:
+        raise CglbmError(rc, lib().cglbm_last_error().decode())
+
+
+def query_sizes(params: Sequence[BoxParams], storage: int = FP32):
+    arr = (BoxParams * len(params))(*params)
+    pop, aux, tot = C.c_size_t(), C.c_size_t(), C.c_int64()
+    _check(lib().cglbm_query_sizes(len(params), arr, storage, C.byref(pop), C.byref(aux),
+                                   C.byref(tot)))
+    return pop.value, aux.value, tot.value
+
+
+def _stream_ptr(stream) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+class Simulation:
+    """A batch of independent boxes advanced together on one GPU.
+
+    rho_r, rho_b: per-box float arrays of shape (nz, ny, nx); u: per-box
+    (3, nz, ny, nx).  They are packed into the concatenated layout and copied
+    to the device once for the initialisation.
+    """
+
+    def __init__(self, params: Sequence[BoxParams], rho_r: List[np.ndarray],
+                 rho_b: List[np.ndarray], u: List[np.ndarray], seed: int = 0,
+                 noise: float = 0.0, storage: int = FP32, device: int = 0, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the colour-gradient LBM library needs an MI355X")
+        self.params = list(params)
+        self.nboxes = len(self.params)
+        self.storage = storage
+        self.device = torch.device("cuda", device)
+        pop_bytes, aux_bytes, total = query_sizes(self.params, storage)
+        self.total = total
+        self.stream = stream
+        dev = self.device
+        self.pop_a = torch.empty(pop_bytes, dtype=torch.uint8, device=dev)
+        self.pop_b = torch.empty(pop_bytes, dtype=torch.uint8, device=dev)
+        self.aux = torch.empty(aux_bytes, dtype=torch.uint8, device=dev)
+        self.offsets = self._offsets_host()
+        rr = self.pack([np.asarray(a, np.float32) for a in rho_r])
+        rb = self.pack([np.asarray(a, np.float32) for a in rho_b])
+        uu = np.zeros((3, total), np.float32)
+        for a in range(3):
+            uu[a] = self.pack([np.asarray(x, np.float32)[a] for x in u])
+        self._init_rr = torch.from_numpy(rr).to(dev)
+        self._init_rb = torch.from_numpy(rb).to(dev)
+        self._init_u = torch.from_numpy(uu).to(dev)
+        arr = (BoxParams * self.nboxes)(*self.params)
+        h = C.c_void_p()
+        _check(lib().cglbm_init(C.byref(h), self.nboxes, arr, storage, self.pop_a.data_ptr(),
+                                self.pop_b.data_ptr(), self.aux.data_ptr(),
+                                self._init_rr.data_ptr(), self._init_rb.data_ptr(),
+                                self._init_u.data_ptr(), C.c_uint64(seed), float(noise),
+                                _stream_ptr(stream)))
+        self.h = h
+        self.steps_done = 0
+
+    def _offsets_host(self):
+        off, out = 0, []
+        for p in self.params:
+            out.append(off)
+            n = p.nx * p.ny * p.nz
+            off = (off + n + 63) // 64 * 64
+        return out
+
+    def pack(self, arrays: List[np.ndarray]) -> np.ndarray:
+        out = np.zeros(self.total, np.float32)
+        for b, a in enumerate(arrays):
+            p = self.params[b]
+            n = p.nx * p.ny * p.nz
+            out[self.offsets[b]:self.offsets[b] + n] = np.asarray(a, np.float32).reshape(n)
+        return out
+
+    def box_offset(self, b: int) -> int:
+        return int(lib().cglbm_box_offset(self.h, b))
+
+    def step(self, n: int = 1):
+        _check(lib().cglbm_step(self.h, int(n), _stream_ptr(self.stream)))
+        self.steps_done += n
+
+    def moments(self, box: int = 0, fields: Sequence[str] = FIELDS):
+        import torch
+        mask = 0
+        for f in fields:
+            mask |= 1 << FIELDS.index(f)
+        names = [f for f in FIELDS if mask & (1 << FIELDS.index(f))]
+        p = self.params[box]
+        out = torch.empty((len(names), p.nz, p.ny, p.nx), dtype=torch.float32, device=self.device)
+        _check(lib().cglbm_moments(self.h, box, mask, out.data_ptr(), _stream_ptr(self.stream)))
+        return {n: out[k] for k, n in enumerate(names)}
+
+    def reduce(self, centres: Optional[Sequence[Sequence[float]]] = None) -> np.ndarray:
+        out = np.zeros((self.nboxes, NDIAG), np.float64)
+        cptr = None
+        if centres is not None:
+            c = np.ascontiguousarray(np.asarray(centres, np.float64).reshape(self.nboxes, 3))
+            cptr = c.ctypes.data_as(C.POINTER(C.c_double))
+        rc = lib().cglbm_reduce(self.h, cptr, out.ctypes.data, 1, _stream_ptr(self.stream))
+        if rc not in (CGLBM_OK, -4):
+            _check(rc)
+        self.last_reduce_unstable = (rc == -4)
+        return out
+
+    def profile_begin(self, max_launches: int):
+        _check(lib().cglbm_profile_begin(self.h, int(max_launches)))
+
+    def profile_end(self):
+        ms = (C.c_double * 3)()
+        cnt = (C.c_int64 * 3)()
+        _check(lib().cglbm_profile_end(self.h, ms, cnt, 3))
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNEL_KINDS)}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().cglbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

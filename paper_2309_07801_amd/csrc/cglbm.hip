@@ -1,0 +1,453 @@
+// cglbm.hip -- host side of the C ABI declared in include/cglbm.h.
+//
+// Parameter validation, layout of the concatenated boxes, block and tile
+// tables, launches on the caller's stream, FP64 diagnostics and per-kernel
+// event timing.  All kernels live in kernels.hpp.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/cglbm.h"
+#include "kernels.hpp"
+
+using namespace cglbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(CGLBM_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),    \
+                  __FILE__, __LINE__);                                                  \
+  } while (0)
+
+constexpr int kTX = 8, kTY = 8, kTZ = 8;   // interface tile
+constexpr int64_t kAlign = 64;             // node alignment of each box's base
+constexpr double kXi = 9.0 / 19.0;
+
+enum { KIND_PULL = 0, KIND_IFACE = 1, KIND_COLLIDE = 2, KIND_N = 3 };
+
+struct Layout {
+  std::vector<BoxDev> boxes;
+  std::vector<int32_t> blk_box, tile_box;
+  int64_t total = 0;  // plane length (nodes, all boxes, aligned)
+  int32_t nblk = 0, ntile = 0;
+};
+
+int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+int validate(int32_t n_boxes, const cglbm_box_params *boxes, int32_t storage) {
+  if (n_boxes <= 0 || !boxes) return fail(CGLBM_EINVAL, "n_boxes must be > 0 and boxes non-NULL");
+  if (storage != CGLBM_FP32)
+    return fail(CGLBM_EUNSUPPORTED, "storage %d is not built (only CGLBM_FP32)", storage);
+  for (int b = 0; b < n_boxes; ++b) {
+    const cglbm_box_params &P = boxes[b];
+    if (P.nx < 1 || P.ny < 1 || P.nz < 1)
+      return fail(CGLBM_EINVAL, "box %d: extents must be >= 1", b);
+    if ((int64_t)P.nx * P.ny * P.nz >= (1ll << 31))
+      return fail(CGLBM_EINVAL, "box %d: more than 2^31-1 nodes", b);
+    if (P.walls & ~3u) return fail(CGLBM_EINVAL, "box %d: unknown wall bits 0x%x", b, P.walls);
+    if ((P.walls & 1u) && P.ny < 3) return fail(CGLBM_EINVAL, "box %d: y walls need ny >= 3", b);
+    if ((P.walls & 2u) && P.nz < 3) return fail(CGLBM_EINVAL, "box %d: z walls need nz >= 3", b);
+    const cglbm_phase *ph[2] = {&P.red, &P.blue};
+    for (int c = 0; c < 2; ++c) {
+      if (!(ph[c]->rho0 > 0.0) || !std::isfinite(ph[c]->rho0))
+        return fail(CGLBM_EINVAL, "box %d: rho0 of colour %d must be > 0", b, c);
+      if (!(ph[c]->alpha >= 0.0 && ph[c]->alpha < 1.0))
+        return fail(CGLBM_EINVAL, "box %d: alpha of colour %d must lie in [0, 1)", b, c);
+      if (!(ph[c]->nu >= 0.0) || !std::isfinite(ph[c]->nu))
+        return fail(CGLBM_EINVAL, "box %d: nu of colour %d must be >= 0", b, c);
+    }
+    if (!std::isfinite(P.sigma) || P.sigma < 0.0)
+      return fail(CGLBM_EINVAL, "box %d: sigma must be finite and >= 0", b);
+    if (!std::isfinite(P.beta) || P.beta < 0.0)
+      return fail(CGLBM_EINVAL, "box %d: beta must be finite and >= 0", b);
+    if (!(P.omega_bulk > 0.0 && P.omega_bulk < 2.0))
+      return fail(CGLBM_EINVAL, "box %d: omega_bulk must lie in (0, 2)", b);
+    for (int k = 0; k < 9; ++k)
+      if (P.omega_hi[k] != 1.0)
+        return fail(CGLBM_EUNSUPPORTED,
+                    "box %d: omega_hi[%d] = %g; only unit higher-order rates are built", b, k,
+                    P.omega_hi[k]);
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(P.body_force[k]))
+        return fail(CGLBM_EINVAL, "box %d: body force must be finite", b);
+  }
+  return CGLBM_OK;
+}
+
+void build_layout(int32_t n_boxes, const cglbm_box_params *boxes, Layout &L) {
+  L = Layout();
+  int64_t off = 0;
+  int32_t blk = 0, tile = 0;
+  for (int b = 0; b < n_boxes; ++b) {
+    const cglbm_box_params &P = boxes[b];
+    BoxDev B;
+    std::memset(&B, 0, sizeof(B));
+    B.nx = P.nx;
+    B.ny = P.ny;
+    B.nz = P.nz;
+    B.walls = P.walls;
+    B.n = (int64_t)P.nx * P.ny * P.nz;
+    B.base = off;
+    off = align_up(off + B.n, kAlign);
+    B.blk0 = blk;
+    const int32_t nb = (int32_t)((B.n + kBlock - 1) / kBlock);
+    for (int32_t k = 0; k < nb; ++k) L.blk_box.push_back(b);
+    blk += nb;
+    B.tile0 = tile;
+    B.tnx = (P.nx + kTX - 1) / kTX;
+    B.tny = (P.ny + kTY - 1) / kTY;
+    const int32_t tnz = (P.nz + kTZ - 1) / kTZ;
+    const int32_t nt = B.tnx * B.tny * tnz;
+    for (int32_t k = 0; k < nt; ++k) L.tile_box.push_back(b);
+    tile += nt;
+    B.fdx = make_fastdiv((uint32_t)P.nx);
+    B.fdy = make_fastdiv((uint32_t)P.ny);
+    B.ftx = make_fastdiv((uint32_t)B.tnx);
+    B.fty = make_fastdiv((uint32_t)B.tny);
+    B.cs2r = (float)(kXi * (1.0 - P.red.alpha));
+    B.cs2b = (float)(kXi * (1.0 - P.blue.alpha));
+    B.ir0r = (float)(1.0 / P.red.rho0);
+    B.ir0b = (float)(1.0 / P.blue.rho0);
+    B.nu_r = (float)P.red.nu;
+    B.nu_b = (float)P.blue.nu;
+    B.sigma = (float)P.sigma;
+    B.beta = (float)P.beta;
+    B.omega2 = (float)P.omega_bulk;
+    B.Gx = (float)P.body_force[0];
+    B.Gy = (float)P.body_force[1];
+    B.Gz = (float)P.body_force[2];
+    L.boxes.push_back(B);
+  }
+  L.total = std::max<int64_t>(off, kAlign);
+  L.nblk = blk;
+  L.ntile = tile;
+}
+
+// Host check of the division helper on the values a box can produce.
+bool fastdiv_ok(uint32_t d, uint32_t nmax) {
+  FastDiv f = make_fastdiv(d);
+  const uint32_t probes[] = {0u, 1u, d - 1, d, d + 1, 2 * d - 1, 2 * d, nmax / 2, nmax - 1, nmax};
+  for (uint32_t n : probes)
+    if (n <= nmax && fdiv(n, f) != n / d) return false;
+  for (uint32_t k = 0; k < 4096; ++k) {
+    uint32_t n = (uint32_t)(((uint64_t)k * 2654435761u) % ((uint64_t)nmax + 1));
+    if (fdiv(n, f) != n / d) return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+struct cglbm_handle {
+  int32_t n_boxes = 0;
+  std::vector<cglbm_box_params> params;
+  Layout L;
+  int32_t storage = CGLBM_FP32;
+  void *pop[2] = {nullptr, nullptr};
+  float *aux = nullptr;
+  int cur = 0;  // buffer holding the stored (post-collision) state
+  int device = 0;
+  BoxDev *d_boxes = nullptr;
+  int32_t *d_blk_box = nullptr;
+  int32_t *d_tile_box = nullptr;
+  double *d_part = nullptr;    // block partials of the reduction
+  double *d_diag = nullptr;    // per box kNPart doubles
+  double *d_centre = nullptr;  // per box 3 doubles
+  // profiling
+  bool prof = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> ev_kind;
+  size_t ev_used = 0;
+};
+
+namespace {
+
+int launch_pull(cglbm_handle *h, hipStream_t s, int bounce) {
+  float *src = (float *)h->pop[h->cur];
+  float *dst = (float *)h->pop[1 - h->cur];
+  hipLaunchKernelGGL(k_pull<StoreF32>, dim3(h->L.nblk), dim3(kBlock), 0, s, h->d_boxes,
+                     h->d_blk_box, src, dst, h->aux, h->L.total, bounce);
+  return CGLBM_OK;
+}
+
+int launch_iface(cglbm_handle *h, hipStream_t s, int write_kappa) {
+  hipLaunchKernelGGL((k_interface<kTX, kTY, kTZ>), dim3(h->L.ntile), dim3(kBlock), 0, s,
+                     h->d_boxes, h->d_tile_box, h->aux, h->L.total, write_kappa);
+  return CGLBM_OK;
+}
+
+int launch_collide(cglbm_handle *h, hipStream_t s) {
+  float *dst = (float *)h->pop[1 - h->cur];
+  hipLaunchKernelGGL(k_collide<StoreF32>, dim3(h->L.nblk), dim3(kBlock), 0, s, h->d_boxes,
+                     h->d_blk_box, h->aux, dst, h->L.total);
+  return CGLBM_OK;
+}
+
+template <class F>
+int timed(cglbm_handle *h, hipStream_t s, int kind, F &&launch) {
+  if (h->prof && h->ev_used + 2 <= h->ev.size()) {
+    HIP_TRY(hipEventRecord(h->ev[h->ev_used], s));
+    int rc = launch();
+    HIP_TRY(hipEventRecord(h->ev[h->ev_used + 1], s));
+    h->ev_kind[h->ev_used / 2] = kind;
+    h->ev_used += 2;
+    return rc;
+  }
+  return launch();
+}
+
+int check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(CGLBM_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
+  return CGLBM_OK;
+}
+
+// Local moments and interface fields of the current state into aux.
+int compute_fields(cglbm_handle *h, hipStream_t s, int write_kappa) {
+  int rc = launch_pull(h, s, 0);
+  if (rc) return rc;
+  rc = launch_iface(h, s, write_kappa);
+  if (rc) return rc;
+  return check_launch();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *cglbm_last_error(void) { return g_err.c_str(); }
+
+const char *cglbm_version(void) { return "cglbm-gfx950 0.1"; }
+
+int cglbm_query_sizes(int32_t n_boxes, const cglbm_box_params *boxes, int32_t storage,
+                      size_t *pop_bytes, size_t *aux_bytes, int64_t *total_nodes) {
+  g_err.clear();
+  int rc = validate(n_boxes, boxes, storage);
+  if (rc) return rc;
+  Layout L;
+  build_layout(n_boxes, boxes, L);
+  if (pop_bytes) *pop_bytes = (size_t)L.total * 2 * kQ * sizeof(float);
+  if (aux_bytes) *aux_bytes = (size_t)L.total * A_COUNT * sizeof(float);
+  if (total_nodes) *total_nodes = L.total;
+  return CGLBM_OK;
+}
+
+int64_t cglbm_box_offset(const cglbm_handle *h, int32_t box) {
+  if (!h || box < 0 || box >= h->n_boxes) return -1;
+  return h->L.boxes[box].base;
+}
+
+int cglbm_init(cglbm_handle **out, int32_t n_boxes, const cglbm_box_params *boxes,
+               int32_t storage, void *pop_a, void *pop_b, void *aux, const float *init_rho_r,
+               const float *init_rho_b, const float *init_u, uint64_t noise_seed,
+               double noise_amp, void *stream) {
+  g_err.clear();
+  if (!out) return fail(CGLBM_EINVAL, "out must not be NULL");
+  *out = nullptr;
+  int rc = validate(n_boxes, boxes, storage);
+  if (rc) return rc;
+  if (!pop_a) return fail(CGLBM_EINVAL, "pop_a must not be NULL");
+  if (!pop_b)
+    return fail(CGLBM_EUNSUPPORTED, "the in-place single-buffer layout is not built; pass pop_b");
+  if (pop_a == pop_b) return fail(CGLBM_EINVAL, "pop_a and pop_b must differ");
+  if (!aux || !init_rho_r || !init_rho_b || !init_u)
+    return fail(CGLBM_EINVAL, "aux and the initial fields must not be NULL");
+  if (!std::isfinite(noise_amp) || noise_amp < 0.0)
+    return fail(CGLBM_EINVAL, "noise_amp must be finite and >= 0");
+  cglbm_handle *h = new cglbm_handle();
+  h->n_boxes = n_boxes;
+  h->params.assign(boxes, boxes + n_boxes);
+  h->storage = storage;
+  build_layout(n_boxes, boxes, h->L);
+  for (const BoxDev &B : h->L.boxes) {
+    if (!fastdiv_ok((uint32_t)B.nx, (uint32_t)B.n) || !fastdiv_ok((uint32_t)B.ny, (uint32_t)B.n) ||
+        !fastdiv_ok((uint32_t)B.tnx, 1u << 20) || !fastdiv_ok((uint32_t)B.tny, 1u << 20)) {
+      delete h;
+      return fail(CGLBM_EINVAL, "index division self-check failed");
+    }
+  }
+  h->pop[0] = pop_a;
+  h->pop[1] = pop_b;
+  h->aux = (float *)aux;
+  hipStream_t s = (hipStream_t)stream;
+  auto cleanup = [&](int code) {
+    cglbm_destroy(h);
+    return code;
+  };
+  hipError_t e;
+  if ((e = hipGetDevice(&h->device)) != hipSuccess ||
+      (e = hipMalloc(&h->d_boxes, sizeof(BoxDev) * n_boxes)) != hipSuccess ||
+      (e = hipMalloc(&h->d_blk_box, sizeof(int32_t) * h->L.blk_box.size())) != hipSuccess ||
+      (e = hipMalloc(&h->d_tile_box, sizeof(int32_t) * h->L.tile_box.size())) != hipSuccess ||
+      (e = hipMalloc(&h->d_part, sizeof(double) * kNPart * (size_t)h->L.nblk)) != hipSuccess ||
+      (e = hipMalloc(&h->d_diag, sizeof(double) * kNPart * (size_t)n_boxes)) != hipSuccess ||
+      (e = hipMalloc(&h->d_centre, sizeof(double) * 3 * (size_t)n_boxes)) != hipSuccess ||
+      (e = hipMemcpyAsync(h->d_boxes, h->L.boxes.data(), sizeof(BoxDev) * n_boxes,
+                          hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(h->d_blk_box, h->L.blk_box.data(),
+                          sizeof(int32_t) * h->L.blk_box.size(), hipMemcpyHostToDevice, s)) !=
+          hipSuccess ||
+      (e = hipMemcpyAsync(h->d_tile_box, h->L.tile_box.data(),
+                          sizeof(int32_t) * h->L.tile_box.size(), hipMemcpyHostToDevice, s)) !=
+          hipSuccess) {
+    return cleanup(fail(CGLBM_EHIP, "init: %s", hipGetErrorString(e)));
+  }
+  // the stored state lives in pop[0]
+  h->cur = 0;
+  hipLaunchKernelGGL(k_init<StoreF32>, dim3(h->L.nblk), dim3(kBlock), 0, s, h->d_boxes,
+                     h->d_blk_box, init_rho_r, init_rho_b, init_u, (float *)h->pop[0],
+                     h->L.total, noise_seed, (float)noise_amp);
+  if ((rc = check_launch())) return cleanup(rc);
+  *out = h;
+  return CGLBM_OK;
+}
+
+int cglbm_step(cglbm_handle *h, int32_t n_steps, void *stream) {
+  g_err.clear();
+  if (!h) return fail(CGLBM_ESTATE, "null handle");
+  if (n_steps < 0) return fail(CGLBM_EINVAL, "n_steps must be >= 0");
+  hipStream_t s = (hipStream_t)stream;
+  for (int32_t k = 0; k < n_steps; ++k) {
+    int rc = timed(h, s, KIND_PULL, [&] { return launch_pull(h, s, 1); });
+    if (!rc) rc = timed(h, s, KIND_IFACE, [&] { return launch_iface(h, s, 0); });
+    if (!rc) rc = timed(h, s, KIND_COLLIDE, [&] { return launch_collide(h, s); });
+    if (!rc) rc = check_launch();
+    if (rc) return rc;
+    h->cur = 1 - h->cur;
+  }
+  return CGLBM_OK;
+}
+
+int cglbm_moments(cglbm_handle *h, int32_t box, uint32_t field_mask, float *out_dev,
+                  void *stream) {
+  g_err.clear();
+  if (!h) return fail(CGLBM_ESTATE, "null handle");
+  if (box < 0 || box >= h->n_boxes) return fail(CGLBM_EINVAL, "box %d out of range", box);
+  if (field_mask == 0 || (field_mask >> 17)) return fail(CGLBM_EINVAL, "bad field mask 0x%x", field_mask);
+  if (!out_dev) return fail(CGLBM_EINVAL, "out_dev must not be NULL");
+  hipStream_t s = (hipStream_t)stream;
+  int rc = compute_fields(h, s, (field_mask >> 10) & 1u);
+  if (rc) return rc;
+  const int64_t n = h->L.boxes[box].n;
+  hipLaunchKernelGGL(k_fields, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                     h->d_boxes, box, h->aux, h->L.total, field_mask, out_dev);
+  return check_launch();
+}
+
+int cglbm_reduce(cglbm_handle *h, const double *centre, double *out, int32_t out_is_host,
+                 void *stream) {
+  g_err.clear();
+  if (!h) return fail(CGLBM_ESTATE, "null handle");
+  if (!out) return fail(CGLBM_EINVAL, "out must not be NULL");
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<double> c(3 * (size_t)h->n_boxes);
+  for (int b = 0; b < h->n_boxes; ++b) {
+    const BoxDev &B = h->L.boxes[b];
+    for (int a = 0; a < 3; ++a) {
+      const int n = a == 0 ? B.nx : (a == 1 ? B.ny : B.nz);
+      c[3 * b + a] = centre ? centre[3 * b + a] : 0.5 * (n - 1);
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(h->d_centre, c.data(), sizeof(double) * c.size(), hipMemcpyHostToDevice, s));
+  int rc = compute_fields(h, s, 0);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_reduce1, dim3(h->L.nblk), dim3(kBlock), 0, s, h->d_boxes, h->d_blk_box,
+                     h->aux, h->L.total, h->d_centre, h->d_part);
+  hipLaunchKernelGGL(k_reduce_final, dim3(h->n_boxes), dim3(64), 0, s, h->d_boxes, h->d_part, 1,
+                     h->d_diag);
+  hipLaunchKernelGGL(k_reduce2, dim3(h->L.nblk), dim3(kBlock), 0, s, h->d_boxes, h->d_blk_box,
+                     h->aux, h->L.total, h->d_centre, h->d_diag, h->d_part);
+  hipLaunchKernelGGL(k_reduce_final, dim3(h->n_boxes), dim3(64), 0, s, h->d_boxes, h->d_part, 2,
+                     h->d_diag);
+  if ((rc = check_launch())) return rc;
+  std::vector<double> diag((size_t)kNPart * h->n_boxes);
+  HIP_TRY(hipMemcpyAsync(diag.data(), h->d_diag, sizeof(double) * diag.size(),
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  bool unstable = false;
+  std::vector<double> packed((size_t)CGLBM_NDIAG * h->n_boxes);
+  for (int b = 0; b < h->n_boxes; ++b) {
+    for (int k = 0; k < CGLBM_NDIAG; ++k) packed[(size_t)b * CGLBM_NDIAG + k] = diag[(size_t)b * kNPart + k];
+    if (diag[(size_t)b * kNPart + 12] != 0.0) unstable = true;
+  }
+  if (out_is_host) {
+    std::memcpy(out, packed.data(), sizeof(double) * packed.size());
+    if (unstable) return fail(CGLBM_EUNSTABLE, "non-finite values in the state");
+    return CGLBM_OK;
+  }
+  HIP_TRY(hipMemcpyAsync(out, packed.data(), sizeof(double) * packed.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return CGLBM_OK;
+}
+
+int cglbm_profile_begin(cglbm_handle *h, int32_t max_launches) {
+  g_err.clear();
+  if (!h) return fail(CGLBM_ESTATE, "null handle");
+  if (max_launches <= 0) return fail(CGLBM_EINVAL, "max_launches must be > 0");
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  h->ev.assign(2 * (size_t)max_launches, nullptr);
+  h->ev_kind.assign((size_t)max_launches, -1);
+  for (auto &e : h->ev) HIP_TRY(hipEventCreate(&e));
+  h->ev_used = 0;
+  h->prof = true;
+  return CGLBM_OK;
+}
+
+int cglbm_profile_end(cglbm_handle *h, double *total_ms, int64_t *launches, int32_t n_kinds) {
+  g_err.clear();
+  if (!h || !h->prof) return fail(CGLBM_ESTATE, "profiling was not started");
+  h->prof = false;
+  std::vector<double> ms(KIND_N, 0.0);
+  std::vector<int64_t> cnt(KIND_N, 0);
+  for (size_t k = 0; k < h->ev_used / 2; ++k) {
+    HIP_TRY(hipEventSynchronize(h->ev[2 * k + 1]));
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, h->ev[2 * k], h->ev[2 * k + 1]));
+    ms[h->ev_kind[k]] += t;
+    cnt[h->ev_kind[k]] += 1;
+  }
+  for (int k = 0; k < n_kinds && k < KIND_N; ++k) {
+    if (total_ms) total_ms[k] = ms[k];
+    if (launches) launches[k] = cnt[k];
+  }
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  h->ev.clear();
+  h->ev_kind.clear();
+  h->ev_used = 0;
+  return CGLBM_OK;
+}
+
+void cglbm_destroy(cglbm_handle *h) {
+  if (!h) return;
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  if (h->d_boxes) (void)hipFree(h->d_boxes);
+  if (h->d_blk_box) (void)hipFree(h->d_blk_box);
+  if (h->d_tile_box) (void)hipFree(h->d_tile_box);
+  if (h->d_part) (void)hipFree(h->d_part);
+  if (h->d_diag) (void)hipFree(h->d_diag);
+  if (h->d_centre) (void)hipFree(h->d_centre);
+  delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,715 @@
+// kernels.hpp -- HIP kernels (gfx950) of the colour-gradient LBM time step.
+//
+// Storage (all boxes concatenated, SoA planes of `plane` elements):
+//   populations  pop[c*27 + i][node]   c = 0 red, 1 blue; i in Eq. (1) order
+//   aux          aux[k][node], float:
+//     0 rho_r  1 rho_b  2..4 j = sum_i f_i c_i  5..10 Pi_xx,yy,zz,xy,xz,yz
+//     11..13 n  14..16 F  17..19 Q  20 kappa (only written on request)
+//
+// One step = three launches:
+//   k_pull     pull-stream (Eq. 5) + local moments; bounce-back at solid nodes
+//   k_interface  LDS-tiled stencils: phi, grad phi, n, kappa, F, u, Q
+//              (Eqs. 11, 14-17, 20, 65)
+//   k_collide  central-moment collision with the generalized equilibrium
+//              (Eqs. 25, 57-63, 66-67), recolouring (Eqs. 18-19), local store
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_bf16.h>
+
+#include "lattice.hpp"
+
+namespace cglbm {
+
+enum AuxPlane {
+  A_RR = 0, A_RB = 1, A_JX = 2, A_JY = 3, A_JZ = 4,
+  A_PXX = 5, A_PYY = 6, A_PZZ = 7, A_PXY = 8, A_PXZ = 9, A_PYZ = 10,
+  A_NX = 11, A_NY = 12, A_NZ = 13, A_FX = 14, A_FY = 15, A_FZ = 16,
+  A_QX = 17, A_QY = 18, A_QZ = 19, A_KAPPA = 20, A_COUNT = 21
+};
+
+// Per-box constants, filled on the host.
+struct BoxDev {
+  int32_t nx, ny, nz;
+  uint32_t walls;
+  int64_t base;         // first node of the box in the concatenated arrays
+  int64_t n;            // nx*ny*nz
+  int32_t blk0;         // first 256-node block of the box (k_pull, k_collide)
+  int32_t tile0;        // first tile of the box (k_interface)
+  int32_t tnx, tny;     // tiles along x, y
+  FastDiv fdx, fdy;     // division by nx, ny
+  FastDiv ftx, fty;     // division by tnx, tny
+  float cs2r, cs2b;     // (c_s^k)^2 = xi (1 - alpha_k)
+  float ir0r, ir0b;     // 1 / rho_k^0
+  float nu_r, nu_b;
+  float sigma, beta;
+  float omega2;
+  float Gx, Gy, Gz;
+};
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ int wrap_once(int v, int n) {
+  // v in [-n, 2n)
+  return v < 0 ? v + n : (v >= n ? v - n : v);
+}
+
+__device__ __forceinline__ int wrap_any(int v, int n) {
+  while (v < 0) v += n;
+  while (v >= n) v -= n;
+  return v;
+}
+
+__device__ __forceinline__ bool is_solid(const BoxDev &B, int y, int z) {
+  return ((B.walls & 1u) && (y == 0 || y == B.ny - 1)) ||
+         ((B.walls & 2u) && (z == 0 || z == B.nz - 1));
+}
+
+// ---------------------------------------------------------------------------
+// Population storage formats
+// ---------------------------------------------------------------------------
+struct StoreF32 {
+  using T = float;
+  __device__ static float load(const T *p) { return __builtin_nontemporal_load(p); }
+  __device__ static void store(T *p, float v) { __builtin_nontemporal_store(v, p); }
+};
+
+// ---------------------------------------------------------------------------
+// k_pull: f^k_i(x) = stored_i(x - c_i); local moments; bounce-back at solid
+// nodes (the pulled populations are reversed and stored for the next step).
+// ---------------------------------------------------------------------------
+template <class S>
+__global__ __launch_bounds__(kBlock) void k_pull(const BoxDev *__restrict__ boxes,
+                                                 const int32_t *__restrict__ blk_box,
+                                                 const typename S::T *__restrict__ src,
+                                                 typename S::T *__restrict__ dst,
+                                                 float *__restrict__ aux, int64_t plane,
+                                                 int bounce) {
+  const int b = blk_box[blockIdx.x];
+  const BoxDev B = boxes[b];
+  const int64_t local = (int64_t)(blockIdx.x - B.blk0) * kBlock + threadIdx.x;
+  if (local >= B.n) return;
+  const uint32_t l = (uint32_t)local;
+  const uint32_t yz = fdiv(l, B.fdx);
+  const int x = (int)(l - yz * (uint32_t)B.nx);
+  const int z = (int)fdiv(yz, B.fdy);
+  const int y = (int)(yz - (uint32_t)z * (uint32_t)B.ny);
+  const int nx = B.nx, ny = B.ny, nz = B.nz;
+  // source coordinates x - c: index 0 -> c = -1 (source x+1), 1 -> c = 0, 2 -> c = +1
+  const int xs[3] = {wrap_once(x + 1, nx), x, wrap_once(x - 1, nx)};
+  const int ys[3] = {wrap_once(y + 1, ny), y, wrap_once(y - 1, ny)};
+  const int zs[3] = {wrap_once(z + 1, nz), z, wrap_once(z - 1, nz)};
+  int64_t row[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) row[a][c] = B.base + (int64_t)nx * (ys[a] + (int64_t)ny * zs[c]);
+
+  float fr[kQ], fb[kQ];
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    const int64_t s = row[kCY[i] + 1][kCZ[i] + 1] + xs[kCX[i] + 1];
+    fr[i] = S::load(src + (int64_t)i * plane + s);
+    fb[i] = S::load(src + (int64_t)(kQ + i) * plane + s);
+  }
+  const int64_t node = B.base + local;
+  if (is_solid(B, y, z)) {
+    if (bounce) {
+#pragma unroll
+      for (int i = 0; i < kQ; ++i) {
+        S::store(dst + (int64_t)opposite(i) * plane + node, fr[i]);
+        S::store(dst + (int64_t)(kQ + opposite(i)) * plane + node, fb[i]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k <= A_PYZ; ++k) aux[(int64_t)k * plane + node] = 0.0f;
+    return;
+  }
+  float rr = 0.f, rb = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+  float pxx = 0.f, pyy = 0.f, pzz = 0.f, pxy = 0.f, pxz = 0.f, pyz = 0.f;
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    rr += fr[i];
+    rb += fb[i];
+    const float f = fr[i] + fb[i];
+    if (kCX[i]) jx += kCX[i] > 0 ? f : -f;
+    if (kCY[i]) jy += kCY[i] > 0 ? f : -f;
+    if (kCZ[i]) jz += kCZ[i] > 0 ? f : -f;
+    if (kCX[i]) pxx += f;
+    if (kCY[i]) pyy += f;
+    if (kCZ[i]) pzz += f;
+    if (kCX[i] * kCY[i]) pxy += kCX[i] * kCY[i] > 0 ? f : -f;
+    if (kCX[i] * kCZ[i]) pxz += kCX[i] * kCZ[i] > 0 ? f : -f;
+    if (kCY[i] * kCZ[i]) pyz += kCY[i] * kCZ[i] > 0 ? f : -f;
+  }
+  aux[(int64_t)A_RR * plane + node] = rr;
+  aux[(int64_t)A_RB * plane + node] = rb;
+  aux[(int64_t)A_JX * plane + node] = jx;
+  aux[(int64_t)A_JY * plane + node] = jy;
+  aux[(int64_t)A_JZ * plane + node] = jz;
+  aux[(int64_t)A_PXX * plane + node] = pxx;
+  aux[(int64_t)A_PYY * plane + node] = pyy;
+  aux[(int64_t)A_PZZ * plane + node] = pzz;
+  aux[(int64_t)A_PXY * plane + node] = pxy;
+  aux[(int64_t)A_PXZ * plane + node] = pxz;
+  aux[(int64_t)A_PYZ * plane + node] = pyz;
+}
+
+// ---------------------------------------------------------------------------
+// k_interface: for a TX*TY*TZ tile, stage phi on the tile + 3 halo, grad phi
+// and n on + 2, grad n, kappa, F, u, q on + 1, and Q on the tile.  Every
+// stencil is Eq. (20): grad chi = 3 sum_i w_i chi(x + c_i) c_i; a neighbour in
+// a solid layer takes the value of the stencil's centre node.
+// ---------------------------------------------------------------------------
+template <int TX, int TY, int TZ>
+struct IfaceGeom {
+  static constexpr int R3X = TX + 6, R3Y = TY + 6, R3Z = TZ + 6, R3 = R3X * R3Y * R3Z;
+  static constexpr int R2X = TX + 4, R2Y = TY + 4, R2Z = TZ + 4, R2 = R2X * R2Y * R2Z;
+  static constexpr int R1X = TX + 2, R1Y = TY + 2, R1Z = TZ + 2, R1 = R1X * R1Y * R1Z;
+  static constexpr int T = TX * TY * TZ;
+};
+
+// 26-point isotropic gradient (Eq. 20) of a scalar field held in LDS with
+// strides (1, SY, SZ).  Each component is summed over pairs of opposite
+// neighbours as w * (chi(+) - chi(-)), so that a uniform field gives exactly
+// zero.  solid(dy, dz) reports whether the neighbour row is solid; solid
+// neighbours take the centre value.
+template <int SY, int SZ, class Solid>
+__device__ __forceinline__ void lds_gradient(const float *f, int c, Solid solid, float &gx,
+                                             float &gy, float &gz) {
+  const float vc = f[c];
+  float v[3][3][3];
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const bool s = solid(dy, dz);
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx)
+        v[dz + 1][dy + 1][dx + 1] = s ? vc : f[c + dx + SY * dy + SZ * dz];
+    }
+  // (1/c_s^2) w_i c_i = 3 * w(dx) w(dy) w(dz) * c_i; for the pair along one
+  // axis the factor is 3 * (1/6) * w(.) w(.) = w(.) w(.) / 2.
+  gx = gy = gz = 0.f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const float w = 0.5f * w1d(a - 1) * w1d(b - 1);
+      gx = fmaf(w, v[b][a][2] - v[b][a][0], gx);  // a: dy, b: dz
+      gy = fmaf(w, v[b][2][a] - v[b][0][a], gy);  // a: dx, b: dz
+      gz = fmaf(w, v[2][b][a] - v[0][b][a], gz);  // a: dx, b: dy
+    }
+}
+
+template <int TX, int TY, int TZ>
+__global__ __launch_bounds__(kBlock) void k_interface(const BoxDev *__restrict__ boxes,
+                                                      const int32_t *__restrict__ tile_box,
+                                                      float *__restrict__ aux, int64_t plane,
+                                                      int write_kappa) {
+  using G = IfaceGeom<TX, TY, TZ>;
+  __shared__ float s_phi[G::R3];
+  __shared__ float s_n[4][G::R2];   // n_x, n_y, n_z, |grad phi|
+  __shared__ float s_q[3][G::R1];
+  __shared__ uint8_t s_sy[G::R3Y], s_sz[G::R3Z];
+
+  const int b = tile_box[blockIdx.x];
+  const BoxDev B = boxes[b];
+  const uint32_t t = blockIdx.x - B.tile0;
+  const uint32_t tyz = fdiv(t, B.ftx);
+  const int tx = (int)(t - tyz * (uint32_t)B.tnx);
+  const int tz = (int)fdiv(tyz, B.fty);
+  const int ty = (int)(tyz - (uint32_t)tz * (uint32_t)B.tny);
+  const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+  const int nx = B.nx, ny = B.ny, nz = B.nz;
+
+  // solid flags of the halo rows
+  for (int i = threadIdx.x; i < G::R3Y; i += kBlock) {
+    const int gy = wrap_any(y0 + i - 3, ny);
+    s_sy[i] = (B.walls & 1u) && (gy == 0 || gy == ny - 1);
+  }
+  for (int i = threadIdx.x; i < G::R3Z; i += kBlock) {
+    const int gz = wrap_any(z0 + i - 3, nz);
+    s_sz[i] = (B.walls & 2u) && (gz == 0 || gz == nz - 1);
+  }
+  // stage 1: phi on the tile + 3 (Eq. 14)
+  for (int i = threadIdx.x; i < G::R3; i += kBlock) {
+    const int lx = i % G::R3X, ly = (i / G::R3X) % G::R3Y, lz = i / (G::R3X * G::R3Y);
+    const int gx = wrap_any(x0 + lx - 3, nx), gy = wrap_any(y0 + ly - 3, ny),
+              gz = wrap_any(z0 + lz - 3, nz);
+    const int64_t node = B.base + gx + (int64_t)nx * (gy + (int64_t)ny * gz);
+    const float rr = aux[(int64_t)A_RR * plane + node] * B.ir0r;
+    const float rb = aux[(int64_t)A_RB * plane + node] * B.ir0b;
+    const float den = rr + rb;
+    s_phi[i] = den > 0.f ? (rr - rb) / den : 0.f;
+  }
+  __syncthreads();
+
+  // stage 2: grad phi and n on the tile + 2 (Eqs. 17, 20)
+  for (int i = threadIdx.x; i < G::R2; i += kBlock) {
+    const int lx = i % G::R2X, ly = (i / G::R2X) % G::R2Y, lz = i / (G::R2X * G::R2Y);
+    const int c3 = (lx + 1) + G::R3X * ((ly + 1) + G::R3Y * (lz + 1));
+    float nxv = 0.f, nyv = 0.f, nzv = 0.f, mag = 0.f;
+    if (!(s_sy[ly + 1] | s_sz[lz + 1])) {
+      float gx, gy, gz;
+      lds_gradient<G::R3X, G::R3X * G::R3Y>(
+          s_phi, c3, [&](int dy, int dz) { return (bool)(s_sy[ly + 1 + dy] | s_sz[lz + 1 + dz]); },
+          gx, gy, gz);
+      mag = sqrtf(gx * gx + gy * gy + gz * gz);
+      if (mag > 1e-12f) {
+        const float inv = 1.0f / mag;
+        nxv = gx * inv;
+        nyv = gy * inv;
+        nzv = gz * inv;
+      } else {
+        mag = 0.f;
+      }
+    }
+    s_n[0][i] = nxv;
+    s_n[1][i] = nyv;
+    s_n[2][i] = nzv;
+    s_n[3][i] = mag;
+  }
+  __syncthreads();
+
+  // stage 3: grad n, kappa, F, u, q on the tile + 1 (Eqs. 11, 15, 16, 65)
+  for (int i = threadIdx.x; i < G::R1; i += kBlock) {
+    const int lx = i % G::R1X, ly = (i / G::R1X) % G::R1Y, lz = i / (G::R1X * G::R1Y);
+    const int c2 = (lx + 1) + G::R2X * ((ly + 1) + G::R2Y * (lz + 1));
+    const int gx = wrap_any(x0 + lx - 1, nx), gy = wrap_any(y0 + ly - 1, ny),
+              gz = wrap_any(z0 + lz - 1, nz);
+    const int64_t node = B.base + gx + (int64_t)nx * (gy + (int64_t)ny * gz);
+    const bool solid = s_sy[ly + 2] | s_sz[lz + 2];
+    float qx = 0.f, qy = 0.f, qz = 0.f;
+    float kap = 0.f, Fx = 0.f, Fy = 0.f, Fz = 0.f;
+    const float nxv = s_n[0][c2], nyv = s_n[1][c2], nzv = s_n[2][c2], mag = s_n[3][c2];
+    if (!solid) {
+      auto sol = [&](int dy, int dz) { return (bool)(s_sy[ly + 2 + dy] | s_sz[lz + 2 + dz]); };
+      float dxx, dxy, dxz, dyx, dyy, dyz, dzx, dzy, dzz;  // d n_a / d x_b
+      lds_gradient<G::R2X, G::R2X * G::R2Y>(s_n[0], c2, sol, dxx, dxy, dxz);
+      lds_gradient<G::R2X, G::R2X * G::R2Y>(s_n[1], c2, sol, dyx, dyy, dyz);
+      lds_gradient<G::R2X, G::R2X * G::R2Y>(s_n[2], c2, sol, dzx, dzy, dzz);
+      // kappa = -(I - n n) : grad n
+      const float div = dxx + dyy + dzz;
+      const float proj = nxv * (nxv * dxx + nyv * dxy + nzv * dxz) +
+                         nyv * (nxv * dyx + nyv * dyy + nzv * dyz) +
+                         nzv * (nxv * dzx + nyv * dzy + nzv * dzz);
+      kap = proj - div;
+      const float hs = 0.5f * B.sigma * kap * mag;
+      Fx = fmaf(hs, nxv, B.Gx);
+      Fy = fmaf(hs, nyv, B.Gy);
+      Fz = fmaf(hs, nzv, B.Gz);
+      const float rr = aux[(int64_t)A_RR * plane + node];
+      const float rb = aux[(int64_t)A_RB * plane + node];
+      const float rho = rr + rb;
+      const float irho = 1.0f / rho;
+      const float ux = fmaf(0.5f, Fx, aux[(int64_t)A_JX * plane + node]) * irho;
+      const float uy = fmaf(0.5f, Fy, aux[(int64_t)A_JY * plane + node]) * irho;
+      const float uz = fmaf(0.5f, Fz, aux[(int64_t)A_JZ * plane + node]) * irho;
+      const float dev = rr * B.cs2r + rb * B.cs2b - rho * kCs2;
+      qx = dev * ux;
+      qy = dev * uy;
+      qz = dev * uz;
+    }
+    s_q[0][i] = qx;
+    s_q[1][i] = qy;
+    s_q[2][i] = qz;
+    // tile nodes: write n, F (and kappa)
+    const int ox = lx - 1, oy = ly - 1, oz = lz - 1;
+    if (ox >= 0 && ox < TX && oy >= 0 && oy < TY && oz >= 0 && oz < TZ && x0 + ox < nx &&
+        y0 + oy < ny && z0 + oz < nz) {
+      aux[(int64_t)A_NX * plane + node] = nxv;
+      aux[(int64_t)A_NY * plane + node] = nyv;
+      aux[(int64_t)A_NZ * plane + node] = nzv;
+      aux[(int64_t)A_FX * plane + node] = Fx;
+      aux[(int64_t)A_FY * plane + node] = Fy;
+      aux[(int64_t)A_FZ * plane + node] = Fz;
+      if (write_kappa) aux[(int64_t)A_KAPPA * plane + node] = kap;
+    }
+  }
+  __syncthreads();
+
+  // stage 4: Q on the tile (Eq. 65, component-wise)
+  for (int i = threadIdx.x; i < G::T; i += kBlock) {
+    const int ox = i % TX, oy = (i / TX) % TY, oz = i / (TX * TY);
+    const int gx = x0 + ox, gy = y0 + oy, gz = z0 + oz;
+    if (gx >= nx || gy >= ny || gz >= nz) continue;
+    const int64_t node = B.base + gx + (int64_t)nx * (gy + (int64_t)ny * gz);
+    const int c1 = (ox + 1) + G::R1X * ((oy + 1) + G::R1Y * (oz + 1));
+    float Qx = 0.f, Qy = 0.f, Qz = 0.f;
+    if (!(s_sy[oy + 3] | s_sz[oz + 3])) {
+      auto sol = [&](int dy, int dz) { return (bool)(s_sy[oy + 3 + dy] | s_sz[oz + 3 + dz]); };
+      float a, bq, c;
+      lds_gradient<G::R1X, G::R1X * G::R1Y>(s_q[0], c1, sol, a, bq, c);
+      Qx = -3.0f * a;
+      lds_gradient<G::R1X, G::R1X * G::R1Y>(s_q[1], c1, sol, a, bq, c);
+      Qy = -3.0f * bq;
+      lds_gradient<G::R1X, G::R1X * G::R1Y>(s_q[2], c1, sol, a, bq, c);
+      Qz = -3.0f * c;
+    }
+    aux[(int64_t)A_QX * plane + node] = Qx;
+    aux[(int64_t)A_QY * plane + node] = Qy;
+    aux[(int64_t)A_QZ * plane + node] = Qz;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Node-local collision + recolouring.  Inputs: local moments (rho_r, rho_b, j,
+// Pi) and interface fields (n, F, Q).  Output: f^{r*}, f^{b*} (Eqs. 18-19).
+// ---------------------------------------------------------------------------
+struct NodeIn {
+  float rr, rb, jx, jy, jz, pxx, pyy, pzz, pxy, pxz, pyz;
+  float nx, ny, nz, Fx, Fy, Fz, Qx, Qy, Qz;
+};
+
+__device__ __forceinline__ void collide_node(const BoxDev &B, const NodeIn &in, float (&fr)[kQ],
+                                             float (&fb)[kQ]) {
+  const float rho = in.rr + in.rb;
+  const float irho = 1.0f / rho;
+  const float ux = fmaf(0.5f, in.Fx, in.jx) * irho;  // Eq. (11)
+  const float uy = fmaf(0.5f, in.Fy, in.jy) * irho;
+  const float uz = fmaf(0.5f, in.Fz, in.jz) * irho;
+  const float p = in.rr * B.cs2r + in.rb * B.cs2b;   // Eq. (12)
+  // Eqs. (14), (21), (22): omega_1 from the interpolated viscosity
+  const float sr = in.rr * B.ir0r, sb = in.rb * B.ir0b;
+  const float phi = (sr - sb) / (sr + sb);
+  const float nu = 0.5f * ((1.0f + phi) * B.nu_r + (1.0f - phi) * B.nu_b);
+  const float w1 = 1.0f / (rho * nu / p + 0.5f);
+  const float w2 = B.omega2;
+  // second-order central moments from raw ones (Eqs. 23-24)
+  const float kxx = in.pxx - 2.0f * ux * in.jx + rho * ux * ux;
+  const float kyy = in.pyy - 2.0f * uy * in.jy + rho * uy * uy;
+  const float kzz = in.pzz - 2.0f * uz * in.jz + rho * uz * uz;
+  const float kxy = in.pxy - ux * in.jy - uy * in.jx + rho * ux * uy;
+  const float kxz = in.pxz - ux * in.jz - uz * in.jx + rho * ux * uz;
+  const float kyz = in.pyz - uy * in.jz - uz * in.jy + rho * uy * uz;
+  // relaxation (Eq. 25 with omega_0 = omega_3..10 = 1 and k^eq of Eqs. 57-63)
+  const float r1 = 1.0f - w1, h1 = 1.0f - 0.5f * w1;
+  const float A = r1 * (kxx - kyy) + h1 * (in.Qx - in.Qy);
+  const float Bd = r1 * (kxx - kzz) + h1 * (in.Qx - in.Qz);
+  const float T = (1.0f - w2) * (kxx + kyy + kzz) + 3.0f * w2 * p +
+                  (1.0f - 0.5f * w2) * (in.Qx + in.Qy + in.Qz);
+  const float third = 1.0f / 3.0f;
+  const float sxx = (A + Bd + T) * third;
+  const float syy = (T - 2.0f * A + Bd) * third;
+  const float szz = (T + A - 2.0f * Bd) * third;
+  float k[27];
+  model_d_moments(rho, p, in.Fx, in.Fy, in.Fz, sxx, syy, szz, r1 * kxy, r1 * kxz, r1 * kyz, k);
+  float f[kQ];
+  central_to_populations(k, ux, uy, uz, f);
+  // recolouring (Eqs. 18-19)
+  const float cr = in.rr * irho, cb = in.rb * irho;
+  const float s = B.beta * cr * cb * p;
+  const float Rx = s * in.nx, Ry = s * in.ny, Rz = s * in.nz;
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    const float cR = (kCX[i] ? (kCX[i] > 0 ? Rx : -Rx) : 0.f) +
+                     (kCY[i] ? (kCY[i] > 0 ? Ry : -Ry) : 0.f) +
+                     (kCZ[i] ? (kCZ[i] > 0 ? Rz : -Rz) : 0.f);
+    const float d = 3.0f * weight(i) * cR;
+    fr[i] = fmaf(cr, f[i], d);
+    fb[i] = fmaf(cb, f[i], -d);
+  }
+}
+
+__device__ __forceinline__ NodeIn load_node_in(const float *__restrict__ aux, int64_t plane,
+                                               int64_t node) {
+  NodeIn in;
+  in.rr = aux[(int64_t)A_RR * plane + node];
+  in.rb = aux[(int64_t)A_RB * plane + node];
+  in.jx = aux[(int64_t)A_JX * plane + node];
+  in.jy = aux[(int64_t)A_JY * plane + node];
+  in.jz = aux[(int64_t)A_JZ * plane + node];
+  in.pxx = aux[(int64_t)A_PXX * plane + node];
+  in.pyy = aux[(int64_t)A_PYY * plane + node];
+  in.pzz = aux[(int64_t)A_PZZ * plane + node];
+  in.pxy = aux[(int64_t)A_PXY * plane + node];
+  in.pxz = aux[(int64_t)A_PXZ * plane + node];
+  in.pyz = aux[(int64_t)A_PYZ * plane + node];
+  in.nx = aux[(int64_t)A_NX * plane + node];
+  in.ny = aux[(int64_t)A_NY * plane + node];
+  in.nz = aux[(int64_t)A_NZ * plane + node];
+  in.Fx = aux[(int64_t)A_FX * plane + node];
+  in.Fy = aux[(int64_t)A_FY * plane + node];
+  in.Fz = aux[(int64_t)A_FZ * plane + node];
+  in.Qx = aux[(int64_t)A_QX * plane + node];
+  in.Qy = aux[(int64_t)A_QY * plane + node];
+  in.Qz = aux[(int64_t)A_QZ * plane + node];
+  return in;
+}
+
+template <class S>
+__global__ __launch_bounds__(kBlock) void k_collide(const BoxDev *__restrict__ boxes,
+                                                    const int32_t *__restrict__ blk_box,
+                                                    const float *__restrict__ aux,
+                                                    typename S::T *__restrict__ dst,
+                                                    int64_t plane) {
+  const int b = blk_box[blockIdx.x];
+  const BoxDev B = boxes[b];
+  const int64_t local = (int64_t)(blockIdx.x - B.blk0) * kBlock + threadIdx.x;
+  if (local >= B.n) return;
+  const uint32_t l = (uint32_t)local;
+  const uint32_t yz = fdiv(l, B.fdx);
+  const int z = (int)fdiv(yz, B.fdy);
+  const int y = (int)(yz - (uint32_t)z * (uint32_t)B.ny);
+  if (is_solid(B, y, z)) return;
+  const int64_t node = B.base + local;
+  const NodeIn in = load_node_in(aux, plane, node);
+  float fr[kQ], fb[kQ];
+  collide_node(B, in, fr, fb);
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    S::store(dst + (int64_t)i * plane + node, fr[i]);
+    S::store(dst + (int64_t)(kQ + i) * plane + node, fb[i]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Initial state: f^k = (rho_k/rho)(f^eq + eta) with the Model D equilibrium
+// built from its central moments (Eqs. 57-63), written un-streamed so that the
+// first pull reproduces f(x, 0): stored_i(x - c_i) = f_i(x).
+// ---------------------------------------------------------------------------
+template <class S>
+__global__ __launch_bounds__(kBlock) void k_init(const BoxDev *__restrict__ boxes,
+                                                 const int32_t *__restrict__ blk_box,
+                                                 const float *__restrict__ in_rr,
+                                                 const float *__restrict__ in_rb,
+                                                 const float *__restrict__ in_u,
+                                                 typename S::T *__restrict__ dst, int64_t plane,
+                                                 uint64_t seed, float amp) {
+  const int b = blk_box[blockIdx.x];
+  const BoxDev B = boxes[b];
+  const int64_t local = (int64_t)(blockIdx.x - B.blk0) * kBlock + threadIdx.x;
+  if (local >= B.n) return;
+  const uint32_t l = (uint32_t)local;
+  const uint32_t yz = fdiv(l, B.fdx);
+  const int x = (int)(l - yz * (uint32_t)B.nx);
+  const int z = (int)fdiv(yz, B.fdy);
+  const int y = (int)(yz - (uint32_t)z * (uint32_t)B.ny);
+  const int64_t node = B.base + local;
+  const float rr = in_rr[node], rb = in_rb[node];
+  const float ux = in_u[node], uy = in_u[plane + node], uz = in_u[2 * plane + node];
+  const float rho = rr + rb;
+  const float p = rr * B.cs2r + rb * B.cs2b;
+  float k[27];
+  model_d_moments(rho, p, 0.f, 0.f, 0.f, p, p, p, 0.f, 0.f, 0.f, k);
+  float f[kQ];
+  central_to_populations(k, ux, uy, uz, f);
+  const float cr = rr / rho, cb = rb / rho;
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    const float ft = amp != 0.f ? f[i] + counter_noise(seed, (uint32_t)b, (uint64_t)local, i, amp)
+                                : f[i];
+    const int xd = wrap_once(x - kCX[i], B.nx), yd = wrap_once(y - kCY[i], B.ny),
+              zd = wrap_once(z - kCZ[i], B.nz);
+    const int64_t d = B.base + xd + (int64_t)B.nx * (yd + (int64_t)B.ny * zd);
+    S::store(dst + (int64_t)i * plane + d, cr * ft);
+    S::store(dst + (int64_t)(kQ + i) * plane + d, cb * ft);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Field export of one box (after k_pull + k_interface).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_fields(const BoxDev *__restrict__ boxes, int box,
+                                                   const float *__restrict__ aux, int64_t plane,
+                                                   uint32_t mask, float *__restrict__ out) {
+  const BoxDev B = boxes[box];
+  const int64_t local = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (local >= B.n) return;
+  const uint32_t l = (uint32_t)local;
+  const uint32_t yz = fdiv(l, B.fdx);
+  const int z = (int)fdiv(yz, B.fdy);
+  const int y = (int)(yz - (uint32_t)z * (uint32_t)B.ny);
+  const int64_t node = B.base + local;
+  const bool solid = is_solid(B, y, z);
+  const NodeIn in = load_node_in(aux, plane, node);
+  const float rho = in.rr + in.rb;
+  const float sr = in.rr * B.ir0r, sb = in.rb * B.ir0b;
+  float v[17];
+  v[0] = in.rr;
+  v[1] = in.rb;
+  v[2] = (sr + sb) > 0.f ? (sr - sb) / (sr + sb) : 0.f;
+  v[3] = in.rr * B.cs2r + in.rb * B.cs2b;
+  v[4] = solid ? 0.f : fmaf(0.5f, in.Fx, in.jx) / rho;
+  v[5] = solid ? 0.f : fmaf(0.5f, in.Fy, in.jy) / rho;
+  v[6] = solid ? 0.f : fmaf(0.5f, in.Fz, in.jz) / rho;
+  v[7] = in.nx;
+  v[8] = in.ny;
+  v[9] = in.nz;
+  v[10] = aux[(int64_t)A_KAPPA * plane + node];
+  v[11] = in.Fx;
+  v[12] = in.Fy;
+  v[13] = in.Fz;
+  v[14] = in.Qx;
+  v[15] = in.Qy;
+  v[16] = in.Qz;
+  int slot = 0;
+  for (int k = 0; k < 17; ++k) {
+    if (mask & (1u << k)) {
+      out[(int64_t)slot * B.n + local] = v[k];
+      ++slot;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic FP64 diagnostics.  Pass 1 per 256-node block: sums of rho_r,
+// rho_b, rho u, V = (1+phi)/2, red centroid offsets, kinetic energy,
+// non-finite count.  Pass 2: inside / outside pressure sums given R_eff.
+// Final passes sum the block partials of each box in block order.
+// ---------------------------------------------------------------------------
+constexpr int kNPart = 16;
+
+__device__ __forceinline__ float periodic_offset(float d, int n, bool periodic) {
+  if (!periodic) return d;
+  const float h = 0.5f * n;
+  if (d > h) d -= n;
+  if (d < -h) d += n;
+  return d;
+}
+
+template <int NV>
+__device__ __forceinline__ void block_sum_f64(double (&v)[NV], double *part) {
+  __shared__ double s[NV][kBlock];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) s[k][threadIdx.x] = v[k];
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) part[k] = s[k][0];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce1(const BoxDev *__restrict__ boxes,
+                                                    const int32_t *__restrict__ blk_box,
+                                                    const float *__restrict__ aux, int64_t plane,
+                                                    const double *__restrict__ centre,
+                                                    double *__restrict__ part) {
+  const int b = blk_box[blockIdx.x];
+  const BoxDev B = boxes[b];
+  const int64_t local = (int64_t)(blockIdx.x - B.blk0) * kBlock + threadIdx.x;
+  double v[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if (local < B.n) {
+    const uint32_t l = (uint32_t)local;
+    const uint32_t yz = fdiv(l, B.fdx);
+    const int x = (int)(l - yz * (uint32_t)B.nx);
+    const int z = (int)fdiv(yz, B.fdy);
+    const int y = (int)(yz - (uint32_t)z * (uint32_t)B.ny);
+    if (!is_solid(B, y, z)) {
+      const int64_t node = B.base + local;
+      const NodeIn in = load_node_in(aux, plane, node);
+      const double rr = in.rr, rb = in.rb, rho = rr + rb;
+      const double jx = (double)in.jx + 0.5 * in.Fx, jy = (double)in.jy + 0.5 * in.Fy,
+                   jz = (double)in.jz + 0.5 * in.Fz;
+      const float sr = in.rr * B.ir0r, sb = in.rb * B.ir0b;
+      const double phi = (sr + sb) > 0.f ? (double)((sr - sb) / (sr + sb)) : 0.0;
+      const double dx = periodic_offset(x - (float)centre[3 * b + 0], B.nx, true);
+      const double dy = periodic_offset(y - (float)centre[3 * b + 1], B.ny, !(B.walls & 1u));
+      const double dz = periodic_offset(z - (float)centre[3 * b + 2], B.nz, !(B.walls & 2u));
+      const bool finite = isfinite(in.rr) && isfinite(in.rb) && isfinite(in.jx) &&
+                          isfinite(in.jy) && isfinite(in.jz) && isfinite(in.pxx) &&
+                          isfinite(in.pyy) && isfinite(in.pzz) && isfinite(in.pxy) &&
+                          isfinite(in.pxz) && isfinite(in.pyz);
+      v[0] = rr;
+      v[1] = rb;
+      v[2] = jx;
+      v[3] = jy;
+      v[4] = jz;
+      v[5] = 0.5 * (1.0 + phi);
+      v[6] = rr * dx;
+      v[7] = rr * dy;
+      v[8] = rr * dz;
+      v[9] = 0.5 * (jx * jx + jy * jy + jz * jz) / rho;
+      v[10] = finite ? 0.0 : 1.0;
+      if (!finite) {
+        for (int k = 0; k < 10; ++k) v[k] = 0.0;
+      }
+    }
+  }
+  block_sum_f64<11>(v, part + (int64_t)blockIdx.x * kNPart);
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce2(const BoxDev *__restrict__ boxes,
+                                                    const int32_t *__restrict__ blk_box,
+                                                    const float *__restrict__ aux, int64_t plane,
+                                                    const double *__restrict__ centre,
+                                                    const double *__restrict__ diag,
+                                                    double *__restrict__ part) {
+  const int b = blk_box[blockIdx.x];
+  const BoxDev B = boxes[b];
+  const int64_t local = (int64_t)(blockIdx.x - B.blk0) * kBlock + threadIdx.x;
+  double v[4] = {0, 0, 0, 0};
+  const double reff = diag[(int64_t)b * kNPart + 7];
+  if (local < B.n) {
+    const uint32_t l = (uint32_t)local;
+    const uint32_t yz = fdiv(l, B.fdx);
+    const int x = (int)(l - yz * (uint32_t)B.nx);
+    const int z = (int)fdiv(yz, B.fdy);
+    const int y = (int)(yz - (uint32_t)z * (uint32_t)B.ny);
+    if (!is_solid(B, y, z)) {
+      const int64_t node = B.base + local;
+      const double p = (double)(aux[(int64_t)A_RR * plane + node] * B.cs2r +
+                                aux[(int64_t)A_RB * plane + node] * B.cs2b);
+      const double dx = periodic_offset(x - (float)centre[3 * b + 0], B.nx, true);
+      const double dy = periodic_offset(y - (float)centre[3 * b + 1], B.ny, !(B.walls & 1u));
+      const double dz = periodic_offset(z - (float)centre[3 * b + 2], B.nz, !(B.walls & 2u));
+      const double d = sqrt(dx * dx + dy * dy + dz * dz);
+      if (isfinite(p)) {
+        if (d < reff - 3.0) {
+          v[0] = p;
+          v[1] = 1.0;
+        }
+        if (d > reff + 5.0) {
+          v[2] = p;
+          v[3] = 1.0;
+        }
+      }
+    }
+  }
+  block_sum_f64<4>(v, part + (int64_t)blockIdx.x * kNPart);
+}
+
+// One block per box: fixed-order sum of the box's block partials.
+// pass 1 fills diag[0..4, 7 (R_eff), 8..10 (centroid), 11, 12]; pass 2 fills 5, 6.
+__global__ __launch_bounds__(64) void k_reduce_final(const BoxDev *__restrict__ boxes,
+                                                     const double *__restrict__ part, int pass,
+                                                     double *__restrict__ diag) {
+  const int b = blockIdx.x;
+  const BoxDev B = boxes[b];
+  const int nblk = (int)((B.n + kBlock - 1) / kBlock);
+  if (threadIdx.x != 0) return;
+  if (pass == 1) {
+    double s[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < nblk; ++k)
+      for (int c = 0; c < 11; ++c) s[c] += part[(int64_t)(B.blk0 + k) * kNPart + c];
+    double *o = diag + (int64_t)b * kNPart;
+    o[0] = s[0];
+    o[1] = s[1];
+    o[2] = s[2];
+    o[3] = s[3];
+    o[4] = s[4];
+    o[7] = cbrt(3.0 * s[5] / (4.0 * 3.14159265358979323846));
+    o[8] = s[0] > 0 ? s[6] / s[0] : 0.0;
+    o[9] = s[0] > 0 ? s[7] / s[0] : 0.0;
+    o[10] = s[0] > 0 ? s[8] / s[0] : 0.0;
+    o[11] = s[9];
+    o[12] = s[10];
+  } else {
+    double s[4] = {0, 0, 0, 0};
+    for (int k = 0; k < nblk; ++k)
+      for (int c = 0; c < 4; ++c) s[c] += part[(int64_t)(B.blk0 + k) * kNPart + c];
+    double *o = diag + (int64_t)b * kNPart;
+    o[5] = s[1] > 0 ? s[0] / s[1] : 0.0;
+    o[6] = s[3] > 0 ? s[2] / s[3] : 0.0;
+  }
+}
+
+}  // namespace cglbm

@@ -1,0 +1,61 @@
+"""Shared helpers of the tests: run the HIP path and the FP64 oracle on the
+same seeded inputs and measure their differences (error norms of density,
+velocity and order parameter as relative or absolute maxima)."""
+import numpy as np
+
+import oracle as O
+import workloads as WL
+
+
+def oracle_params(box: WL.Box, **kw) -> O.Params:
+    d = dict(nx=box.nx, ny=box.ny, nz=box.nz, rho0_r=box.rho0_r, rho0_b=box.rho0_b,
+             alpha_r=box.alpha_r, alpha_b=box.alpha_b, nu_r=box.nu_r, nu_b=box.nu_b,
+             sigma=box.sigma, beta=box.beta, walls=box.walls, body_force=tuple(box.body_force),
+             omega=(1.0, 1.0, box.omega_bulk) + (1.0,) * 8)
+    d.update(kw)
+    return O.Params(**d)
+
+
+def run_oracle(box: WL.Box, rr, rb, u, steps, seed=0, noise=0.0, box_index=0):
+    P = oracle_params(box)
+    f = O.init(P, np.asarray(rr, np.float64), np.asarray(rb, np.float64),
+               np.asarray(u, np.float64), seed=seed, amp=noise, box=box_index)
+    if steps:
+        O.step(P, f, steps)
+    return O.fields(P, f), f
+
+
+def gpu_fields(sim, box_index=0):
+    import torch
+    out = {k: v.double().cpu().numpy() for k, v in sim.moments(box_index).items()}
+    torch.cuda.synchronize()
+    return out
+
+
+def fluid_mask(box: WL.Box):
+    m = np.ones(box.shape, bool)
+    if box.walls & 1:
+        m[:, 0, :] = False
+        m[:, -1, :] = False
+    if box.walls & 2:
+        m[0, :, :] = False
+        m[-1, :, :] = False
+    return m
+
+
+def errors(g, o, box: WL.Box, u_ref: float):
+    """e_rho = max |d rho| / rho_oracle; e_u = max |d u|_2 / u_ref;
+    e_phi = max |d phi|, over fluid nodes."""
+    m = fluid_mask(box)
+    rho_g = g["rho_r"] + g["rho_b"]
+    rho_o = o["rho_r"] + o["rho_b"]
+    du = np.sqrt((g["ux"] - o["ux"]) ** 2 + (g["uy"] - o["uy"]) ** 2 + (g["uz"] - o["uz"]) ** 2)
+    return {
+        "rho": float((np.abs(rho_g - rho_o) / rho_o)[m].max()),
+        "rho_r": float(np.abs(g["rho_r"] - o["rho_r"])[m].max() / box.rho0_r),
+        "rho_b": float(np.abs(g["rho_b"] - o["rho_b"])[m].max() / box.rho0_b),
+        "u": float(du[m].max() / u_ref),
+        "phi": float(np.abs(g["phi"] - o["phi"])[m].max()),
+        "rho_l2": float(np.sqrt((((rho_g - rho_o) / rho_o)[m] ** 2).mean())),
+        "u_l2": float(np.sqrt((du[m] ** 2).mean()) / u_ref),
+    }

@@ -1,0 +1,64 @@
+"""The C-ABI library loads without a GPU, exports every symbol declared in
+include/cglbm.h, and validates parameters on the host (no compute calls)."""
+import os
+import re
+
+import pytest
+
+import paper_2309_07801_amd as pkg
+import workloads as WL
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "cglbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(cglbm_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = pkg.lib()
+    names = _declared_functions()
+    assert "cglbm_init" in names and "cglbm_step" in names
+    assert "cglbm_moments" in names and "cglbm_reduce" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(pkg.EXPORTED) == set(names)
+
+
+def test_query_sizes_layout():
+    boxes = [WL.two_phase_box((10, 7, 5), 10.0, 1.0, 0.8, 0.01, 0.7),
+             WL.two_phase_box((3, 4, 5), 1.0, 1.0, 0.8, 0.01, 0.7)]
+    pop, aux, total = pkg.query_sizes([pkg.box_params_of(b) for b in boxes])
+    # box 0: 350 nodes -> aligned to 384; box 1: 60 nodes -> 448 total
+    assert total == 448
+    assert pop == total * 54 * 4
+    assert aux == total * 21 * 4
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("nx", 0, -1), ("walls", 4, -1), ("sigma", -1.0, -1), ("beta", float("nan"), -1),
+    ("omega_bulk", 2.0, -1), ("omega_hi", 1.2, -3)])
+def test_parameter_validation(field, value, code):
+    b = WL.two_phase_box((8, 8, 8), 10.0, 1.0, 0.8, 0.01, 0.7)
+    p = pkg.box_params_of(b)
+    if field == "omega_hi":
+        p.omega_hi[3] = value
+    else:
+        setattr(p, field, value)
+    with pytest.raises(pkg.CglbmError) as ei:
+        pkg.query_sizes([p])
+    assert ei.value.code == code
+
+
+def test_phase_validation_and_storage():
+    b = WL.two_phase_box((8, 8, 8), 10.0, 1.0, 0.8, 0.01, 0.7)
+    p = pkg.box_params_of(b)
+    p.red.alpha = 1.0
+    with pytest.raises(pkg.CglbmError):
+        pkg.query_sizes([p])
+    p = pkg.box_params_of(b)
+    with pytest.raises(pkg.CglbmError) as ei:
+        pkg.query_sizes([p], storage=7)
+    assert ei.value.code in (-1, -3)
