@@ -142,11 +142,19 @@ int cglbm_reduce(cglbm_handle *h, const double *centre, double *out, int32_t out
 /* Node offset of box b in the concatenated arrays, or -1. */
 int64_t cglbm_box_offset(const cglbm_handle *h, int32_t box);
 
+/* Launch schedule of a step (both compute the same update, bit for bit):
+ *   0 (default) two launches: pull-streaming with local moments, then one
+ *     column-marching kernel for the interface stencils and the collision;
+ *   1 three launches: pull, LDS-tiled interface stencils, collision.
+ * Returns CGLBM_EINVAL for other values. */
+int cglbm_set_schedule(cglbm_handle *h, int32_t schedule);
+
 /* Per-kernel timing with HIP events recorded on the caller's stream around
  * every launch of the step.  begin: reserve room for max_launches launches;
  * end: synchronize the events and return, per kernel kind
- * (0 pull/moments, 1 interface, 2 collide), the total milliseconds and the
- * number of launches timed.  Kinds beyond n_kinds are not reported. */
+ * (0 pull/moments, 1 interface, 2 collide, 3 fused interface+collide), the
+ * total milliseconds and the number of launches timed.  Kinds beyond
+ * n_kinds are not reported. */
 int cglbm_profile_begin(cglbm_handle *h, int32_t max_launches);
 int cglbm_profile_end(cglbm_handle *h, double *total_ms, int64_t *launches, int32_t n_kinds);
 

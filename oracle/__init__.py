@@ -113,6 +113,7 @@ def lib():
         L.orc_init_window.argtypes = [P, dp, dp, dp, C.c_uint64, C.c_double, C.c_int32,
                                       C.POINTER(C.c_int32), C.POINTER(C.c_int32), dp]
         L.orc_step.argtypes = [P, dp, C.c_int32]
+        L.orc_num_threads.restype = C.c_int
         for fn in ("orc_gradient", "orc_fields", "orc_init", "orc_init_window", "orc_step"):
             getattr(L, fn).restype = C.c_int
         _lib = L
@@ -280,3 +281,8 @@ def step(P: Params, f: np.ndarray, nsteps: int = 1) -> np.ndarray:
     if rc != 0:
         raise MemoryError("orc_step failed")
     return f
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().orc_num_threads())

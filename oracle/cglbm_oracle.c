@@ -21,6 +21,7 @@
 #include "cglbm_oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -443,6 +444,8 @@ double orc_noise(uint64_t seed, int32_t box, int64_t node, int32_t i, double amp
 /* ---------------------------------------------------------------------- */
 /* Grid level                                                              */
 /* ---------------------------------------------------------------------- */
+
+int orc_num_threads(void) { return omp_get_max_threads(); }
 
 int orc_is_solid(const orc_params *P, int32_t x, int32_t y, int32_t z) {
   (void)x;

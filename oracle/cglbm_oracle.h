@@ -73,6 +73,7 @@ int orc_init_window(const orc_params *P, const double *rho_r, const double *rho_
                     const int32_t *gdims, const int32_t *goff, double *f);
 int orc_step(const orc_params *P, double *f, int32_t nsteps);
 int orc_is_solid(const orc_params *P, int32_t x, int32_t y, int32_t z);
+int orc_num_threads(void);
 
 #ifdef __cplusplus
 }

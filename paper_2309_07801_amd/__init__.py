@@ -29,10 +29,11 @@ DIAG_NAMES = ("M_r", "M_b", "Px", "Py", "Pz", "p_in", "p_out", "R_eff", "cx", "c
               "KE", "n_nonfinite")
 FIELDS = ("rho_r", "rho_b", "phi", "p", "ux", "uy", "uz", "nx", "ny", "nz", "kappa",
           "Fx", "Fy", "Fz", "Qx", "Qy", "Qz")
-KERNEL_KINDS = ("pull", "interface", "collide")
+KERNEL_KINDS = ("pull", "interface", "collide", "fused")
 
 EXPORTED = ("cglbm_query_sizes", "cglbm_init", "cglbm_step", "cglbm_moments", "cglbm_reduce",
-            "cglbm_box_offset", "cglbm_profile_begin", "cglbm_profile_end", "cglbm_destroy",
+            "cglbm_box_offset", "cglbm_set_schedule", "cglbm_profile_begin",
+            "cglbm_profile_end", "cglbm_destroy",
             "cglbm_last_error", "cglbm_version")
 
 
@@ -94,6 +95,7 @@ def lib():
         L.cglbm_reduce.argtypes = [vp, C.POINTER(C.c_double), vp, i32, vp]
         L.cglbm_box_offset.argtypes = [vp, i32]
         L.cglbm_box_offset.restype = i64
+        L.cglbm_set_schedule.argtypes = [vp, i32]
         L.cglbm_profile_begin.argtypes = [vp, i32]
         L.cglbm_profile_end.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64), i32]
         L.cglbm_destroy.argtypes = [vp]
@@ -101,7 +103,8 @@ def lib():
         L.cglbm_last_error.restype = C.c_char_p
         L.cglbm_version.restype = C.c_char_p
         for fn in ("cglbm_query_sizes", "cglbm_init", "cglbm_step", "cglbm_moments",
-                   "cglbm_reduce", "cglbm_profile_begin", "cglbm_profile_end"):
+                   "cglbm_reduce", "cglbm_set_schedule", "cglbm_profile_begin",
+                   "cglbm_profile_end"):
             getattr(L, fn).restype = C.c_int
         _lib = L
     return _lib
@@ -219,10 +222,14 @@ class Simulation:
     def profile_begin(self, max_launches: int):
         _check(lib().cglbm_profile_begin(self.h, int(max_launches)))
 
+    def set_schedule(self, schedule: int):
+        _check(lib().cglbm_set_schedule(self.h, int(schedule)))
+
     def profile_end(self):
-        ms = (C.c_double * 3)()
-        cnt = (C.c_int64 * 3)()
-        _check(lib().cglbm_profile_end(self.h, ms, cnt, 3))
+        n = len(KERNEL_KINDS)
+        ms = (C.c_double * n)()
+        cnt = (C.c_int64 * n)()
+        _check(lib().cglbm_profile_end(self.h, ms, cnt, n))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNEL_KINDS)}
 
     def close(self):

@@ -13,6 +13,9 @@ DEPS = [os.path.join(HERE, "csrc", n) for n in ("cglbm.hip", "kernels.hpp", "lat
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # contract a*b+c only inside one source expression, so that the same
+    # arithmetic rounds the same way in every kernel it is inlined into
+    "-ffp-contract=on",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",

@@ -40,17 +40,18 @@ int fail(int code, const char *fmt, ...) {
                   __FILE__, __LINE__);                                                  \
   } while (0)
 
-constexpr int kTX = 8, kTY = 8, kTZ = 8;   // interface tile
+constexpr int kTX = 8, kTY = 8, kTZ = 8;   // interface tile (three-kernel schedule)
+constexpr int kFX = 32, kFY = 8, kFZ = 32; // fused column: x, y extent and z chunk
 constexpr int64_t kAlign = 64;             // node alignment of each box's base
 constexpr double kXi = 9.0 / 19.0;
 
-enum { KIND_PULL = 0, KIND_IFACE = 1, KIND_COLLIDE = 2, KIND_N = 3 };
+enum { KIND_PULL = 0, KIND_IFACE = 1, KIND_COLLIDE = 2, KIND_FUSED = 3, KIND_N = 4 };
 
 struct Layout {
   std::vector<BoxDev> boxes;
-  std::vector<int32_t> blk_box, tile_box;
+  std::vector<int32_t> blk_box, tile_box, col_box;
   int64_t total = 0;  // plane length (nodes, all boxes, aligned)
-  int32_t nblk = 0, ntile = 0;
+  int32_t nblk = 0, ntile = 0, ncol = 0;
 };
 
 int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
@@ -98,7 +99,7 @@ int validate(int32_t n_boxes, const cglbm_box_params *boxes, int32_t storage) {
 void build_layout(int32_t n_boxes, const cglbm_box_params *boxes, Layout &L) {
   L = Layout();
   int64_t off = 0;
-  int32_t blk = 0, tile = 0;
+  int32_t blk = 0, tile = 0, col = 0;
   for (int b = 0; b < n_boxes; ++b) {
     const cglbm_box_params &P = boxes[b];
     BoxDev B;
@@ -121,6 +122,15 @@ void build_layout(int32_t n_boxes, const cglbm_box_params *boxes, Layout &L) {
     const int32_t nt = B.tnx * B.tny * tnz;
     for (int32_t k = 0; k < nt; ++k) L.tile_box.push_back(b);
     tile += nt;
+    B.col0 = col;
+    B.ncx = (P.nx + kFX - 1) / kFX;
+    B.ncy = (P.ny + kFY - 1) / kFY;
+    const int32_t ncz = (P.nz + kFZ - 1) / kFZ;
+    const int32_t nc = B.ncx * B.ncy * ncz;
+    for (int32_t k = 0; k < nc; ++k) L.col_box.push_back(b);
+    col += nc;
+    B.fcx = make_fastdiv((uint32_t)B.ncx);
+    B.fcy = make_fastdiv((uint32_t)B.ncy);
     B.fdx = make_fastdiv((uint32_t)P.nx);
     B.fdy = make_fastdiv((uint32_t)P.ny);
     B.ftx = make_fastdiv((uint32_t)B.tnx);
@@ -142,6 +152,7 @@ void build_layout(int32_t n_boxes, const cglbm_box_params *boxes, Layout &L) {
   L.total = std::max<int64_t>(off, kAlign);
   L.nblk = blk;
   L.ntile = tile;
+  L.ncol = col;
 }
 
 // Host check of the division helper on the values a box can produce.
@@ -171,6 +182,8 @@ struct cglbm_handle {
   BoxDev *d_boxes = nullptr;
   int32_t *d_blk_box = nullptr;
   int32_t *d_tile_box = nullptr;
+  int32_t *d_col_box = nullptr;
+  int32_t schedule = 0;        // 0 fused, 1 three kernels
   double *d_part = nullptr;    // block partials of the reduction
   double *d_diag = nullptr;    // per box kNPart doubles
   double *d_centre = nullptr;  // per box 3 doubles
@@ -194,6 +207,14 @@ int launch_pull(cglbm_handle *h, hipStream_t s, int bounce) {
 int launch_iface(cglbm_handle *h, hipStream_t s, int write_kappa) {
   hipLaunchKernelGGL((k_interface<kTX, kTY, kTZ>), dim3(h->L.ntile), dim3(kBlock), 0, s,
                      h->d_boxes, h->d_tile_box, h->aux, h->L.total, write_kappa);
+  return CGLBM_OK;
+}
+
+int launch_fused(cglbm_handle *h, hipStream_t s, int write_pops, int export_fields) {
+  float *dst = (float *)h->pop[1 - h->cur];
+  hipLaunchKernelGGL((k_fused<kFX, kFY, kFZ, StoreF32>), dim3(h->L.ncol), dim3(kFX * kFY), 0, s,
+                     h->d_boxes, h->d_col_box, h->aux, dst, h->L.total, write_pops,
+                     export_fields);
   return CGLBM_OK;
 }
 
@@ -227,7 +248,10 @@ int check_launch() {
 int compute_fields(cglbm_handle *h, hipStream_t s, int write_kappa) {
   int rc = launch_pull(h, s, 0);
   if (rc) return rc;
-  rc = launch_iface(h, s, write_kappa);
+  if (h->schedule == 0)
+    rc = launch_fused(h, s, 0, 1);
+  else
+    rc = launch_iface(h, s, write_kappa);
   if (rc) return rc;
   return check_launch();
 }
@@ -300,6 +324,7 @@ int cglbm_init(cglbm_handle **out, int32_t n_boxes, const cglbm_box_params *boxe
       (e = hipMalloc(&h->d_boxes, sizeof(BoxDev) * n_boxes)) != hipSuccess ||
       (e = hipMalloc(&h->d_blk_box, sizeof(int32_t) * h->L.blk_box.size())) != hipSuccess ||
       (e = hipMalloc(&h->d_tile_box, sizeof(int32_t) * h->L.tile_box.size())) != hipSuccess ||
+      (e = hipMalloc(&h->d_col_box, sizeof(int32_t) * h->L.col_box.size())) != hipSuccess ||
       (e = hipMalloc(&h->d_part, sizeof(double) * kNPart * (size_t)h->L.nblk)) != hipSuccess ||
       (e = hipMalloc(&h->d_diag, sizeof(double) * kNPart * (size_t)n_boxes)) != hipSuccess ||
       (e = hipMalloc(&h->d_centre, sizeof(double) * 3 * (size_t)n_boxes)) != hipSuccess ||
@@ -310,6 +335,9 @@ int cglbm_init(cglbm_handle **out, int32_t n_boxes, const cglbm_box_params *boxe
           hipSuccess ||
       (e = hipMemcpyAsync(h->d_tile_box, h->L.tile_box.data(),
                           sizeof(int32_t) * h->L.tile_box.size(), hipMemcpyHostToDevice, s)) !=
+          hipSuccess ||
+      (e = hipMemcpyAsync(h->d_col_box, h->L.col_box.data(),
+                          sizeof(int32_t) * h->L.col_box.size(), hipMemcpyHostToDevice, s)) !=
           hipSuccess) {
     return cleanup(fail(CGLBM_EHIP, "init: %s", hipGetErrorString(e)));
   }
@@ -330,8 +358,12 @@ int cglbm_step(cglbm_handle *h, int32_t n_steps, void *stream) {
   hipStream_t s = (hipStream_t)stream;
   for (int32_t k = 0; k < n_steps; ++k) {
     int rc = timed(h, s, KIND_PULL, [&] { return launch_pull(h, s, 1); });
-    if (!rc) rc = timed(h, s, KIND_IFACE, [&] { return launch_iface(h, s, 0); });
-    if (!rc) rc = timed(h, s, KIND_COLLIDE, [&] { return launch_collide(h, s); });
+    if (h->schedule == 0) {
+      if (!rc) rc = timed(h, s, KIND_FUSED, [&] { return launch_fused(h, s, 1, 0); });
+    } else {
+      if (!rc) rc = timed(h, s, KIND_IFACE, [&] { return launch_iface(h, s, 0); });
+      if (!rc) rc = timed(h, s, KIND_COLLIDE, [&] { return launch_collide(h, s); });
+    }
     if (!rc) rc = check_launch();
     if (rc) return rc;
     h->cur = 1 - h->cur;
@@ -401,6 +433,14 @@ int cglbm_reduce(cglbm_handle *h, const double *centre, double *out, int32_t out
   return CGLBM_OK;
 }
 
+int cglbm_set_schedule(cglbm_handle *h, int32_t schedule) {
+  g_err.clear();
+  if (!h) return fail(CGLBM_ESTATE, "null handle");
+  if (schedule != 0 && schedule != 1) return fail(CGLBM_EINVAL, "unknown schedule %d", schedule);
+  h->schedule = schedule;
+  return CGLBM_OK;
+}
+
 int cglbm_profile_begin(cglbm_handle *h, int32_t max_launches) {
   g_err.clear();
   if (!h) return fail(CGLBM_ESTATE, "null handle");
@@ -444,6 +484,7 @@ void cglbm_destroy(cglbm_handle *h) {
   if (h->d_boxes) (void)hipFree(h->d_boxes);
   if (h->d_blk_box) (void)hipFree(h->d_blk_box);
   if (h->d_tile_box) (void)hipFree(h->d_tile_box);
+  if (h->d_col_box) (void)hipFree(h->d_col_box);
   if (h->d_part) (void)hipFree(h->d_part);
   if (h->d_diag) (void)hipFree(h->d_diag);
   if (h->d_centre) (void)hipFree(h->d_centre);

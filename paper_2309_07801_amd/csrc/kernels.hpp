@@ -39,6 +39,9 @@ struct BoxDev {
   int32_t tnx, tny;     // tiles along x, y
   FastDiv fdx, fdy;     // division by nx, ny
   FastDiv ftx, fty;     // division by tnx, tny
+  int32_t col0;         // first column block of the box (k_fused)
+  int32_t ncx, ncy;     // columns along x, y
+  FastDiv fcx, fcy;     // division by ncx, ncy
   float cs2r, cs2b;     // (c_s^k)^2 = xi (1 - alpha_k)
   float ir0r, ir0b;     // 1 / rho_k^0
   float nu_r, nu_b;
@@ -505,6 +508,357 @@ __global__ __launch_bounds__(kBlock) void k_init(const BoxDev *__restrict__ boxe
     const int64_t d = B.base + xd + (int64_t)B.nx * (yd + (int64_t)B.ny * zd);
     S::store(dst + (int64_t)i * plane + d, cr * ft);
     S::store(dst + (int64_t)(kQ + i) * plane + d, cb * ft);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_fused: interface stencils and collision in one pass.  A block owns a
+// TX x TY column of the box and marches along z over ZC output slabs.  Slab
+// s of the phase field enters a 3-slot LDS ring; n and |grad phi| of slab
+// s-1, and q = (p - rho c_s^2) u of slab s-2 follow in their own rings; the
+// correction term and the collision of slab s-3 complete the iteration.
+// Halo widths in x, y: 3 for phi, 2 for n, 1 for q.
+// ---------------------------------------------------------------------------
+template <int TX, int TY>
+struct FusedGeom {
+  static constexpr int NT = TX * TY;
+  static constexpr int R3X = TX + 6, R3Y = TY + 6, R3 = R3X * R3Y;
+  static constexpr int R2X = TX + 4, R2Y = TY + 4, R2 = R2X * R2Y;
+  static constexpr int R1X = TX + 2, R1Y = TY + 2, R1 = R1X * R1Y;
+  static constexpr int A_PER = (R3 + NT - 1) / NT;
+};
+
+template <int TX, int TY, int ZC, class S>
+__global__ __launch_bounds__(TX *TY) void k_fused(const BoxDev *__restrict__ boxes,
+                                                  const int32_t *__restrict__ col_box,
+                                                  float *__restrict__ aux,
+                                                  typename S::T *__restrict__ dst, int64_t plane,
+                                                  int write_pops, int export_fields) {
+  using G = FusedGeom<TX, TY>;
+  __shared__ float s_phi[3][G::R3];
+  __shared__ float s_n[3][4][G::R2];
+  __shared__ float s_q[3][3][G::R1];
+  __shared__ uint8_t s_sy[G::R3Y];
+
+  const int tid = threadIdx.x;
+  const int b = col_box[blockIdx.x];
+  const BoxDev B = boxes[b];
+  const uint32_t t = blockIdx.x - B.col0;
+  const uint32_t tyz = fdiv(t, B.fcx);
+  const int cx = (int)(t - tyz * (uint32_t)B.ncx);
+  const int cz = (int)fdiv(tyz, B.fcy);
+  const int cy = (int)(tyz - (uint32_t)cz * (uint32_t)B.ncy);
+  const int x0 = cx * TX, y0 = cy * TY, z0 = cz * ZC;
+  const int nx = B.nx, ny = B.ny, nz = B.nz;
+  const int z1 = min(z0 + ZC, nz);
+  const int64_t nxy = (int64_t)nx * ny;
+  const bool zwalls = (B.walls & 2u) != 0;
+
+  for (int i = tid; i < G::R3Y; i += G::NT) {
+    const int gy = wrap_any(y0 + i - 3, ny);
+    s_sy[i] = (B.walls & 1u) && (gy == 0 || gy == ny - 1);
+  }
+  // xy offsets of this thread's phase-field points (fixed over the march)
+  int a_off[G::A_PER];
+#pragma unroll
+  for (int k = 0; k < G::A_PER; ++k) {
+    const int i = tid + k * G::NT;
+    a_off[k] = 0;
+    if (i < G::R3) {
+      const int lx = i % G::R3X, ly = i / G::R3X;
+      a_off[k] = wrap_any(x0 + lx - 3, nx) + nx * wrap_any(y0 + ly - 3, ny);
+    }
+  }
+  // tile point of this thread
+  const int ox = tid % TX, oy = tid / TX;
+  const int gxo = x0 + ox, gyo = y0 + oy;
+  const bool in_xy = gxo < nx && gyo < ny;
+  const bool solid_y_o = (B.walls & 1u) && (gyo == 0 || gyo == ny - 1);
+  // interface values of the tile point, one slab behind the q ring
+  float h_nx = 0.f, h_ny = 0.f, h_nz = 0.f, h_Fx = 0.f, h_Fy = 0.f, h_Fz = 0.f, h_k = 0.f;
+  auto slab_solid = [&](int s) {
+    if (!zwalls) return false;
+    const int gz = wrap_any(s, nz);
+    return gz == 0 || gz == nz - 1;
+  };
+  __syncthreads();
+
+  for (int s = z0 - 3; s < z1 + 3; ++s) {
+    // ---- A: phase field of slab s (Eq. 14) ----
+    {
+      const int64_t zoff = B.base + nxy * wrap_any(s, nz);
+      float *ph = s_phi[(s + 3) % 3];
+#pragma unroll
+      for (int k = 0; k < G::A_PER; ++k) {
+        const int i = tid + k * G::NT;
+        if (i < G::R3) {
+          const int64_t node = zoff + a_off[k];
+          const float rr = aux[(int64_t)A_RR * plane + node] * B.ir0r;
+          const float rb = aux[(int64_t)A_RB * plane + node] * B.ir0b;
+          const float den = rr + rb;
+          ph[i] = den > 0.f ? (rr - rb) / den : 0.f;
+        }
+      }
+    }
+    __syncthreads();
+    // ---- B: grad phi and n of slab s-1 (Eqs. 17, 20) ----
+    if (s - 1 >= z0 - 2) {
+      const int sb = s - 1;
+      const bool sz_m = slab_solid(sb - 1), sz_c = slab_solid(sb), sz_p = slab_solid(sb + 1);
+      const float *pm = s_phi[(sb - 1 + 3) % 3];
+      const float *pc = s_phi[(sb + 3) % 3];
+      const float *pp = s_phi[(sb + 1 + 3) % 3];
+      float(*nn)[G::R2] = s_n[(sb + 3) % 3];
+      for (int i = tid; i < G::R2; i += G::NT) {
+        const int lx = i % G::R2X, ly = i / G::R2X;
+        const int c3 = (lx + 1) + G::R3X * (ly + 1);
+        float nxv = 0.f, nyv = 0.f, nzv = 0.f, mag = 0.f;
+        if (!(s_sy[ly + 1] | sz_c)) {
+          const float vc = pc[c3];
+          float v[3][3][3];
+#pragma unroll
+          for (int dz = -1; dz <= 1; ++dz) {
+            const float *pl = dz < 0 ? pm : (dz > 0 ? pp : pc);
+            const bool szd = dz < 0 ? sz_m : (dz > 0 ? sz_p : sz_c);
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy) {
+              const bool sd = szd | s_sy[ly + 1 + dy];
+#pragma unroll
+              for (int dx = -1; dx <= 1; ++dx)
+                v[dz + 1][dy + 1][dx + 1] = sd ? vc : pl[c3 + dx + G::R3X * dy];
+            }
+          }
+          float gx = 0.f, gy = 0.f, gz = 0.f;
+#pragma unroll
+          for (int a2 = 0; a2 < 3; ++a2)
+#pragma unroll
+            for (int b2 = 0; b2 < 3; ++b2) {
+              const float w = 0.5f * w1d(a2 - 1) * w1d(b2 - 1);
+              gx = fmaf(w, v[b2][a2][2] - v[b2][a2][0], gx);
+              gy = fmaf(w, v[b2][2][a2] - v[b2][0][a2], gy);
+              gz = fmaf(w, v[2][b2][a2] - v[0][b2][a2], gz);
+            }
+          mag = sqrtf(gx * gx + gy * gy + gz * gz);
+          if (mag > 1e-12f) {
+            const float inv = 1.0f / mag;
+            nxv = gx * inv;
+            nyv = gy * inv;
+            nzv = gz * inv;
+          } else {
+            mag = 0.f;
+          }
+        }
+        nn[0][i] = nxv;
+        nn[1][i] = nyv;
+        nn[2][i] = nzv;
+        nn[3][i] = mag;
+      }
+    }
+    __syncthreads();
+    // ---- C: grad n, kappa, F, u, q of slab s-2 (Eqs. 11, 15, 16, 65) ----
+    float f_nx = 0.f, f_ny = 0.f, f_nz = 0.f, f_Fx = 0.f, f_Fy = 0.f, f_Fz = 0.f, f_k = 0.f;
+    if (s - 2 >= z0 - 1) {
+      const int sc = s - 2;
+      const bool sz_m = slab_solid(sc - 1), sz_c = slab_solid(sc), sz_p = slab_solid(sc + 1);
+      const int64_t zoff = B.base + nxy * wrap_any(sc, nz);
+      float(*nm)[G::R2] = s_n[(sc - 1 + 3) % 3];
+      float(*nc)[G::R2] = s_n[(sc + 3) % 3];
+      float(*np)[G::R2] = s_n[(sc + 1 + 3) % 3];
+      float(*qq)[G::R1] = s_q[(sc + 3) % 3];
+      // first pass: the tile points in thread order, then the halo ring
+      for (int j = tid; j < G::R1; j += G::NT) {
+        int lx, ly;
+        if (j < G::NT) {
+          lx = (j % TX) + 1;
+          ly = (j / TX) + 1;
+        } else {
+          // halo points of the R1 region: top/bottom rows, then side columns
+          const int h = j - G::NT;
+          if (h < 2 * G::R1X) {
+            lx = h % G::R1X;
+            ly = (h / G::R1X) * (G::R1Y - 1);
+          } else {
+            const int h2 = h - 2 * G::R1X;
+            lx = (h2 & 1) * (G::R1X - 1);
+            ly = (h2 >> 1) + 1;
+          }
+        }
+        const int c2 = (lx + 1) + G::R2X * (ly + 1);
+        const int ri = lx + G::R1X * ly;
+        float qx = 0.f, qy = 0.f, qz = 0.f;
+        float kap = 0.f, Fx = 0.f, Fy = 0.f, Fz = 0.f;
+        const float nxv = nc[0][c2], nyv = nc[1][c2], nzv = nc[2][c2], mag = nc[3][c2];
+        if (!(s_sy[ly + 2] | sz_c)) {
+          float d[3][3];  // d[a][b] = d n_a / d x_b
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            const float vc = nc[a][c2];
+            float v[3][3][3];
+#pragma unroll
+            for (int dz = -1; dz <= 1; ++dz) {
+              const float *pl = dz < 0 ? nm[a] : (dz > 0 ? np[a] : nc[a]);
+              const bool szd = dz < 0 ? sz_m : (dz > 0 ? sz_p : sz_c);
+#pragma unroll
+              for (int dy = -1; dy <= 1; ++dy) {
+                const bool sd = szd | s_sy[ly + 2 + dy];
+#pragma unroll
+                for (int dx = -1; dx <= 1; ++dx)
+                  v[dz + 1][dy + 1][dx + 1] = sd ? vc : pl[c2 + dx + G::R2X * dy];
+              }
+            }
+            float gx = 0.f, gy = 0.f, gz = 0.f;
+#pragma unroll
+            for (int a2 = 0; a2 < 3; ++a2)
+#pragma unroll
+              for (int b2 = 0; b2 < 3; ++b2) {
+                const float w = 0.5f * w1d(a2 - 1) * w1d(b2 - 1);
+                gx = fmaf(w, v[b2][a2][2] - v[b2][a2][0], gx);
+                gy = fmaf(w, v[b2][2][a2] - v[b2][0][a2], gy);
+                gz = fmaf(w, v[2][b2][a2] - v[0][b2][a2], gz);
+              }
+            d[a][0] = gx;
+            d[a][1] = gy;
+            d[a][2] = gz;
+          }
+          const float div = d[0][0] + d[1][1] + d[2][2];
+          const float proj = nxv * (nxv * d[0][0] + nyv * d[0][1] + nzv * d[0][2]) +
+                             nyv * (nxv * d[1][0] + nyv * d[1][1] + nzv * d[1][2]) +
+                             nzv * (nxv * d[2][0] + nyv * d[2][1] + nzv * d[2][2]);
+          kap = proj - div;
+          const float hs = 0.5f * B.sigma * kap * mag;
+          Fx = fmaf(hs, nxv, B.Gx);
+          Fy = fmaf(hs, nyv, B.Gy);
+          Fz = fmaf(hs, nzv, B.Gz);
+          const int gx = wrap_any(x0 + lx - 1, nx), gy = wrap_any(y0 + ly - 1, ny);
+          const int64_t node = zoff + gx + (int64_t)nx * gy;
+          const float rr = aux[(int64_t)A_RR * plane + node];
+          const float rb = aux[(int64_t)A_RB * plane + node];
+          const float rho = rr + rb;
+          const float irho = 1.0f / rho;
+          const float ux = fmaf(0.5f, Fx, aux[(int64_t)A_JX * plane + node]) * irho;
+          const float uy = fmaf(0.5f, Fy, aux[(int64_t)A_JY * plane + node]) * irho;
+          const float uz = fmaf(0.5f, Fz, aux[(int64_t)A_JZ * plane + node]) * irho;
+          const float dev = rr * B.cs2r + rb * B.cs2b - rho * kCs2;
+          qx = dev * ux;
+          qy = dev * uy;
+          qz = dev * uz;
+        }
+        qq[0][ri] = qx;
+        qq[1][ri] = qy;
+        qq[2][ri] = qz;
+        if (j < G::NT) {
+          f_nx = nxv;
+          f_ny = nyv;
+          f_nz = nzv;
+          f_Fx = Fx;
+          f_Fy = Fy;
+          f_Fz = Fz;
+          f_k = kap;
+        }
+      }
+    }
+    __syncthreads();
+    // ---- D: Q and the collision of slab s-3 (Eqs. 18-19, 25, 65-67) ----
+    if (s - 3 >= z0) {
+      const int sd = s - 3;
+      const int gz = wrap_any(sd, nz);
+      if (in_xy && !(solid_y_o || slab_solid(sd))) {
+        const bool sz_m = slab_solid(sd - 1), sz_p = slab_solid(sd + 1);
+        float(*qm)[G::R1] = s_q[(sd - 1 + 3) % 3];
+        float(*qc)[G::R1] = s_q[(sd + 3) % 3];
+        float(*qp)[G::R1] = s_q[(sd + 1 + 3) % 3];
+        const int c1 = (ox + 1) + G::R1X * (oy + 1);
+        // d q_x / dx: pairs along x over (dy, dz); likewise y and z
+        float Qx = 0.f, Qy = 0.f, Qz = 0.f;
+#pragma unroll
+        for (int a2 = -1; a2 <= 1; ++a2)
+#pragma unroll
+          for (int b2 = -1; b2 <= 1; ++b2) {
+            const float w = 0.5f * w1d(a2) * w1d(b2);
+            {  // x: a2 = dy, b2 = dz
+              const float *pl = b2 < 0 ? qm[0] : (b2 > 0 ? qp[0] : qc[0]);
+              const bool sdd = (b2 < 0 ? sz_m : (b2 > 0 ? sz_p : false)) | s_sy[oy + 3 + a2];
+              const float vc = qc[0][c1];
+              const float vp = sdd ? vc : pl[c1 + 1 + G::R1X * a2];
+              const float vm = sdd ? vc : pl[c1 - 1 + G::R1X * a2];
+              Qx = fmaf(w, vp - vm, Qx);
+            }
+            {  // y: a2 = dx, b2 = dz
+              const float *pl = b2 < 0 ? qm[1] : (b2 > 0 ? qp[1] : qc[1]);
+              const bool szd = b2 < 0 ? sz_m : (b2 > 0 ? sz_p : false);
+              const float vc = qc[1][c1];
+              const float vp = (szd | s_sy[oy + 4]) ? vc : pl[c1 + a2 + G::R1X];
+              const float vm = (szd | s_sy[oy + 2]) ? vc : pl[c1 + a2 - G::R1X];
+              Qy = fmaf(w, vp - vm, Qy);
+            }
+            {  // z: a2 = dx, b2 = dy
+              const bool syd = s_sy[oy + 3 + b2];
+              const float vc = qc[2][c1];
+              const float vp = (sz_p | syd) ? vc : qp[2][c1 + a2 + G::R1X * b2];
+              const float vm = (sz_m | syd) ? vc : qm[2][c1 + a2 + G::R1X * b2];
+              Qz = fmaf(w, vp - vm, Qz);
+            }
+          }
+        Qx *= -3.0f;
+        Qy *= -3.0f;
+        Qz *= -3.0f;
+        const int64_t node = B.base + gxo + (int64_t)nx * gyo + nxy * gz;
+        if (write_pops) {
+          NodeIn in;
+          in.rr = aux[(int64_t)A_RR * plane + node];
+          in.rb = aux[(int64_t)A_RB * plane + node];
+          in.jx = aux[(int64_t)A_JX * plane + node];
+          in.jy = aux[(int64_t)A_JY * plane + node];
+          in.jz = aux[(int64_t)A_JZ * plane + node];
+          in.pxx = aux[(int64_t)A_PXX * plane + node];
+          in.pyy = aux[(int64_t)A_PYY * plane + node];
+          in.pzz = aux[(int64_t)A_PZZ * plane + node];
+          in.pxy = aux[(int64_t)A_PXY * plane + node];
+          in.pxz = aux[(int64_t)A_PXZ * plane + node];
+          in.pyz = aux[(int64_t)A_PYZ * plane + node];
+          in.nx = h_nx;
+          in.ny = h_ny;
+          in.nz = h_nz;
+          in.Fx = h_Fx;
+          in.Fy = h_Fy;
+          in.Fz = h_Fz;
+          in.Qx = Qx;
+          in.Qy = Qy;
+          in.Qz = Qz;
+          float fr[kQ], fb[kQ];
+          collide_node(B, in, fr, fb);
+#pragma unroll
+          for (int i = 0; i < kQ; ++i) {
+            S::store(dst + (int64_t)i * plane + node, fr[i]);
+            S::store(dst + (int64_t)(kQ + i) * plane + node, fb[i]);
+          }
+        }
+        if (export_fields) {
+          aux[(int64_t)A_NX * plane + node] = h_nx;
+          aux[(int64_t)A_NY * plane + node] = h_ny;
+          aux[(int64_t)A_NZ * plane + node] = h_nz;
+          aux[(int64_t)A_FX * plane + node] = h_Fx;
+          aux[(int64_t)A_FY * plane + node] = h_Fy;
+          aux[(int64_t)A_FZ * plane + node] = h_Fz;
+          aux[(int64_t)A_QX * plane + node] = Qx;
+          aux[(int64_t)A_QY * plane + node] = Qy;
+          aux[(int64_t)A_QZ * plane + node] = Qz;
+          aux[(int64_t)A_KAPPA * plane + node] = h_k;
+        }
+      } else if (export_fields && in_xy) {
+        const int64_t node = B.base + gxo + (int64_t)nx * gyo + nxy * gz;
+#pragma unroll
+        for (int k = A_NX; k <= A_KAPPA; ++k) aux[(int64_t)k * plane + node] = 0.f;
+      }
+    }
+    // the interface values of slab s-2 become those of the next collision
+    h_nx = f_nx;
+    h_ny = f_ny;
+    h_nz = f_nz;
+    h_Fx = f_Fx;
+    h_Fy = f_Fy;
+    h_Fz = f_Fz;
+    h_k = f_k;
   }
 }
 
