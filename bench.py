@@ -42,7 +42,23 @@ def parse():
     ap.add_argument("--size", type=int, default=256, help="box edge (default 256)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--variant", type=int, default=-1,
+                    help="fused launch geometry (default: autotune)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 2 GiB device copy (counter calibration)")
     return ap.parse_args()
+
+
+def copy_probe():
+    """A plain copy kernel of known size: 2 GiB read, 2 GiB written, 5 times."""
+    import torch
+    n = 2 ** 29
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_each_way": n * 4, "launches": 5}))
 
 
 def cpu_baseline(w, seconds):
@@ -86,6 +102,9 @@ def main():
     import paper_2309_07801_amd as pkg
     import workloads as WL
 
+    if args.copy_probe:
+        copy_probe()
+        return
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
@@ -96,10 +115,17 @@ def main():
                          noise=w.noise)
     fluid = box.fluid_nodes()
     d0 = sim.reduce()[0]
+    sim.step(2)
+    if args.variant >= 0:
+        sim.set_variant(args.variant)
+        tune_ms = []
+    else:
+        tune_ms = sim.autotune(reps=5)
+    variant = pkg.variant_info(sim.variant())
     sim.step(args.warmup)
     torch.cuda.synchronize()
 
-    sim.profile_begin(3 * args.steps)
+    sim.profile_begin(4 * args.steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(args.steps)
@@ -140,6 +166,8 @@ def main():
                      "bytes_per_node": KERNEL_BYTES[dom]},
         "step_roofline_frac": round(mlups * 1e6 * STEP_BYTES / (HBM_PEAK_GBS * 1e9), 4),
         "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in kern.items()},
+        "fused_variant": variant,
+        "autotune_ms": [round(m, 4) for m in tune_ms],
         "mass_drift": [float((d1[0] - d0[0]) / d0[0]), float((d1[1] - d0[1]) / d0[1])],
         "nonfinite": int(d1[12]),
     }

@@ -149,6 +149,22 @@ int64_t cglbm_box_offset(const cglbm_handle *h, int32_t box);
  * Returns CGLBM_EINVAL for other values. */
 int cglbm_set_schedule(cglbm_handle *h, int32_t schedule);
 
+/* Launch geometries of the fused kernel (all bitwise equivalent).
+ * cglbm_num_variants: how many; cglbm_variant_info: info[0..3] = column
+ * extent x, y, z chunk, minimum waves per SIMD; cglbm_set_variant selects one
+ * (synchronizes the stream); cglbm_get_variant returns the current one. */
+int cglbm_num_variants(void);
+int cglbm_variant_info(int32_t variant, int32_t *info);
+int cglbm_set_variant(cglbm_handle *h, int32_t variant, void *stream);
+int cglbm_get_variant(const cglbm_handle *h);
+
+/* Autotuner: time every fused variant `reps` times on the current state
+ * (the stored state is not advanced: the fused kernel is re-run on the same
+ * inputs) and select the fastest.  ms_per_variant (optional, length
+ * cglbm_num_variants()) receives the mean milliseconds per launch.
+ * Synchronizes the stream. */
+int cglbm_autotune(cglbm_handle *h, int32_t reps, double *ms_per_variant, void *stream);
+
 /* Per-kernel timing with HIP events recorded on the caller's stream around
  * every launch of the step.  begin: reserve room for max_launches launches;
  * end: synchronize the events and return, per kernel kind

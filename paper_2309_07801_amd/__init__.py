@@ -32,8 +32,9 @@ FIELDS = ("rho_r", "rho_b", "phi", "p", "ux", "uy", "uz", "nx", "ny", "nz", "kap
 KERNEL_KINDS = ("pull", "interface", "collide", "fused")
 
 EXPORTED = ("cglbm_query_sizes", "cglbm_init", "cglbm_step", "cglbm_moments", "cglbm_reduce",
-            "cglbm_box_offset", "cglbm_set_schedule", "cglbm_profile_begin",
-            "cglbm_profile_end", "cglbm_destroy",
+            "cglbm_box_offset", "cglbm_set_schedule", "cglbm_num_variants",
+            "cglbm_variant_info", "cglbm_set_variant", "cglbm_get_variant", "cglbm_autotune",
+            "cglbm_profile_begin", "cglbm_profile_end", "cglbm_destroy",
             "cglbm_last_error", "cglbm_version")
 
 
@@ -96,6 +97,11 @@ def lib():
         L.cglbm_box_offset.argtypes = [vp, i32]
         L.cglbm_box_offset.restype = i64
         L.cglbm_set_schedule.argtypes = [vp, i32]
+        L.cglbm_num_variants.argtypes = []
+        L.cglbm_variant_info.argtypes = [i32, C.POINTER(i32)]
+        L.cglbm_set_variant.argtypes = [vp, i32, vp]
+        L.cglbm_get_variant.argtypes = [vp]
+        L.cglbm_autotune.argtypes = [vp, i32, C.POINTER(C.c_double), vp]
         L.cglbm_profile_begin.argtypes = [vp, i32]
         L.cglbm_profile_end.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64), i32]
         L.cglbm_destroy.argtypes = [vp]
@@ -103,8 +109,9 @@ def lib():
         L.cglbm_last_error.restype = C.c_char_p
         L.cglbm_version.restype = C.c_char_p
         for fn in ("cglbm_query_sizes", "cglbm_init", "cglbm_step", "cglbm_moments",
-                   "cglbm_reduce", "cglbm_set_schedule", "cglbm_profile_begin",
-                   "cglbm_profile_end"):
+                   "cglbm_reduce", "cglbm_set_schedule", "cglbm_num_variants",
+                   "cglbm_variant_info", "cglbm_set_variant", "cglbm_get_variant",
+                   "cglbm_autotune", "cglbm_profile_begin", "cglbm_profile_end"):
             getattr(L, fn).restype = C.c_int
         _lib = L
     return _lib
@@ -121,6 +128,16 @@ def query_sizes(params: Sequence[BoxParams], storage: int = FP32):
     _check(lib().cglbm_query_sizes(len(params), arr, storage, C.byref(pop), C.byref(aux),
                                    C.byref(tot)))
     return pop.value, aux.value, tot.value
+
+
+def num_variants() -> int:
+    return int(lib().cglbm_num_variants())
+
+
+def variant_info(v: int):
+    info = (C.c_int32 * 4)()
+    _check(lib().cglbm_variant_info(int(v), info))
+    return {"tx": info[0], "ty": info[1], "zc": info[2], "min_waves": info[3]}
 
 
 def _stream_ptr(stream) -> int:
@@ -221,6 +238,20 @@ class Simulation:
 
     def profile_begin(self, max_launches: int):
         _check(lib().cglbm_profile_begin(self.h, int(max_launches)))
+
+    def set_variant(self, v: int):
+        _check(lib().cglbm_set_variant(self.h, int(v), _stream_ptr(self.stream)))
+
+    def variant(self) -> int:
+        return int(lib().cglbm_get_variant(self.h))
+
+    def autotune(self, reps: int = 5):
+        """Time every fused launch geometry and keep the fastest; returns the
+        mean milliseconds per variant."""
+        n = num_variants()
+        ms = (C.c_double * n)()
+        _check(lib().cglbm_autotune(self.h, int(reps), ms, _stream_ptr(self.stream)))
+        return list(ms)
 
     def set_schedule(self, schedule: int):
         _check(lib().cglbm_set_schedule(self.h, int(schedule)))

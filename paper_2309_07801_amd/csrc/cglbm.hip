@@ -41,31 +41,57 @@ int fail(int code, const char *fmt, ...) {
   } while (0)
 
 constexpr int kTX = 8, kTY = 8, kTZ = 8;   // interface tile (three-kernel schedule)
-constexpr int kFX = 32, kFY = 8, kFZ = 32; // fused column: x, y extent and z chunk
+
+// Launch geometries of the fused kernel: column extent in x and y, z chunk,
+// minimum waves per SIMD requested from the register allocator.  Every
+// variant performs the same arithmetic per node (results are bitwise equal);
+// cglbm_autotune picks the fastest for the boxes at hand.
+using FusedFn = void (*)(const BoxDev *, const int32_t *, float *, float *, int64_t, int, int);
+struct FusedVariant {
+  int tx, ty, zc, minw;
+  FusedFn fn;        // periodic boxes only
+  FusedFn fn_walls;  // any box with solid layers
+};
+#define FV(TX, TY, ZC, MW) \
+  {TX, TY, ZC, MW, k_fused<TX, TY, ZC, MW, false, StoreF32>, k_fused<TX, TY, ZC, MW, true, StoreF32>}
+const FusedVariant kFusedVariants[] = {
+    FV(32, 8, 32, 4),  FV(32, 8, 64, 4),  FV(32, 8, 16, 4), FV(32, 8, 32, 1),
+    FV(32, 16, 32, 4), FV(32, 16, 64, 4), FV(64, 4, 32, 4), FV(32, 4, 32, 4),
+    FV(32, 8, 32, 5),
+};
+#undef FV
+constexpr int kNumFused = (int)(sizeof(kFusedVariants) / sizeof(kFusedVariants[0]));
 constexpr int64_t kAlign = 64;             // node alignment of each box's base
 constexpr double kXi = 9.0 / 19.0;
 
 enum { KIND_PULL = 0, KIND_IFACE = 1, KIND_COLLIDE = 2, KIND_FUSED = 3, KIND_N = 4 };
 
+int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
 struct Layout {
   std::vector<BoxDev> boxes;
   std::vector<int32_t> blk_box, tile_box, col_box;
   int64_t total = 0;  // plane length (nodes, all boxes, aligned)
-  int32_t nblk = 0, ntile = 0, ncol = 0;
+  int32_t nblk = 0, ntile = 0, ncol = 0, nblk_pad = 0;
+  bool walls = false;
 };
-
-int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
 int validate(int32_t n_boxes, const cglbm_box_params *boxes, int32_t storage) {
   if (n_boxes <= 0 || !boxes) return fail(CGLBM_EINVAL, "n_boxes must be > 0 and boxes non-NULL");
   if (storage != CGLBM_FP32)
     return fail(CGLBM_EUNSUPPORTED, "storage %d is not built (only CGLBM_FP32)", storage);
+  int64_t total = 0;
   for (int b = 0; b < n_boxes; ++b) {
     const cglbm_box_params &P = boxes[b];
     if (P.nx < 1 || P.ny < 1 || P.nz < 1)
       return fail(CGLBM_EINVAL, "box %d: extents must be >= 1", b);
-    if ((int64_t)P.nx * P.ny * P.nz >= (1ll << 31))
-      return fail(CGLBM_EINVAL, "box %d: more than 2^31-1 nodes", b);
+    total += align_up((int64_t)P.nx * P.ny * P.nz, kAlign);
+    if (total >= (1ll << 30))
+      return fail(CGLBM_EINVAL, "all boxes together exceed 2^30 nodes");
+    if (P.nx < 1 || P.ny < 1 || P.nz < 1)
+      return fail(CGLBM_EINVAL, "box %d: extents must be >= 1", b);
+    if ((int64_t)P.nx * P.ny * P.nz >= (1ll << 30))
+      return fail(CGLBM_EINVAL, "box %d: more than 2^30 nodes", b);
     if (P.walls & ~3u) return fail(CGLBM_EINVAL, "box %d: unknown wall bits 0x%x", b, P.walls);
     if ((P.walls & 1u) && P.ny < 3) return fail(CGLBM_EINVAL, "box %d: y walls need ny >= 3", b);
     if ((P.walls & 2u) && P.nz < 3) return fail(CGLBM_EINVAL, "box %d: z walls need nz >= 3", b);
@@ -99,7 +125,7 @@ int validate(int32_t n_boxes, const cglbm_box_params *boxes, int32_t storage) {
 void build_layout(int32_t n_boxes, const cglbm_box_params *boxes, Layout &L) {
   L = Layout();
   int64_t off = 0;
-  int32_t blk = 0, tile = 0, col = 0;
+  int32_t blk = 0, tile = 0;
   for (int b = 0; b < n_boxes; ++b) {
     const cglbm_box_params &P = boxes[b];
     BoxDev B;
@@ -122,15 +148,6 @@ void build_layout(int32_t n_boxes, const cglbm_box_params *boxes, Layout &L) {
     const int32_t nt = B.tnx * B.tny * tnz;
     for (int32_t k = 0; k < nt; ++k) L.tile_box.push_back(b);
     tile += nt;
-    B.col0 = col;
-    B.ncx = (P.nx + kFX - 1) / kFX;
-    B.ncy = (P.ny + kFY - 1) / kFY;
-    const int32_t ncz = (P.nz + kFZ - 1) / kFZ;
-    const int32_t nc = B.ncx * B.ncy * ncz;
-    for (int32_t k = 0; k < nc; ++k) L.col_box.push_back(b);
-    col += nc;
-    B.fcx = make_fastdiv((uint32_t)B.ncx);
-    B.fcy = make_fastdiv((uint32_t)B.ncy);
     B.fdx = make_fastdiv((uint32_t)P.nx);
     B.fdy = make_fastdiv((uint32_t)P.ny);
     B.ftx = make_fastdiv((uint32_t)B.tnx);
@@ -148,11 +165,35 @@ void build_layout(int32_t n_boxes, const cglbm_box_params *boxes, Layout &L) {
     B.Gy = (float)P.body_force[1];
     B.Gz = (float)P.body_force[2];
     L.boxes.push_back(B);
+    if (P.walls) L.walls = true;
   }
   L.total = std::max<int64_t>(off, kAlign);
   L.nblk = blk;
   L.ntile = tile;
-  L.ncol = col;
+  // grids remapped across XCDs are padded to a multiple of 8 idle blocks
+  L.nblk_pad = (int32_t)align_up(blk, 8);
+  while ((int32_t)L.blk_box.size() < L.nblk_pad) L.blk_box.push_back(-1);
+}
+
+// Column table of fused variant v: fills the per-box column fields.
+void build_columns(Layout &L, int v) {
+  const FusedVariant &F = kFusedVariants[v];
+  L.col_box.clear();
+  int32_t col = 0;
+  for (size_t b = 0; b < L.boxes.size(); ++b) {
+    BoxDev &B = L.boxes[b];
+    B.col0 = col;
+    B.ncx = (B.nx + F.tx - 1) / F.tx;
+    B.ncy = (B.ny + F.ty - 1) / F.ty;
+    const int32_t ncz = (B.nz + F.zc - 1) / F.zc;
+    const int32_t nc = B.ncx * B.ncy * ncz;
+    for (int32_t k = 0; k < nc; ++k) L.col_box.push_back((int32_t)b);
+    col += nc;
+    B.fcx = make_fastdiv((uint32_t)B.ncx);
+    B.fcy = make_fastdiv((uint32_t)B.ncy);
+  }
+  L.ncol = (int32_t)align_up(col, 8);
+  while ((int32_t)L.col_box.size() < L.ncol) L.col_box.push_back(-1);
 }
 
 // Host check of the division helper on the values a box can produce.
@@ -184,6 +225,8 @@ struct cglbm_handle {
   int32_t *d_tile_box = nullptr;
   int32_t *d_col_box = nullptr;
   int32_t schedule = 0;        // 0 fused, 1 three kernels
+  int32_t variant = 0;         // fused launch geometry
+  size_t col_cap = 0;          // capacity of d_col_box (entries)
   double *d_part = nullptr;    // block partials of the reduction
   double *d_diag = nullptr;    // per box kNPart doubles
   double *d_centre = nullptr;  // per box 3 doubles
@@ -199,7 +242,7 @@ namespace {
 int launch_pull(cglbm_handle *h, hipStream_t s, int bounce) {
   float *src = (float *)h->pop[h->cur];
   float *dst = (float *)h->pop[1 - h->cur];
-  hipLaunchKernelGGL(k_pull<StoreF32>, dim3(h->L.nblk), dim3(kBlock), 0, s, h->d_boxes,
+  hipLaunchKernelGGL(k_pull<StoreF32>, dim3(h->L.nblk_pad), dim3(kBlock), 0, s, h->d_boxes,
                      h->d_blk_box, src, dst, h->aux, h->L.total, bounce);
   return CGLBM_OK;
 }
@@ -211,16 +254,41 @@ int launch_iface(cglbm_handle *h, hipStream_t s, int write_kappa) {
 }
 
 int launch_fused(cglbm_handle *h, hipStream_t s, int write_pops, int export_fields) {
+  const FusedVariant &F = kFusedVariants[h->variant];
+  const BoxDev *boxes = h->d_boxes;
+  const int32_t *cols = h->d_col_box;
+  float *aux = h->aux;
   float *dst = (float *)h->pop[1 - h->cur];
-  hipLaunchKernelGGL((k_fused<kFX, kFY, kFZ, StoreF32>), dim3(h->L.ncol), dim3(kFX * kFY), 0, s,
-                     h->d_boxes, h->d_col_box, h->aux, dst, h->L.total, write_pops,
-                     export_fields);
+  int64_t plane = h->L.total;
+  void *args[] = {(void *)&boxes, (void *)&cols, (void *)&aux, (void *)&dst,
+                  (void *)&plane, (void *)&write_pops, (void *)&export_fields};
+  HIP_TRY(hipLaunchKernel((const void *)(h->L.walls ? F.fn_walls : F.fn), dim3(h->L.ncol),
+                          dim3(F.tx * F.ty), args, 0, s));
+  return CGLBM_OK;
+}
+
+// Select fused variant v: rebuild and upload the column tables.
+int select_variant(cglbm_handle *h, int v, hipStream_t s) {
+  build_columns(h->L, v);
+  if (h->L.col_box.size() > h->col_cap) {
+    if (h->d_col_box) HIP_TRY(hipFree(h->d_col_box));
+    h->d_col_box = nullptr;
+    HIP_TRY(hipMalloc(&h->d_col_box, sizeof(int32_t) * h->L.col_box.size()));
+    h->col_cap = h->L.col_box.size();
+  }
+  HIP_TRY(hipMemcpyAsync(h->d_col_box, h->L.col_box.data(), sizeof(int32_t) * h->L.col_box.size(),
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(h->d_boxes, h->L.boxes.data(), sizeof(BoxDev) * h->L.boxes.size(),
+                         hipMemcpyHostToDevice, s));
+  // pageable host sources: make sure the copies completed before the vectors change
+  HIP_TRY(hipStreamSynchronize(s));
+  h->variant = v;
   return CGLBM_OK;
 }
 
 int launch_collide(cglbm_handle *h, hipStream_t s) {
   float *dst = (float *)h->pop[1 - h->cur];
-  hipLaunchKernelGGL(k_collide<StoreF32>, dim3(h->L.nblk), dim3(kBlock), 0, s, h->d_boxes,
+  hipLaunchKernelGGL(k_collide<StoreF32>, dim3(h->L.nblk_pad), dim3(kBlock), 0, s, h->d_boxes,
                      h->d_blk_box, h->aux, dst, h->L.total);
   return CGLBM_OK;
 }
@@ -324,7 +392,6 @@ int cglbm_init(cglbm_handle **out, int32_t n_boxes, const cglbm_box_params *boxe
       (e = hipMalloc(&h->d_boxes, sizeof(BoxDev) * n_boxes)) != hipSuccess ||
       (e = hipMalloc(&h->d_blk_box, sizeof(int32_t) * h->L.blk_box.size())) != hipSuccess ||
       (e = hipMalloc(&h->d_tile_box, sizeof(int32_t) * h->L.tile_box.size())) != hipSuccess ||
-      (e = hipMalloc(&h->d_col_box, sizeof(int32_t) * h->L.col_box.size())) != hipSuccess ||
       (e = hipMalloc(&h->d_part, sizeof(double) * kNPart * (size_t)h->L.nblk)) != hipSuccess ||
       (e = hipMalloc(&h->d_diag, sizeof(double) * kNPart * (size_t)n_boxes)) != hipSuccess ||
       (e = hipMalloc(&h->d_centre, sizeof(double) * 3 * (size_t)n_boxes)) != hipSuccess ||
@@ -335,12 +402,10 @@ int cglbm_init(cglbm_handle **out, int32_t n_boxes, const cglbm_box_params *boxe
           hipSuccess ||
       (e = hipMemcpyAsync(h->d_tile_box, h->L.tile_box.data(),
                           sizeof(int32_t) * h->L.tile_box.size(), hipMemcpyHostToDevice, s)) !=
-          hipSuccess ||
-      (e = hipMemcpyAsync(h->d_col_box, h->L.col_box.data(),
-                          sizeof(int32_t) * h->L.col_box.size(), hipMemcpyHostToDevice, s)) !=
           hipSuccess) {
     return cleanup(fail(CGLBM_EHIP, "init: %s", hipGetErrorString(e)));
   }
+  if ((rc = select_variant(h, 0, s))) return cleanup(rc);
   // the stored state lives in pop[0]
   h->cur = 0;
   hipLaunchKernelGGL(k_init<StoreF32>, dim3(h->L.nblk), dim3(kBlock), 0, s, h->d_boxes,
@@ -439,6 +504,67 @@ int cglbm_set_schedule(cglbm_handle *h, int32_t schedule) {
   if (schedule != 0 && schedule != 1) return fail(CGLBM_EINVAL, "unknown schedule %d", schedule);
   h->schedule = schedule;
   return CGLBM_OK;
+}
+
+int cglbm_num_variants(void) { return kNumFused; }
+
+int cglbm_variant_info(int32_t v, int32_t *info) {
+  g_err.clear();
+  if (v < 0 || v >= kNumFused || !info) return fail(CGLBM_EINVAL, "bad variant %d", v);
+  info[0] = kFusedVariants[v].tx;
+  info[1] = kFusedVariants[v].ty;
+  info[2] = kFusedVariants[v].zc;
+  info[3] = kFusedVariants[v].minw;
+  return CGLBM_OK;
+}
+
+int cglbm_set_variant(cglbm_handle *h, int32_t v, void *stream) {
+  g_err.clear();
+  if (!h) return fail(CGLBM_ESTATE, "null handle");
+  if (v < 0 || v >= kNumFused) return fail(CGLBM_EINVAL, "variant %d out of range", v);
+  return select_variant(h, v, (hipStream_t)stream);
+}
+
+int cglbm_get_variant(const cglbm_handle *h) { return h ? h->variant : -1; }
+
+int cglbm_autotune(cglbm_handle *h, int32_t reps, double *ms_per_variant, void *stream) {
+  g_err.clear();
+  if (!h) return fail(CGLBM_ESTATE, "null handle");
+  if (reps < 1) return fail(CGLBM_EINVAL, "reps must be >= 1");
+  hipStream_t s = (hipStream_t)stream;
+  // the fused kernel is idempotent for a fixed pull: time every variant on
+  // the same inputs; the stored state is unchanged afterwards
+  int rc = launch_pull(h, s, 1);
+  if (rc || (rc = check_launch())) return rc;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int best = h->variant;
+  double best_ms = 1e300;
+  for (int v = 0; v < kNumFused; ++v) {
+    if ((rc = select_variant(h, v, s))) break;
+    if ((rc = launch_fused(h, s, 1, 0))) break;
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps && !rc; ++r) rc = launch_fused(h, s, 1, 0);
+    (void)hipEventRecord(e1, s);
+    if (rc || (rc = check_launch())) break;
+    if (hipEventSynchronize(e1) != hipSuccess) {
+      rc = fail(CGLBM_EHIP, "autotune: event synchronize failed");
+      break;
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    const double avg = (double)ms / reps;
+    if (ms_per_variant) ms_per_variant[v] = avg;
+    if (avg < best_ms) {
+      best_ms = avg;
+      best = v;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  return select_variant(h, best, s);
 }
 
 int cglbm_profile_begin(cglbm_handle *h, int32_t max_launches) {

@@ -52,6 +52,20 @@ struct BoxDev {
 
 constexpr int kBlock = 256;
 
+// Plane p of a SoA array: a uniform (scalar) base pointer.  Node offsets are
+// 32-bit (the host limits all boxes together to 2^30 nodes), so every access
+// is a scalar base plus one 32-bit vector offset shared by all planes.
+#define PL(ptr, p) ((ptr) + (int64_t)(p) * plane)
+
+// Workgroups are dispatched to the 8 XCDs in round-robin order.  Remap them
+// so that each XCD, with its own L2, works through a contiguous range of
+// logical blocks: neighbouring rows and columns then share cached halo lines.
+// Grids using this are padded to a multiple of 8 with idle blocks.
+__device__ __forceinline__ uint32_t xcd_block() {
+  const uint32_t per = gridDim.x >> 3;
+  return (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+}
+
 __device__ __forceinline__ int wrap_once(int v, int n) {
   // v in [-n, 2n)
   return v < 0 ? v + n : (v >= n ? v - n : v);
@@ -88,9 +102,11 @@ __global__ __launch_bounds__(kBlock) void k_pull(const BoxDev *__restrict__ boxe
                                                  typename S::T *__restrict__ dst,
                                                  float *__restrict__ aux, int64_t plane,
                                                  int bounce) {
-  const int b = blk_box[blockIdx.x];
+  const uint32_t lb = xcd_block();
+  const int b = blk_box[lb];
+  if (b < 0) return;
   const BoxDev B = boxes[b];
-  const int64_t local = (int64_t)(blockIdx.x - B.blk0) * kBlock + threadIdx.x;
+  const int64_t local = (int64_t)(lb - B.blk0) * kBlock + threadIdx.x;
   if (local >= B.n) return;
   const uint32_t l = (uint32_t)local;
   const uint32_t yz = fdiv(l, B.fdx);
@@ -102,30 +118,31 @@ __global__ __launch_bounds__(kBlock) void k_pull(const BoxDev *__restrict__ boxe
   const int xs[3] = {wrap_once(x + 1, nx), x, wrap_once(x - 1, nx)};
   const int ys[3] = {wrap_once(y + 1, ny), y, wrap_once(y - 1, ny)};
   const int zs[3] = {wrap_once(z + 1, nz), z, wrap_once(z - 1, nz)};
-  int64_t row[3][3];
+  uint32_t row[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) row[a][c] = B.base + (int64_t)nx * (ys[a] + (int64_t)ny * zs[c]);
+    for (int c = 0; c < 3; ++c)
+      row[a][c] = (uint32_t)B.base + (uint32_t)nx * ((uint32_t)ys[a] + (uint32_t)ny * (uint32_t)zs[c]);
 
   float fr[kQ], fb[kQ];
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
-    const int64_t s = row[kCY[i] + 1][kCZ[i] + 1] + xs[kCX[i] + 1];
-    fr[i] = S::load(src + (int64_t)i * plane + s);
-    fb[i] = S::load(src + (int64_t)(kQ + i) * plane + s);
+    const uint32_t s = row[kCY[i] + 1][kCZ[i] + 1] + (uint32_t)xs[kCX[i] + 1];
+    fr[i] = S::load(PL(src, i) + s);
+    fb[i] = S::load(PL(src, kQ + i) + s);
   }
-  const int64_t node = B.base + local;
+  const uint32_t node = (uint32_t)(B.base + local);
   if (is_solid(B, y, z)) {
     if (bounce) {
 #pragma unroll
       for (int i = 0; i < kQ; ++i) {
-        S::store(dst + (int64_t)opposite(i) * plane + node, fr[i]);
-        S::store(dst + (int64_t)(kQ + opposite(i)) * plane + node, fb[i]);
+        S::store(PL(dst, opposite(i)) + node, fr[i]);
+        S::store(PL(dst, kQ + opposite(i)) + node, fb[i]);
       }
     }
 #pragma unroll
-    for (int k = 0; k <= A_PYZ; ++k) aux[(int64_t)k * plane + node] = 0.0f;
+    for (int k = 0; k <= A_PYZ; ++k) PL(aux, k)[node] = 0.0f;
     return;
   }
   float rr = 0.f, rb = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
@@ -145,17 +162,17 @@ __global__ __launch_bounds__(kBlock) void k_pull(const BoxDev *__restrict__ boxe
     if (kCX[i] * kCZ[i]) pxz += kCX[i] * kCZ[i] > 0 ? f : -f;
     if (kCY[i] * kCZ[i]) pyz += kCY[i] * kCZ[i] > 0 ? f : -f;
   }
-  aux[(int64_t)A_RR * plane + node] = rr;
-  aux[(int64_t)A_RB * plane + node] = rb;
-  aux[(int64_t)A_JX * plane + node] = jx;
-  aux[(int64_t)A_JY * plane + node] = jy;
-  aux[(int64_t)A_JZ * plane + node] = jz;
-  aux[(int64_t)A_PXX * plane + node] = pxx;
-  aux[(int64_t)A_PYY * plane + node] = pyy;
-  aux[(int64_t)A_PZZ * plane + node] = pzz;
-  aux[(int64_t)A_PXY * plane + node] = pxy;
-  aux[(int64_t)A_PXZ * plane + node] = pxz;
-  aux[(int64_t)A_PYZ * plane + node] = pyz;
+  PL(aux, A_RR)[node] = rr;
+  PL(aux, A_RB)[node] = rb;
+  PL(aux, A_JX)[node] = jx;
+  PL(aux, A_JY)[node] = jy;
+  PL(aux, A_JZ)[node] = jz;
+  PL(aux, A_PXX)[node] = pxx;
+  PL(aux, A_PYY)[node] = pyy;
+  PL(aux, A_PZZ)[node] = pzz;
+  PL(aux, A_PXY)[node] = pxy;
+  PL(aux, A_PXZ)[node] = pxz;
+  PL(aux, A_PYZ)[node] = pyz;
 }
 
 // ---------------------------------------------------------------------------
@@ -240,9 +257,10 @@ __global__ __launch_bounds__(kBlock) void k_interface(const BoxDev *__restrict__
     const int lx = i % G::R3X, ly = (i / G::R3X) % G::R3Y, lz = i / (G::R3X * G::R3Y);
     const int gx = wrap_any(x0 + lx - 3, nx), gy = wrap_any(y0 + ly - 3, ny),
               gz = wrap_any(z0 + lz - 3, nz);
-    const int64_t node = B.base + gx + (int64_t)nx * (gy + (int64_t)ny * gz);
-    const float rr = aux[(int64_t)A_RR * plane + node] * B.ir0r;
-    const float rb = aux[(int64_t)A_RB * plane + node] * B.ir0b;
+    const uint32_t node =
+        (uint32_t)B.base + (uint32_t)gx + (uint32_t)nx * ((uint32_t)gy + (uint32_t)ny * (uint32_t)gz);
+    const float rr = PL(aux, A_RR)[node] * B.ir0r;
+    const float rb = PL(aux, A_RB)[node] * B.ir0b;
     const float den = rr + rb;
     s_phi[i] = den > 0.f ? (rr - rb) / den : 0.f;
   }
@@ -281,7 +299,8 @@ __global__ __launch_bounds__(kBlock) void k_interface(const BoxDev *__restrict__
     const int c2 = (lx + 1) + G::R2X * ((ly + 1) + G::R2Y * (lz + 1));
     const int gx = wrap_any(x0 + lx - 1, nx), gy = wrap_any(y0 + ly - 1, ny),
               gz = wrap_any(z0 + lz - 1, nz);
-    const int64_t node = B.base + gx + (int64_t)nx * (gy + (int64_t)ny * gz);
+    const uint32_t node =
+        (uint32_t)B.base + (uint32_t)gx + (uint32_t)nx * ((uint32_t)gy + (uint32_t)ny * (uint32_t)gz);
     const bool solid = s_sy[ly + 2] | s_sz[lz + 2];
     float qx = 0.f, qy = 0.f, qz = 0.f;
     float kap = 0.f, Fx = 0.f, Fy = 0.f, Fz = 0.f;
@@ -302,13 +321,13 @@ __global__ __launch_bounds__(kBlock) void k_interface(const BoxDev *__restrict__
       Fx = fmaf(hs, nxv, B.Gx);
       Fy = fmaf(hs, nyv, B.Gy);
       Fz = fmaf(hs, nzv, B.Gz);
-      const float rr = aux[(int64_t)A_RR * plane + node];
-      const float rb = aux[(int64_t)A_RB * plane + node];
+      const float rr = PL(aux, A_RR)[node];
+      const float rb = PL(aux, A_RB)[node];
       const float rho = rr + rb;
       const float irho = 1.0f / rho;
-      const float ux = fmaf(0.5f, Fx, aux[(int64_t)A_JX * plane + node]) * irho;
-      const float uy = fmaf(0.5f, Fy, aux[(int64_t)A_JY * plane + node]) * irho;
-      const float uz = fmaf(0.5f, Fz, aux[(int64_t)A_JZ * plane + node]) * irho;
+      const float ux = fmaf(0.5f, Fx, PL(aux, A_JX)[node]) * irho;
+      const float uy = fmaf(0.5f, Fy, PL(aux, A_JY)[node]) * irho;
+      const float uz = fmaf(0.5f, Fz, PL(aux, A_JZ)[node]) * irho;
       const float dev = rr * B.cs2r + rb * B.cs2b - rho * kCs2;
       qx = dev * ux;
       qy = dev * uy;
@@ -321,13 +340,13 @@ __global__ __launch_bounds__(kBlock) void k_interface(const BoxDev *__restrict__
     const int ox = lx - 1, oy = ly - 1, oz = lz - 1;
     if (ox >= 0 && ox < TX && oy >= 0 && oy < TY && oz >= 0 && oz < TZ && x0 + ox < nx &&
         y0 + oy < ny && z0 + oz < nz) {
-      aux[(int64_t)A_NX * plane + node] = nxv;
-      aux[(int64_t)A_NY * plane + node] = nyv;
-      aux[(int64_t)A_NZ * plane + node] = nzv;
-      aux[(int64_t)A_FX * plane + node] = Fx;
-      aux[(int64_t)A_FY * plane + node] = Fy;
-      aux[(int64_t)A_FZ * plane + node] = Fz;
-      if (write_kappa) aux[(int64_t)A_KAPPA * plane + node] = kap;
+      PL(aux, A_NX)[node] = nxv;
+      PL(aux, A_NY)[node] = nyv;
+      PL(aux, A_NZ)[node] = nzv;
+      PL(aux, A_FX)[node] = Fx;
+      PL(aux, A_FY)[node] = Fy;
+      PL(aux, A_FZ)[node] = Fz;
+      if (write_kappa) PL(aux, A_KAPPA)[node] = kap;
     }
   }
   __syncthreads();
@@ -337,7 +356,8 @@ __global__ __launch_bounds__(kBlock) void k_interface(const BoxDev *__restrict__
     const int ox = i % TX, oy = (i / TX) % TY, oz = i / (TX * TY);
     const int gx = x0 + ox, gy = y0 + oy, gz = z0 + oz;
     if (gx >= nx || gy >= ny || gz >= nz) continue;
-    const int64_t node = B.base + gx + (int64_t)nx * (gy + (int64_t)ny * gz);
+    const uint32_t node =
+        (uint32_t)B.base + (uint32_t)gx + (uint32_t)nx * ((uint32_t)gy + (uint32_t)ny * (uint32_t)gz);
     const int c1 = (ox + 1) + G::R1X * ((oy + 1) + G::R1Y * (oz + 1));
     float Qx = 0.f, Qy = 0.f, Qz = 0.f;
     if (!(s_sy[oy + 3] | s_sz[oz + 3])) {
@@ -350,9 +370,9 @@ __global__ __launch_bounds__(kBlock) void k_interface(const BoxDev *__restrict__
       lds_gradient<G::R1X, G::R1X * G::R1Y>(s_q[2], c1, sol, a, bq, c);
       Qz = -3.0f * c;
     }
-    aux[(int64_t)A_QX * plane + node] = Qx;
-    aux[(int64_t)A_QY * plane + node] = Qy;
-    aux[(int64_t)A_QZ * plane + node] = Qz;
+    PL(aux, A_QX)[node] = Qx;
+    PL(aux, A_QY)[node] = Qy;
+    PL(aux, A_QZ)[node] = Qz;
   }
 }
 
@@ -365,8 +385,11 @@ struct NodeIn {
   float nx, ny, nz, Fx, Fy, Fz, Qx, Qy, Qz;
 };
 
-__device__ __forceinline__ void collide_node(const BoxDev &B, const NodeIn &in, float (&fr)[kQ],
-                                             float (&fb)[kQ]) {
+// Emits each direction's recoloured pair through emit(i, f_r, f_b) as soon as
+// its x-triplet of the back-transform is done, so that the 54 outputs never
+// have to be live at once.
+template <class Emit>
+__device__ __forceinline__ void collide_node(const BoxDev &B, const NodeIn &in, Emit &&emit) {
   const float rho = in.rr + in.rb;
   const float irho = 1.0f / rho;
   const float ux = fmaf(0.5f, in.Fx, in.jx) * irho;  // Eq. (11)
@@ -398,46 +421,65 @@ __device__ __forceinline__ void collide_node(const BoxDev &B, const NodeIn &in, 
   const float szz = (T + A - 2.0f * Bd) * third;
   float k[27];
   model_d_moments(rho, p, in.Fx, in.Fy, in.Fz, sxx, syy, szz, r1 * kxy, r1 * kxz, r1 * kyz, k);
-  float f[kQ];
-  central_to_populations(k, ux, uy, uz, f);
-  // recolouring (Eqs. 18-19)
+  // recolouring (Eqs. 18-19) folded into the last pass of the back-transform
   const float cr = in.rr * irho, cb = in.rb * irho;
   const float s = B.beta * cr * cb * p;
   const float Rx = s * in.nx, Ry = s * in.ny, Rz = s * in.nz;
+  float g[3][3][3];
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) {
-    const float cR = (kCX[i] ? (kCX[i] > 0 ? Rx : -Rx) : 0.f) +
-                     (kCY[i] ? (kCY[i] > 0 ? Ry : -Ry) : 0.f) +
-                     (kCZ[i] ? (kCZ[i] > 0 ? Rz : -Rz) : 0.f);
-    const float d = 3.0f * weight(i) * cR;
-    fr[i] = fmaf(cr, f[i], d);
-    fb[i] = fmaf(cb, f[i], -d);
-  }
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+      cm_to_pop_1d(k[a + 3 * b], k[a + 3 * b + 9], k[a + 3 * b + 18], uz, g[a][b][0], g[a][b][1],
+                   g[a][b][2]);
+  float h[3][3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int cz = 0; cz < 3; ++cz)
+      cm_to_pop_1d(g[a][0][cz], g[a][1][cz], g[a][2][cz], uy, h[a][0][cz], h[a][1][cz],
+                   h[a][2][cz]);
+#pragma unroll
+  for (int cz = 0; cz < 3; ++cz)
+#pragma unroll
+    for (int cy = 0; cy < 3; ++cy) {
+      float fx[3];
+      cm_to_pop_1d(h[0][cy][cz], h[1][cy][cz], h[2][cy][cz], ux, fx[0], fx[1], fx[2]);
+#pragma unroll
+      for (int cx = 0; cx < 3; ++cx) {
+        const int i = dir_of(cx - 1, cy - 1, cz - 1);
+        const float cR = (kCX[i] ? (kCX[i] > 0 ? Rx : -Rx) : 0.f) +
+                         (kCY[i] ? (kCY[i] > 0 ? Ry : -Ry) : 0.f) +
+                         (kCZ[i] ? (kCZ[i] > 0 ? Rz : -Rz) : 0.f);
+        const float d = 3.0f * weight(i) * cR;
+        emit(i, fmaf(cr, fx[cx], d), fmaf(cb, fx[cx], -d));
+      }
+    }
 }
 
 __device__ __forceinline__ NodeIn load_node_in(const float *__restrict__ aux, int64_t plane,
-                                               int64_t node) {
+                                               uint32_t node) {
   NodeIn in;
-  in.rr = aux[(int64_t)A_RR * plane + node];
-  in.rb = aux[(int64_t)A_RB * plane + node];
-  in.jx = aux[(int64_t)A_JX * plane + node];
-  in.jy = aux[(int64_t)A_JY * plane + node];
-  in.jz = aux[(int64_t)A_JZ * plane + node];
-  in.pxx = aux[(int64_t)A_PXX * plane + node];
-  in.pyy = aux[(int64_t)A_PYY * plane + node];
-  in.pzz = aux[(int64_t)A_PZZ * plane + node];
-  in.pxy = aux[(int64_t)A_PXY * plane + node];
-  in.pxz = aux[(int64_t)A_PXZ * plane + node];
-  in.pyz = aux[(int64_t)A_PYZ * plane + node];
-  in.nx = aux[(int64_t)A_NX * plane + node];
-  in.ny = aux[(int64_t)A_NY * plane + node];
-  in.nz = aux[(int64_t)A_NZ * plane + node];
-  in.Fx = aux[(int64_t)A_FX * plane + node];
-  in.Fy = aux[(int64_t)A_FY * plane + node];
-  in.Fz = aux[(int64_t)A_FZ * plane + node];
-  in.Qx = aux[(int64_t)A_QX * plane + node];
-  in.Qy = aux[(int64_t)A_QY * plane + node];
-  in.Qz = aux[(int64_t)A_QZ * plane + node];
+  in.rr = PL(aux, A_RR)[node];
+  in.rb = PL(aux, A_RB)[node];
+  in.jx = PL(aux, A_JX)[node];
+  in.jy = PL(aux, A_JY)[node];
+  in.jz = PL(aux, A_JZ)[node];
+  in.pxx = PL(aux, A_PXX)[node];
+  in.pyy = PL(aux, A_PYY)[node];
+  in.pzz = PL(aux, A_PZZ)[node];
+  in.pxy = PL(aux, A_PXY)[node];
+  in.pxz = PL(aux, A_PXZ)[node];
+  in.pyz = PL(aux, A_PYZ)[node];
+  in.nx = PL(aux, A_NX)[node];
+  in.ny = PL(aux, A_NY)[node];
+  in.nz = PL(aux, A_NZ)[node];
+  in.Fx = PL(aux, A_FX)[node];
+  in.Fy = PL(aux, A_FY)[node];
+  in.Fz = PL(aux, A_FZ)[node];
+  in.Qx = PL(aux, A_QX)[node];
+  in.Qy = PL(aux, A_QY)[node];
+  in.Qz = PL(aux, A_QZ)[node];
   return in;
 }
 
@@ -447,24 +489,23 @@ __global__ __launch_bounds__(kBlock) void k_collide(const BoxDev *__restrict__ b
                                                     const float *__restrict__ aux,
                                                     typename S::T *__restrict__ dst,
                                                     int64_t plane) {
-  const int b = blk_box[blockIdx.x];
+  const uint32_t lb = xcd_block();
+  const int b = blk_box[lb];
+  if (b < 0) return;
   const BoxDev B = boxes[b];
-  const int64_t local = (int64_t)(blockIdx.x - B.blk0) * kBlock + threadIdx.x;
+  const int64_t local = (int64_t)(lb - B.blk0) * kBlock + threadIdx.x;
   if (local >= B.n) return;
   const uint32_t l = (uint32_t)local;
   const uint32_t yz = fdiv(l, B.fdx);
   const int z = (int)fdiv(yz, B.fdy);
   const int y = (int)(yz - (uint32_t)z * (uint32_t)B.ny);
   if (is_solid(B, y, z)) return;
-  const int64_t node = B.base + local;
+  const uint32_t node = (uint32_t)(B.base + local);
   const NodeIn in = load_node_in(aux, plane, node);
-  float fr[kQ], fb[kQ];
-  collide_node(B, in, fr, fb);
-#pragma unroll
-  for (int i = 0; i < kQ; ++i) {
-    S::store(dst + (int64_t)i * plane + node, fr[i]);
-    S::store(dst + (int64_t)(kQ + i) * plane + node, fb[i]);
-  }
+  collide_node(B, in, [&](int i, float fr, float fb) {
+    S::store(PL(dst, i) + node, fr);
+    S::store(PL(dst, kQ + i) + node, fb);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -489,7 +530,7 @@ __global__ __launch_bounds__(kBlock) void k_init(const BoxDev *__restrict__ boxe
   const int x = (int)(l - yz * (uint32_t)B.nx);
   const int z = (int)fdiv(yz, B.fdy);
   const int y = (int)(yz - (uint32_t)z * (uint32_t)B.ny);
-  const int64_t node = B.base + local;
+  const uint32_t node = (uint32_t)(B.base + local);
   const float rr = in_rr[node], rb = in_rb[node];
   const float ux = in_u[node], uy = in_u[plane + node], uz = in_u[2 * plane + node];
   const float rho = rr + rb;
@@ -505,9 +546,10 @@ __global__ __launch_bounds__(kBlock) void k_init(const BoxDev *__restrict__ boxe
                                 : f[i];
     const int xd = wrap_once(x - kCX[i], B.nx), yd = wrap_once(y - kCY[i], B.ny),
               zd = wrap_once(z - kCZ[i], B.nz);
-    const int64_t d = B.base + xd + (int64_t)B.nx * (yd + (int64_t)B.ny * zd);
-    S::store(dst + (int64_t)i * plane + d, cr * ft);
-    S::store(dst + (int64_t)(kQ + i) * plane + d, cb * ft);
+    const uint32_t d = (uint32_t)B.base + (uint32_t)xd +
+                       (uint32_t)B.nx * ((uint32_t)yd + (uint32_t)B.ny * (uint32_t)zd);
+    S::store(PL(dst, i) + d, cr * ft);
+    S::store(PL(dst, kQ + i) + d, cb * ft);
   }
 }
 
@@ -528,8 +570,8 @@ struct FusedGeom {
   static constexpr int A_PER = (R3 + NT - 1) / NT;
 };
 
-template <int TX, int TY, int ZC, class S>
-__global__ __launch_bounds__(TX *TY) void k_fused(const BoxDev *__restrict__ boxes,
+template <int TX, int TY, int ZC, int MINW, bool WALLS, class S>
+__global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict__ boxes,
                                                   const int32_t *__restrict__ col_box,
                                                   float *__restrict__ aux,
                                                   typename S::T *__restrict__ dst, int64_t plane,
@@ -541,9 +583,11 @@ __global__ __launch_bounds__(TX *TY) void k_fused(const BoxDev *__restrict__ box
   __shared__ uint8_t s_sy[G::R3Y];
 
   const int tid = threadIdx.x;
-  const int b = col_box[blockIdx.x];
+  const uint32_t lb = xcd_block();
+  const int b = col_box[lb];
+  if (b < 0) return;
   const BoxDev B = boxes[b];
-  const uint32_t t = blockIdx.x - B.col0;
+  const uint32_t t = lb - B.col0;
   const uint32_t tyz = fdiv(t, B.fcx);
   const int cx = (int)(t - tyz * (uint32_t)B.ncx);
   const int cz = (int)fdiv(tyz, B.fcy);
@@ -551,13 +595,15 @@ __global__ __launch_bounds__(TX *TY) void k_fused(const BoxDev *__restrict__ box
   const int x0 = cx * TX, y0 = cy * TY, z0 = cz * ZC;
   const int nx = B.nx, ny = B.ny, nz = B.nz;
   const int z1 = min(z0 + ZC, nz);
-  const int64_t nxy = (int64_t)nx * ny;
-  const bool zwalls = (B.walls & 2u) != 0;
+  const uint32_t nxy = (uint32_t)nx * (uint32_t)ny;
+  const bool zwalls = WALLS && (B.walls & 2u) != 0;
 
   for (int i = tid; i < G::R3Y; i += G::NT) {
     const int gy = wrap_any(y0 + i - 3, ny);
-    s_sy[i] = (B.walls & 1u) && (gy == 0 || gy == ny - 1);
+    s_sy[i] = WALLS && (B.walls & 1u) && (gy == 0 || gy == ny - 1);
   }
+  // solid flag of an R3 row (always false without walls)
+  auto sy = [&](int r) -> bool { return WALLS ? (bool)s_sy[r] : false; };
   // xy offsets of this thread's phase-field points (fixed over the march)
   int a_off[G::A_PER];
 #pragma unroll
@@ -567,6 +613,36 @@ __global__ __launch_bounds__(TX *TY) void k_fused(const BoxDev *__restrict__ box
     if (i < G::R3) {
       const int lx = i % G::R3X, ly = i / G::R3X;
       a_off[k] = wrap_any(x0 + lx - 3, nx) + nx * wrap_any(y0 + ly - 3, ny);
+    }
+  }
+  // R1 points of this thread: the tile point first, then the halo ring
+  // (top and bottom rows, then the two side columns)
+  auto r1_point = [&](int j, int &lx, int &ly) {
+    if (j < G::NT) {
+      lx = (j % TX) + 1;
+      ly = (j / TX) + 1;
+    } else {
+      const int h = j - G::NT;
+      if (h < 2 * G::R1X) {
+        lx = h % G::R1X;
+        ly = (h / G::R1X) * (G::R1Y - 1);
+      } else {
+        const int h2 = h - 2 * G::R1X;
+        lx = (h2 & 1) * (G::R1X - 1);
+        ly = (h2 >> 1) + 1;
+      }
+    }
+  };
+  constexpr int C_PER = (G::R1 + G::NT - 1) / G::NT;
+  uint32_t c_off[C_PER];
+#pragma unroll
+  for (int kk = 0; kk < C_PER; ++kk) {
+    const int j = tid + kk * G::NT;
+    c_off[kk] = 0;
+    if (j < G::R1) {
+      int lx, ly;
+      r1_point(j, lx, ly);
+      c_off[kk] = (uint32_t)wrap_any(x0 + lx - 1, nx) + (uint32_t)nx * (uint32_t)wrap_any(y0 + ly - 1, ny);
     }
   }
   // tile point of this thread
@@ -586,15 +662,15 @@ __global__ __launch_bounds__(TX *TY) void k_fused(const BoxDev *__restrict__ box
   for (int s = z0 - 3; s < z1 + 3; ++s) {
     // ---- A: phase field of slab s (Eq. 14) ----
     {
-      const int64_t zoff = B.base + nxy * wrap_any(s, nz);
+      const uint32_t zoff = (uint32_t)B.base + nxy * (uint32_t)wrap_any(s, nz);
       float *ph = s_phi[(s + 3) % 3];
 #pragma unroll
       for (int k = 0; k < G::A_PER; ++k) {
         const int i = tid + k * G::NT;
         if (i < G::R3) {
-          const int64_t node = zoff + a_off[k];
-          const float rr = aux[(int64_t)A_RR * plane + node] * B.ir0r;
-          const float rb = aux[(int64_t)A_RB * plane + node] * B.ir0b;
+          const uint32_t node = zoff + (uint32_t)a_off[k];
+          const float rr = PL(aux, A_RR)[node] * B.ir0r;
+          const float rb = PL(aux, A_RB)[node] * B.ir0b;
           const float den = rr + rb;
           ph[i] = den > 0.f ? (rr - rb) / den : 0.f;
         }
@@ -613,7 +689,7 @@ __global__ __launch_bounds__(TX *TY) void k_fused(const BoxDev *__restrict__ box
         const int lx = i % G::R2X, ly = i / G::R2X;
         const int c3 = (lx + 1) + G::R3X * (ly + 1);
         float nxv = 0.f, nyv = 0.f, nzv = 0.f, mag = 0.f;
-        if (!(s_sy[ly + 1] | sz_c)) {
+        if (!(sy(ly + 1) | sz_c)) {
           const float vc = pc[c3];
           float v[3][3][3];
 #pragma unroll
@@ -622,7 +698,7 @@ __global__ __launch_bounds__(TX *TY) void k_fused(const BoxDev *__restrict__ box
             const bool szd = dz < 0 ? sz_m : (dz > 0 ? sz_p : sz_c);
 #pragma unroll
             for (int dy = -1; dy <= 1; ++dy) {
-              const bool sd = szd | s_sy[ly + 1 + dy];
+              const bool sd = szd | sy(ly + 1 + dy);
 #pragma unroll
               for (int dx = -1; dx <= 1; ++dx)
                 v[dz + 1][dy + 1][dx + 1] = sd ? vc : pl[c3 + dx + G::R3X * dy];
@@ -660,35 +736,24 @@ __global__ __launch_bounds__(TX *TY) void k_fused(const BoxDev *__restrict__ box
     if (s - 2 >= z0 - 1) {
       const int sc = s - 2;
       const bool sz_m = slab_solid(sc - 1), sz_c = slab_solid(sc), sz_p = slab_solid(sc + 1);
-      const int64_t zoff = B.base + nxy * wrap_any(sc, nz);
+      const uint32_t zoff = (uint32_t)B.base + nxy * (uint32_t)wrap_any(sc, nz);
       float(*nm)[G::R2] = s_n[(sc - 1 + 3) % 3];
       float(*nc)[G::R2] = s_n[(sc + 3) % 3];
       float(*np)[G::R2] = s_n[(sc + 1 + 3) % 3];
       float(*qq)[G::R1] = s_q[(sc + 3) % 3];
       // first pass: the tile points in thread order, then the halo ring
-      for (int j = tid; j < G::R1; j += G::NT) {
+#pragma unroll
+      for (int kk = 0; kk < C_PER; ++kk) {
+        const int j = tid + kk * G::NT;
+        if (j >= G::R1) break;
         int lx, ly;
-        if (j < G::NT) {
-          lx = (j % TX) + 1;
-          ly = (j / TX) + 1;
-        } else {
-          // halo points of the R1 region: top/bottom rows, then side columns
-          const int h = j - G::NT;
-          if (h < 2 * G::R1X) {
-            lx = h % G::R1X;
-            ly = (h / G::R1X) * (G::R1Y - 1);
-          } else {
-            const int h2 = h - 2 * G::R1X;
-            lx = (h2 & 1) * (G::R1X - 1);
-            ly = (h2 >> 1) + 1;
-          }
-        }
+        r1_point(j, lx, ly);
         const int c2 = (lx + 1) + G::R2X * (ly + 1);
         const int ri = lx + G::R1X * ly;
         float qx = 0.f, qy = 0.f, qz = 0.f;
         float kap = 0.f, Fx = 0.f, Fy = 0.f, Fz = 0.f;
         const float nxv = nc[0][c2], nyv = nc[1][c2], nzv = nc[2][c2], mag = nc[3][c2];
-        if (!(s_sy[ly + 2] | sz_c)) {
+        if (!(sy(ly + 2) | sz_c)) {
           float d[3][3];  // d[a][b] = d n_a / d x_b
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
@@ -700,7 +765,7 @@ __global__ __launch_bounds__(TX *TY) void k_fused(const BoxDev *__restrict__ box
               const bool szd = dz < 0 ? sz_m : (dz > 0 ? sz_p : sz_c);
 #pragma unroll
               for (int dy = -1; dy <= 1; ++dy) {
-                const bool sd = szd | s_sy[ly + 2 + dy];
+                const bool sd = szd | sy(ly + 2 + dy);
 #pragma unroll
                 for (int dx = -1; dx <= 1; ++dx)
                   v[dz + 1][dy + 1][dx + 1] = sd ? vc : pl[c2 + dx + G::R2X * dy];
@@ -729,15 +794,14 @@ __global__ __launch_bounds__(TX *TY) void k_fused(const BoxDev *__restrict__ box
           Fx = fmaf(hs, nxv, B.Gx);
           Fy = fmaf(hs, nyv, B.Gy);
           Fz = fmaf(hs, nzv, B.Gz);
-          const int gx = wrap_any(x0 + lx - 1, nx), gy = wrap_any(y0 + ly - 1, ny);
-          const int64_t node = zoff + gx + (int64_t)nx * gy;
-          const float rr = aux[(int64_t)A_RR * plane + node];
-          const float rb = aux[(int64_t)A_RB * plane + node];
+          const uint32_t node = zoff + c_off[kk];
+          const float rr = PL(aux, A_RR)[node];
+          const float rb = PL(aux, A_RB)[node];
           const float rho = rr + rb;
           const float irho = 1.0f / rho;
-          const float ux = fmaf(0.5f, Fx, aux[(int64_t)A_JX * plane + node]) * irho;
-          const float uy = fmaf(0.5f, Fy, aux[(int64_t)A_JY * plane + node]) * irho;
-          const float uz = fmaf(0.5f, Fz, aux[(int64_t)A_JZ * plane + node]) * irho;
+          const float ux = fmaf(0.5f, Fx, PL(aux, A_JX)[node]) * irho;
+          const float uy = fmaf(0.5f, Fy, PL(aux, A_JY)[node]) * irho;
+          const float uz = fmaf(0.5f, Fz, PL(aux, A_JZ)[node]) * irho;
           const float dev = rr * B.cs2r + rb * B.cs2b - rho * kCs2;
           qx = dev * ux;
           qy = dev * uy;
@@ -777,7 +841,7 @@ __global__ __launch_bounds__(TX *TY) void k_fused(const BoxDev *__restrict__ box
             const float w = 0.5f * w1d(a2) * w1d(b2);
             {  // x: a2 = dy, b2 = dz
               const float *pl = b2 < 0 ? qm[0] : (b2 > 0 ? qp[0] : qc[0]);
-              const bool sdd = (b2 < 0 ? sz_m : (b2 > 0 ? sz_p : false)) | s_sy[oy + 3 + a2];
+              const bool sdd = (b2 < 0 ? sz_m : (b2 > 0 ? sz_p : false)) | sy(oy + 3 + a2);
               const float vc = qc[0][c1];
               const float vp = sdd ? vc : pl[c1 + 1 + G::R1X * a2];
               const float vm = sdd ? vc : pl[c1 - 1 + G::R1X * a2];
@@ -787,12 +851,12 @@ __global__ __launch_bounds__(TX *TY) void k_fused(const BoxDev *__restrict__ box
               const float *pl = b2 < 0 ? qm[1] : (b2 > 0 ? qp[1] : qc[1]);
               const bool szd = b2 < 0 ? sz_m : (b2 > 0 ? sz_p : false);
               const float vc = qc[1][c1];
-              const float vp = (szd | s_sy[oy + 4]) ? vc : pl[c1 + a2 + G::R1X];
-              const float vm = (szd | s_sy[oy + 2]) ? vc : pl[c1 + a2 - G::R1X];
+              const float vp = (szd | sy(oy + 4)) ? vc : pl[c1 + a2 + G::R1X];
+              const float vm = (szd | sy(oy + 2)) ? vc : pl[c1 + a2 - G::R1X];
               Qy = fmaf(w, vp - vm, Qy);
             }
             {  // z: a2 = dx, b2 = dy
-              const bool syd = s_sy[oy + 3 + b2];
+              const bool syd = sy(oy + 3 + b2);
               const float vc = qc[2][c1];
               const float vp = (sz_p | syd) ? vc : qp[2][c1 + a2 + G::R1X * b2];
               const float vm = (sz_m | syd) ? vc : qm[2][c1 + a2 + G::R1X * b2];
@@ -802,20 +866,21 @@ __global__ __launch_bounds__(TX *TY) void k_fused(const BoxDev *__restrict__ box
         Qx *= -3.0f;
         Qy *= -3.0f;
         Qz *= -3.0f;
-        const int64_t node = B.base + gxo + (int64_t)nx * gyo + nxy * gz;
+        const uint32_t node =
+            (uint32_t)B.base + (uint32_t)gxo + (uint32_t)nx * (uint32_t)gyo + nxy * (uint32_t)gz;
         if (write_pops) {
           NodeIn in;
-          in.rr = aux[(int64_t)A_RR * plane + node];
-          in.rb = aux[(int64_t)A_RB * plane + node];
-          in.jx = aux[(int64_t)A_JX * plane + node];
-          in.jy = aux[(int64_t)A_JY * plane + node];
-          in.jz = aux[(int64_t)A_JZ * plane + node];
-          in.pxx = aux[(int64_t)A_PXX * plane + node];
-          in.pyy = aux[(int64_t)A_PYY * plane + node];
-          in.pzz = aux[(int64_t)A_PZZ * plane + node];
-          in.pxy = aux[(int64_t)A_PXY * plane + node];
-          in.pxz = aux[(int64_t)A_PXZ * plane + node];
-          in.pyz = aux[(int64_t)A_PYZ * plane + node];
+          in.rr = PL(aux, A_RR)[node];
+          in.rb = PL(aux, A_RB)[node];
+          in.jx = PL(aux, A_JX)[node];
+          in.jy = PL(aux, A_JY)[node];
+          in.jz = PL(aux, A_JZ)[node];
+          in.pxx = PL(aux, A_PXX)[node];
+          in.pyy = PL(aux, A_PYY)[node];
+          in.pzz = PL(aux, A_PZZ)[node];
+          in.pxy = PL(aux, A_PXY)[node];
+          in.pxz = PL(aux, A_PXZ)[node];
+          in.pyz = PL(aux, A_PYZ)[node];
           in.nx = h_nx;
           in.ny = h_ny;
           in.nz = h_nz;
@@ -825,30 +890,28 @@ __global__ __launch_bounds__(TX *TY) void k_fused(const BoxDev *__restrict__ box
           in.Qx = Qx;
           in.Qy = Qy;
           in.Qz = Qz;
-          float fr[kQ], fb[kQ];
-          collide_node(B, in, fr, fb);
-#pragma unroll
-          for (int i = 0; i < kQ; ++i) {
-            S::store(dst + (int64_t)i * plane + node, fr[i]);
-            S::store(dst + (int64_t)(kQ + i) * plane + node, fb[i]);
-          }
+          collide_node(B, in, [&](int i, float fr, float fb) {
+            S::store(PL(dst, i) + node, fr);
+            S::store(PL(dst, kQ + i) + node, fb);
+          });
         }
         if (export_fields) {
-          aux[(int64_t)A_NX * plane + node] = h_nx;
-          aux[(int64_t)A_NY * plane + node] = h_ny;
-          aux[(int64_t)A_NZ * plane + node] = h_nz;
-          aux[(int64_t)A_FX * plane + node] = h_Fx;
-          aux[(int64_t)A_FY * plane + node] = h_Fy;
-          aux[(int64_t)A_FZ * plane + node] = h_Fz;
-          aux[(int64_t)A_QX * plane + node] = Qx;
-          aux[(int64_t)A_QY * plane + node] = Qy;
-          aux[(int64_t)A_QZ * plane + node] = Qz;
-          aux[(int64_t)A_KAPPA * plane + node] = h_k;
+          PL(aux, A_NX)[node] = h_nx;
+          PL(aux, A_NY)[node] = h_ny;
+          PL(aux, A_NZ)[node] = h_nz;
+          PL(aux, A_FX)[node] = h_Fx;
+          PL(aux, A_FY)[node] = h_Fy;
+          PL(aux, A_FZ)[node] = h_Fz;
+          PL(aux, A_QX)[node] = Qx;
+          PL(aux, A_QY)[node] = Qy;
+          PL(aux, A_QZ)[node] = Qz;
+          PL(aux, A_KAPPA)[node] = h_k;
         }
       } else if (export_fields && in_xy) {
-        const int64_t node = B.base + gxo + (int64_t)nx * gyo + nxy * gz;
+        const uint32_t node =
+            (uint32_t)B.base + (uint32_t)gxo + (uint32_t)nx * (uint32_t)gyo + nxy * (uint32_t)gz;
 #pragma unroll
-        for (int k = A_NX; k <= A_KAPPA; ++k) aux[(int64_t)k * plane + node] = 0.f;
+        for (int k = A_NX; k <= A_KAPPA; ++k) PL(aux, k)[node] = 0.f;
       }
     }
     // the interface values of slab s-2 become those of the next collision
@@ -875,7 +938,7 @@ __global__ __launch_bounds__(kBlock) void k_fields(const BoxDev *__restrict__ bo
   const uint32_t yz = fdiv(l, B.fdx);
   const int z = (int)fdiv(yz, B.fdy);
   const int y = (int)(yz - (uint32_t)z * (uint32_t)B.ny);
-  const int64_t node = B.base + local;
+  const uint32_t node = (uint32_t)(B.base + local);
   const bool solid = is_solid(B, y, z);
   const NodeIn in = load_node_in(aux, plane, node);
   const float rho = in.rr + in.rb;
@@ -891,7 +954,7 @@ __global__ __launch_bounds__(kBlock) void k_fields(const BoxDev *__restrict__ bo
   v[7] = in.nx;
   v[8] = in.ny;
   v[9] = in.nz;
-  v[10] = aux[(int64_t)A_KAPPA * plane + node];
+  v[10] = PL(aux, A_KAPPA)[node];
   v[11] = in.Fx;
   v[12] = in.Fy;
   v[13] = in.Fz;
@@ -958,7 +1021,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce1(const BoxDev *__restrict__ b
     const int z = (int)fdiv(yz, B.fdy);
     const int y = (int)(yz - (uint32_t)z * (uint32_t)B.ny);
     if (!is_solid(B, y, z)) {
-      const int64_t node = B.base + local;
+      const uint32_t node = (uint32_t)(B.base + local);
       const NodeIn in = load_node_in(aux, plane, node);
       const double rr = in.rr, rb = in.rb, rho = rr + rb;
       const double jx = (double)in.jx + 0.5 * in.Fx, jy = (double)in.jy + 0.5 * in.Fy,
@@ -1009,9 +1072,9 @@ __global__ __launch_bounds__(kBlock) void k_reduce2(const BoxDev *__restrict__ b
     const int z = (int)fdiv(yz, B.fdy);
     const int y = (int)(yz - (uint32_t)z * (uint32_t)B.ny);
     if (!is_solid(B, y, z)) {
-      const int64_t node = B.base + local;
-      const double p = (double)(aux[(int64_t)A_RR * plane + node] * B.cs2r +
-                                aux[(int64_t)A_RB * plane + node] * B.cs2b);
+      const uint32_t node = (uint32_t)(B.base + local);
+      const double p = (double)(PL(aux, A_RR)[node] * B.cs2r +
+                                PL(aux, A_RB)[node] * B.cs2b);
       const double dx = periodic_offset(x - (float)centre[3 * b + 0], B.nx, true);
       const double dy = periodic_offset(y - (float)centre[3 * b + 1], B.ny, !(B.walls & 1u));
       const double dz = periodic_offset(z - (float)centre[3 * b + 2], B.nz, !(B.walls & 2u));
