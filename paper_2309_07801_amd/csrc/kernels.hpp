@@ -57,6 +57,19 @@ constexpr int kBlock = 256;
 // is a scalar base plus one 32-bit vector offset shared by all planes.
 #define PL(ptr, p) ((ptr) + (int64_t)(p) * plane)
 
+// Element idx of an array through a 32-bit byte offset (idx * sizeof(T) <
+// 2^32): the address is a scalar base plus a zero-extended 32-bit vector
+// offset, which the hardware addresses directly.
+template <class T>
+__device__ __forceinline__ T &at(T *base, uint32_t idx) {
+  return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + (uint32_t)(idx * (uint32_t)sizeof(T)));
+}
+template <class T>
+__device__ __forceinline__ const T &at(const T *base, uint32_t idx) {
+  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) +
+                                      (uint32_t)(idx * (uint32_t)sizeof(T)));
+}
+
 // Workgroups are dispatched to the 8 XCDs in round-robin order.  Remap them
 // so that each XCD, with its own L2, works through a contiguous range of
 // logical blocks: neighbouring rows and columns then share cached halo lines.
@@ -129,20 +142,20 @@ __global__ __launch_bounds__(kBlock) void k_pull(const BoxDev *__restrict__ boxe
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
     const uint32_t s = row[kCY[i] + 1][kCZ[i] + 1] + (uint32_t)xs[kCX[i] + 1];
-    fr[i] = S::load(PL(src, i) + s);
-    fb[i] = S::load(PL(src, kQ + i) + s);
+    fr[i] = S::load(&at(PL(src, i), s));
+    fb[i] = S::load(&at(PL(src, kQ + i), s));
   }
   const uint32_t node = (uint32_t)(B.base + local);
   if (is_solid(B, y, z)) {
     if (bounce) {
 #pragma unroll
       for (int i = 0; i < kQ; ++i) {
-        S::store(PL(dst, opposite(i)) + node, fr[i]);
-        S::store(PL(dst, kQ + opposite(i)) + node, fb[i]);
+        S::store(&at(PL(dst, opposite(i)), node), fr[i]);
+        S::store(&at(PL(dst, kQ + opposite(i)), node), fb[i]);
       }
     }
 #pragma unroll
-    for (int k = 0; k <= A_PYZ; ++k) PL(aux, k)[node] = 0.0f;
+    for (int k = 0; k <= A_PYZ; ++k) at(PL(aux, k), node) = 0.0f;
     return;
   }
   float rr = 0.f, rb = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
@@ -162,17 +175,17 @@ __global__ __launch_bounds__(kBlock) void k_pull(const BoxDev *__restrict__ boxe
     if (kCX[i] * kCZ[i]) pxz += kCX[i] * kCZ[i] > 0 ? f : -f;
     if (kCY[i] * kCZ[i]) pyz += kCY[i] * kCZ[i] > 0 ? f : -f;
   }
-  PL(aux, A_RR)[node] = rr;
-  PL(aux, A_RB)[node] = rb;
-  PL(aux, A_JX)[node] = jx;
-  PL(aux, A_JY)[node] = jy;
-  PL(aux, A_JZ)[node] = jz;
-  PL(aux, A_PXX)[node] = pxx;
-  PL(aux, A_PYY)[node] = pyy;
-  PL(aux, A_PZZ)[node] = pzz;
-  PL(aux, A_PXY)[node] = pxy;
-  PL(aux, A_PXZ)[node] = pxz;
-  PL(aux, A_PYZ)[node] = pyz;
+  at(PL(aux, A_RR), node) = rr;
+  at(PL(aux, A_RB), node) = rb;
+  at(PL(aux, A_JX), node) = jx;
+  at(PL(aux, A_JY), node) = jy;
+  at(PL(aux, A_JZ), node) = jz;
+  at(PL(aux, A_PXX), node) = pxx;
+  at(PL(aux, A_PYY), node) = pyy;
+  at(PL(aux, A_PZZ), node) = pzz;
+  at(PL(aux, A_PXY), node) = pxy;
+  at(PL(aux, A_PXZ), node) = pxz;
+  at(PL(aux, A_PYZ), node) = pyz;
 }
 
 // ---------------------------------------------------------------------------
@@ -259,8 +272,8 @@ __global__ __launch_bounds__(kBlock) void k_interface(const BoxDev *__restrict__
               gz = wrap_any(z0 + lz - 3, nz);
     const uint32_t node =
         (uint32_t)B.base + (uint32_t)gx + (uint32_t)nx * ((uint32_t)gy + (uint32_t)ny * (uint32_t)gz);
-    const float rr = PL(aux, A_RR)[node] * B.ir0r;
-    const float rb = PL(aux, A_RB)[node] * B.ir0b;
+    const float rr = at(PL(aux, A_RR), node) * B.ir0r;
+    const float rb = at(PL(aux, A_RB), node) * B.ir0b;
     const float den = rr + rb;
     s_phi[i] = den > 0.f ? (rr - rb) / den : 0.f;
   }
@@ -321,13 +334,13 @@ __global__ __launch_bounds__(kBlock) void k_interface(const BoxDev *__restrict__
       Fx = fmaf(hs, nxv, B.Gx);
       Fy = fmaf(hs, nyv, B.Gy);
       Fz = fmaf(hs, nzv, B.Gz);
-      const float rr = PL(aux, A_RR)[node];
-      const float rb = PL(aux, A_RB)[node];
+      const float rr = at(PL(aux, A_RR), node);
+      const float rb = at(PL(aux, A_RB), node);
       const float rho = rr + rb;
       const float irho = 1.0f / rho;
-      const float ux = fmaf(0.5f, Fx, PL(aux, A_JX)[node]) * irho;
-      const float uy = fmaf(0.5f, Fy, PL(aux, A_JY)[node]) * irho;
-      const float uz = fmaf(0.5f, Fz, PL(aux, A_JZ)[node]) * irho;
+      const float ux = fmaf(0.5f, Fx, at(PL(aux, A_JX), node)) * irho;
+      const float uy = fmaf(0.5f, Fy, at(PL(aux, A_JY), node)) * irho;
+      const float uz = fmaf(0.5f, Fz, at(PL(aux, A_JZ), node)) * irho;
       const float dev = rr * B.cs2r + rb * B.cs2b - rho * kCs2;
       qx = dev * ux;
       qy = dev * uy;
@@ -340,13 +353,13 @@ __global__ __launch_bounds__(kBlock) void k_interface(const BoxDev *__restrict__
     const int ox = lx - 1, oy = ly - 1, oz = lz - 1;
     if (ox >= 0 && ox < TX && oy >= 0 && oy < TY && oz >= 0 && oz < TZ && x0 + ox < nx &&
         y0 + oy < ny && z0 + oz < nz) {
-      PL(aux, A_NX)[node] = nxv;
-      PL(aux, A_NY)[node] = nyv;
-      PL(aux, A_NZ)[node] = nzv;
-      PL(aux, A_FX)[node] = Fx;
-      PL(aux, A_FY)[node] = Fy;
-      PL(aux, A_FZ)[node] = Fz;
-      if (write_kappa) PL(aux, A_KAPPA)[node] = kap;
+      at(PL(aux, A_NX), node) = nxv;
+      at(PL(aux, A_NY), node) = nyv;
+      at(PL(aux, A_NZ), node) = nzv;
+      at(PL(aux, A_FX), node) = Fx;
+      at(PL(aux, A_FY), node) = Fy;
+      at(PL(aux, A_FZ), node) = Fz;
+      if (write_kappa) at(PL(aux, A_KAPPA), node) = kap;
     }
   }
   __syncthreads();
@@ -370,9 +383,9 @@ __global__ __launch_bounds__(kBlock) void k_interface(const BoxDev *__restrict__
       lds_gradient<G::R1X, G::R1X * G::R1Y>(s_q[2], c1, sol, a, bq, c);
       Qz = -3.0f * c;
     }
-    PL(aux, A_QX)[node] = Qx;
-    PL(aux, A_QY)[node] = Qy;
-    PL(aux, A_QZ)[node] = Qz;
+    at(PL(aux, A_QX), node) = Qx;
+    at(PL(aux, A_QY), node) = Qy;
+    at(PL(aux, A_QZ), node) = Qz;
   }
 }
 
@@ -460,26 +473,26 @@ __device__ __forceinline__ void collide_node(const BoxDev &B, const NodeIn &in, 
 __device__ __forceinline__ NodeIn load_node_in(const float *__restrict__ aux, int64_t plane,
                                                uint32_t node) {
   NodeIn in;
-  in.rr = PL(aux, A_RR)[node];
-  in.rb = PL(aux, A_RB)[node];
-  in.jx = PL(aux, A_JX)[node];
-  in.jy = PL(aux, A_JY)[node];
-  in.jz = PL(aux, A_JZ)[node];
-  in.pxx = PL(aux, A_PXX)[node];
-  in.pyy = PL(aux, A_PYY)[node];
-  in.pzz = PL(aux, A_PZZ)[node];
-  in.pxy = PL(aux, A_PXY)[node];
-  in.pxz = PL(aux, A_PXZ)[node];
-  in.pyz = PL(aux, A_PYZ)[node];
-  in.nx = PL(aux, A_NX)[node];
-  in.ny = PL(aux, A_NY)[node];
-  in.nz = PL(aux, A_NZ)[node];
-  in.Fx = PL(aux, A_FX)[node];
-  in.Fy = PL(aux, A_FY)[node];
-  in.Fz = PL(aux, A_FZ)[node];
-  in.Qx = PL(aux, A_QX)[node];
-  in.Qy = PL(aux, A_QY)[node];
-  in.Qz = PL(aux, A_QZ)[node];
+  in.rr = at(PL(aux, A_RR), node);
+  in.rb = at(PL(aux, A_RB), node);
+  in.jx = at(PL(aux, A_JX), node);
+  in.jy = at(PL(aux, A_JY), node);
+  in.jz = at(PL(aux, A_JZ), node);
+  in.pxx = at(PL(aux, A_PXX), node);
+  in.pyy = at(PL(aux, A_PYY), node);
+  in.pzz = at(PL(aux, A_PZZ), node);
+  in.pxy = at(PL(aux, A_PXY), node);
+  in.pxz = at(PL(aux, A_PXZ), node);
+  in.pyz = at(PL(aux, A_PYZ), node);
+  in.nx = at(PL(aux, A_NX), node);
+  in.ny = at(PL(aux, A_NY), node);
+  in.nz = at(PL(aux, A_NZ), node);
+  in.Fx = at(PL(aux, A_FX), node);
+  in.Fy = at(PL(aux, A_FY), node);
+  in.Fz = at(PL(aux, A_FZ), node);
+  in.Qx = at(PL(aux, A_QX), node);
+  in.Qy = at(PL(aux, A_QY), node);
+  in.Qz = at(PL(aux, A_QZ), node);
   return in;
 }
 
@@ -503,8 +516,8 @@ __global__ __launch_bounds__(kBlock) void k_collide(const BoxDev *__restrict__ b
   const uint32_t node = (uint32_t)(B.base + local);
   const NodeIn in = load_node_in(aux, plane, node);
   collide_node(B, in, [&](int i, float fr, float fb) {
-    S::store(PL(dst, i) + node, fr);
-    S::store(PL(dst, kQ + i) + node, fb);
+    S::store(&at(PL(dst, i), node), fr);
+    S::store(&at(PL(dst, kQ + i), node), fb);
   });
 }
 
@@ -548,8 +561,8 @@ __global__ __launch_bounds__(kBlock) void k_init(const BoxDev *__restrict__ boxe
               zd = wrap_once(z - kCZ[i], B.nz);
     const uint32_t d = (uint32_t)B.base + (uint32_t)xd +
                        (uint32_t)B.nx * ((uint32_t)yd + (uint32_t)B.ny * (uint32_t)zd);
-    S::store(PL(dst, i) + d, cr * ft);
-    S::store(PL(dst, kQ + i) + d, cb * ft);
+    S::store(&at(PL(dst, i), d), cr * ft);
+    S::store(&at(PL(dst, kQ + i), d), cb * ft);
   }
 }
 
@@ -660,6 +673,39 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
   __syncthreads();
 
   for (int s = z0 - 3; s < z1 + 3; ++s) {
+    // ---- prefetch the global inputs of stages C and D of this iteration, so
+    // that their latency overlaps the stencil work of stages A-C ----
+    float pc_[C_PER][5];
+    if (s - 2 >= z0 - 1) {
+      const uint32_t zoff = (uint32_t)B.base + nxy * (uint32_t)wrap_any(s - 2, nz);
+#pragma unroll
+      for (int kk = 0; kk < C_PER; ++kk) {
+        const uint32_t node = zoff + c_off[kk];
+        const bool ok = tid + kk * G::NT < G::R1;
+        pc_[kk][0] = ok ? at(PL(aux, A_RR), node) : 1.f;
+        pc_[kk][1] = ok ? at(PL(aux, A_RB), node) : 0.f;
+        pc_[kk][2] = ok ? at(PL(aux, A_JX), node) : 0.f;
+        pc_[kk][3] = ok ? at(PL(aux, A_JY), node) : 0.f;
+        pc_[kk][4] = ok ? at(PL(aux, A_JZ), node) : 0.f;
+      }
+    }
+    NodeIn din;
+    const bool d_live = (s - 3 >= z0) && in_xy && write_pops;
+    if (d_live) {
+      const uint32_t node = (uint32_t)B.base + (uint32_t)gxo + (uint32_t)nx * (uint32_t)gyo +
+                            nxy * (uint32_t)wrap_any(s - 3, nz);
+      din.rr = at(PL(aux, A_RR), node);
+      din.rb = at(PL(aux, A_RB), node);
+      din.jx = at(PL(aux, A_JX), node);
+      din.jy = at(PL(aux, A_JY), node);
+      din.jz = at(PL(aux, A_JZ), node);
+      din.pxx = at(PL(aux, A_PXX), node);
+      din.pyy = at(PL(aux, A_PYY), node);
+      din.pzz = at(PL(aux, A_PZZ), node);
+      din.pxy = at(PL(aux, A_PXY), node);
+      din.pxz = at(PL(aux, A_PXZ), node);
+      din.pyz = at(PL(aux, A_PYZ), node);
+    }
     // ---- A: phase field of slab s (Eq. 14) ----
     {
       const uint32_t zoff = (uint32_t)B.base + nxy * (uint32_t)wrap_any(s, nz);
@@ -669,8 +715,8 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
         const int i = tid + k * G::NT;
         if (i < G::R3) {
           const uint32_t node = zoff + (uint32_t)a_off[k];
-          const float rr = PL(aux, A_RR)[node] * B.ir0r;
-          const float rb = PL(aux, A_RB)[node] * B.ir0b;
+          const float rr = at(PL(aux, A_RR), node) * B.ir0r;
+          const float rb = at(PL(aux, A_RB), node) * B.ir0b;
           const float den = rr + rb;
           ph[i] = den > 0.f ? (rr - rb) / den : 0.f;
         }
@@ -736,7 +782,6 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
     if (s - 2 >= z0 - 1) {
       const int sc = s - 2;
       const bool sz_m = slab_solid(sc - 1), sz_c = slab_solid(sc), sz_p = slab_solid(sc + 1);
-      const uint32_t zoff = (uint32_t)B.base + nxy * (uint32_t)wrap_any(sc, nz);
       float(*nm)[G::R2] = s_n[(sc - 1 + 3) % 3];
       float(*nc)[G::R2] = s_n[(sc + 3) % 3];
       float(*np)[G::R2] = s_n[(sc + 1 + 3) % 3];
@@ -794,14 +839,13 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
           Fx = fmaf(hs, nxv, B.Gx);
           Fy = fmaf(hs, nyv, B.Gy);
           Fz = fmaf(hs, nzv, B.Gz);
-          const uint32_t node = zoff + c_off[kk];
-          const float rr = PL(aux, A_RR)[node];
-          const float rb = PL(aux, A_RB)[node];
+          const float rr = pc_[kk][0];
+          const float rb = pc_[kk][1];
           const float rho = rr + rb;
           const float irho = 1.0f / rho;
-          const float ux = fmaf(0.5f, Fx, PL(aux, A_JX)[node]) * irho;
-          const float uy = fmaf(0.5f, Fy, PL(aux, A_JY)[node]) * irho;
-          const float uz = fmaf(0.5f, Fz, PL(aux, A_JZ)[node]) * irho;
+          const float ux = fmaf(0.5f, Fx, pc_[kk][2]) * irho;
+          const float uy = fmaf(0.5f, Fy, pc_[kk][3]) * irho;
+          const float uz = fmaf(0.5f, Fz, pc_[kk][4]) * irho;
           const float dev = rr * B.cs2r + rb * B.cs2b - rho * kCs2;
           qx = dev * ux;
           qy = dev * uy;
@@ -869,18 +913,7 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
         const uint32_t node =
             (uint32_t)B.base + (uint32_t)gxo + (uint32_t)nx * (uint32_t)gyo + nxy * (uint32_t)gz;
         if (write_pops) {
-          NodeIn in;
-          in.rr = PL(aux, A_RR)[node];
-          in.rb = PL(aux, A_RB)[node];
-          in.jx = PL(aux, A_JX)[node];
-          in.jy = PL(aux, A_JY)[node];
-          in.jz = PL(aux, A_JZ)[node];
-          in.pxx = PL(aux, A_PXX)[node];
-          in.pyy = PL(aux, A_PYY)[node];
-          in.pzz = PL(aux, A_PZZ)[node];
-          in.pxy = PL(aux, A_PXY)[node];
-          in.pxz = PL(aux, A_PXZ)[node];
-          in.pyz = PL(aux, A_PYZ)[node];
+          NodeIn in = din;
           in.nx = h_nx;
           in.ny = h_ny;
           in.nz = h_nz;
@@ -891,27 +924,27 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
           in.Qy = Qy;
           in.Qz = Qz;
           collide_node(B, in, [&](int i, float fr, float fb) {
-            S::store(PL(dst, i) + node, fr);
-            S::store(PL(dst, kQ + i) + node, fb);
+            S::store(&at(PL(dst, i), node), fr);
+            S::store(&at(PL(dst, kQ + i), node), fb);
           });
         }
         if (export_fields) {
-          PL(aux, A_NX)[node] = h_nx;
-          PL(aux, A_NY)[node] = h_ny;
-          PL(aux, A_NZ)[node] = h_nz;
-          PL(aux, A_FX)[node] = h_Fx;
-          PL(aux, A_FY)[node] = h_Fy;
-          PL(aux, A_FZ)[node] = h_Fz;
-          PL(aux, A_QX)[node] = Qx;
-          PL(aux, A_QY)[node] = Qy;
-          PL(aux, A_QZ)[node] = Qz;
-          PL(aux, A_KAPPA)[node] = h_k;
+          at(PL(aux, A_NX), node) = h_nx;
+          at(PL(aux, A_NY), node) = h_ny;
+          at(PL(aux, A_NZ), node) = h_nz;
+          at(PL(aux, A_FX), node) = h_Fx;
+          at(PL(aux, A_FY), node) = h_Fy;
+          at(PL(aux, A_FZ), node) = h_Fz;
+          at(PL(aux, A_QX), node) = Qx;
+          at(PL(aux, A_QY), node) = Qy;
+          at(PL(aux, A_QZ), node) = Qz;
+          at(PL(aux, A_KAPPA), node) = h_k;
         }
       } else if (export_fields && in_xy) {
         const uint32_t node =
             (uint32_t)B.base + (uint32_t)gxo + (uint32_t)nx * (uint32_t)gyo + nxy * (uint32_t)gz;
 #pragma unroll
-        for (int k = A_NX; k <= A_KAPPA; ++k) PL(aux, k)[node] = 0.f;
+        for (int k = A_NX; k <= A_KAPPA; ++k) at(PL(aux, k), node) = 0.f;
       }
     }
     // the interface values of slab s-2 become those of the next collision
@@ -954,7 +987,7 @@ __global__ __launch_bounds__(kBlock) void k_fields(const BoxDev *__restrict__ bo
   v[7] = in.nx;
   v[8] = in.ny;
   v[9] = in.nz;
-  v[10] = PL(aux, A_KAPPA)[node];
+  v[10] = at(PL(aux, A_KAPPA), node);
   v[11] = in.Fx;
   v[12] = in.Fy;
   v[13] = in.Fz;
@@ -1073,8 +1106,8 @@ __global__ __launch_bounds__(kBlock) void k_reduce2(const BoxDev *__restrict__ b
     const int y = (int)(yz - (uint32_t)z * (uint32_t)B.ny);
     if (!is_solid(B, y, z)) {
       const uint32_t node = (uint32_t)(B.base + local);
-      const double p = (double)(PL(aux, A_RR)[node] * B.cs2r +
-                                PL(aux, A_RB)[node] * B.cs2b);
+      const double p = (double)(at(PL(aux, A_RR), node) * B.cs2r +
+                                at(PL(aux, A_RB), node) * B.cs2b);
       const double dx = periodic_offset(x - (float)centre[3 * b + 0], B.nx, true);
       const double dy = periodic_offset(y - (float)centre[3 * b + 1], B.ny, !(B.walls & 1u));
       const double dz = periodic_offset(z - (float)centre[3 * b + 2], B.nz, !(B.walls & 2u));
