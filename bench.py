@@ -49,6 +49,34 @@ def parse():
     return ap.parse_args()
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "k_fused_translating_droplet_256_hbm_counters.md")
+SOURCES = ("paper_2309_07801_amd/csrc/kernels.hpp", "paper_2309_07801_amd/csrc/lattice.hpp",
+           "paper_2309_07801_amd/csrc/cglbm.hip")
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per dispatch of `kernel` from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (already scaled by the copy-kernel
+    calibration), or None if the summary is missing or the kernel sources
+    changed since the counters were taken."""
+    import hashlib
+    import re
+    if not os.path.exists(COUNTERS):
+        return None
+    text = open(COUNTERS).read()
+    m = re.search(r"source_sha256: ([0-9a-f]{64})", text)
+    h = hashlib.sha256()
+    for f in SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if not m or m.group(1) != h.hexdigest():
+        return None
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) == 6 and cells[0] == kernel:
+            return float(cells[4])
+    return None
+
+
 def copy_probe():
     """A plain copy kernel of known size: 2 GiB read, 2 GiB written, 5 times."""
     import torch
@@ -144,6 +172,12 @@ def main():
                        "share": ms / 1e3 / dt}
     dom = max(kern, key=lambda k: kern[k]["share"])
     achieved = kern[dom]["gbs"]
+    if dom == "fused":
+        kname = "k_fused<%d, %d, %d, %d, false, f32>" % (variant["tx"], variant["ty"], variant["zc"],
+                                                        variant["min_waves"])
+    else:
+        kname = "k_%s<f32>" % dom
+    traffic = measured_traffic(kname) if n == 256 else None
     line = {
         "metric": "MLUPS and % HBM roofline, FP32 vs FP16-storage vs batched, at fixed error",
         "value": round(mlups, 1),
@@ -162,7 +196,8 @@ def main():
                    "nodes": fluid, "storage": "fp32"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "kernel": "k_" + dom,
+                     "traffic": traffic, "traffic_unit": "bytes per launch",
+                     "algorithmic_bytes": KERNEL_BYTES[dom] * fluid, "kernel": kname,
                      "bytes_per_node": KERNEL_BYTES[dom]},
         "step_roofline_frac": round(mlups * 1e6 * STEP_BYTES / (HBM_PEAK_GBS * 1e9), 4),
         "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in kern.items()},

@@ -471,12 +471,12 @@ int cglbm_reduce(cglbm_handle *h, const double *centre, double *out, int32_t out
   if (rc) return rc;
   hipLaunchKernelGGL(k_reduce1, dim3(h->L.nblk), dim3(kBlock), 0, s, h->d_boxes, h->d_blk_box,
                      h->aux, h->L.total, h->d_centre, h->d_part);
-  hipLaunchKernelGGL(k_reduce_final, dim3(h->n_boxes), dim3(64), 0, s, h->d_boxes, h->d_part, 1,
-                     h->d_diag);
+  hipLaunchKernelGGL(k_reduce_final, dim3(h->n_boxes), dim3(kBlock), 0, s, h->d_boxes, h->d_part,
+                     1, h->d_diag);
   hipLaunchKernelGGL(k_reduce2, dim3(h->L.nblk), dim3(kBlock), 0, s, h->d_boxes, h->d_blk_box,
                      h->aux, h->L.total, h->d_centre, h->d_diag, h->d_part);
-  hipLaunchKernelGGL(k_reduce_final, dim3(h->n_boxes), dim3(64), 0, s, h->d_boxes, h->d_part, 2,
-                     h->d_diag);
+  hipLaunchKernelGGL(k_reduce_final, dim3(h->n_boxes), dim3(kBlock), 0, s, h->d_boxes, h->d_part,
+                     2, h->d_diag);
   if ((rc = check_launch())) return rc;
   std::vector<double> diag((size_t)kNPart * h->n_boxes);
   HIP_TRY(hipMemcpyAsync(diag.data(), h->d_diag, sizeof(double) * diag.size(),

@@ -1127,38 +1127,46 @@ __global__ __launch_bounds__(kBlock) void k_reduce2(const BoxDev *__restrict__ b
   block_sum_f64<4>(v, part + (int64_t)blockIdx.x * kNPart);
 }
 
-// One block per box: fixed-order sum of the box's block partials.
+// One block per box: fixed-order sum of the box's block partials.  Thread t
+// sums the contiguous run [t*c, (t+1)*c) of partials in order, then a fixed
+// tree combines the 256 thread sums; the order depends only on the box.
 // pass 1 fills diag[0..4, 7 (R_eff), 8..10 (centroid), 11, 12]; pass 2 fills 5, 6.
-__global__ __launch_bounds__(64) void k_reduce_final(const BoxDev *__restrict__ boxes,
-                                                     const double *__restrict__ part, int pass,
-                                                     double *__restrict__ diag) {
+__global__ __launch_bounds__(kBlock) void k_reduce_final(const BoxDev *__restrict__ boxes,
+                                                         const double *__restrict__ part, int pass,
+                                                         double *__restrict__ diag) {
   const int b = blockIdx.x;
   const BoxDev B = boxes[b];
   const int nblk = (int)((B.n + kBlock - 1) / kBlock);
+  const int chunk = (nblk + kBlock - 1) / kBlock;
+  const int k0 = min((int)threadIdx.x * chunk, nblk), k1 = min(k0 + chunk, nblk);
+  double v[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  const int nv = pass == 1 ? 11 : 4;
+  for (int k = k0; k < k1; ++k)
+    for (int c = 0; c < nv; ++c) v[c] += part[(int64_t)(B.blk0 + k) * kNPart + c];
+  __shared__ double tot[kNPart];
+  {
+    double w[11];
+    for (int c = 0; c < 11; ++c) w[c] = v[c];
+    block_sum_f64<11>(w, tot);
+  }
+  __syncthreads();
   if (threadIdx.x != 0) return;
+  double *o = diag + (int64_t)b * kNPart;
   if (pass == 1) {
-    double s[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int k = 0; k < nblk; ++k)
-      for (int c = 0; c < 11; ++c) s[c] += part[(int64_t)(B.blk0 + k) * kNPart + c];
-    double *o = diag + (int64_t)b * kNPart;
-    o[0] = s[0];
-    o[1] = s[1];
-    o[2] = s[2];
-    o[3] = s[3];
-    o[4] = s[4];
-    o[7] = cbrt(3.0 * s[5] / (4.0 * 3.14159265358979323846));
-    o[8] = s[0] > 0 ? s[6] / s[0] : 0.0;
-    o[9] = s[0] > 0 ? s[7] / s[0] : 0.0;
-    o[10] = s[0] > 0 ? s[8] / s[0] : 0.0;
-    o[11] = s[9];
-    o[12] = s[10];
+    o[0] = tot[0];
+    o[1] = tot[1];
+    o[2] = tot[2];
+    o[3] = tot[3];
+    o[4] = tot[4];
+    o[7] = cbrt(3.0 * tot[5] / (4.0 * 3.14159265358979323846));
+    o[8] = tot[0] > 0 ? tot[6] / tot[0] : 0.0;
+    o[9] = tot[0] > 0 ? tot[7] / tot[0] : 0.0;
+    o[10] = tot[0] > 0 ? tot[8] / tot[0] : 0.0;
+    o[11] = tot[9];
+    o[12] = tot[10];
   } else {
-    double s[4] = {0, 0, 0, 0};
-    for (int k = 0; k < nblk; ++k)
-      for (int c = 0; c < 4; ++c) s[c] += part[(int64_t)(B.blk0 + k) * kNPart + c];
-    double *o = diag + (int64_t)b * kNPart;
-    o[5] = s[1] > 0 ? s[0] / s[1] : 0.0;
-    o[6] = s[3] > 0 ? s[2] / s[3] : 0.0;
+    o[5] = tot[1] > 0 ? tot[0] / tot[1] : 0.0;
+    o[6] = tot[3] > 0 ? tot[2] / tot[3] : 0.0;
   }
 }
 
