@@ -46,20 +46,23 @@ constexpr int kTX = 8, kTY = 8, kTZ = 8;   // interface tile (three-kernel sched
 // minimum waves per SIMD requested from the register allocator.  Every
 // variant performs the same arithmetic per node (results are bitwise equal);
 // cglbm_autotune picks the fastest for the boxes at hand.
-using FusedFn = void (*)(const BoxDev *, const int32_t *, float *, float *, int64_t, int, int);
+using FusedFn = void (*)(const BoxDev *, const int32_t *, float *, void *, int64_t, int, int);
 struct FusedVariant {
   int tx, ty, zc, minw;
-  FusedFn fn;        // periodic boxes only
-  FusedFn fn_walls;  // any box with solid layers
+  FusedFn fn[4][2];  // [storage][any box with solid layers]
 };
-#define FV(TX, TY, ZC, MW) \
-  {TX, TY, ZC, MW, k_fused<TX, TY, ZC, MW, false, StoreF32>, k_fused<TX, TY, ZC, MW, true, StoreF32>}
+#define FV_S(TX, TY, ZC, MW, S) {k_fused<TX, TY, ZC, MW, false, S>, k_fused<TX, TY, ZC, MW, true, S>}
+#define FV(TX, TY, ZC, MW)                                                                    \
+  {TX, TY, ZC, MW,                                                                           \
+   {FV_S(TX, TY, ZC, MW, StoreF32), FV_S(TX, TY, ZC, MW, StoreF16), FV_S(TX, TY, ZC, MW, StoreBF16), \
+    FV_S(TX, TY, ZC, MW, StoreF32X)}}
 const FusedVariant kFusedVariants[] = {
     FV(32, 8, 32, 4),  FV(32, 8, 64, 4),  FV(32, 8, 16, 4), FV(32, 8, 32, 1),
     FV(32, 16, 32, 4), FV(32, 16, 64, 4), FV(64, 4, 32, 4), FV(32, 4, 32, 4),
     FV(32, 8, 32, 5),
 };
 #undef FV
+#undef FV_S
 constexpr int kNumFused = (int)(sizeof(kFusedVariants) / sizeof(kFusedVariants[0]));
 constexpr int64_t kAlign = 64;             // node alignment of each box's base
 constexpr double kXi = 9.0 / 19.0;
@@ -67,6 +70,27 @@ constexpr double kXi = 9.0 / 19.0;
 enum { KIND_PULL = 0, KIND_IFACE = 1, KIND_COLLIDE = 2, KIND_FUSED = 3, KIND_N = 4 };
 
 int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+// Kernels by storage format (index = cglbm_storage).
+using PullFn = void (*)(const BoxDev *, const int32_t *, void *, void *, float *, int64_t, int);
+using CollideFn = void (*)(const BoxDev *, const int32_t *, float *, void *, int64_t);
+using InitFn = void (*)(const BoxDev *, const int32_t *, const float *, const float *,
+                        const float *, void *, int64_t, uint64_t, float);
+const PullFn kPull[4] = {k_pull<StoreF32>, k_pull<StoreF16>, k_pull<StoreBF16>, k_pull<StoreF32X>};
+const CollideFn kCollide[4] = {k_collide<StoreF32>, k_collide<StoreF16>, k_collide<StoreBF16>,
+                               k_collide<StoreF32X>};
+const InitFn kInit[4] = {k_init<StoreF32>, k_init<StoreF16>, k_init<StoreBF16>, k_init<StoreF32X>};
+bool storage_exact(int32_t st) { return st != CGLBM_FP32; }
+size_t storage_bytes(int32_t st) { return (st == CGLBM_FP16_SHIFT || st == CGLBM_BF16_SHIFT) ? 2 : 4; }
+
+// Bytes of one population buffer and of the aux buffer for `total` nodes.
+void buffer_sizes(int32_t st, int64_t total, size_t *pop, size_t *aux) {
+  if (storage_exact(st))
+    *pop = (size_t)align256(52 * total * (int64_t)storage_bytes(st)) + (size_t)(2 * total * 8);
+  else
+    *pop = (size_t)(54 * total * 4);
+  *aux = (size_t)align256((int64_t)A_COUNT * total * 4) + (storage_exact(st) ? (size_t)(2 * total * 8) : 0);
+}
 
 struct Layout {
   std::vector<BoxDev> boxes;
@@ -78,8 +102,8 @@ struct Layout {
 
 int validate(int32_t n_boxes, const cglbm_box_params *boxes, int32_t storage) {
   if (n_boxes <= 0 || !boxes) return fail(CGLBM_EINVAL, "n_boxes must be > 0 and boxes non-NULL");
-  if (storage != CGLBM_FP32)
-    return fail(CGLBM_EUNSUPPORTED, "storage %d is not built (only CGLBM_FP32)", storage);
+  if (storage < CGLBM_FP32 || storage > CGLBM_FP32_EXACT)
+    return fail(CGLBM_EINVAL, "unknown storage format %d", storage);
   int64_t total = 0;
   for (int b = 0; b < n_boxes; ++b) {
     const cglbm_box_params &P = boxes[b];
@@ -164,6 +188,14 @@ void build_layout(int32_t n_boxes, const cglbm_box_params *boxes, Layout &L) {
     B.Gx = (float)P.body_force[0];
     B.Gy = (float)P.body_force[1];
     B.Gz = (float)P.body_force[2];
+    {
+      // pure-phase rest equilibrium of each colour: w_i rho_k^0 (c_s^k)^2 / c_s^2
+      const double w[4] = {8.0 / 27.0, 2.0 / 27.0, 1.0 / 54.0, 1.0 / 216.0};
+      const double p0[2] = {P.red.rho0 * kXi * (1.0 - P.red.alpha),
+                            P.blue.rho0 * kXi * (1.0 - P.blue.alpha)};
+      for (int c = 0; c < 2; ++c)
+        for (int k = 0; k < 4; ++k) B.shift[c][k] = (float)(w[k] * p0[c] * 3.0);
+    }
     L.boxes.push_back(B);
     if (P.walls) L.walls = true;
   }
@@ -240,10 +272,9 @@ struct cglbm_handle {
 namespace {
 
 int launch_pull(cglbm_handle *h, hipStream_t s, int bounce) {
-  float *src = (float *)h->pop[h->cur];
-  float *dst = (float *)h->pop[1 - h->cur];
-  hipLaunchKernelGGL(k_pull<StoreF32>, dim3(h->L.nblk_pad), dim3(kBlock), 0, s, h->d_boxes,
-                     h->d_blk_box, src, dst, h->aux, h->L.total, bounce);
+  hipLaunchKernelGGL(kPull[h->storage], dim3(h->L.nblk_pad), dim3(kBlock), 0, s, h->d_boxes,
+                     h->d_blk_box, h->pop[h->cur], h->pop[1 - h->cur], h->aux, h->L.total,
+                     bounce);
   return CGLBM_OK;
 }
 
@@ -258,11 +289,11 @@ int launch_fused(cglbm_handle *h, hipStream_t s, int write_pops, int export_fiel
   const BoxDev *boxes = h->d_boxes;
   const int32_t *cols = h->d_col_box;
   float *aux = h->aux;
-  float *dst = (float *)h->pop[1 - h->cur];
+  void *dst = h->pop[1 - h->cur];
   int64_t plane = h->L.total;
   void *args[] = {(void *)&boxes, (void *)&cols, (void *)&aux, (void *)&dst,
                   (void *)&plane, (void *)&write_pops, (void *)&export_fields};
-  HIP_TRY(hipLaunchKernel((const void *)(h->L.walls ? F.fn_walls : F.fn), dim3(h->L.ncol),
+  HIP_TRY(hipLaunchKernel((const void *)F.fn[h->storage][h->L.walls ? 1 : 0], dim3(h->L.ncol),
                           dim3(F.tx * F.ty), args, 0, s));
   return CGLBM_OK;
 }
@@ -287,9 +318,8 @@ int select_variant(cglbm_handle *h, int v, hipStream_t s) {
 }
 
 int launch_collide(cglbm_handle *h, hipStream_t s) {
-  float *dst = (float *)h->pop[1 - h->cur];
-  hipLaunchKernelGGL(k_collide<StoreF32>, dim3(h->L.nblk_pad), dim3(kBlock), 0, s, h->d_boxes,
-                     h->d_blk_box, h->aux, dst, h->L.total);
+  hipLaunchKernelGGL(kCollide[h->storage], dim3(h->L.nblk_pad), dim3(kBlock), 0, s, h->d_boxes,
+                     h->d_blk_box, h->aux, h->pop[1 - h->cur], h->L.total);
   return CGLBM_OK;
 }
 
@@ -339,8 +369,10 @@ int cglbm_query_sizes(int32_t n_boxes, const cglbm_box_params *boxes, int32_t st
   if (rc) return rc;
   Layout L;
   build_layout(n_boxes, boxes, L);
-  if (pop_bytes) *pop_bytes = (size_t)L.total * 2 * kQ * sizeof(float);
-  if (aux_bytes) *aux_bytes = (size_t)L.total * A_COUNT * sizeof(float);
+  size_t pb, ab;
+  buffer_sizes(storage, L.total, &pb, &ab);
+  if (pop_bytes) *pop_bytes = pb;
+  if (aux_bytes) *aux_bytes = ab;
   if (total_nodes) *total_nodes = L.total;
   return CGLBM_OK;
 }
@@ -408,9 +440,9 @@ int cglbm_init(cglbm_handle **out, int32_t n_boxes, const cglbm_box_params *boxe
   if ((rc = select_variant(h, 0, s))) return cleanup(rc);
   // the stored state lives in pop[0]
   h->cur = 0;
-  hipLaunchKernelGGL(k_init<StoreF32>, dim3(h->L.nblk), dim3(kBlock), 0, s, h->d_boxes,
-                     h->d_blk_box, init_rho_r, init_rho_b, init_u, (float *)h->pop[0],
-                     h->L.total, noise_seed, (float)noise_amp);
+  hipLaunchKernelGGL(kInit[storage], dim3(h->L.nblk), dim3(kBlock), 0, s, h->d_boxes,
+                     h->d_blk_box, init_rho_r, init_rho_b, init_u, h->pop[0], h->L.total,
+                     noise_seed, (float)noise_amp);
   if ((rc = check_launch())) return cleanup(rc);
   *out = h;
   return CGLBM_OK;
@@ -469,8 +501,12 @@ int cglbm_reduce(cglbm_handle *h, const double *centre, double *out, int32_t out
   HIP_TRY(hipMemcpyAsync(h->d_centre, c.data(), sizeof(double) * c.size(), hipMemcpyHostToDevice, s));
   int rc = compute_fields(h, s, 0);
   if (rc) return rc;
+  const double *rho64 =
+      storage_exact(h->storage)
+          ? (const double *)((const char *)h->aux + align256((int64_t)A_COUNT * h->L.total * 4))
+          : nullptr;
   hipLaunchKernelGGL(k_reduce1, dim3(h->L.nblk), dim3(kBlock), 0, s, h->d_boxes, h->d_blk_box,
-                     h->aux, h->L.total, h->d_centre, h->d_part);
+                     h->aux, h->L.total, rho64, h->d_centre, h->d_part);
   hipLaunchKernelGGL(k_reduce_final, dim3(h->n_boxes), dim3(kBlock), 0, s, h->d_boxes, h->d_part,
                      1, h->d_diag);
   hipLaunchKernelGGL(k_reduce2, dim3(h->L.nblk), dim3(kBlock), 0, s, h->d_boxes, h->d_blk_box,

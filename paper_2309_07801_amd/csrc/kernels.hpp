@@ -48,6 +48,7 @@ struct BoxDev {
   float sigma, beta;
   float omega2;
   float Gx, Gy, Gz;
+  float shift[2][4];    // storage shift by colour and speed class |c|^2
 };
 
 constexpr int kBlock = 256;
@@ -96,13 +97,88 @@ __device__ __forceinline__ bool is_solid(const BoxDev &B, int y, int z) {
 }
 
 // ---------------------------------------------------------------------------
-// Population storage formats
+// Population storage formats.
+//
+// Plain FP32: 54 float planes, plane c*27 + i.
+// Mass-exact formats: the 26 moving directions of each colour are stored in
+// type T, plane c*26 + (i - 1), and the two rest populations in FP64 planes
+// after them.  The collision sets the rest population from the node's
+// colour density (carried in FP64) minus the 26 stored moving populations
+// as they will be read back, so each colour's mass is conserved to FP64
+// rounding whatever the storage precision.  FP16/BF16 store each moving
+// population minus the pure-phase rest equilibrium of its colour,
+// s^k_i = w_i rho_k^0 (c_s^k)^2 / c_s^2, rounded to T (zero stays exact).
 // ---------------------------------------------------------------------------
 struct StoreF32 {
   using T = float;
-  __device__ static float load(const T *p) { return __builtin_nontemporal_load(p); }
-  __device__ static void store(T *p, float v) { __builtin_nontemporal_store(v, p); }
+  static constexpr bool kExact = false, kShift = false;
+  __device__ static T enc(float v) { return v; }
+  __device__ static float dec(T g) { return g; }
 };
+struct StoreF32X {
+  using T = float;
+  static constexpr bool kExact = true, kShift = false;
+  __device__ static T enc(float v) { return v; }
+  __device__ static float dec(T g) { return g; }
+};
+struct StoreF16 {
+  using T = uint16_t;
+  static constexpr bool kExact = true, kShift = true;
+  __device__ static T enc(float v) { return __builtin_bit_cast(uint16_t, (_Float16)v); }
+  __device__ static float dec(T g) { return (float)__builtin_bit_cast(_Float16, g); }
+};
+struct StoreBF16 {
+  using T = uint16_t;
+  static constexpr bool kExact = true, kShift = true;
+  // round to nearest even on the bit pattern; NaN kept quiet
+  __device__ static T enc(float v) {
+    const uint32_t u = __builtin_bit_cast(uint32_t, v);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+  }
+  __device__ static float dec(T g) { return __builtin_bit_cast(float, (uint32_t)g << 16); }
+};
+
+__host__ __device__ inline int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
+
+// Views of one population buffer and of the FP64 aux planes.
+template <class S>
+struct Pops {
+  typename S::T *mv;
+  double *rest;
+  int64_t plane;
+  __device__ Pops(void *base, int64_t plane_) : plane(plane_) {
+    mv = (typename S::T *)base;
+    rest = (double *)((char *)base + align256((S::kExact ? 52 : 54) * plane_ *
+                                               (int64_t)sizeof(typename S::T)));
+  }
+  __device__ typename S::T *mvp(int c, int i) const {
+    return mv + (int64_t)(S::kExact ? c * 26 + i - 1 : c * 27 + i) * plane;
+  }
+  __device__ double *restp(int c) const { return rest + (int64_t)c * plane; }
+};
+
+// FP64 colour densities (mass-exact formats), after the 21 float aux planes.
+__device__ __forceinline__ double *aux_rho64(float *aux, int64_t plane) {
+  return (double *)((char *)aux + align256((int64_t)A_COUNT * plane * 4));
+}
+
+// Shift of direction i of colour c (0 without shift), as a value of T.
+template <class S>
+__device__ __forceinline__ float pop_shift(const BoxDev &B, int c, int i) {
+  if (!S::kShift || i == 0) return 0.f;
+  const int cls = kCX[i] * kCX[i] + kCY[i] * kCY[i] + kCZ[i] * kCZ[i];
+  return S::dec(S::enc(B.shift[c][cls]));
+}
+
+template <class S>
+__device__ __forceinline__ typename S::T ld(const typename S::T *p) {
+  return __builtin_nontemporal_load(p);
+}
+template <class S>
+__device__ __forceinline__ void st(typename S::T *p, typename S::T v) {
+  __builtin_nontemporal_store(v, p);
+}
 
 // ---------------------------------------------------------------------------
 // k_pull: f^k_i(x) = stored_i(x - c_i); local moments; bounce-back at solid
@@ -111,8 +187,7 @@ struct StoreF32 {
 template <class S>
 __global__ __launch_bounds__(kBlock) void k_pull(const BoxDev *__restrict__ boxes,
                                                  const int32_t *__restrict__ blk_box,
-                                                 const typename S::T *__restrict__ src,
-                                                 typename S::T *__restrict__ dst,
+                                                 void *__restrict__ src_, void *__restrict__ dst_,
                                                  float *__restrict__ aux, int64_t plane,
                                                  int bounce) {
   const uint32_t lb = xcd_block();
@@ -121,6 +196,7 @@ __global__ __launch_bounds__(kBlock) void k_pull(const BoxDev *__restrict__ boxe
   const BoxDev B = boxes[b];
   const int64_t local = (int64_t)(lb - B.blk0) * kBlock + threadIdx.x;
   if (local >= B.n) return;
+  const Pops<S> src(src_, plane), dst(dst_, plane);
   const uint32_t l = (uint32_t)local;
   const uint32_t yz = fdiv(l, B.fdx);
   const int x = (int)(l - yz * (uint32_t)B.nx);
@@ -137,34 +213,58 @@ __global__ __launch_bounds__(kBlock) void k_pull(const BoxDev *__restrict__ boxe
 #pragma unroll
     for (int c = 0; c < 3; ++c)
       row[a][c] = (uint32_t)B.base + (uint32_t)nx * ((uint32_t)ys[a] + (uint32_t)ny * (uint32_t)zs[c]);
-
-  float fr[kQ], fb[kQ];
-#pragma unroll
-  for (int i = 0; i < kQ; ++i) {
-    const uint32_t s = row[kCY[i] + 1][kCZ[i] + 1] + (uint32_t)xs[kCX[i] + 1];
-    fr[i] = S::load(&at(PL(src, i), s));
-    fb[i] = S::load(&at(PL(src, kQ + i), s));
-  }
   const uint32_t node = (uint32_t)(B.base + local);
+
+  typename S::T gr[kQ], gb[kQ];
+  constexpr int i0 = S::kExact ? 1 : 0;
+#pragma unroll
+  for (int i = i0; i < kQ; ++i) {
+    const uint32_t s = row[kCY[i] + 1][kCZ[i] + 1] + (uint32_t)xs[kCX[i] + 1];
+    gr[i] = ld<S>(&at(src.mvp(0, i), s));
+    gb[i] = ld<S>(&at(src.mvp(1, i), s));
+  }
+  double rr0 = 0.0, rb0 = 0.0;
+  if (S::kExact) {
+    rr0 = at(src.restp(0), node);
+    rb0 = at(src.restp(1), node);
+  }
   if (is_solid(B, y, z)) {
     if (bounce) {
+      // the shift of direction i equals that of its opposite: copy raw values
 #pragma unroll
-      for (int i = 0; i < kQ; ++i) {
-        S::store(&at(PL(dst, opposite(i)), node), fr[i]);
-        S::store(&at(PL(dst, kQ + opposite(i)), node), fb[i]);
+      for (int i = i0; i < kQ; ++i) {
+        st<S>(&at(dst.mvp(0, opposite(i)), node), gr[i]);
+        st<S>(&at(dst.mvp(1, opposite(i)), node), gb[i]);
+      }
+      if (S::kExact) {
+        at(dst.restp(0), node) = rr0;
+        at(dst.restp(1), node) = rb0;
       }
     }
 #pragma unroll
     for (int k = 0; k <= A_PYZ; ++k) at(PL(aux, k), node) = 0.0f;
+    if (S::kExact) {
+      double *r64 = aux_rho64(aux, plane);
+      at(r64, node) = 0.0;
+      at(r64 + plane, node) = 0.0;
+    }
     return;
   }
   float rr = 0.f, rb = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
   float pxx = 0.f, pyy = 0.f, pzz = 0.f, pxy = 0.f, pxz = 0.f, pyz = 0.f;
+  double drr = rr0, drb = rb0;
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) {
-    rr += fr[i];
-    rb += fb[i];
-    const float f = fr[i] + fb[i];
+  for (int i = i0; i < kQ; ++i) {
+    const float vr = S::dec(gr[i]) + pop_shift<S>(B, 0, i);
+    const float vb = S::dec(gb[i]) + pop_shift<S>(B, 1, i);
+    if (S::kExact) {
+      drr += (double)vr;
+      drb += (double)vb;
+    } else {
+      rr += vr;
+      rb += vb;
+    }
+    const float f = vr + vb;
     if (kCX[i]) jx += kCX[i] > 0 ? f : -f;
     if (kCY[i]) jy += kCY[i] > 0 ? f : -f;
     if (kCZ[i]) jz += kCZ[i] > 0 ? f : -f;
@@ -174,6 +274,13 @@ __global__ __launch_bounds__(kBlock) void k_pull(const BoxDev *__restrict__ boxe
     if (kCX[i] * kCY[i]) pxy += kCX[i] * kCY[i] > 0 ? f : -f;
     if (kCX[i] * kCZ[i]) pxz += kCX[i] * kCZ[i] > 0 ? f : -f;
     if (kCY[i] * kCZ[i]) pyz += kCY[i] * kCZ[i] > 0 ? f : -f;
+  }
+  if (S::kExact) {
+    rr = (float)drr;
+    rb = (float)drb;
+    double *r64 = aux_rho64(aux, plane);
+    at(r64, node) = drr;
+    at(r64 + plane, node) = drb;
   }
   at(PL(aux, A_RR), node) = rr;
   at(PL(aux, A_RB), node) = rb;
@@ -496,12 +603,40 @@ __device__ __forceinline__ NodeIn load_node_in(const float *__restrict__ aux, in
   return in;
 }
 
+// Writes one node's collided, recoloured populations in storage format S.
+// Mass-exact formats skip the rest population during the emission and close
+// it at the end from the node's FP64 colour densities.
+template <class S>
+struct PopWriter {
+  const Pops<S> &dst;
+  const BoxDev &B;
+  uint32_t node;
+  double sr = 0.0, sb = 0.0;
+  __device__ PopWriter(const Pops<S> &d, const BoxDev &b, uint32_t n) : dst(d), B(b), node(n) {}
+  __device__ __forceinline__ void operator()(int i, float fr, float fb) {
+    if (S::kExact && i == 0) return;
+    const float shr = pop_shift<S>(B, 0, i), shb = pop_shift<S>(B, 1, i);
+    const typename S::T er = S::enc(fr - shr), eb = S::enc(fb - shb);
+    st<S>(&at(dst.mvp(0, i), node), er);
+    st<S>(&at(dst.mvp(1, i), node), eb);
+    if (S::kExact) {
+      sr += (double)(S::dec(er) + shr);
+      sb += (double)(S::dec(eb) + shb);
+    }
+  }
+  __device__ __forceinline__ void finish(double rho_r, double rho_b) {
+    if (S::kExact) {
+      at(dst.restp(0), node) = rho_r - sr;
+      at(dst.restp(1), node) = rho_b - sb;
+    }
+  }
+};
+
 template <class S>
 __global__ __launch_bounds__(kBlock) void k_collide(const BoxDev *__restrict__ boxes,
                                                     const int32_t *__restrict__ blk_box,
-                                                    const float *__restrict__ aux,
-                                                    typename S::T *__restrict__ dst,
-                                                    int64_t plane) {
+                                                    float *__restrict__ aux,
+                                                    void *__restrict__ dst_, int64_t plane) {
   const uint32_t lb = xcd_block();
   const int b = blk_box[lb];
   if (b < 0) return;
@@ -515,16 +650,20 @@ __global__ __launch_bounds__(kBlock) void k_collide(const BoxDev *__restrict__ b
   if (is_solid(B, y, z)) return;
   const uint32_t node = (uint32_t)(B.base + local);
   const NodeIn in = load_node_in(aux, plane, node);
-  collide_node(B, in, [&](int i, float fr, float fb) {
-    S::store(&at(PL(dst, i), node), fr);
-    S::store(&at(PL(dst, kQ + i), node), fb);
-  });
+  const Pops<S> dst(dst_, plane);
+  PopWriter<S> w(dst, B, node);
+  collide_node(B, in, w);
+  if (S::kExact) {
+    const double *r64 = aux_rho64(aux, plane);
+    w.finish(at(r64, node), at(r64 + plane, node));
+  }
 }
 
 // ---------------------------------------------------------------------------
 // Initial state: f^k = (rho_k/rho)(f^eq + eta) with the Model D equilibrium
 // built from its central moments (Eqs. 57-63), written un-streamed so that the
-// first pull reproduces f(x, 0): stored_i(x - c_i) = f_i(x).
+// first pull reproduces f(x, 0): stored_i(x - c_i) = f_i(x).  Mass-exact
+// formats close the rest population on the FP64 sum of the node's values.
 // ---------------------------------------------------------------------------
 template <class S>
 __global__ __launch_bounds__(kBlock) void k_init(const BoxDev *__restrict__ boxes,
@@ -532,12 +671,13 @@ __global__ __launch_bounds__(kBlock) void k_init(const BoxDev *__restrict__ boxe
                                                  const float *__restrict__ in_rr,
                                                  const float *__restrict__ in_rb,
                                                  const float *__restrict__ in_u,
-                                                 typename S::T *__restrict__ dst, int64_t plane,
+                                                 void *__restrict__ dst_, int64_t plane,
                                                  uint64_t seed, float amp) {
   const int b = blk_box[blockIdx.x];
   const BoxDev B = boxes[b];
   const int64_t local = (int64_t)(blockIdx.x - B.blk0) * kBlock + threadIdx.x;
   if (local >= B.n) return;
+  const Pops<S> dst(dst_, plane);
   const uint32_t l = (uint32_t)local;
   const uint32_t yz = fdiv(l, B.fdx);
   const int x = (int)(l - yz * (uint32_t)B.nx);
@@ -553,16 +693,29 @@ __global__ __launch_bounds__(kBlock) void k_init(const BoxDev *__restrict__ boxe
   float f[kQ];
   central_to_populations(k, ux, uy, uz, f);
   const float cr = rr / rho, cb = rb / rho;
+  double tr = 0.0, tb = 0.0, sr = 0.0, sb = 0.0;
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
     const float ft = amp != 0.f ? f[i] + counter_noise(seed, (uint32_t)b, (uint64_t)local, i, amp)
                                 : f[i];
+    const float vr = cr * ft, vb = cb * ft;
+    tr += (double)vr;
+    tb += (double)vb;
+    if (S::kExact && i == 0) continue;
     const int xd = wrap_once(x - kCX[i], B.nx), yd = wrap_once(y - kCY[i], B.ny),
               zd = wrap_once(z - kCZ[i], B.nz);
     const uint32_t d = (uint32_t)B.base + (uint32_t)xd +
                        (uint32_t)B.nx * ((uint32_t)yd + (uint32_t)B.ny * (uint32_t)zd);
-    S::store(&at(PL(dst, i), d), cr * ft);
-    S::store(&at(PL(dst, kQ + i), d), cb * ft);
+    const float shr = pop_shift<S>(B, 0, i), shb = pop_shift<S>(B, 1, i);
+    const typename S::T er = S::enc(vr - shr), eb = S::enc(vb - shb);
+    st<S>(&at(dst.mvp(0, i), d), er);
+    st<S>(&at(dst.mvp(1, i), d), eb);
+    sr += (double)(S::dec(er) + shr);
+    sb += (double)(S::dec(eb) + shb);
+  }
+  if (S::kExact) {
+    at(dst.restp(0), node) = tr - sr;
+    at(dst.restp(1), node) = tb - sb;
   }
 }
 
@@ -587,7 +740,7 @@ template <int TX, int TY, int ZC, int MINW, bool WALLS, class S>
 __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict__ boxes,
                                                   const int32_t *__restrict__ col_box,
                                                   float *__restrict__ aux,
-                                                  typename S::T *__restrict__ dst, int64_t plane,
+                                                  void *__restrict__ dst_, int64_t plane,
                                                   int write_pops, int export_fields) {
   using G = FusedGeom<TX, TY>;
   __shared__ float s_phi[3][G::R3];
@@ -690,10 +843,16 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
       }
     }
     NodeIn din;
+    double d_rr = 0.0, d_rb = 0.0;
     const bool d_live = (s - 3 >= z0) && in_xy && write_pops;
     if (d_live) {
       const uint32_t node = (uint32_t)B.base + (uint32_t)gxo + (uint32_t)nx * (uint32_t)gyo +
                             nxy * (uint32_t)wrap_any(s - 3, nz);
+      if (S::kExact) {
+        const double *r64 = aux_rho64(aux, plane);
+        d_rr = at(r64, node);
+        d_rb = at(r64 + plane, node);
+      }
       din.rr = at(PL(aux, A_RR), node);
       din.rb = at(PL(aux, A_RB), node);
       din.jx = at(PL(aux, A_JX), node);
@@ -923,10 +1082,10 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
           in.Qx = Qx;
           in.Qy = Qy;
           in.Qz = Qz;
-          collide_node(B, in, [&](int i, float fr, float fb) {
-            S::store(&at(PL(dst, i), node), fr);
-            S::store(&at(PL(dst, kQ + i), node), fb);
-          });
+          const Pops<S> dst(dst_, plane);
+          PopWriter<S> w(dst, B, node);
+          collide_node(B, in, w);
+          w.finish(d_rr, d_rb);
         }
         if (export_fields) {
           at(PL(aux, A_NX), node) = h_nx;
@@ -1041,6 +1200,7 @@ __device__ __forceinline__ void block_sum_f64(double (&v)[NV], double *part) {
 __global__ __launch_bounds__(kBlock) void k_reduce1(const BoxDev *__restrict__ boxes,
                                                     const int32_t *__restrict__ blk_box,
                                                     const float *__restrict__ aux, int64_t plane,
+                                                    const double *__restrict__ rho64,
                                                     const double *__restrict__ centre,
                                                     double *__restrict__ part) {
   const int b = blk_box[blockIdx.x];
@@ -1056,7 +1216,10 @@ __global__ __launch_bounds__(kBlock) void k_reduce1(const BoxDev *__restrict__ b
     if (!is_solid(B, y, z)) {
       const uint32_t node = (uint32_t)(B.base + local);
       const NodeIn in = load_node_in(aux, plane, node);
-      const double rr = in.rr, rb = in.rb, rho = rr + rb;
+      // colour densities in FP64 where the storage carries them
+      const double rr = rho64 ? at(rho64, node) : (double)in.rr;
+      const double rb = rho64 ? at(rho64 + plane, node) : (double)in.rb;
+      const double rho = rr + rb;
       const double jx = (double)in.jx + 0.5 * in.Fx, jy = (double)in.jy + 0.5 * in.Fy,
                    jz = (double)in.jz + 0.5 * in.Fz;
       const float sr = in.rr * B.ir0r, sb = in.rb * B.ir0b;

@@ -52,6 +52,20 @@ def test_parameter_validation(field, value, code):
     assert ei.value.code == code
 
 
+def test_storage_buffer_sizes():
+    b = WL.two_phase_box((10, 7, 5), 10.0, 1.0, 0.8, 0.01, 0.7)
+    pb = [pkg.box_params_of(b)]
+    pop32, aux32, total = pkg.query_sizes(pb, pkg.FP32)
+    pop16, aux16, _ = pkg.query_sizes(pb, pkg.FP16_SHIFT)
+    popx, auxx, _ = pkg.query_sizes(pb, pkg.FP32_EXACT)
+    align = lambda v: (v + 255) // 256 * 256
+    assert total == 384
+    assert pop32 == 54 * total * 4 and aux32 == 21 * total * 4
+    assert pop16 == align(52 * total * 2) + 2 * total * 8
+    assert popx == align(52 * total * 4) + 2 * total * 8
+    assert aux16 == align(21 * total * 4) + 2 * total * 8 == auxx
+
+
 def test_phase_validation_and_storage():
     b = WL.two_phase_box((8, 8, 8), 10.0, 1.0, 0.8, 0.01, 0.7)
     p = pkg.box_params_of(b)
