@@ -1,6 +1,6 @@
 """Benchmark of the colour-gradient LBM hot path on one MI355X.
 
-Workload (default): the translating-droplet case -- 256^3 periodic box, red
+Default workload: the translating-droplet case -- 256^3 periodic box, red
 droplet of radius 32 moving with u = 0.05 along x in a blue carrier, density
 ratio 10, equal dynamic viscosities, shear rate 1.6 and bulk rate 1.0,
 sigma = 0.005, beta = 0.7, +-1e-6 counter noise on the populations, FP32
@@ -9,8 +9,11 @@ storage and arithmetic.  A step is one full time update of every node
 
 Prints ONE JSON line: MLUPS of the timed steps, the roofline of the dominant
 kernel (algorithmic bytes per launch / average launch time from HIP events
-recorded on the launch stream during the timed region), and the FP64 CPU
-oracle timed on a bounded sample of the same workload.
+recorded on the launch stream during the timed region) and the FP64 CPU
+oracle timed on a bounded sample of the same workload.  `forms` reports, on
+the same workload and step counts, the FP16/BF16-shifted and mass-exact FP32
+storage (with their difference to the FP32 run as a proxy error) and the
+96-box batched workload.
 """
 import argparse
 import json
@@ -24,29 +27,30 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per node of each kernel (FP32): what it must read and write
-KERNEL_BYTES = {
-    "pull": 54 * 4 + 11 * 4,          # 54 populations in, 11 local moments out
-    "interface": (2 + 3) * 4 + 9 * 4,  # rho_r, rho_b, j in; n, F, Q out
-    "collide": 20 * 4 + 54 * 4,        # moments + interface fields in, 54 populations out
-    "fused": 11 * 4 + 54 * 4,          # local moments in, 54 populations out
-}
-STEP_BYTES = 2 * 54 * 4               # whole step: every population read once, written once
+STORAGES = {"fp32": 0, "fp16": 1, "bf16": 2, "fp32x": 3}
+DTYPE = {"fp32": "f32", "fp16": "f16 storage, f32 arithmetic", "bf16": "bf16 storage, f32 arithmetic",
+         "fp32x": "f32"}
 
 
-def parse():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--size", type=int, default=256, help="box edge (default 256)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--variant", type=int, default=-1,
-                    help="fused launch geometry (default: autotune)")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="only run a plain 2 GiB device copy (counter calibration)")
-    return ap.parse_args()
+def kernel_bytes(storage: str):
+    """Algorithmic bytes per node of each kernel: what it must read and write."""
+    if storage == "fp32":
+        pops, aux_rho = 54 * 4, 0
+    else:
+        s = 4 if storage == "fp32x" else 2
+        pops, aux_rho = 52 * s + 2 * 8, 2 * 8      # moving populations + FP64 rest
+    return {
+        "pull": pops + 11 * 4 + aux_rho,           # populations in, 11 local moments out
+        "interface": (2 + 3) * 4 + 9 * 4,          # rho_r, rho_b, j in; n, F, Q out
+        "collide": 20 * 4 + aux_rho + pops,        # moments + interface fields in, populations out
+        "fused": 11 * 4 + aux_rho + pops,          # local moments in, populations out
+    }
+
+
+def step_bytes(storage: str) -> int:
+    """The whole step's algorithmic bytes: every population read and written
+    once, 2 * 54 * (bytes per stored population)."""
+    return 2 * 54 * (2 if storage in ("fp16", "bf16") else 4)
 
 
 COUNTERS = os.path.join(ROOT, "profiles", "k_fused_translating_droplet_256_hbm_counters.md")
@@ -75,6 +79,24 @@ def measured_traffic(kernel: str):
         if len(cells) == 6 and cells[0] == kernel:
             return float(cells[4])
     return None
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--size", type=int, default=256, help="box edge (default 256)")
+    ap.add_argument("--storage", default="fp32", choices=sorted(STORAGES))
+    ap.add_argument("--forms", default="fp16,bf16,fp32x,batched",
+                    help="extra forms on the same workload ('' for none)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--variant", type=int, default=-1,
+                    help="fused launch geometry (default: autotune)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 2 GiB device copy (counter calibration)")
+    return ap.parse_args()
 
 
 def copy_probe():
@@ -120,6 +142,67 @@ def cpu_baseline(w, seconds):
                       "definitions), %.1f s" % (steps, box.nx, box.ny, box.nz, el)}
 
 
+def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=False):
+    """Initialise, autotune, time `steps` steps; return throughput, per-kernel
+    event timings and (optionally) the final fields of box 0."""
+    import torch
+    import paper_2309_07801_amd as pkg
+    sim = pkg.Simulation([pkg.box_params_of(w.box) for w in workloads],
+                         [w.rho_r for w in workloads], [w.rho_b for w in workloads],
+                         [w.u for w in workloads], seed=workloads[0].seed,
+                         noise=workloads[0].noise, storage=STORAGES[storage])
+    fluid = sum(w.box.fluid_nodes() for w in workloads)
+    d0 = sim.reduce()
+    sim.step(2)
+    if variant >= 0:
+        sim.set_variant(variant)
+        tune_ms = []
+    else:
+        tune_ms = sim.autotune(reps=5)
+    var = pkg.variant_info(sim.variant())
+    sim.step(max(warmup - 2, 0))
+    torch.cuda.synchronize()
+    sim.profile_begin(4 * steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = sim.profile_end()
+    dt = t1 - t0
+    d1 = sim.reduce()
+    kb = kernel_bytes(storage)
+    kern = {}
+    for k, (ms, cnt) in prof.items():
+        if cnt:
+            avg = ms / cnt / 1e3
+            kern[k] = {"avg_ms": avg * 1e3, "gbs": kb[k] * fluid / avg / 1e9, "share": ms / 1e3 / dt}
+    m0 = d0[:, :2].sum(axis=0)
+    m1 = d1[:, :2].sum(axis=0)
+    out = {"mlups": fluid * steps / dt / 1e6, "ms_per_step": dt / steps * 1e3, "dt": dt,
+           "fluid": fluid, "kernels": kern, "variant": var, "autotune_ms": tune_ms,
+           "mass_drift": [float((m1[0] - m0[0]) / m0[0]), float((m1[1] - m0[1]) / m0[1])],
+           "nonfinite": int(d1[:, 12].sum()), "steps": steps}
+    if keep_fields:
+        out["fields"] = {k: v.cpu().numpy() for k, v in
+                         sim.moments(0, ("rho_r", "rho_b", "phi", "ux", "uy", "uz")).items()}
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
+def proxy_errors(g, ref, u_ref):
+    """Difference of a run to the FP32 run after the same steps (the survey's
+    proxy for full-size runs the oracle cannot afford)."""
+    rho_g, rho_f = g["rho_r"] + g["rho_b"], ref["rho_r"] + ref["rho_b"]
+    du = np.sqrt((g["ux"] - ref["ux"]) ** 2 + (g["uy"] - ref["uy"]) ** 2 + (g["uz"] - ref["uz"]) ** 2)
+    return {"e_rho": float((np.abs(rho_g - rho_f) / rho_f).max()),
+            "e_u": float(du.max() / u_ref), "e_phi": float(np.abs(g["phi"] - ref["phi"]).max()),
+            "e_rho_l2": float(np.sqrt((((rho_g - rho_f) / rho_f) ** 2).mean())),
+            "e_u_l2": float(np.sqrt((du ** 2).mean()) / u_ref)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -127,7 +210,6 @@ def main():
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
-    import paper_2309_07801_amd as pkg
     import workloads as WL
 
     if args.copy_probe:
@@ -138,74 +220,77 @@ def main():
         sys.exit(1)
     n = args.size
     w = WL.translating_droplet(n=n, R=32.0 * n / 256.0)
-    box = w.box
-    sim = pkg.Simulation([pkg.box_params_of(box)], [w.rho_r], [w.rho_b], [w.u], seed=w.seed,
-                         noise=w.noise)
-    fluid = box.fluid_nodes()
-    d0 = sim.reduce()[0]
-    sim.step(2)
-    if args.variant >= 0:
-        sim.set_variant(args.variant)
-        tune_ms = []
-    else:
-        tune_ms = sim.autotune(reps=5)
-    variant = pkg.variant_info(sim.variant())
-    sim.step(args.warmup)
-    torch.cuda.synchronize()
-
-    sim.profile_begin(4 * args.steps)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(args.steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = sim.profile_end()
-    dt = t1 - t0
-    mlups = fluid * args.steps / dt / 1e6
-
-    d1 = sim.reduce()[0]
-    kern = {}
-    for k, (ms, cnt) in prof.items():
-        if cnt:
-            avg = ms / cnt / 1e3
-            kern[k] = {"avg_ms": avg * 1e3, "gbs": KERNEL_BYTES[k] * fluid / avg / 1e9,
-                       "share": ms / 1e3 / dt}
+    forms_req = [f for f in args.forms.split(",") if f]
+    main_r = run_form([w], args.storage, args.steps, args.warmup, args.variant,
+                      keep_fields=any(f in STORAGES for f in forms_req))
+    fluid = main_r["fluid"]
+    kern = main_r["kernels"]
     dom = max(kern, key=lambda k: kern[k]["share"])
-    achieved = kern[dom]["gbs"]
+    var = main_r["variant"]
     if dom == "fused":
-        kname = "k_fused<%d, %d, %d, %d, false, f32>" % (variant["tx"], variant["ty"], variant["zc"],
-                                                        variant["min_waves"])
+        kname = "k_fused<%d, %d, %d, %d, false, f32>" % (var["tx"], var["ty"], var["zc"],
+                                                        var["min_waves"])
     else:
         kname = "k_%s<f32>" % dom
-    traffic = measured_traffic(kname) if n == 256 else None
+    traffic = measured_traffic(kname) if (n == 256 and args.storage == "fp32") else None
+    kb = kernel_bytes(args.storage)
+    sb = step_bytes(args.storage)
     line = {
         "metric": "MLUPS and % HBM roofline, FP32 vs FP16-storage vs batched, at fixed error",
-        "value": round(mlups, 1),
+        "value": round(main_r["mlups"], 1),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "ms_per_step": round(main_r["ms_per_step"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": DTYPE[args.storage],
         "data": "synthetic",
         "config": {"workload": "translating droplet %d^3 periodic, density ratio 10, R=%g, "
-                               "u=0.05, FP32 storage" % (n, w.radii[0]),
-                   "nodes": fluid, "storage": "fp32"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                               "u=0.05, %s storage" % (n, w.radii[0], args.storage),
+                   "nodes": fluid, "storage": args.storage},
+        "roofline": {"bound": "hbm", "achieved": round(kern[dom]["gbs"], 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(kern[dom]["gbs"] / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "traffic_unit": "bytes per launch",
-                     "algorithmic_bytes": KERNEL_BYTES[dom] * fluid, "kernel": kname,
-                     "bytes_per_node": KERNEL_BYTES[dom]},
-        "step_roofline_frac": round(mlups * 1e6 * STEP_BYTES / (HBM_PEAK_GBS * 1e9), 4),
+                     "algorithmic_bytes": kb[dom] * fluid, "kernel": kname},
+        "step_roofline_frac": round(main_r["mlups"] * 1e6 * sb / (HBM_PEAK_GBS * 1e9), 4),
+        "step_bytes_per_node": sb,
         "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in kern.items()},
-        "fused_variant": variant,
-        "autotune_ms": [round(m, 4) for m in tune_ms],
-        "mass_drift": [float((d1[0] - d0[0]) / d0[0]), float((d1[1] - d0[1]) / d0[1])],
-        "nonfinite": int(d1[12]),
+        "fused_variant": var,
+        "autotune_ms": [round(m, 4) for m in main_r["autotune_ms"]],
+        "mass_drift": main_r["mass_drift"],
+        "nonfinite": main_r["nonfinite"],
     }
+    forms = {}
+    u_ref = 0.05
+    for f in forms_req:
+        if f in STORAGES:
+            r = run_form([w], f, args.steps, args.warmup, args.variant, keep_fields=True)
+            sbf = step_bytes(f)
+            forms[f] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+                        "step_roofline_frac": round(r["mlups"] * 1e6 * sbf / (HBM_PEAK_GBS * 1e9), 4),
+                        "step_bytes_per_node": sbf,
+                        "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()}
+                                    for k, v in r["kernels"].items()},
+                        "mass_drift": r["mass_drift"], "nonfinite": r["nonfinite"],
+                        "vs_fp32_after_same_steps": proxy_errors(r["fields"], main_r["fields"], u_ref)}
+        elif f == "batched":
+            boxes = WL.batched_boxes()
+            steps_b = min(args.steps, 1000)
+            r = run_form(boxes, "fp32", steps_b, args.warmup, args.variant)
+            forms["batched"] = {"workload": "96 periodic boxes, edges U{24..128}, density ratio "
+                                            "in {1,10,100}, FP32", "nodes": r["fluid"],
+                                "steps": steps_b, "mlups": round(r["mlups"], 1),
+                                "ms_per_step": round(r["ms_per_step"], 4),
+                                "step_roofline_frac": round(r["mlups"] * 1e6 * 432 / (HBM_PEAK_GBS * 1e9), 4),
+                                "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()}
+                                            for k, v in r["kernels"].items()},
+                                "mass_drift": r["mass_drift"], "nonfinite": r["nonfinite"]}
+    if forms:
+        line["forms"] = forms
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(line), flush=True)
