@@ -71,6 +71,47 @@ __device__ __forceinline__ const T &at(const T *base, uint32_t idx) {
                                       (uint32_t)(idx * (uint32_t)sizeof(T)));
 }
 
+// The value unchanged, but opaque to the optimizer: address arithmetic
+// derived from it inside the z-march is not hoisted out of the loop, where
+// the many plane base pointers would not fit in scalar registers.
+__device__ __forceinline__ int64_t opaque_i64(int64_t v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
+
+// Hardware reciprocal and reciprocal square root (about 1 ulp), in place of
+// the correctly rounded division and square root sequences.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// Scalar buffer descriptor of plane p of an SoA array whose planes are
+// plane_bytes apart.  A plane spans less than 4 GiB (at most 2^30 nodes of at
+// most 4 bytes), so a lane addresses it with one 32-bit byte offset and no
+// vector address arithmetic.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *base, int64_t plane_bytes,
+                                                             int p) {
+  return __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<char *>(static_cast<const char *>(base)) + p * plane_bytes, 0, -1, 0x00020000);
+}
+// Population stores carry the non-temporal hint: the stored state is read
+// only by the next step's pull, and keeping it out of the caches measured
+// faster for both kernels of the step than plain stores.
+constexpr int kNonTemporal = 2;  // cache policy bit of a streaming access
+__device__ __forceinline__ float buf_ld_f32(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ void buf_st(float v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, 0,
+                                        kNonTemporal);
+}
+__device__ __forceinline__ void buf_st(uint16_t v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+  __builtin_amdgcn_raw_buffer_store_b16(v, r, (int)off, 0, kNonTemporal);
+}
+// Float plane p of an aux-like array at node.
+__device__ __forceinline__ float ldpl(const float *base, int64_t plane, int p, uint32_t node) {
+  return buf_ld_f32(plane_rsrc(base, plane * 4, p), node * 4u);
+}
+
 // Workgroups are dispatched to the 8 XCDs in round-robin order.  Remap them
 // so that each XCD, with its own L2, works through a contiguous range of
 // logical blocks: neighbouring rows and columns then share cached halo lines.
@@ -382,6 +423,8 @@ __global__ __launch_bounds__(kBlock) void k_interface(const BoxDev *__restrict__
     const float rr = at(PL(aux, A_RR), node) * B.ir0r;
     const float rb = at(PL(aux, A_RB), node) * B.ir0b;
     const float den = rr + rb;
+    // correctly rounded: phi is exactly +-1 in a pure phase, so the bulk
+    // gradient is exactly zero
     s_phi[i] = den > 0.f ? (rr - rb) / den : 0.f;
   }
   __syncthreads();
@@ -396,14 +439,13 @@ __global__ __launch_bounds__(kBlock) void k_interface(const BoxDev *__restrict__
       lds_gradient<G::R3X, G::R3X * G::R3Y>(
           s_phi, c3, [&](int dy, int dz) { return (bool)(s_sy[ly + 1 + dy] | s_sz[lz + 1 + dz]); },
           gx, gy, gz);
-      mag = sqrtf(gx * gx + gy * gy + gz * gz);
-      if (mag > 1e-12f) {
-        const float inv = 1.0f / mag;
+      const float g2 = gx * gx + gy * gy + gz * gz;
+      if (g2 > 1e-24f) {  // |grad phi| > 1e-12
+        const float inv = rsq(g2);
+        mag = g2 * inv;
         nxv = gx * inv;
         nyv = gy * inv;
         nzv = gz * inv;
-      } else {
-        mag = 0.f;
       }
     }
     s_n[0][i] = nxv;
@@ -444,7 +486,7 @@ __global__ __launch_bounds__(kBlock) void k_interface(const BoxDev *__restrict__
       const float rr = at(PL(aux, A_RR), node);
       const float rb = at(PL(aux, A_RB), node);
       const float rho = rr + rb;
-      const float irho = 1.0f / rho;
+      const float irho = rcp(rho);
       const float ux = fmaf(0.5f, Fx, at(PL(aux, A_JX), node)) * irho;
       const float uy = fmaf(0.5f, Fy, at(PL(aux, A_JY), node)) * irho;
       const float uz = fmaf(0.5f, Fz, at(PL(aux, A_JZ), node)) * irho;
@@ -511,16 +553,16 @@ struct NodeIn {
 template <class Emit>
 __device__ __forceinline__ void collide_node(const BoxDev &B, const NodeIn &in, Emit &&emit) {
   const float rho = in.rr + in.rb;
-  const float irho = 1.0f / rho;
+  const float irho = rcp(rho);
   const float ux = fmaf(0.5f, in.Fx, in.jx) * irho;  // Eq. (11)
   const float uy = fmaf(0.5f, in.Fy, in.jy) * irho;
   const float uz = fmaf(0.5f, in.Fz, in.jz) * irho;
   const float p = in.rr * B.cs2r + in.rb * B.cs2b;   // Eq. (12)
   // Eqs. (14), (21), (22): omega_1 from the interpolated viscosity
   const float sr = in.rr * B.ir0r, sb = in.rb * B.ir0b;
-  const float phi = (sr - sb) / (sr + sb);
+  const float phi = (sr - sb) * rcp(sr + sb);
   const float nu = 0.5f * ((1.0f + phi) * B.nu_r + (1.0f - phi) * B.nu_b);
-  const float w1 = 1.0f / (rho * nu / p + 0.5f);
+  const float w1 = p * rcp(fmaf(rho, nu, 0.5f * p));  // 1 / (rho nu / p + 1/2)
   const float w2 = B.omega2;
   // second-order central moments from raw ones (Eqs. 23-24)
   const float kxx = in.pxx - 2.0f * ux * in.jx + rho * ux * ux;
@@ -617,8 +659,10 @@ struct PopWriter {
     if (S::kExact && i == 0) return;
     const float shr = pop_shift<S>(B, 0, i), shb = pop_shift<S>(B, 1, i);
     const typename S::T er = S::enc(fr - shr), eb = S::enc(fb - shb);
-    st<S>(&at(dst.mvp(0, i), node), er);
-    st<S>(&at(dst.mvp(1, i), node), eb);
+    constexpr uint32_t sz = sizeof(typename S::T);
+    const int64_t pb = dst.plane * (int64_t)sz;
+    buf_st(er, plane_rsrc(dst.mv, pb, S::kExact ? i - 1 : i), node * sz);
+    buf_st(eb, plane_rsrc(dst.mv, pb, S::kExact ? 25 + i : 27 + i), node * sz);
     if (S::kExact) {
       sr += (double)(S::dec(er) + shr);
       sb += (double)(S::dec(eb) + shb);
@@ -740,7 +784,7 @@ template <int TX, int TY, int ZC, int MINW, bool WALLS, class S>
 __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict__ boxes,
                                                   const int32_t *__restrict__ col_box,
                                                   float *__restrict__ aux,
-                                                  void *__restrict__ dst_, int64_t plane,
+                                                  void *__restrict__ dst_, int64_t plane_arg,
                                                   int write_pops, int export_fields) {
   using G = FusedGeom<TX, TY>;
   __shared__ float s_phi[3][G::R3];
@@ -826,6 +870,7 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
   __syncthreads();
 
   for (int s = z0 - 3; s < z1 + 3; ++s) {
+    const int64_t plane = opaque_i64(plane_arg);
     // ---- prefetch the global inputs of stages C and D of this iteration, so
     // that their latency overlaps the stencil work of stages A-C ----
     float pc_[C_PER][5];
@@ -835,11 +880,11 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
       for (int kk = 0; kk < C_PER; ++kk) {
         const uint32_t node = zoff + c_off[kk];
         const bool ok = tid + kk * G::NT < G::R1;
-        pc_[kk][0] = ok ? at(PL(aux, A_RR), node) : 1.f;
-        pc_[kk][1] = ok ? at(PL(aux, A_RB), node) : 0.f;
-        pc_[kk][2] = ok ? at(PL(aux, A_JX), node) : 0.f;
-        pc_[kk][3] = ok ? at(PL(aux, A_JY), node) : 0.f;
-        pc_[kk][4] = ok ? at(PL(aux, A_JZ), node) : 0.f;
+        pc_[kk][0] = ok ? ldpl(aux, plane, A_RR, node) : 1.f;
+        pc_[kk][1] = ok ? ldpl(aux, plane, A_RB, node) : 0.f;
+        pc_[kk][2] = ok ? ldpl(aux, plane, A_JX, node) : 0.f;
+        pc_[kk][3] = ok ? ldpl(aux, plane, A_JY, node) : 0.f;
+        pc_[kk][4] = ok ? ldpl(aux, plane, A_JZ, node) : 0.f;
       }
     }
     NodeIn din;
@@ -853,17 +898,17 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
         d_rr = at(r64, node);
         d_rb = at(r64 + plane, node);
       }
-      din.rr = at(PL(aux, A_RR), node);
-      din.rb = at(PL(aux, A_RB), node);
-      din.jx = at(PL(aux, A_JX), node);
-      din.jy = at(PL(aux, A_JY), node);
-      din.jz = at(PL(aux, A_JZ), node);
-      din.pxx = at(PL(aux, A_PXX), node);
-      din.pyy = at(PL(aux, A_PYY), node);
-      din.pzz = at(PL(aux, A_PZZ), node);
-      din.pxy = at(PL(aux, A_PXY), node);
-      din.pxz = at(PL(aux, A_PXZ), node);
-      din.pyz = at(PL(aux, A_PYZ), node);
+      din.rr = ldpl(aux, plane, A_RR, node);
+      din.rb = ldpl(aux, plane, A_RB, node);
+      din.jx = ldpl(aux, plane, A_JX, node);
+      din.jy = ldpl(aux, plane, A_JY, node);
+      din.jz = ldpl(aux, plane, A_JZ, node);
+      din.pxx = ldpl(aux, plane, A_PXX, node);
+      din.pyy = ldpl(aux, plane, A_PYY, node);
+      din.pzz = ldpl(aux, plane, A_PZZ, node);
+      din.pxy = ldpl(aux, plane, A_PXY, node);
+      din.pxz = ldpl(aux, plane, A_PXZ, node);
+      din.pyz = ldpl(aux, plane, A_PYZ, node);
     }
     // ---- A: phase field of slab s (Eq. 14) ----
     {
@@ -874,8 +919,8 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
         const int i = tid + k * G::NT;
         if (i < G::R3) {
           const uint32_t node = zoff + (uint32_t)a_off[k];
-          const float rr = at(PL(aux, A_RR), node) * B.ir0r;
-          const float rb = at(PL(aux, A_RB), node) * B.ir0b;
+          const float rr = ldpl(aux, plane, A_RR, node) * B.ir0r;
+          const float rb = ldpl(aux, plane, A_RB, node) * B.ir0b;
           const float den = rr + rb;
           ph[i] = den > 0.f ? (rr - rb) / den : 0.f;
         }
@@ -919,14 +964,13 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
               gy = fmaf(w, v[b2][2][a2] - v[b2][0][a2], gy);
               gz = fmaf(w, v[2][b2][a2] - v[0][b2][a2], gz);
             }
-          mag = sqrtf(gx * gx + gy * gy + gz * gz);
-          if (mag > 1e-12f) {
-            const float inv = 1.0f / mag;
+          const float g2 = gx * gx + gy * gy + gz * gz;
+          if (g2 > 1e-24f) {  // |grad phi| > 1e-12
+            const float inv = rsq(g2);
+            mag = g2 * inv;
             nxv = gx * inv;
             nyv = gy * inv;
             nzv = gz * inv;
-          } else {
-            mag = 0.f;
           }
         }
         nn[0][i] = nxv;
@@ -1001,7 +1045,7 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
           const float rr = pc_[kk][0];
           const float rb = pc_[kk][1];
           const float rho = rr + rb;
-          const float irho = 1.0f / rho;
+          const float irho = rcp(rho);
           const float ux = fmaf(0.5f, Fx, pc_[kk][2]) * irho;
           const float uy = fmaf(0.5f, Fy, pc_[kk][3]) * irho;
           const float uz = fmaf(0.5f, Fz, pc_[kk][4]) * irho;
