@@ -46,16 +46,19 @@ constexpr int kTX = 8, kTY = 8, kTZ = 8;   // interface tile (three-kernel sched
 // minimum waves per SIMD requested from the register allocator.  Every
 // variant performs the same arithmetic per node (results are bitwise equal);
 // cglbm_autotune picks the fastest for the boxes at hand.
-using FusedFn = void (*)(const BoxDev *, const int32_t *, float *, void *, int64_t, int, int);
+using FusedFn = void (*)(const BoxDev *, const int32_t *, float *, void *, int64_t);
 struct FusedVariant {
   int tx, ty, zc, minw;
-  FusedFn fn[4][2];  // [storage][any box with solid layers]
+  FusedFn fn[4][2];  // time step: [storage][any box with solid layers]
+  FusedFn fx[2];     // field export (no population store): [solid layers]
 };
-#define FV_S(TX, TY, ZC, MW, S) {k_fused<TX, TY, ZC, MW, false, S>, k_fused<TX, TY, ZC, MW, true, S>}
+#define FV_S(TX, TY, ZC, MW, S) \
+  {k_fused<TX, TY, ZC, MW, false, S, false>, k_fused<TX, TY, ZC, MW, true, S, false>}
 #define FV(TX, TY, ZC, MW)                                                                    \
   {TX, TY, ZC, MW,                                                                           \
    {FV_S(TX, TY, ZC, MW, StoreF32), FV_S(TX, TY, ZC, MW, StoreF16), FV_S(TX, TY, ZC, MW, StoreBF16), \
-    FV_S(TX, TY, ZC, MW, StoreF32X)}}
+    FV_S(TX, TY, ZC, MW, StoreF32X)},                                                        \
+   {k_fused<TX, TY, ZC, MW, false, StoreF32, true>, k_fused<TX, TY, ZC, MW, true, StoreF32, true>}}
 const FusedVariant kFusedVariants[] = {
     FV(32, 8, 32, 4),  FV(32, 8, 64, 4),  FV(32, 8, 16, 4), FV(32, 8, 32, 1),
     FV(32, 16, 32, 4), FV(32, 16, 64, 4), FV(64, 4, 32, 4), FV(32, 4, 32, 4),
@@ -65,6 +68,9 @@ const FusedVariant kFusedVariants[] = {
 #undef FV_S
 constexpr int kNumFused = (int)(sizeof(kFusedVariants) / sizeof(kFusedVariants[0]));
 constexpr int64_t kAlign = 64;             // node alignment of each box's base
+// Limit of all boxes together: every plane of 8-byte values stays below
+// 4 GiB, so that kernels address a plane with 32-bit byte offsets.
+constexpr int64_t kMaxNodes = (1ll << 29) - (1ll << 20);
 constexpr double kXi = 9.0 / 19.0;
 
 enum { KIND_PULL = 0, KIND_IFACE = 1, KIND_COLLIDE = 2, KIND_FUSED = 3, KIND_N = 4 };
@@ -110,12 +116,12 @@ int validate(int32_t n_boxes, const cglbm_box_params *boxes, int32_t storage) {
     if (P.nx < 1 || P.ny < 1 || P.nz < 1)
       return fail(CGLBM_EINVAL, "box %d: extents must be >= 1", b);
     total += align_up((int64_t)P.nx * P.ny * P.nz, kAlign);
-    if (total >= (1ll << 30))
-      return fail(CGLBM_EINVAL, "all boxes together exceed 2^30 nodes");
+    if (total > kMaxNodes)
+      return fail(CGLBM_EINVAL, "all boxes together exceed %lld nodes", (long long)kMaxNodes);
     if (P.nx < 1 || P.ny < 1 || P.nz < 1)
       return fail(CGLBM_EINVAL, "box %d: extents must be >= 1", b);
-    if ((int64_t)P.nx * P.ny * P.nz >= (1ll << 30))
-      return fail(CGLBM_EINVAL, "box %d: more than 2^30 nodes", b);
+    if ((int64_t)P.nx * P.ny * P.nz > kMaxNodes)
+      return fail(CGLBM_EINVAL, "box %d: more than %lld nodes", b, (long long)kMaxNodes);
     if (P.walls & ~3u) return fail(CGLBM_EINVAL, "box %d: unknown wall bits 0x%x", b, P.walls);
     if ((P.walls & 1u) && P.ny < 3) return fail(CGLBM_EINVAL, "box %d: y walls need ny >= 3", b);
     if ((P.walls & 2u) && P.nz < 3) return fail(CGLBM_EINVAL, "box %d: z walls need nz >= 3", b);
@@ -284,17 +290,19 @@ int launch_iface(cglbm_handle *h, hipStream_t s, int write_kappa) {
   return CGLBM_OK;
 }
 
-int launch_fused(cglbm_handle *h, hipStream_t s, int write_pops, int export_fields) {
+// export == 0: interface stencils + collision of a time step; export != 0:
+// the interface fields n, F, Q, kappa into aux, populations untouched.
+int launch_fused(cglbm_handle *h, hipStream_t s, int export_fields) {
   const FusedVariant &F = kFusedVariants[h->variant];
   const BoxDev *boxes = h->d_boxes;
   const int32_t *cols = h->d_col_box;
   float *aux = h->aux;
   void *dst = h->pop[1 - h->cur];
   int64_t plane = h->L.total;
-  void *args[] = {(void *)&boxes, (void *)&cols, (void *)&aux, (void *)&dst,
-                  (void *)&plane, (void *)&write_pops, (void *)&export_fields};
-  HIP_TRY(hipLaunchKernel((const void *)F.fn[h->storage][h->L.walls ? 1 : 0], dim3(h->L.ncol),
-                          dim3(F.tx * F.ty), args, 0, s));
+  void *args[] = {(void *)&boxes, (void *)&cols, (void *)&aux, (void *)&dst, (void *)&plane};
+  const int w = h->L.walls ? 1 : 0;
+  const FusedFn fn = export_fields ? F.fx[w] : F.fn[h->storage][w];
+  HIP_TRY(hipLaunchKernel((const void *)fn, dim3(h->L.ncol), dim3(F.tx * F.ty), args, 0, s));
   return CGLBM_OK;
 }
 
@@ -347,7 +355,7 @@ int compute_fields(cglbm_handle *h, hipStream_t s, int write_kappa) {
   int rc = launch_pull(h, s, 0);
   if (rc) return rc;
   if (h->schedule == 0)
-    rc = launch_fused(h, s, 0, 1);
+    rc = launch_fused(h, s, 1);
   else
     rc = launch_iface(h, s, write_kappa);
   if (rc) return rc;
@@ -456,7 +464,7 @@ int cglbm_step(cglbm_handle *h, int32_t n_steps, void *stream) {
   for (int32_t k = 0; k < n_steps; ++k) {
     int rc = timed(h, s, KIND_PULL, [&] { return launch_pull(h, s, 1); });
     if (h->schedule == 0) {
-      if (!rc) rc = timed(h, s, KIND_FUSED, [&] { return launch_fused(h, s, 1, 0); });
+      if (!rc) rc = timed(h, s, KIND_FUSED, [&] { return launch_fused(h, s, 0); });
     } else {
       if (!rc) rc = timed(h, s, KIND_IFACE, [&] { return launch_iface(h, s, 0); });
       if (!rc) rc = timed(h, s, KIND_COLLIDE, [&] { return launch_collide(h, s); });
@@ -579,9 +587,9 @@ int cglbm_autotune(cglbm_handle *h, int32_t reps, double *ms_per_variant, void *
   double best_ms = 1e300;
   for (int v = 0; v < kNumFused; ++v) {
     if ((rc = select_variant(h, v, s))) break;
-    if ((rc = launch_fused(h, s, 1, 0))) break;
+    if ((rc = launch_fused(h, s, 0))) break;
     (void)hipEventRecord(e0, s);
-    for (int r = 0; r < reps && !rc; ++r) rc = launch_fused(h, s, 1, 0);
+    for (int r = 0; r < reps && !rc; ++r) rc = launch_fused(h, s, 0);
     (void)hipEventRecord(e1, s);
     if (rc || (rc = check_launch())) break;
     if (hipEventSynchronize(e1) != hipSuccess) {

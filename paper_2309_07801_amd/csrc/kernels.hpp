@@ -85,20 +85,28 @@ __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x);
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
 // Scalar buffer descriptor of plane p of an SoA array whose planes are
-// plane_bytes apart.  A plane spans less than 4 GiB (at most 2^30 nodes of at
-// most 4 bytes), so a lane addresses it with one 32-bit byte offset and no
-// vector address arithmetic.
+// plane_bytes apart.  The host keeps every plane below 4 GiB, so a lane
+// addresses it with one 32-bit byte offset and no vector address arithmetic.
+// The descriptor's extent is the plane itself: an access at kDrop lies
+// beyond it, a store there is discarded and a load returns zero, which lets
+// lanes without work issue the same memory instructions as the others.
+constexpr uint32_t kDrop = 0xFFFFFFF0u;
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *base, int64_t plane_bytes,
                                                              int p) {
   return __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<char *>(static_cast<const char *>(base)) + p * plane_bytes, 0, -1, 0x00020000);
+      const_cast<char *>(static_cast<const char *>(base)) + p * plane_bytes, 0,
+      (int)(uint32_t)plane_bytes, 0x00020000);
 }
 // Population stores carry the non-temporal hint: the stored state is read
 // only by the next step's pull, and keeping it out of the caches measured
 // faster for both kernels of the step than plain stores.
 constexpr int kNonTemporal = 2;  // cache policy bit of a streaming access
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ float buf_ld_f32(__amdgpu_buffer_rsrc_t r, uint32_t off) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ double buf_ld_f64(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
 }
 __device__ __forceinline__ void buf_st(float v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, 0,
@@ -107,9 +115,19 @@ __device__ __forceinline__ void buf_st(float v, __amdgpu_buffer_rsrc_t r, uint32
 __device__ __forceinline__ void buf_st(uint16_t v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
   __builtin_amdgcn_raw_buffer_store_b16(v, r, (int)off, 0, kNonTemporal);
 }
+__device__ __forceinline__ void buf_st(double v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)off, 0,
+                                        kNonTemporal);
+}
 // Float plane p of an aux-like array at node.
 __device__ __forceinline__ float ldpl(const float *base, int64_t plane, int p, uint32_t node) {
   return buf_ld_f32(plane_rsrc(base, plane * 4, p), node * 4u);
+}
+// Byte offset of node in a plane of T, or kDrop for a lane that must not
+// access it.
+template <class T>
+__device__ __forceinline__ uint32_t boff(bool live, uint32_t node) {
+  return live ? node * (uint32_t)sizeof(T) : kDrop;
 }
 
 // Workgroups are dispatched to the 8 XCDs in round-robin order.  Remap them
@@ -652,17 +670,20 @@ template <class S>
 struct PopWriter {
   const Pops<S> &dst;
   const BoxDev &B;
+  bool live;
   uint32_t node;
   double sr = 0.0, sb = 0.0;
-  __device__ PopWriter(const Pops<S> &d, const BoxDev &b, uint32_t n) : dst(d), B(b), node(n) {}
+  __device__ PopWriter(const Pops<S> &d, const BoxDev &b, uint32_t n, bool l = true)
+      : dst(d), B(b), live(l), node(n) {}
   __device__ __forceinline__ void operator()(int i, float fr, float fb) {
     if (S::kExact && i == 0) return;
     const float shr = pop_shift<S>(B, 0, i), shb = pop_shift<S>(B, 1, i);
     const typename S::T er = S::enc(fr - shr), eb = S::enc(fb - shb);
-    constexpr uint32_t sz = sizeof(typename S::T);
-    const int64_t pb = dst.plane * (int64_t)sz;
-    buf_st(er, plane_rsrc(dst.mv, pb, S::kExact ? i - 1 : i), node * sz);
-    buf_st(eb, plane_rsrc(dst.mv, pb, S::kExact ? 25 + i : 27 + i), node * sz);
+    using T = typename S::T;
+    const int64_t pb = dst.plane * (int64_t)sizeof(T);
+    const uint32_t off = boff<T>(live, node);
+    buf_st(er, plane_rsrc(dst.mv, pb, S::kExact ? i - 1 : i), off);
+    buf_st(eb, plane_rsrc(dst.mv, pb, S::kExact ? 25 + i : 27 + i), off);
     if (S::kExact) {
       sr += (double)(S::dec(er) + shr);
       sb += (double)(S::dec(eb) + shb);
@@ -670,8 +691,10 @@ struct PopWriter {
   }
   __device__ __forceinline__ void finish(double rho_r, double rho_b) {
     if (S::kExact) {
-      at(dst.restp(0), node) = rho_r - sr;
-      at(dst.restp(1), node) = rho_b - sb;
+      const int64_t pb = dst.plane * 8;
+      const uint32_t off = boff<double>(live, node);
+      buf_st(rho_r - sr, plane_rsrc(dst.rest, pb, 0), off);
+      buf_st(rho_b - sb, plane_rsrc(dst.rest, pb, 1), off);
     }
   }
 };
@@ -780,12 +803,11 @@ struct FusedGeom {
   static constexpr int A_PER = (R3 + NT - 1) / NT;
 };
 
-template <int TX, int TY, int ZC, int MINW, bool WALLS, class S>
+template <int TX, int TY, int ZC, int MINW, bool WALLS, class S, bool EXPORT>
 __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict__ boxes,
                                                   const int32_t *__restrict__ col_box,
                                                   float *__restrict__ aux,
-                                                  void *__restrict__ dst_, int64_t plane_arg,
-                                                  int write_pops, int export_fields) {
+                                                  void *__restrict__ dst_, int64_t plane_arg) {
   using G = FusedGeom<TX, TY>;
   __shared__ float s_phi[3][G::R3];
   __shared__ float s_n[3][4][G::R2];
@@ -859,6 +881,9 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
   const int ox = tid % TX, oy = tid / TX;
   const int gxo = x0 + ox, gyo = y0 + oy;
   const bool in_xy = gxo < nx && gyo < ny;
+  // the tile point clamped into the box: lanes outside it load valid
+  // addresses and store nowhere
+  const uint32_t oxy = (uint32_t)min(gxo, nx - 1) + (uint32_t)nx * (uint32_t)min(gyo, ny - 1);
   const bool solid_y_o = (B.walls & 1u) && (gyo == 0 || gyo == ny - 1);
   // interface values of the tile point, one slab behind the q ring
   float h_nx = 0.f, h_ny = 0.f, h_nz = 0.f, h_Fx = 0.f, h_Fy = 0.f, h_Fz = 0.f, h_k = 0.f;
@@ -867,36 +892,64 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
     const int gz = wrap_any(s, nz);
     return gz == 0 || gz == nz - 1;
   };
+  // Every vector memory access of the march is issued on every lane and in
+  // every iteration (lanes and slabs without work use clamped addresses or
+  // discarded stores), and the loads of stages A and C run one iteration
+  // ahead, before the stores of the collision.  The waits for them then
+  // never include those stores, which share the in-order vector memory
+  // counter with the loads.
+  float a_rr[G::A_PER], a_rb[G::A_PER];
+  float pc_[C_PER][5];
+  auto load_a = [&](int sl, int64_t pl) {
+    const uint32_t zoff = (uint32_t)B.base + nxy * (uint32_t)wrap_any(sl, nz);
+#pragma unroll
+    for (int k = 0; k < G::A_PER; ++k) {
+      const uint32_t node = zoff + (uint32_t)a_off[k];
+      a_rr[k] = ldpl(aux, pl, A_RR, node);
+      a_rb[k] = ldpl(aux, pl, A_RB, node);
+    }
+  };
+  auto load_c = [&](int sl, int64_t pl) {
+    const uint32_t zoff = (uint32_t)B.base + nxy * (uint32_t)wrap_any(sl, nz);
+#pragma unroll
+    for (int kk = 0; kk < C_PER; ++kk) {
+      const uint32_t node = zoff + c_off[kk];
+      pc_[kk][0] = ldpl(aux, pl, A_RR, node);
+      pc_[kk][1] = ldpl(aux, pl, A_RB, node);
+      pc_[kk][2] = ldpl(aux, pl, A_JX, node);
+      pc_[kk][3] = ldpl(aux, pl, A_JY, node);
+      pc_[kk][4] = ldpl(aux, pl, A_JZ, node);
+    }
+  };
+  load_a(z0 - 3, plane_arg);
+  load_c(z0 - 5, plane_arg);
+  // as many stores as stage D issues, all discarded: on entry to the march
+  // the loads above are then followed by the same count of memory
+  // instructions as in every later iteration, so the waits for them are
+  // the same on both paths into the loop
+  if (!EXPORT) {
+    const Pops<S> dst(dst_, plane_arg);
+    PopWriter<S> w(dst, B, 0u, false);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) w(i, 0.f, 0.f);
+    w.finish(0.0, 0.0);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 10; ++k) buf_st(0.f, plane_rsrc(aux, plane_arg * 4, A_NX + k), kDrop);
+  }
   __syncthreads();
 
   for (int s = z0 - 3; s < z1 + 3; ++s) {
     const int64_t plane = opaque_i64(plane_arg);
-    // ---- prefetch the global inputs of stages C and D of this iteration, so
-    // that their latency overlaps the stencil work of stages A-C ----
-    float pc_[C_PER][5];
-    if (s - 2 >= z0 - 1) {
-      const uint32_t zoff = (uint32_t)B.base + nxy * (uint32_t)wrap_any(s - 2, nz);
-#pragma unroll
-      for (int kk = 0; kk < C_PER; ++kk) {
-        const uint32_t node = zoff + c_off[kk];
-        const bool ok = tid + kk * G::NT < G::R1;
-        pc_[kk][0] = ok ? ldpl(aux, plane, A_RR, node) : 1.f;
-        pc_[kk][1] = ok ? ldpl(aux, plane, A_RB, node) : 0.f;
-        pc_[kk][2] = ok ? ldpl(aux, plane, A_JX, node) : 0.f;
-        pc_[kk][3] = ok ? ldpl(aux, plane, A_JY, node) : 0.f;
-        pc_[kk][4] = ok ? ldpl(aux, plane, A_JZ, node) : 0.f;
-      }
-    }
+    // inputs of the collision of slab s-3 at the (clamped) tile point
     NodeIn din;
     double d_rr = 0.0, d_rb = 0.0;
-    const bool d_live = (s - 3 >= z0) && in_xy && write_pops;
-    if (d_live) {
-      const uint32_t node = (uint32_t)B.base + (uint32_t)gxo + (uint32_t)nx * (uint32_t)gyo +
-                            nxy * (uint32_t)wrap_any(s - 3, nz);
+    if (!EXPORT) {
+      const uint32_t node = (uint32_t)B.base + oxy + nxy * (uint32_t)wrap_any(s - 3, nz);
       if (S::kExact) {
         const double *r64 = aux_rho64(aux, plane);
-        d_rr = at(r64, node);
-        d_rb = at(r64 + plane, node);
+        d_rr = buf_ld_f64(plane_rsrc(r64, plane * 8, 0), node * 8u);
+        d_rb = buf_ld_f64(plane_rsrc(r64, plane * 8, 1), node * 8u);
       }
       din.rr = ldpl(aux, plane, A_RR, node);
       din.rb = ldpl(aux, plane, A_RB, node);
@@ -912,15 +965,13 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
     }
     // ---- A: phase field of slab s (Eq. 14) ----
     {
-      const uint32_t zoff = (uint32_t)B.base + nxy * (uint32_t)wrap_any(s, nz);
       float *ph = s_phi[(s + 3) % 3];
 #pragma unroll
       for (int k = 0; k < G::A_PER; ++k) {
         const int i = tid + k * G::NT;
         if (i < G::R3) {
-          const uint32_t node = zoff + (uint32_t)a_off[k];
-          const float rr = ldpl(aux, plane, A_RR, node) * B.ir0r;
-          const float rb = ldpl(aux, plane, A_RB, node) * B.ir0b;
+          const float rr = a_rr[k] * B.ir0r;
+          const float rb = a_rb[k] * B.ir0b;
           const float den = rr + rb;
           ph[i] = den > 0.f ? (rr - rb) / den : 0.f;
         }
@@ -1069,85 +1120,78 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
       }
     }
     __syncthreads();
+    // loads of the next iteration, ahead of the stores below
+    load_a(s + 1, plane);
+    load_c(s - 1, plane);
     // ---- D: Q and the collision of slab s-3 (Eqs. 18-19, 25, 65-67) ----
-    if (s - 3 >= z0) {
+    // Runs on every lane and in every iteration; only lanes of a fluid node
+    // of the box in an output slab store.  The ring index keeps the slot
+    // non-negative for the slabs before the first output slab.
+    {
       const int sd = s - 3;
-      const int gz = wrap_any(sd, nz);
-      if (in_xy && !(solid_y_o || slab_solid(sd))) {
-        const bool sz_m = slab_solid(sd - 1), sz_p = slab_solid(sd + 1);
-        float(*qm)[G::R1] = s_q[(sd - 1 + 3) % 3];
-        float(*qc)[G::R1] = s_q[(sd + 3) % 3];
-        float(*qp)[G::R1] = s_q[(sd + 1 + 3) % 3];
-        const int c1 = (ox + 1) + G::R1X * (oy + 1);
-        // d q_x / dx: pairs along x over (dy, dz); likewise y and z
-        float Qx = 0.f, Qy = 0.f, Qz = 0.f;
+      const bool sz_m = slab_solid(sd - 1), sz_p = slab_solid(sd + 1);
+      const bool fluid = in_xy && !(solid_y_o || slab_solid(sd));
+      float(*qm)[G::R1] = s_q[(sd + 8) % 3];
+      float(*qc)[G::R1] = s_q[(sd + 9) % 3];
+      float(*qp)[G::R1] = s_q[(sd + 10) % 3];
+      const int c1 = (ox + 1) + G::R1X * (oy + 1);
+      // d q_x / dx: pairs along x over (dy, dz); likewise y and z
+      float Qx = 0.f, Qy = 0.f, Qz = 0.f;
 #pragma unroll
-        for (int a2 = -1; a2 <= 1; ++a2)
+      for (int a2 = -1; a2 <= 1; ++a2)
 #pragma unroll
-          for (int b2 = -1; b2 <= 1; ++b2) {
-            const float w = 0.5f * w1d(a2) * w1d(b2);
-            {  // x: a2 = dy, b2 = dz
-              const float *pl = b2 < 0 ? qm[0] : (b2 > 0 ? qp[0] : qc[0]);
-              const bool sdd = (b2 < 0 ? sz_m : (b2 > 0 ? sz_p : false)) | sy(oy + 3 + a2);
-              const float vc = qc[0][c1];
-              const float vp = sdd ? vc : pl[c1 + 1 + G::R1X * a2];
-              const float vm = sdd ? vc : pl[c1 - 1 + G::R1X * a2];
-              Qx = fmaf(w, vp - vm, Qx);
-            }
-            {  // y: a2 = dx, b2 = dz
-              const float *pl = b2 < 0 ? qm[1] : (b2 > 0 ? qp[1] : qc[1]);
-              const bool szd = b2 < 0 ? sz_m : (b2 > 0 ? sz_p : false);
-              const float vc = qc[1][c1];
-              const float vp = (szd | sy(oy + 4)) ? vc : pl[c1 + a2 + G::R1X];
-              const float vm = (szd | sy(oy + 2)) ? vc : pl[c1 + a2 - G::R1X];
-              Qy = fmaf(w, vp - vm, Qy);
-            }
-            {  // z: a2 = dx, b2 = dy
-              const bool syd = sy(oy + 3 + b2);
-              const float vc = qc[2][c1];
-              const float vp = (sz_p | syd) ? vc : qp[2][c1 + a2 + G::R1X * b2];
-              const float vm = (sz_m | syd) ? vc : qm[2][c1 + a2 + G::R1X * b2];
-              Qz = fmaf(w, vp - vm, Qz);
-            }
+        for (int b2 = -1; b2 <= 1; ++b2) {
+          const float w = 0.5f * w1d(a2) * w1d(b2);
+          {  // x: a2 = dy, b2 = dz
+            const float *pl = b2 < 0 ? qm[0] : (b2 > 0 ? qp[0] : qc[0]);
+            const bool sdd = (b2 < 0 ? sz_m : (b2 > 0 ? sz_p : false)) | sy(oy + 3 + a2);
+            const float vc = qc[0][c1];
+            const float vp = sdd ? vc : pl[c1 + 1 + G::R1X * a2];
+            const float vm = sdd ? vc : pl[c1 - 1 + G::R1X * a2];
+            Qx = fmaf(w, vp - vm, Qx);
           }
-        Qx *= -3.0f;
-        Qy *= -3.0f;
-        Qz *= -3.0f;
-        const uint32_t node =
-            (uint32_t)B.base + (uint32_t)gxo + (uint32_t)nx * (uint32_t)gyo + nxy * (uint32_t)gz;
-        if (write_pops) {
-          NodeIn in = din;
-          in.nx = h_nx;
-          in.ny = h_ny;
-          in.nz = h_nz;
-          in.Fx = h_Fx;
-          in.Fy = h_Fy;
-          in.Fz = h_Fz;
-          in.Qx = Qx;
-          in.Qy = Qy;
-          in.Qz = Qz;
-          const Pops<S> dst(dst_, plane);
-          PopWriter<S> w(dst, B, node);
-          collide_node(B, in, w);
-          w.finish(d_rr, d_rb);
+          {  // y: a2 = dx, b2 = dz
+            const float *pl = b2 < 0 ? qm[1] : (b2 > 0 ? qp[1] : qc[1]);
+            const bool szd = b2 < 0 ? sz_m : (b2 > 0 ? sz_p : false);
+            const float vc = qc[1][c1];
+            const float vp = (szd | sy(oy + 4)) ? vc : pl[c1 + a2 + G::R1X];
+            const float vm = (szd | sy(oy + 2)) ? vc : pl[c1 + a2 - G::R1X];
+            Qy = fmaf(w, vp - vm, Qy);
+          }
+          {  // z: a2 = dx, b2 = dy
+            const bool syd = sy(oy + 3 + b2);
+            const float vc = qc[2][c1];
+            const float vp = (sz_p | syd) ? vc : qp[2][c1 + a2 + G::R1X * b2];
+            const float vm = (sz_m | syd) ? vc : qm[2][c1 + a2 + G::R1X * b2];
+            Qz = fmaf(w, vp - vm, Qz);
+          }
         }
-        if (export_fields) {
-          at(PL(aux, A_NX), node) = h_nx;
-          at(PL(aux, A_NY), node) = h_ny;
-          at(PL(aux, A_NZ), node) = h_nz;
-          at(PL(aux, A_FX), node) = h_Fx;
-          at(PL(aux, A_FY), node) = h_Fy;
-          at(PL(aux, A_FZ), node) = h_Fz;
-          at(PL(aux, A_QX), node) = Qx;
-          at(PL(aux, A_QY), node) = Qy;
-          at(PL(aux, A_QZ), node) = Qz;
-          at(PL(aux, A_KAPPA), node) = h_k;
-        }
-      } else if (export_fields && in_xy) {
-        const uint32_t node =
-            (uint32_t)B.base + (uint32_t)gxo + (uint32_t)nx * (uint32_t)gyo + nxy * (uint32_t)gz;
+      Qx *= -3.0f;
+      Qy *= -3.0f;
+      Qz *= -3.0f;
+      const uint32_t node = (uint32_t)B.base + oxy + nxy * (uint32_t)wrap_any(sd, nz);
+      if (!EXPORT) {
+        NodeIn in = din;
+        in.nx = h_nx;
+        in.ny = h_ny;
+        in.nz = h_nz;
+        in.Fx = h_Fx;
+        in.Fy = h_Fy;
+        in.Fz = h_Fz;
+        in.Qx = Qx;
+        in.Qy = Qy;
+        in.Qz = Qz;
+        const Pops<S> dst(dst_, plane);
+        PopWriter<S> w(dst, B, node, fluid && sd >= z0);
+        collide_node(B, in, w);
+        w.finish(d_rr, d_rb);
+      } else {
+        // interface fields of every node of the box (zero at solid nodes)
+        const uint32_t off = boff<float>(in_xy && sd >= z0, node);
+        const float v[10] = {h_nx, h_ny, h_nz, h_Fx, h_Fy, h_Fz, Qx, Qy, Qz, h_k};
 #pragma unroll
-        for (int k = A_NX; k <= A_KAPPA; ++k) at(PL(aux, k), node) = 0.f;
+        for (int k = 0; k < 10; ++k)
+          buf_st(fluid ? v[k] : 0.f, plane_rsrc(aux, plane * 4, A_NX + k), off);
       }
     }
     // the interface values of slab s-2 become those of the next collision
