@@ -228,8 +228,8 @@ def main():
     dom = max(kern, key=lambda k: kern[k]["share"])
     var = main_r["variant"]
     if dom == "fused":
-        kname = "k_fused<%d, %d, %d, %d, false, f32>" % (var["tx"], var["ty"], var["zc"],
-                                                        var["min_waves"])
+        kname = "k_fused<%d, %d, %d, %d, false, f32, false>" % (var["tx"], var["ty"], var["zc"],
+                                                               var["min_waves"])
     else:
         kname = "k_%s<f32>" % dom
     traffic = measured_traffic(kname) if (n == 256 and args.storage == "fp32") else None
