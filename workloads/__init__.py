@@ -125,21 +125,44 @@ def periodic_distance(shape_xyz, centre, walls=0):
     return np.sqrt(d[0] ** 2 + d[1] ** 2 + d[2] ** 2)
 
 
+def _sphere(box: Box, centre, r):
+    """Nodes within distance r of centre, as index vectors (z, y, x) and a
+    mask over their outer product.  Only the sphere's bounding box is
+    visited; distances are formed as in periodic_distance."""
+    axes = []
+    for c, n, periodic in ((centre[0], box.nx, True), (centre[1], box.ny, not (box.walls & 1)),
+                           (centre[2], box.nz, not (box.walls & 2))):
+        lo, hi = int(math.floor(c - r)), int(math.ceil(c + r))
+        if periodic:
+            coord = np.arange(n) if hi - lo + 1 >= n else np.mod(np.arange(lo, hi + 1), n)
+            dd = np.abs(coord - c)
+            dd = np.minimum(dd, n - dd)
+        else:
+            coord = np.arange(max(lo, 0), min(hi, n - 1) + 1)
+            dd = np.abs(coord - c)
+        axes.append((coord, dd))
+    (xc, dx), (yc, dy), (zc, dz) = axes
+    d = np.sqrt(dx[None, None, :] ** 2 + dy[None, :, None] ** 2 + dz[:, None, None] ** 2)
+    return (zc, yc, xc), d <= r
+
+
 def droplet_fields(box: Box, centres, radii, u_drop=None, u_carrier=None):
     """Sharp droplets of red fluid in blue fluid; returns float32 arrays."""
     red = np.zeros(box.shape, dtype=bool)
-    for c, r in zip(centres, radii):
-        red |= periodic_distance((box.nx, box.ny, box.nz), c, box.walls) <= r
+    spheres = [_sphere(box, c, r) for c, r in zip(centres, radii)]
+    for idx, m in spheres:
+        sub = np.ix_(*idx)
+        red[sub] |= m
     rho_r = np.where(red, box.rho0_r, 0.0).astype(np.float32)
     rho_b = np.where(red, 0.0, box.rho0_b).astype(np.float32)
     u = np.zeros((3,) + box.shape, dtype=np.float32)
     if u_carrier is not None:
         u[:] = np.asarray(u_carrier, dtype=np.float32).reshape(3, 1, 1, 1)
     if u_drop is not None:
-        for c, r, ud in zip(centres, radii, u_drop):
-            m = periodic_distance((box.nx, box.ny, box.nz), c, box.walls) <= r
+        for (idx, m), ud in zip(spheres, u_drop):
+            sub = np.ix_(*idx)
             for a in range(3):
-                u[a][m] = ud[a]
+                u[a][sub] = np.where(m, np.float32(ud[a]), u[a][sub])
     return rho_r, rho_b, u
 
 
@@ -197,9 +220,16 @@ def place_droplets(n: int, count: int, rmin: float, rmax: float, gap: float, see
 
 def sheared_droplets(n: int = 512, count: int = 8, rmin: float = 20.0, rmax: float = 48.0,
                      gamma: float = 1000.0, U: float = 0.04, Re: float = 1000.0,
-                     visc_ratio_dyn: float = 10.0, sigma: float = 0.005, beta: float = 0.2,
+                     visc_ratio_dyn: float = 1000.0, sigma: float = 1e-4, beta: float = 0.2,
                      seed: int = 3, steps: int = 2000) -> Workload:
-    """Several heavy droplets in a light carrier with a sinusoidal shear."""
+    """Several heavy droplets in a light carrier with a sinusoidal shear.
+
+    Defaults: equal kinematic viscosities (dynamic ratio = density ratio) and
+    sigma = 0.1 rho_light, the choices of the stationary-droplet tests at a
+    density ratio of 1000 (Table II).  With a dynamic ratio of 10 (the heavy
+    phase 100 times less viscous kinematically, relaxation time 1.1) or
+    sigma = 0.005, the FP64 reference update diverges within a few tens of
+    steps from sharp or tanh-smoothed droplets alike."""
     rho_r0, rho_b0 = 1.0, 1.0 / gamma
     nu_b = U * n / Re
     nu_r = visc_ratio_dyn * rho_b0 * nu_b / rho_r0
