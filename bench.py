@@ -12,8 +12,11 @@ kernel (algorithmic bytes per launch / average launch time from HIP events
 recorded on the launch stream during the timed region) and the FP64 CPU
 oracle timed on a bounded sample of the same workload.  `forms` reports, on
 the same workload and step counts, the FP16/BF16-shifted and mass-exact FP32
-storage (with their difference to the FP32 run as a proxy error) and the
-96-box batched workload.
+storage (with their difference to the FP32 run as a proxy error), the
+96-box batched workload and the 32^3 static droplet.  The timed region
+launches every kernel directly (HIP events around each launch); after it,
+`graph_mlups` times the same update as replays of the captured two-step
+graph that cglbm_step uses by default.
 """
 import argparse
 import json
@@ -27,6 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+GRAPH_STEPS = 500   # steps of the graph-replay run after the timed region
 STORAGES = {"fp32": 0, "fp16": 1, "bf16": 2, "fp32x": 3}
 DTYPE = {"fp32": "f32", "fp16": "f16 storage, f32 arithmetic", "bf16": "bf16 storage, f32 arithmetic",
          "fp32x": "f32"}
@@ -54,8 +58,7 @@ def step_bytes(storage: str) -> int:
 
 
 COUNTERS = os.path.join(ROOT, "profiles", "k_fused_translating_droplet_256_hbm_counters.md")
-SOURCES = ("paper_2309_07801_amd/csrc/kernels.hpp", "paper_2309_07801_amd/csrc/lattice.hpp",
-           "paper_2309_07801_amd/csrc/cglbm.hip")
+SOURCES = ("paper_2309_07801_amd/csrc/kernels.hpp", "paper_2309_07801_amd/csrc/lattice.hpp")
 
 
 def measured_traffic(kernel: str):
@@ -88,7 +91,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--size", type=int, default=256, help="box edge (default 256)")
     ap.add_argument("--storage", default="fp32", choices=sorted(STORAGES))
-    ap.add_argument("--forms", default="fp16,bf16,fp32x,batched",
+    ap.add_argument("--forms", default="fp16,bf16,fp32x,batched,small",
                     help="extra forms on the same workload ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -160,8 +163,9 @@ def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=False):
     else:
         tune_ms = sim.autotune(reps=5)
     var = pkg.variant_info(sim.variant())
-    sim.step(max(warmup - 2, 0))
+    sim.step(max(warmup - 2, 0))  # also captures the step graph
     torch.cuda.synchronize()
+    # timed region: direct launches with HIP events around every kernel
     sim.profile_begin(4 * steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -170,6 +174,12 @@ def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=False):
     t1 = time.perf_counter()
     prof = sim.profile_end()
     dt = t1 - t0
+    # the same update as replays of the captured two-step graph
+    ngraph = min(steps, GRAPH_STEPS)
+    t2 = time.perf_counter()
+    sim.step(ngraph)
+    torch.cuda.synchronize()
+    graph_mlups = fluid * ngraph / (time.perf_counter() - t2) / 1e6
     d1 = sim.reduce()
     kb = kernel_bytes(storage)
     kern = {}
@@ -180,6 +190,7 @@ def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=False):
     m0 = d0[:, :2].sum(axis=0)
     m1 = d1[:, :2].sum(axis=0)
     out = {"mlups": fluid * steps / dt / 1e6, "ms_per_step": dt / steps * 1e3, "dt": dt,
+           "graph_mlups": graph_mlups,
            "fluid": fluid, "kernels": kern, "variant": var, "autotune_ms": tune_ms,
            "mass_drift": [float((m1[0] - m0[0]) / m0[0]), float((m1[1] - m0[1]) / m0[1])],
            "nonfinite": int(d1[:, 12].sum()), "steps": steps}
@@ -257,6 +268,7 @@ def main():
                      "traffic": traffic, "traffic_unit": "bytes per launch",
                      "algorithmic_bytes": kb[dom] * fluid, "kernel": kname},
         "step_roofline_frac": round(main_r["mlups"] * 1e6 * sb / (HBM_PEAK_GBS * 1e9), 4),
+        "graph_mlups": round(main_r["graph_mlups"], 1),
         "step_bytes_per_node": sb,
         "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in kern.items()},
         "fused_variant": var,
@@ -271,6 +283,7 @@ def main():
             r = run_form([w], f, args.steps, args.warmup, args.variant, keep_fields=True)
             sbf = step_bytes(f)
             forms[f] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+                        "graph_mlups": round(r["graph_mlups"], 1),
                         "step_roofline_frac": round(r["mlups"] * 1e6 * sbf / (HBM_PEAK_GBS * 1e9), 4),
                         "step_bytes_per_node": sbf,
                         "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()}
@@ -285,10 +298,21 @@ def main():
                                             "in {1,10,100}, FP32", "nodes": r["fluid"],
                                 "steps": steps_b, "mlups": round(r["mlups"], 1),
                                 "ms_per_step": round(r["ms_per_step"], 4),
+                                "graph_mlups": round(r["graph_mlups"], 1),
                                 "step_roofline_frac": round(r["mlups"] * 1e6 * 432 / (HBM_PEAK_GBS * 1e9), 4),
                                 "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()}
                                             for k, v in r["kernels"].items()},
                                 "mass_drift": r["mass_drift"], "nonfinite": r["nonfinite"]}
+        elif f == "small":
+            ws = WL.static_droplet()
+            steps_s = min(args.steps, 2000)
+            r = run_form([ws], "fp32", steps_s, args.warmup, args.variant)
+            forms["small"] = {"workload": "static droplet 32^3 (density ratio 1, R=8), FP32",
+                              "nodes": r["fluid"], "steps": steps_s,
+                              "mlups_direct_launches": round(r["mlups"], 1),
+                              "graph_mlups": round(r["graph_mlups"], 1),
+                              "ms_per_step": round(r["ms_per_step"], 4),
+                              "mass_drift": r["mass_drift"], "nonfinite": r["nonfinite"]}
     if forms:
         line["forms"] = forms
     if not args.no_cpu_baseline:

@@ -161,6 +161,15 @@ int64_t cglbm_box_offset(const cglbm_handle *h, int32_t box);
  * Returns CGLBM_EINVAL for other values. */
 int cglbm_set_schedule(cglbm_handle *h, int32_t schedule);
 
+/* Graph execution of cglbm_step: 1 (default) runs pairs of time steps as one
+ * captured HIP graph (captured on first use on a private stream of default
+ * priority, launched on the caller's stream; captured again after
+ * cglbm_set_variant or cglbm_set_schedule; an odd last step is launched
+ * directly); 0 launches every kernel directly.  Both give bitwise identical
+ * results.  While per-kernel profiling is active steps are launched directly.
+ * Returns CGLBM_EINVAL for other values. */
+int cglbm_set_graph(cglbm_handle *h, int32_t enable);
+
 /* Launch geometries of the fused kernel (all bitwise equivalent).
  * cglbm_num_variants: how many; cglbm_variant_info: info[0..3] = column
  * extent x, y, z chunk, minimum waves per SIMD; cglbm_set_variant selects one

@@ -34,7 +34,7 @@ FIELDS = ("rho_r", "rho_b", "phi", "p", "ux", "uy", "uz", "nx", "ny", "nz", "kap
 KERNEL_KINDS = ("pull", "interface", "collide", "fused")
 
 EXPORTED = ("cglbm_query_sizes", "cglbm_init", "cglbm_step", "cglbm_moments", "cglbm_reduce",
-            "cglbm_box_offset", "cglbm_set_schedule", "cglbm_num_variants",
+            "cglbm_box_offset", "cglbm_set_schedule", "cglbm_set_graph", "cglbm_num_variants",
             "cglbm_variant_info", "cglbm_set_variant", "cglbm_get_variant", "cglbm_autotune",
             "cglbm_profile_begin", "cglbm_profile_end", "cglbm_destroy",
             "cglbm_last_error", "cglbm_version")
@@ -99,6 +99,7 @@ def lib():
         L.cglbm_box_offset.argtypes = [vp, i32]
         L.cglbm_box_offset.restype = i64
         L.cglbm_set_schedule.argtypes = [vp, i32]
+        L.cglbm_set_graph.argtypes = [vp, i32]
         L.cglbm_num_variants.argtypes = []
         L.cglbm_variant_info.argtypes = [i32, C.POINTER(i32)]
         L.cglbm_set_variant.argtypes = [vp, i32, vp]
@@ -111,7 +112,7 @@ def lib():
         L.cglbm_last_error.restype = C.c_char_p
         L.cglbm_version.restype = C.c_char_p
         for fn in ("cglbm_query_sizes", "cglbm_init", "cglbm_step", "cglbm_moments",
-                   "cglbm_reduce", "cglbm_set_schedule", "cglbm_num_variants",
+                   "cglbm_reduce", "cglbm_set_schedule", "cglbm_set_graph", "cglbm_num_variants",
                    "cglbm_variant_info", "cglbm_set_variant", "cglbm_get_variant",
                    "cglbm_autotune", "cglbm_profile_begin", "cglbm_profile_end"):
             getattr(L, fn).restype = C.c_int
@@ -257,6 +258,11 @@ class Simulation:
 
     def set_schedule(self, schedule: int):
         _check(lib().cglbm_set_schedule(self.h, int(schedule)))
+
+    def set_graph(self, enable: bool):
+        """Run pairs of steps as a captured HIP graph (default) or launch
+        every kernel directly; results are bitwise identical."""
+        _check(lib().cglbm_set_graph(self.h, int(bool(enable))))
 
     def profile_end(self):
         n = len(KERNEL_KINDS)

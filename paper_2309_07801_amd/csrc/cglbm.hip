@@ -268,6 +268,10 @@ struct cglbm_handle {
   double *d_part = nullptr;    // block partials of the reduction
   double *d_diag = nullptr;    // per box kNPart doubles
   double *d_centre = nullptr;  // per box 3 doubles
+  // time steps as a captured graph: two steps from each buffer parity
+  int32_t use_graph = 1;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
   // profiling
   bool prof = false;
   std::vector<hipEvent_t> ev;
@@ -307,7 +311,16 @@ int launch_fused(cglbm_handle *h, hipStream_t s, int export_fields) {
 }
 
 // Select fused variant v: rebuild and upload the column tables.
+void drop_graphs(cglbm_handle *h) {
+  for (hipGraphExec_t &g : h->graph)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
+
 int select_variant(cglbm_handle *h, int v, hipStream_t s) {
+  drop_graphs(h);
   build_columns(h->L, v);
   if (h->L.col_box.size() > h->col_cap) {
     if (h->d_col_box) HIP_TRY(hipFree(h->d_col_box));
@@ -351,6 +364,45 @@ int check_launch() {
 }
 
 // Local moments and interface fields of the current state into aux.
+// One time step on stream s (launches only); flips the buffer parity.
+int launch_step(cglbm_handle *h, hipStream_t s) {
+  int rc = timed(h, s, KIND_PULL, [&] { return launch_pull(h, s, 1); });
+  if (h->schedule == 0) {
+    if (!rc) rc = timed(h, s, KIND_FUSED, [&] { return launch_fused(h, s, 0); });
+  } else {
+    if (!rc) rc = timed(h, s, KIND_IFACE, [&] { return launch_iface(h, s, 0); });
+    if (!rc) rc = timed(h, s, KIND_COLLIDE, [&] { return launch_collide(h, s); });
+  }
+  if (!rc) rc = check_launch();
+  if (!rc) h->cur = 1 - h->cur;
+  return rc;
+}
+
+// Capture two steps from the current parity (which they restore) on the
+// handle's private stream and instantiate them as an executable graph.
+int capture_pair(cglbm_handle *h) {
+  if (!h->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  const int c0 = h->cur;
+  HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  int rc = launch_step(h, h->cap_stream);
+  if (!rc) rc = launch_step(h, h->cap_stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+  h->cur = c0;
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(CGLBM_EHIP, "graph capture: %s", hipGetErrorString(e));
+  const hipError_t ei = hipGraphInstantiate(&h->graph[c0], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) {
+    h->graph[c0] = nullptr;
+    return fail(CGLBM_EHIP, "graph instantiate: %s", hipGetErrorString(ei));
+  }
+  return CGLBM_OK;
+}
+
 int compute_fields(cglbm_handle *h, hipStream_t s, int write_kappa) {
   int rc = launch_pull(h, s, 0);
   if (rc) return rc;
@@ -461,18 +513,26 @@ int cglbm_step(cglbm_handle *h, int32_t n_steps, void *stream) {
   if (!h) return fail(CGLBM_ESTATE, "null handle");
   if (n_steps < 0) return fail(CGLBM_EINVAL, "n_steps must be >= 0");
   hipStream_t s = (hipStream_t)stream;
-  for (int32_t k = 0; k < n_steps; ++k) {
-    int rc = timed(h, s, KIND_PULL, [&] { return launch_pull(h, s, 1); });
-    if (h->schedule == 0) {
-      if (!rc) rc = timed(h, s, KIND_FUSED, [&] { return launch_fused(h, s, 0); });
-    } else {
-      if (!rc) rc = timed(h, s, KIND_IFACE, [&] { return launch_iface(h, s, 0); });
-      if (!rc) rc = timed(h, s, KIND_COLLIDE, [&] { return launch_collide(h, s); });
+  int32_t k = 0;
+  if (h->use_graph && !h->prof && n_steps >= 2) {
+    if (!h->graph[h->cur]) {
+      const int rc = capture_pair(h);
+      if (rc) return rc;
     }
-    if (!rc) rc = check_launch();
-    if (rc) return rc;
-    h->cur = 1 - h->cur;
+    for (; k + 1 < n_steps; k += 2) HIP_TRY(hipGraphLaunch(h->graph[h->cur], s));
   }
+  for (; k < n_steps; ++k) {
+    const int rc = launch_step(h, s);
+    if (rc) return rc;
+  }
+  return CGLBM_OK;
+}
+
+int cglbm_set_graph(cglbm_handle *h, int32_t enable) {
+  g_err.clear();
+  if (!h) return fail(CGLBM_ESTATE, "null handle");
+  if (enable != 0 && enable != 1) return fail(CGLBM_EINVAL, "enable must be 0 or 1");
+  h->use_graph = enable;
   return CGLBM_OK;
 }
 
@@ -546,6 +606,7 @@ int cglbm_set_schedule(cglbm_handle *h, int32_t schedule) {
   g_err.clear();
   if (!h) return fail(CGLBM_ESTATE, "null handle");
   if (schedule != 0 && schedule != 1) return fail(CGLBM_EINVAL, "unknown schedule %d", schedule);
+  if (schedule != h->schedule) drop_graphs(h);
   h->schedule = schedule;
   return CGLBM_OK;
 }
@@ -650,6 +711,8 @@ int cglbm_profile_end(cglbm_handle *h, double *total_ms, int64_t *launches, int3
 
 void cglbm_destroy(cglbm_handle *h) {
   if (!h) return;
+  drop_graphs(h);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   if (h->d_boxes) (void)hipFree(h->d_boxes);
   if (h->d_blk_box) (void)hipFree(h->d_blk_box);
