@@ -60,6 +60,16 @@ typedef struct {
   double nu;
 } cglbm_phase;
 
+/* Equilibrium families of Table I: A (Eq. 31, the standard second-order
+ * equilibrium), B (Eq. 39), C (Eq. 48), D (Eq. 56, the generalized
+ * equilibrium with velocity-independent central moments). */
+typedef enum {
+  CGLBM_MODEL_A = 0,
+  CGLBM_MODEL_B = 1,
+  CGLBM_MODEL_C = 2,
+  CGLBM_MODEL_D = 3
+} cglbm_model;
+
 /* One box.  walls: bit0 = solid node layers at y = 0 and y = ny-1, bit1 =
  * solid layers at z = 0 and z = nz-1 (full-way bounce-back); other axes are
  * periodic.  sigma: interfacial tension of the CSF force (Eq. 15); beta:
@@ -67,7 +77,11 @@ typedef struct {
  * omega_hi: omega_0 and omega_3..omega_10 of Eq. (25) -- only 1.0 is built
  * (the choice of the paper, Sec. III.E), anything else gives
  * CGLBM_EUNSUPPORTED; body_force: constant force density added to the CSF
- * force. */
+ * force; model: a cglbm_model; q_correction: 1 adds the correction term Q of
+ * Eq. (65) to the second-order relaxation, 0 omits it.  Model D with the
+ * correction runs the fused schedule; as soon as one box uses another model
+ * or omits the correction, every step of the handle runs the three-kernel
+ * schedule (same update for the Model D boxes, bit for bit). */
 typedef struct {
   int32_t nx, ny, nz;
   uint32_t walls;
@@ -76,6 +90,8 @@ typedef struct {
   double omega_bulk;
   double omega_hi[9];
   double body_force[3];
+  int32_t model;
+  int32_t q_correction;
 } cglbm_box_params;
 
 /* Population storage formats.  Arithmetic is FP32 in all cases.

@@ -104,6 +104,7 @@ struct Layout {
   int64_t total = 0;  // plane length (nodes, all boxes, aligned)
   int32_t nblk = 0, ntile = 0, ncol = 0, nblk_pad = 0;
   bool walls = false;
+  bool general = false;  // a box with Model A, B or C or without Q: three-kernel schedule
 };
 
 int validate(int32_t n_boxes, const cglbm_box_params *boxes, int32_t storage) {
@@ -138,6 +139,10 @@ int validate(int32_t n_boxes, const cglbm_box_params *boxes, int32_t storage) {
       return fail(CGLBM_EINVAL, "box %d: sigma must be finite and >= 0", b);
     if (!std::isfinite(P.beta) || P.beta < 0.0)
       return fail(CGLBM_EINVAL, "box %d: beta must be finite and >= 0", b);
+    if (P.model < CGLBM_MODEL_A || P.model > CGLBM_MODEL_D)
+      return fail(CGLBM_EINVAL, "box %d: unknown equilibrium model %d", b, P.model);
+    if (P.q_correction != 0 && P.q_correction != 1)
+      return fail(CGLBM_EINVAL, "box %d: q_correction must be 0 or 1", b);
     if (!(P.omega_bulk > 0.0 && P.omega_bulk < 2.0))
       return fail(CGLBM_EINVAL, "box %d: omega_bulk must lie in (0, 2)", b);
     for (int k = 0; k < 9; ++k)
@@ -194,6 +199,9 @@ void build_layout(int32_t n_boxes, const cglbm_box_params *boxes, Layout &L) {
     B.Gx = (float)P.body_force[0];
     B.Gy = (float)P.body_force[1];
     B.Gz = (float)P.body_force[2];
+    B.model = P.model;
+    B.qcorr = P.q_correction;
+    if (P.model != CGLBM_MODEL_D || !P.q_correction) L.general = true;
     {
       // pure-phase rest equilibrium of each colour: w_i rho_k^0 (c_s^k)^2 / c_s^2
       const double w[4] = {8.0 / 27.0, 2.0 / 27.0, 1.0 / 54.0, 1.0 / 216.0};
@@ -364,10 +372,15 @@ int check_launch() {
 }
 
 // Local moments and interface fields of the current state into aux.
+// The fused kernel implements Model D with the correction term; layouts with
+// any other box run the three-kernel schedule, whose collision takes each
+// box's equilibrium family and correction switch.
+int effective_schedule(const cglbm_handle *h) { return h->L.general ? 1 : h->schedule; }
+
 // One time step on stream s (launches only); flips the buffer parity.
 int launch_step(cglbm_handle *h, hipStream_t s) {
   int rc = timed(h, s, KIND_PULL, [&] { return launch_pull(h, s, 1); });
-  if (h->schedule == 0) {
+  if (effective_schedule(h) == 0) {
     if (!rc) rc = timed(h, s, KIND_FUSED, [&] { return launch_fused(h, s, 0); });
   } else {
     if (!rc) rc = timed(h, s, KIND_IFACE, [&] { return launch_iface(h, s, 0); });
@@ -406,7 +419,7 @@ int capture_pair(cglbm_handle *h) {
 int compute_fields(cglbm_handle *h, hipStream_t s, int write_kappa) {
   int rc = launch_pull(h, s, 0);
   if (rc) return rc;
-  if (h->schedule == 0)
+  if (effective_schedule(h) == 0)
     rc = launch_fused(h, s, 1);
   else
     rc = launch_iface(h, s, write_kappa);

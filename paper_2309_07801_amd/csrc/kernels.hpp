@@ -49,6 +49,8 @@ struct BoxDev {
   float omega2;
   float Gx, Gy, Gz;
   float shift[2][4];    // storage shift by colour and speed class |c|^2
+  int32_t model;        // equilibrium family of Table I (MODEL_A..MODEL_D)
+  int32_t qcorr;        // 1: correction term Q of Eq. (65) in the collision
 };
 
 constexpr int kBlock = 256;
@@ -567,8 +569,9 @@ struct NodeIn {
 
 // Emits each direction's recoloured pair through emit(i, f_r, f_b) as soon as
 // its x-triplet of the back-transform is done, so that the 54 outputs never
-// have to be live at once.
-template <class Emit>
+// have to be live at once.  GENERAL: the box's equilibrium family and
+// correction switch apply; otherwise Model D with the correction Q.
+template <bool GENERAL = false, class Emit>
 __device__ __forceinline__ void collide_node(const BoxDev &B, const NodeIn &in, Emit &&emit) {
   const float rho = in.rr + in.rb;
   const float irho = rcp(rho);
@@ -590,17 +593,23 @@ __device__ __forceinline__ void collide_node(const BoxDev &B, const NodeIn &in, 
   const float kxz = in.pxz - ux * in.jz - uz * in.jx + rho * ux * uz;
   const float kyz = in.pyz - uy * in.jz - uz * in.jy + rho * uy * uz;
   // relaxation (Eq. 25 with omega_0 = omega_3..10 = 1 and k^eq of Eqs. 57-63)
+  const bool use_q = !GENERAL || B.qcorr;
+  const float Qx = use_q ? in.Qx : 0.f, Qy = use_q ? in.Qy : 0.f, Qz = use_q ? in.Qz : 0.f;
   const float r1 = 1.0f - w1, h1 = 1.0f - 0.5f * w1;
-  const float A = r1 * (kxx - kyy) + h1 * (in.Qx - in.Qy);
-  const float Bd = r1 * (kxx - kzz) + h1 * (in.Qx - in.Qz);
+  const float A = r1 * (kxx - kyy) + h1 * (Qx - Qy);
+  const float Bd = r1 * (kxx - kzz) + h1 * (Qx - Qz);
   const float T = (1.0f - w2) * (kxx + kyy + kzz) + 3.0f * w2 * p +
-                  (1.0f - 0.5f * w2) * (in.Qx + in.Qy + in.Qz);
+                  (1.0f - 0.5f * w2) * (Qx + Qy + Qz);
   const float third = 1.0f / 3.0f;
   const float sxx = (A + Bd + T) * third;
   const float syy = (T - 2.0f * A + Bd) * third;
   const float szz = (T + A - 2.0f * Bd) * third;
   float k[27];
-  model_d_moments(rho, p, in.Fx, in.Fy, in.Fz, sxx, syy, szz, r1 * kxy, r1 * kxz, r1 * kyz, k);
+  if (GENERAL)
+    model_moments(B.model, rho, p, ux, uy, uz, in.Fx, in.Fy, in.Fz, sxx, syy, szz, r1 * kxy,
+                  r1 * kxz, r1 * kyz, k);
+  else
+    model_d_moments(rho, p, in.Fx, in.Fy, in.Fz, sxx, syy, szz, r1 * kxy, r1 * kxz, r1 * kyz, k);
   // recolouring (Eqs. 18-19) folded into the last pass of the back-transform
   const float cr = in.rr * irho, cb = in.rb * irho;
   const float s = B.beta * cr * cb * p;
@@ -719,7 +728,7 @@ __global__ __launch_bounds__(kBlock) void k_collide(const BoxDev *__restrict__ b
   const NodeIn in = load_node_in(aux, plane, node);
   const Pops<S> dst(dst_, plane);
   PopWriter<S> w(dst, B, node);
-  collide_node(B, in, w);
+  collide_node<true>(B, in, w);
   if (S::kExact) {
     const double *r64 = aux_rho64(aux, plane);
     w.finish(at(r64, node), at(r64 + plane, node));
@@ -756,7 +765,7 @@ __global__ __launch_bounds__(kBlock) void k_init(const BoxDev *__restrict__ boxe
   const float rho = rr + rb;
   const float p = rr * B.cs2r + rb * B.cs2b;
   float k[27];
-  model_d_moments(rho, p, 0.f, 0.f, 0.f, p, p, p, 0.f, 0.f, 0.f, k);
+  model_moments(B.model, rho, p, ux, uy, uz, 0.f, 0.f, 0.f, p, p, p, 0.f, 0.f, 0.f, k);
   float f[kQ];
   central_to_populations(k, ux, uy, uz, f);
   const float cr = rr / rho, cb = rb / rho;

@@ -144,6 +144,77 @@ __device__ __forceinline__ void model_d_moments(float rho, float p, float Fx, fl
 #undef K_
 }
 
+// Equilibrium families of Table I.
+enum { MODEL_A = 0, MODEL_B = 1, MODEL_C = 2, MODEL_D = 3 };
+
+// Post-collision central moments with unit higher-order rates for any of the
+// four equilibria of Table I: the Model D moments and the forcing moments
+// above, plus the velocity-dependent parts of the equilibrium moments of
+// order three and higher of Models A (Eqs. 32-38), B (Eqs. 40-46) and C
+// (Eqs. 49-55), with dev = p - rho c_s^2.  `model` is uniform per box.
+__device__ __forceinline__ void model_moments(int model, float rho, float p, float ux, float uy,
+                                              float uz, float Fx, float Fy, float Fz, float kxx,
+                                              float kyy, float kzz, float kxy, float kxz,
+                                              float kyz, float (&k)[27]) {
+  model_d_moments(rho, p, Fx, Fy, Fz, kxx, kyy, kzz, kxy, kxz, kyz, k);
+  if (model == MODEL_D) return;
+#define K_(a, b, c) k[(a) + 3 * (b) + 9 * (c)]
+  const float dev = p - rho * kCs2;
+  const float x2 = ux * ux, y2 = uy * uy, z2 = uz * uz;
+  const float s2 = x2 * y2 + x2 * z2 + y2 * z2, u2 = x2 + y2 + z2;
+  if (model == MODEL_C) {
+    // Eqs. 49-55: no third-order part; the others with the opposite sign
+    K_(2, 2, 0) -= dev * (x2 + y2);
+    K_(2, 0, 2) -= dev * (x2 + z2);
+    K_(0, 2, 2) -= dev * (y2 + z2);
+    K_(2, 1, 1) -= dev * uy * uz;
+    K_(1, 2, 1) -= dev * ux * uz;
+    K_(1, 1, 2) -= dev * ux * uy;
+    K_(1, 2, 2) += dev * ux * (2.0f * (y2 + z2) + kCs2);
+    K_(2, 1, 2) += dev * uy * (2.0f * (x2 + z2) + kCs2);
+    K_(2, 2, 1) += dev * uz * (2.0f * (x2 + y2) + kCs2);
+    K_(2, 2, 2) -= 3.0f * dev * (s2 + kCs2 * u2);
+  } else {
+    // Model B (Eqs. 40-46); Model A (Eqs. 32-38) adds the rho terms below
+    K_(1, 2, 0) -= dev * ux;
+    K_(1, 0, 2) -= dev * ux;
+    K_(2, 1, 0) -= dev * uy;
+    K_(0, 1, 2) -= dev * uy;
+    K_(2, 0, 1) -= dev * uz;
+    K_(0, 2, 1) -= dev * uz;
+    K_(2, 2, 0) += dev * (x2 + y2);
+    K_(2, 0, 2) += dev * (x2 + z2);
+    K_(0, 2, 2) += dev * (y2 + z2);
+    K_(2, 1, 1) += dev * uy * uz;
+    K_(1, 2, 1) += dev * ux * uz;
+    K_(1, 1, 2) += dev * ux * uy;
+    K_(1, 2, 2) -= dev * ux * (y2 + z2 + kCs2);
+    K_(2, 1, 2) -= dev * uy * (x2 + z2 + kCs2);
+    K_(2, 2, 1) -= dev * uz * (x2 + y2 + kCs2);
+    K_(2, 2, 2) += dev * (s2 + kCs2 * u2);
+    if (model == MODEL_A) {
+      K_(1, 2, 0) -= rho * ux * y2;
+      K_(1, 0, 2) -= rho * ux * z2;
+      K_(2, 1, 0) -= rho * x2 * uy;
+      K_(0, 1, 2) -= rho * uy * z2;
+      K_(2, 0, 1) -= rho * x2 * uz;
+      K_(0, 2, 1) -= rho * y2 * uz;
+      K_(1, 1, 1) -= rho * ux * uy * uz;
+      K_(2, 2, 0) += 3.0f * rho * x2 * y2;
+      K_(2, 0, 2) += 3.0f * rho * x2 * z2;
+      K_(0, 2, 2) += 3.0f * rho * y2 * z2;
+      K_(2, 1, 1) += 3.0f * rho * x2 * uy * uz;
+      K_(1, 2, 1) += 3.0f * rho * ux * y2 * uz;
+      K_(1, 1, 2) += 3.0f * rho * ux * uy * z2;
+      K_(1, 2, 2) -= rho * ux * (6.0f * y2 * z2 + kCs2 * (y2 + z2));
+      K_(2, 1, 2) -= rho * uy * (6.0f * x2 * z2 + kCs2 * (x2 + z2));
+      K_(2, 2, 1) -= rho * uz * (6.0f * x2 * y2 + kCs2 * (x2 + y2));
+      K_(2, 2, 2) += rho * (10.0f * x2 * y2 * z2 + 3.0f * kCs2 * s2);
+    }
+  }
+#undef K_
+}
+
 // SplitMix64 output function (Steele, Lea, Flood 2014).
 __host__ __device__ inline uint64_t splitmix64(uint64_t state) {
   uint64_t z = state + 0x9E3779B97F4A7C15ull;

@@ -56,6 +56,8 @@ class Box:
     omega_bulk: float = 1.0
     body_force: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     walls: int = 0
+    model: int = 3        # equilibrium family of Table I: 0 A, 1 B, 2 C, 3 D
+    use_q: int = 1        # correction term Q of Eq. (65)
 
     @property
     def shape(self):
