@@ -192,6 +192,7 @@ def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=False):
     out = {"mlups": fluid * steps / dt / 1e6, "ms_per_step": dt / steps * 1e3, "dt": dt,
            "graph_mlups": graph_mlups,
            "fluid": fluid, "kernels": kern, "variant": var, "autotune_ms": tune_ms,
+           "schedule": ("fused", "three kernels")[sim.schedule()],
            "mass_drift": [float((m1[0] - m0[0]) / m0[0]), float((m1[1] - m0[1]) / m0[1])],
            "nonfinite": int(d1[:, 12].sum()), "steps": steps}
     if keep_fields:
@@ -272,6 +273,7 @@ def main():
         "step_bytes_per_node": sb,
         "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in kern.items()},
         "fused_variant": var,
+        "schedule": main_r["schedule"],
         "autotune_ms": [round(m, 4) for m in main_r["autotune_ms"]],
         "mass_drift": main_r["mass_drift"],
         "nonfinite": main_r["nonfinite"],
@@ -284,6 +286,7 @@ def main():
             sbf = step_bytes(f)
             forms[f] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
                         "graph_mlups": round(r["graph_mlups"], 1),
+                        "schedule": r["schedule"],
                         "step_roofline_frac": round(r["mlups"] * 1e6 * sbf / (HBM_PEAK_GBS * 1e9), 4),
                         "step_bytes_per_node": sbf,
                         "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()}
@@ -299,6 +302,7 @@ def main():
                                 "steps": steps_b, "mlups": round(r["mlups"], 1),
                                 "ms_per_step": round(r["ms_per_step"], 4),
                                 "graph_mlups": round(r["graph_mlups"], 1),
+                                "schedule": r["schedule"],
                                 "step_roofline_frac": round(r["mlups"] * 1e6 * 432 / (HBM_PEAK_GBS * 1e9), 4),
                                 "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()}
                                             for k, v in r["kernels"].items()},
@@ -311,6 +315,7 @@ def main():
                               "nodes": r["fluid"], "steps": steps_s,
                               "mlups_direct_launches": round(r["mlups"], 1),
                               "graph_mlups": round(r["graph_mlups"], 1),
+                              "schedule": r["schedule"],
                               "ms_per_step": round(r["ms_per_step"], 4),
                               "mass_drift": r["mass_drift"], "nonfinite": r["nonfinite"]}
     if forms:

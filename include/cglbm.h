@@ -177,6 +177,10 @@ int64_t cglbm_box_offset(const cglbm_handle *h, int32_t box);
  * Returns CGLBM_EINVAL for other values. */
 int cglbm_set_schedule(cglbm_handle *h, int32_t schedule);
 
+/* Schedule the next step runs: 0 or 1 as above (1 whenever a box needs the
+ * three-kernel schedule), -1 for a NULL handle. */
+int cglbm_get_schedule(const cglbm_handle *h);
+
 /* Graph execution of cglbm_step: 1 (default) runs pairs of time steps as one
  * captured HIP graph (captured on first use on a private stream of default
  * priority, launched on the caller's stream; captured again after
@@ -195,11 +199,14 @@ int cglbm_variant_info(int32_t variant, int32_t *info);
 int cglbm_set_variant(cglbm_handle *h, int32_t variant, void *stream);
 int cglbm_get_variant(const cglbm_handle *h);
 
-/* Autotuner: time every fused variant `reps` times on the current state
- * (the stored state is not advanced: the fused kernel is re-run on the same
- * inputs) and select the fastest.  ms_per_variant (optional, length
- * cglbm_num_variants()) receives the mean milliseconds per launch.
- * Synchronizes the stream. */
+/* Autotuner: time every fused variant and the three-kernel schedule `reps`
+ * times on the current state (the stored state is not advanced: the kernels
+ * after the pull are re-run on the same inputs) and select the fastest
+ * geometry and schedule (the three-kernel schedule wins on boxes too small to
+ * fill the GPU with fused columns).  ms_per_variant (optional, length
+ * cglbm_num_variants() + 1) receives the mean milliseconds per launch of
+ * each fused variant, then of the interface + collide pair.  Synchronizes
+ * the stream. */
 int cglbm_autotune(cglbm_handle *h, int32_t reps, double *ms_per_variant, void *stream);
 
 /* Per-kernel timing with HIP events recorded on the caller's stream around

@@ -34,7 +34,8 @@ FIELDS = ("rho_r", "rho_b", "phi", "p", "ux", "uy", "uz", "nx", "ny", "nz", "kap
 KERNEL_KINDS = ("pull", "interface", "collide", "fused")
 
 EXPORTED = ("cglbm_query_sizes", "cglbm_init", "cglbm_step", "cglbm_moments", "cglbm_reduce",
-            "cglbm_box_offset", "cglbm_set_schedule", "cglbm_set_graph", "cglbm_num_variants",
+            "cglbm_box_offset", "cglbm_set_schedule", "cglbm_get_schedule", "cglbm_set_graph",
+            "cglbm_num_variants",
             "cglbm_variant_info", "cglbm_set_variant", "cglbm_get_variant", "cglbm_autotune",
             "cglbm_profile_begin", "cglbm_profile_end", "cglbm_destroy",
             "cglbm_last_error", "cglbm_version")
@@ -107,6 +108,7 @@ def lib():
         L.cglbm_box_offset.argtypes = [vp, i32]
         L.cglbm_box_offset.restype = i64
         L.cglbm_set_schedule.argtypes = [vp, i32]
+        L.cglbm_get_schedule.argtypes = [vp]
         L.cglbm_set_graph.argtypes = [vp, i32]
         L.cglbm_num_variants.argtypes = []
         L.cglbm_variant_info.argtypes = [i32, C.POINTER(i32)]
@@ -120,7 +122,8 @@ def lib():
         L.cglbm_last_error.restype = C.c_char_p
         L.cglbm_version.restype = C.c_char_p
         for fn in ("cglbm_query_sizes", "cglbm_init", "cglbm_step", "cglbm_moments",
-                   "cglbm_reduce", "cglbm_set_schedule", "cglbm_set_graph", "cglbm_num_variants",
+                   "cglbm_reduce", "cglbm_set_schedule", "cglbm_get_schedule", "cglbm_set_graph",
+                   "cglbm_num_variants",
                    "cglbm_variant_info", "cglbm_set_variant", "cglbm_get_variant",
                    "cglbm_autotune", "cglbm_profile_begin", "cglbm_profile_end"):
             getattr(L, fn).restype = C.c_int
@@ -257,15 +260,20 @@ class Simulation:
         return int(lib().cglbm_get_variant(self.h))
 
     def autotune(self, reps: int = 5):
-        """Time every fused launch geometry and keep the fastest; returns the
-        mean milliseconds per variant."""
-        n = num_variants()
+        """Time every fused launch geometry and the three-kernel schedule and
+        keep the fastest; returns the mean milliseconds per fused variant,
+        then of the three-kernel schedule."""
+        n = num_variants() + 1
         ms = (C.c_double * n)()
         _check(lib().cglbm_autotune(self.h, int(reps), ms, _stream_ptr(self.stream)))
         return list(ms)
 
     def set_schedule(self, schedule: int):
         _check(lib().cglbm_set_schedule(self.h, int(schedule)))
+
+    def schedule(self) -> int:
+        """Schedule in use: 0 fused, 1 three kernels."""
+        return int(lib().cglbm_get_schedule(self.h))
 
     def set_graph(self, enable: bool):
         """Run pairs of steps as a captured HIP graph (default) or launch
