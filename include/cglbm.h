@@ -77,7 +77,9 @@ typedef enum {
  * omega_hi: omega_0 and omega_3..omega_10 of Eq. (25) -- only 1.0 is built
  * (the choice of the paper, Sec. III.E), anything else gives
  * CGLBM_EUNSUPPORTED; body_force: constant force density added to the CSF
- * force; model: a cglbm_model; q_correction: 1 adds the correction term Q of
+ * force; gravity, rho_ref: the buoyancy force -(rho - rho_ref) gravity of the
+ * Rayleigh-Taylor case (Sec. IV.E), also added (zero gravity disables it);
+ * model: a cglbm_model; q_correction: 1 adds the correction term Q of
  * Eq. (65) to the second-order relaxation, 0 omits it.  Model D with the
  * correction runs the fused schedule; as soon as one box uses another model
  * or omits the correction, every step of the handle runs the three-kernel
@@ -92,6 +94,8 @@ typedef struct {
   double body_force[3];
   int32_t model;
   int32_t q_correction;
+  double gravity[3];
+  double rho_ref;
 } cglbm_box_params;
 
 /* Population storage formats.  Arithmetic is FP32 in all cases.

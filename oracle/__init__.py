@@ -36,6 +36,7 @@ class _CParams(C.Structure):
         ("nu_r", C.c_double), ("nu_b", C.c_double),
         ("sigma", C.c_double), ("beta", C.c_double),
         ("omega", C.c_double * 11), ("body_force", C.c_double * 3),
+        ("gravity", C.c_double * 3), ("rho_ref", C.c_double),
     ]
 
 
@@ -55,6 +56,8 @@ class Params:
     beta: float
     omega: tuple = (1.0,) * 11          # omega_0..omega_10; omega_1 is per node
     body_force: tuple = (0.0, 0.0, 0.0)
+    gravity: tuple = (0.0, 0.0, 0.0)   # buoyancy force -(rho - rho_ref) g, Sec. IV.E
+    rho_ref: float = 0.0
     walls: int = 0
     model: int = MODEL_D
     use_q: int = 1
@@ -66,6 +69,8 @@ class Params:
             setattr(cp, name, getattr(self, name))
         cp.omega = (C.c_double * 11)(*[float(v) for v in self.omega])
         cp.body_force = (C.c_double * 3)(*[float(v) for v in self.body_force])
+        cp.gravity = (C.c_double * 3)(*[float(v) for v in self.gravity])
+        cp.rho_ref = float(self.rho_ref)
         return cp
 
     @property

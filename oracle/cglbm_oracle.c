@@ -584,9 +584,12 @@ static void compute_fields(const orc_params *P, const double *f, fields_t *W) {
           for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) proj += nv[a] * nv[b] * dn[a][b];
           kap = -(div - proj);
-          Fx = 0.5 * P->sigma * kap * W->gphi[c] + P->body_force[0];
-          Fy = 0.5 * P->sigma * kap * W->gphi[N + c] + P->body_force[1];
-          Fz = 0.5 * P->sigma * kap * W->gphi[2 * N + c] + P->body_force[2];
+          /* Eq. (15) plus the constant body force and the buoyancy force
+           * -(rho - rho_ref) g of the Rayleigh-Taylor case (Sec. IV.E) */
+          const double drho = W->rho[c] - P->rho_ref;
+          Fx = 0.5 * P->sigma * kap * W->gphi[c] + P->body_force[0] - drho * P->gravity[0];
+          Fy = 0.5 * P->sigma * kap * W->gphi[N + c] + P->body_force[1] - drho * P->gravity[1];
+          Fz = 0.5 * P->sigma * kap * W->gphi[2 * N + c] + P->body_force[2] - drho * P->gravity[2];
         }
         W->kappa[c] = kap;
         W->F[c] = Fx;

@@ -34,6 +34,8 @@ typedef struct {
   double omega[11];        /* omega_0..omega_10 of Eq. (25); omega[1] is ignored
                               (it follows from Eqs. (21)-(22) at every node) */
   double body_force[3];    /* constant force density added to F */
+  double gravity[3];       /* g of the buoyancy force -(rho - rho_ref) g (Sec. IV.E) */
+  double rho_ref;          /* reference density of the buoyancy force */
 } orc_params;
 
 /* ---- lattice and single-node pieces (exported for pin tests) ---- */

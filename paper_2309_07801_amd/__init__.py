@@ -55,7 +55,8 @@ class BoxParams(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("walls", C.c_uint32),
                 ("red", Phase), ("blue", Phase), ("sigma", C.c_double), ("beta", C.c_double),
                 ("omega_bulk", C.c_double), ("omega_hi", C.c_double * 9),
-                ("body_force", C.c_double * 3), ("model", C.c_int32), ("q_correction", C.c_int32)]
+                ("body_force", C.c_double * 3), ("model", C.c_int32), ("q_correction", C.c_int32),
+                ("gravity", C.c_double * 3), ("rho_ref", C.c_double)]
 
 
 # equilibrium families of Table I (cglbm_model)
@@ -64,9 +65,11 @@ MODEL_A, MODEL_B, MODEL_C, MODEL_D = 0, 1, 2, 3
 
 def box_params(nx, ny, nz, rho0_r, rho0_b, alpha_r, alpha_b, nu_r, nu_b, sigma, beta,
                omega_bulk=1.0, body_force=(0.0, 0.0, 0.0), walls=0, omega_hi=(1.0,) * 9,
-               model=MODEL_D, q_correction=1):
+               model=MODEL_D, q_correction=1, gravity=(0.0, 0.0, 0.0), rho_ref=0.0):
     p = BoxParams()
     p.model, p.q_correction = int(model), int(q_correction)
+    p.gravity = (C.c_double * 3)(*[float(v) for v in gravity])
+    p.rho_ref = float(rho_ref)
     p.nx, p.ny, p.nz, p.walls = int(nx), int(ny), int(nz), int(walls)
     p.red = Phase(float(rho0_r), float(alpha_r), float(nu_r))
     p.blue = Phase(float(rho0_b), float(alpha_b), float(nu_b))
@@ -82,7 +85,9 @@ def box_params_of(box) -> BoxParams:
                       box.nu_r, box.nu_b, box.sigma, box.beta, getattr(box, "omega_bulk", 1.0),
                       getattr(box, "body_force", (0.0, 0.0, 0.0)), getattr(box, "walls", 0),
                       model=getattr(box, "model", MODEL_D),
-                      q_correction=getattr(box, "use_q", 1))
+                      q_correction=getattr(box, "use_q", 1),
+                      gravity=getattr(box, "gravity", (0.0, 0.0, 0.0)),
+                      rho_ref=getattr(box, "rho_ref", 0.0))
 
 
 _lib = None

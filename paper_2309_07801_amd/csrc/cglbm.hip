@@ -139,6 +139,10 @@ int validate(int32_t n_boxes, const cglbm_box_params *boxes, int32_t storage) {
       return fail(CGLBM_EINVAL, "box %d: sigma must be finite and >= 0", b);
     if (!std::isfinite(P.beta) || P.beta < 0.0)
       return fail(CGLBM_EINVAL, "box %d: beta must be finite and >= 0", b);
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(P.gravity[a]) || !std::isfinite(P.body_force[a]))
+        return fail(CGLBM_EINVAL, "box %d: body force and gravity must be finite", b);
+    if (!std::isfinite(P.rho_ref)) return fail(CGLBM_EINVAL, "box %d: rho_ref must be finite", b);
     if (P.model < CGLBM_MODEL_A || P.model > CGLBM_MODEL_D)
       return fail(CGLBM_EINVAL, "box %d: unknown equilibrium model %d", b, P.model);
     if (P.q_correction != 0 && P.q_correction != 1)
@@ -199,6 +203,10 @@ void build_layout(int32_t n_boxes, const cglbm_box_params *boxes, Layout &L) {
     B.Gx = (float)P.body_force[0];
     B.Gy = (float)P.body_force[1];
     B.Gz = (float)P.body_force[2];
+    B.bgx = (float)P.gravity[0];
+    B.bgy = (float)P.gravity[1];
+    B.bgz = (float)P.gravity[2];
+    B.rho_ref = (float)P.rho_ref;
     B.model = P.model;
     B.qcorr = P.q_correction;
     if (P.model != CGLBM_MODEL_D || !P.q_correction) L.general = true;

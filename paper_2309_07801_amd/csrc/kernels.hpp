@@ -49,6 +49,8 @@ struct BoxDev {
   float omega2;
   float Gx, Gy, Gz;
   float shift[2][4];    // storage shift by colour and speed class |c|^2
+  float bgx, bgy, bgz;  // g of the buoyancy force -(rho - rho_ref) g
+  float rho_ref;
   int32_t model;        // equilibrium family of Table I (MODEL_A..MODEL_D)
   int32_t qcorr;        // 1: correction term Q of Eq. (65) in the collision
 };
@@ -356,6 +358,19 @@ __global__ __launch_bounds__(kBlock) void k_pull(const BoxDev *__restrict__ boxe
   at(PL(aux, A_PYZ), node) = pyz;
 }
 
+// Force density at a fluid node: the CSF force of Eq. (15) from the
+// curvature, |grad phi| and the normal, the constant body force G, and the
+// buoyancy force -(rho - rho_ref) g of the Rayleigh-Taylor case (Sec. IV.E).
+__device__ __forceinline__ void interface_force(const BoxDev &B, float kap, float mag, float nxv,
+                                                float nyv, float nzv, float rho, float &Fx,
+                                                float &Fy, float &Fz) {
+  const float hs = 0.5f * B.sigma * kap * mag;
+  const float drho = rho - B.rho_ref;
+  Fx = fmaf(-drho, B.bgx, fmaf(hs, nxv, B.Gx));
+  Fy = fmaf(-drho, B.bgy, fmaf(hs, nyv, B.Gy));
+  Fz = fmaf(-drho, B.bgz, fmaf(hs, nzv, B.Gz));
+}
+
 // ---------------------------------------------------------------------------
 // k_interface: for a TX*TY*TZ tile, stage phi on the tile + 3 halo, grad phi
 // and n on + 2, grad n, kappa, F, u, q on + 1, and Q on the tile.  Every
@@ -499,13 +514,10 @@ __global__ __launch_bounds__(kBlock) void k_interface(const BoxDev *__restrict__
                          nyv * (nxv * dyx + nyv * dyy + nzv * dyz) +
                          nzv * (nxv * dzx + nyv * dzy + nzv * dzz);
       kap = proj - div;
-      const float hs = 0.5f * B.sigma * kap * mag;
-      Fx = fmaf(hs, nxv, B.Gx);
-      Fy = fmaf(hs, nyv, B.Gy);
-      Fz = fmaf(hs, nzv, B.Gz);
       const float rr = at(PL(aux, A_RR), node);
       const float rb = at(PL(aux, A_RB), node);
       const float rho = rr + rb;
+      interface_force(B, kap, mag, nxv, nyv, nzv, rho, Fx, Fy, Fz);
       const float irho = rcp(rho);
       const float ux = fmaf(0.5f, Fx, at(PL(aux, A_JX), node)) * irho;
       const float uy = fmaf(0.5f, Fy, at(PL(aux, A_JY), node)) * irho;
@@ -1098,13 +1110,10 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
                              nyv * (nxv * d[1][0] + nyv * d[1][1] + nzv * d[1][2]) +
                              nzv * (nxv * d[2][0] + nyv * d[2][1] + nzv * d[2][2]);
           kap = proj - div;
-          const float hs = 0.5f * B.sigma * kap * mag;
-          Fx = fmaf(hs, nxv, B.Gx);
-          Fy = fmaf(hs, nyv, B.Gy);
-          Fz = fmaf(hs, nzv, B.Gz);
           const float rr = pc_[kk][0];
           const float rb = pc_[kk][1];
           const float rho = rr + rb;
+          interface_force(B, kap, mag, nxv, nyv, nzv, rho, Fx, Fy, Fz);
           const float irho = rcp(rho);
           const float ux = fmaf(0.5f, Fx, pc_[kk][2]) * irho;
           const float uy = fmaf(0.5f, Fy, pc_[kk][3]) * irho;

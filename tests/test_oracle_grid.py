@@ -217,3 +217,23 @@ def test_shear_wave_viscosity():
     k = 2 * np.pi / n
     nu_meas = -np.log(amp / U) / (k * k * t)
     assert nu_meas == pytest.approx(nu, rel=0.01)
+
+
+def test_buoyancy_force_accelerates_a_uniform_fluid():
+    """Sec. IV.E's buoyancy force F = -(rho - rho_ref) g on a uniform, single
+    phase periodic fluid at rest: each step adds F to the momentum, so the
+    velocity of the fields (which include F/2, Eq. 11) is (k + 1/2) F / rho
+    after k steps, at every node."""
+    g = (1e-4, -2e-4, 3e-5)
+    rho, rho_ref, k = 0.8, 0.3, 5
+    P = O.Params(nx=6, ny=5, nz=4, rho0_r=1.0, rho0_b=0.5, alpha_r=WL.ALPHA_LIGHT,
+                 alpha_b=WL.ALPHA_LIGHT, nu_r=0.1, nu_b=0.1, sigma=0.01, beta=0.7,
+                 gravity=g, rho_ref=rho_ref)
+    shape = (4, 5, 6)
+    f = O.init(P, np.full(shape, rho), np.zeros(shape), np.zeros((3,) + shape))
+    O.step(P, f, k)
+    F = O.fields(P, f)
+    for a, name in enumerate(("ux", "uy", "uz")):
+        expect = (k + 0.5) * (-(rho - rho_ref) * g[a]) / rho
+        assert np.allclose(F[name], expect, rtol=1e-12, atol=1e-18), name
+        assert np.allclose(F["F" + name[1]], -(rho - rho_ref) * g[a], rtol=1e-12)

@@ -58,6 +58,8 @@ class Box:
     walls: int = 0
     model: int = 3        # equilibrium family of Table I: 0 A, 1 B, 2 C, 3 D
     use_q: int = 1        # correction term Q of Eq. (65)
+    gravity: Tuple[float, float, float] = (0.0, 0.0, 0.0)   # buoyancy -(rho - rho_ref) g
+    rho_ref: float = 0.0
 
     @property
     def shape(self):
@@ -286,6 +288,53 @@ def head_on_collision(nx: int = 768, ny: int = 384, nz: int = 384, R: float = 48
     cs = [(nx / 2.0 - 2 * R, cy, cz), (nx / 2.0 + 2 * R, cy, cz)]
     rr, rb, u = droplet_fields(box, cs, [R, R], u_drop=[(U, 0, 0), (-U, 0, 0)])
     return Workload("head_on_collision", box, rr, rb, u, steps=steps, centres=cs, radii=[R, R])
+
+
+def rayleigh_taylor(W: int = 128, At: float = 0.5, Re: Optional[float] = 1024.0,
+                    sqrt_wg: float = 0.04, beta: float = 0.7, model: int = 3,
+                    steps: int = 16000) -> Workload:
+    """Single-mode Rayleigh-Taylor instability in 3D (Sec. IV.E).
+
+    W x W x 4W nodes, solid layers at z = 0 and z = 4W - 1, periodic in x and
+    y.  Heavy (red) and light (blue) phases of Atwood number At (density
+    ratio (1 + At)/(1 - At), light density 1), equal kinematic viscosities
+    nu = sqrt(W g) W / Re (Re = None: nu = 0), no interfacial tension,
+    buoyancy -(rho - (rho_r^0 + rho_b^0)/2) g with g = (0, 0, -g) and
+    sqrt(W g) = sqrt_wg.  The interface lies at the mid-height plus
+    h(x, y) = 0.05 W (cos 2 pi x / W + cos 2 pi y / W).  With g = (0, 0, -g)
+    the printed force accelerates the heavy phase toward +z, so the heavy
+    phase fills the side below the interface: the unstable arrangement.
+    Time unit: sqrt(W / g) steps."""
+    gamma = (1.0 + At) / (1.0 - At)
+    rho_l, rho_h = 1.0, gamma
+    g = sqrt_wg ** 2 / W
+    nu = 0.0 if Re is None else sqrt_wg * W / Re
+    nz = 4 * W
+    box = Box(nx=W, ny=W, nz=nz, rho0_r=rho_h, rho0_b=rho_l, alpha_r=alpha_heavy(gamma),
+              alpha_b=ALPHA_LIGHT, nu_r=nu, nu_b=nu, sigma=0.0, beta=beta, walls=2,
+              model=model, gravity=(0.0, 0.0, -g), rho_ref=0.5 * (rho_h + rho_l))
+    x = np.arange(W)
+    h = 0.05 * W * (np.cos(2.0 * np.pi * x / W)[None, :] + np.cos(2.0 * np.pi * x / W)[:, None])
+    zi = (nz - 1) / 2.0 + h                       # [y, x]
+    z = np.arange(nz, dtype=np.float64)[:, None, None]
+    heavy = z < zi[None, :, :]
+    rho_r = np.where(heavy, rho_h, 0.0).astype(np.float32)
+    rho_b = np.where(heavy, 0.0, rho_l).astype(np.float32)
+    u = np.zeros((3,) + box.shape, dtype=np.float32)
+    return Workload("rayleigh_taylor_%d" % W, box, rho_r, rho_b, u, steps=steps)
+
+
+def interface_height(phi: np.ndarray, x: int, y: int) -> float:
+    """Height z of the phi = 0 crossing in column (x, y), the crossing nearest
+    to the box's mid-height (linear interpolation)."""
+    col = phi[:, y, x]
+    nz = col.shape[0]
+    s = np.sign(col)
+    idx = np.nonzero(s[1:] * s[:-1] < 0)[0]
+    if len(idx) == 0:
+        return float("nan")
+    k = idx[np.argmin(np.abs(idx - nz / 2.0))]
+    return float(k + col[k] / (col[k] - col[k + 1]))
 
 
 def layered_channel(case: str, a: int = 8, b: int = 16, nu: float = 0.02,
