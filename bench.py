@@ -13,7 +13,9 @@ recorded on the launch stream during the timed region) and the FP64 CPU
 oracle timed on a bounded sample of the same workload.  `forms` reports, on
 the same workload and step counts, the FP16/BF16-shifted and mass-exact FP32
 storage (with their difference to the FP32 run as a proxy error), the
-96-box batched workload and the 32^3 static droplet.  The timed region
+96-box batched workload, the 32^3 static droplet, the Rayleigh-Taylor case
+at the paper's size (Models D and A) and the translating droplet's
+deformation per equilibrium model.  The timed region
 launches every kernel directly (HIP events around each launch); after it,
 `graph_mlups` times the same update as replays of the captured two-step
 graph that cglbm_step uses by default.
@@ -28,6 +30,8 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+
+import workloads as WL  # noqa: E402  (seeded inputs; numpy only)
 
 HBM_PEAK_GBS = 8000.0
 GRAPH_STEPS = 500   # steps of the graph-replay run after the timed region
@@ -91,7 +95,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--size", type=int, default=256, help="box edge (default 256)")
     ap.add_argument("--storage", default="fp32", choices=sorted(STORAGES))
-    ap.add_argument("--forms", default="fp16,bf16,fp32x,batched,small",
+    ap.add_argument("--forms", default="fp16,bf16,fp32x,batched,small,rti,galilean",
                     help="extra forms on the same workload ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -204,6 +208,82 @@ def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=False):
     return out
 
 
+def rti_form(W=128, T_list=(1.0, 2.0, 3.0, 4.0)):
+    """Single-mode Rayleigh-Taylor instability at the paper's size (W = 128,
+    W x W x 4W, At = 0.5, Re = 1024), Models D and A: interface heights / W
+    of the spike (x = y = 0), bubble (x = y = W/2) and saddle (x = 0,
+    y = W/2) columns at T = t (g/W)^(1/2), and the throughput of the run."""
+    import torch
+    import paper_2309_07801_amd as pkg
+    out = {"workload": "Rayleigh-Taylor %dx%dx%d, At 0.5, Re 1024, walls at z" % (W, W, 4 * W)}
+    for model in (3, 0):
+        w = WL.rayleigh_taylor(W=W, model=model)
+        tu = np.sqrt(W / -w.box.gravity[2])
+        sim = pkg.Simulation([pkg.box_params_of(w.box)], [w.rho_r], [w.rho_b], [w.u])
+        sim.autotune(reps=2)
+        hist, done, t_run = [], 0, 0.0
+        for T in T_list:
+            n = int(round(T * tu))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.step(n - done)
+            torch.cuda.synchronize()
+            t_run += time.perf_counter() - t0
+            done = n
+            phi = sim.moments(0, ("phi",))["phi"].cpu().numpy()
+            hist.append([T] + [round(WL.interface_height(phi, x, y) / W, 4)
+                               for x, y in ((0, 0), (W // 2, W // 2), (0, W // 2))])
+        d = sim.reduce()
+        out["model_" + "ABCD"[model]] = {
+            "mlups": round(w.box.fluid_nodes() * done / t_run / 1e6, 1), "steps": done,
+            "schedule": ("fused", "three kernels")[sim.schedule()],
+            "T_spike_bubble_saddle": hist, "nonfinite": int(d[0, 12])}
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    return out
+
+
+def galilean_form(steps=20000):
+    """A droplet carried by a uniform flow U = 0.05 through a periodic
+    64x48x48 box (density ratio 3, mu_r = mu_b = 0.075, sigma 4.4e-3,
+    R = 12): deformation (l_max - l_min)/(l_max + l_min) of the inertia
+    tensor of the red region after `steps` steps, per equilibrium model."""
+    import dataclasses
+    import paper_2309_07801_amd as pkg
+    n, R, U, mu = (64, 48, 48), 12.0, 0.05, 0.075
+    c = tuple((v - 1) / 2.0 for v in n)
+    out = {"workload": "translating droplet 64x48x48, U 0.05, density ratio 3", "steps": steps}
+    for model, q, label in ((0, 1, "A"), (1, 1, "B"), (2, 1, "C"), (3, 1, "D"), (3, 0, "D_without_Q")):
+        box = dataclasses.replace(WL.two_phase_box(n, 3.0, 3.0, 1.0, 4.4e-3, 0.7), nu_r=mu / 3.0,
+                                  nu_b=mu, model=model, use_q=q)
+        rr, rb, u = WL.droplet_fields(box, [c], [R], u_carrier=(U, 0.0, 0.0))
+        sim = pkg.Simulation([pkg.box_params_of(box)], [rr], [rb], [u])
+        sim.step(steps)
+        phi = sim.moments(0, ("phi",))["phi"].double().cpu().numpy()
+        out[label] = round(deformation(phi), 4)
+        sim.close()
+    return out
+
+
+def deformation(phi):
+    """(l_max - l_min)/(l_max + l_min) of the inertia tensor of the red region
+    (weights (1 + phi)/2) about its periodic centroid."""
+    wgt = np.clip((1.0 + phi) / 2.0, 0.0, 1.0)
+    coords = []
+    for a, n in zip((2, 1, 0), (phi.shape[2], phi.shape[1], phi.shape[0])):
+        shape = [1, 1, 1]
+        shape[a] = n
+        ang = 2.0 * np.pi * np.arange(n) / n
+        cen = (np.arctan2((wgt * np.sin(ang).reshape(shape)).sum(),
+                          (wgt * np.cos(ang).reshape(shape)).sum()) % (2.0 * np.pi)) * n / (2.0 * np.pi)
+        d = (np.arange(n) - cen + n / 2.0) % n - n / 2.0
+        coords.append(d.reshape(shape))
+    M = np.array([[(wgt * ci * cj).sum() for cj in coords] for ci in coords])
+    ev = np.linalg.eigvalsh(M)
+    return float((ev[-1] - ev[0]) / (ev[-1] + ev[0]))
+
+
 def proxy_errors(g, ref, u_ref):
     """Difference of a run to the FP32 run after the same steps (the survey's
     proxy for full-size runs the oracle cannot afford)."""
@@ -222,7 +302,6 @@ def main():
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
-    import workloads as WL
 
     if args.copy_probe:
         copy_probe()
@@ -318,6 +397,10 @@ def main():
                               "schedule": r["schedule"],
                               "ms_per_step": round(r["ms_per_step"], 4),
                               "mass_drift": r["mass_drift"], "nonfinite": r["nonfinite"]}
+        elif f == "rti":
+            forms["rti"] = rti_form()
+        elif f == "galilean":
+            forms["galilean"] = galilean_form()
     if forms:
         line["forms"] = forms
     if not args.no_cpu_baseline:
