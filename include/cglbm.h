@@ -74,15 +74,17 @@ typedef enum {
  * solid layers at z = 0 and z = nz-1 (full-way bounce-back); other axes are
  * periodic.  sigma: interfacial tension of the CSF force (Eq. 15); beta:
  * recolouring parameter (Eq. 19); omega_bulk: omega_2 of Eq. (25);
- * omega_hi: omega_0 and omega_3..omega_10 of Eq. (25) -- only 1.0 is built
- * (the choice of the paper, Sec. III.E), anything else gives
- * CGLBM_EUNSUPPORTED; body_force: constant force density added to the CSF
+ * omega_hi: omega_0 and omega_3..omega_10 of Eq. (25), each in (0, 2] (1 is
+ * the paper's choice, Sec. III.E; other values relax every central moment
+ * of the pulled distribution, a slower path of the three-kernel schedule);
+ * body_force: constant force density added to the CSF
  * force; gravity, rho_ref: the buoyancy force -(rho - rho_ref) gravity of the
  * Rayleigh-Taylor case (Sec. IV.E), also added (zero gravity disables it);
  * model: a cglbm_model; q_correction: 1 adds the correction term Q of
  * Eq. (65) to the second-order relaxation, 0 omits it.  Model D with the
- * correction runs the fused schedule; as soon as one box uses another model
- * or omits the correction, every step of the handle runs the three-kernel
+ * correction and unit higher-order rates runs the fused schedule; as soon as
+ * one box uses another model, omits the correction or sets another rate,
+ * every step of the handle runs the three-kernel
  * schedule (same update for the Model D boxes, bit for bit). */
 typedef struct {
   int32_t nx, ny, nz;

@@ -84,6 +84,7 @@ def box_params_of(box) -> BoxParams:
     return box_params(box.nx, box.ny, box.nz, box.rho0_r, box.rho0_b, box.alpha_r, box.alpha_b,
                       box.nu_r, box.nu_b, box.sigma, box.beta, getattr(box, "omega_bulk", 1.0),
                       getattr(box, "body_force", (0.0, 0.0, 0.0)), getattr(box, "walls", 0),
+                      omega_hi=getattr(box, "omega_hi", (1.0,) * 9),
                       model=getattr(box, "model", MODEL_D),
                       q_correction=getattr(box, "use_q", 1),
                       gravity=getattr(box, "gravity", (0.0, 0.0, 0.0)),

@@ -79,7 +79,8 @@ int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
 // Kernels by storage format (index = cglbm_storage).
 using PullFn = void (*)(const BoxDev *, const int32_t *, void *, void *, float *, int64_t, int);
-using CollideFn = void (*)(const BoxDev *, const int32_t *, float *, void *, int64_t);
+using CollideFn = void (*)(const BoxDev *, const int32_t *, float *, const void *, void *,
+                          int64_t);
 using InitFn = void (*)(const BoxDev *, const int32_t *, const float *, const float *,
                         const float *, void *, int64_t, uint64_t, float);
 const PullFn kPull[4] = {k_pull<StoreF32>, k_pull<StoreF16>, k_pull<StoreBF16>, k_pull<StoreF32X>};
@@ -150,9 +151,8 @@ int validate(int32_t n_boxes, const cglbm_box_params *boxes, int32_t storage) {
     if (!(P.omega_bulk > 0.0 && P.omega_bulk < 2.0))
       return fail(CGLBM_EINVAL, "box %d: omega_bulk must lie in (0, 2)", b);
     for (int k = 0; k < 9; ++k)
-      if (P.omega_hi[k] != 1.0)
-        return fail(CGLBM_EUNSUPPORTED,
-                    "box %d: omega_hi[%d] = %g; only unit higher-order rates are built", b, k,
+      if (!(P.omega_hi[k] > 0.0 && P.omega_hi[k] <= 2.0))
+        return fail(CGLBM_EINVAL, "box %d: omega_hi[%d] = %g must lie in (0, 2]", b, k,
                     P.omega_hi[k]);
     for (int k = 0; k < 3; ++k)
       if (!std::isfinite(P.body_force[k]))
@@ -209,7 +209,12 @@ void build_layout(int32_t n_boxes, const cglbm_box_params *boxes, Layout &L) {
     B.rho_ref = (float)P.rho_ref;
     B.model = P.model;
     B.qcorr = P.q_correction;
-    if (P.model != CGLBM_MODEL_D || !P.q_correction) L.general = true;
+    B.full_rates = 0;
+    for (int k = 0; k < 9; ++k) {
+      B.omh[k] = (float)P.omega_hi[k];
+      if (P.omega_hi[k] != 1.0) B.full_rates = 1;
+    }
+    if (P.model != CGLBM_MODEL_D || !P.q_correction || B.full_rates) L.general = true;
     {
       // pure-phase rest equilibrium of each colour: w_i rho_k^0 (c_s^k)^2 / c_s^2
       const double w[4] = {8.0 / 27.0, 2.0 / 27.0, 1.0 / 54.0, 1.0 / 216.0};
@@ -356,7 +361,8 @@ int select_variant(cglbm_handle *h, int v, hipStream_t s) {
 
 int launch_collide(cglbm_handle *h, hipStream_t s) {
   hipLaunchKernelGGL(kCollide[h->storage], dim3(h->L.nblk_pad), dim3(kBlock), 0, s, h->d_boxes,
-                     h->d_blk_box, h->aux, h->pop[1 - h->cur], h->L.total);
+                     h->d_blk_box, h->aux, (const void *)h->pop[h->cur], h->pop[1 - h->cur],
+                     h->L.total);
   return CGLBM_OK;
 }
 

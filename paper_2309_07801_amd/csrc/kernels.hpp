@@ -51,6 +51,8 @@ struct BoxDev {
   float shift[2][4];    // storage shift by colour and speed class |c|^2
   float bgx, bgy, bgz;  // g of the buoyancy force -(rho - rho_ref) g
   float rho_ref;
+  float omh[9];         // omega_0, omega_3..omega_10 of Eq. (25)
+  int32_t full_rates;   // 1: some higher-order rate differs from 1
   int32_t model;        // equilibrium family of Table I (MODEL_A..MODEL_D)
   int32_t qcorr;        // 1: correction term Q of Eq. (65) in the collision
 };
@@ -579,6 +581,51 @@ struct NodeIn {
   float nx, ny, nz, Fx, Fy, Fz, Qx, Qy, Qz;
 };
 
+// Back-transform of post-collision central moments k about u into
+// populations (three passes of 1D triplet maps, z, y, x) with the
+// recolouring of Eqs. (18)-(19) folded into the last pass: each direction's
+// pair goes out through emit(i, f_r, f_b).
+template <class Emit>
+__device__ __forceinline__ void emit_recoloured(const BoxDev &B, const float (&k)[27], float ux,
+                                                float uy, float uz, float rr, float rb,
+                                                float irho, float p, float nx, float ny,
+                                                float nz, Emit &&emit) {
+  const float cr = rr * irho, cb = rb * irho;
+  const float s = B.beta * cr * cb * p;
+  const float Rx = s * nx, Ry = s * ny, Rz = s * nz;
+  float g[3][3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+      cm_to_pop_1d(k[a + 3 * b], k[a + 3 * b + 9], k[a + 3 * b + 18], uz, g[a][b][0], g[a][b][1],
+                   g[a][b][2]);
+  float h[3][3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int cz = 0; cz < 3; ++cz)
+      cm_to_pop_1d(g[a][0][cz], g[a][1][cz], g[a][2][cz], uy, h[a][0][cz], h[a][1][cz],
+                   h[a][2][cz]);
+#pragma unroll
+  for (int cz = 0; cz < 3; ++cz)
+#pragma unroll
+    for (int cy = 0; cy < 3; ++cy) {
+      float fx[3];
+      cm_to_pop_1d(h[0][cy][cz], h[1][cy][cz], h[2][cy][cz], ux, fx[0], fx[1], fx[2]);
+#pragma unroll
+      for (int cx = 0; cx < 3; ++cx) {
+        const int i = dir_of(cx - 1, cy - 1, cz - 1);
+        const float cR = (kCX[i] ? (kCX[i] > 0 ? Rx : -Rx) : 0.f) +
+                         (kCY[i] ? (kCY[i] > 0 ? Ry : -Ry) : 0.f) +
+                         (kCZ[i] ? (kCZ[i] > 0 ? Rz : -Rz) : 0.f);
+        const float d = 3.0f * weight(i) * cR;
+        emit(i, fmaf(cr, fx[cx], d), fmaf(cb, fx[cx], -d));
+      }
+    }
+}
+
+
 // Emits each direction's recoloured pair through emit(i, f_r, f_b) as soon as
 // its x-triplet of the back-transform is done, so that the 54 outputs never
 // have to be live at once.  GENERAL: the box's equilibrium family and
@@ -622,40 +669,146 @@ __device__ __forceinline__ void collide_node(const BoxDev &B, const NodeIn &in, 
                   r1 * kxz, r1 * kyz, k);
   else
     model_d_moments(rho, p, in.Fx, in.Fy, in.Fz, sxx, syy, szz, r1 * kxy, r1 * kxz, r1 * kyz, k);
-  // recolouring (Eqs. 18-19) folded into the last pass of the back-transform
-  const float cr = in.rr * irho, cb = in.rb * irho;
-  const float s = B.beta * cr * cb * p;
-  const float Rx = s * in.nx, Ry = s * in.ny, Rz = s * in.nz;
-  float g[3][3][3];
+  emit_recoloured(B, k, ux, uy, uz, in.rr, in.rb, irho, p, in.nx, in.ny, in.nz, emit);
+}
+
+// Populations -> central moments about u along one axis: (f_-, f_0, f_+) ->
+// (k_0, k_1, k_2) = sum f (c - u)^n, n = 0, 1, 2 (Eq. 24 on D1Q3).
+__device__ __forceinline__ void pop_to_cm_1d(float fm, float f0, float fp, float u, float &k0,
+                                             float &k1, float &k2) {
+  k0 = fm + f0 + fp;
+  const float m1 = fp - fm, m2 = fp + fm;
+  k1 = m1 - u * k0;
+  k2 = m2 - 2.0f * u * m1 + u * u * k0;
+}
+
+// Collision with all relaxation rates of Eq. (25) (omega_0, omega_3..10 of
+// the box, omega_1 from the viscosity, omega_2 the bulk rate): the 27
+// central moments of the pulled total distribution f about u (x, y and z
+// passes of pop_to_cm_1d), relaxed toward the equilibrium moments of the
+// box's family with the forcing and correction terms, then back-transformed
+// and recoloured.
+template <class Emit>
+__device__ __forceinline__ void collide_full(const BoxDev &B, const NodeIn &in,
+                                             const float (&f)[27], Emit &&emit) {
+  const float rho = in.rr + in.rb;
+  const float irho = rcp(rho);
+  const float ux = fmaf(0.5f, in.Fx, in.jx) * irho;
+  const float uy = fmaf(0.5f, in.Fy, in.jy) * irho;
+  const float uz = fmaf(0.5f, in.Fz, in.jz) * irho;
+  const float p = in.rr * B.cs2r + in.rb * B.cs2b;
+  const float sr = in.rr * B.ir0r, sb = in.rb * B.ir0b;
+  const float phi = (sr - sb) * rcp(sr + sb);
+  const float nu = 0.5f * ((1.0f + phi) * B.nu_r + (1.0f - phi) * B.nu_b);
+  const float w1 = p * rcp(fmaf(rho, nu, 0.5f * p));
+  const float w2 = B.omega2;
+  const float w0 = B.omh[0], w3 = B.omh[1], w4 = B.omh[2], w5 = B.omh[3], w6 = B.omh[4],
+              w7 = B.omh[5], w8 = B.omh[6], w9 = B.omh[7], w10 = B.omh[8];
+  const float Qx = B.qcorr ? in.Qx : 0.f, Qy = B.qcorr ? in.Qy : 0.f, Qz = B.qcorr ? in.Qz : 0.f;
+  // central moments of f, k[a + 3b + 9c] = sum f (cx-ux)^a (cy-uy)^b (cz-uz)^c
+  float g[3][3][3], h[3][3][3], k[27];
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
+  for (int cy = 0; cy < 3; ++cy)
 #pragma unroll
-    for (int b = 0; b < 3; ++b)
-      cm_to_pop_1d(k[a + 3 * b], k[a + 3 * b + 9], k[a + 3 * b + 18], uz, g[a][b][0], g[a][b][1],
-                   g[a][b][2]);
-  float h[3][3][3];
+    for (int cz = 0; cz < 3; ++cz)
+      pop_to_cm_1d(f[dir_of(-1, cy - 1, cz - 1)], f[dir_of(0, cy - 1, cz - 1)],
+                   f[dir_of(1, cy - 1, cz - 1)], ux, g[0][cy][cz], g[1][cy][cz], g[2][cy][cz]);
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int cz = 0; cz < 3; ++cz)
-      cm_to_pop_1d(g[a][0][cz], g[a][1][cz], g[a][2][cz], uy, h[a][0][cz], h[a][1][cz],
+      pop_to_cm_1d(g[a][0][cz], g[a][1][cz], g[a][2][cz], uy, h[a][0][cz], h[a][1][cz],
                    h[a][2][cz]);
 #pragma unroll
-  for (int cz = 0; cz < 3; ++cz)
+  for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int cy = 0; cy < 3; ++cy) {
-      float fx[3];
-      cm_to_pop_1d(h[0][cy][cz], h[1][cy][cz], h[2][cy][cz], ux, fx[0], fx[1], fx[2]);
+    for (int b = 0; b < 3; ++b)
+      pop_to_cm_1d(h[a][b][0], h[a][b][1], h[a][b][2], uz, k[a + 3 * b], k[a + 3 * b + 9],
+                   k[a + 3 * b + 18]);
+  float e[27];  // equilibrium central moments of the box's family
+  model_moments(B.model, rho, p, ux, uy, uz, 0.f, 0.f, 0.f, p, p, p, 0.f, 0.f, 0.f, e);
+#define K_(a, b, c) k[(a) + 3 * (b) + 9 * (c)]
+#define E_(a, b, c) e[(a) + 3 * (b) + 9 * (c)]
+#define S_(a, b, c) ks[(a) + 3 * (b) + 9 * (c)]
+  float ks[27];
+  S_(0, 0, 0) = rho;
+  S_(1, 0, 0) = (1.0f - w0) * K_(1, 0, 0) + (1.0f - 0.5f * w0) * in.Fx;
+  S_(0, 1, 0) = (1.0f - w0) * K_(0, 1, 0) + (1.0f - 0.5f * w0) * in.Fy;
+  S_(0, 0, 1) = (1.0f - w0) * K_(0, 0, 1) + (1.0f - 0.5f * w0) * in.Fz;
+  S_(1, 1, 0) = (1.0f - w1) * K_(1, 1, 0);
+  S_(1, 0, 1) = (1.0f - w1) * K_(1, 0, 1);
+  S_(0, 1, 1) = (1.0f - w1) * K_(0, 1, 1);
+  {
+    const float kxx = K_(2, 0, 0), kyy = K_(0, 2, 0), kzz = K_(0, 0, 2);
+    const float exx = E_(2, 0, 0), eyy = E_(0, 2, 0), ezz = E_(0, 0, 2);
+    const float A = (1.0f - w1) * (kxx - kyy) + w1 * (exx - eyy) + (1.0f - 0.5f * w1) * (Qx - Qy);
+    const float Bd = (1.0f - w1) * (kxx - kzz) + w1 * (exx - ezz) + (1.0f - 0.5f * w1) * (Qx - Qz);
+    const float T = (1.0f - w2) * (kxx + kyy + kzz) + w2 * (exx + eyy + ezz) +
+                    (1.0f - 0.5f * w2) * (Qx + Qy + Qz);
+    const float third = 1.0f / 3.0f;
+    S_(2, 0, 0) = (A + Bd + T) * third;
+    S_(0, 2, 0) = (T - 2.0f * A + Bd) * third;
+    S_(0, 0, 2) = (T + A - 2.0f * Bd) * third;
+  }
+  {
+    // third order: sums with omega_3 (and the force), differences with omega_4
+    const int pa[3] = {1 + 3 * 2, 2 + 3 * 1, 2 + 9 * 1};  // k120, k210, k201
+    const int pb[3] = {1 + 9 * 2, 3 * 1 + 9 * 2, 3 * 2 + 9 * 1};  // k102, k012, k021
+    const float Fd[3] = {in.Fx, in.Fy, in.Fz};
 #pragma unroll
-      for (int cx = 0; cx < 3; ++cx) {
-        const int i = dir_of(cx - 1, cy - 1, cz - 1);
-        const float cR = (kCX[i] ? (kCX[i] > 0 ? Rx : -Rx) : 0.f) +
-                         (kCY[i] ? (kCY[i] > 0 ? Ry : -Ry) : 0.f) +
-                         (kCZ[i] ? (kCZ[i] > 0 ? Rz : -Rz) : 0.f);
-        const float d = 3.0f * weight(i) * cR;
-        emit(i, fmaf(cr, fx[cx], d), fmaf(cb, fx[cx], -d));
-      }
+    for (int d = 0; d < 3; ++d) {
+      const float S3 = (1.0f - w3) * (k[pa[d]] + k[pb[d]]) + w3 * (e[pa[d]] + e[pb[d]]) +
+                       2.0f * (1.0f - 0.5f * w3) * Fd[d] * kCs2;
+      const float D3 = (1.0f - w4) * (k[pa[d]] - k[pb[d]]) + w4 * (e[pa[d]] - e[pb[d]]);
+      ks[pa[d]] = 0.5f * (S3 + D3);
+      ks[pb[d]] = 0.5f * (S3 - D3);
     }
+  }
+  S_(1, 1, 1) = (1.0f - w5) * K_(1, 1, 1) + w5 * E_(1, 1, 1);
+  {
+    const float a = K_(2, 2, 0), b = K_(2, 0, 2), c = K_(0, 2, 2);
+    const float ea = E_(2, 2, 0), eb = E_(2, 0, 2), ec = E_(0, 2, 2);
+    const float X = (1.0f - w6) * (a - 2.0f * b + c) + w6 * (ea - 2.0f * eb + ec);
+    const float Y = (1.0f - w6) * (a + b - 2.0f * c) + w6 * (ea + eb - 2.0f * ec);
+    const float Z = (1.0f - w7) * (a + b + c) + w7 * (ea + eb + ec);
+    const float third = 1.0f / 3.0f;
+    S_(2, 2, 0) = (X + Y + Z) * third;
+    S_(2, 0, 2) = (Z - X) * third;
+    S_(0, 2, 2) = (Z - Y) * third;
+  }
+  S_(2, 1, 1) = (1.0f - w8) * K_(2, 1, 1) + w8 * E_(2, 1, 1);
+  S_(1, 2, 1) = (1.0f - w8) * K_(1, 2, 1) + w8 * E_(1, 2, 1);
+  S_(1, 1, 2) = (1.0f - w8) * K_(1, 1, 2) + w8 * E_(1, 1, 2);
+  S_(1, 2, 2) = (1.0f - w9) * K_(1, 2, 2) + w9 * E_(1, 2, 2) + (1.0f - 0.5f * w9) * in.Fx * kCs4;
+  S_(2, 1, 2) = (1.0f - w9) * K_(2, 1, 2) + w9 * E_(2, 1, 2) + (1.0f - 0.5f * w9) * in.Fy * kCs4;
+  S_(2, 2, 1) = (1.0f - w9) * K_(2, 2, 1) + w9 * E_(2, 2, 1) + (1.0f - 0.5f * w9) * in.Fz * kCs4;
+  S_(2, 2, 2) = (1.0f - w10) * K_(2, 2, 2) + w10 * E_(2, 2, 2);
+#undef K_
+#undef E_
+#undef S_
+  emit_recoloured(B, ks, ux, uy, uz, in.rr, in.rb, irho, p, in.nx, in.ny, in.nz, emit);
+}
+
+// Pulled total distribution f_i(x) = sum over colours of stored_i(x - c_i),
+// decoded from storage format S (the rest populations of the mass-exact
+// formats come from their FP64 planes at x).
+template <class S>
+__device__ __forceinline__ void pull_total(const BoxDev &B, const void *src_, int64_t plane, int x,
+                                           int y, int z, uint32_t node, float (&f)[27]) {
+  const Pops<S> src(const_cast<void *>(src_), plane);
+  const int nx = B.nx, ny = B.ny, nz = B.nz;
+  const int xs[3] = {wrap_once(x + 1, nx), x, wrap_once(x - 1, nx)};
+  const int ys[3] = {wrap_once(y + 1, ny), y, wrap_once(y - 1, ny)};
+  const int zs[3] = {wrap_once(z + 1, nz), z, wrap_once(z - 1, nz)};
+  constexpr int i0 = S::kExact ? 1 : 0;
+#pragma unroll
+  for (int i = i0; i < kQ; ++i) {
+    const uint32_t s = (uint32_t)B.base + (uint32_t)xs[kCX[i] + 1] +
+                       (uint32_t)nx * ((uint32_t)ys[kCY[i] + 1] + (uint32_t)ny * (uint32_t)zs[kCZ[i] + 1]);
+    f[i] = (S::dec(ld<S>(&at(src.mvp(0, i), s))) + pop_shift<S>(B, 0, i)) +
+           (S::dec(ld<S>(&at(src.mvp(1, i), s))) + pop_shift<S>(B, 1, i));
+  }
+  if (S::kExact) f[0] = (float)(at(src.restp(0), node) + at(src.restp(1), node));
 }
 
 __device__ __forceinline__ NodeIn load_node_in(const float *__restrict__ aux, int64_t plane,
@@ -724,6 +877,7 @@ template <class S>
 __global__ __launch_bounds__(kBlock) void k_collide(const BoxDev *__restrict__ boxes,
                                                     const int32_t *__restrict__ blk_box,
                                                     float *__restrict__ aux,
+                                                    const void *__restrict__ src_,
                                                     void *__restrict__ dst_, int64_t plane) {
   const uint32_t lb = xcd_block();
   const int b = blk_box[lb];
@@ -740,7 +894,15 @@ __global__ __launch_bounds__(kBlock) void k_collide(const BoxDev *__restrict__ b
   const NodeIn in = load_node_in(aux, plane, node);
   const Pops<S> dst(dst_, plane);
   PopWriter<S> w(dst, B, node);
-  collide_node<true>(B, in, w);
+  if (B.full_rates) {
+    // non-unit higher-order rates need every central moment: pull again
+    float f[27];
+    const int x = (int)(l - yz * (uint32_t)B.nx);
+    pull_total<S>(B, src_, plane, x, y, z, node, f);
+    collide_full(B, in, f, w);
+  } else {
+    collide_node<true>(B, in, w);
+  }
   if (S::kExact) {
     const double *r64 = aux_rho64(aux, plane);
     w.finish(at(r64, node), at(r64 + plane, node));

@@ -12,7 +12,7 @@ def oracle_params(box: WL.Box, **kw) -> O.Params:
              alpha_r=box.alpha_r, alpha_b=box.alpha_b, nu_r=box.nu_r, nu_b=box.nu_b,
              sigma=box.sigma, beta=box.beta, walls=box.walls, body_force=tuple(box.body_force),
              model=box.model, use_q=box.use_q, gravity=tuple(box.gravity), rho_ref=box.rho_ref,
-             omega=(1.0, 1.0, box.omega_bulk) + (1.0,) * 8)
+             omega=(box.omega_hi[0], 1.0, box.omega_bulk) + tuple(box.omega_hi[1:]))
     d.update(kw)
     return O.Params(**d)
 

@@ -39,7 +39,8 @@ def test_query_sizes_layout():
 
 @pytest.mark.parametrize("field,value,code", [
     ("nx", 0, -1), ("walls", 4, -1), ("sigma", -1.0, -1), ("beta", float("nan"), -1),
-    ("omega_bulk", 2.0, -1), ("omega_hi", 1.2, -3), ("model", 4, -1), ("model", -1, -1),
+    ("omega_bulk", 2.0, -1), ("omega_hi", 2.5, -1), ("omega_hi", 0.0, -1), ("model", 4, -1),
+    ("model", -1, -1),
     ("q_correction", 2, -1)])
 def test_parameter_validation(field, value, code):
     b = WL.two_phase_box((8, 8, 8), 10.0, 1.0, 0.8, 0.01, 0.7)

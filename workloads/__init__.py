@@ -60,6 +60,7 @@ class Box:
     use_q: int = 1        # correction term Q of Eq. (65)
     gravity: Tuple[float, float, float] = (0.0, 0.0, 0.0)   # buoyancy -(rho - rho_ref) g
     rho_ref: float = 0.0
+    omega_hi: Tuple[float, ...] = (1.0,) * 9   # omega_0, omega_3..omega_10 of Eq. (25)
 
     @property
     def shape(self):
