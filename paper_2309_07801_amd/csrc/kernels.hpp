@@ -121,6 +121,13 @@ __device__ __forceinline__ void buf_st(float v, __amdgpu_buffer_rsrc_t r, uint32
 __device__ __forceinline__ void buf_st(uint16_t v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
   __builtin_amdgcn_raw_buffer_store_b16(v, r, (int)off, 0, kNonTemporal);
 }
+__device__ __forceinline__ void buf_st(uint32_t v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+  __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)off, 0, kNonTemporal);
+}
+__device__ __forceinline__ void buf_st(uint64_t v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)off, 0,
+                                        kNonTemporal);
+}
 __device__ __forceinline__ void buf_st(double v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)off, 0,
                                         kNonTemporal);
@@ -174,25 +181,42 @@ __device__ __forceinline__ bool is_solid(const BoxDev &B, int y, int z) {
 // population minus the pure-phase rest equilibrium of its colour,
 // s^k_i = w_i rho_k^0 (c_s^k)^2 / c_s^2, rounded to T (zero stays exact).
 // ---------------------------------------------------------------------------
-struct StoreF32 {
+// A direction's red and blue populations stream from and to the same node,
+// so they are stored as one pair word (red in the low half): one memory
+// access moves both.
+struct Pair32 {
+  using W = uint64_t;
+  __device__ static W pack(float r, float b) {
+    return (uint64_t)__builtin_bit_cast(uint32_t, r) | ((uint64_t)__builtin_bit_cast(uint32_t, b) << 32);
+  }
+  __device__ static float lo(W w) { return __builtin_bit_cast(float, (uint32_t)w); }
+  __device__ static float hi(W w) { return __builtin_bit_cast(float, (uint32_t)(w >> 32)); }
+};
+struct Pair16 {
+  using W = uint32_t;
+  __device__ static W pack(uint16_t r, uint16_t b) { return (uint32_t)r | ((uint32_t)b << 16); }
+  __device__ static uint16_t lo(W w) { return (uint16_t)w; }
+  __device__ static uint16_t hi(W w) { return (uint16_t)(w >> 16); }
+};
+struct StoreF32 : Pair32 {
   using T = float;
   static constexpr bool kExact = false, kShift = false;
   __device__ static T enc(float v) { return v; }
   __device__ static float dec(T g) { return g; }
 };
-struct StoreF32X {
+struct StoreF32X : Pair32 {
   using T = float;
   static constexpr bool kExact = true, kShift = false;
   __device__ static T enc(float v) { return v; }
   __device__ static float dec(T g) { return g; }
 };
-struct StoreF16 {
+struct StoreF16 : Pair16 {
   using T = uint16_t;
   static constexpr bool kExact = true, kShift = true;
   __device__ static T enc(float v) { return __builtin_bit_cast(uint16_t, (_Float16)v); }
   __device__ static float dec(T g) { return (float)__builtin_bit_cast(_Float16, g); }
 };
-struct StoreBF16 {
+struct StoreBF16 : Pair16 {
   using T = uint16_t;
   static constexpr bool kExact = true, kShift = true;
   // round to nearest even on the bit pattern; NaN kept quiet
@@ -206,20 +230,22 @@ struct StoreBF16 {
 
 __host__ __device__ inline int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
 
-// Views of one population buffer and of the FP64 aux planes.
+// Views of one population buffer: pair planes of the moving (mass-exact
+// formats) or of all directions, then (mass-exact formats) the FP64 rest
+// populations of the two colours.
 template <class S>
 struct Pops {
-  typename S::T *mv;
+  using W = typename S::W;
+  static constexpr int kPairs = S::kExact ? 26 : 27;
+  W *pw;
   double *rest;
   int64_t plane;
   __device__ Pops(void *base, int64_t plane_) : plane(plane_) {
-    mv = (typename S::T *)base;
-    rest = (double *)((char *)base + align256((S::kExact ? 52 : 54) * plane_ *
-                                               (int64_t)sizeof(typename S::T)));
+    pw = (W *)base;
+    rest = (double *)((char *)base + align256(kPairs * plane_ * (int64_t)sizeof(W)));
   }
-  __device__ typename S::T *mvp(int c, int i) const {
-    return mv + (int64_t)(S::kExact ? c * 26 + i - 1 : c * 27 + i) * plane;
-  }
+  __device__ static int slot(int i) { return S::kExact ? i - 1 : i; }
+  __device__ W *pair(int i) const { return pw + (int64_t)slot(i) * plane; }
   __device__ double *restp(int c) const { return rest + (int64_t)c * plane; }
 };
 
@@ -236,12 +262,12 @@ __device__ __forceinline__ float pop_shift(const BoxDev &B, int c, int i) {
   return S::dec(S::enc(B.shift[c][cls]));
 }
 
-template <class S>
-__device__ __forceinline__ typename S::T ld(const typename S::T *p) {
+template <class W>
+__device__ __forceinline__ W ld(const W *p) {
   return __builtin_nontemporal_load(p);
 }
-template <class S>
-__device__ __forceinline__ void st(typename S::T *p, typename S::T v) {
+template <class W>
+__device__ __forceinline__ void st(W *p, W v) {
   __builtin_nontemporal_store(v, p);
 }
 
@@ -280,13 +306,12 @@ __global__ __launch_bounds__(kBlock) void k_pull(const BoxDev *__restrict__ boxe
       row[a][c] = (uint32_t)B.base + (uint32_t)nx * ((uint32_t)ys[a] + (uint32_t)ny * (uint32_t)zs[c]);
   const uint32_t node = (uint32_t)(B.base + local);
 
-  typename S::T gr[kQ], gb[kQ];
+  typename S::W gw[kQ];
   constexpr int i0 = S::kExact ? 1 : 0;
 #pragma unroll
   for (int i = i0; i < kQ; ++i) {
     const uint32_t s = row[kCY[i] + 1][kCZ[i] + 1] + (uint32_t)xs[kCX[i] + 1];
-    gr[i] = ld<S>(&at(src.mvp(0, i), s));
-    gb[i] = ld<S>(&at(src.mvp(1, i), s));
+    gw[i] = ld(&at(src.pair(i), s));
   }
   double rr0 = 0.0, rb0 = 0.0;
   if (S::kExact) {
@@ -295,12 +320,9 @@ __global__ __launch_bounds__(kBlock) void k_pull(const BoxDev *__restrict__ boxe
   }
   if (is_solid(B, y, z)) {
     if (bounce) {
-      // the shift of direction i equals that of its opposite: copy raw values
+      // the shift of direction i equals that of its opposite: copy raw pairs
 #pragma unroll
-      for (int i = i0; i < kQ; ++i) {
-        st<S>(&at(dst.mvp(0, opposite(i)), node), gr[i]);
-        st<S>(&at(dst.mvp(1, opposite(i)), node), gb[i]);
-      }
+      for (int i = i0; i < kQ; ++i) st(&at(dst.pair(opposite(i)), node), gw[i]);
       if (S::kExact) {
         at(dst.restp(0), node) = rr0;
         at(dst.restp(1), node) = rb0;
@@ -320,8 +342,8 @@ __global__ __launch_bounds__(kBlock) void k_pull(const BoxDev *__restrict__ boxe
   double drr = rr0, drb = rb0;
 #pragma unroll
   for (int i = i0; i < kQ; ++i) {
-    const float vr = S::dec(gr[i]) + pop_shift<S>(B, 0, i);
-    const float vb = S::dec(gb[i]) + pop_shift<S>(B, 1, i);
+    const float vr = S::dec(S::lo(gw[i])) + pop_shift<S>(B, 0, i);
+    const float vb = S::dec(S::hi(gw[i])) + pop_shift<S>(B, 1, i);
     if (S::kExact) {
       drr += (double)vr;
       drb += (double)vb;
@@ -630,8 +652,15 @@ __device__ __forceinline__ void emit_recoloured(const BoxDev &B, const float (&k
 // its x-triplet of the back-transform is done, so that the 54 outputs never
 // have to be live at once.  GENERAL: the box's equilibrium family and
 // correction switch apply; otherwise Model D with the correction Q.
-template <bool GENERAL = false, class Emit>
-__device__ __forceinline__ void collide_node(const BoxDev &B, const NodeIn &in, Emit &&emit) {
+struct NoHook {
+  __device__ void operator()() const {}
+};
+
+// pre() runs after the central moments are built and before the first
+// population is emitted (the fused kernel issues the next slab's loads there).
+template <bool GENERAL = false, class Emit, class Pre = NoHook>
+__device__ __forceinline__ void collide_node(const BoxDev &B, const NodeIn &in, Emit &&emit,
+                                             Pre &&pre = Pre()) {
   const float rho = in.rr + in.rb;
   const float irho = rcp(rho);
   const float ux = fmaf(0.5f, in.Fx, in.jx) * irho;  // Eq. (11)
@@ -669,6 +698,7 @@ __device__ __forceinline__ void collide_node(const BoxDev &B, const NodeIn &in, 
                   r1 * kxz, r1 * kyz, k);
   else
     model_d_moments(rho, p, in.Fx, in.Fy, in.Fz, sxx, syy, szz, r1 * kxy, r1 * kxz, r1 * kyz, k);
+  pre();
   emit_recoloured(B, k, ux, uy, uz, in.rr, in.rb, irho, p, in.nx, in.ny, in.nz, emit);
 }
 
@@ -805,8 +835,8 @@ __device__ __forceinline__ void pull_total(const BoxDev &B, const void *src_, in
   for (int i = i0; i < kQ; ++i) {
     const uint32_t s = (uint32_t)B.base + (uint32_t)xs[kCX[i] + 1] +
                        (uint32_t)nx * ((uint32_t)ys[kCY[i] + 1] + (uint32_t)ny * (uint32_t)zs[kCZ[i] + 1]);
-    f[i] = (S::dec(ld<S>(&at(src.mvp(0, i), s))) + pop_shift<S>(B, 0, i)) +
-           (S::dec(ld<S>(&at(src.mvp(1, i), s))) + pop_shift<S>(B, 1, i));
+    const typename S::W w = ld(&at(src.pair(i), s));
+    f[i] = (S::dec(S::lo(w)) + pop_shift<S>(B, 0, i)) + (S::dec(S::hi(w)) + pop_shift<S>(B, 1, i));
   }
   if (S::kExact) f[0] = (float)(at(src.restp(0), node) + at(src.restp(1), node));
 }
@@ -853,11 +883,9 @@ struct PopWriter {
     if (S::kExact && i == 0) return;
     const float shr = pop_shift<S>(B, 0, i), shb = pop_shift<S>(B, 1, i);
     const typename S::T er = S::enc(fr - shr), eb = S::enc(fb - shb);
-    using T = typename S::T;
-    const int64_t pb = dst.plane * (int64_t)sizeof(T);
-    const uint32_t off = boff<T>(live, node);
-    buf_st(er, plane_rsrc(dst.mv, pb, S::kExact ? i - 1 : i), off);
-    buf_st(eb, plane_rsrc(dst.mv, pb, S::kExact ? 25 + i : 27 + i), off);
+    using W = typename S::W;
+    const int64_t pb = dst.plane * (int64_t)sizeof(W);
+    buf_st(S::pack(er, eb), plane_rsrc(dst.pw, pb, Pops<S>::slot(i)), boff<W>(live, node));
     if (S::kExact) {
       sr += (double)(S::dec(er) + shr);
       sb += (double)(S::dec(eb) + shb);
@@ -958,8 +986,7 @@ __global__ __launch_bounds__(kBlock) void k_init(const BoxDev *__restrict__ boxe
                        (uint32_t)B.nx * ((uint32_t)yd + (uint32_t)B.ny * (uint32_t)zd);
     const float shr = pop_shift<S>(B, 0, i), shb = pop_shift<S>(B, 1, i);
     const typename S::T er = S::enc(vr - shr), eb = S::enc(vb - shb);
-    st<S>(&at(dst.mvp(0, i), d), er);
-    st<S>(&at(dst.mvp(1, i), d), eb);
+    st(&at(dst.pair(i), d), S::pack(er, eb));
     sr += (double)(S::dec(er) + shr);
     sb += (double)(S::dec(eb) + shb);
   }
@@ -1104,8 +1131,36 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
       pc_[kk][4] = ldpl(aux, pl, A_JZ, node);
     }
   };
+  // inputs of the collision at the (clamped) tile point.  With 16-bit
+  // storage they are loaded one iteration ahead, inside the collision before
+  // its first store (measured faster); with 32-bit storage at the top of the
+  // iteration (the earlier issue measured slower there).
+  constexpr bool kPipeD = sizeof(typename S::T) == 2;
+  NodeIn din;
+  double d_rr = 0.0, d_rb = 0.0;
+  auto load_d = [&](int sl, int64_t pl) {
+    if (EXPORT) return;
+    const uint32_t node = (uint32_t)B.base + oxy + nxy * (uint32_t)wrap_any(sl, nz);
+    if (S::kExact) {
+      const double *r64 = aux_rho64(aux, pl);
+      d_rr = buf_ld_f64(plane_rsrc(r64, pl * 8, 0), node * 8u);
+      d_rb = buf_ld_f64(plane_rsrc(r64, pl * 8, 1), node * 8u);
+    }
+    din.rr = ldpl(aux, pl, A_RR, node);
+    din.rb = ldpl(aux, pl, A_RB, node);
+    din.jx = ldpl(aux, pl, A_JX, node);
+    din.jy = ldpl(aux, pl, A_JY, node);
+    din.jz = ldpl(aux, pl, A_JZ, node);
+    din.pxx = ldpl(aux, pl, A_PXX, node);
+    din.pyy = ldpl(aux, pl, A_PYY, node);
+    din.pzz = ldpl(aux, pl, A_PZZ, node);
+    din.pxy = ldpl(aux, pl, A_PXY, node);
+    din.pxz = ldpl(aux, pl, A_PXZ, node);
+    din.pyz = ldpl(aux, pl, A_PYZ, node);
+  };
   load_a(z0 - 3, plane_arg);
   load_c(z0 - 5, plane_arg);
+  if (kPipeD) load_d(z0 - 6, plane_arg);
   // as many stores as stage D issues, all discarded: on entry to the march
   // the loads above are then followed by the same count of memory
   // instructions as in every later iteration, so the waits for them are
@@ -1124,28 +1179,8 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
 
   for (int s = z0 - 3; s < z1 + 3; ++s) {
     const int64_t plane = opaque_i64(plane_arg);
+    if (!kPipeD) load_d(s - 3, plane);
     // inputs of the collision of slab s-3 at the (clamped) tile point
-    NodeIn din;
-    double d_rr = 0.0, d_rb = 0.0;
-    if (!EXPORT) {
-      const uint32_t node = (uint32_t)B.base + oxy + nxy * (uint32_t)wrap_any(s - 3, nz);
-      if (S::kExact) {
-        const double *r64 = aux_rho64(aux, plane);
-        d_rr = buf_ld_f64(plane_rsrc(r64, plane * 8, 0), node * 8u);
-        d_rb = buf_ld_f64(plane_rsrc(r64, plane * 8, 1), node * 8u);
-      }
-      din.rr = ldpl(aux, plane, A_RR, node);
-      din.rb = ldpl(aux, plane, A_RB, node);
-      din.jx = ldpl(aux, plane, A_JX, node);
-      din.jy = ldpl(aux, plane, A_JY, node);
-      din.jz = ldpl(aux, plane, A_JZ, node);
-      din.pxx = ldpl(aux, plane, A_PXX, node);
-      din.pyy = ldpl(aux, plane, A_PYY, node);
-      din.pzz = ldpl(aux, plane, A_PZZ, node);
-      din.pxy = ldpl(aux, plane, A_PXY, node);
-      din.pxz = ldpl(aux, plane, A_PXZ, node);
-      din.pyz = ldpl(aux, plane, A_PYZ, node);
-    }
     // ---- A: phase field of slab s (Eq. 14) ----
     {
       float *ph = s_phi[(s + 3) % 3];
@@ -1361,10 +1396,13 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
         in.Qx = Qx;
         in.Qy = Qy;
         in.Qz = Qz;
+        const double fr = d_rr, fb = d_rb;
         const Pops<S> dst(dst_, plane);
         PopWriter<S> w(dst, B, node, fluid && sd >= z0);
-        collide_node(B, in, w);
-        w.finish(d_rr, d_rb);
+        collide_node(B, in, w, [&] {
+          if (kPipeD) load_d(s - 2, plane);
+        });
+        w.finish(fr, fb);
       } else {
         // interface fields of every node of the box (zero at solid nodes)
         const uint32_t off = boff<float>(in_xy && sd >= z0, node);
