@@ -21,6 +21,9 @@
  *   - Velocities are ordered as the columns of the matrix of Eq. (1).
  *   - Node index inside a box: x + nx*(y + ny*z); x fastest.  Boxes are
  *     concatenated; box b starts at node offset cglbm_box_offset(h, b).
+ *     Offsets are multiples of 64; the arrays' length total_nodes (from
+ *     cglbm_query_sizes) is an odd multiple of 64 and may exceed the last
+ *     box's end by up to 127 nodes.
  *   - The state at time t is the pre-collision distribution f(x,t).  The
  *     library stores the post-collision distribution of step t-1 at x, so
  *     that a pull reproduces f(x,t).

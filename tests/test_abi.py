@@ -61,7 +61,8 @@ def test_storage_buffer_sizes():
     pop16, aux16, _ = pkg.query_sizes(pb, pkg.FP16_SHIFT)
     popx, auxx, _ = pkg.query_sizes(pb, pkg.FP32_EXACT)
     align = lambda v: (v + 255) // 256 * 256
-    assert total == 384
+    # 350 nodes -> 384 (multiple of 64) -> 448 (odd multiple of 64)
+    assert total == 448
     assert pop32 == 54 * total * 4 and aux32 == 21 * total * 4
     assert pop16 == align(52 * total * 2) + 2 * total * 8
     assert popx == align(52 * total * 4) + 2 * total * 8
