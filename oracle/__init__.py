@@ -84,7 +84,9 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB):
+        if not os.path.exists(_build.LIB) or any(
+                os.path.getmtime(src) > os.path.getmtime(_build.LIB)
+                for src in _build.SRC + [os.path.splitext(x)[0] + ".h" for x in _build.SRC]):
             _build.build()
         L = C.CDLL(_build.LIB)
         dp = C.POINTER(C.c_double)

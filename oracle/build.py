@@ -8,7 +8,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "cglbm_oracle.c")
+SRC = [os.path.join(HERE, "cglbm_oracle.c"), os.path.join(HERE, "d2q9_oracle.c")]
 LIB = os.path.join(HERE, "liborc.so")
 
 
@@ -16,7 +16,7 @@ def build(verbose: bool = False) -> str:
     cmd = [
         "gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
         "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
-        "-o", LIB + ".tmp", SRC, "-lm",
+        "-o", LIB + ".tmp", *SRC, "-lm",
     ]
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
