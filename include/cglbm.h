@@ -148,6 +148,32 @@ int cglbm_init(cglbm_handle **out, int32_t n_boxes, const cglbm_box_params *boxe
                const float *init_rho_b, const float *init_u, uint64_t noise_seed,
                double noise_amp, void *stream);
 
+/* The two-dimensional lattice D2Q9 of App. A (Eqs. A1-A2, xi = 3/5 so that
+ * (c_s^k)^2 = 3 (1 - alpha_k) / 5), with the generalized equilibrium of
+ * Eq. (A10) (central moments Eqs. A12-A16), the colour-gradient steps of
+ * Sec. II in two dimensions and the correction term Q of Eq. (65) per
+ * component.  Same box parameters, buffers, fields, diagnostics and calls as
+ * the D3Q27 handle, with these restrictions: nz = 1 and no z walls
+ * (CGLBM_EINVAL otherwise); storage FP32, model CGLBM_MODEL_D, omega_hi all 1
+ * and gravity zero (CGLBM_EUNSUPPORTED otherwise); init_u is [3][total_nodes]
+ * with its z plane ignored; z components of the fields are zero; the
+ * diagnostic R_eff is (V/pi)^(1/2).  Populations: 9 planes of colour pairs
+ * (2 x float, red first), 72 bytes per node; aux as for D3Q27.
+ * One launch per step (the pull, the interface stencils and the collision
+ * of a tile in one kernel); cglbm_set_schedule accepts 0 only; variants are
+ * its tile shapes (4 of them), chosen by cglbm_autotune, which writes their
+ * times to ms_per_variant[0..3]. */
+int cglbm_query_sizes_d2q9(int32_t n_boxes, const cglbm_box_params *boxes, int32_t storage,
+                           size_t *pop_bytes, size_t *aux_bytes, int64_t *total_nodes);
+int cglbm_init_d2q9(cglbm_handle **out, int32_t n_boxes, const cglbm_box_params *boxes,
+                    int32_t storage, void *pop_a, void *pop_b, void *aux, const float *init_rho_r,
+                    const float *init_rho_b, const float *init_u, uint64_t noise_seed,
+                    double noise_amp, void *stream);
+
+/* Lattice of a handle: 0 D3Q27 (cglbm_init), 1 D2Q9 (cglbm_init_d2q9), -1
+ * for NULL. */
+int cglbm_lattice(const cglbm_handle *h);
+
 /* Advance every box by n_steps time steps (steps 1-5 above).  Asynchronous. */
 int cglbm_step(cglbm_handle *h, int32_t n_steps, void *stream);
 

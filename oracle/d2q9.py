@@ -92,7 +92,9 @@ def lib():
         L.orc2_fields.argtypes = [P, dp, dp]
         L.orc2_init.argtypes = [P, dp, dp, dp, C.c_uint64, C.c_double, C.c_int32, dp]
         L.orc2_step.argtypes = [P, dp, C.c_int32]
-        for fn in ("orc2_fields", "orc2_init", "orc2_step"):
+        L.orc2_init_window.argtypes = [P, dp, dp, dp, C.c_uint64, C.c_double, C.c_int32,
+                                       C.POINTER(C.c_int32), C.POINTER(C.c_int32), dp]
+        for fn in ("orc2_fields", "orc2_init", "orc2_init_window", "orc2_step"):
             getattr(L, fn).restype = C.c_int
         _L = L
     return _L
@@ -193,6 +195,23 @@ def init(P: Params, rho_r, rho_b, u, seed=0, amp=0.0, box=0) -> np.ndarray:
     if lib().orc2_init(C.byref(cp), _dp(rho_r), _dp(rho_b), _dp(u), C.c_uint64(seed), amp, box,
                        _dp(f)) != 0:
         raise ValueError("orc2_init: non-positive total density")
+    return f
+
+
+def init_window(P: Params, rho_r, rho_b, u, global_dims, offset, seed=0, amp=0.0,
+                box=0) -> np.ndarray:
+    """Initial state of a window of a larger periodic box (noise keyed by the
+    larger box's node index).  global_dims, offset: (x, y)."""
+    rho_r = np.ascontiguousarray(rho_r, dtype=np.float64).reshape(P.shape)
+    rho_b = np.ascontiguousarray(rho_b, dtype=np.float64).reshape(P.shape)
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape((2,) + P.shape)
+    f = np.zeros((2, NQ) + P.shape)
+    cp = P.c()
+    gd = (C.c_int32 * 2)(*[int(v) for v in global_dims])
+    go = (C.c_int32 * 2)(*[int(v) for v in offset])
+    if lib().orc2_init_window(C.byref(cp), _dp(rho_r), _dp(rho_b), _dp(u), C.c_uint64(seed), amp,
+                              box, gd, go, _dp(f)) != 0:
+        raise ValueError("orc2_init_window: non-positive total density")
     return f
 
 

@@ -486,6 +486,17 @@ int orc2_step(const orc2_params *P, double *f, int32_t nsteps) {
  * rho_k / rho so that pure phases stay pure. */
 int orc2_init(const orc2_params *P, const double *rho_r, const double *rho_b, const double *u,
               uint64_t seed, double amp, int32_t box, double *f) {
+  const int32_t dims[2] = {P->nx, P->ny};
+  const int32_t zero[2] = {0, 0};
+  return orc2_init_window(P, rho_r, rho_b, u, seed, amp, box, dims, zero, f);
+}
+
+/* As orc2_init for a window of a larger periodic box: node (x, y) of the
+ * window is node ((x+ox) mod Nx, (y+oy) mod Ny) of the larger box, whose
+ * index keys the noise. */
+int orc2_init_window(const orc2_params *P, const double *rho_r, const double *rho_b,
+                     const double *u, uint64_t seed, double amp, int32_t box,
+                     const int32_t *gdims, const int32_t *goff, double *f) {
   const int64_t N = (int64_t)P->nx * P->ny;
   const double xi = orc2_xi();
   const double cs2r = xi * (1.0 - P->alpha_r), cs2b = xi * (1.0 - P->alpha_b);
@@ -501,8 +512,10 @@ int orc2_init(const orc2_params *P, const double *rho_r, const double *rho_b, co
     const double uu[2] = {u[c], u[N + c]};
     double feq[NQ];
     orc2_feq(rho, p, uu, feq);
+    const int64_t gnode = (int64_t)wrap((int)(c % P->nx + goff[0]), gdims[0]) +
+                          (int64_t)gdims[0] * wrap((int)(c / P->nx + goff[1]), gdims[1]);
     for (int i = 0; i < NQ; ++i) {
-      const double ft = feq[i] + (amp != 0.0 ? orc2_noise(seed, box, c, i, amp) : 0.0);
+      const double ft = feq[i] + (amp != 0.0 ? orc2_noise(seed, box, gnode, i, amp) : 0.0);
       f[(int64_t)i * N + c] = rho_r[c] / rho * ft;
       f[(int64_t)(NQ + i) * N + c] = rho_b[c] / rho * ft;
     }

@@ -58,6 +58,9 @@ int orc2_fields(const orc2_params *P, const double *f, double *out);
 int orc2_init(const orc2_params *P, const double *rho_r, const double *rho_b,
               const double *u /* [2][N] */, uint64_t seed, double amp, int32_t box,
               double *f);
+int orc2_init_window(const orc2_params *P, const double *rho_r, const double *rho_b,
+                     const double *u, uint64_t seed, double amp, int32_t box,
+                     const int32_t *gdims /* Nx, Ny */, const int32_t *goff, double *f);
 int orc2_step(const orc2_params *P, double *f, int32_t nsteps);
 
 #ifdef __cplusplus

@@ -38,7 +38,11 @@ EXPORTED = ("cglbm_query_sizes", "cglbm_init", "cglbm_step", "cglbm_moments", "c
             "cglbm_num_variants",
             "cglbm_variant_info", "cglbm_set_variant", "cglbm_get_variant", "cglbm_autotune",
             "cglbm_profile_begin", "cglbm_profile_end", "cglbm_destroy",
-            "cglbm_last_error", "cglbm_version")
+            "cglbm_last_error", "cglbm_version", "cglbm_query_sizes_d2q9", "cglbm_init_d2q9",
+            "cglbm_lattice")
+# Lattices: the D3Q27 model of the paper's body and the D2Q9 model of App. A.
+LATTICES = ("d3q27", "d2q9")
+NUM_VARIANTS_D2Q9 = 4
 
 
 class CglbmError(RuntimeError):
@@ -108,6 +112,9 @@ def lib():
                                         C.POINTER(C.c_size_t), C.POINTER(i64)]
         L.cglbm_init.argtypes = [C.POINTER(vp), i32, BP, i32, vp, vp, vp, vp, vp, vp,
                                  C.c_uint64, C.c_double, vp]
+        L.cglbm_query_sizes_d2q9.argtypes = L.cglbm_query_sizes.argtypes
+        L.cglbm_init_d2q9.argtypes = L.cglbm_init.argtypes
+        L.cglbm_lattice.argtypes = [vp]
         L.cglbm_step.argtypes = [vp, i32, vp]
         L.cglbm_moments.argtypes = [vp, i32, u32, vp, vp]
         L.cglbm_reduce.argtypes = [vp, C.POINTER(C.c_double), vp, i32, vp]
@@ -127,7 +134,8 @@ def lib():
         L.cglbm_destroy.restype = None
         L.cglbm_last_error.restype = C.c_char_p
         L.cglbm_version.restype = C.c_char_p
-        for fn in ("cglbm_query_sizes", "cglbm_init", "cglbm_step", "cglbm_moments",
+        for fn in ("cglbm_query_sizes", "cglbm_init", "cglbm_query_sizes_d2q9", "cglbm_init_d2q9",
+                   "cglbm_lattice", "cglbm_step", "cglbm_moments",
                    "cglbm_reduce", "cglbm_set_schedule", "cglbm_get_schedule", "cglbm_set_graph",
                    "cglbm_num_variants",
                    "cglbm_variant_info", "cglbm_set_variant", "cglbm_get_variant",
@@ -142,12 +150,18 @@ def _check(rc: int):
         raise CglbmError(rc, lib().cglbm_last_error().decode())
 
 
-def query_sizes(params: Sequence[BoxParams], storage: int = FP32):
+def query_sizes(params: Sequence[BoxParams], storage: int = FP32, lattice: str = "d3q27"):
     arr = (BoxParams * len(params))(*params)
     pop, aux, tot = C.c_size_t(), C.c_size_t(), C.c_int64()
-    _check(lib().cglbm_query_sizes(len(params), arr, storage, C.byref(pop), C.byref(aux),
-                                   C.byref(tot)))
+    fn = lib().cglbm_query_sizes_d2q9 if _lattice_id(lattice) == 1 else lib().cglbm_query_sizes
+    _check(fn(len(params), arr, storage, C.byref(pop), C.byref(aux), C.byref(tot)))
     return pop.value, aux.value, tot.value
+
+
+def _lattice_id(lattice: str) -> int:
+    if lattice not in LATTICES:
+        raise ValueError("lattice must be one of %s" % (LATTICES,))
+    return LATTICES.index(lattice)
 
 
 def num_variants() -> int:
@@ -171,20 +185,25 @@ class Simulation:
 
     rho_r, rho_b: per-box float arrays of shape (nz, ny, nx); u: per-box
     (3, nz, ny, nx).  They are packed into the concatenated layout and copied
-    to the device once for the initialisation.
+    to the device once for the initialisation.  lattice "d2q9" runs the
+    two-dimensional model of App. A on boxes with nz = 1 (u may then have
+    two components).
     """
 
     def __init__(self, params: Sequence[BoxParams], rho_r: List[np.ndarray],
                  rho_b: List[np.ndarray], u: List[np.ndarray], seed: int = 0,
-                 noise: float = 0.0, storage: int = FP32, device: int = 0, stream=None):
+                 noise: float = 0.0, storage: int = FP32, device: int = 0, stream=None,
+                 lattice: str = "d3q27"):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the colour-gradient LBM library needs an MI355X")
+        self.lattice = lattice
+        lat = _lattice_id(lattice)
         self.params = list(params)
         self.nboxes = len(self.params)
         self.storage = storage
         self.device = torch.device("cuda", device)
-        pop_bytes, aux_bytes, total = query_sizes(self.params, storage)
+        pop_bytes, aux_bytes, total = query_sizes(self.params, storage, lattice)
         self.total = total
         self.stream = stream
         dev = self.device
@@ -196,13 +215,16 @@ class Simulation:
         rb = self.pack([np.asarray(a, np.float32) for a in rho_b])
         uu = np.zeros((3, total), np.float32)
         for a in range(3):
-            uu[a] = self.pack([np.asarray(x, np.float32)[a] for x in u])
+            uu[a] = self.pack([np.asarray(x, np.float32)[a] if a < len(x) else
+                               np.zeros(p.nx * p.ny * p.nz, np.float32)
+                               for x, p in zip(u, self.params)])
         self._init_rr = torch.from_numpy(rr).to(dev)
         self._init_rb = torch.from_numpy(rb).to(dev)
         self._init_u = torch.from_numpy(uu).to(dev)
         arr = (BoxParams * self.nboxes)(*self.params)
         h = C.c_void_p()
-        _check(lib().cglbm_init(C.byref(h), self.nboxes, arr, storage, self.pop_a.data_ptr(),
+        init = lib().cglbm_init_d2q9 if lat == 1 else lib().cglbm_init
+        _check(init(C.byref(h), self.nboxes, arr, storage, self.pop_a.data_ptr(),
                                 self.pop_b.data_ptr(), self.aux.data_ptr(),
                                 self._init_rr.data_ptr(), self._init_rb.data_ptr(),
                                 self._init_u.data_ptr(), C.c_uint64(seed), float(noise),
@@ -268,11 +290,11 @@ class Simulation:
     def autotune(self, reps: int = 5):
         """Time every fused launch geometry and the three-kernel schedule and
         keep the fastest; returns the mean milliseconds per fused variant,
-        then of the three-kernel schedule."""
+        then of the three-kernel schedule (D2Q9: per tile shape)."""
         n = num_variants() + 1
         ms = (C.c_double * n)()
         _check(lib().cglbm_autotune(self.h, int(reps), ms, _stream_ptr(self.stream)))
-        return list(ms)
+        return list(ms)[:NUM_VARIANTS_D2Q9] if self.lattice == "d2q9" else list(ms)
 
     def set_schedule(self, schedule: int):
         _check(lib().cglbm_set_schedule(self.h, int(schedule)))

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/cglbm.h"
+#include "d2q9.hpp"
 #include "kernels.hpp"
 
 using namespace cglbm;
@@ -67,12 +68,27 @@ const FusedVariant kFusedVariants[] = {
 #undef FV
 #undef FV_S
 constexpr int kNumFused = (int)(sizeof(kFusedVariants) / sizeof(kFusedVariants[0]));
+
+// Tile shapes of the two-dimensional (D2Q9) step kernel, 256 threads each;
+// bitwise equal results, picked by cglbm_autotune.
+using Step2Fn = void (*)(const BoxDev *, const int32_t *, const d2q9::W *, d2q9::W *, float *,
+                         int64_t);
+struct Variant2 {
+  int tx, ty;
+  Step2Fn step, fields;
+};
+#define V2(TX, TY) {TX, TY, d2q9::k2_step<TX, TY, 256, false>, d2q9::k2_step<TX, TY, 256, true>}
+const Variant2 kVariants2[] = {V2(64, 16), V2(32, 32), V2(64, 8), V2(32, 16)};
+#undef V2
+constexpr int kNumV2 = (int)(sizeof(kVariants2) / sizeof(kVariants2[0]));
+enum { LATTICE_D3Q27 = 0, LATTICE_D2Q9 = 1 };
 constexpr int64_t kAlign = 64;             // node alignment of each box's base
 // Limit of all boxes together: every plane of 8-byte values (with the plane
 // length's padding of at most 2 * kAlign nodes) stays below 4 GiB, so that
 // kernels address a plane with 32-bit byte offsets.
 constexpr int64_t kMaxNodes = (1ll << 29) - (1ll << 20);
-constexpr double kXi = 9.0 / 19.0;
+constexpr double kXi = 9.0 / 19.0;   // D3Q27 (Sec. II.A)
+constexpr double kXi2 = 3.0 / 5.0;   // D2Q9: the rest fractions of Eq. (8) sum to one
 
 enum { KIND_PULL = 0, KIND_IFACE = 1, KIND_COLLIDE = 2, KIND_FUSED = 3, KIND_N = 4 };
 
@@ -92,7 +108,12 @@ bool storage_exact(int32_t st) { return st != CGLBM_FP32; }
 size_t storage_bytes(int32_t st) { return (st == CGLBM_FP16_SHIFT || st == CGLBM_BF16_SHIFT) ? 2 : 4; }
 
 // Bytes of one population buffer and of the aux buffer for `total` nodes.
-void buffer_sizes(int32_t st, int64_t total, size_t *pop, size_t *aux) {
+void buffer_sizes(int32_t st, int64_t total, size_t *pop, size_t *aux, int lattice = LATTICE_D3Q27) {
+  if (lattice == LATTICE_D2Q9) {
+    *pop = (size_t)(d2q9::kQ * total * (int64_t)sizeof(d2q9::W));
+    *aux = (size_t)((int64_t)A_COUNT * total * 4);
+    return;
+  }
   if (storage_exact(st))
     *pop = (size_t)align256(52 * total * (int64_t)storage_bytes(st)) + (size_t)(2 * total * 8);
   else
@@ -107,6 +128,7 @@ struct Layout {
   int32_t nblk = 0, ntile = 0, ncol = 0, nblk_pad = 0;
   bool walls = false;
   bool general = false;  // a box with Model A, B or C or without Q: three-kernel schedule
+  int lattice = LATTICE_D3Q27;
 };
 
 int validate(int32_t n_boxes, const cglbm_box_params *boxes, int32_t storage) {
@@ -160,8 +182,33 @@ int validate(int32_t n_boxes, const cglbm_box_params *boxes, int32_t storage) {
   return CGLBM_OK;
 }
 
-void build_layout(int32_t n_boxes, const cglbm_box_params *boxes, Layout &L) {
+// The D2Q9 lattice of App. A: one-layer boxes, FP32 storage, the generalized
+// equilibrium of Eq. (A10) with unit rates above second order.
+int validate_d2q9(int32_t n_boxes, const cglbm_box_params *boxes, int32_t storage) {
+  int rc = validate(n_boxes, boxes, storage);
+  if (rc) return rc;
+  if (storage != CGLBM_FP32)
+    return fail(CGLBM_EUNSUPPORTED, "D2Q9 boxes are stored in FP32 only");
+  for (int b = 0; b < n_boxes; ++b) {
+    const cglbm_box_params &P = boxes[b];
+    if (P.nz != 1) return fail(CGLBM_EINVAL, "box %d: a D2Q9 box has nz = 1", b);
+    if (P.walls & 2u) return fail(CGLBM_EINVAL, "box %d: a D2Q9 box has no z walls", b);
+    if (P.model != CGLBM_MODEL_D)
+      return fail(CGLBM_EUNSUPPORTED, "box %d: D2Q9 implements the equilibrium of Eq. (A10) only", b);
+    for (int k = 0; k < 9; ++k)
+      if (P.omega_hi[k] != 1.0)
+        return fail(CGLBM_EUNSUPPORTED, "box %d: D2Q9 relaxes the higher moments at rate 1", b);
+    for (int a = 0; a < 3; ++a)
+      if (P.gravity[a] != 0.0) return fail(CGLBM_EUNSUPPORTED, "box %d: no buoyancy force in D2Q9", b);
+  }
+  return CGLBM_OK;
+}
+
+void build_layout(int32_t n_boxes, const cglbm_box_params *boxes, Layout &L,
+                  int lattice = LATTICE_D3Q27) {
   L = Layout();
+  L.lattice = lattice;
+  const double xi = lattice == LATTICE_D2Q9 ? kXi2 : kXi;
   int64_t off = 0;
   int32_t blk = 0, tile = 0;
   for (int b = 0; b < n_boxes; ++b) {
@@ -190,8 +237,9 @@ void build_layout(int32_t n_boxes, const cglbm_box_params *boxes, Layout &L) {
     B.fdy = make_fastdiv((uint32_t)P.ny);
     B.ftx = make_fastdiv((uint32_t)B.tnx);
     B.fty = make_fastdiv((uint32_t)B.tny);
-    B.cs2r = (float)(kXi * (1.0 - P.red.alpha));
-    B.cs2b = (float)(kXi * (1.0 - P.blue.alpha));
+    B.cs2r = (float)(xi * (1.0 - P.red.alpha));
+    B.cs2b = (float)(xi * (1.0 - P.blue.alpha));
+    B.d2q9 = lattice == LATTICE_D2Q9 ? 1 : 0;
     B.ir0r = (float)(1.0 / P.red.rho0);
     B.ir0b = (float)(1.0 / P.blue.rho0);
     B.nu_r = (float)P.red.nu;
@@ -259,6 +307,26 @@ void build_columns(Layout &L, int v) {
   while ((int32_t)L.col_box.size() < L.ncol) L.col_box.push_back(-1);
 }
 
+// Tile table of the D2Q9 step kernel for variant v (kept in the column
+// table's place): per box tile0, tnx, tny, ftx.
+void build_tiles2(Layout &L, int v) {
+  const Variant2 &V = kVariants2[v];
+  L.col_box.clear();
+  int32_t tile = 0;
+  for (size_t b = 0; b < L.boxes.size(); ++b) {
+    BoxDev &B = L.boxes[b];
+    B.tile0 = tile;
+    B.tnx = (B.nx + V.tx - 1) / V.tx;
+    B.tny = (B.ny + V.ty - 1) / V.ty;
+    B.ftx = make_fastdiv((uint32_t)B.tnx);
+    const int32_t nt = B.tnx * B.tny;
+    for (int32_t k = 0; k < nt; ++k) L.col_box.push_back((int32_t)b);
+    tile += nt;
+  }
+  L.ncol = (int32_t)align_up(tile, 8);
+  while ((int32_t)L.col_box.size() < L.ncol) L.col_box.push_back(-1);
+}
+
 // Host check of the division helper on the values a box can produce.
 bool fastdiv_ok(uint32_t d, uint32_t nmax) {
   FastDiv f = make_fastdiv(d);
@@ -287,7 +355,8 @@ struct cglbm_handle {
   int32_t *d_blk_box = nullptr;
   int32_t *d_tile_box = nullptr;
   int32_t *d_col_box = nullptr;
-  int32_t schedule = 0;        // 0 fused, 1 three kernels
+  int32_t schedule = 0;        // 0 fused, 1 three kernels (D3Q27)
+  int32_t lattice = LATTICE_D3Q27;
   int32_t variant = 0;         // fused launch geometry
   size_t col_cap = 0;          // capacity of d_col_box (entries)
   double *d_part = nullptr;    // block partials of the reduction
@@ -346,7 +415,14 @@ void drop_graphs(cglbm_handle *h) {
 
 int select_variant(cglbm_handle *h, int v, hipStream_t s) {
   drop_graphs(h);
-  build_columns(h->L, v);
+  if (h->lattice == LATTICE_D2Q9) {
+    build_tiles2(h->L, v);
+    for (const BoxDev &B : h->L.boxes)
+      if (!fastdiv_ok((uint32_t)B.tnx, (uint32_t)(B.tnx * B.tny)))
+        return fail(CGLBM_EINVAL, "index division self-check failed");
+  } else {
+    build_columns(h->L, v);
+  }
   if (h->L.col_box.size() > h->col_cap) {
     if (h->d_col_box) HIP_TRY(hipFree(h->d_col_box));
     h->d_col_box = nullptr;
@@ -395,8 +471,24 @@ int check_launch() {
 // box's equilibrium family and correction switch.
 int effective_schedule(const cglbm_handle *h) { return h->L.general ? 1 : h->schedule; }
 
+// D2Q9: one launch of the step kernel (export != 0: the fields of the
+// stored state into aux, populations untouched).
+int launch_step2(cglbm_handle *h, hipStream_t s, int export_fields) {
+  const Variant2 &V = kVariants2[h->variant];
+  hipLaunchKernelGGL(export_fields ? V.fields : V.step, dim3(h->L.ncol), dim3(256), 0, s,
+                     h->d_boxes, h->d_col_box, (const d2q9::W *)h->pop[h->cur],
+                     (d2q9::W *)h->pop[1 - h->cur], h->aux, h->L.total);
+  return CGLBM_OK;
+}
+
 // One time step on stream s (launches only); flips the buffer parity.
 int launch_step(cglbm_handle *h, hipStream_t s) {
+  if (h->lattice == LATTICE_D2Q9) {
+    int rc = timed(h, s, KIND_FUSED, [&] { return launch_step2(h, s, 0); });
+    if (!rc) rc = check_launch();
+    if (!rc) h->cur = 1 - h->cur;
+    return rc;
+  }
   int rc = timed(h, s, KIND_PULL, [&] { return launch_pull(h, s, 1); });
   if (effective_schedule(h) == 0) {
     if (!rc) rc = timed(h, s, KIND_FUSED, [&] { return launch_fused(h, s, 0); });
@@ -435,6 +527,10 @@ int capture_pair(cglbm_handle *h) {
 }
 
 int compute_fields(cglbm_handle *h, hipStream_t s, int write_kappa) {
+  if (h->lattice == LATTICE_D2Q9) {
+    const int rc = launch_step2(h, s, 1);
+    return rc ? rc : check_launch();
+  }
   int rc = launch_pull(h, s, 0);
   if (rc) return rc;
   if (effective_schedule(h) == 0)
@@ -445,6 +541,40 @@ int compute_fields(cglbm_handle *h, hipStream_t s, int write_kappa) {
   return check_launch();
 }
 
+// D2Q9: time every tile variant of the step kernel on the same stored state
+// (the kernel reads one buffer and writes the other, so repeated launches
+// are idempotent) and keep the fastest.
+int autotune2(cglbm_handle *h, int32_t reps, double *ms_per_variant, hipStream_t s) {
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int rc = CGLBM_OK, best = h->variant;
+  double best_ms = 1e300;
+  for (int v = 0; v < kNumV2 && !rc; ++v) {
+    if ((rc = select_variant(h, v, s)) || (rc = launch_step2(h, s, 0))) break;
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps && !rc; ++r) rc = launch_step2(h, s, 0);
+    (void)hipEventRecord(e1, s);
+    if (rc || (rc = check_launch())) break;
+    if (hipEventSynchronize(e1) != hipSuccess) {
+      rc = fail(CGLBM_EHIP, "autotune: event synchronize failed");
+      break;
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    const double avg = (double)ms / reps;
+    if (ms_per_variant) ms_per_variant[v] = avg;
+    if (avg < best_ms) {
+      best_ms = avg;
+      best = v;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  return select_variant(h, best, s);
+}
+
 }  // namespace
 
 extern "C" {
@@ -453,34 +583,81 @@ const char *cglbm_last_error(void) { return g_err.c_str(); }
 
 const char *cglbm_version(void) { return "cglbm-gfx950 0.1"; }
 
-int cglbm_query_sizes(int32_t n_boxes, const cglbm_box_params *boxes, int32_t storage,
-                      size_t *pop_bytes, size_t *aux_bytes, int64_t *total_nodes) {
+}  // extern "C"
+
+namespace {
+
+int query_sizes(int lattice, int32_t n_boxes, const cglbm_box_params *boxes, int32_t storage,
+                size_t *pop_bytes, size_t *aux_bytes, int64_t *total_nodes) {
   g_err.clear();
-  int rc = validate(n_boxes, boxes, storage);
+  int rc = lattice == LATTICE_D2Q9 ? validate_d2q9(n_boxes, boxes, storage)
+                                   : validate(n_boxes, boxes, storage);
   if (rc) return rc;
   Layout L;
-  build_layout(n_boxes, boxes, L);
+  build_layout(n_boxes, boxes, L, lattice);
   size_t pb, ab;
-  buffer_sizes(storage, L.total, &pb, &ab);
+  buffer_sizes(storage, L.total, &pb, &ab, lattice);
   if (pop_bytes) *pop_bytes = pb;
   if (aux_bytes) *aux_bytes = ab;
   if (total_nodes) *total_nodes = L.total;
   return CGLBM_OK;
 }
 
-int64_t cglbm_box_offset(const cglbm_handle *h, int32_t box) {
-  if (!h || box < 0 || box >= h->n_boxes) return -1;
-  return h->L.boxes[box].base;
+int init_handle(int lattice, cglbm_handle **out, int32_t n_boxes, const cglbm_box_params *boxes,
+                int32_t storage, void *pop_a, void *pop_b, void *aux, const float *init_rho_r,
+                const float *init_rho_b, const float *init_u, uint64_t noise_seed,
+                double noise_amp, void *stream);
+
+}  // namespace
+
+extern "C" {
+
+int cglbm_query_sizes(int32_t n_boxes, const cglbm_box_params *boxes, int32_t storage,
+                      size_t *pop_bytes, size_t *aux_bytes, int64_t *total_nodes) {
+  return query_sizes(LATTICE_D3Q27, n_boxes, boxes, storage, pop_bytes, aux_bytes, total_nodes);
+}
+
+int cglbm_query_sizes_d2q9(int32_t n_boxes, const cglbm_box_params *boxes, int32_t storage,
+                           size_t *pop_bytes, size_t *aux_bytes, int64_t *total_nodes) {
+  return query_sizes(LATTICE_D2Q9, n_boxes, boxes, storage, pop_bytes, aux_bytes, total_nodes);
 }
 
 int cglbm_init(cglbm_handle **out, int32_t n_boxes, const cglbm_box_params *boxes,
                int32_t storage, void *pop_a, void *pop_b, void *aux, const float *init_rho_r,
                const float *init_rho_b, const float *init_u, uint64_t noise_seed,
                double noise_amp, void *stream) {
+  return init_handle(LATTICE_D3Q27, out, n_boxes, boxes, storage, pop_a, pop_b, aux, init_rho_r,
+                     init_rho_b, init_u, noise_seed, noise_amp, stream);
+}
+
+int cglbm_init_d2q9(cglbm_handle **out, int32_t n_boxes, const cglbm_box_params *boxes,
+                    int32_t storage, void *pop_a, void *pop_b, void *aux, const float *init_rho_r,
+                    const float *init_rho_b, const float *init_u, uint64_t noise_seed,
+                    double noise_amp, void *stream) {
+  return init_handle(LATTICE_D2Q9, out, n_boxes, boxes, storage, pop_a, pop_b, aux, init_rho_r,
+                     init_rho_b, init_u, noise_seed, noise_amp, stream);
+}
+
+int cglbm_lattice(const cglbm_handle *h) { return h ? h->lattice : -1; }
+
+int64_t cglbm_box_offset(const cglbm_handle *h, int32_t box) {
+  if (!h || box < 0 || box >= h->n_boxes) return -1;
+  return h->L.boxes[box].base;
+}
+
+}  // extern "C"
+
+namespace {
+
+int init_handle(int lattice, cglbm_handle **out, int32_t n_boxes, const cglbm_box_params *boxes,
+                int32_t storage, void *pop_a, void *pop_b, void *aux, const float *init_rho_r,
+                const float *init_rho_b, const float *init_u, uint64_t noise_seed,
+                double noise_amp, void *stream) {
   g_err.clear();
   if (!out) return fail(CGLBM_EINVAL, "out must not be NULL");
   *out = nullptr;
-  int rc = validate(n_boxes, boxes, storage);
+  int rc = lattice == LATTICE_D2Q9 ? validate_d2q9(n_boxes, boxes, storage)
+                                   : validate(n_boxes, boxes, storage);
   if (rc) return rc;
   if (!pop_a) return fail(CGLBM_EINVAL, "pop_a must not be NULL");
   if (!pop_b)
@@ -494,7 +671,8 @@ int cglbm_init(cglbm_handle **out, int32_t n_boxes, const cglbm_box_params *boxe
   h->n_boxes = n_boxes;
   h->params.assign(boxes, boxes + n_boxes);
   h->storage = storage;
-  build_layout(n_boxes, boxes, h->L);
+  h->lattice = lattice;
+  build_layout(n_boxes, boxes, h->L, lattice);
   for (const BoxDev &B : h->L.boxes) {
     if (!fastdiv_ok((uint32_t)B.nx, (uint32_t)B.n) || !fastdiv_ok((uint32_t)B.ny, (uint32_t)B.n) ||
         !fastdiv_ok((uint32_t)B.tnx, 1u << 20) || !fastdiv_ok((uint32_t)B.tny, 1u << 20)) {
@@ -531,13 +709,22 @@ int cglbm_init(cglbm_handle **out, int32_t n_boxes, const cglbm_box_params *boxe
   if ((rc = select_variant(h, 0, s))) return cleanup(rc);
   // the stored state lives in pop[0]
   h->cur = 0;
-  hipLaunchKernelGGL(kInit[storage], dim3(h->L.nblk), dim3(kBlock), 0, s, h->d_boxes,
-                     h->d_blk_box, init_rho_r, init_rho_b, init_u, h->pop[0], h->L.total,
-                     noise_seed, (float)noise_amp);
+  if (lattice == LATTICE_D2Q9)
+    hipLaunchKernelGGL(d2q9::k2_init, dim3(h->L.nblk), dim3(kBlock), 0, s, h->d_boxes,
+                       h->d_blk_box, init_rho_r, init_rho_b, init_u, (d2q9::W *)h->pop[0],
+                       h->L.total, noise_seed, (float)noise_amp);
+  else
+    hipLaunchKernelGGL(kInit[storage], dim3(h->L.nblk), dim3(kBlock), 0, s, h->d_boxes,
+                       h->d_blk_box, init_rho_r, init_rho_b, init_u, h->pop[0], h->L.total,
+                       noise_seed, (float)noise_amp);
   if ((rc = check_launch())) return cleanup(rc);
   *out = h;
   return CGLBM_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int cglbm_step(cglbm_handle *h, int32_t n_steps, void *stream) {
   g_err.clear();
@@ -637,6 +824,8 @@ int cglbm_set_schedule(cglbm_handle *h, int32_t schedule) {
   g_err.clear();
   if (!h) return fail(CGLBM_ESTATE, "null handle");
   if (schedule != 0 && schedule != 1) return fail(CGLBM_EINVAL, "unknown schedule %d", schedule);
+  if (schedule != 0 && h->lattice == LATTICE_D2Q9)
+    return fail(CGLBM_EUNSUPPORTED, "D2Q9 steps have one schedule (0)");
   if (schedule != h->schedule) drop_graphs(h);
   h->schedule = schedule;
   return CGLBM_OK;
@@ -659,7 +848,8 @@ int cglbm_variant_info(int32_t v, int32_t *info) {
 int cglbm_set_variant(cglbm_handle *h, int32_t v, void *stream) {
   g_err.clear();
   if (!h) return fail(CGLBM_ESTATE, "null handle");
-  if (v < 0 || v >= kNumFused) return fail(CGLBM_EINVAL, "variant %d out of range", v);
+  const int nv = h->lattice == LATTICE_D2Q9 ? kNumV2 : kNumFused;
+  if (v < 0 || v >= nv) return fail(CGLBM_EINVAL, "variant %d out of range", v);
   return select_variant(h, v, (hipStream_t)stream);
 }
 
@@ -670,6 +860,7 @@ int cglbm_autotune(cglbm_handle *h, int32_t reps, double *ms_per_variant, void *
   if (!h) return fail(CGLBM_ESTATE, "null handle");
   if (reps < 1) return fail(CGLBM_EINVAL, "reps must be >= 1");
   hipStream_t s = (hipStream_t)stream;
+  if (h->lattice == LATTICE_D2Q9) return autotune2(h, reps, ms_per_variant, s);
   // the fused kernel is idempotent for a fixed pull: time every variant on
   // the same inputs; the stored state is unchanged afterwards
   int rc = launch_pull(h, s, 1);

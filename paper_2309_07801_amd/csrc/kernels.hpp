@@ -55,6 +55,7 @@ struct BoxDev {
   int32_t full_rates;   // 1: some higher-order rate differs from 1
   int32_t model;        // equilibrium family of Table I (MODEL_A..MODEL_D)
   int32_t qcorr;        // 1: correction term Q of Eq. (65) in the collision
+  int32_t d2q9;         // 1: two-dimensional box of the D2Q9 lattice (App. A)
 };
 
 constexpr int kBlock = 256;
@@ -1627,7 +1628,9 @@ __global__ __launch_bounds__(kBlock) void k_reduce_final(const BoxDev *__restric
     o[2] = tot[2];
     o[3] = tot[3];
     o[4] = tot[4];
-    o[7] = cbrt(3.0 * tot[5] / (4.0 * 3.14159265358979323846));
+    // equivalent radius of the red volume (area in two dimensions)
+    o[7] = B.d2q9 ? sqrt(tot[5] / 3.14159265358979323846)
+                  : cbrt(3.0 * tot[5] / (4.0 * 3.14159265358979323846));
     o[8] = tot[0] > 0 ? tot[6] / tot[0] : 0.0;
     o[9] = tot[0] > 0 ? tot[7] / tot[0] : 0.0;
     o[10] = tot[0] > 0 ? tot[8] / tot[0] : 0.0;

@@ -5,6 +5,7 @@ import numpy as np
 
 import oracle as O
 import workloads as WL
+from oracle import d2q9 as O2
 
 
 def oracle_params(box: WL.Box, **kw) -> O.Params:
@@ -60,3 +61,30 @@ def errors(g, o, box: WL.Box, u_ref: float):
         "rho_l2": float(np.sqrt((((rho_g - rho_o) / rho_o)[m] ** 2).mean())),
         "u_l2": float(np.sqrt((du[m] ** 2).mean()) / u_ref),
     }
+
+
+# ---- two-dimensional (D2Q9) boxes: workloads.Box with nz = 1 ----
+
+def oracle_params_2d(box: WL.Box, **kw) -> O2.Params:
+    d = dict(nx=box.nx, ny=box.ny, rho0_r=box.rho0_r, rho0_b=box.rho0_b, alpha_r=box.alpha_r,
+             alpha_b=box.alpha_b, nu_r=box.nu_r, nu_b=box.nu_b, sigma=box.sigma, beta=box.beta,
+             walls=box.walls, body_force=tuple(box.body_force[:2]), use_q=box.use_q,
+             omega=(1.0, 1.0, box.omega_bulk, 1.0, 1.0))
+    d.update(kw)
+    return O2.Params(**d)
+
+
+def run_oracle_2d(box: WL.Box, rr, rb, u, steps, seed=0, noise=0.0, box_index=0):
+    """Oracle fields as (1, ny, nx) arrays (the shape of the GPU's fields),
+    with zero z components."""
+    P = oracle_params_2d(box)
+    sh = (box.ny, box.nx)
+    f = O2.init(P, np.asarray(rr, np.float64).reshape(sh), np.asarray(rb, np.float64).reshape(sh),
+                np.asarray(u, np.float64)[:2].reshape((2,) + sh), seed=seed, amp=noise,
+                box=box_index)
+    if steps:
+        O2.step(P, f, steps)
+    F = {k: v.reshape((1,) + sh) for k, v in O2.fields(P, f).items()}
+    for k in ("uz", "nz", "Fz", "Qz"):
+        F[k] = np.zeros((1,) + sh)
+    return F, f

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared_functions():
     src = open(os.path.join(ROOT, "include", "cglbm.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(cglbm_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(cglbm_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -79,3 +79,34 @@ def test_phase_validation_and_storage():
     with pytest.raises(pkg.CglbmError) as ei:
         pkg.query_sizes([p], storage=7)
     assert ei.value.code in (-1, -3)
+
+
+def _box2d(nx=40, ny=30, **kw):
+    b = WL.stationary_droplet_2d(n=nx, R=8.0).box
+    import dataclasses
+    return dataclasses.replace(b, nx=nx, ny=ny, **kw)
+
+
+def test_d2q9_sizes_and_validation():
+    """The D2Q9 entry points: 9 pair planes of 2 x float per node, the aux
+    layout of D3Q27; nz = 1 and FP32 storage, Eq. (A10) only."""
+    p = [pkg.box_params_of(_box2d())]
+    pop, aux, total = pkg.query_sizes(p, pkg.FP32, lattice="d2q9")
+    assert total == 1216          # 1200 -> 1216 (multiple of 64) is odd multiple of 64 (19)
+    assert pop == 9 * 8 * total and aux == 21 * 4 * total
+    for field, value, code in (("nz", 2, -1), ("walls", 2, -1), ("model", 0, -3)):
+        q = pkg.box_params_of(_box2d())
+        setattr(q, field, value)
+        with pytest.raises(pkg.CglbmError) as ei:
+            pkg.query_sizes([q], pkg.FP32, lattice="d2q9")
+        assert ei.value.code == code, field
+    q = pkg.box_params_of(_box2d())
+    q.omega_hi[2] = 1.5
+    with pytest.raises(pkg.CglbmError) as ei:
+        pkg.query_sizes([q], pkg.FP32, lattice="d2q9")
+    assert ei.value.code == -3
+    with pytest.raises(pkg.CglbmError) as ei:
+        pkg.query_sizes(p, pkg.FP16_SHIFT, lattice="d2q9")
+    assert ei.value.code == -3
+    with pytest.raises(ValueError):
+        pkg.query_sizes(p, pkg.FP32, lattice="d3q19")

@@ -363,3 +363,52 @@ def layered_channel(case: str, a: int = 8, b: int = 16, nu: float = 0.02,
     u = np.zeros((3,) + box.shape, dtype=np.float32)
     return Workload("layered_%s" % case, box, rho_r, rho_b, u, centres=None, radii=None), M
 
+
+
+# ---------------------------------------------------------------------------
+# Two-dimensional cases (D2Q9 lattice of App. A): Boxes with nz = 1.
+#   * xi = 3/5 (the rest fractions of Eq. 8 sum to one on D2Q9);
+#   * the lighter phase takes alpha = 4/9 (squared sound speed 1/3), the
+#     heavier alpha = 1 - (5/9)/g for density ratio g (equal pressures,
+#     Eq. 13).
+# ---------------------------------------------------------------------------
+
+XI_2D = 3.0 / 5.0
+ALPHA_LIGHT_2D = 4.0 / 9.0
+
+
+def alpha_heavy_2d(gamma: float) -> float:
+    return 1.0 - (5.0 / 9.0) / gamma
+
+
+def stationary_droplet_2d(gamma: float = 1.0, sigma: float = 0.072, n: int = 100,
+                          R: float = 25.0, nu: float = 1.0 / 6.0, beta: float = 0.7,
+                          steps: int = 20000) -> Workload:
+    """Table II's stationary droplet: a red circle of radius R (density
+    gamma) in blue fluid of density 1, periodic n x n box, nu_r = nu_b = nu
+    (Sec. IV.A)."""
+    box = Box(nx=n, ny=n, nz=1, rho0_r=gamma, rho0_b=1.0, alpha_r=alpha_heavy_2d(gamma),
+              alpha_b=ALPHA_LIGHT_2D, nu_r=nu, nu_b=nu, sigma=sigma, beta=beta)
+    c = ((n - 1) / 2.0, (n - 1) / 2.0, 0.0)
+    rr, rb, u = droplet_fields(box, [c], [R])
+    return Workload("stationary_droplet_2d_g%g_s%g" % (gamma, sigma), box, rr, rb, u,
+                    steps=steps, centres=[c], radii=[R])
+
+
+def droplets_2d(n: int = 4096, per_side: int = 16, R: float = 48.0, gamma: float = 10.0,
+                sigma: float = 0.01, nu: float = 0.05, U: float = 0.05, beta: float = 0.7,
+                seed: int = 7, noise: float = 1e-4) -> Workload:
+    """A periodic n x n field of per_side^2 circular droplets (radius R,
+    density ratio gamma, centres on a jittered square grid) carried by a
+    uniform flow U along x: the two-dimensional throughput case."""
+    box = Box(nx=n, ny=n, nz=1, rho0_r=gamma, rho0_b=1.0, alpha_r=alpha_heavy_2d(gamma),
+              alpha_b=ALPHA_LIGHT_2D, nu_r=nu, nu_b=nu, sigma=sigma, beta=beta)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pitch = n / per_side
+    jit = max(pitch / 2.0 - R - 4.0, 0.0)
+    centres = [((i + 0.5) * pitch + rng.uniform(-jit, jit),
+                (j + 0.5) * pitch + rng.uniform(-jit, jit), 0.0)
+               for j in range(per_side) for i in range(per_side)]
+    rr, rb, u = droplet_fields(box, centres, [R] * len(centres), u_carrier=(U, 0.0, 0.0))
+    return Workload("droplets_2d_%d" % n, box, rr, rb, u, seed=seed, noise=noise,
+                    centres=centres, radii=[R] * len(centres))
