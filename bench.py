@@ -14,8 +14,9 @@ oracle timed on a bounded sample of the same workload.  `forms` reports, on
 the same workload and step counts, the FP16/BF16-shifted and mass-exact FP32
 storage (with their difference to the FP32 run as a proxy error), the
 96-box batched workload, the 32^3 static droplet, the Rayleigh-Taylor case
-at the paper's size (Models D and A) and the translating droplet's
-deformation per equilibrium model.  The timed region
+at the paper's size (Models D and A), the translating droplet's
+deformation per equilibrium model, the two-dimensional model of App. A on a
+4096^2 droplet field (d2q9) and Table II's surface tensions (table2).  The timed region
 launches every kernel directly (HIP events around each launch); after it,
 `graph_mlups` times the same update as replays of the captured two-step
 graph that cglbm_step uses by default.
@@ -53,6 +54,11 @@ def kernel_bytes(storage: str):
         "collide": 20 * 4 + aux_rho + pops,        # moments + interface fields in, populations out
         "fused": 11 * 4 + aux_rho + pops,          # local moments in, populations out
     }
+
+
+# D2Q9 step kernel (one launch per step): 9 colour pairs of 2 x float read
+# and written per node; every moment and interface field stays on chip.
+D2Q9_BYTES = 2 * 9 * 8
 
 
 def step_bytes(storage: str) -> int:
@@ -95,7 +101,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--size", type=int, default=256, help="box edge (default 256)")
     ap.add_argument("--storage", default="fp32", choices=sorted(STORAGES))
-    ap.add_argument("--forms", default="fp16,bf16,fp32x,batched,small,rti,galilean",
+    ap.add_argument("--forms", default="fp16,bf16,fp32x,batched,small,rti,galilean,d2q9,table2",
                     help="extra forms on the same workload ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -149,7 +155,8 @@ def cpu_baseline(w, seconds):
                       "definitions), %.1f s" % (steps, box.nx, box.ny, box.nz, el)}
 
 
-def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=False):
+def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=False,
+             lattice="d3q27"):
     """Initialise, autotune, time `steps` steps; return throughput, per-kernel
     event timings and (optionally) the final fields of box 0."""
     import torch
@@ -157,7 +164,7 @@ def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=False):
     sim = pkg.Simulation([pkg.box_params_of(w.box) for w in workloads],
                          [w.rho_r for w in workloads], [w.rho_b for w in workloads],
                          [w.u for w in workloads], seed=workloads[0].seed,
-                         noise=workloads[0].noise, storage=STORAGES[storage])
+                         noise=workloads[0].noise, storage=STORAGES[storage], lattice=lattice)
     fluid = sum(w.box.fluid_nodes() for w in workloads)
     d0 = sim.reduce()
     sim.step(2)
@@ -166,7 +173,7 @@ def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=False):
         tune_ms = []
     else:
         tune_ms = sim.autotune(reps=5)
-    var = pkg.variant_info(sim.variant())
+    var = pkg.variant_info(sim.variant(), lattice)
     sim.step(max(warmup - 2, 0))  # also captures the step graph
     torch.cuda.synchronize()
     # timed region: direct launches with HIP events around every kernel
@@ -185,7 +192,7 @@ def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=False):
     torch.cuda.synchronize()
     graph_mlups = fluid * ngraph / (time.perf_counter() - t2) / 1e6
     d1 = sim.reduce()
-    kb = kernel_bytes(storage)
+    kb = kernel_bytes(storage) if lattice == "d3q27" else {"fused": D2Q9_BYTES}
     kern = {}
     for k, (ms, cnt) in prof.items():
         if cnt:
@@ -205,6 +212,45 @@ def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=False):
     sim.close()
     del sim
     torch.cuda.empty_cache()
+    return out
+
+
+def d2q9_form(steps, warmup):
+    """The two-dimensional model of App. A: throughput on a 4096^2 field of
+    256 droplets (density ratio 10, carried at U = 0.05)."""
+    w = WL.droplets_2d()
+    r = run_form([w], "fp32", steps, warmup, lattice="d2q9")
+    k = r["kernels"]["fused"]
+    out = {"workload": "4096^2 periodic, 16 x 16 droplets R=48, density ratio 10, U=0.05, FP32",
+           "nodes": r["fluid"], "steps": steps, "mlups": round(r["mlups"], 1),
+           "graph_mlups": round(r["graph_mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+           "kernel": {"name": "k2_step<%d, %d, 256, false>" % (r["variant"]["tx"], r["variant"]["ty"]),
+                      "avg_ms": round(k["avg_ms"], 4), "gbs": round(k["gbs"], 1),
+                      "algorithmic_bytes_per_node": D2Q9_BYTES,
+                      "frac": round(k["gbs"] / HBM_PEAK_GBS, 4)},
+           "autotune_ms": [round(m, 4) for m in r["autotune_ms"]],
+           "mass_drift": r["mass_drift"], "nonfinite": r["nonfinite"]}
+    return out
+
+
+def table2_form():
+    """Table II's stationary droplets in two dimensions (eight 100^2 boxes in
+    one batch, 20000 steps): the surface tension from Laplace's law
+    (Eq. 68), sigma_cal = R_eff (p_in - p_out), and its error."""
+    import paper_2309_07801_amd as pkg
+    out = {}
+    cases = ((1, 0.012), (1, 0.072), (1, 0.24), (2, 0.112), (10, 0.132), (30, 0.1116),
+             (100, 0.10), (1000, 0.10))
+    ws = [WL.stationary_droplet_2d(gamma=float(g), sigma=s) for g, s in cases]
+    sim = pkg.Simulation([pkg.box_params_of(x.box) for x in ws], [x.rho_r for x in ws],
+                         [x.rho_b for x in ws], [x.u for x in ws], lattice="d2q9")
+    sim.step(ws[0].steps)
+    d = sim.reduce(centres=[x.centres[0] for x in ws])
+    sim.close()
+    out["cases"] = [{"gamma": g, "sigma_th": s,
+                        "sigma_cal": round(float(d[k, 7] * (d[k, 5] - d[k, 6])), 6),
+                        "E_percent": round(float(abs(d[k, 7] * (d[k, 5] - d[k, 6]) - s) / s * 100), 3)}
+                       for k, (g, s) in enumerate(cases)]
     return out
 
 
@@ -401,6 +447,10 @@ def main():
             forms["rti"] = rti_form()
         elif f == "galilean":
             forms["galilean"] = galilean_form()
+        elif f == "d2q9":
+            forms["d2q9"] = d2q9_form(min(args.steps, 2000), args.warmup)
+        elif f == "table2":
+            forms["table2"] = table2_form()
     if forms:
         line["forms"] = forms
     if not args.no_cpu_baseline:

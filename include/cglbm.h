@@ -174,6 +174,11 @@ int cglbm_init_d2q9(cglbm_handle **out, int32_t n_boxes, const cglbm_box_params 
  * for NULL. */
 int cglbm_lattice(const cglbm_handle *h);
 
+/* Tile shape of D2Q9 variant v (0..3): info[0] = x extent, info[1] = y
+ * extent of the tile one 256-thread block updates.  CGLBM_EINVAL for other
+ * v or a NULL info. */
+int cglbm_variant_info_d2q9(int32_t v, int32_t *info);
+
 /* Advance every box by n_steps time steps (steps 1-5 above).  Asynchronous. */
 int cglbm_step(cglbm_handle *h, int32_t n_steps, void *stream);
 

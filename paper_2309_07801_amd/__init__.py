@@ -39,7 +39,7 @@ EXPORTED = ("cglbm_query_sizes", "cglbm_init", "cglbm_step", "cglbm_moments", "c
             "cglbm_variant_info", "cglbm_set_variant", "cglbm_get_variant", "cglbm_autotune",
             "cglbm_profile_begin", "cglbm_profile_end", "cglbm_destroy",
             "cglbm_last_error", "cglbm_version", "cglbm_query_sizes_d2q9", "cglbm_init_d2q9",
-            "cglbm_lattice")
+            "cglbm_lattice", "cglbm_variant_info_d2q9")
 # Lattices: the D3Q27 model of the paper's body and the D2Q9 model of App. A.
 LATTICES = ("d3q27", "d2q9")
 NUM_VARIANTS_D2Q9 = 4
@@ -115,6 +115,7 @@ def lib():
         L.cglbm_query_sizes_d2q9.argtypes = L.cglbm_query_sizes.argtypes
         L.cglbm_init_d2q9.argtypes = L.cglbm_init.argtypes
         L.cglbm_lattice.argtypes = [vp]
+        L.cglbm_variant_info_d2q9.argtypes = [i32, C.POINTER(i32)]
         L.cglbm_step.argtypes = [vp, i32, vp]
         L.cglbm_moments.argtypes = [vp, i32, u32, vp, vp]
         L.cglbm_reduce.argtypes = [vp, C.POINTER(C.c_double), vp, i32, vp]
@@ -135,7 +136,7 @@ def lib():
         L.cglbm_last_error.restype = C.c_char_p
         L.cglbm_version.restype = C.c_char_p
         for fn in ("cglbm_query_sizes", "cglbm_init", "cglbm_query_sizes_d2q9", "cglbm_init_d2q9",
-                   "cglbm_lattice", "cglbm_step", "cglbm_moments",
+                   "cglbm_lattice", "cglbm_variant_info_d2q9", "cglbm_step", "cglbm_moments",
                    "cglbm_reduce", "cglbm_set_schedule", "cglbm_get_schedule", "cglbm_set_graph",
                    "cglbm_num_variants",
                    "cglbm_variant_info", "cglbm_set_variant", "cglbm_get_variant",
@@ -168,8 +169,11 @@ def num_variants() -> int:
     return int(lib().cglbm_num_variants())
 
 
-def variant_info(v: int):
+def variant_info(v: int, lattice: str = "d3q27"):
     info = (C.c_int32 * 4)()
+    if _lattice_id(lattice) == 1:
+        _check(lib().cglbm_variant_info_d2q9(int(v), info))
+        return {"tx": info[0], "ty": info[1]}
     _check(lib().cglbm_variant_info(int(v), info))
     return {"tx": info[0], "ty": info[1], "zc": info[2], "min_waves": info[3]}
 

@@ -845,6 +845,14 @@ int cglbm_variant_info(int32_t v, int32_t *info) {
   return CGLBM_OK;
 }
 
+int cglbm_variant_info_d2q9(int32_t v, int32_t *info) {
+  g_err.clear();
+  if (v < 0 || v >= kNumV2 || !info) return fail(CGLBM_EINVAL, "bad D2Q9 variant %d", v);
+  info[0] = kVariants2[v].tx;
+  info[1] = kVariants2[v].ty;
+  return CGLBM_OK;
+}
+
 int cglbm_set_variant(cglbm_handle *h, int32_t v, void *stream) {
   g_err.clear();
   if (!h) return fail(CGLBM_ESTATE, "null handle");
