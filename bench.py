@@ -342,6 +342,7 @@ def proxy_errors(g, ref, u_ref):
 
 
 def main():
+    T0 = time.perf_counter()
     args = parse()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -403,6 +404,8 @@ def main():
         "mass_drift": main_r["mass_drift"],
         "nonfinite": main_r["nonfinite"],
     }
+    print("bench: main line %.1f MLUPS (%.1f s)" % (main_r["mlups"], time.perf_counter() - T0),
+          file=sys.stderr, flush=True)
     forms = {}
     u_ref = 0.05
     for f in forms_req:
@@ -451,10 +454,14 @@ def main():
             forms["d2q9"] = d2q9_form(min(args.steps, 2000), args.warmup)
         elif f == "table2":
             forms["table2"] = table2_form()
+        print("bench: form %s done (%.1f s)" % (f, time.perf_counter() - T0), file=sys.stderr,
+              flush=True)
     if forms:
         line["forms"] = forms
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        print("bench: cpu baseline done (%.1f s)" % (time.perf_counter() - T0), file=sys.stderr,
+              flush=True)
     print(json.dumps(line), flush=True)
 
 
