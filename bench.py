@@ -36,14 +36,14 @@ import workloads as WL  # noqa: E402  (seeded inputs; numpy only)
 
 HBM_PEAK_GBS = 8000.0
 GRAPH_STEPS = 500   # steps of the graph-replay run after the timed region
-STORAGES = {"fp32": 0, "fp16": 1, "bf16": 2, "fp32x": 3}
+STORAGES = {"fp32": 0, "fp16": 1, "bf16": 2, "fp32x": 3, "fp32p": 4}
 DTYPE = {"fp32": "f32", "fp16": "f16 storage, f32 arithmetic", "bf16": "bf16 storage, f32 arithmetic",
-         "fp32x": "f32"}
+         "fp32x": "f32", "fp32p": "f32"}
 
 
 def kernel_bytes(storage: str):
     """Algorithmic bytes per node of each kernel: what it must read and write."""
-    if storage == "fp32":
+    if storage in ("fp32", "fp32p"):
         pops, aux_rho = 54 * 4, 0
     else:
         s = 4 if storage == "fp32x" else 2
@@ -424,9 +424,10 @@ def main():
         elif f == "batched":
             boxes = WL.batched_boxes()
             steps_b = min(args.steps, 1000)
-            r = run_form(boxes, "fp32", steps_b, args.warmup, args.variant)
+            r = run_form(boxes, "fp32p", steps_b, args.warmup, args.variant)
             forms["batched"] = {"workload": "96 periodic boxes, edges U{24..128}, density ratio "
-                                            "in {1,10,100}, FP32", "nodes": r["fluid"],
+                                            "in {1,10,100}, FP32 (colour-pair layout)",
+                                "nodes": r["fluid"],
                                 "steps": steps_b, "mlups": round(r["mlups"], 1),
                                 "ms_per_step": round(r["ms_per_step"], 4),
                                 "graph_mlups": round(r["graph_mlups"], 1),

@@ -104,14 +104,19 @@ typedef struct {
 } cglbm_box_params;
 
 /* Population storage formats.  Arithmetic is FP32 in all cases.
- *   CGLBM_FP32        54 float planes.
+ *   CGLBM_FP32        54 float planes (colour c, direction i: plane 27c + i).
+ *   CGLBM_FP32_PAIRS  the same values as CGLBM_FP32, bit for bit, stored as
+ *                     27 planes of colour pairs (8 bytes: red, then blue):
+ *                     faster for batches of small boxes, slower for large
+ *                     ones (the same buffer sizes).
  *   CGLBM_FP16_SHIFT  the 26 moving directions of each colour in IEEE half,
  *                     stored as f^k_i - s^k_i with s^k_i = w_i rho_k^0
  *                     (c_s^k)^2 / c_s^2 (the pure-phase rest equilibrium of
  *                     colour k, rounded to half); rest populations in FP64.
  *   CGLBM_BF16_SHIFT  the same with bfloat16.
  *   CGLBM_FP32_EXACT  moving directions in float, rest populations in FP64.
- * The three last formats carry the colour densities in FP64 from the pull to
+ * FP16_SHIFT, BF16_SHIFT and FP32_EXACT store colour pairs as well and carry
+ * the colour densities in FP64 from the pull to
  * the collision and set each rest population so that the node's colour mass
  * equals the FP64 sum of what the next step reads back: per-colour mass is
  * conserved to FP64 rounding. */
@@ -119,7 +124,8 @@ typedef enum {
   CGLBM_FP32 = 0,
   CGLBM_FP16_SHIFT = 1,
   CGLBM_BF16_SHIFT = 2,
-  CGLBM_FP32_EXACT = 3
+  CGLBM_FP32_EXACT = 3,
+  CGLBM_FP32_PAIRS = 4
 } cglbm_storage;
 
 typedef struct cglbm_handle cglbm_handle;

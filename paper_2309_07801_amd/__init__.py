@@ -23,9 +23,9 @@ LIB_PATH = os.path.join(_HERE, "libcglbm.so")
 CGLBM_OK = 0
 ERRORS = {-1: "CGLBM_EINVAL", -2: "CGLBM_EHIP", -3: "CGLBM_EUNSUPPORTED",
           -4: "CGLBM_EUNSTABLE", -5: "CGLBM_ESTATE"}
-FP32, FP16_SHIFT, BF16_SHIFT, FP32_EXACT = 0, 1, 2, 3
+FP32, FP16_SHIFT, BF16_SHIFT, FP32_EXACT, FP32_PAIRS = 0, 1, 2, 3, 4
 STORAGE_NAMES = {FP32: "fp32", FP16_SHIFT: "fp16_shift", BF16_SHIFT: "bf16_shift",
-                 FP32_EXACT: "fp32_exact"}
+                 FP32_EXACT: "fp32_exact", FP32_PAIRS: "fp32_pairs"}
 NDIAG = 13
 DIAG_NAMES = ("M_r", "M_b", "Px", "Py", "Pz", "p_in", "p_out", "R_eff", "cx", "cy", "cz",
               "KE", "n_nonfinite")

@@ -50,7 +50,7 @@ constexpr int kTX = 8, kTY = 8, kTZ = 8;   // interface tile (three-kernel sched
 using FusedFn = void (*)(const BoxDev *, const int32_t *, float *, void *, int64_t);
 struct FusedVariant {
   int tx, ty, zc, minw;
-  FusedFn fn[4][2];  // time step: [storage][any box with solid layers]
+  FusedFn fn[5][2];  // time step: [storage][any box with solid layers]
   FusedFn fx[2];     // field export (no population store): [solid layers]
 };
 #define FV_S(TX, TY, ZC, MW, S) \
@@ -58,7 +58,7 @@ struct FusedVariant {
 #define FV(TX, TY, ZC, MW)                                                                    \
   {TX, TY, ZC, MW,                                                                           \
    {FV_S(TX, TY, ZC, MW, StoreF32), FV_S(TX, TY, ZC, MW, StoreF16), FV_S(TX, TY, ZC, MW, StoreBF16), \
-    FV_S(TX, TY, ZC, MW, StoreF32X)},                                                        \
+    FV_S(TX, TY, ZC, MW, StoreF32X), FV_S(TX, TY, ZC, MW, StoreF32P)},                       \
    {k_fused<TX, TY, ZC, MW, false, StoreF32, true>, k_fused<TX, TY, ZC, MW, true, StoreF32, true>}}
 const FusedVariant kFusedVariants[] = {
     FV(32, 8, 32, 4),  FV(32, 8, 64, 4),  FV(32, 8, 16, 4), FV(32, 8, 32, 1),
@@ -100,11 +100,13 @@ using CollideFn = void (*)(const BoxDev *, const int32_t *, float *, const void 
                           int64_t);
 using InitFn = void (*)(const BoxDev *, const int32_t *, const float *, const float *,
                         const float *, void *, int64_t, uint64_t, float);
-const PullFn kPull[4] = {k_pull<StoreF32>, k_pull<StoreF16>, k_pull<StoreBF16>, k_pull<StoreF32X>};
-const CollideFn kCollide[4] = {k_collide<StoreF32>, k_collide<StoreF16>, k_collide<StoreBF16>,
-                               k_collide<StoreF32X>};
-const InitFn kInit[4] = {k_init<StoreF32>, k_init<StoreF16>, k_init<StoreBF16>, k_init<StoreF32X>};
-bool storage_exact(int32_t st) { return st != CGLBM_FP32; }
+const PullFn kPull[5] = {k_pull<StoreF32>, k_pull<StoreF16>, k_pull<StoreBF16>, k_pull<StoreF32X>,
+                         k_pull<StoreF32P>};
+const CollideFn kCollide[5] = {k_collide<StoreF32>, k_collide<StoreF16>, k_collide<StoreBF16>,
+                               k_collide<StoreF32X>, k_collide<StoreF32P>};
+const InitFn kInit[5] = {k_init<StoreF32>, k_init<StoreF16>, k_init<StoreBF16>, k_init<StoreF32X>,
+                         k_init<StoreF32P>};
+bool storage_exact(int32_t st) { return st != CGLBM_FP32 && st != CGLBM_FP32_PAIRS; }
 size_t storage_bytes(int32_t st) { return (st == CGLBM_FP16_SHIFT || st == CGLBM_BF16_SHIFT) ? 2 : 4; }
 
 // Bytes of one population buffer and of the aux buffer for `total` nodes.
@@ -133,7 +135,7 @@ struct Layout {
 
 int validate(int32_t n_boxes, const cglbm_box_params *boxes, int32_t storage) {
   if (n_boxes <= 0 || !boxes) return fail(CGLBM_EINVAL, "n_boxes must be > 0 and boxes non-NULL");
-  if (storage < CGLBM_FP32 || storage > CGLBM_FP32_EXACT)
+  if (storage < CGLBM_FP32 || storage > CGLBM_FP32_PAIRS)
     return fail(CGLBM_EINVAL, "unknown storage format %d", storage);
   int64_t total = 0;
   for (int b = 0; b < n_boxes; ++b) {

@@ -1,17 +1,21 @@
 // kernels.hpp -- HIP kernels (gfx950) of the colour-gradient LBM time step.
 //
 // Storage (all boxes concatenated, SoA planes of `plane` elements):
-//   populations  pop[c*27 + i][node]   c = 0 red, 1 blue; i in Eq. (1) order
+//   populations  FP32: pop[c*27 + i][node], c = 0 red, 1 blue, i in Eq. (1)
+//                order; mass-exact formats: colour pairs of the 26 moving
+//                directions, then the FP64 rest populations (see Pops)
 //   aux          aux[k][node], float:
 //     0 rho_r  1 rho_b  2..4 j = sum_i f_i c_i  5..10 Pi_xx,yy,zz,xy,xz,yz
 //     11..13 n  14..16 F  17..19 Q  20 kappa (only written on request)
 //
-// One step = three launches:
+// One step = two launches (schedule 0):
 //   k_pull     pull-stream (Eq. 5) + local moments; bounce-back at solid nodes
-//   k_interface  LDS-tiled stencils: phi, grad phi, n, kappa, F, u, Q
-//              (Eqs. 11, 14-17, 20, 65)
-//   k_collide  central-moment collision with the generalized equilibrium
-//              (Eqs. 25, 57-63, 66-67), recolouring (Eqs. 18-19), local store
+//   k_fused    z-marching interface stencils (Eqs. 11, 14-17, 20, 65) and
+//              the collision with the generalized equilibrium (Eqs. 25,
+//              57-63, 66-67) and recolouring (Eqs. 18-19), local store
+// or three (schedule 1, and general models or rates):
+//   k_pull, then k_interface (LDS-tiled stencils: phi, grad phi, n, kappa,
+//   F, u, Q) and k_collide (collision, recolouring, local store)
 #pragma once
 
 #include <hip/hip_fp16.h>
@@ -173,9 +177,9 @@ __device__ __forceinline__ bool is_solid(const BoxDev &B, int y, int z) {
 // Population storage formats.
 //
 // Plain FP32: 54 float planes, plane c*27 + i.
-// Mass-exact formats: the 26 moving directions of each colour are stored in
-// type T, plane c*26 + (i - 1), and the two rest populations in FP64 planes
-// after them.  The collision sets the rest population from the node's
+// Mass-exact formats: the 26 moving directions are stored in type T as
+// colour pairs, pair plane i - 1, and the two rest populations in FP64
+// planes after them.  The collision sets the rest population from the node's
 // colour density (carried in FP64) minus the 26 stored moving populations
 // as they will be read back, so each colour's mass is conserved to FP64
 // rounding whatever the storage precision.  FP16/BF16 store each moving
@@ -183,10 +187,17 @@ __device__ __forceinline__ bool is_solid(const BoxDev &B, int y, int z) {
 // s^k_i = w_i rho_k^0 (c_s^k)^2 / c_s^2, rounded to T (zero stays exact).
 // ---------------------------------------------------------------------------
 // A direction's red and blue populations stream from and to the same node,
-// so they are stored as one pair word (red in the low half): one memory
-// access moves both.
+// so the mass-exact formats store them as one pair word (red in the low
+// half): one memory access moves both.  Plain FP32 keeps one plane per
+// colour and direction: its collision kernel stores the populations faster
+// that way, and its pull loses less than the collision gains (measured).
+struct Split32 {
+  using W = float;  // one plane element
+  static constexpr bool kPaired = false;
+};
 struct Pair32 {
   using W = uint64_t;
+  static constexpr bool kPaired = true;
   __device__ static W pack(float r, float b) {
     return (uint64_t)__builtin_bit_cast(uint32_t, r) | ((uint64_t)__builtin_bit_cast(uint32_t, b) << 32);
   }
@@ -195,11 +206,20 @@ struct Pair32 {
 };
 struct Pair16 {
   using W = uint32_t;
+  static constexpr bool kPaired = true;
   __device__ static W pack(uint16_t r, uint16_t b) { return (uint32_t)r | ((uint32_t)b << 16); }
   __device__ static uint16_t lo(W w) { return (uint16_t)w; }
   __device__ static uint16_t hi(W w) { return (uint16_t)(w >> 16); }
 };
-struct StoreF32 : Pair32 {
+struct StoreF32 : Split32 {
+  using T = float;
+  static constexpr bool kExact = false, kShift = false;
+  __device__ static T enc(float v) { return v; }
+  __device__ static float dec(T g) { return g; }
+};
+// Plain FP32 in colour pairs: the same values as StoreF32, another layout
+// (27 pair planes); faster where many small boxes leave tiles ragged.
+struct StoreF32P : Pair32 {
   using T = float;
   static constexpr bool kExact = false, kShift = false;
   __device__ static T enc(float v) { return v; }
@@ -231,22 +251,27 @@ struct StoreBF16 : Pair16 {
 
 __host__ __device__ inline int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
 
-// Views of one population buffer: pair planes of the moving (mass-exact
-// formats) or of all directions, then (mass-exact formats) the FP64 rest
+// Views of one population buffer.  Plain FP32: 54 float planes, plane
+// c*27 + i (paired: 27 pair planes, plane i).  Mass-exact formats: 26 pair
+// planes of the moving directions (plane i - 1), then the FP64 rest
 // populations of the two colours.
 template <class S>
 struct Pops {
   using W = typename S::W;
-  static constexpr int kPairs = S::kExact ? 26 : 27;
+  static constexpr int kDirs = S::kExact ? 26 : 27;  // stored directions per colour
+  static constexpr int kPlanes = S::kPaired ? kDirs : 2 * kDirs;
   W *pw;
   double *rest;
   int64_t plane;
   __device__ Pops(void *base, int64_t plane_) : plane(plane_) {
     pw = (W *)base;
-    rest = (double *)((char *)base + align256(kPairs * plane_ * (int64_t)sizeof(W)));
+    rest = (double *)((char *)base + align256(kPlanes * plane_ * (int64_t)sizeof(W)));
   }
-  __device__ static int slot(int i) { return S::kExact ? i - 1 : i; }
-  __device__ W *pair(int i) const { return pw + (int64_t)slot(i) * plane; }
+  // plane of direction i (paired), or of direction i and colour c (split)
+  __device__ static int slot(int i, int c = 0) {
+    return (S::kExact ? i - 1 : i) + (S::kPaired ? 0 : c * kDirs);
+  }
+  __device__ W *plane_of(int i, int c = 0) const { return pw + (int64_t)slot(i, c) * plane; }
   __device__ double *restp(int c) const { return rest + (int64_t)c * plane; }
 };
 
@@ -270,6 +295,30 @@ __device__ __forceinline__ W ld(const W *p) {
 template <class W>
 __device__ __forceinline__ void st(W *p, W v) {
   __builtin_nontemporal_store(v, p);
+}
+
+// Both colours of direction i at node s, as stored (values of S::T).
+template <class S>
+__device__ __forceinline__ void ld_rb(const Pops<S> &p, int i, uint32_t s, typename S::T &r,
+                                      typename S::T &b) {
+  if constexpr (S::kPaired) {
+    const typename S::W w = ld(&at(p.plane_of(i), s));
+    r = S::lo(w);
+    b = S::hi(w);
+  } else {
+    r = ld(&at(p.plane_of(i, 0), s));
+    b = ld(&at(p.plane_of(i, 1), s));
+  }
+}
+template <class S>
+__device__ __forceinline__ void st_rb(const Pops<S> &p, int i, uint32_t d, typename S::T r,
+                                      typename S::T b) {
+  if constexpr (S::kPaired) {
+    st(&at(p.plane_of(i), d), S::pack(r, b));
+  } else {
+    st(&at(p.plane_of(i, 0), d), r);
+    st(&at(p.plane_of(i, 1), d), b);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -307,12 +356,12 @@ __global__ __launch_bounds__(kBlock) void k_pull(const BoxDev *__restrict__ boxe
       row[a][c] = (uint32_t)B.base + (uint32_t)nx * ((uint32_t)ys[a] + (uint32_t)ny * (uint32_t)zs[c]);
   const uint32_t node = (uint32_t)(B.base + local);
 
-  typename S::W gw[kQ];
+  typename S::T gr[kQ], gb[kQ];
   constexpr int i0 = S::kExact ? 1 : 0;
 #pragma unroll
   for (int i = i0; i < kQ; ++i) {
     const uint32_t s = row[kCY[i] + 1][kCZ[i] + 1] + (uint32_t)xs[kCX[i] + 1];
-    gw[i] = ld(&at(src.pair(i), s));
+    ld_rb(src, i, s, gr[i], gb[i]);
   }
   double rr0 = 0.0, rb0 = 0.0;
   if (S::kExact) {
@@ -323,7 +372,7 @@ __global__ __launch_bounds__(kBlock) void k_pull(const BoxDev *__restrict__ boxe
     if (bounce) {
       // the shift of direction i equals that of its opposite: copy raw pairs
 #pragma unroll
-      for (int i = i0; i < kQ; ++i) st(&at(dst.pair(opposite(i)), node), gw[i]);
+      for (int i = i0; i < kQ; ++i) st_rb(dst, opposite(i), node, gr[i], gb[i]);
       if (S::kExact) {
         at(dst.restp(0), node) = rr0;
         at(dst.restp(1), node) = rb0;
@@ -343,8 +392,8 @@ __global__ __launch_bounds__(kBlock) void k_pull(const BoxDev *__restrict__ boxe
   double drr = rr0, drb = rb0;
 #pragma unroll
   for (int i = i0; i < kQ; ++i) {
-    const float vr = S::dec(S::lo(gw[i])) + pop_shift<S>(B, 0, i);
-    const float vb = S::dec(S::hi(gw[i])) + pop_shift<S>(B, 1, i);
+    const float vr = S::dec(gr[i]) + pop_shift<S>(B, 0, i);
+    const float vb = S::dec(gb[i]) + pop_shift<S>(B, 1, i);
     if (S::kExact) {
       drr += (double)vr;
       drb += (double)vb;
@@ -836,8 +885,9 @@ __device__ __forceinline__ void pull_total(const BoxDev &B, const void *src_, in
   for (int i = i0; i < kQ; ++i) {
     const uint32_t s = (uint32_t)B.base + (uint32_t)xs[kCX[i] + 1] +
                        (uint32_t)nx * ((uint32_t)ys[kCY[i] + 1] + (uint32_t)ny * (uint32_t)zs[kCZ[i] + 1]);
-    const typename S::W w = ld(&at(src.pair(i), s));
-    f[i] = (S::dec(S::lo(w)) + pop_shift<S>(B, 0, i)) + (S::dec(S::hi(w)) + pop_shift<S>(B, 1, i));
+    typename S::T r, b;
+    ld_rb(src, i, s, r, b);
+    f[i] = (S::dec(r) + pop_shift<S>(B, 0, i)) + (S::dec(b) + pop_shift<S>(B, 1, i));
   }
   if (S::kExact) f[0] = (float)(at(src.restp(0), node) + at(src.restp(1), node));
 }
@@ -886,7 +936,12 @@ struct PopWriter {
     const typename S::T er = S::enc(fr - shr), eb = S::enc(fb - shb);
     using W = typename S::W;
     const int64_t pb = dst.plane * (int64_t)sizeof(W);
-    buf_st(S::pack(er, eb), plane_rsrc(dst.pw, pb, Pops<S>::slot(i)), boff<W>(live, node));
+    if constexpr (S::kPaired) {
+      buf_st(S::pack(er, eb), plane_rsrc(dst.pw, pb, Pops<S>::slot(i)), boff<W>(live, node));
+    } else {
+      buf_st(er, plane_rsrc(dst.pw, pb, Pops<S>::slot(i, 0)), boff<W>(live, node));
+      buf_st(eb, plane_rsrc(dst.pw, pb, Pops<S>::slot(i, 1)), boff<W>(live, node));
+    }
     if (S::kExact) {
       sr += (double)(S::dec(er) + shr);
       sb += (double)(S::dec(eb) + shb);
@@ -987,7 +1042,7 @@ __global__ __launch_bounds__(kBlock) void k_init(const BoxDev *__restrict__ boxe
                        (uint32_t)B.nx * ((uint32_t)yd + (uint32_t)B.ny * (uint32_t)zd);
     const float shr = pop_shift<S>(B, 0, i), shb = pop_shift<S>(B, 1, i);
     const typename S::T er = S::enc(vr - shr), eb = S::enc(vb - shb);
-    st(&at(dst.pair(i), d), S::pack(er, eb));
+    st_rb(dst, i, d, er, eb);
     sr += (double)(S::dec(er) + shr);
     sb += (double)(S::dec(eb) + shb);
   }

@@ -67,6 +67,9 @@ def test_storage_buffer_sizes():
     assert pop16 == align(52 * total * 2) + 2 * total * 8
     assert popx == align(52 * total * 4) + 2 * total * 8
     assert aux16 == align(21 * total * 4) + 2 * total * 8 == auxx
+    assert pkg.query_sizes(pb, pkg.FP32_PAIRS) == (pop32, aux32, total)
+    with pytest.raises(pkg.CglbmError):
+        pkg.query_sizes(pb, 5)
 
 
 def test_phase_validation_and_storage():
