@@ -63,7 +63,7 @@ struct FusedVariant {
 const FusedVariant kFusedVariants[] = {
     FV(32, 8, 32, 4),  FV(32, 8, 64, 4),  FV(32, 8, 16, 4), FV(32, 8, 32, 1),
     FV(32, 16, 32, 4), FV(32, 16, 64, 4), FV(64, 4, 32, 4), FV(32, 4, 32, 4),
-    FV(32, 8, 32, 5),
+    FV(32, 8, 32, 5),  FV(64, 8, 64, 4),  FV(64, 8, 32, 4),
 };
 #undef FV
 #undef FV_S

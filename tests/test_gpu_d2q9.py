@@ -212,3 +212,32 @@ def test_table_ii_surface_tension():
     for g, e, drift in res:
         assert e < 1.0, (g, e)
         assert drift <= 5e-4, (g, drift)
+
+
+def test_reduce_matches_oracle_fields():
+    """FP64 diagnostics of a D2Q9 box: colour masses, momentum, R_eff =
+    (A/pi)^(1/2) with A = sum (1 + phi)/2, the Laplace pressures over the
+    bands |x - c| < R_eff - 3 and > R_eff + 5, and the red centroid, against
+    the same sums over the oracle's fields."""
+    box = _box((61, 47), gamma=5.0, sigma=0.02)
+    c = (30.0, 23.0, 0.0)
+    fl = WL.droplet_fields(box, [c], [12.0], u_carrier=(0.03, 0.01, 0.0))
+    sim = _sim([box], [fl], seed=2, noise=1e-6)
+    sim.step(20)
+    d = sim.reduce(centres=[c])[0]
+    sim.close()
+    o, _ = run_oracle_2d(box, *fl, 20, seed=2, noise=1e-6)
+    rho = o["rho_r"] + o["rho_b"]
+    assert d[0] == pytest.approx(o["rho_r"].sum(), rel=1e-6)
+    assert d[1] == pytest.approx(o["rho_b"].sum(), rel=1e-6)
+    assert d[2] == pytest.approx((rho * o["ux"]).sum(), rel=1e-4)
+    assert d[3] == pytest.approx((rho * o["uy"]).sum(), rel=1e-4)
+    assert d[4] == 0
+    A = ((1 + o["phi"]) / 2).sum()
+    reff = np.sqrt(A / np.pi)
+    assert d[7] == pytest.approx(reff, rel=1e-6)
+    dist = WL.periodic_distance((box.nx, box.ny, 1), c)
+    p = o["p"]
+    assert d[5] == pytest.approx(p[dist < reff - 3].mean(), rel=1e-5)
+    assert d[6] == pytest.approx(p[dist > reff + 5].mean(), rel=1e-5)
+    assert d[12] == 0
