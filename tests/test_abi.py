@@ -113,3 +113,22 @@ def test_d2q9_sizes_and_validation():
     assert ei.value.code == -3
     with pytest.raises(ValueError):
         pkg.query_sizes(p, pkg.FP32, lattice="d3q19")
+
+
+def test_empty_and_oversized_inputs_are_rejected():
+    """No boxes, and all boxes together beyond the node limit (every plane of
+    8-byte values must stay below 4 GiB), are CGLBM_EINVAL on the host."""
+    import ctypes as C
+    pop, aux, tot = C.c_size_t(), C.c_size_t(), C.c_int64()
+    rc = pkg.lib().cglbm_query_sizes(0, None, pkg.FP32, C.byref(pop), C.byref(aux), C.byref(tot))
+    assert rc == -1
+    big = WL.two_phase_box((1024, 1024, 512), 10.0, 1.0, 0.8, 0.01, 0.7)   # 2^29 nodes
+    with pytest.raises(pkg.CglbmError) as ei:
+        pkg.query_sizes([pkg.box_params_of(big)])
+    assert ei.value.code == -1
+    # just below the limit in two boxes: accepted, total stays under 2^29 nodes
+    a = WL.two_phase_box((1024, 1024, 255), 10.0, 1.0, 0.8, 0.01, 0.7)
+    pop_b, aux_b, total = pkg.query_sizes([pkg.box_params_of(a), pkg.box_params_of(a)])
+    assert total < (1 << 29) and pop_b == 54 * 4 * total
+    with pytest.raises(pkg.CglbmError):
+        pkg.query_sizes([pkg.box_params_of(a)] * 3)

@@ -5,6 +5,8 @@ rounds each population a few dozen times; differences then grow slowly with
 the step count through the nonlinear recolouring and curvature terms.  The
 bars below are the spec bar for FP32 (1e-5 relative after 1000 steps)
 or tighter for short runs; every test prints its measured errors."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -209,3 +211,39 @@ def test_fused_variants_agree_bitwise_and_autotune_keeps_state():
     g = gpu_fields(sim)
     for k in ref:
         assert np.array_equal(ref[k], g[k]), k
+
+
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_degenerate_boxes(schedule):
+    """The method's degenerate cases in one batch, each against the oracle
+    after 20 steps: a one-node box; a pure single phase (phi = 1 everywhere,
+    so the normal's guard holds at every node and F = Q = 0); beta = 0 and
+    sigma = 0 (no recolouring and no tension: the colours interdiffuse);
+    boxes one node wide in x and in y; the smallest walled box (ny = 3: a
+    single fluid row between the walls)."""
+    cases = []
+    one = WL.two_phase_box((1, 1, 1), 10.0, 1.0, 0.7, 0.01, 0.7)
+    cases.append((one, (np.full(one.shape, 1.0, np.float32), np.full(one.shape, 0.05, np.float32),
+                        np.full((3,) + one.shape, 0.01, np.float32))))
+    pure = WL.two_phase_box((9, 7, 6), 10.0, 1.0, 0.7, 0.01, 0.7)
+    u = np.zeros((3,) + pure.shape, np.float32)
+    u[0] = 0.02
+    cases.append((pure, (np.full(pure.shape, 1.0, np.float32), np.zeros(pure.shape, np.float32), u)))
+    cases.append(_case(shape=(8, 7, 6), sigma=0.0, R=2.5))
+    cases[-1] = (dataclasses.replace(cases[-1][0], beta=0.0), cases[-1][1])
+    cases.append(_case(shape=(1, 11, 9), R=3.0))
+    cases.append(_case(shape=(10, 1, 8), R=3.0))
+    cases.append(_case(shape=(9, 3, 7), R=2.0, walls=1))
+    boxes = [b for b, _ in cases]
+    sim = _sim(boxes, [f for _, f in cases], seed=8, noise=1e-6)
+    sim.set_schedule(schedule)
+    sim.step(20)
+    for k, (b, fl) in enumerate(cases):
+        o, _ = run_oracle(b, *fl, 20, seed=8, noise=1e-6, box_index=k)
+        g = gpu_fields(sim, k)
+        e = errors(g, o, b, 0.02)
+        print(k, (b.nx, b.ny, b.nz), e)
+        assert e["rho"] < 1e-5 and e["u"] < 1e-4 and e["phi"] < 1e-4, (k, e)
+        assert np.isfinite(g["kappa"]).all() and np.isfinite(g["Fx"]).all()
+    assert np.all(sim.reduce()[:, 12] == 0)
+    sim.close()
