@@ -16,7 +16,8 @@ storage (with their difference to the FP32 run as a proxy error), the
 96-box batched workload, the 32^3 static droplet, the Rayleigh-Taylor case
 at the paper's size (Models D and A), the translating droplet's
 deformation per equilibrium model, the two-dimensional model of App. A on a
-4096^2 droplet field (d2q9) and Table II's surface tensions (table2).  The timed region
+4096^2 droplet field (d2q9; d2q9_fp16 and d2q9_bf16 with 16-bit shifted
+storage) and Table II's surface tensions (table2).  The timed region
 launches every kernel directly (HIP events around each launch); after it,
 `graph_mlups` times the same update as replays of the captured two-step
 graph that cglbm_step uses by default.
@@ -56,9 +57,19 @@ def kernel_bytes(storage: str):
     }
 
 
-# D2Q9 step kernel (one launch per step): 9 colour pairs of 2 x float read
-# and written per node; every moment and interface field stays on chip.
-D2Q9_BYTES = 2 * 9 * 8
+# D2Q9 step kernel (one launch per step): the stored populations read and
+# written once per node (9 colour pairs of 2 x float; mass-exact formats: 8
+# pairs and the two FP64 rest populations); every moment and interface field
+# stays on chip.
+def d2q9_bytes(storage: str) -> int:
+    if storage in ("fp32", "fp32p"):
+        return 2 * 9 * 8
+    return 2 * (8 * (8 if storage == "fp32x" else 4) + 2 * 8)
+
+
+# storage format of the D2Q9 step kernel's template argument
+SNAMES = {"fp32": "StoreF32P", "fp32p": "StoreF32P", "fp16": "StoreF16", "bf16": "StoreBF16",
+          "fp32x": "StoreF32X"}
 
 
 def step_bytes(storage: str) -> int:
@@ -101,7 +112,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--size", type=int, default=256, help="box edge (default 256)")
     ap.add_argument("--storage", default="fp32", choices=sorted(STORAGES))
-    ap.add_argument("--forms", default="fp16,bf16,fp32x,batched,small,rti,galilean,d2q9,table2",
+    ap.add_argument("--forms", default="fp16,bf16,fp32x,batched,small,rti,galilean,d2q9,"
+                    "d2q9_fp16,d2q9_bf16,table2",
                     help="extra forms on the same workload ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -192,7 +204,7 @@ def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=False,
     torch.cuda.synchronize()
     graph_mlups = fluid * ngraph / (time.perf_counter() - t2) / 1e6
     d1 = sim.reduce()
-    kb = kernel_bytes(storage) if lattice == "d3q27" else {"fused": D2Q9_BYTES}
+    kb = kernel_bytes(storage) if lattice == "d3q27" else {"fused": d2q9_bytes(storage)}
     kern = {}
     for k, (ms, cnt) in prof.items():
         if cnt:
@@ -215,18 +227,20 @@ def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=False,
     return out
 
 
-def d2q9_form(steps, warmup):
+def d2q9_form(steps, warmup, storage="fp32"):
     """The two-dimensional model of App. A: throughput on a 4096^2 field of
     256 droplets (density ratio 10, carried at U = 0.05)."""
     w = WL.droplets_2d()
-    r = run_form([w], "fp32", steps, warmup, lattice="d2q9")
+    r = run_form([w], storage, steps, warmup, lattice="d2q9")
     k = r["kernels"]["fused"]
-    out = {"workload": "4096^2 periodic, 16 x 16 droplets R=48, density ratio 10, U=0.05, FP32",
+    out = {"workload": "4096^2 periodic, 16 x 16 droplets R=48, density ratio 10, U=0.05, %s"
+                       % storage.upper(),
            "nodes": r["fluid"], "steps": steps, "mlups": round(r["mlups"], 1),
            "graph_mlups": round(r["graph_mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
-           "kernel": {"name": "k2_step<%d, %d, 256, false>" % (r["variant"]["tx"], r["variant"]["ty"]),
+           "kernel": {"name": "k2_step<%s, %d, %d, 256, false>"
+                              % (SNAMES[storage], r["variant"]["tx"], r["variant"]["ty"]),
                       "avg_ms": round(k["avg_ms"], 4), "gbs": round(k["gbs"], 1),
-                      "algorithmic_bytes_per_node": D2Q9_BYTES,
+                      "algorithmic_bytes_per_node": d2q9_bytes(storage),
                       "frac": round(k["gbs"] / HBM_PEAK_GBS, 4)},
            "autotune_ms": [round(m, 4) for m in r["autotune_ms"]],
            "mass_drift": r["mass_drift"], "nonfinite": r["nonfinite"]}
@@ -453,6 +467,8 @@ def main():
             forms["galilean"] = galilean_form()
         elif f == "d2q9":
             forms["d2q9"] = d2q9_form(min(args.steps, 2000), args.warmup)
+        elif f in ("d2q9_fp16", "d2q9_bf16"):
+            forms[f] = d2q9_form(min(args.steps, 2000), args.warmup, f[5:])
         elif f == "table2":
             forms["table2"] = table2_form()
         print("bench: form %s done (%.1f s)" % (f, time.perf_counter() - T0), file=sys.stderr,

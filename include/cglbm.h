@@ -160,11 +160,17 @@ int cglbm_init(cglbm_handle **out, int32_t n_boxes, const cglbm_box_params *boxe
  * Sec. II in two dimensions and the correction term Q of Eq. (65) per
  * component.  Same box parameters, buffers, fields, diagnostics and calls as
  * the D3Q27 handle, with these restrictions: nz = 1 and no z walls
- * (CGLBM_EINVAL otherwise); storage FP32, model CGLBM_MODEL_D, omega_hi all 1
- * and gravity zero (CGLBM_EUNSUPPORTED otherwise); init_u is [3][total_nodes]
- * with its z plane ignored; z components of the fields are zero; the
- * diagnostic R_eff is (V/pi)^(1/2).  Populations: 9 planes of colour pairs
- * (2 x float, red first), 72 bytes per node; aux as for D3Q27.
+ * (CGLBM_EINVAL otherwise); model CGLBM_MODEL_D, omega_hi all 1 and gravity
+ * zero (CGLBM_EUNSUPPORTED otherwise); init_u is [3][total_nodes] with its z
+ * plane ignored; z components of the fields are zero; the diagnostic R_eff
+ * is (V/pi)^(1/2).  Populations: CGLBM_FP32 and CGLBM_FP32_PAIRS both keep 9
+ * planes of colour pairs (2 x float, red first), 72 bytes per node, bit for
+ * bit the same results; the mass-exact formats keep 8 planes of colour pairs
+ * of the moving directions (2 x half or bfloat16 stored minus
+ * w_i rho_k^0 (c_s^k)^2 / c_s^2 with the D2Q9 weights of Eq. (A2), or
+ * 2 x float), then the two FP64 rest planes, with the mass closure described
+ * for D3Q27 (48 or 80 bytes per node).  aux as for D3Q27 (with the FP64
+ * colour densities after it for the mass-exact formats).
  * One launch per step (the pull, the interface stencils and the collision
  * of a tile in one kernel); cglbm_set_schedule accepts 0 only; variants are
  * its tile shapes (4 of them), chosen by cglbm_autotune, which writes their

@@ -70,16 +70,25 @@ const FusedVariant kFusedVariants[] = {
 constexpr int kNumFused = (int)(sizeof(kFusedVariants) / sizeof(kFusedVariants[0]));
 
 // Tile shapes of the two-dimensional (D2Q9) step kernel, 256 threads each;
-// bitwise equal results, picked by cglbm_autotune.
-using Step2Fn = void (*)(const BoxDev *, const int32_t *, const d2q9::W *, d2q9::W *, float *,
-                         int64_t);
+// bitwise equal results, picked by cglbm_autotune.  Kernels per storage slot
+// (storage2_slot): FP32 pairs (for FP32 and FP32_PAIRS), FP16, BF16, FP32X.
+using Step2Fn = void (*)(const BoxDev *, const int32_t *, const void *, void *, float *, int64_t);
 struct Variant2 {
   int tx, ty;
-  Step2Fn step, fields;
+  Step2Fn step[4], fields[4];
 };
-#define V2(TX, TY) {TX, TY, d2q9::k2_step<TX, TY, 256, false>, d2q9::k2_step<TX, TY, 256, true>}
+#define V2_S(S, TX, TY) d2q9::k2_step<S, TX, TY, 256, false>
+#define V2_F(S, TX, TY) d2q9::k2_step<S, TX, TY, 256, true>
+#define V2(TX, TY)                                                                              \
+  {TX, TY,                                                                                      \
+   {V2_S(StoreF32P, TX, TY), V2_S(StoreF16, TX, TY), V2_S(StoreBF16, TX, TY),                   \
+    V2_S(StoreF32X, TX, TY)},                                                                   \
+   {V2_F(StoreF32P, TX, TY), V2_F(StoreF16, TX, TY), V2_F(StoreBF16, TX, TY),                   \
+    V2_F(StoreF32X, TX, TY)}}
 const Variant2 kVariants2[] = {V2(64, 16), V2(32, 32), V2(64, 8), V2(32, 16)};
 #undef V2
+#undef V2_S
+#undef V2_F
 constexpr int kNumV2 = (int)(sizeof(kVariants2) / sizeof(kVariants2[0]));
 enum { LATTICE_D3Q27 = 0, LATTICE_D2Q9 = 1 };
 constexpr int64_t kAlign = 64;             // node alignment of each box's base
@@ -106,14 +115,23 @@ const CollideFn kCollide[5] = {k_collide<StoreF32>, k_collide<StoreF16>, k_colli
                                k_collide<StoreF32X>, k_collide<StoreF32P>};
 const InitFn kInit[5] = {k_init<StoreF32>, k_init<StoreF16>, k_init<StoreBF16>, k_init<StoreF32X>,
                          k_init<StoreF32P>};
+const InitFn kInit2[4] = {d2q9::k2_init<StoreF32P>, d2q9::k2_init<StoreF16>,
+                           d2q9::k2_init<StoreBF16>, d2q9::k2_init<StoreF32X>};
+// D2Q9 keeps FP32 in colour pairs in either FP32 format
+int storage2_slot(int32_t st) { return st == CGLBM_FP32_PAIRS ? 0 : st; }
 bool storage_exact(int32_t st) { return st != CGLBM_FP32 && st != CGLBM_FP32_PAIRS; }
 size_t storage_bytes(int32_t st) { return (st == CGLBM_FP16_SHIFT || st == CGLBM_BF16_SHIFT) ? 2 : 4; }
 
 // Bytes of one population buffer and of the aux buffer for `total` nodes.
 void buffer_sizes(int32_t st, int64_t total, size_t *pop, size_t *aux, int lattice = LATTICE_D3Q27) {
   if (lattice == LATTICE_D2Q9) {
-    *pop = (size_t)(d2q9::kQ * total * (int64_t)sizeof(d2q9::W));
-    *aux = (size_t)((int64_t)A_COUNT * total * 4);
+    // pair planes (9, or 8 and the FP64 rest planes of the mass-exact formats)
+    const int64_t word = 2 * (int64_t)storage_bytes(st);
+    if (storage_exact(st))
+      *pop = (size_t)align256(8 * total * word) + (size_t)(2 * total * 8);
+    else
+      *pop = (size_t)(d2q9::kQ * total * word);
+    *aux = (size_t)align256((int64_t)A_COUNT * total * 4) + (storage_exact(st) ? (size_t)(2 * total * 8) : 0);
     return;
   }
   if (storage_exact(st))
@@ -184,13 +202,11 @@ int validate(int32_t n_boxes, const cglbm_box_params *boxes, int32_t storage) {
   return CGLBM_OK;
 }
 
-// The D2Q9 lattice of App. A: one-layer boxes, FP32 storage, the generalized
-// equilibrium of Eq. (A10) with unit rates above second order.
+// The D2Q9 lattice of App. A: one-layer boxes, the generalized equilibrium
+// of Eq. (A10) with unit rates above second order.
 int validate_d2q9(int32_t n_boxes, const cglbm_box_params *boxes, int32_t storage) {
   int rc = validate(n_boxes, boxes, storage);
   if (rc) return rc;
-  if (storage != CGLBM_FP32)
-    return fail(CGLBM_EUNSUPPORTED, "D2Q9 boxes are stored in FP32 only");
   for (int b = 0; b < n_boxes; ++b) {
     const cglbm_box_params &P = boxes[b];
     if (P.nz != 1) return fail(CGLBM_EINVAL, "box %d: a D2Q9 box has nz = 1", b);
@@ -265,10 +281,13 @@ void build_layout(int32_t n_boxes, const cglbm_box_params *boxes, Layout &L,
     }
     if (P.model != CGLBM_MODEL_D || !P.q_correction || B.full_rates) L.general = true;
     {
-      // pure-phase rest equilibrium of each colour: w_i rho_k^0 (c_s^k)^2 / c_s^2
-      const double w[4] = {8.0 / 27.0, 2.0 / 27.0, 1.0 / 54.0, 1.0 / 216.0};
-      const double p0[2] = {P.red.rho0 * kXi * (1.0 - P.red.alpha),
-                            P.blue.rho0 * kXi * (1.0 - P.blue.alpha)};
+      // pure-phase rest equilibrium of each colour: w_i rho_k^0 (c_s^k)^2 / c_s^2,
+      // by speed class |c_i|^2 (D3Q27 weights, or the D2Q9 ones of Eq. A2)
+      const double w3[4] = {8.0 / 27.0, 2.0 / 27.0, 1.0 / 54.0, 1.0 / 216.0};
+      const double w2[4] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 36.0, 0.0};
+      const double *w = lattice == LATTICE_D2Q9 ? w2 : w3;
+      const double p0[2] = {P.red.rho0 * xi * (1.0 - P.red.alpha),
+                            P.blue.rho0 * xi * (1.0 - P.blue.alpha)};
       for (int c = 0; c < 2; ++c)
         for (int k = 0; k < 4; ++k) B.shift[c][k] = (float)(w[k] * p0[c] * 3.0);
     }
@@ -477,9 +496,10 @@ int effective_schedule(const cglbm_handle *h) { return h->L.general ? 1 : h->sch
 // stored state into aux, populations untouched).
 int launch_step2(cglbm_handle *h, hipStream_t s, int export_fields) {
   const Variant2 &V = kVariants2[h->variant];
-  hipLaunchKernelGGL(export_fields ? V.fields : V.step, dim3(h->L.ncol), dim3(256), 0, s,
-                     h->d_boxes, h->d_col_box, (const d2q9::W *)h->pop[h->cur],
-                     (d2q9::W *)h->pop[1 - h->cur], h->aux, h->L.total);
+  const int slot = storage2_slot(h->storage);
+  hipLaunchKernelGGL(export_fields ? V.fields[slot] : V.step[slot], dim3(h->L.ncol), dim3(256), 0,
+                     s, h->d_boxes, h->d_col_box, (const void *)h->pop[h->cur],
+                     h->pop[1 - h->cur], h->aux, h->L.total);
   return CGLBM_OK;
 }
 
@@ -712,8 +732,8 @@ int init_handle(int lattice, cglbm_handle **out, int32_t n_boxes, const cglbm_bo
   // the stored state lives in pop[0]
   h->cur = 0;
   if (lattice == LATTICE_D2Q9)
-    hipLaunchKernelGGL(d2q9::k2_init, dim3(h->L.nblk), dim3(kBlock), 0, s, h->d_boxes,
-                       h->d_blk_box, init_rho_r, init_rho_b, init_u, (d2q9::W *)h->pop[0],
+    hipLaunchKernelGGL(kInit2[storage2_slot(storage)], dim3(h->L.nblk), dim3(kBlock), 0, s,
+                       h->d_boxes, h->d_blk_box, init_rho_r, init_rho_b, init_u, h->pop[0],
                        h->L.total, noise_seed, (float)noise_amp);
   else
     hipLaunchKernelGGL(kInit[storage], dim3(h->L.nblk), dim3(kBlock), 0, s, h->d_boxes,

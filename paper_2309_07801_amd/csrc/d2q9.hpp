@@ -1,10 +1,13 @@
 // d2q9.hpp -- HIP kernels (gfx950) of the two-dimensional (D2Q9, App. A)
 // colour-gradient step with the generalized equilibrium of Eq. (A10).
 //
-// Storage: populations as 9 colour-pair planes (red in the low half) of
-// FP32, pair plane i for direction i in the order of Eq. (A1); the aux planes
-// keep the layout of the three-dimensional path (z components zero), so the
-// field export and the diagnostics kernels serve both lattices.
+// Storage: populations as colour-pair planes (red in the low half), pair
+// plane i for direction i in the order of Eq. (A1): FP32 keeps all 9
+// directions; the mass-exact formats (FP16 / BF16 shifted, FP32 exact) keep
+// the 8 moving directions and the two rest populations in FP64 planes after
+// them, as in three dimensions.  The aux planes keep the layout of the
+// three-dimensional path (z components zero), so the field export and the
+// diagnostics kernels serve both lattices.
 //
 // One step is one launch.  A block owns a TX x TY tile of a box: it pulls
 // the populations of the tile and of a 3-node halo (Eq. 5) and forms the
@@ -35,7 +38,31 @@ __host__ __device__ constexpr float weight(int i) {
 // 1 / c_s^2 times a weight: the coefficient of the isotropic gradient (Eq. 20)
 __host__ __device__ constexpr float gw(int i) { return 3.0f * weight(i); }
 
-using W = uint64_t;  // FP32 colour pair
+// Views of one population buffer: pair planes, then (mass-exact formats)
+// the FP64 rest populations of the two colours.
+template <class S>
+struct Pops2 {
+  using W = typename S::W;
+  static constexpr int kDirs = S::kExact ? kQ - 1 : kQ;
+  W *pw;
+  double *rest;
+  int64_t plane;
+  __device__ Pops2(void *base, int64_t plane_) : plane(plane_) {
+    pw = (W *)base;
+    rest = (double *)((char *)base + align256(kDirs * plane_ * (int64_t)sizeof(W)));
+  }
+  __device__ W *plane_of(int i) const { return pw + (int64_t)(S::kExact ? i - 1 : i) * plane; }
+  __device__ double *restp(int c) const { return rest + (int64_t)c * plane; }
+};
+
+// Shift of direction i of colour c: the pure-phase rest equilibrium of the
+// colour with the D2Q9 weight of i (host table by |c_i|^2), rounded to the
+// format; zero for unshifted formats and the rest direction.
+template <class S>
+__device__ __forceinline__ float shift2(const BoxDev &B, int c, int i) {
+  if (!S::kShift || i == 0) return 0.f;
+  return S::dec(S::enc(B.shift[c][kCX[i] * kCX[i] + kCY[i] * kCY[i]]));
+}
 
 // Index of direction (cx, cy).
 __host__ __device__ constexpr int dir_of(int cx, int cy) {
@@ -78,12 +105,13 @@ __device__ __forceinline__ void equilibrium_cms(float rho, float p, float (&k)[9
 // velocity (from its central moments) plus counter noise, split by colour
 // fraction; stored un-streamed (direction i of node x at x - c_i), so that
 // the first pull reproduces it at x.
+template <class S>
 __global__ __launch_bounds__(kBlock) void k2_init(const BoxDev *__restrict__ boxes,
                                                   const int32_t *__restrict__ blk_box,
                                                   const float *__restrict__ in_rr,
                                                   const float *__restrict__ in_rb,
                                                   const float *__restrict__ in_u,
-                                                  W *__restrict__ dst, int64_t plane,
+                                                  void *__restrict__ dst_, int64_t plane,
                                                   uint64_t seed, float amp) {
   const int b = blk_box[blockIdx.x];
   const BoxDev B = boxes[b];
@@ -102,13 +130,28 @@ __global__ __launch_bounds__(kBlock) void k2_init(const BoxDev *__restrict__ box
   float f[kQ];
   central_to_pops(k, ux, uy, f);
   const float cr = rr / rho, cb = rb / rho;
+  const Pops2<S> dst(dst_, plane);
+  double tr = 0.0, tb = 0.0, sr = 0.0, sb = 0.0;
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
     const float ft = amp != 0.f ? f[i] + counter_noise(seed, (uint32_t)b, (uint64_t)local, i, amp)
                                 : f[i];
+    const float vr = cr * ft, vb = cb * ft;
+    tr += (double)vr;
+    tb += (double)vb;
+    if (S::kExact && i == 0) continue;
     const int xd = wrap_once(x - kCX[i], B.nx), yd = wrap_once(y - kCY[i], B.ny);
     const uint32_t d = (uint32_t)B.base + (uint32_t)xd + (uint32_t)B.nx * (uint32_t)yd;
-    st(&at(dst + (int64_t)i * plane, d), Pair32::pack(cr * ft, cb * ft));
+    const float shr = shift2<S>(B, 0, i), shb = shift2<S>(B, 1, i);
+    const typename S::T er = S::enc(vr - shr), eb = S::enc(vb - shb);
+    st(&at(dst.plane_of(i), d), S::pack(er, eb));
+    sr += (double)(S::dec(er) + shr);
+    sb += (double)(S::dec(eb) + shb);
+  }
+  // mass-exact formats: the rest populations close each colour's mass
+  if (S::kExact) {
+    st(&at(dst.restp(0), node), tr - sr);
+    st(&at(dst.restp(1), node), tb - sb);
   }
 }
 
@@ -116,11 +159,14 @@ __global__ __launch_bounds__(kBlock) void k2_init(const BoxDev *__restrict__ box
 // state into aux (EXPORT = true: moments, n, F, Q, kappa; no populations
 // written).  Grid: one block per tile (tile table tile_box, XCD-remapped,
 // padded with idle blocks).
-template <int TX, int TY, int NT, bool EXPORT>
+template <class S, int TX, int TY, int NT, bool EXPORT>
 __global__ __launch_bounds__(NT) void k2_step(const BoxDev *__restrict__ boxes,
                                               const int32_t *__restrict__ tile_box,
-                                              const W *__restrict__ src, W *__restrict__ dst,
-                                              float *__restrict__ aux, int64_t plane) {
+                                              const void *__restrict__ src_,
+                                              void *__restrict__ dst_, float *__restrict__ aux,
+                                              int64_t plane) {
+  using W = typename S::W;
+  constexpr int i0 = S::kExact ? 1 : 0;  // first stored pair plane's direction
   constexpr int RW = TX + 6, RH = TY + 6;  // pulled region: halo 3
   constexpr int GW = TX + 4, GH = TY + 4;  // n, |grad phi|: halo 2
   constexpr int KW = TX + 2, KH = TY + 2;  // F, q: halo 1
@@ -146,6 +192,7 @@ __global__ __launch_bounds__(NT) void k2_step(const BoxDev *__restrict__ boxes,
   const int x0 = txi * TX, y0 = tyi * TY;
   const int nx = B.nx, ny = B.ny;
   const int tid = threadIdx.x;
+  const Pops2<S> src(const_cast<void *>(src_), plane), dst(dst_, plane);
 
   if (tid < RH) {
     const int gy = wrap_any(y0 - 3 + tid, ny);
@@ -155,38 +202,63 @@ __global__ __launch_bounds__(NT) void k2_step(const BoxDev *__restrict__ boxes,
   __syncthreads();
 
   // ---- pull (Eq. 5) and local moments of one region node ----
-  auto pull = [&](int rx, int ry, bool own, float &pxx, float &pyy, float &pxy) {
+  // Mass-exact formats sum each colour in FP64 (rest population included),
+  // so that every tile holding a node as halo or as its own sees the same
+  // densities; the FP64 sums of own nodes close the rest populations.
+  auto pull = [&](int rx, int ry, bool own, float &pxx, float &pyy, float &pxy, double &drr,
+                  double &drb) {
     const int gx = wrap_any(x0 - 3 + rx, nx), gy = s_ry[ry];
     const int xs[3] = {wrap_once(gx + 1, nx), gx, wrap_once(gx - 1, nx)};
     const int ys[3] = {wrap_once(gy + 1, ny), gy, wrap_once(gy - 1, ny)};
+    const uint32_t node = (uint32_t)B.base + (uint32_t)gx + (uint32_t)nx * (uint32_t)gy;
     W gw_[kQ];
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) {
+    for (int i = i0; i < kQ; ++i) {
       const uint32_t s = (uint32_t)B.base + (uint32_t)xs[kCX[i] + 1] +
                          (uint32_t)nx * (uint32_t)ys[kCY[i] + 1];
-      gw_[i] = at(src + (int64_t)i * plane, s);
+      gw_[i] = at(src.plane_of(i), s);
+    }
+    drr = drb = 0.0;
+    if (S::kExact) {
+      drr = at(src.restp(0), node);
+      drb = at(src.restp(1), node);
     }
     float rr = 0.f, rb = 0.f, jx = 0.f, jy = 0.f;
     pxx = pyy = pxy = 0.f;
     if (s_sol[ry]) {
-      // full-way bounce-back: reverse what arrived
+      // full-way bounce-back: reverse what arrived (the shift of a direction
+      // equals its opposite's, so raw pairs are copied)
       if (own && !EXPORT) {
-        const uint32_t node = (uint32_t)B.base + (uint32_t)gx + (uint32_t)nx * (uint32_t)gy;
 #pragma unroll
-        for (int i = 0; i < kQ; ++i) st(&at(dst + (int64_t)opposite(i) * plane, node), gw_[i]);
+        for (int i = i0; i < kQ; ++i) st(&at(dst.plane_of(opposite(i)), node), gw_[i]);
+        if (S::kExact) {
+          st(&at(dst.restp(0), node), drr);
+          st(&at(dst.restp(1), node), drb);
+        }
       }
+      drr = drb = 0.0;
     } else {
 #pragma unroll
-      for (int i = 0; i < kQ; ++i) {
-        const float vr = Pair32::lo(gw_[i]), vb = Pair32::hi(gw_[i]);
-        rr += vr;
-        rb += vb;
+      for (int i = i0; i < kQ; ++i) {
+        const float vr = S::dec(S::lo(gw_[i])) + shift2<S>(B, 0, i);
+        const float vb = S::dec(S::hi(gw_[i])) + shift2<S>(B, 1, i);
+        if (S::kExact) {
+          drr += (double)vr;
+          drb += (double)vb;
+        } else {
+          rr += vr;
+          rb += vb;
+        }
         const float f = vr + vb;
         if (kCX[i]) jx += kCX[i] > 0 ? f : -f;
         if (kCY[i]) jy += kCY[i] > 0 ? f : -f;
         if (kCX[i]) pxx += f;
         if (kCY[i]) pyy += f;
         if (kCX[i] * kCY[i]) pxy += kCX[i] * kCY[i] > 0 ? f : -f;
+      }
+      if (S::kExact) {
+        rr = (float)drr;
+        rb = (float)drb;
       }
     }
     if (rx >= 2 && rx < RW - 2 && ry >= 2 && ry < RH - 2) {
@@ -202,11 +274,12 @@ __global__ __launch_bounds__(NT) void k2_step(const BoxDev *__restrict__ boxes,
 
   const int ix = tid % TX, iy0 = tid / TX;
   float opxx[PER], opyy[PER], opxy[PER];
+  double odrr[PER], odrb[PER];
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
     const int ry = 3 + iy0 + k * ROWS;
     const bool in_box = x0 + ix < nx && y0 + iy0 + k * ROWS < ny;
-    pull(3 + ix, ry, in_box, opxx[k], opyy[k], opxy[k]);
+    pull(3 + ix, ry, in_box, opxx[k], opyy[k], opxy[k], odrr[k], odrb[k]);
   }
   {
     // the halo ring: 3 rows above and below, 3 columns left and right
@@ -226,7 +299,8 @@ __global__ __launch_bounds__(NT) void k2_step(const BoxDev *__restrict__ boxes,
         rx = c < 3 ? c : RW - 6 + c;
       }
       float a, bb, c;
-      pull(rx, ry, false, a, bb, c);
+      double da, db;
+      pull(rx, ry, false, a, bb, c, da, db);
     }
   }
   __syncthreads();
@@ -332,6 +406,11 @@ __global__ __launch_bounds__(NT) void k2_step(const BoxDev *__restrict__ boxes,
         at(PL(aux, A_QX), node) = 0.f;
         at(PL(aux, A_QY), node) = 0.f;
         at(PL(aux, A_QZ), node) = 0.f;
+        if (S::kExact) {
+          double *r64 = aux_rho64(aux, plane);
+          at(r64, node) = 0.0;
+          at(r64 + plane, node) = 0.0;
+        }
       }
       continue;
     }
@@ -367,6 +446,11 @@ __global__ __launch_bounds__(NT) void k2_step(const BoxDev *__restrict__ boxes,
       at(PL(aux, A_QX), node) = Qx;
       at(PL(aux, A_QY), node) = Qy;
       at(PL(aux, A_QZ), node) = 0.f;
+      if (S::kExact) {
+        double *r64 = aux_rho64(aux, plane);
+        at(r64, node) = odrr[k];
+        at(r64 + plane, node) = odrb[k];
+      }
       continue;
     }
     const float rho = rr + rb;
@@ -404,13 +488,26 @@ __global__ __launch_bounds__(NT) void k2_step(const BoxDev *__restrict__ boxes,
     // mass step after step
     const float cr = rr / rho, cb = rb / rho;
     const float rs = B.beta * cr * cb * p;
+    double sr = 0.0, sb = 0.0;
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) {
+    for (int i = i0; i < kQ; ++i) {
       float cR = 0.f;
       if (kCX[i]) cR = fmaf((float)kCX[i], nxc, cR);
       if (kCY[i]) cR = fmaf((float)kCY[i], nyc, cR);
       const float d = gw(i) * rs * cR;
-      st(&at(dst + (int64_t)i * plane, node), Pair32::pack(fmaf(cr, f[i], d), fmaf(cb, f[i], -d)));
+      const float shr = shift2<S>(B, 0, i), shb = shift2<S>(B, 1, i);
+      const typename S::T er = S::enc(fmaf(cr, f[i], d) - shr), eb = S::enc(fmaf(cb, f[i], -d) - shb);
+      st(&at(dst.plane_of(i), node), S::pack(er, eb));
+      if (S::kExact) {
+        sr += (double)(S::dec(er) + shr);
+        sb += (double)(S::dec(eb) + shb);
+      }
+    }
+    // mass-exact formats: the rest populations close each colour's mass on
+    // the node's FP64 densities
+    if (S::kExact) {
+      st(&at(dst.restp(0), node), odrr[k] - sr);
+      st(&at(dst.restp(1), node), odrb[k] - sb);
     }
   }
 }

@@ -90,13 +90,24 @@ def _box2d(nx=40, ny=30, **kw):
     return dataclasses.replace(b, nx=nx, ny=ny, **kw)
 
 
+def _align256(v):
+    return (v + 255) // 256 * 256
+
+
 def test_d2q9_sizes_and_validation():
-    """The D2Q9 entry points: 9 pair planes of 2 x float per node, the aux
-    layout of D3Q27; nz = 1 and FP32 storage, Eq. (A10) only."""
+    """The D2Q9 entry points: 9 pair planes of 2 x float per node (either
+    FP32 format), or 8 pair planes and two FP64 rest planes (mass-exact
+    formats, whose aux also carries the FP64 colour densities); the aux
+    layout of D3Q27; nz = 1, Eq. (A10) only."""
     p = [pkg.box_params_of(_box2d())]
     pop, aux, total = pkg.query_sizes(p, pkg.FP32, lattice="d2q9")
     assert total == 1216          # 1200 -> 1216 (multiple of 64) is odd multiple of 64 (19)
     assert pop == 9 * 8 * total and aux == 21 * 4 * total
+    assert pkg.query_sizes(p, pkg.FP32_PAIRS, lattice="d2q9") == (pop, aux, total)
+    aux_x = _align256(21 * 4 * total) + 2 * 8 * total
+    for st, word in ((pkg.FP16_SHIFT, 4), (pkg.BF16_SHIFT, 4), (pkg.FP32_EXACT, 8)):
+        assert pkg.query_sizes(p, st, lattice="d2q9") == (
+            _align256(8 * word * total) + 2 * 8 * total, aux_x, total), st
     for field, value, code in (("nz", 2, -1), ("walls", 2, -1), ("model", 0, -3)):
         q = pkg.box_params_of(_box2d())
         setattr(q, field, value)
@@ -109,8 +120,8 @@ def test_d2q9_sizes_and_validation():
         pkg.query_sizes([q], pkg.FP32, lattice="d2q9")
     assert ei.value.code == -3
     with pytest.raises(pkg.CglbmError) as ei:
-        pkg.query_sizes(p, pkg.FP16_SHIFT, lattice="d2q9")
-    assert ei.value.code == -3
+        pkg.query_sizes(p, 5, lattice="d2q9")
+    assert ei.value.code == -1
     with pytest.raises(ValueError):
         pkg.query_sizes(p, pkg.FP32, lattice="d3q19")
 

@@ -9,7 +9,10 @@ of Eq. A10) on the GPU, against the FP64 oracle of the same model.
 * the full-size throughput case (4096^2, 256 droplets) on sampled nodes
   against oracle windows;
 * Table II: the stationary droplet's surface tension from Laplace's law
-  (Eq. 68) for the eight printed density ratios and tensions.
+  (Eq. 68) for the eight printed density ratios and tensions;
+* the mass-exact storage formats (FP32 exact, FP16 / BF16 shifted) against
+  the oracle, their per-colour mass conservation, and bitwise agreement of
+  the tile shapes in every format.
 Bars as for the D3Q27 path: FP32 arithmetic against FP64."""
 import dataclasses
 import json
@@ -40,11 +43,11 @@ def _droplet(box, R, u=(0.04, -0.02, 0.0)):
     return WL.droplet_fields(box, [c], [R], u_carrier=u)
 
 
-def _sim(boxes, fields, seed=0, noise=0.0):
+def _sim(boxes, fields, seed=0, noise=0.0, storage=0):
     import paper_2309_07801_amd as pkg
     return pkg.Simulation([pkg.box_params_of(b) for b in boxes], [f[0] for f in fields],
                           [f[1] for f in fields], [f[2] for f in fields], seed=seed, noise=noise,
-                          lattice="d2q9")
+                          storage=storage, lattice="d2q9")
 
 
 @pytest.mark.parametrize("variant", range(4))
@@ -241,3 +244,71 @@ def test_reduce_matches_oracle_fields():
     assert d[5] == pytest.approx(p[dist < reff - 3].mean(), rel=1e-5)
     assert d[6] == pytest.approx(p[dist > reff + 5].mean(), rel=1e-5)
     assert d[12] == 0
+
+
+# (storage, e_rho, e_u, e_phi) bars after 50 steps, as for D3Q27: the
+# storage unit roundoff times the stored deviations, grown over the steps
+STORAGE_BARS = {3: (1e-5, 1e-4, 1e-4), 1: (2e-3, 5e-2, 2e-2), 2: (2e-2, 3e-1, 1.5e-1)}
+
+
+@pytest.mark.parametrize("storage", [3, 1, 2])
+@pytest.mark.parametrize("walls", [0, 1])
+def test_storage_parity_with_oracle(storage, walls):
+    """The mass-exact formats (FP32 exact, FP16 and BF16 shifted by the D2Q9
+    pure-phase rest equilibrium) against the FP64 oracle after 50 steps of a
+    translating droplet on a ragged box of several tiles."""
+    box = _box((77, 45), gamma=10.0, visc_ratio=3.0, walls=walls)
+    fl = _droplet(box, 11.5, u=(0.02, -0.01, 0.0))
+    sim = _sim([box], [fl], seed=3, noise=1e-6, storage=storage)
+    sim.step(50)
+    g = gpu_fields(sim)
+    sim.close()
+    o, _ = run_oracle_2d(box, *fl, 50, seed=3, noise=1e-6)
+    e = errors(g, o, box, 0.02)
+    print("storage", storage, "walls", walls, e)
+    br, bu, bp = STORAGE_BARS[storage]
+    assert e["rho"] < br and e["u"] < bu and e["phi"] < bp
+
+
+@pytest.mark.parametrize("storage", [3, 1, 2])
+def test_mass_exact_storage_conserves_colour_mass(storage):
+    """Per-colour mass over 200 steps of a droplet carried by a uniform flow
+    at density ratio 10 stays at FP64 rounding level (FP32 storage drifts by
+    its rounding of the collision)."""
+    box = _box((72, 48), gamma=10.0)
+    fl = _droplet(box, 12.0, u=(0.05, 0.0, 0.0))
+    sim = _sim([box], [fl], seed=5, noise=1e-6, storage=storage)
+    d0 = sim.reduce()[0]
+    sim.step(200)
+    d1 = sim.reduce()[0]
+    sim.close()
+    drift = [(d1[k] - d0[k]) / d0[k] for k in (0, 1)]
+    print("storage", storage, "mass drift", drift)
+    assert abs(drift[0]) < 1e-12 and abs(drift[1]) < 1e-12
+    assert d1[12] == 0
+
+
+@pytest.mark.parametrize("storage", [4, 1, 2, 3])
+def test_storage_variants_agree_bitwise(storage):
+    """Every tile shape gives the same bits in every storage format (FP32
+    pairs bitwise equal to FP32 as well), on a two-box batch with walls."""
+    cases = [(_box((77, 45), walls=1), 11.5), (_box((30, 21)), 6.0)]
+    boxes = [b for b, _ in cases]
+    fields = [_droplet(b, R) for b, R in cases]
+    ref = None
+    if storage == 4:
+        sim = _sim(boxes, fields, seed=8, noise=1e-6, storage=0)
+        sim.step(12)
+        ref = [gpu_fields(sim, k) for k in range(2)]
+        sim.close()
+    for v in range(4):
+        sim = _sim(boxes, fields, seed=8, noise=1e-6, storage=storage)
+        sim.set_variant(v)
+        sim.step(12)
+        out = [gpu_fields(sim, k) for k in range(2)]
+        sim.close()
+        if ref is None:
+            ref = out
+        for a, b in zip(ref, out):
+            for name in a:
+                assert np.array_equal(a[name], b[name]), (storage, v, name)
