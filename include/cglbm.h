@@ -211,7 +211,8 @@ int cglbm_moments(cglbm_handle *h, int32_t box, uint32_t field_mask, float *out_
  *   5 p_in (mean p where |x-c| < R_eff-3), 6 p_out (mean p where
  *   |x-c| > R_eff+5, periodic distance), 7 R_eff = (3V/4pi)^(1/3) with
  *   V = sum (1+phi)/2, 8-10 red centroid relative to c, 11 kinetic energy
- *   sum rho u^2/2, 12 count of non-finite populations.
+ *   sum rho u^2/2, 12 count of fluid nodes whose pulled local moments
+ *   (densities, momentum, second moments) are not all finite.
  * out_is_host != 0: out is host memory and the call synchronizes the stream;
  * returns CGLBM_EUNSTABLE if any count of non-finite values is nonzero.
  * Otherwise out is device memory and the call is asynchronous. */
@@ -221,6 +222,21 @@ int cglbm_reduce(cglbm_handle *h, const double *centre, double *out, int32_t out
 
 /* Node offset of box b in the concatenated arrays, or -1. */
 int64_t cglbm_box_offset(const cglbm_handle *h, int32_t box);
+
+/* Checkpoint and resume.  The state of every box is the content of one of
+ * the two population buffers (which one alternates with the step parity);
+ * aux holds only fields derived from it, and the initial noise enters only
+ * through it.  cglbm_state_buffer returns that buffer (pop_a or pop_b, a
+ * device pointer to pop_bytes), valid until the next cglbm_step; NULL for a
+ * NULL handle.  A copy of it ordered after the work enqueued so far is a
+ * checkpoint.  cglbm_load_state copies pop_bytes from the device buffer src
+ * into the state buffer of h, on stream (asynchronous); h must have been
+ * created with the same boxes, storage and lattice as the run that wrote the
+ * checkpoint (the library cannot check this).  Stepping on from a loaded
+ * checkpoint gives bit for bit the results of the uninterrupted run.
+ * CGLBM_ESTATE for a NULL handle, CGLBM_EINVAL for a NULL src. */
+void *cglbm_state_buffer(const cglbm_handle *h);
+int cglbm_load_state(cglbm_handle *h, const void *src, void *stream);
 
 /* Launch schedule of a step (both compute the same update, bit for bit):
  *   0 (default) two launches: pull-streaming with local moments, then one

@@ -39,7 +39,8 @@ EXPORTED = ("cglbm_query_sizes", "cglbm_init", "cglbm_step", "cglbm_moments", "c
             "cglbm_variant_info", "cglbm_set_variant", "cglbm_get_variant", "cglbm_autotune",
             "cglbm_profile_begin", "cglbm_profile_end", "cglbm_destroy",
             "cglbm_last_error", "cglbm_version", "cglbm_query_sizes_d2q9", "cglbm_init_d2q9",
-            "cglbm_lattice", "cglbm_variant_info_d2q9")
+            "cglbm_lattice", "cglbm_variant_info_d2q9", "cglbm_state_buffer",
+            "cglbm_load_state")
 # Lattices: the D3Q27 model of the paper's body and the D2Q9 model of App. A.
 LATTICES = ("d3q27", "d2q9")
 NUM_VARIANTS_D2Q9 = 4
@@ -121,6 +122,9 @@ def lib():
         L.cglbm_reduce.argtypes = [vp, C.POINTER(C.c_double), vp, i32, vp]
         L.cglbm_box_offset.argtypes = [vp, i32]
         L.cglbm_box_offset.restype = i64
+        L.cglbm_state_buffer.argtypes = [vp]
+        L.cglbm_state_buffer.restype = vp
+        L.cglbm_load_state.argtypes = [vp, vp, vp]
         L.cglbm_set_schedule.argtypes = [vp, i32]
         L.cglbm_get_schedule.argtypes = [vp]
         L.cglbm_set_graph.argtypes = [vp, i32]
@@ -254,6 +258,32 @@ class Simulation:
 
     def box_offset(self, b: int) -> int:
         return int(lib().cglbm_box_offset(self.h, b))
+
+    def state_tensor(self):
+        """The population buffer that holds the current state (a view, valid
+        until the next step)."""
+        ptr = lib().cglbm_state_buffer(self.h)
+        if ptr == self.pop_a.data_ptr():
+            return self.pop_a
+        if ptr == self.pop_b.data_ptr():
+            return self.pop_b
+        raise CglbmError(-5, "state buffer is neither population buffer")
+
+    def checkpoint(self):
+        """A device copy of the current state (ordered on the simulation's
+        stream after the work enqueued so far)."""
+        import contextlib
+        import torch
+        ctx = torch.cuda.stream(self.stream) if self.stream is not None else contextlib.nullcontext()
+        with ctx:
+            return self.state_tensor().clone()
+
+    def load_state(self, state):
+        """Continue from a checkpoint taken on a simulation with the same
+        boxes, storage and lattice."""
+        if state.numel() != self.pop_a.numel() or state.device != self.device:
+            raise ValueError("checkpoint size or device does not match this simulation")
+        _check(lib().cglbm_load_state(self.h, state.data_ptr(), _stream_ptr(self.stream)))
 
     def step(self, n: int = 1):
         _check(lib().cglbm_step(self.h, int(n), _stream_ptr(self.stream)))

@@ -667,6 +667,19 @@ int64_t cglbm_box_offset(const cglbm_handle *h, int32_t box) {
   return h->L.boxes[box].base;
 }
 
+void *cglbm_state_buffer(const cglbm_handle *h) { return h ? h->pop[h->cur] : nullptr; }
+
+int cglbm_load_state(cglbm_handle *h, const void *src, void *stream) {
+  g_err.clear();
+  if (!h) return fail(CGLBM_ESTATE, "null handle");
+  if (!src) return fail(CGLBM_EINVAL, "src must not be NULL");
+  size_t pop = 0, aux = 0;
+  buffer_sizes(h->storage, h->L.total, &pop, &aux, h->lattice);
+  if (src == h->pop[h->cur]) return CGLBM_OK;
+  HIP_TRY(hipMemcpyAsync(h->pop[h->cur], src, pop, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return CGLBM_OK;
+}
+
 }  // extern "C"
 
 namespace {

@@ -143,3 +143,17 @@ def test_empty_and_oversized_inputs_are_rejected():
     assert total < (1 << 29) and pop_b == 54 * 4 * total
     with pytest.raises(pkg.CglbmError):
         pkg.query_sizes([pkg.box_params_of(a)] * 3)
+
+
+def test_null_handle_calls_fail_cleanly():
+    """Host-side error paths of the handle calls (no device work): a NULL
+    handle gives CGLBM_ESTATE or a NULL / -1 result, never a crash."""
+    import ctypes as C
+    L = pkg.lib()
+    assert L.cglbm_state_buffer(None) is None
+    assert L.cglbm_load_state(None, None, None) == -5
+    assert L.cglbm_step(None, 1, None) == -5
+    assert L.cglbm_lattice(None) == -1
+    assert L.cglbm_box_offset(None, 0) == -1
+    out = (C.c_double * 13)()
+    assert L.cglbm_reduce(None, None, out, 1, None) == -5
