@@ -17,7 +17,8 @@ storage (with their difference to the FP32 run as a proxy error), the
 at the paper's size (Models D and A), the translating droplet's
 deformation per equilibrium model, the two-dimensional model of App. A on a
 4096^2 droplet field (d2q9; d2q9_fp16 and d2q9_bf16 with 16-bit shifted
-storage) and Table II's surface tensions (table2).  The timed region
+storage), the main workload in the in-place layout (inplace) and Table II's
+surface tensions (table2).  The timed region
 launches every kernel directly (HIP events around each launch); after it,
 `graph_mlups` times the same update as replays of the captured two-step
 graph that cglbm_step uses by default.
@@ -112,7 +113,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--size", type=int, default=256, help="box edge (default 256)")
     ap.add_argument("--storage", default="fp32", choices=sorted(STORAGES))
-    ap.add_argument("--forms", default="fp16,bf16,fp32x,batched,small,rti,galilean,d2q9,"
+    ap.add_argument("--forms", default="fp16,bf16,fp32x,batched,inplace,small,rti,galilean,d2q9,"
                     "d2q9_fp16,d2q9_bf16,table2",
                     help="extra forms on the same workload ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -168,7 +169,7 @@ def cpu_baseline(w, seconds):
 
 
 def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=False,
-             lattice="d3q27"):
+             lattice="d3q27", inplace=False):
     """Initialise, autotune, time `steps` steps; return throughput, per-kernel
     event timings and (optionally) the final fields of box 0."""
     import torch
@@ -176,7 +177,8 @@ def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=False,
     sim = pkg.Simulation([pkg.box_params_of(w.box) for w in workloads],
                          [w.rho_r for w in workloads], [w.rho_b for w in workloads],
                          [w.u for w in workloads], seed=workloads[0].seed,
-                         noise=workloads[0].noise, storage=STORAGES[storage], lattice=lattice)
+                         noise=workloads[0].noise, storage=STORAGES[storage], lattice=lattice,
+                         inplace=inplace)
     fluid = sum(w.box.fluid_nodes() for w in workloads)
     d0 = sim.reduce()
     sim.step(2)
@@ -217,7 +219,8 @@ def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=False,
            "fluid": fluid, "kernels": kern, "variant": var, "autotune_ms": tune_ms,
            "schedule": ("fused", "three kernels")[sim.schedule()],
            "mass_drift": [float((m1[0] - m0[0]) / m0[0]), float((m1[1] - m0[1]) / m0[1])],
-           "nonfinite": int(d1[:, 12].sum()), "steps": steps}
+           "nonfinite": int(d1[:, 12].sum()), "steps": steps,
+           "pop_buffer_bytes": sim.pop_a.numel() * (1 if inplace else 2)}
     if keep_fields:
         out["fields"] = {k: v.cpu().numpy() for k, v in
                          sim.moments(0, ("rho_r", "rho_b", "phi", "ux", "uy", "uz")).items()}
@@ -447,6 +450,18 @@ def main():
                                 "graph_mlups": round(r["graph_mlups"], 1),
                                 "schedule": r["schedule"],
                                 "step_roofline_frac": round(r["mlups"] * 1e6 * 432 / (HBM_PEAK_GBS * 1e9), 4),
+                                "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()}
+                                            for k, v in r["kernels"].items()},
+                                "mass_drift": r["mass_drift"], "nonfinite": r["nonfinite"]}
+        elif f == "inplace":
+            r = run_form([w], args.storage, args.steps, args.warmup, args.variant, inplace=True)
+            forms["inplace"] = {"workload": "the main line's workload with one population buffer",
+                                "population_buffer_bytes": r["pop_buffer_bytes"],
+                                "two_buffer_bytes": main_r["pop_buffer_bytes"],
+                                "mlups": round(r["mlups"], 1),
+                                "ms_per_step": round(r["ms_per_step"], 4),
+                                "graph_mlups": round(r["graph_mlups"], 1),
+                                "schedule": r["schedule"],
                                 "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()}
                                             for k, v in r["kernels"].items()},
                                 "mass_drift": r["mass_drift"], "nonfinite": r["nonfinite"]}

@@ -137,8 +137,16 @@ int cglbm_query_sizes(int32_t n_boxes, const cglbm_box_params *boxes, int32_t st
                       size_t *pop_bytes, size_t *aux_bytes, int64_t *total_nodes);
 
 /* Create a handle and write the initial state.
- * pop_a, pop_b: two device buffers of pop_bytes each; pop_b must not be NULL
- *   (the in-place single-buffer layout is not built: CGLBM_EUNSUPPORTED).
+ * pop_a, pop_b: two device buffers of pop_bytes each, or pop_b = NULL for
+ *   the in-place layout: one population buffer, which every step reads (in
+ *   its pull) and then overwrites with the next state.  This is exact for
+ *   the D3Q27 schedules because only the pull reads populations; solid wall
+ *   nodes, whose reversed populations other nodes of the same pull still
+ *   read, go through a small library-owned stash (allocated here, about
+ *   pop_bytes / nodes x wall nodes) and a copy kernel after the pull.  The
+ *   results are bit for bit those of the two-buffer layout.
+ *   CGLBM_EUNSUPPORTED for a box with a higher-order rate other than 1
+ *   (whose collision pulls the populations again).
  * aux: device buffer of aux_bytes.
  * init_rho_r, init_rho_b: device float arrays of total_nodes values (all
  *   boxes concatenated as described above; values in alignment gaps are
@@ -172,7 +180,8 @@ int cglbm_init(cglbm_handle **out, int32_t n_boxes, const cglbm_box_params *boxe
  * for D3Q27 (48 or 80 bytes per node).  aux as for D3Q27 (with the FP64
  * colour densities after it for the mass-exact formats).
  * One launch per step (the pull, the interface stencils and the collision
- * of a tile in one kernel); cglbm_set_schedule accepts 0 only; variants are
+ * of a tile in one kernel, so pop_b must not be NULL: CGLBM_EUNSUPPORTED);
+ * cglbm_set_schedule accepts 0 only; variants are
  * its tile shapes (4 of them), chosen by cglbm_autotune, which writes their
  * times to ms_per_variant[0..3]. */
 int cglbm_query_sizes_d2q9(int32_t n_boxes, const cglbm_box_params *boxes, int32_t storage,
@@ -269,7 +278,9 @@ int cglbm_get_variant(const cglbm_handle *h);
 
 /* Autotuner: time every fused variant and the three-kernel schedule `reps`
  * times on the current state (the stored state is not advanced: the kernels
- * after the pull are re-run on the same inputs) and select the fastest
+ * after the pull are re-run on the same inputs; in the in-place layout they
+ * all write the next state into the one buffer, so the call advances the
+ * state by exactly one step) and select the fastest
  * geometry and schedule (the three-kernel schedule wins on boxes too small to
  * fill the GPU with fused columns).  ms_per_variant (optional, length
  * cglbm_num_variants() + 1) receives the mean milliseconds per launch of

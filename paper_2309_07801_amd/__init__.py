@@ -195,13 +195,14 @@ class Simulation:
     (3, nz, ny, nx).  They are packed into the concatenated layout and copied
     to the device once for the initialisation.  lattice "d2q9" runs the
     two-dimensional model of App. A on boxes with nz = 1 (u may then have
-    two components).
+    two components).  inplace=True keeps one population buffer (D3Q27 with
+    unit higher-order rates; bitwise the same results).
     """
 
     def __init__(self, params: Sequence[BoxParams], rho_r: List[np.ndarray],
                  rho_b: List[np.ndarray], u: List[np.ndarray], seed: int = 0,
                  noise: float = 0.0, storage: int = FP32, device: int = 0, stream=None,
-                 lattice: str = "d3q27"):
+                 lattice: str = "d3q27", inplace: bool = False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the colour-gradient LBM library needs an MI355X")
@@ -215,8 +216,9 @@ class Simulation:
         self.total = total
         self.stream = stream
         dev = self.device
+        self.inplace = bool(inplace)
         self.pop_a = torch.empty(pop_bytes, dtype=torch.uint8, device=dev)
-        self.pop_b = torch.empty(pop_bytes, dtype=torch.uint8, device=dev)
+        self.pop_b = None if self.inplace else torch.empty(pop_bytes, dtype=torch.uint8, device=dev)
         self.aux = torch.empty(aux_bytes, dtype=torch.uint8, device=dev)
         self.offsets = self._offsets_host()
         rr = self.pack([np.asarray(a, np.float32) for a in rho_r])
@@ -233,7 +235,7 @@ class Simulation:
         h = C.c_void_p()
         init = lib().cglbm_init_d2q9 if lat == 1 else lib().cglbm_init
         _check(init(C.byref(h), self.nboxes, arr, storage, self.pop_a.data_ptr(),
-                                self.pop_b.data_ptr(), self.aux.data_ptr(),
+                                None if self.inplace else self.pop_b.data_ptr(), self.aux.data_ptr(),
                                 self._init_rr.data_ptr(), self._init_rb.data_ptr(),
                                 self._init_u.data_ptr(), C.c_uint64(seed), float(noise),
                                 _stream_ptr(stream)))
@@ -265,7 +267,7 @@ class Simulation:
         ptr = lib().cglbm_state_buffer(self.h)
         if ptr == self.pop_a.data_ptr():
             return self.pop_a
-        if ptr == self.pop_b.data_ptr():
+        if self.pop_b is not None and ptr == self.pop_b.data_ptr():
             return self.pop_b
         raise CglbmError(-5, "state buffer is neither population buffer")
 
@@ -324,10 +326,13 @@ class Simulation:
     def autotune(self, reps: int = 5):
         """Time every fused launch geometry and the three-kernel schedule and
         keep the fastest; returns the mean milliseconds per fused variant,
-        then of the three-kernel schedule (D2Q9: per tile shape)."""
+        then of the three-kernel schedule (D2Q9: per tile shape).  In the
+        in-place layout the call advances the state by one step."""
         n = num_variants() + 1
         ms = (C.c_double * n)()
         _check(lib().cglbm_autotune(self.h, int(reps), ms, _stream_ptr(self.stream)))
+        if self.inplace:
+            self.steps_done += 1
         return list(ms)[:NUM_VARIANTS_D2Q9] if self.lattice == "d2q9" else list(ms)
 
     def set_schedule(self, schedule: int):

@@ -104,7 +104,10 @@ enum { KIND_PULL = 0, KIND_IFACE = 1, KIND_COLLIDE = 2, KIND_FUSED = 3, KIND_N =
 int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
 // Kernels by storage format (index = cglbm_storage).
-using PullFn = void (*)(const BoxDev *, const int32_t *, void *, void *, float *, int64_t, int);
+using PullFn = void (*)(const BoxDev *, const int32_t *, void *, void *, float *, int64_t, int,
+                        void *, int64_t);
+using WallCopyFn = void (*)(const BoxDev *, const int32_t *, const void *, void *, int64_t,
+                            int64_t);
 using CollideFn = void (*)(const BoxDev *, const int32_t *, float *, const void *, void *,
                           int64_t);
 using InitFn = void (*)(const BoxDev *, const int32_t *, const float *, const float *,
@@ -115,6 +118,9 @@ const CollideFn kCollide[5] = {k_collide<StoreF32>, k_collide<StoreF16>, k_colli
                                k_collide<StoreF32X>, k_collide<StoreF32P>};
 const InitFn kInit[5] = {k_init<StoreF32>, k_init<StoreF16>, k_init<StoreBF16>, k_init<StoreF32X>,
                          k_init<StoreF32P>};
+const WallCopyFn kWallCopy[5] = {k_wall_copy<StoreF32>, k_wall_copy<StoreF16>,
+                                 k_wall_copy<StoreBF16>, k_wall_copy<StoreF32X>,
+                                 k_wall_copy<StoreF32P>};
 const InitFn kInit2[4] = {d2q9::k2_init<StoreF32P>, d2q9::k2_init<StoreF16>,
                            d2q9::k2_init<StoreBF16>, d2q9::k2_init<StoreF32X>};
 // D2Q9 keeps FP32 in colour pairs in either FP32 format
@@ -144,6 +150,8 @@ void buffer_sizes(int32_t st, int64_t total, size_t *pop, size_t *aux, int latti
 struct Layout {
   std::vector<BoxDev> boxes;
   std::vector<int32_t> blk_box, tile_box, col_box;
+  std::vector<int32_t> wblk_box;  // k_wall_copy blocks (in-place layouts with walls)
+  int64_t wtotal = 0;             // wall-node slots of all boxes (stash plane length)
   int64_t total = 0;  // plane length (nodes, all boxes, aligned)
   int32_t nblk = 0, ntile = 0, ncol = 0, nblk_pad = 0;
   bool walls = false;
@@ -291,6 +299,16 @@ void build_layout(int32_t n_boxes, const cglbm_box_params *boxes, Layout &L,
       for (int c = 0; c < 2; ++c)
         for (int k = 0; k < 4; ++k) B.shift[c][k] = (float)(w[k] * p0[c] * 3.0);
     }
+    // solid nodes: the z-wall planes, then the y-wall rows of the other layers
+    {
+      const int64_t nzw = (P.walls & 2u) ? 2 : 0;
+      const int64_t wn = nzw * P.nx * P.ny + ((P.walls & 1u) ? 2 * (int64_t)P.nx * (P.nz - nzw) : 0);
+      B.wbase = (int32_t)L.wtotal;
+      B.wn = (int32_t)wn;
+      B.wblk0 = (int32_t)L.wblk_box.size();
+      for (int64_t k = 0; k < (wn + kBlock - 1) / kBlock; ++k) L.wblk_box.push_back(b);
+      L.wtotal = align_up(L.wtotal + wn, kAlign);
+    }
     L.boxes.push_back(B);
     if (P.walls) L.walls = true;
   }
@@ -371,6 +389,9 @@ struct cglbm_handle {
   void *pop[2] = {nullptr, nullptr};
   float *aux = nullptr;
   int cur = 0;  // buffer holding the stored (post-collision) state
+  bool inplace = false;          // pop[0] == pop[1]: one population buffer
+  void *stash = nullptr;         // in-place layouts with walls: solid nodes' populations
+  int32_t *d_wblk_box = nullptr;
   int device = 0;
   BoxDev *d_boxes = nullptr;
   int32_t *d_blk_box = nullptr;
@@ -396,10 +417,18 @@ struct cglbm_handle {
 
 namespace {
 
+// The pull (bounce != 0: with the bounce-back writes of a time step).  In
+// place, the solid nodes' reversed populations go to the stash and
+// k_wall_copy moves them into the buffer after the pull has completed.
 int launch_pull(cglbm_handle *h, hipStream_t s, int bounce) {
+  void *stash = bounce && h->stash ? h->stash : nullptr;
   hipLaunchKernelGGL(kPull[h->storage], dim3(h->L.nblk_pad), dim3(kBlock), 0, s, h->d_boxes,
                      h->d_blk_box, h->pop[h->cur], h->pop[1 - h->cur], h->aux, h->L.total,
-                     bounce);
+                     bounce, stash, h->L.wtotal);
+  if (stash && !h->L.wblk_box.empty())
+    hipLaunchKernelGGL(kWallCopy[h->storage], dim3((unsigned)h->L.wblk_box.size()), dim3(kBlock),
+                       0, s, h->d_boxes, h->d_wblk_box, (const void *)stash, h->pop[1 - h->cur],
+                       h->L.total, h->L.wtotal);
   return CGLBM_OK;
 }
 
@@ -695,9 +724,18 @@ int init_handle(int lattice, cglbm_handle **out, int32_t n_boxes, const cglbm_bo
                                    : validate(n_boxes, boxes, storage);
   if (rc) return rc;
   if (!pop_a) return fail(CGLBM_EINVAL, "pop_a must not be NULL");
-  if (!pop_b)
-    return fail(CGLBM_EUNSUPPORTED, "the in-place single-buffer layout is not built; pass pop_b");
   if (pop_a == pop_b) return fail(CGLBM_EINVAL, "pop_a and pop_b must differ");
+  const bool inplace = pop_b == nullptr;
+  if (inplace) {
+    // one buffer works where populations are read by the pull alone
+    if (lattice == LATTICE_D2Q9)
+      return fail(CGLBM_EUNSUPPORTED, "D2Q9 steps read and write populations in one kernel: pass pop_b");
+    for (int b = 0; b < n_boxes; ++b)
+      for (int k = 0; k < 9; ++k)
+        if (boxes[b].omega_hi[k] != 1.0)
+          return fail(CGLBM_EUNSUPPORTED,
+                      "box %d: non-unit higher-order rates pull the populations again: pass pop_b", b);
+  }
   if (!aux || !init_rho_r || !init_rho_b || !init_u)
     return fail(CGLBM_EINVAL, "aux and the initial fields must not be NULL");
   if (!std::isfinite(noise_amp) || noise_amp < 0.0)
@@ -716,7 +754,8 @@ int init_handle(int lattice, cglbm_handle **out, int32_t n_boxes, const cglbm_bo
     }
   }
   h->pop[0] = pop_a;
-  h->pop[1] = pop_b;
+  h->pop[1] = inplace ? pop_a : pop_b;
+  h->inplace = inplace;
   h->aux = (float *)aux;
   hipStream_t s = (hipStream_t)stream;
   auto cleanup = [&](int code) {
@@ -740,6 +779,16 @@ int init_handle(int lattice, cglbm_handle **out, int32_t n_boxes, const cglbm_bo
                           sizeof(int32_t) * h->L.tile_box.size(), hipMemcpyHostToDevice, s)) !=
           hipSuccess) {
     return cleanup(fail(CGLBM_EHIP, "init: %s", hipGetErrorString(e)));
+  }
+  if (inplace && h->L.walls) {
+    size_t sb = 0, ab = 0;
+    buffer_sizes(storage, h->L.wtotal, &sb, &ab, lattice);
+    if ((e = hipMalloc(&h->stash, sb)) != hipSuccess ||
+        (e = hipMalloc(&h->d_wblk_box, sizeof(int32_t) * h->L.wblk_box.size())) != hipSuccess ||
+        (e = hipMemcpyAsync(h->d_wblk_box, h->L.wblk_box.data(),
+                            sizeof(int32_t) * h->L.wblk_box.size(), hipMemcpyHostToDevice, s)) !=
+            hipSuccess)
+      return cleanup(fail(CGLBM_EHIP, "init: %s", hipGetErrorString(e)));
   }
   if ((rc = select_variant(h, 0, s))) return cleanup(rc);
   // the stored state lives in pop[0]
@@ -905,7 +954,9 @@ int cglbm_autotune(cglbm_handle *h, int32_t reps, double *ms_per_variant, void *
   hipStream_t s = (hipStream_t)stream;
   if (h->lattice == LATTICE_D2Q9) return autotune2(h, reps, ms_per_variant, s);
   // the fused kernel is idempotent for a fixed pull: time every variant on
-  // the same inputs; the stored state is unchanged afterwards
+  // the same inputs; the stored state is unchanged afterwards (in place, the
+  // variants all write the next state into the one buffer: the call then
+  // advances the state by exactly one step)
   int rc = launch_pull(h, s, 1);
   if (rc || (rc = check_launch())) return rc;
   hipEvent_t e0, e1;
@@ -960,6 +1011,7 @@ int cglbm_autotune(cglbm_handle *h, int32_t reps, double *ms_per_variant, void *
   const int32_t sched = three_ms < best_ms ? 1 : 0;
   if (sched != h->schedule) drop_graphs(h);
   h->schedule = sched;
+  if (h->inplace) h->cur = 1 - h->cur;
   return CGLBM_OK;
 }
 
@@ -1012,6 +1064,8 @@ void cglbm_destroy(cglbm_handle *h) {
   if (h->d_part) (void)hipFree(h->d_part);
   if (h->d_diag) (void)hipFree(h->d_diag);
   if (h->d_centre) (void)hipFree(h->d_centre);
+  if (h->stash) (void)hipFree(h->stash);
+  if (h->d_wblk_box) (void)hipFree(h->d_wblk_box);
   delete h;
 }
 

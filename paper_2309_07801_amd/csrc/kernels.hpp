@@ -60,6 +60,8 @@ struct BoxDev {
   int32_t model;        // equilibrium family of Table I (MODEL_A..MODEL_D)
   int32_t qcorr;        // 1: correction term Q of Eq. (65) in the collision
   int32_t d2q9;         // 1: two-dimensional box of the D2Q9 lattice (App. A)
+  int32_t wbase, wn;    // wall-node slots of the box in the in-place stash
+  int32_t wblk0;        // first block of the box in k_wall_copy
 };
 
 constexpr int kBlock = 256;
@@ -180,6 +182,37 @@ __device__ __forceinline__ int wrap_any(int v, int n) {
 __device__ __forceinline__ bool is_solid(const BoxDev &B, int y, int z) {
   return ((B.walls & 1u) && (y == 0 || y == B.ny - 1)) ||
          ((B.walls & 2u) && (z == 0 || z == B.nz - 1));
+}
+
+// Slots of a box's solid nodes in the in-place wall stash (box-local; the
+// box's slots start at B.wbase): first the z-wall planes (z = 0, then
+// z = nz-1; slot z' nx ny + y nx + x), then the y-wall rows of the other
+// layers (y = 0 and y = ny-1 alternating, layer by layer).  wall_node
+// inverts the map.
+__host__ __device__ inline uint32_t wall_slot(const BoxDev &B, int x, int y, int z) {
+  const uint32_t nx = (uint32_t)B.nx, nxy = nx * (uint32_t)B.ny;
+  const bool zw = (B.walls & 2u) != 0u;
+  if (zw && (z == 0 || z == B.nz - 1))
+    return (z == 0 ? 0u : nxy) + (uint32_t)y * nx + (uint32_t)x;
+  const uint32_t zoff = zw ? 2u * nxy : 0u;
+  const uint32_t layer = (uint32_t)(z - (zw ? 1 : 0));
+  return zoff + (2u * layer + (y == 0 ? 0u : 1u)) * nx + (uint32_t)x;
+}
+__host__ __device__ inline void wall_node(const BoxDev &B, uint32_t slot, int &x, int &y, int &z) {
+  const uint32_t nx = (uint32_t)B.nx, nxy = nx * (uint32_t)B.ny;
+  const bool zw = (B.walls & 2u) != 0u;
+  if (zw && slot < 2u * nxy) {
+    z = slot < nxy ? 0 : B.nz - 1;
+    const uint32_t r = slot < nxy ? slot : slot - nxy;
+    y = (int)(r / nx);
+    x = (int)(r - (uint32_t)y * nx);
+    return;
+  }
+  const uint32_t r = slot - (zw ? 2u * nxy : 0u);
+  const uint32_t row = r / nx;
+  x = (int)(r - row * nx);
+  z = (int)(row / 2u) + (zw ? 1 : 0);
+  y = (row & 1u) ? B.ny - 1 : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -331,13 +364,18 @@ __device__ __forceinline__ void st_rb(const Pops<S> &p, int i, uint32_t d, typen
 // ---------------------------------------------------------------------------
 // k_pull: f^k_i(x) = stored_i(x - c_i); local moments; bounce-back at solid
 // nodes (the pulled populations are reversed and stored for the next step).
+// In-place layouts (src == dst) pass a wall stash: the reversed populations
+// of solid nodes go there (slot wall_slot, plane length wplane), because
+// other nodes of this launch still read what the solid node holds;
+// k_wall_copy moves them into place once the pull has completed.
 // ---------------------------------------------------------------------------
 template <class S>
 __global__ __launch_bounds__(kBlock) void k_pull(const BoxDev *__restrict__ boxes,
                                                  const int32_t *__restrict__ blk_box,
                                                  void *__restrict__ src_, void *__restrict__ dst_,
                                                  float *__restrict__ aux, int64_t plane,
-                                                 int bounce) {
+                                                 int bounce, void *__restrict__ stash_,
+                                                 int64_t wplane) {
   const uint32_t lb = xcd_block();
   const int b = blk_box[lb];
   if (b < 0) return;
@@ -378,11 +416,14 @@ __global__ __launch_bounds__(kBlock) void k_pull(const BoxDev *__restrict__ boxe
   if (is_solid(B, y, z)) {
     if (bounce) {
       // the shift of direction i equals that of its opposite: copy raw pairs
+      const bool stash = stash_ != nullptr;
+      const Pops<S> out(stash ? stash_ : dst_, stash ? wplane : plane);
+      const uint32_t at_ = stash ? (uint32_t)B.wbase + wall_slot(B, x, y, z) : node;
 #pragma unroll
-      for (int i = i0; i < kQ; ++i) st_rb(dst, opposite(i), node, gr[i], gb[i]);
+      for (int i = i0; i < kQ; ++i) st_rb(out, opposite(i), at_, gr[i], gb[i]);
       if (S::kExact) {
-        at(dst.restp(0), node) = rr0;
-        at(dst.restp(1), node) = rb0;
+        at(out.restp(0), at_) = rr0;
+        at(out.restp(1), at_) = rb0;
       }
     }
 #pragma unroll
@@ -1000,6 +1041,42 @@ __global__ __launch_bounds__(kBlock) void k_collide(const BoxDev *__restrict__ b
   if (S::kExact) {
     const double *r64 = aux_rho64(aux, plane);
     w.finish(at(r64, node), at(r64 + plane, node));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_wall_copy: the solid nodes' reversed populations, stashed by k_pull of an
+// in-place layout, into the population buffer (after the pull has
+// completed; no other kernel of the step touches solid nodes).  One thread
+// per wall slot; blocks per box from wblk_box.
+// ---------------------------------------------------------------------------
+template <class S>
+__global__ __launch_bounds__(kBlock) void k_wall_copy(const BoxDev *__restrict__ boxes,
+                                                      const int32_t *__restrict__ wblk_box,
+                                                      const void *__restrict__ stash_,
+                                                      void *__restrict__ pop_, int64_t plane,
+                                                      int64_t wplane) {
+  const int b = wblk_box[blockIdx.x];
+  if (b < 0) return;
+  const BoxDev B = boxes[b];
+  const int32_t local = (int32_t)(blockIdx.x - (uint32_t)B.wblk0) * kBlock + (int32_t)threadIdx.x;
+  if (local >= B.wn) return;
+  int x, y, z;
+  wall_node(B, (uint32_t)local, x, y, z);
+  const uint32_t node = (uint32_t)B.base + (uint32_t)x +
+                        (uint32_t)B.nx * ((uint32_t)y + (uint32_t)B.ny * (uint32_t)z);
+  const uint32_t slot = (uint32_t)(B.wbase + local);
+  const Pops<S> src(const_cast<void *>(stash_), wplane), dst(pop_, plane);
+  constexpr int i0 = S::kExact ? 1 : 0;
+#pragma unroll
+  for (int i = i0; i < kQ; ++i) {
+    typename S::T r, bl;
+    ld_rb(src, i, slot, r, bl);
+    st_rb(dst, i, node, r, bl);
+  }
+  if (S::kExact) {
+    at(dst.restp(0), node) = at(src.restp(0), slot);
+    at(dst.restp(1), node) = at(src.restp(1), slot);
   }
 }
 

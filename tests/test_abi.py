@@ -157,3 +157,24 @@ def test_null_handle_calls_fail_cleanly():
     assert L.cglbm_box_offset(None, 0) == -1
     out = (C.c_double * 13)()
     assert L.cglbm_reduce(None, None, out, 1, None) == -5
+
+
+def test_inplace_layout_restrictions():
+    """pop_b = NULL (one population buffer) is refused on the host, before any
+    device work, where a kernel reads populations after the pull: D2Q9 (one
+    kernel pulls and stores) and non-unit higher-order rates (the collision
+    pulls again)."""
+    import ctypes as C
+    L = pkg.lib()
+    fake = C.c_void_p(0x1000)     # never dereferenced: the calls fail first
+    h = C.c_void_p()
+
+    def init(fn, params):
+        arr = (pkg.BoxParams * 1)(params)
+        return fn(C.byref(h), 1, arr, pkg.FP32, fake, None, fake, fake, fake, fake, 0, 0.0, None)
+
+    assert init(L.cglbm_init_d2q9, pkg.box_params_of(_box2d())) == -3
+    q = pkg.box_params_of(WL.two_phase_box((8, 8, 8), 10.0, 1.0, 0.7, 0.01, 0.7))
+    q.omega_hi[3] = 1.2
+    assert init(L.cglbm_init, q) == -3
+    assert "pop_b" in L.cglbm_last_error().decode()
