@@ -386,7 +386,7 @@ def main():
         kname = "k_fused<%d, %d, %d, %d, false, f32, false>" % (var["tx"], var["ty"], var["zc"],
                                                                var["min_waves"])
     else:
-        kname = "k_%s<f32>" % dom
+        kname = "k_%s<f32%s>" % (dom, ", false" if dom == "pull" else "")
     traffic = measured_traffic(kname) if (n == 256 and args.storage == "fp32") else None
     kb = kernel_bytes(args.storage)
     sb = step_bytes(args.storage)

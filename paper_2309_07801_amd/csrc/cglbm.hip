@@ -112,8 +112,13 @@ using CollideFn = void (*)(const BoxDev *, const int32_t *, float *, const void 
                           int64_t);
 using InitFn = void (*)(const BoxDev *, const int32_t *, const float *, const float *,
                         const float *, void *, int64_t, uint64_t, float);
-const PullFn kPull[5] = {k_pull<StoreF32>, k_pull<StoreF16>, k_pull<StoreBF16>, k_pull<StoreF32X>,
-                         k_pull<StoreF32P>};
+// [stash][storage]: the in-place layout's pull writes solid nodes to the stash
+const PullFn kPull[2][5] = {{k_pull<StoreF32, false>, k_pull<StoreF16, false>,
+                             k_pull<StoreBF16, false>, k_pull<StoreF32X, false>,
+                             k_pull<StoreF32P, false>},
+                            {k_pull<StoreF32, true>, k_pull<StoreF16, true>,
+                             k_pull<StoreBF16, true>, k_pull<StoreF32X, true>,
+                             k_pull<StoreF32P, true>}};
 const CollideFn kCollide[5] = {k_collide<StoreF32>, k_collide<StoreF16>, k_collide<StoreBF16>,
                                k_collide<StoreF32X>, k_collide<StoreF32P>};
 const InitFn kInit[5] = {k_init<StoreF32>, k_init<StoreF16>, k_init<StoreBF16>, k_init<StoreF32X>,
@@ -422,7 +427,8 @@ namespace {
 // k_wall_copy moves them into the buffer after the pull has completed.
 int launch_pull(cglbm_handle *h, hipStream_t s, int bounce) {
   void *stash = bounce && h->stash ? h->stash : nullptr;
-  hipLaunchKernelGGL(kPull[h->storage], dim3(h->L.nblk_pad), dim3(kBlock), 0, s, h->d_boxes,
+  hipLaunchKernelGGL(kPull[stash ? 1 : 0][h->storage], dim3(h->L.nblk_pad), dim3(kBlock), 0, s,
+                     h->d_boxes,
                      h->d_blk_box, h->pop[h->cur], h->pop[1 - h->cur], h->aux, h->L.total,
                      bounce, stash, h->L.wtotal);
   if (stash && !h->L.wblk_box.empty())
