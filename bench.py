@@ -68,6 +68,12 @@ def d2q9_bytes(storage: str) -> int:
     return 2 * (8 * (8 if storage == "fp32x" else 4) + 2 * 8)
 
 
+# Compact schedule (FP32, periodic boxes): per node the pull reads the 17
+# floats of the compact post-collision state and writes the 11 moments; the
+# fused kernel reads the moments and writes the compact state; once per
+# call the emission reads the compact state and stores the populations.
+COMPACT_BYTES = {"pull": 17 * 4 + 11 * 4, "fused": 11 * 4 + 17 * 4, "collide": 17 * 4 + 54 * 4}
+
 # storage format of the D2Q9 step kernel's template argument
 SNAMES = {"fp32": "StoreF32P", "fp32p": "StoreF32P", "fp16": "StoreF16", "bf16": "StoreBF16",
           "fp32x": "StoreF32X"}
@@ -79,15 +85,17 @@ def step_bytes(storage: str) -> int:
     return 2 * 54 * (2 if storage in ("fp16", "bf16") else 4)
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "k_fused_translating_droplet_256_hbm_counters.md")
+COUNTERS = os.path.join(ROOT, "profiles", "step_kernels_translating_droplet_256_counters.md")
+# FP32 vector issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# lane operations per second, unpacked (the 157.3 TFLOP/s figure counts an
+# FMA as two operations and packed FP32 as two lanes)
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 SOURCES = ("paper_2309_07801_amd/csrc/kernels.hpp", "paper_2309_07801_amd/csrc/lattice.hpp")
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per dispatch of `kernel` from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary (already scaled by the copy-kernel
-    calibration), or None if the summary is missing or the kernel sources
-    changed since the counters were taken."""
+def _counter_rows():
+    """Table rows of the committed rocprofv3 counter summary, or None if it
+    is missing or the kernel sources changed since it was taken."""
     import hashlib
     import re
     if not os.path.exists(COUNTERS):
@@ -99,10 +107,24 @@ def measured_traffic(kernel: str):
         h.update(open(os.path.join(ROOT, f), "rb").read())
     if not m or m.group(1) != h.hexdigest():
         return None
-    for line in text.splitlines():
-        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+    return [[c.strip() for c in line.strip().strip("|").split("|")] for line in text.splitlines()]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per dispatch of `kernel` (FETCH_SIZE / WRITE_SIZE, scaled by
+    the copy-kernel calibration), or None."""
+    for cells in _counter_rows() or []:
         if len(cells) == 6 and cells[0] == kernel:
             return float(cells[4])
+    return None
+
+
+def measured_valu(kernel: str):
+    """VALU wave64 instructions per dispatch of `kernel` (SQ_INSTS_VALU), or
+    None."""
+    for cells in _counter_rows() or []:
+        if len(cells) == 4 and cells[0] == kernel:
+            return float(cells[2])
     return None
 
 
@@ -118,6 +140,8 @@ def parse():
                     help="extra forms on the same workload ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--schedule", type=int, default=None, choices=(0, 1, 2),
+                    help="step schedule (default: the autotuner's choice)")
     ap.add_argument("--variant", type=int, default=-1,
                     help="fused launch geometry (default: autotune)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -169,7 +193,7 @@ def cpu_baseline(w, seconds):
 
 
 def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=False,
-             lattice="d3q27", inplace=False):
+             lattice="d3q27", inplace=False, schedule=None):
     """Initialise, autotune, time `steps` steps; return throughput, per-kernel
     event timings and (optionally) the final fields of box 0."""
     import torch
@@ -188,6 +212,8 @@ def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=False,
     else:
         tune_ms = sim.autotune(reps=5)
     var = pkg.variant_info(sim.variant(), lattice)
+    if schedule is not None:
+        sim.set_schedule(schedule)
     sim.step(max(warmup - 2, 0))  # also captures the step graph
     torch.cuda.synchronize()
     # timed region: direct launches with HIP events around every kernel
@@ -206,7 +232,12 @@ def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=False,
     torch.cuda.synchronize()
     graph_mlups = fluid * ngraph / (time.perf_counter() - t2) / 1e6
     d1 = sim.reduce()
-    kb = kernel_bytes(storage) if lattice == "d3q27" else {"fused": d2q9_bytes(storage)}
+    if lattice != "d3q27":
+        kb = {"fused": d2q9_bytes(storage)}
+    elif sim.schedule() == 2:
+        kb = COMPACT_BYTES
+    else:
+        kb = kernel_bytes(storage)
     kern = {}
     for k, (ms, cnt) in prof.items():
         if cnt:
@@ -217,7 +248,7 @@ def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=False,
     out = {"mlups": fluid * steps / dt / 1e6, "ms_per_step": dt / steps * 1e3, "dt": dt,
            "graph_mlups": graph_mlups,
            "fluid": fluid, "kernels": kern, "variant": var, "autotune_ms": tune_ms,
-           "schedule": ("fused", "three kernels")[sim.schedule()],
+           "schedule": ("fused", "three kernels", "compact")[sim.schedule()],
            "mass_drift": [float((m1[0] - m0[0]) / m0[0]), float((m1[1] - m0[1]) / m0[1])],
            "nonfinite": int(d1[:, 12].sum()), "steps": steps,
            "pop_buffer_bytes": sim.pop_a.numel() * (1 if inplace else 2)}
@@ -299,7 +330,7 @@ def rti_form(W=128, T_list=(1.0, 2.0, 3.0, 4.0)):
         d = sim.reduce()
         out["model_" + "ABCD"[model]] = {
             "mlups": round(w.box.fluid_nodes() * done / t_run / 1e6, 1), "steps": done,
-            "schedule": ("fused", "three kernels")[sim.schedule()],
+            "schedule": ("fused", "three kernels", "compact")[sim.schedule()],
             "T_spike_bubble_saddle": hist, "nonfinite": int(d[0, 12])}
         sim.close()
         del sim
@@ -376,20 +407,48 @@ def main():
     n = args.size
     w = WL.translating_droplet(n=n, R=32.0 * n / 256.0)
     forms_req = [f for f in args.forms.split(",") if f]
+    sched = args.schedule
+    if sched is None and args.storage in ("fp32", "fp32p"):
+        sched = 2  # the compact schedule serves this periodic FP32 workload
     main_r = run_form([w], args.storage, args.steps, args.warmup, args.variant,
-                      keep_fields=any(f in STORAGES for f in forms_req))
+                      keep_fields=any(f in STORAGES for f in forms_req), schedule=sched)
     fluid = main_r["fluid"]
-    kern = main_r["kernels"]
+    kern = {k: v for k, v in main_r["kernels"].items() if k != "collide" or main_r["schedule"] != "compact"}
     dom = max(kern, key=lambda k: kern[k]["share"])
     var = main_r["variant"]
-    if dom == "fused":
-        kname = "k_fused<%d, %d, %d, %d, false, f32, false>" % (var["tx"], var["ty"], var["zc"],
-                                                               var["min_waves"])
+    compact = main_r["schedule"] == "compact"
+    geo = (var["tx"], var["ty"], var["zc"], var["min_waves"])
+    if compact:
+        kname = {"pull": "k_cpull<32, 8, 32>",
+                 "fused": "k_fused<%d, %d, %d, %d, false, f32, false, true>" % geo}[dom]
+        kb = COMPACT_BYTES
     else:
-        kname = "k_%s<f32%s>" % (dom, ", false" if dom == "pull" else "")
-    traffic = measured_traffic(kname) if (n == 256 and args.storage == "fp32") else None
-    kb = kernel_bytes(args.storage)
+        kname = ("k_fused<%d, %d, %d, %d, false, f32, false>" % geo if dom == "fused"
+                 else "k_%s<f32%s>" % (dom, ", false" if dom == "pull" else ""))
+        kb = kernel_bytes(args.storage)
+    measured = n == 256 and args.storage == "fp32"
+    traffic = measured_traffic(kname) if measured else None
+    valu = measured_valu(kname) if measured else None
     sb = step_bytes(args.storage)
+    hbm_frac = kern[dom]["gbs"] / HBM_PEAK_GBS
+    roof = {"bound": "hbm", "achieved": round(kern[dom]["gbs"], 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(hbm_frac, 4), "traffic": traffic,
+            "traffic_unit": "bytes per launch", "algorithmic_bytes": kb[dom] * fluid, "kernel": kname}
+    if valu is not None:
+        # VALU issue rate of the dominant kernel: its counted wave64 VALU
+        # instructions per launch x 64 lanes / the live mean launch time
+        tops = valu * 64 / (kern[dom]["avg_ms"] * 1e-3) / 1e12
+        if tops / VALU_PEAK_TOPS > hbm_frac:
+            roof = {"bound": "alu", "achieved": round(tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
+                    "unit": "TOP/s", "frac": round(tops / VALU_PEAK_TOPS, 4),
+                    "op_unit": "FP32 VALU lane operations issued (SQ_INSTS_VALU x 64)",
+                    "traffic": traffic, "traffic_unit": "bytes per launch",
+                    "hbm": {"achieved": round(kern[dom]["gbs"], 1), "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": round(hbm_frac, 4),
+                            "algorithmic_bytes": kb[dom] * fluid},
+                    "kernel": kname}
+        else:
+            roof["valu_tops"] = round(tops, 2)
     line = {
         "metric": "MLUPS and % HBM roofline, FP32 vs FP16-storage vs batched, at fixed error",
         "value": round(main_r["mlups"], 1),
@@ -405,16 +464,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": "translating droplet %d^3 periodic, density ratio 10, R=%g, "
                                "u=0.05, %s storage" % (n, w.radii[0], args.storage),
-                   "nodes": fluid, "storage": args.storage},
-        "roofline": {"bound": "hbm", "achieved": round(kern[dom]["gbs"], 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(kern[dom]["gbs"] / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "traffic_unit": "bytes per launch",
-                     "algorithmic_bytes": kb[dom] * fluid, "kernel": kname},
+                   "nodes": fluid, "storage": args.storage, "schedule": main_r["schedule"]},
+        "roofline": roof,
         "step_roofline_frac": round(main_r["mlups"] * 1e6 * sb / (HBM_PEAK_GBS * 1e9), 4),
         "graph_mlups": round(main_r["graph_mlups"], 1),
         "step_bytes_per_node": sb,
-        "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in kern.items()},
+        "step_bytes_moved_per_node": (COMPACT_BYTES["pull"] + COMPACT_BYTES["fused"]) if compact
+                                     else kernel_bytes(args.storage)["pull"] + kernel_bytes(args.storage)["fused"],
+        "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()}
+                    for k, v in main_r["kernels"].items()},
         "fused_variant": var,
         "schedule": main_r["schedule"],
         "autotune_ms": [round(m, 4) for m in main_r["autotune_ms"]],
@@ -441,9 +499,9 @@ def main():
         elif f == "batched":
             boxes = WL.batched_boxes()
             steps_b = min(args.steps, 1000)
-            r = run_form(boxes, "fp32p", steps_b, args.warmup, args.variant)
+            r = run_form(boxes, "fp32p", steps_b, args.warmup, args.variant, schedule=2)
             forms["batched"] = {"workload": "96 periodic boxes, edges U{24..128}, density ratio "
-                                            "in {1,10,100}, FP32 (colour-pair layout)",
+                                            "in {1,10,100}, FP32 (colour-pair layout), compact schedule",
                                 "nodes": r["fluid"],
                                 "steps": steps_b, "mlups": round(r["mlups"], 1),
                                 "ms_per_step": round(r["ms_per_step"], 4),

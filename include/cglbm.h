@@ -247,15 +247,33 @@ int64_t cglbm_box_offset(const cglbm_handle *h, int32_t box);
 void *cglbm_state_buffer(const cglbm_handle *h);
 int cglbm_load_state(cglbm_handle *h, const void *src, void *stream);
 
-/* Launch schedule of a step (both compute the same update, bit for bit):
+/* Launch schedule of a step (0 and 1 compute the same update, bit for bit):
  *   0 (default) two launches: pull-streaming with local moments, then one
  *     column-marching kernel for the interface stencils and the collision;
- *   1 three launches: pull, LDS-tiled interface stencils, collision.
+ *   1 three launches: pull, LDS-tiled interface stencils, collision;
+ *   2 compact: the same update with the state between the steps of one
+ *     cglbm_step call held as each node's compact post-collision state
+ *     (17 floats: rho_r, rho_b, u, F, the six relaxed second-order central
+ *     moments and n; with unit higher-order rates the collided, recoloured
+ *     populations of Eqs. 66-67 and 18-19 are a function of them).  Each
+ *     step is a column-marching pull that rebuilds the collided populations
+ *     of a column and its ring in registers and sums the streamed moments
+ *     (Eq. 5), then the fused kernel writing compact states: about 224 bytes
+ *     per node and step instead of 520.  The first step of a call pulls the
+ *     stored populations and the call ends by storing the populations again
+ *     (one extra launch per call), so the stored state, the fields, the
+ *     diagnostics and checkpoints are those of schedule 0.  Results equal
+ *     schedule 0 bit for bit for one step per call and to FP32 rounding
+ *     otherwise (the moment sums run in another order).  Layouts: D3Q27,
+ *     CGLBM_FP32 or CGLBM_FP32_PAIRS storage, two buffers, Model D with Q,
+ *     unit higher rates, no walls; CGLBM_EUNSUPPORTED otherwise.  The
+ *     compact state lives in the population buffer that does not hold the
+ *     state.  cglbm_autotune chooses between 0 and 1 only: select 2 after it.
  * Returns CGLBM_EINVAL for other values. */
 int cglbm_set_schedule(cglbm_handle *h, int32_t schedule);
 
-/* Schedule the next step runs: 0 or 1 as above (1 whenever a box needs the
- * three-kernel schedule), -1 for a NULL handle. */
+/* Schedule the next step runs: 0, 1 or 2 as above (1 whenever a box needs
+ * the three-kernel schedule), -1 for a NULL handle. */
 int cglbm_get_schedule(const cglbm_handle *h);
 
 /* Graph execution of cglbm_step: 1 (default) runs pairs of time steps as one

@@ -339,7 +339,7 @@ class Simulation:
         _check(lib().cglbm_set_schedule(self.h, int(schedule)))
 
     def schedule(self) -> int:
-        """Schedule in use: 0 fused, 1 three kernels."""
+        """Schedule in use: 0 fused, 1 three kernels, 2 compact."""
         return int(lib().cglbm_get_schedule(self.h))
 
     def set_graph(self, enable: bool):

@@ -52,6 +52,7 @@ struct FusedVariant {
   int tx, ty, zc, minw;
   FusedFn fn[5][2];  // time step: [storage][any box with solid layers]
   FusedFn fx[2];     // field export (no population store): [solid layers]
+  FusedFn fc;        // compact schedule: compact state out (periodic, FP32)
 };
 #define FV_S(TX, TY, ZC, MW, S) \
   {k_fused<TX, TY, ZC, MW, false, S, false>, k_fused<TX, TY, ZC, MW, true, S, false>}
@@ -59,7 +60,8 @@ struct FusedVariant {
   {TX, TY, ZC, MW,                                                                           \
    {FV_S(TX, TY, ZC, MW, StoreF32), FV_S(TX, TY, ZC, MW, StoreF16), FV_S(TX, TY, ZC, MW, StoreBF16), \
     FV_S(TX, TY, ZC, MW, StoreF32X), FV_S(TX, TY, ZC, MW, StoreF32P)},                       \
-   {k_fused<TX, TY, ZC, MW, false, StoreF32, true>, k_fused<TX, TY, ZC, MW, true, StoreF32, true>}}
+   {k_fused<TX, TY, ZC, MW, false, StoreF32, true>, k_fused<TX, TY, ZC, MW, true, StoreF32, true>}, \
+   k_fused<TX, TY, ZC, MW, false, StoreF32, false, true>}
 const FusedVariant kFusedVariants[] = {
     FV(32, 8, 32, 4),  FV(32, 8, 64, 4),  FV(32, 8, 16, 4), FV(32, 8, 32, 1),
     FV(32, 16, 32, 4), FV(32, 16, 64, 4), FV(64, 4, 32, 4), FV(32, 4, 32, 4),
@@ -68,6 +70,13 @@ const FusedVariant kFusedVariants[] = {
 #undef FV
 #undef FV_S
 constexpr int kNumFused = (int)(sizeof(kFusedVariants) / sizeof(kFusedVariants[0]));
+
+// The compact schedule's pull (column tile and z chunk) and its conversion
+// back to stored populations (FP32 planes or FP32 pairs).
+constexpr int kCTX = 32, kCTY = 8, kCZC = 32;
+using CPullFn = void (*)(const BoxDev *, const int32_t *, const float *, float *, int64_t);
+using EmitFn = void (*)(const BoxDev *, const int32_t *, const float *, void *, int64_t);
+const CPullFn kCPull = k_cpull<kCTX, kCTY, kCZC>;
 
 // Tile shapes of the two-dimensional (D2Q9) step kernel, 256 threads each;
 // bitwise equal results, picked by cglbm_autotune.  Kernels per storage slot
@@ -123,6 +132,7 @@ const CollideFn kCollide[5] = {k_collide<StoreF32>, k_collide<StoreF16>, k_colli
                                k_collide<StoreF32X>, k_collide<StoreF32P>};
 const InitFn kInit[5] = {k_init<StoreF32>, k_init<StoreF16>, k_init<StoreBF16>, k_init<StoreF32X>,
                          k_init<StoreF32P>};
+const EmitFn kEmit[2] = {k_emit<StoreF32>, k_emit<StoreF32P>};
 const WallCopyFn kWallCopy[5] = {k_wall_copy<StoreF32>, k_wall_copy<StoreF16>,
                                  k_wall_copy<StoreBF16>, k_wall_copy<StoreF32X>,
                                  k_wall_copy<StoreF32P>};
@@ -156,6 +166,7 @@ struct Layout {
   std::vector<BoxDev> boxes;
   std::vector<int32_t> blk_box, tile_box, col_box;
   std::vector<int32_t> wblk_box;  // k_wall_copy blocks (in-place layouts with walls)
+  std::vector<int32_t> ccol_box;  // k_cpull column blocks (padded to a multiple of 8)
   int64_t wtotal = 0;             // wall-node slots of all boxes (stash plane length)
   int64_t total = 0;  // plane length (nodes, all boxes, aligned)
   int32_t nblk = 0, ntile = 0, ncol = 0, nblk_pad = 0;
@@ -328,6 +339,20 @@ void build_layout(int32_t n_boxes, const cglbm_box_params *boxes, Layout &L,
   // grids remapped across XCDs are padded to a multiple of 8 idle blocks
   L.nblk_pad = (int32_t)align_up(blk, 8);
   while ((int32_t)L.blk_box.size() < L.nblk_pad) L.blk_box.push_back(-1);
+  // k_cpull columns
+  int32_t ccol = 0;
+  for (size_t b = 0; b < L.boxes.size(); ++b) {
+    BoxDev &B = L.boxes[b];
+    B.ccol0 = ccol;
+    B.cncx = (B.nx + kCTX - 1) / kCTX;
+    B.cncy = (B.ny + kCTY - 1) / kCTY;
+    const int32_t nc = B.cncx * B.cncy * ((B.nz + kCZC - 1) / kCZC);
+    for (int32_t k = 0; k < nc; ++k) L.ccol_box.push_back((int32_t)b);
+    ccol += nc;
+    B.fccx = make_fastdiv((uint32_t)B.cncx);
+    B.fccy = make_fastdiv((uint32_t)B.cncy);
+  }
+  while ((int32_t)L.ccol_box.size() < align_up(ccol, 8)) L.ccol_box.push_back(-1);
 }
 
 // Column table of fused variant v: fills the per-box column fields.
@@ -397,6 +422,7 @@ struct cglbm_handle {
   bool inplace = false;          // pop[0] == pop[1]: one population buffer
   void *stash = nullptr;         // in-place layouts with walls: solid nodes' populations
   int32_t *d_wblk_box = nullptr;
+  int32_t *d_ccol_box = nullptr;  // k_cpull columns
   int device = 0;
   BoxDev *d_boxes = nullptr;
   int32_t *d_blk_box = nullptr;
@@ -413,6 +439,7 @@ struct cglbm_handle {
   int32_t use_graph = 1;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t graphc[2] = {nullptr, nullptr};  // compact schedule: two inner steps
   // profiling
   bool prof = false;
   std::vector<hipEvent_t> ev;
@@ -446,6 +473,39 @@ int launch_iface(cglbm_handle *h, hipStream_t s, int write_kappa) {
 
 // export == 0: interface stencils + collision of a time step; export != 0:
 // the interface fields n, F, Q, kappa into aux, populations untouched.
+// Compact schedule: the fused kernel writes the compact state into the
+// other population buffer; k_cpull turns it into the moments of the next
+// step; k_emit stores it as populations in the state buffer.
+int launch_fused_compact(cglbm_handle *h, hipStream_t s) {
+  const FusedVariant &F = kFusedVariants[h->variant];
+  const BoxDev *boxes = h->d_boxes;
+  const int32_t *cols = h->d_col_box;
+  float *aux = h->aux;
+  void *dst = h->pop[1 - h->cur];
+  int64_t plane = h->L.total;
+  void *args[] = {(void *)&boxes, (void *)&cols, (void *)&aux, (void *)&dst, (void *)&plane};
+  HIP_TRY(hipLaunchKernel((const void *)F.fc, dim3(h->L.ncol), dim3(F.tx * F.ty), args, 0, s));
+  return CGLBM_OK;
+}
+int launch_cpull(cglbm_handle *h, hipStream_t s) {
+  hipLaunchKernelGGL(kCPull, dim3((unsigned)h->L.ccol_box.size()), dim3(kCTX * kCTY), 0, s,
+                     h->d_boxes, h->d_ccol_box, (const float *)h->pop[1 - h->cur], h->aux,
+                     h->L.total);
+  return CGLBM_OK;
+}
+int launch_emit(cglbm_handle *h, hipStream_t s) {
+  hipLaunchKernelGGL(kEmit[h->storage == CGLBM_FP32_PAIRS ? 1 : 0], dim3(h->L.nblk_pad), dim3(kBlock),
+                     0, s, h->d_boxes, h->d_blk_box, (const float *)h->pop[1 - h->cur],
+                     h->pop[h->cur], h->L.total);
+  return CGLBM_OK;
+}
+// Layouts the compact schedule serves: D3Q27, FP32 storage (either layout),
+// two buffers, Model D with Q and unit higher rates, no walls.
+bool compact_ok(const cglbm_handle *h) {
+  return h->lattice == LATTICE_D3Q27 && !h->inplace && !h->L.general && !h->L.walls &&
+         (h->storage == CGLBM_FP32 || h->storage == CGLBM_FP32_PAIRS);
+}
+
 int launch_fused(cglbm_handle *h, hipStream_t s, int export_fields) {
   const FusedVariant &F = kFusedVariants[h->variant];
   const BoxDev *boxes = h->d_boxes;
@@ -463,6 +523,11 @@ int launch_fused(cglbm_handle *h, hipStream_t s, int export_fields) {
 // Select fused variant v: rebuild and upload the column tables.
 void drop_graphs(cglbm_handle *h) {
   for (hipGraphExec_t &g : h->graph)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+  for (hipGraphExec_t &g : h->graphc)
     if (g) {
       (void)hipGraphExecDestroy(g);
       g = nullptr;
@@ -558,6 +623,51 @@ int launch_step(cglbm_handle *h, hipStream_t s) {
   return rc;
 }
 
+// n steps of the compact schedule (launches only).  The state between calls
+// stays in stored populations: the first step pulls them, the last converts
+// the compact state back, and the state buffer parity is unchanged.
+int capture_compact_pair(cglbm_handle *h) {
+  if (!h->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  int rc = CGLBM_OK;
+  for (int k = 0; k < 2 && !rc; ++k) {
+    rc = launch_cpull(h, h->cap_stream);
+    if (!rc) rc = launch_fused_compact(h, h->cap_stream);
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(CGLBM_EHIP, "graph capture: %s", hipGetErrorString(e));
+  const hipError_t ei = hipGraphInstantiate(&h->graphc[h->cur], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) {
+    h->graphc[h->cur] = nullptr;
+    return fail(CGLBM_EHIP, "graph instantiate: %s", hipGetErrorString(ei));
+  }
+  return CGLBM_OK;
+}
+
+int step_compact(cglbm_handle *h, int32_t n, hipStream_t s) {
+  if (n == 0) return CGLBM_OK;
+  int rc = timed(h, s, KIND_PULL, [&] { return launch_pull(h, s, 1); });
+  if (!rc) rc = timed(h, s, KIND_FUSED, [&] { return launch_fused_compact(h, s); });
+  int32_t k = 1;
+  if (!rc && h->use_graph && !h->prof && n >= 3) {
+    if (!h->graphc[h->cur]) rc = capture_compact_pair(h);
+    for (; !rc && k + 1 < n; k += 2) HIP_TRY(hipGraphLaunch(h->graphc[h->cur], s));
+  }
+  for (; k < n && !rc; ++k) {
+    rc = timed(h, s, KIND_PULL, [&] { return launch_cpull(h, s); });
+    if (!rc) rc = timed(h, s, KIND_FUSED, [&] { return launch_fused_compact(h, s); });
+  }
+  if (!rc) rc = timed(h, s, KIND_COLLIDE, [&] { return launch_emit(h, s); });
+  if (!rc) rc = check_launch();
+  return rc;
+}
+
 // Capture two steps from the current parity (which they restore) on the
 // handle's private stream and instantiate them as an executable graph.
 int capture_pair(cglbm_handle *h) {
@@ -590,7 +700,7 @@ int compute_fields(cglbm_handle *h, hipStream_t s, int write_kappa) {
   }
   int rc = launch_pull(h, s, 0);
   if (rc) return rc;
-  if (effective_schedule(h) == 0)
+  if (effective_schedule(h) != 1)
     rc = launch_fused(h, s, 1);
   else
     rc = launch_iface(h, s, write_kappa);
@@ -754,7 +864,8 @@ int init_handle(int lattice, cglbm_handle **out, int32_t n_boxes, const cglbm_bo
   build_layout(n_boxes, boxes, h->L, lattice);
   for (const BoxDev &B : h->L.boxes) {
     if (!fastdiv_ok((uint32_t)B.nx, (uint32_t)B.n) || !fastdiv_ok((uint32_t)B.ny, (uint32_t)B.n) ||
-        !fastdiv_ok((uint32_t)B.tnx, 1u << 20) || !fastdiv_ok((uint32_t)B.tny, 1u << 20)) {
+        !fastdiv_ok((uint32_t)B.tnx, 1u << 20) || !fastdiv_ok((uint32_t)B.tny, 1u << 20) ||
+        !fastdiv_ok((uint32_t)B.cncx, 1u << 20) || !fastdiv_ok((uint32_t)B.cncy, 1u << 20)) {
       delete h;
       return fail(CGLBM_EINVAL, "index division self-check failed");
     }
@@ -776,6 +887,10 @@ int init_handle(int lattice, cglbm_handle **out, int32_t n_boxes, const cglbm_bo
       (e = hipMalloc(&h->d_part, sizeof(double) * kNPart * (size_t)h->L.nblk)) != hipSuccess ||
       (e = hipMalloc(&h->d_diag, sizeof(double) * kNPart * (size_t)n_boxes)) != hipSuccess ||
       (e = hipMalloc(&h->d_centre, sizeof(double) * 3 * (size_t)n_boxes)) != hipSuccess ||
+      (e = hipMalloc(&h->d_ccol_box, sizeof(int32_t) * h->L.ccol_box.size())) != hipSuccess ||
+      (e = hipMemcpyAsync(h->d_ccol_box, h->L.ccol_box.data(),
+                          sizeof(int32_t) * h->L.ccol_box.size(), hipMemcpyHostToDevice, s)) !=
+          hipSuccess ||
       (e = hipMemcpyAsync(h->d_boxes, h->L.boxes.data(), sizeof(BoxDev) * n_boxes,
                           hipMemcpyHostToDevice, s)) != hipSuccess ||
       (e = hipMemcpyAsync(h->d_blk_box, h->L.blk_box.data(),
@@ -821,6 +936,7 @@ int cglbm_step(cglbm_handle *h, int32_t n_steps, void *stream) {
   if (!h) return fail(CGLBM_ESTATE, "null handle");
   if (n_steps < 0) return fail(CGLBM_EINVAL, "n_steps must be >= 0");
   hipStream_t s = (hipStream_t)stream;
+  if (effective_schedule(h) == 2) return step_compact(h, n_steps, s);
   int32_t k = 0;
   if (h->use_graph && !h->prof && n_steps >= 2) {
     if (!h->graph[h->cur]) {
@@ -913,9 +1029,13 @@ int cglbm_reduce(cglbm_handle *h, const double *centre, double *out, int32_t out
 int cglbm_set_schedule(cglbm_handle *h, int32_t schedule) {
   g_err.clear();
   if (!h) return fail(CGLBM_ESTATE, "null handle");
-  if (schedule != 0 && schedule != 1) return fail(CGLBM_EINVAL, "unknown schedule %d", schedule);
+  if (schedule < 0 || schedule > 2) return fail(CGLBM_EINVAL, "unknown schedule %d", schedule);
   if (schedule != 0 && h->lattice == LATTICE_D2Q9)
     return fail(CGLBM_EUNSUPPORTED, "D2Q9 steps have one schedule (0)");
+  if (schedule == 2 && !compact_ok(h))
+    return fail(CGLBM_EUNSUPPORTED,
+                "the compact schedule needs FP32 storage, two buffers, Model D with Q, unit "
+                "higher rates and no walls");
   if (schedule != h->schedule) drop_graphs(h);
   h->schedule = schedule;
   return CGLBM_OK;
@@ -1072,6 +1192,7 @@ void cglbm_destroy(cglbm_handle *h) {
   if (h->d_centre) (void)hipFree(h->d_centre);
   if (h->stash) (void)hipFree(h->stash);
   if (h->d_wblk_box) (void)hipFree(h->d_wblk_box);
+  if (h->d_ccol_box) (void)hipFree(h->d_ccol_box);
   delete h;
 }
 

@@ -62,6 +62,9 @@ struct BoxDev {
   int32_t d2q9;         // 1: two-dimensional box of the D2Q9 lattice (App. A)
   int32_t wbase, wn;    // wall-node slots of the box in the in-place stash
   int32_t wblk0;        // first block of the box in k_wall_copy
+  int32_t ccol0;        // first column block of the box (k_cpull)
+  int32_t cncx, cncy;   // k_cpull columns along x, y
+  FastDiv fccx, fccy;   // division by cncx, cncy
 };
 
 constexpr int kBlock = 256;
@@ -803,6 +806,84 @@ __device__ __forceinline__ void collide_node(const BoxDev &B, const NodeIn &in, 
   emit_recoloured(B, k, ux, uy, uz, in.rr, in.rb, irho, p, in.nx, in.ny, in.nz, emit);
 }
 
+// ---------------------------------------------------------------------------
+// Compact post-collision state (unit higher rates, Model D with Q).  With
+// every rate above second order equal to one, the collided populations of a
+// node (Eqs. 66-67) and their recolouring (Eqs. 18-19) are a function of 17
+// values: rho_r, rho_b, u, F, the six relaxed second-order central moments
+// and n.  compact_of computes them from a node's moments and interface
+// fields with the arithmetic of collide_node; emit_compact rebuilds the
+// populations from them, bit for bit those collide_node emits.
+// ---------------------------------------------------------------------------
+constexpr int kCompact = 17;  // planes: rr rb ux uy uz Fx Fy Fz sxx syy szz sxy sxz syz nx ny nz
+
+__device__ __forceinline__ void compact_of(const BoxDev &B, const NodeIn &in, float (&c)[kCompact]) {
+  const float rho = in.rr + in.rb;
+  const float irho = rcp(rho);
+  const float ux = fmaf(0.5f, in.Fx, in.jx) * irho;
+  const float uy = fmaf(0.5f, in.Fy, in.jy) * irho;
+  const float uz = fmaf(0.5f, in.Fz, in.jz) * irho;
+  const float p = in.rr * B.cs2r + in.rb * B.cs2b;
+  const float sr = in.rr * B.ir0r, sb = in.rb * B.ir0b;
+  const float phi = (sr - sb) * rcp(sr + sb);
+  const float nu = 0.5f * ((1.0f + phi) * B.nu_r + (1.0f - phi) * B.nu_b);
+  const float w1 = p * rcp(fmaf(rho, nu, 0.5f * p));
+  const float w2 = B.omega2;
+  const float kxx = in.pxx - 2.0f * ux * in.jx + rho * ux * ux;
+  const float kyy = in.pyy - 2.0f * uy * in.jy + rho * uy * uy;
+  const float kzz = in.pzz - 2.0f * uz * in.jz + rho * uz * uz;
+  const float kxy = in.pxy - ux * in.jy - uy * in.jx + rho * ux * uy;
+  const float kxz = in.pxz - ux * in.jz - uz * in.jx + rho * ux * uz;
+  const float kyz = in.pyz - uy * in.jz - uz * in.jy + rho * uy * uz;
+  const float r1 = 1.0f - w1, h1 = 1.0f - 0.5f * w1;
+  const float A = r1 * (kxx - kyy) + h1 * (in.Qx - in.Qy);
+  const float Bd = r1 * (kxx - kzz) + h1 * (in.Qx - in.Qz);
+  const float T = (1.0f - w2) * (kxx + kyy + kzz) + 3.0f * w2 * p +
+                  (1.0f - 0.5f * w2) * (in.Qx + in.Qy + in.Qz);
+  const float third = 1.0f / 3.0f;
+  c[0] = in.rr;
+  c[1] = in.rb;
+  c[2] = ux;
+  c[3] = uy;
+  c[4] = uz;
+  c[5] = in.Fx;
+  c[6] = in.Fy;
+  c[7] = in.Fz;
+  c[8] = (A + Bd + T) * third;
+  c[9] = (T - 2.0f * A + Bd) * third;
+  c[10] = (T + A - 2.0f * Bd) * third;
+  c[11] = r1 * kxy;
+  c[12] = r1 * kxz;
+  c[13] = r1 * kyz;
+  c[14] = in.nx;
+  c[15] = in.ny;
+  c[16] = in.nz;
+}
+
+// The central moments and recolouring inputs of a compact state: k (Eqs.
+// 57-63 at unit higher rates), u, the colour fractions and R of Eq. (19).
+struct CompactPost {
+  float k[27];
+  float ux, uy, uz, cr, cb, Rx, Ry, Rz;
+};
+__device__ __forceinline__ void compact_post(const BoxDev &B, const float (&c)[kCompact],
+                                             CompactPost &o) {
+  const float rr = c[0], rb = c[1];
+  const float rho = rr + rb;
+  const float irho = rcp(rho);
+  const float p = rr * B.cs2r + rb * B.cs2b;
+  model_d_moments(rho, p, c[5], c[6], c[7], c[8], c[9], c[10], c[11], c[12], c[13], o.k);
+  o.ux = c[2];
+  o.uy = c[3];
+  o.uz = c[4];
+  o.cr = rr * irho;
+  o.cb = rb * irho;
+  const float s = B.beta * o.cr * o.cb * p;
+  o.Rx = s * c[14];
+  o.Ry = s * c[15];
+  o.Rz = s * c[16];
+}
+
 // Populations -> central moments about u along one axis: (f_-, f_0, f_+) ->
 // (k_0, k_1, k_2) = sum f (c - u)^n, n = 0, 1, 2 (Eq. 24 on D1Q3).
 __device__ __forceinline__ void pop_to_cm_1d(float fm, float f0, float fp, float u, float &k0,
@@ -1157,7 +1238,9 @@ struct FusedGeom {
   static constexpr int A_PER = (R3 + NT - 1) / NT;
 };
 
-template <int TX, int TY, int ZC, int MINW, bool WALLS, class S, bool EXPORT>
+// COMPACT: store each node's compact post-collision state (17 float planes
+// of dst, see compact_of) instead of its populations.
+template <int TX, int TY, int ZC, int MINW, bool WALLS, class S, bool EXPORT, bool COMPACT = false>
 __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict__ boxes,
                                                   const int32_t *__restrict__ col_box,
                                                   float *__restrict__ aux,
@@ -1310,7 +1393,11 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
   // the loads above are then followed by the same count of memory
   // instructions as in every later iteration, so the waits for them are
   // the same on both paths into the loop
-  if (!EXPORT) {
+  if (!EXPORT && COMPACT) {
+#pragma unroll
+    for (int k = 0; k < kCompact; ++k)
+      buf_st(0.f, plane_rsrc(dst_, plane_arg * 4, k), kDrop);
+  } else if (!EXPORT) {
     const Pops<S> dst(dst_, plane_arg);
     PopWriter<S> w(dst, B, 0u, false);
 #pragma unroll
@@ -1541,13 +1628,21 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
         in.Qx = Qx;
         in.Qy = Qy;
         in.Qz = Qz;
-        const double fr = d_rr, fb = d_rb;
-        const Pops<S> dst(dst_, plane);
-        PopWriter<S> w(dst, B, node, fluid && sd >= z0);
-        collide_node(B, in, w, [&] {
-          if (kPipeD) load_d(s - 2, plane);
-        });
-        w.finish(fr, fb);
+        if (COMPACT) {
+          float c[kCompact];
+          compact_of(B, in, c);
+          const uint32_t off = boff<float>(fluid && sd >= z0, node);
+#pragma unroll
+          for (int k = 0; k < kCompact; ++k) buf_st(c[k], plane_rsrc(dst_, plane * 4, k), off);
+        } else {
+          const double fr = d_rr, fb = d_rb;
+          const Pops<S> dst(dst_, plane);
+          PopWriter<S> w(dst, B, node, fluid && sd >= z0);
+          collide_node(B, in, w, [&] {
+            if (kPipeD) load_d(s - 2, plane);
+          });
+          w.finish(fr, fb);
+        }
       } else {
         // interface fields of every node of the box (zero at solid nodes)
         const uint32_t off = boff<float>(in_xy && sd >= z0, node);
@@ -1566,6 +1661,198 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
     h_Fz = f_Fz;
     h_k = f_k;
   }
+}
+
+// ---------------------------------------------------------------------------
+// k_cpull: the pull of the compact schedule.  The stored state is the
+// compact post-collision state of every node (k_fused<..., COMPACT>); the
+// moments of a node after streaming (Eq. 5) are sums of its neighbours'
+// collided populations, f_i(x) = f*_i(x - c_i).  A block owns a TX x TY
+// column and marches along z: for slab s it rebuilds the collided
+// populations of the column and its one-node ring in registers (z and y
+// passes of the back-transform), then, for each z component cz of the
+// velocities in turn, finishes the x pass of those 9 directions, hands them
+// through LDS, and every column node adds the 9 values arriving from its
+// neighbours to the moments of slab s + cz.  Slab s - 1 is then complete
+// (it received cz = +1 from s - 2, cz = 0 from s - 1 and cz = -1 from s, in
+// that order) and its 11 moments go to aux.  Periodic boxes only.
+// ---------------------------------------------------------------------------
+template <int TX, int TY>
+struct CPullGeom {
+  static constexpr int NT = TX * TY;
+  static constexpr int R1X = TX + 2, R1Y = TY + 2, R1 = R1X * R1Y;
+  static constexpr int CP = (R1 + NT - 1) / NT;  // ring points per thread
+};
+
+template <int TX, int TY, int ZC>
+__global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ boxes,
+                                                  const int32_t *__restrict__ ccol_box,
+                                                  const float *__restrict__ cst,
+                                                  float *__restrict__ aux, int64_t plane_arg) {
+  using G = CPullGeom<TX, TY>;
+  __shared__ float xb[18][G::R1];  // one z component: 9 directions x 2 colours
+  const int tid = threadIdx.x;
+  const uint32_t lb = xcd_block();
+  const int b = ccol_box[lb];
+  if (b < 0) return;
+  const BoxDev B = boxes[b];
+  const uint32_t t = lb - (uint32_t)B.ccol0;
+  const uint32_t tyz = fdiv(t, B.fccx);
+  const int cxi = (int)(t - tyz * (uint32_t)B.cncx);
+  const int czi = (int)fdiv(tyz, B.fccy);
+  const int cyi = (int)(tyz - (uint32_t)czi * (uint32_t)B.cncy);
+  const int x0 = cxi * TX, y0 = cyi * TY, z0 = czi * ZC;
+  const int nx = B.nx, ny = B.ny, nz = B.nz;
+  const int z1 = min(z0 + ZC, nz);
+  const uint32_t nxy = (uint32_t)nx * (uint32_t)ny;
+  // ring points of this thread (column and one-node ring, row-major);
+  // lanes past the ring read point 0 and write nothing
+  uint32_t roff[G::CP];
+#pragma unroll
+  for (int k = 0; k < G::CP; ++k) {
+    const int j = tid + k * G::NT;
+    roff[k] = 0;
+    if (j < G::R1) {
+      const int lx = j % G::R1X, ly = j / G::R1X;
+      roff[k] = (uint32_t)wrap_any(x0 + lx - 1, nx) + (uint32_t)nx * (uint32_t)wrap_any(y0 + ly - 1, ny);
+    }
+  }
+  const int ox = tid % TX, oy = tid / TX;
+  const bool in_xy = x0 + ox < nx && y0 + oy < ny;
+  const uint32_t oxy = (uint32_t)min(x0 + ox, nx - 1) + (uint32_t)nx * (uint32_t)min(y0 + oy, ny - 1);
+  // moments of slabs s-1, s, s+1 at the column node
+  float acc[3][11];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int m = 0; m < 11; ++m) acc[a][m] = 0.f;
+
+  for (int s = z0 - 1; s <= z1; ++s) {
+    const int64_t plane = opaque_i64(plane_arg);
+    const uint32_t zoff = (uint32_t)B.base + nxy * (uint32_t)wrap_any(s, nz);
+    float h[G::CP][3][3][3];
+    float pux[G::CP], pcr[G::CP], pcb[G::CP], pRx[G::CP], pRy[G::CP], pRz[G::CP];
+#pragma unroll
+    for (int k = 0; k < G::CP; ++k) {
+      float c[kCompact];
+#pragma unroll
+      for (int m = 0; m < kCompact; ++m) c[m] = ldpl(cst, plane, m, zoff + roff[k]);
+      CompactPost o;
+      compact_post(B, c, o);
+      float g[3][3][3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb)
+          cm_to_pop_1d(o.k[a + 3 * bb], o.k[a + 3 * bb + 9], o.k[a + 3 * bb + 18], o.uz, g[a][bb][0],
+                       g[a][bb][1], g[a][bb][2]);
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int cz = 0; cz < 3; ++cz)
+          cm_to_pop_1d(g[a][0][cz], g[a][1][cz], g[a][2][cz], o.uy, h[k][a][0][cz], h[k][a][1][cz],
+                       h[k][a][2][cz]);
+      pux[k] = o.ux;
+      pcr[k] = o.cr;
+      pcb[k] = o.cb;
+      pRx[k] = o.Rx;
+      pRy[k] = o.Ry;
+      pRz[k] = o.Rz;
+    }
+#pragma unroll
+    for (int pz = 0; pz < 3; ++pz) {
+      // the x pass and the recolouring (Eqs. 18-19) of the directions with
+      // z component pz - 1, as emit_recoloured computes them
+#pragma unroll
+      for (int k = 0; k < G::CP; ++k) {
+        const int j = tid + k * G::NT;
+        if (j < G::R1) {
+#pragma unroll
+          for (int cy = 0; cy < 3; ++cy) {
+            float fx[3];
+            cm_to_pop_1d(h[k][0][cy][pz], h[k][1][cy][pz], h[k][2][cy][pz], pux[k], fx[0], fx[1], fx[2]);
+#pragma unroll
+            for (int cx = 0; cx < 3; ++cx) {
+              const int i = dir_of(cx - 1, cy - 1, pz - 1);
+              const float cR = (kCX[i] ? (kCX[i] > 0 ? pRx[k] : -pRx[k]) : 0.f) +
+                               (kCY[i] ? (kCY[i] > 0 ? pRy[k] : -pRy[k]) : 0.f) +
+                               (kCZ[i] ? (kCZ[i] > 0 ? pRz[k] : -pRz[k]) : 0.f);
+              const float d = 3.0f * weight(i) * cR;
+              const int q = 3 * cy + cx;
+              xb[2 * q][j] = fmaf(pcr[k], fx[cx], d);
+              xb[2 * q + 1][j] = fmaf(pcb[k], fx[cx], -d);
+            }
+          }
+        }
+      }
+      __syncthreads();
+      // what arrives at the column node from (x - c_x, y - c_y) of slab s
+#pragma unroll
+      for (int cy = 0; cy < 3; ++cy)
+#pragma unroll
+        for (int cx = 0; cx < 3; ++cx) {
+          const int q = 3 * cy + cx;
+          const int ddx = cx - 1, ddy = cy - 1, ddz = pz - 1;
+          const int src = (ox + 1 - ddx) + G::R1X * (oy + 1 - ddy);
+          const float fr = xb[2 * q][src], fb = xb[2 * q + 1][src];
+          const float f = fr + fb;
+          float *a = acc[pz];
+          a[0] += fr;
+          a[1] += fb;
+          if (ddx) a[2] += ddx > 0 ? f : -f;
+          if (ddy) a[3] += ddy > 0 ? f : -f;
+          if (ddz) a[4] += ddz > 0 ? f : -f;
+          if (ddx) a[5] += f;
+          if (ddy) a[6] += f;
+          if (ddz) a[7] += f;
+          if (ddx * ddy) a[8] += ddx * ddy > 0 ? f : -f;
+          if (ddx * ddz) a[9] += ddx * ddz > 0 ? f : -f;
+          if (ddy * ddz) a[10] += ddy * ddz > 0 ? f : -f;
+        }
+      __syncthreads();
+    }
+    // slab s - 1 is complete
+    const uint32_t node = (uint32_t)B.base + oxy + nxy * (uint32_t)wrap_any(s - 1, nz);
+    const uint32_t off = boff<float>(in_xy && s - 1 >= z0, node);
+#pragma unroll
+    for (int m = 0; m < 11; ++m) buf_st(acc[0][m], plane_rsrc(aux, plane * 4, A_RR + m), off);
+#pragma unroll
+    for (int m = 0; m < 11; ++m) {
+      acc[0][m] = acc[1][m];
+      acc[1][m] = acc[2][m];
+      acc[2][m] = 0.f;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_emit: the compact state back to stored populations in format S: each
+// node's collided, recoloured populations (bit for bit those the fused
+// kernel would have stored), the state the next pull reads.
+// ---------------------------------------------------------------------------
+template <class S>
+__global__ __launch_bounds__(kBlock) void k_emit(const BoxDev *__restrict__ boxes,
+                                                 const int32_t *__restrict__ blk_box,
+                                                 const float *__restrict__ cst,
+                                                 void *__restrict__ dst_, int64_t plane) {
+  const uint32_t lb = xcd_block();
+  const int b = blk_box[lb];
+  if (b < 0) return;
+  const BoxDev B = boxes[b];
+  const int64_t local = (int64_t)(lb - B.blk0) * kBlock + threadIdx.x;
+  if (local >= B.n) return;
+  const uint32_t node = (uint32_t)(B.base + local);
+  float c[kCompact];
+#pragma unroll
+  for (int m = 0; m < kCompact; ++m) c[m] = ldpl_nt(cst, plane, m, node);
+  const float rho = c[0] + c[1];
+  const float irho = rcp(rho);
+  const float p = c[0] * B.cs2r + c[1] * B.cs2b;
+  float k[27];
+  model_d_moments(rho, p, c[5], c[6], c[7], c[8], c[9], c[10], c[11], c[12], c[13], k);
+  const Pops<S> dst(dst_, plane);
+  PopWriter<S> w(dst, B, node);
+  emit_recoloured(B, k, c[2], c[3], c[4], c[0], c[1], irho, p, c[14], c[15], c[16], w);
 }
 
 // ---------------------------------------------------------------------------

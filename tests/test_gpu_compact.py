@@ -1,0 +1,105 @@
+"""The compact schedule (schedule 2): the state of a node between the steps
+of one cglbm_step call is its compact post-collision state (17 values) and
+the pull rebuilds the collided populations of a column and its ring in
+registers.  Checks:
+
+* one step per call is bit for bit the fused schedule (the call is the
+  population pull, the compact fused kernel and the emission, whose
+  populations equal the fused kernel's);
+* many steps per call against the FP64 oracle with the FP32 bars, on a
+  ragged box and on a batch of unlike boxes, in both FP32 layouts;
+* close to the fused schedule after many steps (FP32 rounding of the moment
+  sums in another order), mass drift at FP32 rounding level;
+* layouts it does not serve are refused with CGLBM_EUNSUPPORTED."""
+import numpy as np
+import pytest
+
+import workloads as WL
+from _common import errors, gpu_fields, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(shape=(17, 13, 11), gamma=10.0, R=3.5, u=(0.02, -0.01, 0.005), walls=0, **kw):
+    box = WL.two_phase_box(shape, gamma, 1.0, 0.7, 0.01, 0.7, walls=walls, **kw)
+    c = tuple((n - 1) / 2.0 for n in shape)
+    return box, WL.droplet_fields(box, [c], [R], u_carrier=u)
+
+
+def _sim(cases, storage=0, **kw):
+    import paper_2309_07801_amd as pkg
+    return pkg.Simulation([pkg.box_params_of(b) for b, _ in cases], [f[0] for _, f in cases],
+                          [f[1] for _, f in cases], [f[2] for _, f in cases], seed=4, noise=1e-6,
+                          storage=storage, **kw)
+
+
+@pytest.mark.parametrize("storage", [0, 4])
+def test_single_step_calls_equal_fused_schedule(storage):
+    cases = [_case(), _case((40, 33, 21), R=6.0)]
+    out = []
+    for sched in (0, 2):
+        sim = _sim(cases, storage)
+        sim.set_schedule(sched)
+        assert sim.schedule() == sched
+        for _ in range(6):
+            sim.step(1)
+        out.append([gpu_fields(sim, k) for k in range(2)])
+        sim.close()
+    for a, b in zip(out[0], out[1]):
+        for name in a:
+            assert np.array_equal(a[name], b[name]), name
+
+
+@pytest.mark.parametrize("storage", [0, 4])
+def test_compact_schedule_parity_with_oracle(storage):
+    cases = [_case(), _case((24, 20, 9), gamma=3.0, R=4.0, u=(0.05, 0.0, 0.0)),
+             _case((40, 12, 45), R=4.0)]
+    sim = _sim(cases, storage)
+    sim.set_schedule(2)
+    sim.step(50)
+    for k, (box, fl) in enumerate(cases):
+        o = run_oracle(box, *fl, 50, seed=4, noise=1e-6, box_index=k)[0]
+        e = errors(gpu_fields(sim, k), o, box, 0.05)
+        print(k, e)
+        assert e["rho"] < 1e-5 and e["u"] < 1e-4 and e["phi"] < 1e-4, (k, e)
+    d = sim.reduce()
+    assert d[:, 12].sum() == 0
+    sim.close()
+
+
+def test_compact_schedule_close_to_fused_and_conserves_mass():
+    cases = [_case((48, 40, 36), R=8.0, u=(0.05, 0.0, 0.0))]
+    out, drift = [], []
+    for sched in (0, 2):
+        sim = _sim(cases)
+        sim.set_schedule(sched)
+        d0 = sim.reduce()[0]
+        sim.step(300)
+        d1 = sim.reduce()[0]
+        drift.append([(d1[k] - d0[k]) / d0[k] for k in (0, 1)])
+        out.append(gpu_fields(sim))
+        sim.close()
+    print("mass drift fused / compact", drift)
+    for name in ("rho_r", "rho_b"):
+        assert np.abs(out[0][name] - out[1][name]).max() <= 5e-5 * np.abs(out[0][name]).max(), name
+    for name in ("ux", "uy", "uz"):
+        assert np.abs(out[0][name] - out[1][name]).max() <= 5e-4 * 0.05, name
+    assert max(abs(x) for x in drift[1]) < 1e-4
+
+
+def test_compact_schedule_refuses_other_layouts():
+    import dataclasses
+    import paper_2309_07801_amd as pkg
+    b, f = _case()
+    refused = [
+        ([_case(walls=1)], {}),
+        ([(b, f)], {"storage": 1}),
+        ([(b, f)], {"inplace": True}),
+        ([(dataclasses.replace(b, model=0), f)], {}),
+    ]
+    for cases, kw in refused:
+        sim = _sim(cases, **kw)
+        with pytest.raises(pkg.CglbmError) as ei:
+            sim.set_schedule(2)
+        assert ei.value.code == -3
+        sim.close()

@@ -39,12 +39,14 @@ FIELDS = ("rho_r", "rho_b", "phi", "ux", "uy", "uz")
 BARS = {0: (2e-5, 2e-5, 2e-5), 1: (2e-3, 5e-2, 2e-2), 2: (2e-2, 3e-1, 1.5e-1)}
 
 
-def _gpu_run(w, storage, steps):
+def _gpu_run(w, storage, steps, schedule=None):
     import torch
     import paper_2309_07801_amd as pkg
     sim = pkg.Simulation([pkg.box_params_of(w.box)], [w.rho_r], [w.rho_b], [w.u], seed=w.seed,
                          noise=w.noise, storage=storage)
     sim.autotune(reps=1)
+    if schedule is not None:
+        sim.set_schedule(schedule)
     sim.step(steps)
     torch.cuda.synchronize()
     return sim
@@ -116,8 +118,8 @@ def _u_ref(box, U):
     return max(U, box.sigma / mu_max)
 
 
-def _check(w, storage, samples, U):
-    sim = _gpu_run(w, storage, STEPS)
+def _check(w, storage, samples, U, schedule=None):
+    sim = _gpu_run(w, storage, STEPS, schedule)
     box = w.box
     u_ref = _u_ref(box, U)
     nodes = [x + box.nx * (y + box.ny * z) for (x, y, z), _ in samples]
@@ -143,6 +145,14 @@ def test_translating_droplet_256_sampled():
     w = WL.translating_droplet()
     rng = np.random.Generator(np.random.PCG64(21))
     _check(w, 0, _samples(w, rng), 0.05)
+
+
+def test_translating_droplet_256_sampled_compact_schedule():
+    """The same workload in the compact schedule (two steps in one call: the
+    population pull, the compact pull, the emission back to populations)."""
+    w = WL.translating_droplet()
+    rng = np.random.Generator(np.random.PCG64(21))
+    _check(w, 0, _samples(w, rng), 0.05, schedule=2)
 
 
 @pytest.fixture(scope="module")
