@@ -212,6 +212,7 @@ def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=False,
     else:
         tune_ms = sim.autotune(reps=5)
     var = pkg.variant_info(sim.variant(), lattice)
+    cvar = sim.compact_variant() if lattice == "d3q27" else None
     if schedule is not None:
         sim.set_schedule(schedule)
     sim.step(max(warmup - 2, 0))  # also captures the step graph
@@ -251,7 +252,7 @@ def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=False,
            "schedule": ("fused", "three kernels", "compact")[sim.schedule()],
            "mass_drift": [float((m1[0] - m0[0]) / m0[0]), float((m1[1] - m0[1]) / m0[1])],
            "nonfinite": int(d1[:, 12].sum()), "steps": steps,
-           "pop_buffer_bytes": sim.pop_a.numel() * (1 if inplace else 2)}
+           "pop_buffer_bytes": sim.pop_a.numel() * (1 if inplace else 2), "compact_variant": cvar}
     if keep_fields:
         out["fields"] = {k: v.cpu().numpy() for k, v in
                          sim.moments(0, ("rho_r", "rho_b", "phi", "ux", "uy", "uz")).items()}
@@ -419,7 +420,8 @@ def main():
     compact = main_r["schedule"] == "compact"
     geo = (var["tx"], var["ty"], var["zc"], var["min_waves"])
     if compact:
-        kname = {"pull": "k_cpull<32, 8, 32>",
+        cv = main_r["compact_variant"]
+        kname = {"pull": "k_cpull<%d, %d, %d>" % (cv["tx"], cv["ty"], cv["zc"]),
                  "fused": "k_fused<%d, %d, %d, %d, false, f32, false, true>" % geo}[dom]
         kb = COMPACT_BYTES
     else:
@@ -474,6 +476,7 @@ def main():
         "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()}
                     for k, v in main_r["kernels"].items()},
         "fused_variant": var,
+        "compact_variant": main_r["compact_variant"],
         "schedule": main_r["schedule"],
         "autotune_ms": [round(m, 4) for m in main_r["autotune_ms"]],
         "mass_drift": main_r["mass_drift"],

@@ -276,6 +276,15 @@ int cglbm_set_schedule(cglbm_handle *h, int32_t schedule);
  * the three-kernel schedule), -1 for a NULL handle. */
 int cglbm_get_schedule(const cglbm_handle *h);
 
+/* Geometry of the compact schedule's pull: returns its index (-1 for a NULL
+ * handle) and, if info is not NULL, writes info[0] = x extent, info[1] =
+ * y extent of a block's column, info[2] = its z chunk.  cglbm_autotune
+ * chooses it (equal results) whenever the layout admits schedule 2. */
+int cglbm_compact_variant(const cglbm_handle *h, int32_t *info);
+/* Select the compact pull geometry v (0..4); synchronizes the stream.
+ * CGLBM_EINVAL for other v. */
+int cglbm_set_compact_variant(cglbm_handle *h, int32_t v, void *stream);
+
 /* Graph execution of cglbm_step: 1 (default) runs pairs of time steps as one
  * captured HIP graph (captured on first use on a private stream of default
  * priority, launched on the caller's stream; captured again after

@@ -40,7 +40,7 @@ EXPORTED = ("cglbm_query_sizes", "cglbm_init", "cglbm_step", "cglbm_moments", "c
             "cglbm_profile_begin", "cglbm_profile_end", "cglbm_destroy",
             "cglbm_last_error", "cglbm_version", "cglbm_query_sizes_d2q9", "cglbm_init_d2q9",
             "cglbm_lattice", "cglbm_variant_info_d2q9", "cglbm_state_buffer",
-            "cglbm_load_state")
+            "cglbm_load_state", "cglbm_compact_variant", "cglbm_set_compact_variant")
 # Lattices: the D3Q27 model of the paper's body and the D2Q9 model of App. A.
 LATTICES = ("d3q27", "d2q9")
 NUM_VARIANTS_D2Q9 = 4
@@ -122,6 +122,8 @@ def lib():
         L.cglbm_reduce.argtypes = [vp, C.POINTER(C.c_double), vp, i32, vp]
         L.cglbm_box_offset.argtypes = [vp, i32]
         L.cglbm_box_offset.restype = i64
+        L.cglbm_compact_variant.argtypes = [vp, C.POINTER(i32)]
+        L.cglbm_set_compact_variant.argtypes = [vp, i32, vp]
         L.cglbm_state_buffer.argtypes = [vp]
         L.cglbm_state_buffer.restype = vp
         L.cglbm_load_state.argtypes = [vp, vp, vp]
@@ -322,6 +324,15 @@ class Simulation:
 
     def variant(self) -> int:
         return int(lib().cglbm_get_variant(self.h))
+
+    def set_compact_variant(self, v: int):
+        _check(lib().cglbm_set_compact_variant(self.h, int(v), _stream_ptr(self.stream)))
+
+    def compact_variant(self):
+        """Column tile and z chunk of the compact schedule's pull."""
+        info = (C.c_int32 * 3)()
+        v = int(lib().cglbm_compact_variant(self.h, info))
+        return {"index": v, "tx": info[0], "ty": info[1], "zc": info[2]}
 
     def autotune(self, reps: int = 5):
         """Time every fused launch geometry and the three-kernel schedule and

@@ -71,12 +71,20 @@ const FusedVariant kFusedVariants[] = {
 #undef FV_S
 constexpr int kNumFused = (int)(sizeof(kFusedVariants) / sizeof(kFusedVariants[0]));
 
-// The compact schedule's pull (column tile and z chunk) and its conversion
-// back to stored populations (FP32 planes or FP32 pairs).
-constexpr int kCTX = 32, kCTY = 8, kCZC = 32;
+// The compact schedule's pull (column tile and z chunk, chosen by the
+// autotuner; equal results) and its conversion back to stored populations
+// (FP32 planes or FP32 pairs).
 using CPullFn = void (*)(const BoxDev *, const int32_t *, const float *, float *, int64_t);
 using EmitFn = void (*)(const BoxDev *, const int32_t *, const float *, void *, int64_t);
-const CPullFn kCPull = k_cpull<kCTX, kCTY, kCZC>;
+struct CPullVariant {
+  int tx, ty, zc;
+  CPullFn fn;
+};
+#define CV(TX, TY, ZC) {TX, TY, ZC, k_cpull<TX, TY, ZC>}
+const CPullVariant kCPullVariants[] = {CV(64, 8, 64), CV(64, 8, 32), CV(32, 8, 32), CV(64, 4, 32),
+                                       CV(32, 8, 64)};
+#undef CV
+constexpr int kNumCPull = (int)(sizeof(kCPullVariants) / sizeof(kCPullVariants[0]));
 
 // Tile shapes of the two-dimensional (D2Q9) step kernel, 256 threads each;
 // bitwise equal results, picked by cglbm_autotune.  Kernels per storage slot
@@ -339,14 +347,19 @@ void build_layout(int32_t n_boxes, const cglbm_box_params *boxes, Layout &L,
   // grids remapped across XCDs are padded to a multiple of 8 idle blocks
   L.nblk_pad = (int32_t)align_up(blk, 8);
   while ((int32_t)L.blk_box.size() < L.nblk_pad) L.blk_box.push_back(-1);
-  // k_cpull columns
+}
+
+// Column table of k_cpull variant v: fills the per-box ccol fields.
+void build_ccolumns(Layout &L, int v) {
+  const CPullVariant &C = kCPullVariants[v];
+  L.ccol_box.clear();
   int32_t ccol = 0;
   for (size_t b = 0; b < L.boxes.size(); ++b) {
     BoxDev &B = L.boxes[b];
     B.ccol0 = ccol;
-    B.cncx = (B.nx + kCTX - 1) / kCTX;
-    B.cncy = (B.ny + kCTY - 1) / kCTY;
-    const int32_t nc = B.cncx * B.cncy * ((B.nz + kCZC - 1) / kCZC);
+    B.cncx = (B.nx + C.tx - 1) / C.tx;
+    B.cncy = (B.ny + C.ty - 1) / C.ty;
+    const int32_t nc = B.cncx * B.cncy * ((B.nz + C.zc - 1) / C.zc);
     for (int32_t k = 0; k < nc; ++k) L.ccol_box.push_back((int32_t)b);
     ccol += nc;
     B.fccx = make_fastdiv((uint32_t)B.cncx);
@@ -423,6 +436,8 @@ struct cglbm_handle {
   void *stash = nullptr;         // in-place layouts with walls: solid nodes' populations
   int32_t *d_wblk_box = nullptr;
   int32_t *d_ccol_box = nullptr;  // k_cpull columns
+  size_t ccol_cap = 0;             // capacity of d_ccol_box (entries)
+  int32_t cvariant = 0;            // k_cpull geometry
   int device = 0;
   BoxDev *d_boxes = nullptr;
   int32_t *d_blk_box = nullptr;
@@ -488,7 +503,8 @@ int launch_fused_compact(cglbm_handle *h, hipStream_t s) {
   return CGLBM_OK;
 }
 int launch_cpull(cglbm_handle *h, hipStream_t s) {
-  hipLaunchKernelGGL(kCPull, dim3((unsigned)h->L.ccol_box.size()), dim3(kCTX * kCTY), 0, s,
+  const CPullVariant &C = kCPullVariants[h->cvariant];
+  hipLaunchKernelGGL(C.fn, dim3((unsigned)h->L.ccol_box.size()), dim3(C.tx * C.ty), 0, s,
                      h->d_boxes, h->d_ccol_box, (const float *)h->pop[1 - h->cur], h->aux,
                      h->L.total);
   return CGLBM_OK;
@@ -532,6 +548,28 @@ void drop_graphs(cglbm_handle *h) {
       (void)hipGraphExecDestroy(g);
       g = nullptr;
     }
+}
+
+// Select k_cpull variant v: rebuild and upload its column table.
+int select_cvariant(cglbm_handle *h, int v, hipStream_t s) {
+  drop_graphs(h);
+  build_ccolumns(h->L, v);
+  for (const BoxDev &B : h->L.boxes)
+    if (!fastdiv_ok((uint32_t)B.cncx, 1u << 20) || !fastdiv_ok((uint32_t)B.cncy, 1u << 20))
+      return fail(CGLBM_EINVAL, "index division self-check failed");
+  if (h->L.ccol_box.size() > h->ccol_cap) {
+    if (h->d_ccol_box) HIP_TRY(hipFree(h->d_ccol_box));
+    h->d_ccol_box = nullptr;
+    HIP_TRY(hipMalloc(&h->d_ccol_box, sizeof(int32_t) * h->L.ccol_box.size()));
+    h->ccol_cap = h->L.ccol_box.size();
+  }
+  HIP_TRY(hipMemcpyAsync(h->d_ccol_box, h->L.ccol_box.data(),
+                         sizeof(int32_t) * h->L.ccol_box.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(h->d_boxes, h->L.boxes.data(), sizeof(BoxDev) * h->L.boxes.size(),
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  h->cvariant = v;
+  return CGLBM_OK;
 }
 
 int select_variant(cglbm_handle *h, int v, hipStream_t s) {
@@ -862,6 +900,8 @@ int init_handle(int lattice, cglbm_handle **out, int32_t n_boxes, const cglbm_bo
   h->storage = storage;
   h->lattice = lattice;
   build_layout(n_boxes, boxes, h->L, lattice);
+  build_ccolumns(h->L, 0);
+  h->ccol_cap = h->L.ccol_box.size();
   for (const BoxDev &B : h->L.boxes) {
     if (!fastdiv_ok((uint32_t)B.nx, (uint32_t)B.n) || !fastdiv_ok((uint32_t)B.ny, (uint32_t)B.n) ||
         !fastdiv_ok((uint32_t)B.tnx, 1u << 20) || !fastdiv_ok((uint32_t)B.tny, 1u << 20) ||
@@ -1073,6 +1113,24 @@ int cglbm_set_variant(cglbm_handle *h, int32_t v, void *stream) {
 
 int cglbm_get_variant(const cglbm_handle *h) { return h ? h->variant : -1; }
 
+int cglbm_set_compact_variant(cglbm_handle *h, int32_t v, void *stream) {
+  g_err.clear();
+  if (!h) return fail(CGLBM_ESTATE, "null handle");
+  if (v < 0 || v >= kNumCPull) return fail(CGLBM_EINVAL, "compact variant %d out of range", v);
+  return select_cvariant(h, v, (hipStream_t)stream);
+}
+
+int cglbm_compact_variant(const cglbm_handle *h, int32_t *info) {
+  if (!h) return -1;
+  if (info) {
+    const CPullVariant &C = kCPullVariants[h->cvariant];
+    info[0] = C.tx;
+    info[1] = C.ty;
+    info[2] = C.zc;
+  }
+  return h->cvariant;
+}
+
 int cglbm_autotune(cglbm_handle *h, int32_t reps, double *ms_per_variant, void *stream) {
   g_err.clear();
   if (!h) return fail(CGLBM_ESTATE, "null handle");
@@ -1130,6 +1188,30 @@ int cglbm_autotune(cglbm_handle *h, int32_t reps, double *ms_per_variant, void *
       three_ms = (double)ms / reps;
       if (ms_per_variant) ms_per_variant[kNumFused] = three_ms;
     }
+  }
+  // the compact schedule's pull geometry: the compact state the fused kernel
+  // writes into the other buffer from the same pull, then each k_cpull
+  // variant on it (both write only that buffer and aux)
+  if (!rc && compact_ok(h) && !(rc = launch_fused_compact(h, s))) {
+    int cbest = h->cvariant;
+    double cbest_ms = 1e300;
+    for (int v = 0; v < kNumCPull && !rc; ++v) {
+      if ((rc = select_cvariant(h, v, s)) || (rc = launch_cpull(h, s))) break;
+      (void)hipEventRecord(e0, s);
+      for (int r = 0; r < reps && !rc; ++r) rc = launch_cpull(h, s);
+      (void)hipEventRecord(e1, s);
+      if (!rc) rc = check_launch();
+      if (!rc && hipEventSynchronize(e1) != hipSuccess)
+        rc = fail(CGLBM_EHIP, "autotune: event synchronize failed");
+      if (rc) break;
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if ((double)ms / reps < cbest_ms) {
+        cbest_ms = (double)ms / reps;
+        cbest = v;
+      }
+    }
+    if (!rc) rc = select_cvariant(h, cbest, s);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -16,6 +16,13 @@
 // or three (schedule 1, and general models or rates):
 //   k_pull, then k_interface (LDS-tiled stencils: phi, grad phi, n, kappa,
 //   F, u, Q) and k_collide (collision, recolouring, local store)
+// or, within one call of many steps (schedule 2, compact):
+//   k_cpull    the moments after streaming, summed from the collided
+//              populations the pull rebuilds from each node's 17-value
+//              compact post-collision state
+//   k_fused    as above, storing compact states instead of populations
+//   (the call's first step runs k_pull, and k_emit stores the populations
+//   at its end)
 #pragma once
 
 #include <hip/hip_fp16.h>
