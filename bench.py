@@ -214,7 +214,8 @@ def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=False,
     var = pkg.variant_info(sim.variant(), lattice)
     cvar = sim.compact_variant() if lattice == "d3q27" else None
     if schedule is not None:
-        sim.set_schedule(schedule)
+        sim.set_schedule(schedule)  # loads the geometry the autotuner chose for it
+        var = pkg.variant_info(sim.variant(), lattice)
     sim.step(max(warmup - 2, 0))  # also captures the step graph
     torch.cuda.synchronize()
     # timed region: direct launches with HIP events around every kernel

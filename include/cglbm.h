@@ -268,7 +268,11 @@ int cglbm_load_state(cglbm_handle *h, const void *src, void *stream);
  *     CGLBM_FP32 or CGLBM_FP32_PAIRS storage, two buffers, Model D with Q,
  *     unit higher rates, no walls; CGLBM_EUNSUPPORTED otherwise.  The
  *     compact state lives in the population buffer that does not hold the
- *     state.  cglbm_autotune chooses between 0 and 1 only: select 2 after it.
+ *     state.  cglbm_autotune chooses between 0 and 1 only (select 2 after
+ *     it); for layouts that admit 2 it also times the compact fused kernel
+ *     and pull per geometry and keeps the fastest for schedule 2.
+ * Selecting a schedule loads the fused geometry the autotuner chose for it
+ * (or the one cglbm_set_variant set), synchronizing the null stream.
  * Returns CGLBM_EINVAL for other values. */
 int cglbm_set_schedule(cglbm_handle *h, int32_t schedule);
 

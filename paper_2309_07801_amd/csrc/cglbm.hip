@@ -445,7 +445,9 @@ struct cglbm_handle {
   int32_t *d_col_box = nullptr;
   int32_t schedule = 0;        // 0 fused, 1 three kernels (D3Q27)
   int32_t lattice = LATTICE_D3Q27;
-  int32_t variant = 0;         // fused launch geometry
+  int32_t variant = 0;         // fused launch geometry (its column table is loaded)
+  int32_t fvar_pop = 0;        // fused geometry for schedules 0 and 1
+  int32_t fvar_compact = 0;    // fused geometry for schedule 2
   size_t col_cap = 0;          // capacity of d_col_box (entries)
   double *d_part = nullptr;    // block partials of the reduction
   double *d_diag = nullptr;    // per box kNPart doubles
@@ -1078,6 +1080,11 @@ int cglbm_set_schedule(cglbm_handle *h, int32_t schedule) {
                 "higher rates and no walls");
   if (schedule != h->schedule) drop_graphs(h);
   h->schedule = schedule;
+  // the fused geometry preferred by the schedule (the autotuner's choices)
+  if (h->lattice == LATTICE_D3Q27) {
+    const int32_t v = schedule == 2 ? h->fvar_compact : h->fvar_pop;
+    if (v != h->variant) return select_variant(h, v, nullptr);
+  }
   return CGLBM_OK;
 }
 
@@ -1108,6 +1115,7 @@ int cglbm_set_variant(cglbm_handle *h, int32_t v, void *stream) {
   if (!h) return fail(CGLBM_ESTATE, "null handle");
   const int nv = h->lattice == LATTICE_D2Q9 ? kNumV2 : kNumFused;
   if (v < 0 || v >= nv) return fail(CGLBM_EINVAL, "variant %d out of range", v);
+  h->fvar_pop = h->fvar_compact = v;
   return select_variant(h, v, (hipStream_t)stream);
 }
 
@@ -1168,6 +1176,30 @@ int cglbm_autotune(cglbm_handle *h, int32_t reps, double *ms_per_variant, void *
       best = v;
     }
   }
+  // the compact schedule's fused kernel on the same inputs (it writes
+  // compact states into the other buffer only): its own best geometry
+  int cfbest = best;
+  if (!rc && compact_ok(h)) {
+    double cf_ms = 1e300;
+    for (int v = 0; v < kNumFused && !rc; ++v) {
+      if ((rc = select_variant(h, v, s)) || (rc = launch_fused_compact(h, s))) break;
+      (void)hipEventRecord(e0, s);
+      for (int r = 0; r < reps && !rc; ++r) rc = launch_fused_compact(h, s);
+      (void)hipEventRecord(e1, s);
+      if (!rc) rc = check_launch();
+      if (!rc && hipEventSynchronize(e1) != hipSuccess)
+        rc = fail(CGLBM_EHIP, "autotune: event synchronize failed");
+      if (rc) break;
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if ((double)ms / reps < cf_ms) {
+        cf_ms = (double)ms / reps;
+        cfbest = v;
+      }
+    }
+  }
+  h->fvar_pop = best;
+  h->fvar_compact = cfbest;
   // the three-kernel schedule on the same inputs (its interface and collide
   // kernels are idempotent for a fixed pull as well)
   double three_ms = 1e300;
@@ -1192,7 +1224,8 @@ int cglbm_autotune(cglbm_handle *h, int32_t reps, double *ms_per_variant, void *
   // the compact schedule's pull geometry: the compact state the fused kernel
   // writes into the other buffer from the same pull, then each k_cpull
   // variant on it (both write only that buffer and aux)
-  if (!rc && compact_ok(h) && !(rc = launch_fused_compact(h, s))) {
+  if (!rc && compact_ok(h) && !(rc = select_variant(h, cfbest, s)) &&
+      !(rc = launch_fused_compact(h, s))) {
     int cbest = h->cvariant;
     double cbest_ms = 1e300;
     for (int v = 0; v < kNumCPull && !rc; ++v) {
@@ -1215,6 +1248,8 @@ int cglbm_autotune(cglbm_handle *h, int32_t reps, double *ms_per_variant, void *
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  if (!rc) rc = select_variant(h, best, s);
   if (rc) return rc;
   const int32_t sched = three_ms < best_ms ? 1 : 0;
   if (sched != h->schedule) drop_graphs(h);
