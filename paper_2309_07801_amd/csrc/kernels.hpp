@@ -1793,29 +1793,54 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
         }
       }
       __syncthreads();
-      // what arrives at the column node from (x - c_x, y - c_y) of slab s
+      // what arrives at the column node from (x - c_x, y - c_y) of slab s:
+      // the colour sums, then the moments of f = f_r + f_b over the 3 x 3
+      // directions by an x pass (sum, difference, sum of the ends of each
+      // row) and a y pass of the same kind
+      {
+        float fr[9], fb[9], f[9];
 #pragma unroll
-      for (int cy = 0; cy < 3; ++cy)
+        for (int cy = 0; cy < 3; ++cy)
 #pragma unroll
-        for (int cx = 0; cx < 3; ++cx) {
-          const int q = 3 * cy + cx;
-          const int ddx = cx - 1, ddy = cy - 1, ddz = pz - 1;
-          const int src = (ox + 1 - ddx) + G::R1X * (oy + 1 - ddy);
-          const float fr = xb[2 * q][src], fb = xb[2 * q + 1][src];
-          const float f = fr + fb;
-          float *a = acc[pz];
-          a[0] += fr;
-          a[1] += fb;
-          if (ddx) a[2] += ddx > 0 ? f : -f;
-          if (ddy) a[3] += ddy > 0 ? f : -f;
-          if (ddz) a[4] += ddz > 0 ? f : -f;
-          if (ddx) a[5] += f;
-          if (ddy) a[6] += f;
-          if (ddz) a[7] += f;
-          if (ddx * ddy) a[8] += ddx * ddy > 0 ? f : -f;
-          if (ddx * ddz) a[9] += ddx * ddz > 0 ? f : -f;
-          if (ddy * ddz) a[10] += ddy * ddz > 0 ? f : -f;
+          for (int cx = 0; cx < 3; ++cx) {
+            const int q = 3 * cy + cx;
+            const int src = (ox + 2 - cx) + G::R1X * (oy + 2 - cy);
+            fr[q] = xb[2 * q][src];
+            fb[q] = xb[2 * q + 1][src];
+            f[q] = fr[q] + fb[q];
+          }
+        float sr = fr[0], sb = fb[0];
+#pragma unroll
+        for (int q = 1; q < 9; ++q) {
+          sr += fr[q];
+          sb += fb[q];
         }
+        float r0[3], r1[3], r2[3];  // per row: sum, c_x-weighted, c_x^2-weighted
+#pragma unroll
+        for (int cy = 0; cy < 3; ++cy) {
+          r2[cy] = f[3 * cy + 2] + f[3 * cy];
+          r1[cy] = f[3 * cy + 2] - f[3 * cy];
+          r0[cy] = r2[cy] + f[3 * cy + 1];
+        }
+        const float m02 = r0[2] + r0[0], m01 = r0[2] - r0[0], m00 = m02 + r0[1];
+        const float m11 = r1[2] - r1[0], m10 = (r1[2] + r1[0]) + r1[1];
+        const float m20 = (r2[2] + r2[0]) + r2[1];
+        float *a = acc[pz];
+        a[0] += sr;
+        a[1] += sb;
+        a[2] += m10;
+        a[3] += m01;
+        a[5] += m20;
+        a[6] += m02;
+        a[8] += m11;
+        if (pz != 1) {
+          const bool up = pz == 2;
+          a[4] += up ? m00 : -m00;
+          a[7] += m00;
+          a[9] += up ? m10 : -m10;
+          a[10] += up ? m01 : -m01;
+        }
+      }
       __syncthreads();
     }
     // slab s - 1 is complete
