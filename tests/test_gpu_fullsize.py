@@ -179,11 +179,13 @@ def test_head_on_collision_768_sampled(storage):
     _check(w, storage, samples, 0.1)
 
 
-def test_batched_96_boxes_sampled():
+@pytest.mark.parametrize("schedule", [None, 2])
+def test_batched_96_boxes_sampled(schedule):
     """The 96-box batch as the benchmark runs it (FP32 colour-pair storage,
-    autotuned geometry, 44.9 M nodes): after 2 steps, nodes of six boxes
-    (the smallest and the largest among them) on the droplet interface and
-    inside and outside it, against 20^3 oracle windows of the same box."""
+    autotuned geometry, 44.9 M nodes; the autotuner's schedule and the
+    compact schedule): after 2 steps, nodes of six boxes (the smallest and
+    the largest among them) on the droplet interface and inside and outside
+    it, against 20^3 oracle windows of the same box."""
     import torch
     import paper_2309_07801_amd as pkg
     ws = WL.batched_boxes()
@@ -191,6 +193,8 @@ def test_batched_96_boxes_sampled():
                          [w.rho_b for w in ws], [w.u for w in ws], seed=ws[0].seed,
                          noise=ws[0].noise, storage=pkg.FP32_PAIRS)
     sim.autotune(reps=1)
+    if schedule is not None:
+        sim.set_schedule(schedule)
     sim.step(STEPS)
     torch.cuda.synchronize()
     sizes = [w.box.nodes for w in ws]
