@@ -266,9 +266,10 @@ int cglbm_load_state(cglbm_handle *h, const void *src, void *stream);
  *     schedule 0 bit for bit for one step per call and to FP32 rounding
  *     otherwise (the moment sums run in another order).  Layouts: D3Q27,
  *     CGLBM_FP32 or CGLBM_FP32_PAIRS storage, two buffers, Model D with Q,
- *     unit higher rates, no walls; CGLBM_EUNSUPPORTED otherwise.  The
- *     compact state lives in the population buffer that does not hold the
- *     state.  cglbm_autotune chooses between 0 and 1 only (select 2 after
+ *     unit higher rates; CGLBM_EUNSUPPORTED otherwise.  The compact state
+ *     lives in the population buffer that does not hold the state; solid
+ *     wall nodes keep their (bounced) populations in two library-owned
+ *     wall stashes allocated by cglbm_init.  cglbm_autotune chooses between 0 and 1 only (select 2 after
  *     it); for layouts that admit 2 it also times the compact fused kernel
  *     and pull per geometry and keeps the fastest for schedule 2.
  * Selecting a schedule loads the fused geometry the autotuner chose for it

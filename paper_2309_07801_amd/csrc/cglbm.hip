@@ -52,7 +52,7 @@ struct FusedVariant {
   int tx, ty, zc, minw;
   FusedFn fn[5][2];  // time step: [storage][any box with solid layers]
   FusedFn fx[2];     // field export (no population store): [solid layers]
-  FusedFn fc;        // compact schedule: compact state out (periodic, FP32)
+  FusedFn fc[2];     // compact schedule: compact state out (FP32): [solid layers]
 };
 #define FV_S(TX, TY, ZC, MW, S) \
   {k_fused<TX, TY, ZC, MW, false, S, false>, k_fused<TX, TY, ZC, MW, true, S, false>}
@@ -61,7 +61,8 @@ struct FusedVariant {
    {FV_S(TX, TY, ZC, MW, StoreF32), FV_S(TX, TY, ZC, MW, StoreF16), FV_S(TX, TY, ZC, MW, StoreBF16), \
     FV_S(TX, TY, ZC, MW, StoreF32X), FV_S(TX, TY, ZC, MW, StoreF32P)},                       \
    {k_fused<TX, TY, ZC, MW, false, StoreF32, true>, k_fused<TX, TY, ZC, MW, true, StoreF32, true>}, \
-   k_fused<TX, TY, ZC, MW, false, StoreF32, false, true>}
+   {k_fused<TX, TY, ZC, MW, false, StoreF32, false, true>,                                    \
+    k_fused<TX, TY, ZC, MW, true, StoreF32, false, true>}}
 const FusedVariant kFusedVariants[] = {
     FV(32, 8, 32, 4),  FV(32, 8, 64, 4),  FV(32, 8, 16, 4), FV(32, 8, 32, 1),
     FV(32, 16, 32, 4), FV(32, 16, 64, 4), FV(64, 4, 32, 4), FV(32, 4, 32, 4),
@@ -74,13 +75,17 @@ constexpr int kNumFused = (int)(sizeof(kFusedVariants) / sizeof(kFusedVariants[0
 // The compact schedule's pull (column tile and z chunk, chosen by the
 // autotuner; equal results) and its conversion back to stored populations
 // (FP32 planes or FP32 pairs).
-using CPullFn = void (*)(const BoxDev *, const int32_t *, const float *, float *, int64_t);
+using CPullFn = void (*)(const BoxDev *, const int32_t *, const float *, float *, int64_t,
+                         const void *, void *, int64_t);
 using EmitFn = void (*)(const BoxDev *, const int32_t *, const float *, void *, int64_t);
 struct CPullVariant {
   int tx, ty, zc;
-  CPullFn fn;
+  CPullFn fn;     // periodic boxes
+  CPullFn fw[2];  // solid layers present: wall stash in FP32 planes / FP32 pairs
 };
-#define CV(TX, TY, ZC) {TX, TY, ZC, k_cpull<TX, TY, ZC>}
+#define CV(TX, TY, ZC)                                                     \
+  {TX, TY, ZC, k_cpull<TX, TY, ZC>,                                        \
+   {k_cpull<TX, TY, ZC, true, StoreF32>, k_cpull<TX, TY, ZC, true, StoreF32P>}}
 const CPullVariant kCPullVariants[] = {CV(64, 8, 64), CV(64, 8, 32), CV(32, 8, 32), CV(64, 4, 32),
                                        CV(32, 8, 64)};
 #undef CV
@@ -436,6 +441,7 @@ struct cglbm_handle {
   void *stash = nullptr;         // in-place layouts with walls: solid nodes' populations
   int32_t *d_wblk_box = nullptr;
   int32_t *d_ccol_box = nullptr;  // k_cpull columns
+  void *cstash[2] = {nullptr, nullptr};  // compact schedule with walls: solid nodes' populations
   size_t ccol_cap = 0;             // capacity of d_ccol_box (entries)
   int32_t cvariant = 0;            // k_cpull geometry
   int device = 0;
@@ -501,26 +507,44 @@ int launch_fused_compact(cglbm_handle *h, hipStream_t s) {
   void *dst = h->pop[1 - h->cur];
   int64_t plane = h->L.total;
   void *args[] = {(void *)&boxes, (void *)&cols, (void *)&aux, (void *)&dst, (void *)&plane};
-  HIP_TRY(hipLaunchKernel((const void *)F.fc, dim3(h->L.ncol), dim3(F.tx * F.ty), args, 0, s));
+  HIP_TRY(hipLaunchKernel((const void *)F.fc[h->L.walls ? 1 : 0], dim3(h->L.ncol),
+                          dim3(F.tx * F.ty), args, 0, s));
   return CGLBM_OK;
 }
-int launch_cpull(cglbm_handle *h, hipStream_t s) {
+// rd: the wall stash this step's solid points emit from; the arrivals at
+// solid nodes go to the other one
+int launch_cpull(cglbm_handle *h, hipStream_t s, int rd = 0) {
   const CPullVariant &C = kCPullVariants[h->cvariant];
-  hipLaunchKernelGGL(C.fn, dim3((unsigned)h->L.ccol_box.size()), dim3(C.tx * C.ty), 0, s,
+  const CPullFn fn = h->L.walls ? C.fw[h->storage == CGLBM_FP32_PAIRS ? 1 : 0] : C.fn;
+  hipLaunchKernelGGL(fn, dim3((unsigned)h->L.ccol_box.size()), dim3(C.tx * C.ty), 0, s,
                      h->d_boxes, h->d_ccol_box, (const float *)h->pop[1 - h->cur], h->aux,
-                     h->L.total);
+                     h->L.total, (const void *)h->cstash[rd], h->cstash[1 - rd], h->L.wtotal);
   return CGLBM_OK;
 }
-int launch_emit(cglbm_handle *h, hipStream_t s) {
+// wi: the wall stash the last step wrote (the solid nodes' stored values)
+int launch_emit(cglbm_handle *h, hipStream_t s, int wi = 0) {
   hipLaunchKernelGGL(kEmit[h->storage == CGLBM_FP32_PAIRS ? 1 : 0], dim3(h->L.nblk_pad), dim3(kBlock),
                      0, s, h->d_boxes, h->d_blk_box, (const float *)h->pop[1 - h->cur],
                      h->pop[h->cur], h->L.total);
+  if (h->L.walls && !h->L.wblk_box.empty())
+    hipLaunchKernelGGL(kWallCopy[h->storage], dim3((unsigned)h->L.wblk_box.size()), dim3(kBlock),
+                       0, s, h->d_boxes, h->d_wblk_box, (const void *)h->cstash[wi],
+                       h->pop[h->cur], h->L.total, h->L.wtotal);
+  return CGLBM_OK;
+}
+// The first step of a compact call: the population pull, with the solid
+// nodes' reversed populations going to wall stash 0.
+int launch_pull_compact(cglbm_handle *h, hipStream_t s) {
+  void *stash = h->L.walls ? h->cstash[0] : nullptr;
+  hipLaunchKernelGGL(kPull[stash ? 1 : 0][h->storage], dim3(h->L.nblk_pad), dim3(kBlock), 0, s,
+                     h->d_boxes, h->d_blk_box, h->pop[h->cur], h->pop[1 - h->cur], h->aux,
+                     h->L.total, 1, stash, h->L.wtotal);
   return CGLBM_OK;
 }
 // Layouts the compact schedule serves: D3Q27, FP32 storage (either layout),
-// two buffers, Model D with Q and unit higher rates, no walls.
+// two buffers, Model D with Q and unit higher rates.
 bool compact_ok(const cglbm_handle *h) {
-  return h->lattice == LATTICE_D3Q27 && !h->inplace && !h->L.general && !h->L.walls &&
+  return h->lattice == LATTICE_D3Q27 && !h->inplace && !h->L.general &&
          (h->storage == CGLBM_FP32 || h->storage == CGLBM_FP32_PAIRS);
 }
 
@@ -671,7 +695,7 @@ int capture_compact_pair(cglbm_handle *h) {
   HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
   int rc = CGLBM_OK;
   for (int k = 0; k < 2 && !rc; ++k) {
-    rc = launch_cpull(h, h->cap_stream);
+    rc = launch_cpull(h, h->cap_stream, k);
     if (!rc) rc = launch_fused_compact(h, h->cap_stream);
   }
   hipGraph_t g = nullptr;
@@ -692,7 +716,11 @@ int capture_compact_pair(cglbm_handle *h) {
 
 int step_compact(cglbm_handle *h, int32_t n, hipStream_t s) {
   if (n == 0) return CGLBM_OK;
-  int rc = timed(h, s, KIND_PULL, [&] { return launch_pull(h, s, 1); });
+  // wall stashes (boxes with solid layers): step k's solid points emit from
+  // stash wi, its arrivals at solid nodes go to 1 - wi; the first step
+  // (the population pull) writes stash 0
+  int wi = 0;
+  int rc = timed(h, s, KIND_PULL, [&] { return launch_pull_compact(h, s); });
   if (!rc) rc = timed(h, s, KIND_FUSED, [&] { return launch_fused_compact(h, s); });
   int32_t k = 1;
   if (!rc && h->use_graph && !h->prof && n >= 3) {
@@ -700,10 +728,11 @@ int step_compact(cglbm_handle *h, int32_t n, hipStream_t s) {
     for (; !rc && k + 1 < n; k += 2) HIP_TRY(hipGraphLaunch(h->graphc[h->cur], s));
   }
   for (; k < n && !rc; ++k) {
-    rc = timed(h, s, KIND_PULL, [&] { return launch_cpull(h, s); });
+    rc = timed(h, s, KIND_PULL, [&] { return launch_cpull(h, s, wi); });
     if (!rc) rc = timed(h, s, KIND_FUSED, [&] { return launch_fused_compact(h, s); });
+    wi = 1 - wi;
   }
-  if (!rc) rc = timed(h, s, KIND_COLLIDE, [&] { return launch_emit(h, s); });
+  if (!rc) rc = timed(h, s, KIND_COLLIDE, [&] { return launch_emit(h, s, wi); });
   if (!rc) rc = check_launch();
   return rc;
 }
@@ -943,14 +972,19 @@ int init_handle(int lattice, cglbm_handle **out, int32_t n_boxes, const cglbm_bo
           hipSuccess) {
     return cleanup(fail(CGLBM_EHIP, "init: %s", hipGetErrorString(e)));
   }
-  if (inplace && h->L.walls) {
+  if (h->L.walls) {
+    // wall stashes: the in-place layout's, or the compact schedule's pair
     size_t sb = 0, ab = 0;
     buffer_sizes(storage, h->L.wtotal, &sb, &ab, lattice);
-    if ((e = hipMalloc(&h->stash, sb)) != hipSuccess ||
-        (e = hipMalloc(&h->d_wblk_box, sizeof(int32_t) * h->L.wblk_box.size())) != hipSuccess ||
+    const bool cst = lattice == LATTICE_D3Q27 && !inplace &&
+                     (storage == CGLBM_FP32 || storage == CGLBM_FP32_PAIRS);
+    if ((e = hipMalloc(&h->d_wblk_box, sizeof(int32_t) * h->L.wblk_box.size())) != hipSuccess ||
         (e = hipMemcpyAsync(h->d_wblk_box, h->L.wblk_box.data(),
                             sizeof(int32_t) * h->L.wblk_box.size(), hipMemcpyHostToDevice, s)) !=
-            hipSuccess)
+            hipSuccess ||
+        (inplace && (e = hipMalloc(&h->stash, sb)) != hipSuccess) ||
+        (cst && ((e = hipMalloc(&h->cstash[0], sb)) != hipSuccess ||
+                 (e = hipMalloc(&h->cstash[1], sb)) != hipSuccess)))
       return cleanup(fail(CGLBM_EHIP, "init: %s", hipGetErrorString(e)));
   }
   if ((rc = select_variant(h, 0, s))) return cleanup(rc);
@@ -1308,6 +1342,8 @@ void cglbm_destroy(cglbm_handle *h) {
   if (h->d_diag) (void)hipFree(h->d_diag);
   if (h->d_centre) (void)hipFree(h->d_centre);
   if (h->stash) (void)hipFree(h->stash);
+  for (void *p : h->cstash)
+    if (p) (void)hipFree(p);
   if (h->d_wblk_box) (void)hipFree(h->d_wblk_box);
   if (h->d_ccol_box) (void)hipFree(h->d_ccol_box);
   delete h;

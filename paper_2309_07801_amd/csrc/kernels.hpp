@@ -1682,7 +1682,11 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
 // through LDS, and every column node adds the 9 values arriving from its
 // neighbours to the moments of slab s + cz.  Slab s - 1 is then complete
 // (it received cz = +1 from s - 2, cz = 0 from s - 1 and cz = -1 from s, in
-// that order) and its 11 moments go to aux.  Periodic boxes only.
+// that order) and its 11 moments go to aux.
+// WALLS: solid nodes keep populations (full-way bounce-back): a solid ring
+// point emits what its slot of the wall stash wst_in holds (in storage
+// format S), and what arrives at a solid column node is stored reversed in
+// wst_out for the next step; its moments are zero.
 // ---------------------------------------------------------------------------
 template <int TX, int TY>
 struct CPullGeom {
@@ -1691,11 +1695,13 @@ struct CPullGeom {
   static constexpr int CP = (R1 + NT - 1) / NT;  // ring points per thread
 };
 
-template <int TX, int TY, int ZC>
+template <int TX, int TY, int ZC, bool WALLS = false, class S = StoreF32>
 __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ boxes,
                                                   const int32_t *__restrict__ ccol_box,
                                                   const float *__restrict__ cst,
-                                                  float *__restrict__ aux, int64_t plane_arg) {
+                                                  float *__restrict__ aux, int64_t plane_arg,
+                                                  const void *__restrict__ wst_in,
+                                                  void *__restrict__ wst_out, int64_t wplane) {
   using G = CPullGeom<TX, TY>;
   __shared__ float xb[18][G::R1];  // one z component: 9 directions x 2 colours
   const int tid = threadIdx.x;
@@ -1715,17 +1721,22 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
   // ring points of this thread (column and one-node ring, row-major);
   // lanes past the ring read point 0 and write nothing
   uint32_t roff[G::CP];
+  int rgx[G::CP], rgy[G::CP];
 #pragma unroll
   for (int k = 0; k < G::CP; ++k) {
     const int j = tid + k * G::NT;
     roff[k] = 0;
+    rgx[k] = rgy[k] = 0;
     if (j < G::R1) {
       const int lx = j % G::R1X, ly = j / G::R1X;
-      roff[k] = (uint32_t)wrap_any(x0 + lx - 1, nx) + (uint32_t)nx * (uint32_t)wrap_any(y0 + ly - 1, ny);
+      rgx[k] = wrap_any(x0 + lx - 1, nx);
+      rgy[k] = wrap_any(y0 + ly - 1, ny);
+      roff[k] = (uint32_t)rgx[k] + (uint32_t)nx * (uint32_t)rgy[k];
     }
   }
   const int ox = tid % TX, oy = tid / TX;
   const bool in_xy = x0 + ox < nx && y0 + oy < ny;
+  const int gxo = min(x0 + ox, nx - 1), gyo = min(y0 + oy, ny - 1);
   const uint32_t oxy = (uint32_t)min(x0 + ox, nx - 1) + (uint32_t)nx * (uint32_t)min(y0 + oy, ny - 1);
   // moments of slabs s-1, s, s+1 at the column node
   float acc[3][11];
@@ -1736,7 +1747,15 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
 
   for (int s = z0 - 1; s <= z1; ++s) {
     const int64_t plane = opaque_i64(plane_arg);
-    const uint32_t zoff = (uint32_t)B.base + nxy * (uint32_t)wrap_any(s, nz);
+    const int gz = wrap_any(s, nz);
+    const uint32_t zoff = (uint32_t)B.base + nxy * (uint32_t)gz;
+    bool rsolid[G::CP];
+    uint32_t rslot[G::CP];
+#pragma unroll
+    for (int k = 0; k < G::CP; ++k) {
+      rsolid[k] = WALLS && tid + k * G::NT < G::R1 && is_solid(B, rgy[k], gz);
+      rslot[k] = rsolid[k] ? (uint32_t)B.wbase + wall_slot(B, rgx[k], rgy[k], gz) : 0u;
+    }
     float h[G::CP][3][3][3];
     float pux[G::CP], pcr[G::CP], pcb[G::CP], pRx[G::CP], pRy[G::CP], pRz[G::CP];
 #pragma unroll
@@ -1786,8 +1805,17 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
                                (kCZ[i] ? (kCZ[i] > 0 ? pRz[k] : -pRz[k]) : 0.f);
               const float d = 3.0f * weight(i) * cR;
               const int q = 3 * cy + cx;
-              xb[2 * q][j] = fmaf(pcr[k], fx[cx], d);
-              xb[2 * q + 1][j] = fmaf(pcb[k], fx[cx], -d);
+              float vr = fmaf(pcr[k], fx[cx], d), vb = fmaf(pcb[k], fx[cx], -d);
+              if (WALLS && rsolid[k]) {
+                // a solid point emits what the bounce-back stored there
+                const Pops<S> win(const_cast<void *>(wst_in), wplane);
+                typename S::T er, eb;
+                ld_rb(win, i, rslot[k], er, eb);
+                vr = S::dec(er);
+                vb = S::dec(eb);
+              }
+              xb[2 * q][j] = vr;
+              xb[2 * q + 1][j] = vb;
             }
           }
         }
@@ -1825,6 +1853,22 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
         const float m02 = r0[2] + r0[0], m01 = r0[2] - r0[0], m00 = m02 + r0[1];
         const float m11 = r1[2] - r1[0], m10 = (r1[2] + r1[0]) + r1[1];
         const float m20 = (r2[2] + r2[0]) + r2[1];
+        if (WALLS) {
+          // a solid column node keeps what arrives, reversed, for the next step
+          const int d = s + pz - 1, gd = wrap_any(d, nz);
+          if (in_xy && d >= z0 && d < z1 && is_solid(B, gyo, gd)) {
+            const Pops<S> wout(wst_out, wplane);
+            const uint32_t slot = (uint32_t)B.wbase + wall_slot(B, gxo, gyo, gd);
+#pragma unroll
+            for (int cy = 0; cy < 3; ++cy)
+#pragma unroll
+              for (int cx = 0; cx < 3; ++cx) {
+                const int q = 3 * cy + cx;
+                st_rb(wout, opposite(dir_of(cx - 1, cy - 1, pz - 1)), slot, S::enc(fr[q]),
+                      S::enc(fb[q]));
+              }
+          }
+        }
         float *a = acc[pz];
         a[0] += sr;
         a[1] += sb;
@@ -1843,11 +1887,14 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
       }
       __syncthreads();
     }
-    // slab s - 1 is complete
-    const uint32_t node = (uint32_t)B.base + oxy + nxy * (uint32_t)wrap_any(s - 1, nz);
+    // slab s - 1 is complete (solid nodes: zero moments)
+    const int gzm = wrap_any(s - 1, nz);
+    const uint32_t node = (uint32_t)B.base + oxy + nxy * (uint32_t)gzm;
     const uint32_t off = boff<float>(in_xy && s - 1 >= z0, node);
+    const bool osolid = WALLS && is_solid(B, gyo, gzm);
 #pragma unroll
-    for (int m = 0; m < 11; ++m) buf_st(acc[0][m], plane_rsrc(aux, plane * 4, A_RR + m), off);
+    for (int m = 0; m < 11; ++m)
+      buf_st(osolid ? 0.f : acc[0][m], plane_rsrc(aux, plane * 4, A_RR + m), off);
 #pragma unroll
     for (int m = 0; m < 11; ++m) {
       acc[0][m] = acc[1][m];

@@ -10,6 +10,8 @@ registers.  Checks:
   ragged box and on a batch of unlike boxes, in both FP32 layouts;
 * close to the fused schedule after many steps (FP32 rounding of the moment
   sums in another order), mass drift at FP32 rounding level;
+* boxes with solid walls (the wall stashes of the bounce-back): one step per
+  call bitwise, many steps against the oracle;
 * layouts it does not serve are refused with CGLBM_EUNSUPPORTED."""
 import numpy as np
 import pytest
@@ -92,7 +94,6 @@ def test_compact_schedule_refuses_other_layouts():
     import paper_2309_07801_amd as pkg
     b, f = _case()
     refused = [
-        ([_case(walls=1)], {}),
         ([(b, f)], {"storage": 1}),
         ([(b, f)], {"inplace": True}),
         ([(dataclasses.replace(b, model=0), f)], {}),
@@ -138,3 +139,62 @@ def test_compact_pull_geometries_agree_bitwise():
     for a, b in zip(out[0], out[1]):
         for name in a:
             assert np.array_equal(a[name], b[name]), name
+
+
+WALLED = (((17, 13, 11), 3), ((24, 20, 9), 1), ((20, 9, 14), 2), ((23, 16, 12), 0))
+
+
+def _walled_cases():
+    out = []
+    for shape, walls in WALLED:
+        out.append(_case(shape, R=3.0, u=(0.02, 0.0, 0.01), walls=walls))
+    return out
+
+
+@pytest.mark.parametrize("storage", [0, 4])
+def test_walls_single_step_calls_equal_fused_schedule(storage):
+    cases = _walled_cases()
+    out = []
+    for sched in (0, 2):
+        sim = _sim(cases, storage)
+        sim.set_schedule(sched)
+        for _ in range(5):
+            sim.step(1)
+        out.append([gpu_fields(sim, k) for k in range(len(cases))])
+        sim.close()
+    for a, b in zip(out[0], out[1]):
+        for name in a:
+            assert np.array_equal(a[name], b[name]), name
+
+
+@pytest.mark.parametrize("storage", [0, 4])
+def test_walls_parity_with_oracle(storage):
+    """A batch of boxes with every wall combination, 60 steps in one call
+    (graph pairs, the wall stashes alternating), against the oracle."""
+    cases = _walled_cases()
+    sim = _sim(cases, storage)
+    sim.set_schedule(2)
+    sim.step(60)
+    for k, (box, fl) in enumerate(cases):
+        o = run_oracle(box, *fl, 60, seed=4, noise=1e-6, box_index=k)[0]
+        e = errors(gpu_fields(sim, k), o, box, 0.02)
+        print(k, box.walls, e)
+        assert e["rho"] < 1e-5 and e["u"] < 1e-4 and e["phi"] < 1e-4, (k, e)
+    d = sim.reduce()
+    assert d[:, 12].sum() == 0
+    sim.close()
+
+
+def test_walls_close_to_fused_over_many_steps():
+    cases = [_case((40, 24, 30), R=6.0, u=(0.04, 0.0, 0.0), walls=3)]
+    out = []
+    for sched in (0, 2):
+        sim = _sim(cases)
+        sim.set_schedule(sched)
+        sim.step(250)
+        out.append(gpu_fields(sim))
+        sim.close()
+    for name in ("rho_r", "rho_b"):
+        assert np.abs(out[0][name] - out[1][name]).max() <= 5e-5 * np.abs(out[0][name]).max(), name
+    for name in ("ux", "uy", "uz"):
+        assert np.abs(out[0][name] - out[1][name]).max() <= 5e-4 * 0.04, name
