@@ -167,8 +167,9 @@ def test_sheared_droplets_512_sampled(sheared_512, storage):
     _check(w, storage, _samples(w, rng, n_iface=2, n_in=1, n_out=1), 0.04)
 
 
-@pytest.mark.parametrize("storage", [0, 1])
-def test_head_on_collision_768_sampled(storage):
+@pytest.mark.parametrize("storage,schedule", [(0, None), (1, None), (0, 2)])
+def test_head_on_collision_768_sampled(storage, schedule):
+    """Walls in y and z; the compact schedule's wall stashes included."""
     w = WL.head_on_collision()
     box = w.box
     rng = np.random.Generator(np.random.PCG64(23))
@@ -176,7 +177,7 @@ def test_head_on_collision_768_sampled(storage):
     # next to the walls: first fluid layers of y, of z, and of both
     for wall_axes, (y, z) in ((1, (1, 190)), (1, (2, 100)), (2, (190, 1)), (3, (1, 1)), (3, (2, 3))):
         samples.append(((int(rng.integers(0, box.nx)), y, z), wall_axes))
-    _check(w, storage, samples, 0.1)
+    _check(w, storage, samples, 0.1, schedule=schedule)
 
 
 @pytest.mark.parametrize("schedule", [None, 2])
