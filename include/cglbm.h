@@ -29,8 +29,9 @@
  *     that a pull reproduces f(x,t).
  *   - All device pointers are caller-owned device memory (for instance torch
  *     tensors).  The library never frees caller memory; it owns only the
- *     handle, small parameter tables, a reduction scratch area and captured
- *     graphs.
+ *     handle, small parameter tables, a reduction scratch area, captured
+ *     graphs and, for boxes with walls, the wall stashes of the in-place
+ *     layout and of the compact schedule (populations of solid nodes only).
  *   - `stream` is a hipStream_t passed as void*.  Every call enqueues its work
  *     on that stream and returns without synchronizing, except where stated.
  *   - Return codes: CGLBM_OK (0) or a negative CGLBM_E* code; a message for
