@@ -5,11 +5,16 @@ droplet of radius 32 moving with u = 0.05 along x in a blue carrier, density
 ratio 10, equal dynamic viscosities, shear rate 1.6 and bulk rate 1.0,
 sigma = 0.005, beta = 0.7, +-1e-6 counter noise on the populations, FP32
 storage and arithmetic.  A step is one full time update of every node
-(pull-streaming, moments, interface stencils, collision, recolouring).
+(pull-streaming, moments, interface stencils, collision, recolouring).  The
+FP32 lines run the compact schedule (the state between the steps of a call
+held as each node's 17-value post-collision state); `--schedule 0` runs the
+population schedule.
 
 Prints ONE JSON line: MLUPS of the timed steps, the roofline of the dominant
-kernel (algorithmic bytes per launch / average launch time from HIP events
-recorded on the launch stream during the timed region) and the FP64 CPU
+kernel (against HBM: algorithmic bytes per launch / average launch time from
+HIP events recorded on the launch stream during the timed region; against
+the FP32 vector issue rate: the committed SQ_INSTS_VALU count per launch x 64
+lanes / the same time; reported against the closer ceiling) and the FP64 CPU
 oracle timed on a bounded sample of the same workload.  `forms` reports, on
 the same workload and step counts, the FP16/BF16-shifted and mass-exact FP32
 storage (with their difference to the FP32 run as a proxy error), the
