@@ -274,7 +274,8 @@ int cglbm_load_state(cglbm_handle *h, const void *src, void *stream);
  *     it); for layouts that admit 2 it also times the compact fused kernel
  *     and pull per geometry and keeps the fastest for schedule 2.
  * Selecting a schedule loads the fused geometry the autotuner chose for it
- * (or the one cglbm_set_variant set), synchronizing the null stream.
+ * (or the one cglbm_set_variant set); when that changes the geometry the
+ * call synchronizes the device first.
  * Returns CGLBM_EINVAL for other values. */
 int cglbm_set_schedule(cglbm_handle *h, int32_t schedule);
 

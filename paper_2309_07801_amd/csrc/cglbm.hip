@@ -1114,10 +1114,15 @@ int cglbm_set_schedule(cglbm_handle *h, int32_t schedule) {
                 "higher rates and no walls");
   if (schedule != h->schedule) drop_graphs(h);
   h->schedule = schedule;
-  // the fused geometry preferred by the schedule (the autotuner's choices)
+  // the fused geometry preferred by the schedule (the autotuner's choices);
+  // work still running on any stream may read the column tables, so the
+  // device is synchronized before they are replaced
   if (h->lattice == LATTICE_D3Q27) {
     const int32_t v = schedule == 2 ? h->fvar_compact : h->fvar_pop;
-    if (v != h->variant) return select_variant(h, v, nullptr);
+    if (v != h->variant) {
+      HIP_TRY(hipDeviceSynchronize());
+      return select_variant(h, v, nullptr);
+    }
   }
   return CGLBM_OK;
 }
