@@ -270,9 +270,10 @@ int cglbm_load_state(cglbm_handle *h, const void *src, void *stream);
  *     unit higher rates; CGLBM_EUNSUPPORTED otherwise.  The compact state
  *     lives in the population buffer that does not hold the state; solid
  *     wall nodes keep their (bounced) populations in two library-owned
- *     wall stashes allocated by cglbm_init.  cglbm_autotune chooses between 0 and 1 only (select 2 after
- *     it); for layouts that admit 2 it also times the compact fused kernel
- *     and pull per geometry and keeps the fastest for schedule 2.
+ *     wall stashes allocated by cglbm_init.  cglbm_autotune chooses
+ *     between 0 and 1 only (select 2 after it); for layouts that admit 2 it
+ *     also times the compact fused kernel and pull per geometry and keeps
+ *     the fastest for schedule 2.
  * Selecting a schedule loads the fused geometry the autotuner chose for it
  * (or the one cglbm_set_variant set); when that changes the geometry the
  * call synchronizes the device first.
@@ -304,7 +305,9 @@ int cglbm_set_graph(cglbm_handle *h, int32_t enable);
 /* Launch geometries of the fused kernel (all bitwise equivalent).
  * cglbm_num_variants: how many; cglbm_variant_info: info[0..3] = column
  * extent x, y, z chunk, minimum waves per SIMD; cglbm_set_variant selects one
- * (synchronizes the stream); cglbm_get_variant returns the current one. */
+ * for every schedule (synchronizes the stream); cglbm_get_variant returns
+ * the one loaded (the current schedule's: the autotuner keeps one for
+ * schedules 0 and 1 and one for schedule 2). */
 int cglbm_num_variants(void);
 int cglbm_variant_info(int32_t variant, int32_t *info);
 int cglbm_set_variant(cglbm_handle *h, int32_t variant, void *stream);
