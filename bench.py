@@ -322,8 +322,7 @@ def rti_form(W=128, T_list=(1.0, 2.0, 3.0, 4.0)):
         tu = np.sqrt(W / -w.box.gravity[2])
         sim = pkg.Simulation([pkg.box_params_of(w.box)], [w.rho_r], [w.rho_b], [w.u])
         sim.autotune(reps=2)
-        if model == 3:
-            sim.set_schedule(2)  # Model D with Q: the compact schedule (walls included)
+        sim.set_schedule(2)  # the compact schedule (walls, every equilibrium family)
         hist, done, t_run = [], 0, 0.0
         for T in T_list:
             n = int(round(T * tu))

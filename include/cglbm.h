@@ -266,8 +266,11 @@ int cglbm_load_state(cglbm_handle *h, const void *src, void *stream);
  *     diagnostics and checkpoints are those of schedule 0.  Results equal
  *     schedule 0 bit for bit for one step per call and to FP32 rounding
  *     otherwise (the moment sums run in another order).  Layouts: D3Q27,
- *     CGLBM_FP32 or CGLBM_FP32_PAIRS storage, two buffers, Model D with Q,
- *     unit higher rates; CGLBM_EUNSUPPORTED otherwise.  The compact state
+ *     CGLBM_FP32 or CGLBM_FP32_PAIRS storage, two buffers, unit higher
+ *     rates, any equilibrium family and Q switch (Model D with Q runs the
+ *     fused kernel; the others the interface and collide kernels, writing
+ *     compact states; one step per call then equals schedule 1 bit for
+ *     bit); CGLBM_EUNSUPPORTED otherwise.  The compact state
  *     lives in the population buffer that does not hold the state; solid
  *     wall nodes keep their (bounced) populations in two library-owned
  *     wall stashes allocated by cglbm_init.  cglbm_autotune chooses

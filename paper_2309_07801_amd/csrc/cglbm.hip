@@ -80,15 +80,17 @@ using CPullFn = void (*)(const BoxDev *, const int32_t *, const float *, float *
 using EmitFn = void (*)(const BoxDev *, const int32_t *, const float *, void *, int64_t);
 struct CPullVariant {
   int tx, ty, zc;
-  CPullFn fn;     // periodic boxes
-  CPullFn fw[2];  // solid layers present: wall stash in FP32 planes / FP32 pairs
+  // [general equilibrium family][0 periodic, 1 walls with FP32 planes, 2 walls with FP32 pairs]
+  CPullFn fn[2][3];
 };
-#define CV(TX, TY, ZC)                                                     \
-  {TX, TY, ZC, k_cpull<TX, TY, ZC>,                                        \
-   {k_cpull<TX, TY, ZC, true, StoreF32>, k_cpull<TX, TY, ZC, true, StoreF32P>}}
+#define CV_M(TX, TY, ZC, G)                                                              \
+  {k_cpull<TX, TY, ZC, false, StoreF32, G>, k_cpull<TX, TY, ZC, true, StoreF32, G>,      \
+   k_cpull<TX, TY, ZC, true, StoreF32P, G>}
+#define CV(TX, TY, ZC) {TX, TY, ZC, {CV_M(TX, TY, ZC, false), CV_M(TX, TY, ZC, true)}}
 const CPullVariant kCPullVariants[] = {CV(64, 8, 64), CV(64, 8, 32), CV(32, 8, 32), CV(64, 4, 32),
                                        CV(32, 8, 64)};
 #undef CV
+#undef CV_M
 constexpr int kNumCPull = (int)(sizeof(kCPullVariants) / sizeof(kCPullVariants[0]));
 
 // Tile shapes of the two-dimensional (D2Q9) step kernel, 256 threads each;
@@ -145,7 +147,11 @@ const CollideFn kCollide[5] = {k_collide<StoreF32>, k_collide<StoreF16>, k_colli
                                k_collide<StoreF32X>, k_collide<StoreF32P>};
 const InitFn kInit[5] = {k_init<StoreF32>, k_init<StoreF16>, k_init<StoreBF16>, k_init<StoreF32X>,
                          k_init<StoreF32P>};
-const EmitFn kEmit[2] = {k_emit<StoreF32>, k_emit<StoreF32P>};
+// [FP32 pairs][general equilibrium family]
+const EmitFn kEmit[2][2] = {{k_emit<StoreF32, false>, k_emit<StoreF32, true>},
+                            {k_emit<StoreF32P, false>, k_emit<StoreF32P, true>}};
+// the three-kernel schedule's collision writing compact states
+const CollideFn kCollideCompact = k_collide<StoreF32, true>;
 const WallCopyFn kWallCopy[5] = {k_wall_copy<StoreF32>, k_wall_copy<StoreF16>,
                                  k_wall_copy<StoreBF16>, k_wall_copy<StoreF32X>,
                                  k_wall_copy<StoreF32P>};
@@ -185,6 +191,7 @@ struct Layout {
   int32_t nblk = 0, ntile = 0, ncol = 0, nblk_pad = 0;
   bool walls = false;
   bool general = false;  // a box with Model A, B or C or without Q: three-kernel schedule
+  bool full_rates = false;  // a box with a higher-order rate other than 1
   int lattice = LATTICE_D3Q27;
 };
 
@@ -317,6 +324,7 @@ void build_layout(int32_t n_boxes, const cglbm_box_params *boxes, Layout &L,
       if (P.omega_hi[k] != 1.0) B.full_rates = 1;
     }
     if (P.model != CGLBM_MODEL_D || !P.q_correction || B.full_rates) L.general = true;
+    if (B.full_rates) L.full_rates = true;
     {
       // pure-phase rest equilibrium of each colour: w_i rho_k^0 (c_s^k)^2 / c_s^2,
       // by speed class |c_i|^2 (D3Q27 weights, or the D2Q9 ones of Eq. A2)
@@ -515,7 +523,8 @@ int launch_fused_compact(cglbm_handle *h, hipStream_t s) {
 // solid nodes go to the other one
 int launch_cpull(cglbm_handle *h, hipStream_t s, int rd = 0) {
   const CPullVariant &C = kCPullVariants[h->cvariant];
-  const CPullFn fn = h->L.walls ? C.fw[h->storage == CGLBM_FP32_PAIRS ? 1 : 0] : C.fn;
+  const int wk = h->L.walls ? (h->storage == CGLBM_FP32_PAIRS ? 2 : 1) : 0;
+  const CPullFn fn = C.fn[h->L.general ? 1 : 0][wk];
   hipLaunchKernelGGL(fn, dim3((unsigned)h->L.ccol_box.size()), dim3(C.tx * C.ty), 0, s,
                      h->d_boxes, h->d_ccol_box, (const float *)h->pop[1 - h->cur], h->aux,
                      h->L.total, (const void *)h->cstash[rd], h->cstash[1 - rd], h->L.wtotal);
@@ -523,9 +532,9 @@ int launch_cpull(cglbm_handle *h, hipStream_t s, int rd = 0) {
 }
 // wi: the wall stash the last step wrote (the solid nodes' stored values)
 int launch_emit(cglbm_handle *h, hipStream_t s, int wi = 0) {
-  hipLaunchKernelGGL(kEmit[h->storage == CGLBM_FP32_PAIRS ? 1 : 0], dim3(h->L.nblk_pad), dim3(kBlock),
-                     0, s, h->d_boxes, h->d_blk_box, (const float *)h->pop[1 - h->cur],
-                     h->pop[h->cur], h->L.total);
+  hipLaunchKernelGGL(kEmit[h->storage == CGLBM_FP32_PAIRS ? 1 : 0][h->L.general ? 1 : 0],
+                     dim3(h->L.nblk_pad), dim3(kBlock), 0, s, h->d_boxes, h->d_blk_box,
+                     (const float *)h->pop[1 - h->cur], h->pop[h->cur], h->L.total);
   if (h->L.walls && !h->L.wblk_box.empty())
     hipLaunchKernelGGL(kWallCopy[h->storage], dim3((unsigned)h->L.wblk_box.size()), dim3(kBlock),
                        0, s, h->d_boxes, h->d_wblk_box, (const void *)h->cstash[wi],
@@ -542,9 +551,9 @@ int launch_pull_compact(cglbm_handle *h, hipStream_t s) {
   return CGLBM_OK;
 }
 // Layouts the compact schedule serves: D3Q27, FP32 storage (either layout),
-// two buffers, Model D with Q and unit higher rates.
+// two buffers, unit higher rates.
 bool compact_ok(const cglbm_handle *h) {
-  return h->lattice == LATTICE_D3Q27 && !h->inplace && !h->L.general &&
+  return h->lattice == LATTICE_D3Q27 && !h->inplace && !h->L.full_rates &&
          (h->storage == CGLBM_FP32 || h->storage == CGLBM_FP32_PAIRS);
 }
 
@@ -631,6 +640,19 @@ int launch_collide(cglbm_handle *h, hipStream_t s) {
   return CGLBM_OK;
 }
 
+// The collision half of a compact step: the fused kernel for Model D with
+// Q; for the general families the interface kernel and the collision
+// writing compact states.
+int launch_compact_collide(cglbm_handle *h, hipStream_t s) {
+  if (!h->L.general) return launch_fused_compact(h, s);
+  int rc = launch_iface(h, s, 0);
+  if (rc) return rc;
+  hipLaunchKernelGGL(kCollideCompact, dim3(h->L.nblk_pad), dim3(kBlock), 0, s, h->d_boxes,
+                     h->d_blk_box, h->aux, (const void *)h->pop[h->cur], h->pop[1 - h->cur],
+                     h->L.total);
+  return CGLBM_OK;
+}
+
 template <class F>
 int timed(cglbm_handle *h, hipStream_t s, int kind, F &&launch) {
   if (h->prof && h->ev_used + 2 <= h->ev.size()) {
@@ -654,7 +676,10 @@ int check_launch() {
 // The fused kernel implements Model D with the correction term; layouts with
 // any other box run the three-kernel schedule, whose collision takes each
 // box's equilibrium family and correction switch.
-int effective_schedule(const cglbm_handle *h) { return h->L.general ? 1 : h->schedule; }
+int effective_schedule(const cglbm_handle *h) {
+  if (h->schedule == 2) return 2;  // set only where compact_ok holds
+  return h->L.general ? 1 : h->schedule;
+}
 
 // D2Q9: one launch of the step kernel (export != 0: the fields of the
 // stored state into aux, populations untouched).
@@ -696,7 +721,7 @@ int capture_compact_pair(cglbm_handle *h) {
   int rc = CGLBM_OK;
   for (int k = 0; k < 2 && !rc; ++k) {
     rc = launch_cpull(h, h->cap_stream, k);
-    if (!rc) rc = launch_fused_compact(h, h->cap_stream);
+    if (!rc) rc = launch_compact_collide(h, h->cap_stream);
   }
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
@@ -721,7 +746,7 @@ int step_compact(cglbm_handle *h, int32_t n, hipStream_t s) {
   // (the population pull) writes stash 0
   int wi = 0;
   int rc = timed(h, s, KIND_PULL, [&] { return launch_pull_compact(h, s); });
-  if (!rc) rc = timed(h, s, KIND_FUSED, [&] { return launch_fused_compact(h, s); });
+  if (!rc) rc = timed(h, s, KIND_FUSED, [&] { return launch_compact_collide(h, s); });
   int32_t k = 1;
   if (!rc && h->use_graph && !h->prof && n >= 3) {
     if (!h->graphc[h->cur]) rc = capture_compact_pair(h);
@@ -729,7 +754,7 @@ int step_compact(cglbm_handle *h, int32_t n, hipStream_t s) {
   }
   for (; k < n && !rc; ++k) {
     rc = timed(h, s, KIND_PULL, [&] { return launch_cpull(h, s, wi); });
-    if (!rc) rc = timed(h, s, KIND_FUSED, [&] { return launch_fused_compact(h, s); });
+    if (!rc) rc = timed(h, s, KIND_FUSED, [&] { return launch_compact_collide(h, s); });
     wi = 1 - wi;
   }
   if (!rc) rc = timed(h, s, KIND_COLLIDE, [&] { return launch_emit(h, s, wi); });
@@ -1110,8 +1135,8 @@ int cglbm_set_schedule(cglbm_handle *h, int32_t schedule) {
     return fail(CGLBM_EUNSUPPORTED, "D2Q9 steps have one schedule (0)");
   if (schedule == 2 && !compact_ok(h))
     return fail(CGLBM_EUNSUPPORTED,
-                "the compact schedule needs FP32 storage, two buffers, Model D with Q, unit "
-                "higher rates and no walls");
+                "the compact schedule needs D3Q27, FP32 storage, two buffers and unit "
+                "higher-order rates");
   if (schedule != h->schedule) drop_graphs(h);
   h->schedule = schedule;
   // the fused geometry preferred by the schedule (the autotuner's choices);
@@ -1218,7 +1243,7 @@ int cglbm_autotune(cglbm_handle *h, int32_t reps, double *ms_per_variant, void *
   // the compact schedule's fused kernel on the same inputs (it writes
   // compact states into the other buffer only): its own best geometry
   int cfbest = best;
-  if (!rc && compact_ok(h)) {
+  if (!rc && compact_ok(h) && !h->L.general) {
     double cf_ms = 1e300;
     for (int v = 0; v < kNumFused && !rc; ++v) {
       if ((rc = select_variant(h, v, s)) || (rc = launch_fused_compact(h, s))) break;
@@ -1264,7 +1289,7 @@ int cglbm_autotune(cglbm_handle *h, int32_t reps, double *ms_per_variant, void *
   // writes into the other buffer from the same pull, then each k_cpull
   // variant on it (both write only that buffer and aux)
   if (!rc && compact_ok(h) && !(rc = select_variant(h, cfbest, s)) &&
-      !(rc = launch_fused_compact(h, s))) {
+      !(rc = launch_compact_collide(h, s))) {
     int cbest = h->cvariant;
     double cbest_ms = 1e300;
     for (int v = 0; v < kNumCPull && !rc; ++v) {

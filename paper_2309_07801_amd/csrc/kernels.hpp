@@ -824,6 +824,9 @@ __device__ __forceinline__ void collide_node(const BoxDev &B, const NodeIn &in, 
 // ---------------------------------------------------------------------------
 constexpr int kCompact = 17;  // planes: rr rb ux uy uz Fx Fy Fz sxx syy szz sxy sxz syz nx ny nz
 
+// GENERAL: the box's equilibrium family and correction switch (as
+// collide_node<true>); the relaxed second moments have the same form.
+template <bool GENERAL = false>
 __device__ __forceinline__ void compact_of(const BoxDev &B, const NodeIn &in, float (&c)[kCompact]) {
   const float rho = in.rr + in.rb;
   const float irho = rcp(rho);
@@ -843,10 +846,12 @@ __device__ __forceinline__ void compact_of(const BoxDev &B, const NodeIn &in, fl
   const float kxz = in.pxz - ux * in.jz - uz * in.jx + rho * ux * uz;
   const float kyz = in.pyz - uy * in.jz - uz * in.jy + rho * uy * uz;
   const float r1 = 1.0f - w1, h1 = 1.0f - 0.5f * w1;
-  const float A = r1 * (kxx - kyy) + h1 * (in.Qx - in.Qy);
-  const float Bd = r1 * (kxx - kzz) + h1 * (in.Qx - in.Qz);
+  const bool use_q = !GENERAL || B.qcorr;
+  const float Qx = use_q ? in.Qx : 0.f, Qy = use_q ? in.Qy : 0.f, Qz = use_q ? in.Qz : 0.f;
+  const float A = r1 * (kxx - kyy) + h1 * (Qx - Qy);
+  const float Bd = r1 * (kxx - kzz) + h1 * (Qx - Qz);
   const float T = (1.0f - w2) * (kxx + kyy + kzz) + 3.0f * w2 * p +
-                  (1.0f - 0.5f * w2) * (in.Qx + in.Qy + in.Qz);
+                  (1.0f - 0.5f * w2) * (Qx + Qy + Qz);
   const float third = 1.0f / 3.0f;
   c[0] = in.rr;
   c[1] = in.rb;
@@ -873,13 +878,18 @@ struct CompactPost {
   float k[27];
   float ux, uy, uz, cr, cb, Rx, Ry, Rz;
 };
+template <bool GENERAL = false>
 __device__ __forceinline__ void compact_post(const BoxDev &B, const float (&c)[kCompact],
                                              CompactPost &o) {
   const float rr = c[0], rb = c[1];
   const float rho = rr + rb;
   const float irho = rcp(rho);
   const float p = rr * B.cs2r + rb * B.cs2b;
-  model_d_moments(rho, p, c[5], c[6], c[7], c[8], c[9], c[10], c[11], c[12], c[13], o.k);
+  if (GENERAL)
+    model_moments(B.model, rho, p, c[2], c[3], c[4], c[5], c[6], c[7], c[8], c[9], c[10], c[11],
+                  c[12], c[13], o.k);
+  else
+    model_d_moments(rho, p, c[5], c[6], c[7], c[8], c[9], c[10], c[11], c[12], c[13], o.k);
   o.ux = c[2];
   o.uy = c[3];
   o.uz = c[4];
@@ -1097,7 +1107,9 @@ struct PopWriter {
   }
 };
 
-template <class S>
+// COMPACT: store the compact post-collision state (17 float planes of dst,
+// see compact_of) instead of the populations; unit higher rates only.
+template <class S, bool COMPACT = false>
 __global__ __launch_bounds__(kBlock) void k_collide(const BoxDev *__restrict__ boxes,
                                                     const int32_t *__restrict__ blk_box,
                                                     float *__restrict__ aux,
@@ -1116,6 +1128,13 @@ __global__ __launch_bounds__(kBlock) void k_collide(const BoxDev *__restrict__ b
   if (is_solid(B, y, z)) return;
   const uint32_t node = (uint32_t)(B.base + local);
   const NodeIn in = load_node_in(aux, plane, node);
+  if (COMPACT) {
+    float c[kCompact];
+    compact_of<true>(B, in, c);
+#pragma unroll
+    for (int k = 0; k < kCompact; ++k) buf_st(c[k], plane_rsrc(dst_, plane * 4, k), node * 4u);
+    return;
+  }
   const Pops<S> dst(dst_, plane);
   PopWriter<S> w(dst, B, node);
   if (B.full_rates) {
@@ -1695,7 +1714,7 @@ struct CPullGeom {
   static constexpr int CP = (R1 + NT - 1) / NT;  // ring points per thread
 };
 
-template <int TX, int TY, int ZC, bool WALLS = false, class S = StoreF32>
+template <int TX, int TY, int ZC, bool WALLS = false, class S = StoreF32, bool GENERAL = false>
 __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ boxes,
                                                   const int32_t *__restrict__ ccol_box,
                                                   const float *__restrict__ cst,
@@ -1764,7 +1783,7 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
 #pragma unroll
       for (int m = 0; m < kCompact; ++m) c[m] = ldpl(cst, plane, m, zoff + roff[k]);
       CompactPost o;
-      compact_post(B, c, o);
+      compact_post<GENERAL>(B, c, o);
       float g[3][3][3];
 #pragma unroll
       for (int a = 0; a < 3; ++a)
@@ -1909,7 +1928,7 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
 // node's collided, recoloured populations (bit for bit those the fused
 // kernel would have stored), the state the next pull reads.
 // ---------------------------------------------------------------------------
-template <class S>
+template <class S, bool GENERAL = false>
 __global__ __launch_bounds__(kBlock) void k_emit(const BoxDev *__restrict__ boxes,
                                                  const int32_t *__restrict__ blk_box,
                                                  const float *__restrict__ cst,
@@ -1928,7 +1947,11 @@ __global__ __launch_bounds__(kBlock) void k_emit(const BoxDev *__restrict__ boxe
   const float irho = rcp(rho);
   const float p = c[0] * B.cs2r + c[1] * B.cs2b;
   float k[27];
-  model_d_moments(rho, p, c[5], c[6], c[7], c[8], c[9], c[10], c[11], c[12], c[13], k);
+  if (GENERAL)
+    model_moments(B.model, rho, p, c[2], c[3], c[4], c[5], c[6], c[7], c[8], c[9], c[10], c[11],
+                  c[12], c[13], k);
+  else
+    model_d_moments(rho, p, c[5], c[6], c[7], c[8], c[9], c[10], c[11], c[12], c[13], k);
   const Pops<S> dst(dst_, plane);
   PopWriter<S> w(dst, B, node);
   emit_recoloured(B, k, c[2], c[3], c[4], c[0], c[1], irho, p, c[14], c[15], c[16], w);

@@ -12,6 +12,9 @@ registers.  Checks:
   sums in another order), mass drift at FP32 rounding level;
 * boxes with solid walls (the wall stashes of the bounce-back): one step per
   call bitwise, many steps against the oracle;
+* the equilibrium families A, B, C and Model D without Q (the interface and
+  collide kernels writing compact states): one step per call bitwise equal
+  to the three-kernel schedule, many steps against the oracle;
 * layouts it does not serve are refused with CGLBM_EUNSUPPORTED."""
 import numpy as np
 import pytest
@@ -96,7 +99,7 @@ def test_compact_schedule_refuses_other_layouts():
     refused = [
         ([(b, f)], {"storage": 1}),
         ([(b, f)], {"inplace": True}),
-        ([(dataclasses.replace(b, model=0), f)], {}),
+        ([(dataclasses.replace(b, omega_hi=(1.0, 1.2) + (1.0,) * 7), f)], {}),
     ]
     for cases, kw in refused:
         sim = _sim(cases, **kw)
@@ -198,3 +201,43 @@ def test_walls_close_to_fused_over_many_steps():
         assert np.abs(out[0][name] - out[1][name]).max() <= 5e-5 * np.abs(out[0][name]).max(), name
     for name in ("ux", "uy", "uz"):
         assert np.abs(out[0][name] - out[1][name]).max() <= 5e-4 * 0.04, name
+
+
+def _general_cases():
+    import dataclasses
+    out = []
+    for k, (model, use_q) in enumerate(((0, 1), (1, 1), (2, 1), (3, 0))):
+        b, f = _case((17 + 2 * k, 13, 11), R=3.0, u=(0.03, 0.0, 0.01), walls=k % 2)
+        out.append((dataclasses.replace(b, model=model, use_q=use_q), f))
+    return out
+
+
+def test_general_models_single_step_calls_equal_three_kernel_schedule():
+    cases = _general_cases()
+    out = []
+    for sched in (1, 2):
+        sim = _sim(cases)
+        sim.set_schedule(sched)
+        assert sim.schedule() == sched
+        for _ in range(4):
+            sim.step(1)
+        out.append([gpu_fields(sim, k) for k in range(len(cases))])
+        sim.close()
+    for a, b in zip(out[0], out[1]):
+        for name in a:
+            assert np.array_equal(a[name], b[name]), name
+
+
+def test_general_models_parity_with_oracle():
+    """Models A, B, C with Q and Model D without Q in one batch (two of the
+    boxes walled), 50 steps in one call, against the oracle."""
+    cases = _general_cases()
+    sim = _sim(cases)
+    sim.set_schedule(2)
+    sim.step(50)
+    for k, (box, fl) in enumerate(cases):
+        o = run_oracle(box, *fl, 50, seed=4, noise=1e-6, box_index=k)[0]
+        e = errors(gpu_fields(sim, k), o, box, 0.03)
+        print(k, box.model, box.use_q, e)
+        assert e["rho"] < 1e-5 and e["u"] < 1e-4 and e["phi"] < 1e-4, (k, e)
+    sim.close()
