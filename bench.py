@@ -428,7 +428,7 @@ def main():
     geo = (var["tx"], var["ty"], var["zc"], var["min_waves"])
     if compact:
         cv = main_r["compact_variant"]
-        kname = {"pull": "k_cpull<%d, %d, %d, false, f32>" % (cv["tx"], cv["ty"], cv["zc"]),
+        kname = {"pull": "k_cpull<%d, %d, %d, false, f32, false>" % (cv["tx"], cv["ty"], cv["zc"]),
                  "fused": "k_fused<%d, %d, %d, %d, false, f32, false, true>" % geo}[dom]
         kb = COMPACT_BYTES
     else:
