@@ -15,7 +15,9 @@
 
 #include "../../include/cglbm.h"
 #include "d2q9.hpp"
+#include "diag.hpp"
 #include "kernels.hpp"
+#include "tables.hpp"
 
 using namespace cglbm;
 
@@ -43,77 +45,10 @@ int fail(int code, const char *fmt, ...) {
 
 constexpr int kTX = 8, kTY = 8, kTZ = 8;   // interface tile (three-kernel schedule)
 
-// Launch geometries of the fused kernel: column extent in x and y, z chunk,
-// minimum waves per SIMD requested from the register allocator.  Every
-// variant performs the same arithmetic per node (results are bitwise equal);
-// cglbm_autotune picks the fastest for the boxes at hand.
-using FusedFn = void (*)(const BoxDev *, const int32_t *, float *, void *, int64_t);
-struct FusedVariant {
-  int tx, ty, zc, minw;
-  FusedFn fn[5][2];  // time step: [storage][any box with solid layers]
-  FusedFn fx[2];     // field export (no population store): [solid layers]
-  FusedFn fc[2];     // compact schedule: compact state out (FP32): [solid layers]
-};
-#define FV_S(TX, TY, ZC, MW, S) \
-  {k_fused<TX, TY, ZC, MW, false, S, false>, k_fused<TX, TY, ZC, MW, true, S, false>}
-#define FV(TX, TY, ZC, MW)                                                                    \
-  {TX, TY, ZC, MW,                                                                           \
-   {FV_S(TX, TY, ZC, MW, StoreF32), FV_S(TX, TY, ZC, MW, StoreF16), FV_S(TX, TY, ZC, MW, StoreBF16), \
-    FV_S(TX, TY, ZC, MW, StoreF32X), FV_S(TX, TY, ZC, MW, StoreF32P)},                       \
-   {k_fused<TX, TY, ZC, MW, false, StoreF32, true>, k_fused<TX, TY, ZC, MW, true, StoreF32, true>}, \
-   {k_fused<TX, TY, ZC, MW, false, StoreF32, false, true>,                                    \
-    k_fused<TX, TY, ZC, MW, true, StoreF32, false, true>}}
-const FusedVariant kFusedVariants[] = {
-    FV(32, 8, 32, 4),  FV(32, 8, 64, 4),  FV(32, 8, 16, 4), FV(32, 8, 32, 1),
-    FV(32, 16, 32, 4), FV(32, 16, 64, 4), FV(64, 4, 32, 4), FV(32, 4, 32, 4),
-    FV(32, 8, 32, 5),  FV(64, 8, 64, 4),  FV(64, 8, 32, 4),
-};
-#undef FV
-#undef FV_S
-constexpr int kNumFused = (int)(sizeof(kFusedVariants) / sizeof(kFusedVariants[0]));
-
-// The compact schedule's pull (column tile and z chunk, chosen by the
-// autotuner; equal results) and its conversion back to stored populations
-// (FP32 planes or FP32 pairs).
-using CPullFn = void (*)(const BoxDev *, const int32_t *, const float *, float *, int64_t,
-                         const void *, void *, int64_t);
 using EmitFn = void (*)(const BoxDev *, const int32_t *, const float *, void *, int64_t);
-struct CPullVariant {
-  int tx, ty, zc;
-  // [general equilibrium family][0 periodic, 1 walls with FP32 planes, 2 walls with FP32 pairs]
-  CPullFn fn[2][3];
-};
-#define CV_M(TX, TY, ZC, G)                                                              \
-  {k_cpull<TX, TY, ZC, false, StoreF32, G>, k_cpull<TX, TY, ZC, true, StoreF32, G>,      \
-   k_cpull<TX, TY, ZC, true, StoreF32P, G>}
-#define CV(TX, TY, ZC) {TX, TY, ZC, {CV_M(TX, TY, ZC, false), CV_M(TX, TY, ZC, true)}}
-const CPullVariant kCPullVariants[] = {CV(64, 8, 64), CV(64, 8, 32), CV(32, 8, 32), CV(64, 4, 32),
-                                       CV(32, 8, 64)};
-#undef CV
-#undef CV_M
-constexpr int kNumCPull = (int)(sizeof(kCPullVariants) / sizeof(kCPullVariants[0]));
-
-// Tile shapes of the two-dimensional (D2Q9) step kernel, 256 threads each;
-// bitwise equal results, picked by cglbm_autotune.  Kernels per storage slot
-// (storage2_slot): FP32 pairs (for FP32 and FP32_PAIRS), FP16, BF16, FP32X.
-using Step2Fn = void (*)(const BoxDev *, const int32_t *, const void *, void *, float *, int64_t);
-struct Variant2 {
-  int tx, ty;
-  Step2Fn step[4], fields[4];
-};
-#define V2_S(S, TX, TY) d2q9::k2_step<S, TX, TY, 256, false>
-#define V2_F(S, TX, TY) d2q9::k2_step<S, TX, TY, 256, true>
-#define V2(TX, TY)                                                                              \
-  {TX, TY,                                                                                      \
-   {V2_S(StoreF32P, TX, TY), V2_S(StoreF16, TX, TY), V2_S(StoreBF16, TX, TY),                   \
-    V2_S(StoreF32X, TX, TY)},                                                                   \
-   {V2_F(StoreF32P, TX, TY), V2_F(StoreF16, TX, TY), V2_F(StoreBF16, TX, TY),                   \
-    V2_F(StoreF32X, TX, TY)}}
-const Variant2 kVariants2[] = {V2(64, 16), V2(32, 32), V2(64, 8), V2(32, 16)};
-#undef V2
-#undef V2_S
-#undef V2_F
-constexpr int kNumV2 = (int)(sizeof(kVariants2) / sizeof(kVariants2[0]));
+constexpr int kNumFused = kNumFusedVariants;
+constexpr int kNumCPull = kNumCPullVariants;
+constexpr int kNumV2 = kNumVariants2;
 enum { LATTICE_D3Q27 = 0, LATTICE_D2Q9 = 1 };
 constexpr int64_t kAlign = 64;             // node alignment of each box's base
 // Limit of all boxes together: every plane of 8-byte values (with the plane
@@ -134,8 +69,6 @@ using WallCopyFn = void (*)(const BoxDev *, const int32_t *, const void *, void 
                             int64_t);
 using CollideFn = void (*)(const BoxDev *, const int32_t *, float *, const void *, void *,
                           int64_t);
-using InitFn = void (*)(const BoxDev *, const int32_t *, const float *, const float *,
-                        const float *, void *, int64_t, uint64_t, float);
 // [stash][storage]: the in-place layout's pull writes solid nodes to the stash
 const PullFn kPull[2][5] = {{k_pull<StoreF32, false>, k_pull<StoreF16, false>,
                              k_pull<StoreBF16, false>, k_pull<StoreF32X, false>,
@@ -155,8 +88,7 @@ const CollideFn kCollideCompact = k_collide<StoreF32, true>;
 const WallCopyFn kWallCopy[5] = {k_wall_copy<StoreF32>, k_wall_copy<StoreF16>,
                                  k_wall_copy<StoreBF16>, k_wall_copy<StoreF32X>,
                                  k_wall_copy<StoreF32P>};
-const InitFn kInit2[4] = {d2q9::k2_init<StoreF32P>, d2q9::k2_init<StoreF16>,
-                           d2q9::k2_init<StoreBF16>, d2q9::k2_init<StoreF32X>};
+
 // D2Q9 keeps FP32 in colour pairs in either FP32 format
 int storage2_slot(int32_t st) { return st == CGLBM_FP32_PAIRS ? 0 : st; }
 bool storage_exact(int32_t st) { return st != CGLBM_FP32 && st != CGLBM_FP32_PAIRS; }
@@ -364,7 +296,7 @@ void build_layout(int32_t n_boxes, const cglbm_box_params *boxes, Layout &L,
 
 // Column table of k_cpull variant v: fills the per-box ccol fields.
 void build_ccolumns(Layout &L, int v) {
-  const CPullVariant &C = kCPullVariants[v];
+  const CPullVariant &C = cpull_variant(v);
   L.ccol_box.clear();
   int32_t ccol = 0;
   for (size_t b = 0; b < L.boxes.size(); ++b) {
@@ -383,7 +315,7 @@ void build_ccolumns(Layout &L, int v) {
 
 // Column table of fused variant v: fills the per-box column fields.
 void build_columns(Layout &L, int v) {
-  const FusedVariant &F = kFusedVariants[v];
+  const FusedVariant &F = fused_variant(v);
   L.col_box.clear();
   int32_t col = 0;
   for (size_t b = 0; b < L.boxes.size(); ++b) {
@@ -405,7 +337,7 @@ void build_columns(Layout &L, int v) {
 // Tile table of the D2Q9 step kernel for variant v (kept in the column
 // table's place): per box tile0, tnx, tny, ftx.
 void build_tiles2(Layout &L, int v) {
-  const Variant2 &V = kVariants2[v];
+  const Variant2 &V = variant2(v);
   L.col_box.clear();
   int32_t tile = 0;
   for (size_t b = 0; b < L.boxes.size(); ++b) {
@@ -508,7 +440,7 @@ int launch_iface(cglbm_handle *h, hipStream_t s, int write_kappa) {
 // other population buffer; k_cpull turns it into the moments of the next
 // step; k_emit stores it as populations in the state buffer.
 int launch_fused_compact(cglbm_handle *h, hipStream_t s) {
-  const FusedVariant &F = kFusedVariants[h->variant];
+  const FusedVariant &F = fused_variant(h->variant);
   const BoxDev *boxes = h->d_boxes;
   const int32_t *cols = h->d_col_box;
   float *aux = h->aux;
@@ -522,7 +454,7 @@ int launch_fused_compact(cglbm_handle *h, hipStream_t s) {
 // rd: the wall stash this step's solid points emit from; the arrivals at
 // solid nodes go to the other one
 int launch_cpull(cglbm_handle *h, hipStream_t s, int rd = 0) {
-  const CPullVariant &C = kCPullVariants[h->cvariant];
+  const CPullVariant &C = cpull_variant(h->cvariant);
   const int wk = h->L.walls ? (h->storage == CGLBM_FP32_PAIRS ? 2 : 1) : 0;
   const CPullFn fn = C.fn[h->L.general ? 1 : 0][wk];
   hipLaunchKernelGGL(fn, dim3((unsigned)h->L.ccol_box.size()), dim3(C.tx * C.ty), 0, s,
@@ -558,7 +490,7 @@ bool compact_ok(const cglbm_handle *h) {
 }
 
 int launch_fused(cglbm_handle *h, hipStream_t s, int export_fields) {
-  const FusedVariant &F = kFusedVariants[h->variant];
+  const FusedVariant &F = fused_variant(h->variant);
   const BoxDev *boxes = h->d_boxes;
   const int32_t *cols = h->d_col_box;
   float *aux = h->aux;
@@ -684,7 +616,7 @@ int effective_schedule(const cglbm_handle *h) {
 // D2Q9: one launch of the step kernel (export != 0: the fields of the
 // stored state into aux, populations untouched).
 int launch_step2(cglbm_handle *h, hipStream_t s, int export_fields) {
-  const Variant2 &V = kVariants2[h->variant];
+  const Variant2 &V = variant2(h->variant);
   const int slot = storage2_slot(h->storage);
   hipLaunchKernelGGL(export_fields ? V.fields[slot] : V.step[slot], dim3(h->L.ncol), dim3(256), 0,
                      s, h->d_boxes, h->d_col_box, (const void *)h->pop[h->cur],
@@ -1159,18 +1091,18 @@ int cglbm_num_variants(void) { return kNumFused; }
 int cglbm_variant_info(int32_t v, int32_t *info) {
   g_err.clear();
   if (v < 0 || v >= kNumFused || !info) return fail(CGLBM_EINVAL, "bad variant %d", v);
-  info[0] = kFusedVariants[v].tx;
-  info[1] = kFusedVariants[v].ty;
-  info[2] = kFusedVariants[v].zc;
-  info[3] = kFusedVariants[v].minw;
+  info[0] = fused_variant(v).tx;
+  info[1] = fused_variant(v).ty;
+  info[2] = fused_variant(v).zc;
+  info[3] = fused_variant(v).minw;
   return CGLBM_OK;
 }
 
 int cglbm_variant_info_d2q9(int32_t v, int32_t *info) {
   g_err.clear();
   if (v < 0 || v >= kNumV2 || !info) return fail(CGLBM_EINVAL, "bad D2Q9 variant %d", v);
-  info[0] = kVariants2[v].tx;
-  info[1] = kVariants2[v].ty;
+  info[0] = variant2(v).tx;
+  info[1] = variant2(v).ty;
   return CGLBM_OK;
 }
 
@@ -1195,7 +1127,7 @@ int cglbm_set_compact_variant(cglbm_handle *h, int32_t v, void *stream) {
 int cglbm_compact_variant(const cglbm_handle *h, int32_t *info) {
   if (!h) return -1;
   if (info) {
-    const CPullVariant &C = kCPullVariants[h->cvariant];
+    const CPullVariant &C = cpull_variant(h->cvariant);
     info[0] = C.tx;
     info[1] = C.ty;
     info[2] = C.zc;
