@@ -121,6 +121,8 @@ def lib():
                                       C.POINTER(C.c_int32), C.POINTER(C.c_int32), dp]
         L.orc_step.argtypes = [P, dp, C.c_int32]
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_num_threads.argtypes = [C.c_int32]
+        L.orc_set_num_threads.restype = None
         for fn in ("orc_gradient", "orc_fields", "orc_init", "orc_init_window", "orc_step"):
             getattr(L, fn).restype = C.c_int
         _lib = L
@@ -293,3 +295,8 @@ def step(P: Params, f: np.ndarray, nsteps: int = 1) -> np.ndarray:
 def num_threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on."""
+    lib().orc_set_num_threads(int(n))

@@ -447,6 +447,11 @@ double orc_noise(uint64_t seed, int32_t box, int64_t node, int32_t i, double amp
 
 int orc_num_threads(void) { return omp_get_max_threads(); }
 
+/* Threads of the parallel loops from now on (n >= 1). */
+void orc_set_num_threads(int32_t n) {
+  if (n >= 1) omp_set_num_threads(n);
+}
+
 int orc_is_solid(const orc_params *P, int32_t x, int32_t y, int32_t z) {
   (void)x;
   if ((P->walls & 1u) && (y == 0 || y == P->ny - 1)) return 1;

@@ -76,6 +76,7 @@ int orc_init_window(const orc_params *P, const double *rho_r, const double *rho_
 int orc_step(const orc_params *P, double *f, int32_t nsteps);
 int orc_is_solid(const orc_params *P, int32_t x, int32_t y, int32_t z);
 int orc_num_threads(void);
+void orc_set_num_threads(int32_t n);
 
 #ifdef __cplusplus
 }
