@@ -116,17 +116,38 @@ typedef struct {
  *                     colour k, rounded to half); rest populations in FP64.
  *   CGLBM_BF16_SHIFT  the same with bfloat16.
  *   CGLBM_FP32_EXACT  moving directions in float, rest populations in FP64.
- * FP16_SHIFT, BF16_SHIFT and FP32_EXACT store colour pairs as well and carry
- * the colour densities in FP64 from the pull to
+ *   CGLBM_FP16_CSHIFT as CGLBM_FP16_SHIFT, with each moving population stored
+ *                     as f^k_i - c_k s^k_i: the shift scaled by the colour
+ *                     fraction c_k = rho_k / rho of the node that wrote it
+ *                     (red c_r, blue 1 - c_r; s^k_i unrounded), which is
+ *                     stored per node as one more 16-bit plane (c_r in half,
+ *                     correctly rounded from rho_r / rho: 1 and 0 exactly in
+ *                     the pure phases).  A pull decodes each population with
+ *                     the fraction of its source node x - c_i.  Pure phases
+ *                     store deviations from equilibrium and the opposite
+ *                     colour exact zeros, as with the constant shift; at the
+ *                     interface each colour stores its deviation from its
+ *                     share of the equilibrium instead of a remainder of the
+ *                     order of s (the colour-scaled reading of the "shifted
+ *                     by their lattice weights" storage of Sec. II).  Solid
+ *                     wall nodes re-encode the populations they reverse with
+ *                     the fraction of their wall-normal fluid neighbour.
+ *                     D3Q27 only.
+ *   CGLBM_BF16_CSHIFT the same with bfloat16 (the fraction in bfloat16).
+ * FP16_SHIFT, BF16_SHIFT, FP32_EXACT and the two CSHIFT formats store colour
+ * pairs as well and carry the colour densities in FP64 from the pull to
  * the collision and set each rest population so that the node's colour mass
  * equals the FP64 sum of what the next step reads back: per-colour mass is
- * conserved to FP64 rounding. */
+ * conserved to FP64 rounding (for the CSHIFT formats in boxes without walls:
+ * the re-encoding at solid nodes rounds the reversed populations once more). */
 typedef enum {
   CGLBM_FP32 = 0,
   CGLBM_FP16_SHIFT = 1,
   CGLBM_BF16_SHIFT = 2,
   CGLBM_FP32_EXACT = 3,
-  CGLBM_FP32_PAIRS = 4
+  CGLBM_FP32_PAIRS = 4,
+  CGLBM_FP16_CSHIFT = 5,
+  CGLBM_BF16_CSHIFT = 6
 } cglbm_storage;
 
 typedef struct cglbm_handle cglbm_handle;
@@ -213,19 +234,27 @@ int cglbm_step(cglbm_handle *h, int32_t n_steps, void *stream);
 int cglbm_moments(cglbm_handle *h, int32_t box, uint32_t field_mask, float *out_dev,
                   void *stream);
 
-/* Per-box diagnostics in FP64, deterministic (fixed summation order that
- * depends only on the box).  centre: per box 3 doubles (droplet centre used
- * for the Laplace measurement and the periodic centroid) or NULL (box
- * centre).  out: per box CGLBM_NDIAG doubles:
+/* Per-box diagnostics in FP64, deterministic (a fixed summation order that
+ * depends only on the box: never on the launch geometry, the other boxes of
+ * the handle or the schedule).  Definitions follow Sec. IV.A (Laplace's law,
+ * Eq. 68 in its three-dimensional form 2 sigma / R) and Eqs. 10-14.
+ * centre: host array of 3 doubles per box (droplet centre used for the
+ * Laplace measurement and the periodic centroid) or NULL (box centre).
+ * out: per box CGLBM_NDIAG doubles:
  *   0 M_r, 1 M_b (sums of rho_k over fluid nodes), 2-4 momentum sum rho*u,
  *   5 p_in (mean p where |x-c| < R_eff-3), 6 p_out (mean p where
  *   |x-c| > R_eff+5, periodic distance), 7 R_eff = (3V/4pi)^(1/3) with
  *   V = sum (1+phi)/2, 8-10 red centroid relative to c, 11 kinetic energy
  *   sum rho u^2/2, 12 count of fluid nodes whose pulled local moments
  *   (densities, momentum, second moments) are not all finite.
- * out_is_host != 0: out is host memory and the call synchronizes the stream;
- * returns CGLBM_EUNSTABLE if any count of non-finite values is nonzero.
- * Otherwise out is device memory and the call is asynchronous. */
+ * out_is_host != 0: out is host memory; the call synchronizes the stream and
+ *   returns CGLBM_EUNSTABLE if any box's count of non-finite values is
+ *   nonzero (out is filled either way).
+ * out_is_host == 0: out is device memory of n_boxes * CGLBM_NDIAG doubles;
+ *   the call only enqueues work on the stream (no host synchronization), so
+ *   it cannot inspect the result: the caller reads the non-finite count
+ *   from out[13 b + 12].
+ * The library's reduction buffers are allocated by cglbm_init. */
 #define CGLBM_NDIAG 13
 int cglbm_reduce(cglbm_handle *h, const double *centre, double *out, int32_t out_is_host,
                  void *stream);
@@ -331,9 +360,12 @@ int cglbm_autotune(cglbm_handle *h, int32_t reps, double *ms_per_variant, void *
 /* Per-kernel timing with HIP events recorded on the caller's stream around
  * every launch of the step.  begin: reserve room for max_launches launches;
  * end: synchronize the events and return, per kernel kind
- * (0 pull/moments, 1 interface, 2 collide, 3 fused interface+collide), the
- * total milliseconds and the number of launches timed.  Kinds beyond
- * n_kinds are not reported. */
+ * (0 pull/moments: k_pull, or k_cpull in the compact schedule; 1 interface;
+ * 2 collide; 3 fused interface+collide, the compact fused kernel in the
+ * compact schedule; 4 the population pull that starts a compact call; 5 the
+ * emission of populations that ends a compact call), the total milliseconds
+ * and the number of launches timed.  Kinds beyond n_kinds are not
+ * reported. */
 int cglbm_profile_begin(cglbm_handle *h, int32_t max_launches);
 int cglbm_profile_end(cglbm_handle *h, double *total_ms, int64_t *launches, int32_t n_kinds);
 

@@ -23,15 +23,16 @@ LIB_PATH = os.path.join(_HERE, "libcglbm.so")
 CGLBM_OK = 0
 ERRORS = {-1: "CGLBM_EINVAL", -2: "CGLBM_EHIP", -3: "CGLBM_EUNSUPPORTED",
           -4: "CGLBM_EUNSTABLE", -5: "CGLBM_ESTATE"}
-FP32, FP16_SHIFT, BF16_SHIFT, FP32_EXACT, FP32_PAIRS = 0, 1, 2, 3, 4
+FP32, FP16_SHIFT, BF16_SHIFT, FP32_EXACT, FP32_PAIRS, FP16_CSHIFT, BF16_CSHIFT = range(7)
 STORAGE_NAMES = {FP32: "fp32", FP16_SHIFT: "fp16_shift", BF16_SHIFT: "bf16_shift",
-                 FP32_EXACT: "fp32_exact", FP32_PAIRS: "fp32_pairs"}
+                 FP32_EXACT: "fp32_exact", FP32_PAIRS: "fp32_pairs", FP16_CSHIFT: "fp16_cshift",
+                 BF16_CSHIFT: "bf16_cshift"}
 NDIAG = 13
 DIAG_NAMES = ("M_r", "M_b", "Px", "Py", "Pz", "p_in", "p_out", "R_eff", "cx", "cy", "cz",
               "KE", "n_nonfinite")
 FIELDS = ("rho_r", "rho_b", "phi", "p", "ux", "uy", "uz", "nx", "ny", "nz", "kappa",
           "Fx", "Fy", "Fz", "Qx", "Qy", "Qz")
-KERNEL_KINDS = ("pull", "interface", "collide", "fused")
+KERNEL_KINDS = ("pull", "interface", "collide", "fused", "pull_first", "emit")
 
 EXPORTED = ("cglbm_query_sizes", "cglbm_init", "cglbm_step", "cglbm_moments", "cglbm_reduce",
             "cglbm_box_offset", "cglbm_set_schedule", "cglbm_get_schedule", "cglbm_set_graph",
@@ -314,6 +315,19 @@ class Simulation:
         if rc not in (CGLBM_OK, -4):
             _check(rc)
         self.last_reduce_unstable = (rc == -4)
+        return out
+
+    def reduce_device(self, centres: Optional[Sequence[Sequence[float]]] = None):
+        """The diagnostics of reduce() into a new device tensor of shape
+        (n_boxes, NDIAG), float64, enqueued on the simulation's stream with no
+        host synchronization; column 12 holds the non-finite counts."""
+        import torch
+        out = torch.empty((self.nboxes, NDIAG), dtype=torch.float64, device=self.device)
+        cptr = None
+        if centres is not None:
+            c = np.ascontiguousarray(np.asarray(centres, np.float64).reshape(self.nboxes, 3))
+            cptr = c.ctypes.data_as(C.POINTER(C.c_double))
+        _check(lib().cglbm_reduce(self.h, cptr, out.data_ptr(), 0, _stream_ptr(self.stream)))
         return out
 
     def profile_begin(self, max_launches: int):

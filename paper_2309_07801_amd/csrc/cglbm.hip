@@ -58,7 +58,19 @@ constexpr int64_t kMaxNodes = (1ll << 29) - (1ll << 20);
 constexpr double kXi = 9.0 / 19.0;   // D3Q27 (Sec. II.A)
 constexpr double kXi2 = 3.0 / 5.0;   // D2Q9: the rest fractions of Eq. (8) sum to one
 
-enum { KIND_PULL = 0, KIND_IFACE = 1, KIND_COLLIDE = 2, KIND_FUSED = 3, KIND_N = 4 };
+// Kinds of timed launches: the pull of a step (k_pull, or k_cpull in the
+// compact schedule), the interface and collide kernels of the three-kernel
+// schedule, the fused kernel (the compact fused kernel in schedule 2), and
+// the population pull that starts and the emission that ends a compact call.
+enum {
+  KIND_PULL = 0,
+  KIND_IFACE = 1,
+  KIND_COLLIDE = 2,
+  KIND_FUSED = 3,
+  KIND_PULL_FIRST = 4,
+  KIND_EMIT = 5,
+  KIND_N = 6
+};
 
 int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
@@ -70,29 +82,40 @@ using WallCopyFn = void (*)(const BoxDev *, const int32_t *, const void *, void 
 using CollideFn = void (*)(const BoxDev *, const int32_t *, float *, const void *, void *,
                           int64_t);
 // [stash][storage]: the in-place layout's pull writes solid nodes to the stash
-const PullFn kPull[2][5] = {{k_pull<StoreF32, false>, k_pull<StoreF16, false>,
+const PullFn kPull[2][7] = {{k_pull<StoreF32, false>, k_pull<StoreF16, false>,
                              k_pull<StoreBF16, false>, k_pull<StoreF32X, false>,
-                             k_pull<StoreF32P, false>},
+                             k_pull<StoreF32P, false>, k_pull<StoreF16C, false>,
+                             k_pull<StoreBF16C, false>},
                             {k_pull<StoreF32, true>, k_pull<StoreF16, true>,
                              k_pull<StoreBF16, true>, k_pull<StoreF32X, true>,
-                             k_pull<StoreF32P, true>}};
-const CollideFn kCollide[5] = {k_collide<StoreF32>, k_collide<StoreF16>, k_collide<StoreBF16>,
-                               k_collide<StoreF32X>, k_collide<StoreF32P>};
-const InitFn kInit[5] = {k_init<StoreF32>, k_init<StoreF16>, k_init<StoreBF16>, k_init<StoreF32X>,
-                         k_init<StoreF32P>};
+                             k_pull<StoreF32P, true>, k_pull<StoreF16C, true>,
+                             k_pull<StoreBF16C, true>}};
+const CollideFn kCollide[7] = {k_collide<StoreF32>,  k_collide<StoreF16>,  k_collide<StoreBF16>,
+                               k_collide<StoreF32X>, k_collide<StoreF32P>, k_collide<StoreF16C>,
+                               k_collide<StoreBF16C>};
+const InitFn kInit[7] = {k_init<StoreF32>,  k_init<StoreF16>,  k_init<StoreBF16>, k_init<StoreF32X>,
+                         k_init<StoreF32P>, k_init<StoreF16C>, k_init<StoreBF16C>};
 // [FP32 pairs][general equilibrium family]
 const EmitFn kEmit[2][2] = {{k_emit<StoreF32, false>, k_emit<StoreF32, true>},
                             {k_emit<StoreF32P, false>, k_emit<StoreF32P, true>}};
 // the three-kernel schedule's collision writing compact states
 const CollideFn kCollideCompact = k_collide<StoreF32, true>;
-const WallCopyFn kWallCopy[5] = {k_wall_copy<StoreF32>, k_wall_copy<StoreF16>,
+const WallCopyFn kWallCopy[7] = {k_wall_copy<StoreF32>,  k_wall_copy<StoreF16>,
                                  k_wall_copy<StoreBF16>, k_wall_copy<StoreF32X>,
-                                 k_wall_copy<StoreF32P>};
+                                 k_wall_copy<StoreF32P>, k_wall_copy<StoreF16C>,
+                                 k_wall_copy<StoreBF16C>};
 
 // D2Q9 keeps FP32 in colour pairs in either FP32 format
 int storage2_slot(int32_t st) { return st == CGLBM_FP32_PAIRS ? 0 : st; }
 bool storage_exact(int32_t st) { return st != CGLBM_FP32 && st != CGLBM_FP32_PAIRS; }
-size_t storage_bytes(int32_t st) { return (st == CGLBM_FP16_SHIFT || st == CGLBM_BF16_SHIFT) ? 2 : 4; }
+size_t storage_bytes(int32_t st) {
+  return (st == CGLBM_FP16_SHIFT || st == CGLBM_BF16_SHIFT || st == CGLBM_FP16_CSHIFT ||
+          st == CGLBM_BF16_CSHIFT)
+             ? 2
+             : 4;
+}
+// the colour-fraction-shifted formats keep one 16-bit fraction per node
+bool storage_cshift(int32_t st) { return st == CGLBM_FP16_CSHIFT || st == CGLBM_BF16_CSHIFT; }
 
 // Bytes of one population buffer and of the aux buffer for `total` nodes.
 void buffer_sizes(int32_t st, int64_t total, size_t *pop, size_t *aux, int lattice = LATTICE_D3Q27) {
@@ -107,7 +130,8 @@ void buffer_sizes(int32_t st, int64_t total, size_t *pop, size_t *aux, int latti
     return;
   }
   if (storage_exact(st))
-    *pop = (size_t)align256(52 * total * (int64_t)storage_bytes(st)) + (size_t)(2 * total * 8);
+    *pop = (size_t)align256(52 * total * (int64_t)storage_bytes(st)) + (size_t)(2 * total * 8) +
+           (storage_cshift(st) ? (size_t)(2 * total) : 0);
   else
     *pop = (size_t)(54 * total * 4);
   *aux = (size_t)align256((int64_t)A_COUNT * total * 4) + (storage_exact(st) ? (size_t)(2 * total * 8) : 0);
@@ -118,6 +142,7 @@ struct Layout {
   std::vector<int32_t> blk_box, tile_box, col_box;
   std::vector<int32_t> wblk_box;  // k_wall_copy blocks (in-place layouts with walls)
   std::vector<int32_t> ccol_box;  // k_cpull column blocks (padded to a multiple of 8)
+  std::vector<int32_t> rch_box;   // reduction chunks (kRedChunk nodes of one box each)
   int64_t wtotal = 0;             // wall-node slots of all boxes (stash plane length)
   int64_t total = 0;  // plane length (nodes, all boxes, aligned)
   int32_t nblk = 0, ntile = 0, ncol = 0, nblk_pad = 0;
@@ -129,7 +154,7 @@ struct Layout {
 
 int validate(int32_t n_boxes, const cglbm_box_params *boxes, int32_t storage) {
   if (n_boxes <= 0 || !boxes) return fail(CGLBM_EINVAL, "n_boxes must be > 0 and boxes non-NULL");
-  if (storage < CGLBM_FP32 || storage > CGLBM_FP32_PAIRS)
+  if (storage < CGLBM_FP32 || storage > CGLBM_BF16_CSHIFT)
     return fail(CGLBM_EINVAL, "unknown storage format %d", storage);
   int64_t total = 0;
   for (int b = 0; b < n_boxes; ++b) {
@@ -186,6 +211,8 @@ int validate_d2q9(int32_t n_boxes, const cglbm_box_params *boxes, int32_t storag
   for (int b = 0; b < n_boxes; ++b) {
     const cglbm_box_params &P = boxes[b];
     if (P.nz != 1) return fail(CGLBM_EINVAL, "box %d: a D2Q9 box has nz = 1", b);
+    if (storage_cshift(storage))
+      return fail(CGLBM_EUNSUPPORTED, "the colour-fraction-shifted formats are built for D3Q27 only");
     if (P.walls & 2u) return fail(CGLBM_EINVAL, "box %d: a D2Q9 box has no z walls", b);
     if (P.model != CGLBM_MODEL_D)
       return fail(CGLBM_EUNSUPPORTED, "box %d: D2Q9 implements the equilibrium of Eq. (A10) only", b);
@@ -220,6 +247,8 @@ void build_layout(int32_t n_boxes, const cglbm_box_params *boxes, Layout &L,
     const int32_t nb = (int32_t)((B.n + kBlock - 1) / kBlock);
     for (int32_t k = 0; k < nb; ++k) L.blk_box.push_back(b);
     blk += nb;
+    B.rch0 = (int32_t)L.rch_box.size();
+    for (int64_t k = 0; k < (B.n + kRedChunk - 1) / kRedChunk; ++k) L.rch_box.push_back(b);
     B.tile0 = tile;
     B.tnx = (P.nx + kTX - 1) / kTX;
     B.tny = (P.ny + kTY - 1) / kTY;
@@ -395,9 +424,11 @@ struct cglbm_handle {
   int32_t fvar_pop = 0;        // fused geometry for schedules 0 and 1
   int32_t fvar_compact = 0;    // fused geometry for schedule 2
   size_t col_cap = 0;          // capacity of d_col_box (entries)
-  double *d_part = nullptr;    // block partials of the reduction
+  int32_t *d_rch_box = nullptr;  // reduction chunk -> box
+  double *d_part = nullptr;    // chunk partials of the reduction (kNPart doubles each)
   double *d_diag = nullptr;    // per box kNPart doubles
   double *d_centre = nullptr;  // per box 3 doubles
+  double *d_out = nullptr;     // per box CGLBM_NDIAG doubles (host-output reduce)
   // time steps as a captured graph: two steps from each buffer parity
   int32_t use_graph = 1;
   hipStream_t cap_stream = nullptr;
@@ -677,7 +708,7 @@ int step_compact(cglbm_handle *h, int32_t n, hipStream_t s) {
   // stash wi, its arrivals at solid nodes go to 1 - wi; the first step
   // (the population pull) writes stash 0
   int wi = 0;
-  int rc = timed(h, s, KIND_PULL, [&] { return launch_pull_compact(h, s); });
+  int rc = timed(h, s, KIND_PULL_FIRST, [&] { return launch_pull_compact(h, s); });
   if (!rc) rc = timed(h, s, KIND_FUSED, [&] { return launch_compact_collide(h, s); });
   int32_t k = 1;
   if (!rc && h->use_graph && !h->prof && n >= 3) {
@@ -689,7 +720,7 @@ int step_compact(cglbm_handle *h, int32_t n, hipStream_t s) {
     if (!rc) rc = timed(h, s, KIND_FUSED, [&] { return launch_compact_collide(h, s); });
     wi = 1 - wi;
   }
-  if (!rc) rc = timed(h, s, KIND_COLLIDE, [&] { return launch_emit(h, s, wi); });
+  if (!rc) rc = timed(h, s, KIND_EMIT, [&] { return launch_emit(h, s, wi); });
   if (!rc) rc = check_launch();
   return rc;
 }
@@ -731,6 +762,31 @@ int compute_fields(cglbm_handle *h, hipStream_t s, int write_kappa) {
   else
     rc = launch_iface(h, s, write_kappa);
   if (rc) return rc;
+  return check_launch();
+}
+
+// The diagnostics of the current state: local moments and interface fields
+// into aux, then the two chunked passes and the per-box finals (launches
+// only).  centre: device array of 3 doubles per box, or NULL for the box
+// centres; part: room for one partial per reduction chunk; diag: kNPart
+// doubles per box; out: the packed CGLBM_NDIAG doubles per box, device.
+int reduce_launch(cglbm_handle *h, hipStream_t s, const double *centre, double *part,
+                  double *diag, double *out) {
+  int rc = compute_fields(h, s, 0);
+  if (rc) return rc;
+  const double *rho64 =
+      storage_exact(h->storage)
+          ? (const double *)((const char *)h->aux + align256((int64_t)A_COUNT * h->L.total * 4))
+          : nullptr;
+  const unsigned nch = (unsigned)h->L.rch_box.size();
+  hipLaunchKernelGGL(k_reduce1, dim3(nch), dim3(kBlock), 0, s, h->d_boxes, h->d_rch_box, h->aux,
+                     h->L.total, rho64, centre, part);
+  hipLaunchKernelGGL(k_reduce_final, dim3(h->n_boxes), dim3(kBlock), 0, s, h->d_boxes,
+                     (const double *)part, 1, diag, (double *)nullptr);
+  hipLaunchKernelGGL(k_reduce2, dim3(nch), dim3(kBlock), 0, s, h->d_boxes, h->d_rch_box, h->aux,
+                     h->L.total, centre, (const double *)diag, part);
+  hipLaunchKernelGGL(k_reduce_final, dim3(h->n_boxes), dim3(kBlock), 0, s, h->d_boxes,
+                     (const double *)part, 2, diag, out);
   return check_launch();
 }
 
@@ -912,9 +968,14 @@ int init_handle(int lattice, cglbm_handle **out, int32_t n_boxes, const cglbm_bo
       (e = hipMalloc(&h->d_boxes, sizeof(BoxDev) * n_boxes)) != hipSuccess ||
       (e = hipMalloc(&h->d_blk_box, sizeof(int32_t) * h->L.blk_box.size())) != hipSuccess ||
       (e = hipMalloc(&h->d_tile_box, sizeof(int32_t) * h->L.tile_box.size())) != hipSuccess ||
-      (e = hipMalloc(&h->d_part, sizeof(double) * kNPart * (size_t)h->L.nblk)) != hipSuccess ||
+      (e = hipMalloc(&h->d_rch_box, sizeof(int32_t) * h->L.rch_box.size())) != hipSuccess ||
+      (e = hipMalloc(&h->d_part, sizeof(double) * kNPart * h->L.rch_box.size())) != hipSuccess ||
       (e = hipMalloc(&h->d_diag, sizeof(double) * kNPart * (size_t)n_boxes)) != hipSuccess ||
       (e = hipMalloc(&h->d_centre, sizeof(double) * 3 * (size_t)n_boxes)) != hipSuccess ||
+      (e = hipMalloc(&h->d_out, sizeof(double) * CGLBM_NDIAG * (size_t)n_boxes)) != hipSuccess ||
+      (e = hipMemcpyAsync(h->d_rch_box, h->L.rch_box.data(),
+                          sizeof(int32_t) * h->L.rch_box.size(), hipMemcpyHostToDevice, s)) !=
+          hipSuccess ||
       (e = hipMalloc(&h->d_ccol_box, sizeof(int32_t) * h->L.ccol_box.size())) != hipSuccess ||
       (e = hipMemcpyAsync(h->d_ccol_box, h->L.ccol_box.data(),
                           sizeof(int32_t) * h->L.ccol_box.size(), hipMemcpyHostToDevice, s)) !=
@@ -1015,47 +1076,22 @@ int cglbm_reduce(cglbm_handle *h, const double *centre, double *out, int32_t out
   if (!h) return fail(CGLBM_ESTATE, "null handle");
   if (!out) return fail(CGLBM_EINVAL, "out must not be NULL");
   hipStream_t s = (hipStream_t)stream;
-  std::vector<double> c(3 * (size_t)h->n_boxes);
-  for (int b = 0; b < h->n_boxes; ++b) {
-    const BoxDev &B = h->L.boxes[b];
-    for (int a = 0; a < 3; ++a) {
-      const int n = a == 0 ? B.nx : (a == 1 ? B.ny : B.nz);
-      c[3 * b + a] = centre ? centre[3 * b + a] : 0.5 * (n - 1);
-    }
+  const double *dc = nullptr;  // NULL: the kernels use each box's centre
+  if (centre) {
+    HIP_TRY(hipMemcpyAsync(h->d_centre, centre, sizeof(double) * 3 * (size_t)h->n_boxes,
+                           hipMemcpyHostToDevice, s));
+    dc = h->d_centre;
   }
-  HIP_TRY(hipMemcpyAsync(h->d_centre, c.data(), sizeof(double) * c.size(), hipMemcpyHostToDevice, s));
-  int rc = compute_fields(h, s, 0);
+  double *dout = out_is_host ? h->d_out : out;
+  int rc = reduce_launch(h, s, dc, h->d_part, h->d_diag, dout);
   if (rc) return rc;
-  const double *rho64 =
-      storage_exact(h->storage)
-          ? (const double *)((const char *)h->aux + align256((int64_t)A_COUNT * h->L.total * 4))
-          : nullptr;
-  hipLaunchKernelGGL(k_reduce1, dim3(h->L.nblk), dim3(kBlock), 0, s, h->d_boxes, h->d_blk_box,
-                     h->aux, h->L.total, rho64, h->d_centre, h->d_part);
-  hipLaunchKernelGGL(k_reduce_final, dim3(h->n_boxes), dim3(kBlock), 0, s, h->d_boxes, h->d_part,
-                     1, h->d_diag);
-  hipLaunchKernelGGL(k_reduce2, dim3(h->L.nblk), dim3(kBlock), 0, s, h->d_boxes, h->d_blk_box,
-                     h->aux, h->L.total, h->d_centre, h->d_diag, h->d_part);
-  hipLaunchKernelGGL(k_reduce_final, dim3(h->n_boxes), dim3(kBlock), 0, s, h->d_boxes, h->d_part,
-                     2, h->d_diag);
-  if ((rc = check_launch())) return rc;
-  std::vector<double> diag((size_t)kNPart * h->n_boxes);
-  HIP_TRY(hipMemcpyAsync(diag.data(), h->d_diag, sizeof(double) * diag.size(),
+  if (!out_is_host) return CGLBM_OK;
+  HIP_TRY(hipMemcpyAsync(out, h->d_out, sizeof(double) * CGLBM_NDIAG * (size_t)h->n_boxes,
                          hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  bool unstable = false;
-  std::vector<double> packed((size_t)CGLBM_NDIAG * h->n_boxes);
-  for (int b = 0; b < h->n_boxes; ++b) {
-    for (int k = 0; k < CGLBM_NDIAG; ++k) packed[(size_t)b * CGLBM_NDIAG + k] = diag[(size_t)b * kNPart + k];
-    if (diag[(size_t)b * kNPart + 12] != 0.0) unstable = true;
-  }
-  if (out_is_host) {
-    std::memcpy(out, packed.data(), sizeof(double) * packed.size());
-    if (unstable) return fail(CGLBM_EUNSTABLE, "non-finite values in the state");
-    return CGLBM_OK;
-  }
-  HIP_TRY(hipMemcpyAsync(out, packed.data(), sizeof(double) * packed.size(), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipStreamSynchronize(s));
+  for (int b = 0; b < h->n_boxes; ++b)
+    if (out[(size_t)b * CGLBM_NDIAG + 12] != 0.0)
+      return fail(CGLBM_EUNSTABLE, "non-finite values in the state");
   return CGLBM_OK;
 }
 
@@ -1301,6 +1337,8 @@ void cglbm_destroy(cglbm_handle *h) {
   if (h->d_tile_box) (void)hipFree(h->d_tile_box);
   if (h->d_col_box) (void)hipFree(h->d_col_box);
   if (h->d_part) (void)hipFree(h->d_part);
+  if (h->d_rch_box) (void)hipFree(h->d_rch_box);
+  if (h->d_out) (void)hipFree(h->d_out);
   if (h->d_diag) (void)hipFree(h->d_diag);
   if (h->d_centre) (void)hipFree(h->d_centre);
   if (h->stash) (void)hipFree(h->stash);

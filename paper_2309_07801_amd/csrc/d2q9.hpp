@@ -456,7 +456,8 @@ __global__ __launch_bounds__(NT) void k2_step(const BoxDev *__restrict__ boxes,
     const float rho = rr + rb;
     const float irho = rcp(rho);
     const float p = rr * B.cs2r + rb * B.cs2b;
-    const float ux = fmaf(0.5f, Fx, jx) * irho, uy = fmaf(0.5f, Fy, jy) * irho;
+    const float ux = div_refined(fmaf(0.5f, Fx, jx), rho, irho);
+    const float uy = div_refined(fmaf(0.5f, Fy, jy), rho, irho);
     // Eqs. (21)-(22): omega_1 = 1 / tau, tau = rho nu / p + 1/2
     const float ph = s_phi[ry][rx];
     const float nu = 0.5f * ((1.f + ph) * B.nu_r + (1.f - ph) * B.nu_b);

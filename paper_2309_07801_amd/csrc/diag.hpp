@@ -53,12 +53,18 @@ __global__ __launch_bounds__(kBlock) void k_fields(const BoxDev *__restrict__ bo
 }
 
 // ---------------------------------------------------------------------------
-// Deterministic FP64 diagnostics.  Pass 1 per 256-node block: sums of rho_r,
+// Deterministic FP64 diagnostics.  Each box is cut into chunks of
+// kRedChunk = kRedG x 256 consecutive nodes; a block of 256 threads sums one
+// chunk (thread t adds nodes t, t + 256, ... in that order, then a fixed
+// tree combines the 256 thread sums).  Pass 1 per chunk: sums of rho_r,
 // rho_b, rho u, V = (1+phi)/2, red centroid offsets, kinetic energy,
 // non-finite count.  Pass 2: inside / outside pressure sums given R_eff.
-// Final passes sum the block partials of each box in block order.
+// The final passes sum the chunk partials of each box in chunk order: the
+// order depends only on the box, never on the launch or the other boxes.
 // ---------------------------------------------------------------------------
-constexpr int kNPart = 16;
+constexpr int kNPart = 16;  // doubles per partial and per box in diag
+constexpr int kRedG = 64;
+constexpr int64_t kRedChunk = (int64_t)kRedG * kBlock;
 
 __device__ __forceinline__ float periodic_offset(float d, int n, bool periodic) {
   if (!periodic) return d;
@@ -66,6 +72,12 @@ __device__ __forceinline__ float periodic_offset(float d, int n, bool periodic) 
   if (d > h) d -= n;
   if (d < -h) d += n;
   return d;
+}
+
+// Centre coordinate a of box b: the caller's (centre != NULL) or the box's.
+__device__ __forceinline__ float centre_of(const BoxDev &B, const double *centre, int b, int a) {
+  const int n = a == 0 ? B.nx : (a == 1 ? B.ny : B.nz);
+  return centre ? (float)centre[3 * b + a] : (float)(0.5 * (n - 1));
 }
 
 template <int NV>
@@ -88,114 +100,122 @@ __device__ __forceinline__ void block_sum_f64(double (&v)[NV], double *part) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_reduce1(const BoxDev *__restrict__ boxes,
-                                                    const int32_t *__restrict__ blk_box,
+                                                    const int32_t *__restrict__ rch_box,
                                                     const float *__restrict__ aux, int64_t plane,
                                                     const double *__restrict__ rho64,
                                                     const double *__restrict__ centre,
                                                     double *__restrict__ part) {
-  const int b = blk_box[blockIdx.x];
+  const int b = rch_box[blockIdx.x];
   const BoxDev B = boxes[b];
-  const int64_t local = (int64_t)(blockIdx.x - B.blk0) * kBlock + threadIdx.x;
+  const float cx = centre_of(B, centre, b, 0), cy = centre_of(B, centre, b, 1),
+              cz = centre_of(B, centre, b, 2);
   double v[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  if (local < B.n) {
+  const int64_t first = (int64_t)(blockIdx.x - (uint32_t)B.rch0) * kRedChunk + threadIdx.x;
+  for (int g = 0; g < kRedG; ++g) {
+    const int64_t local = first + (int64_t)g * kBlock;
+    if (local >= B.n) break;
     const uint32_t l = (uint32_t)local;
     const uint32_t yz = fdiv(l, B.fdx);
     const int x = (int)(l - yz * (uint32_t)B.nx);
     const int z = (int)fdiv(yz, B.fdy);
     const int y = (int)(yz - (uint32_t)z * (uint32_t)B.ny);
-    if (!is_solid(B, y, z)) {
-      const uint32_t node = (uint32_t)(B.base + local);
-      const NodeIn in = load_node_in(aux, plane, node);
-      // colour densities in FP64 where the storage carries them
-      const double rr = rho64 ? at(rho64, node) : (double)in.rr;
-      const double rb = rho64 ? at(rho64 + plane, node) : (double)in.rb;
-      const double rho = rr + rb;
-      const double jx = (double)in.jx + 0.5 * in.Fx, jy = (double)in.jy + 0.5 * in.Fy,
-                   jz = (double)in.jz + 0.5 * in.Fz;
-      const float sr = in.rr * B.ir0r, sb = in.rb * B.ir0b;
-      const double phi = (sr + sb) > 0.f ? (double)((sr - sb) / (sr + sb)) : 0.0;
-      const double dx = periodic_offset(x - (float)centre[3 * b + 0], B.nx, true);
-      const double dy = periodic_offset(y - (float)centre[3 * b + 1], B.ny, !(B.walls & 1u));
-      const double dz = periodic_offset(z - (float)centre[3 * b + 2], B.nz, !(B.walls & 2u));
-      const bool finite = isfinite(in.rr) && isfinite(in.rb) && isfinite(in.jx) &&
-                          isfinite(in.jy) && isfinite(in.jz) && isfinite(in.pxx) &&
-                          isfinite(in.pyy) && isfinite(in.pzz) && isfinite(in.pxy) &&
-                          isfinite(in.pxz) && isfinite(in.pyz);
-      v[0] = rr;
-      v[1] = rb;
-      v[2] = jx;
-      v[3] = jy;
-      v[4] = jz;
-      v[5] = 0.5 * (1.0 + phi);
-      v[6] = rr * dx;
-      v[7] = rr * dy;
-      v[8] = rr * dz;
-      v[9] = 0.5 * (jx * jx + jy * jy + jz * jz) / rho;
-      v[10] = finite ? 0.0 : 1.0;
-      if (!finite) {
-        for (int k = 0; k < 10; ++k) v[k] = 0.0;
-      }
+    if (is_solid(B, y, z)) continue;
+    const uint32_t node = (uint32_t)(B.base + local);
+    const NodeIn in = load_node_in(aux, plane, node);
+    const bool finite = isfinite(in.rr) && isfinite(in.rb) && isfinite(in.jx) &&
+                        isfinite(in.jy) && isfinite(in.jz) && isfinite(in.pxx) &&
+                        isfinite(in.pyy) && isfinite(in.pzz) && isfinite(in.pxy) &&
+                        isfinite(in.pxz) && isfinite(in.pyz);
+    if (!finite) {
+      v[10] += 1.0;
+      continue;
     }
+    // colour densities in FP64 where the storage carries them
+    const double rr = rho64 ? at(rho64, node) : (double)in.rr;
+    const double rb = rho64 ? at(rho64 + plane, node) : (double)in.rb;
+    const double rho = rr + rb;
+    const double jx = (double)in.jx + 0.5 * in.Fx, jy = (double)in.jy + 0.5 * in.Fy,
+                 jz = (double)in.jz + 0.5 * in.Fz;
+    const float sr = in.rr * B.ir0r, sb = in.rb * B.ir0b;
+    const double phi = (sr + sb) > 0.f ? (double)((sr - sb) / (sr + sb)) : 0.0;
+    const double dx = periodic_offset(x - cx, B.nx, true);
+    const double dy = periodic_offset(y - cy, B.ny, !(B.walls & 1u));
+    const double dz = periodic_offset(z - cz, B.nz, !(B.walls & 2u));
+    v[0] += rr;
+    v[1] += rb;
+    v[2] += jx;
+    v[3] += jy;
+    v[4] += jz;
+    v[5] += 0.5 * (1.0 + phi);
+    v[6] += rr * dx;
+    v[7] += rr * dy;
+    v[8] += rr * dz;
+    v[9] += 0.5 * (jx * jx + jy * jy + jz * jz) / rho;
   }
   block_sum_f64<11>(v, part + (int64_t)blockIdx.x * kNPart);
 }
 
 __global__ __launch_bounds__(kBlock) void k_reduce2(const BoxDev *__restrict__ boxes,
-                                                    const int32_t *__restrict__ blk_box,
+                                                    const int32_t *__restrict__ rch_box,
                                                     const float *__restrict__ aux, int64_t plane,
                                                     const double *__restrict__ centre,
                                                     const double *__restrict__ diag,
                                                     double *__restrict__ part) {
-  const int b = blk_box[blockIdx.x];
+  const int b = rch_box[blockIdx.x];
   const BoxDev B = boxes[b];
-  const int64_t local = (int64_t)(blockIdx.x - B.blk0) * kBlock + threadIdx.x;
+  const float cx = centre_of(B, centre, b, 0), cy = centre_of(B, centre, b, 1),
+              cz = centre_of(B, centre, b, 2);
   double v[4] = {0, 0, 0, 0};
   const double reff = diag[(int64_t)b * kNPart + 7];
-  if (local < B.n) {
+  const int64_t first = (int64_t)(blockIdx.x - (uint32_t)B.rch0) * kRedChunk + threadIdx.x;
+  for (int g = 0; g < kRedG; ++g) {
+    const int64_t local = first + (int64_t)g * kBlock;
+    if (local >= B.n) break;
     const uint32_t l = (uint32_t)local;
     const uint32_t yz = fdiv(l, B.fdx);
     const int x = (int)(l - yz * (uint32_t)B.nx);
     const int z = (int)fdiv(yz, B.fdy);
     const int y = (int)(yz - (uint32_t)z * (uint32_t)B.ny);
-    if (!is_solid(B, y, z)) {
-      const uint32_t node = (uint32_t)(B.base + local);
-      const double p = (double)(at(PL(aux, A_RR), node) * B.cs2r +
-                                at(PL(aux, A_RB), node) * B.cs2b);
-      const double dx = periodic_offset(x - (float)centre[3 * b + 0], B.nx, true);
-      const double dy = periodic_offset(y - (float)centre[3 * b + 1], B.ny, !(B.walls & 1u));
-      const double dz = periodic_offset(z - (float)centre[3 * b + 2], B.nz, !(B.walls & 2u));
-      const double d = sqrt(dx * dx + dy * dy + dz * dz);
-      if (isfinite(p)) {
-        if (d < reff - 3.0) {
-          v[0] = p;
-          v[1] = 1.0;
-        }
-        if (d > reff + 5.0) {
-          v[2] = p;
-          v[3] = 1.0;
-        }
+    if (is_solid(B, y, z)) continue;
+    const uint32_t node = (uint32_t)(B.base + local);
+    const double p = (double)(at(PL(aux, A_RR), node) * B.cs2r + at(PL(aux, A_RB), node) * B.cs2b);
+    const double dx = periodic_offset(x - cx, B.nx, true);
+    const double dy = periodic_offset(y - cy, B.ny, !(B.walls & 1u));
+    const double dz = periodic_offset(z - cz, B.nz, !(B.walls & 2u));
+    const double d = sqrt(dx * dx + dy * dy + dz * dz);
+    if (isfinite(p)) {
+      if (d < reff - 3.0) {
+        v[0] += p;
+        v[1] += 1.0;
+      }
+      if (d > reff + 5.0) {
+        v[2] += p;
+        v[3] += 1.0;
       }
     }
   }
   block_sum_f64<4>(v, part + (int64_t)blockIdx.x * kNPart);
 }
 
-// One block per box: fixed-order sum of the box's block partials.  Thread t
+// One block per box: fixed-order sum of the box's chunk partials.  Thread t
 // sums the contiguous run [t*c, (t+1)*c) of partials in order, then a fixed
 // tree combines the 256 thread sums; the order depends only on the box.
-// pass 1 fills diag[0..4, 7 (R_eff), 8..10 (centroid), 11, 12]; pass 2 fills 5, 6.
+// pass 1 fills diag[0..4, 7 (R_eff), 8..10 (centroid), 11, 12]; pass 2 fills
+// 5, 6 and, if out is not NULL, writes the box's CGLBM_NDIAG (13) values,
+// diag[0..12], to out[13 b ...] (the packed layout of cglbm_reduce).
 __global__ __launch_bounds__(kBlock) void k_reduce_final(const BoxDev *__restrict__ boxes,
                                                          const double *__restrict__ part, int pass,
-                                                         double *__restrict__ diag) {
+                                                         double *__restrict__ diag,
+                                                         double *__restrict__ out) {
   const int b = blockIdx.x;
   const BoxDev B = boxes[b];
-  const int nblk = (int)((B.n + kBlock - 1) / kBlock);
-  const int chunk = (nblk + kBlock - 1) / kBlock;
-  const int k0 = min((int)threadIdx.x * chunk, nblk), k1 = min(k0 + chunk, nblk);
+  const int nch = (int)((B.n + kRedChunk - 1) / kRedChunk);
+  const int chunk = (nch + kBlock - 1) / kBlock;
+  const int k0 = min((int)threadIdx.x * chunk, nch), k1 = min(k0 + chunk, nch);
   double v[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   const int nv = pass == 1 ? 11 : 4;
   for (int k = k0; k < k1; ++k)
-    for (int c = 0; c < nv; ++c) v[c] += part[(int64_t)(B.blk0 + k) * kNPart + c];
+    for (int c = 0; c < nv; ++c) v[c] += part[(int64_t)(B.rch0 + k) * kNPart + c];
   __shared__ double tot[kNPart];
   {
     double w[11];
@@ -222,6 +242,9 @@ __global__ __launch_bounds__(kBlock) void k_reduce_final(const BoxDev *__restric
   } else {
     o[5] = tot[1] > 0 ? tot[0] / tot[1] : 0.0;
     o[6] = tot[3] > 0 ? tot[2] / tot[3] : 0.0;
+    if (out) {
+      for (int k = 0; k < 13; ++k) out[(int64_t)b * 13 + k] = o[k];
+    }
   }
 }
 

@@ -70,6 +70,7 @@ struct BoxDev {
   int32_t wbase, wn;    // wall-node slots of the box in the in-place stash
   int32_t wblk0;        // first block of the box in k_wall_copy
   int32_t ccol0;        // first column block of the box (k_cpull)
+  int32_t rch0;         // first reduction chunk of the box (k_reduce1, k_reduce2)
   int32_t cncx, cncy;   // k_cpull columns along x, y
   FastDiv fccx, fccy;   // division by cncx, cncy
 };
@@ -106,6 +107,17 @@ __device__ __forceinline__ int64_t opaque_i64(int64_t v) {
 // the correctly rounded division and square root sequences.
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+// num / den from r, the hardware reciprocal of den, refined by one
+// Newton-Raphson step on the residual num - den q (formed exactly by an
+// FMA): within about half an ulp, exactly 1 for num == den and 0 for
+// num == 0.  The colour fractions and the velocity use it: num * r alone
+// carries the fixed relative error of r for a given den, which made the
+// colour masses and momenta of uniform regions drift by the same fraction
+// of an ulp at every step.
+__device__ __forceinline__ float div_refined(float num, float den, float r) {
+  const float q = num * r;
+  return fmaf(r, fmaf(-den, q, num), q);
+}
 
 // Scalar buffer descriptor of plane p of an SoA array whose planes are
 // plane_bytes apart.  The host keeps every plane below 4 GiB, so a lane
@@ -246,10 +258,12 @@ __host__ __device__ inline void wall_node(const BoxDev &B, uint32_t slot, int &x
 struct Split32 {
   using W = float;  // one plane element
   static constexpr bool kPaired = false;
+  static constexpr bool kCShift = false;
 };
 struct Pair32 {
   using W = uint64_t;
   static constexpr bool kPaired = true;
+  static constexpr bool kCShift = false;
   __device__ static W pack(float r, float b) {
     return (uint64_t)__builtin_bit_cast(uint32_t, r) | ((uint64_t)__builtin_bit_cast(uint32_t, b) << 32);
   }
@@ -259,6 +273,7 @@ struct Pair32 {
 struct Pair16 {
   using W = uint32_t;
   static constexpr bool kPaired = true;
+  static constexpr bool kCShift = false;
   __device__ static W pack(uint16_t r, uint16_t b) { return (uint32_t)r | ((uint32_t)b << 16); }
   __device__ static uint16_t lo(W w) { return (uint16_t)w; }
   __device__ static uint16_t hi(W w) { return (uint16_t)(w >> 16); }
@@ -299,6 +314,23 @@ struct StoreBF16 : Pair16 {
   __device__ static float dec(T g) { return __builtin_bit_cast(float, (uint32_t)g << 16); }
 };
 
+// Colour-fraction-scaled shift (FP16 / BF16): each moving population is
+// stored as f^k_i - c_k s^k_i, with s^k_i the pure-phase rest equilibrium of
+// colour k as above (unrounded) and c_k the colour fraction rho_k / rho of
+// the node that wrote it (red c_r, blue 1 - c_r), itself stored per node in
+// the format's 16-bit type.  In a pure phase the stored values are the small
+// deviations from equilibrium and the opposite colour stores exact zeros; at
+// the interface, where the constant shift leaves a remainder of the order of
+// s itself, each colour stores its deviation from its own share of the
+// equilibrium.  A reader decodes a population with the fraction stored at
+// its source node x - c_i.
+struct StoreF16C : StoreF16 {
+  static constexpr bool kCShift = true;
+};
+struct StoreBF16C : StoreBF16 {
+  static constexpr bool kCShift = true;
+};
+
 __host__ __device__ inline int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
 
 // Views of one population buffer.  Plain FP32: 54 float planes, plane
@@ -312,10 +344,12 @@ struct Pops {
   static constexpr int kPlanes = S::kPaired ? kDirs : 2 * kDirs;
   W *pw;
   double *rest;
+  typename S::T *cfr;  // colour-fraction formats: the red fraction of each node
   int64_t plane;
   __device__ Pops(void *base, int64_t plane_) : plane(plane_) {
     pw = (W *)base;
     rest = (double *)((char *)base + align256(kPlanes * plane_ * (int64_t)sizeof(W)));
+    cfr = (typename S::T *)(rest + 2 * plane_);
   }
   // plane of direction i (paired), or of direction i and colour c (split)
   __device__ static int slot(int i, int c = 0) {
@@ -330,12 +364,28 @@ __device__ __forceinline__ double *aux_rho64(float *aux, int64_t plane) {
   return (double *)((char *)aux + align256((int64_t)A_COUNT * plane * 4));
 }
 
-// Shift of direction i of colour c (0 without shift), as a value of T.
+// Shift of direction i of colour c (0 without shift): the constant shift
+// rounded to the storage type, or, for the colour-fraction formats, the
+// unrounded constant scaled by the writer's colour fraction (cr: its red
+// fraction as stored; blue takes 1 - cr).  The stored value of a population
+// f is enc(f - shift); it reads back as dec(stored) + shift, an expression
+// every kernel evaluates the same way.
 template <class S>
-__device__ __forceinline__ float pop_shift(const BoxDev &B, int c, int i) {
+__device__ __forceinline__ float pop_shift(const BoxDev &B, int c, int i, float cr = 0.f) {
   if (!S::kShift || i == 0) return 0.f;
   const int cls = kCX[i] * kCX[i] + kCY[i] * kCY[i] + kCZ[i] * kCZ[i];
-  return S::dec(S::enc(B.shift[c][cls]));
+  if constexpr (S::kCShift) {
+    const float frac = c == 0 ? cr : 1.0f - cr;
+    return frac * B.shift[c][cls];
+  } else {
+    return S::dec(S::enc(B.shift[c][cls]));
+  }
+}
+// Red fraction rho_r / rho of a node as the colour-fraction formats store it
+// (correctly rounded quotient: exactly 1 and 0 in the pure phases).
+template <class S>
+__device__ __forceinline__ typename S::T stored_fraction(float rr, float rb) {
+  return S::enc(rr / (rr + rb));
 }
 
 template <class W>
@@ -420,6 +470,15 @@ __global__ __launch_bounds__(kBlock) void k_pull(const BoxDev *__restrict__ boxe
     const uint32_t s = row[kCY[i] + 1][kCZ[i] + 1] + (uint32_t)xs[kCX[i] + 1];
     ld_rb(src, i, s, gr[i], gb[i]);
   }
+  // colour-fraction formats: the red fraction stored at each source node
+  float csrc[kQ];
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) csrc[i] = 0.f;
+  if constexpr (S::kCShift) {
+#pragma unroll
+    for (int i = 1; i < kQ; ++i)
+      csrc[i] = S::dec(ld(&at(src.cfr, row[kCY[i] + 1][kCZ[i] + 1] + (uint32_t)xs[kCX[i] + 1])));
+  }
   double rr0 = 0.0, rb0 = 0.0;
   if (S::kExact) {
     rr0 = at(src.restp(0), node);
@@ -430,8 +489,30 @@ __global__ __launch_bounds__(kBlock) void k_pull(const BoxDev *__restrict__ boxe
       // the shift of direction i equals that of its opposite: copy raw pairs
       const Pops<S> out(STASH ? stash_ : dst_, STASH ? wplane : plane);
       const uint32_t at_ = STASH ? (uint32_t)B.wbase + wall_slot(B, x, y, z) : node;
+      if constexpr (S::kCShift) {
+        // the solid node takes the red fraction of its wall-normal fluid
+        // neighbour and re-encodes each reversed population with it (one
+        // more rounding of the bounced values; exact where the fluid next to
+        // the wall is a pure phase and the decoded value less its shift is
+        // the stored one)
+        const int dy = (B.walls & 1u) ? (y == 0 ? -1 : (y == ny - 1 ? 1 : 0)) : 0;
+        const int dz = (B.walls & 2u) ? (z == 0 ? -1 : (z == nz - 1 ? 1 : 0)) : 0;
+        const uint32_t nb = (uint32_t)B.base + (uint32_t)x +
+                            (uint32_t)nx * ((uint32_t)(y - dy) + (uint32_t)ny * (uint32_t)(z - dz));
+        const typename S::T craw = ld(&at(src.cfr, nb));
+        const float cown = S::dec(craw);
 #pragma unroll
-      for (int i = i0; i < kQ; ++i) st_rb(out, opposite(i), at_, gr[i], gb[i]);
+        for (int i = 1; i < kQ; ++i) {
+          const float fr = S::dec(gr[i]) + pop_shift<S>(B, 0, i, csrc[i]);
+          const float fb = S::dec(gb[i]) + pop_shift<S>(B, 1, i, csrc[i]);
+          st_rb(out, opposite(i), at_, S::enc(fr - pop_shift<S>(B, 0, i, cown)),
+                S::enc(fb - pop_shift<S>(B, 1, i, cown)));
+        }
+        at(out.cfr, at_) = craw;
+      } else {
+#pragma unroll
+        for (int i = i0; i < kQ; ++i) st_rb(out, opposite(i), at_, gr[i], gb[i]);
+      }
       if (S::kExact) {
         at(out.restp(0), at_) = rr0;
         at(out.restp(1), at_) = rb0;
@@ -451,8 +532,8 @@ __global__ __launch_bounds__(kBlock) void k_pull(const BoxDev *__restrict__ boxe
   double drr = rr0, drb = rb0;
 #pragma unroll
   for (int i = i0; i < kQ; ++i) {
-    const float vr = S::dec(gr[i]) + pop_shift<S>(B, 0, i);
-    const float vb = S::dec(gb[i]) + pop_shift<S>(B, 1, i);
+    const float vr = S::dec(gr[i]) + pop_shift<S>(B, 0, i, csrc[i]);
+    const float vb = S::dec(gb[i]) + pop_shift<S>(B, 1, i, csrc[i]);
     if (S::kExact) {
       drr += (double)vr;
       drb += (double)vb;
@@ -720,10 +801,9 @@ struct NodeIn {
 // pair goes out through emit(i, f_r, f_b).
 template <class Emit>
 __device__ __forceinline__ void emit_recoloured(const BoxDev &B, const float (&k)[27], float ux,
-                                                float uy, float uz, float rr, float rb,
-                                                float irho, float p, float nx, float ny,
-                                                float nz, Emit &&emit) {
-  const float cr = rr * irho, cb = rb * irho;
+                                                float uy, float uz, float cr, float cb,
+                                                float p, float nx, float ny, float nz,
+                                                Emit &&emit) {
   const float s = B.beta * cr * cb * p;
   const float Rx = s * nx, Ry = s * ny, Rz = s * nz;
   float g[3][3][3];
@@ -774,9 +854,9 @@ __device__ __forceinline__ void collide_node(const BoxDev &B, const NodeIn &in, 
                                              Pre &&pre = Pre()) {
   const float rho = in.rr + in.rb;
   const float irho = rcp(rho);
-  const float ux = fmaf(0.5f, in.Fx, in.jx) * irho;  // Eq. (11)
-  const float uy = fmaf(0.5f, in.Fy, in.jy) * irho;
-  const float uz = fmaf(0.5f, in.Fz, in.jz) * irho;
+  const float ux = div_refined(fmaf(0.5f, in.Fx, in.jx), rho, irho);  // Eq. (11)
+  const float uy = div_refined(fmaf(0.5f, in.Fy, in.jy), rho, irho);
+  const float uz = div_refined(fmaf(0.5f, in.Fz, in.jz), rho, irho);
   const float p = in.rr * B.cs2r + in.rb * B.cs2b;   // Eq. (12)
   // Eqs. (14), (21), (22): omega_1 from the interpolated viscosity
   const float sr = in.rr * B.ir0r, sb = in.rb * B.ir0b;
@@ -810,7 +890,8 @@ __device__ __forceinline__ void collide_node(const BoxDev &B, const NodeIn &in, 
   else
     model_d_moments(rho, p, in.Fx, in.Fy, in.Fz, sxx, syy, szz, r1 * kxy, r1 * kxz, r1 * kyz, k);
   pre();
-  emit_recoloured(B, k, ux, uy, uz, in.rr, in.rb, irho, p, in.nx, in.ny, in.nz, emit);
+  emit_recoloured(B, k, ux, uy, uz, div_refined(in.rr, rho, irho), div_refined(in.rb, rho, irho),
+                  p, in.nx, in.ny, in.nz, emit);
 }
 
 // ---------------------------------------------------------------------------
@@ -830,9 +911,9 @@ template <bool GENERAL = false>
 __device__ __forceinline__ void compact_of(const BoxDev &B, const NodeIn &in, float (&c)[kCompact]) {
   const float rho = in.rr + in.rb;
   const float irho = rcp(rho);
-  const float ux = fmaf(0.5f, in.Fx, in.jx) * irho;
-  const float uy = fmaf(0.5f, in.Fy, in.jy) * irho;
-  const float uz = fmaf(0.5f, in.Fz, in.jz) * irho;
+  const float ux = div_refined(fmaf(0.5f, in.Fx, in.jx), rho, irho);
+  const float uy = div_refined(fmaf(0.5f, in.Fy, in.jy), rho, irho);
+  const float uz = div_refined(fmaf(0.5f, in.Fz, in.jz), rho, irho);
   const float p = in.rr * B.cs2r + in.rb * B.cs2b;
   const float sr = in.rr * B.ir0r, sb = in.rb * B.ir0b;
   const float phi = (sr - sb) * rcp(sr + sb);
@@ -893,8 +974,8 @@ __device__ __forceinline__ void compact_post(const BoxDev &B, const float (&c)[k
   o.ux = c[2];
   o.uy = c[3];
   o.uz = c[4];
-  o.cr = rr * irho;
-  o.cb = rb * irho;
+  o.cr = div_refined(rr, rho, irho);
+  o.cb = div_refined(rb, rho, irho);
   const float s = B.beta * o.cr * o.cb * p;
   o.Rx = s * c[14];
   o.Ry = s * c[15];
@@ -922,9 +1003,9 @@ __device__ __forceinline__ void collide_full(const BoxDev &B, const NodeIn &in,
                                              const float (&f)[27], Emit &&emit) {
   const float rho = in.rr + in.rb;
   const float irho = rcp(rho);
-  const float ux = fmaf(0.5f, in.Fx, in.jx) * irho;
-  const float uy = fmaf(0.5f, in.Fy, in.jy) * irho;
-  const float uz = fmaf(0.5f, in.Fz, in.jz) * irho;
+  const float ux = div_refined(fmaf(0.5f, in.Fx, in.jx), rho, irho);
+  const float uy = div_refined(fmaf(0.5f, in.Fy, in.jy), rho, irho);
+  const float uz = div_refined(fmaf(0.5f, in.Fz, in.jz), rho, irho);
   const float p = in.rr * B.cs2r + in.rb * B.cs2b;
   const float sr = in.rr * B.ir0r, sb = in.rb * B.ir0b;
   const float phi = (sr - sb) * rcp(sr + sb);
@@ -1015,7 +1096,8 @@ __device__ __forceinline__ void collide_full(const BoxDev &B, const NodeIn &in,
 #undef K_
 #undef E_
 #undef S_
-  emit_recoloured(B, ks, ux, uy, uz, in.rr, in.rb, irho, p, in.nx, in.ny, in.nz, emit);
+  emit_recoloured(B, ks, ux, uy, uz, div_refined(in.rr, rho, irho), div_refined(in.rb, rho, irho),
+                  p, in.nx, in.ny, in.nz, emit);
 }
 
 // Pulled total distribution f_i(x) = sum over colours of stored_i(x - c_i),
@@ -1036,7 +1118,8 @@ __device__ __forceinline__ void pull_total(const BoxDev &B, const void *src_, in
                        (uint32_t)nx * ((uint32_t)ys[kCY[i] + 1] + (uint32_t)ny * (uint32_t)zs[kCZ[i] + 1]);
     typename S::T r, b;
     ld_rb(src, i, s, r, b);
-    f[i] = (S::dec(r) + pop_shift<S>(B, 0, i)) + (S::dec(b) + pop_shift<S>(B, 1, i));
+    const float cs = S::kCShift ? S::dec(ld(&at(src.cfr, s))) : 0.f;
+    f[i] = (S::dec(r) + pop_shift<S>(B, 0, i, cs)) + (S::dec(b) + pop_shift<S>(B, 1, i, cs));
   }
   if (S::kExact) f[0] = (float)(at(src.restp(0), node) + at(src.restp(1), node));
 }
@@ -1078,11 +1161,20 @@ struct PopWriter {
   bool live;
   uint32_t node;
   double sr = 0.0, sb = 0.0;
+  typename S::T craw{};  // colour-fraction formats: the node's red fraction as stored
+  float cr = 0.f;        // and its value
   __device__ PopWriter(const Pops<S> &d, const BoxDev &b, uint32_t n, bool l = true)
       : dst(d), B(b), live(l), node(n) {}
+  // the node's colour densities (colour-fraction formats; before the emission)
+  __device__ __forceinline__ void set_fraction(float rr, float rb) {
+    if constexpr (S::kCShift) {
+      craw = stored_fraction<S>(rr, rb);
+      cr = S::dec(craw);
+    }
+  }
   __device__ __forceinline__ void operator()(int i, float fr, float fb) {
     if (S::kExact && i == 0) return;
-    const float shr = pop_shift<S>(B, 0, i), shb = pop_shift<S>(B, 1, i);
+    const float shr = pop_shift<S>(B, 0, i, cr), shb = pop_shift<S>(B, 1, i, cr);
     const typename S::T er = S::enc(fr - shr), eb = S::enc(fb - shb);
     using W = typename S::W;
     const int64_t pb = dst.plane * (int64_t)sizeof(W);
@@ -1104,6 +1196,8 @@ struct PopWriter {
       buf_st(rho_r - sr, plane_rsrc(dst.rest, pb, 0), off);
       buf_st(rho_b - sb, plane_rsrc(dst.rest, pb, 1), off);
     }
+    if constexpr (S::kCShift)
+      buf_st((uint16_t)craw, plane_rsrc(dst.cfr, dst.plane * 2, 0), boff<uint16_t>(live, node));
   }
 };
 
@@ -1137,6 +1231,7 @@ __global__ __launch_bounds__(kBlock) void k_collide(const BoxDev *__restrict__ b
   }
   const Pops<S> dst(dst_, plane);
   PopWriter<S> w(dst, B, node);
+  w.set_fraction(in.rr, in.rb);
   if (B.full_rates) {
     // non-unit higher-order rates need every central moment: pull again
     float f[27];
@@ -1186,6 +1281,7 @@ __global__ __launch_bounds__(kBlock) void k_wall_copy(const BoxDev *__restrict__
     at(dst.restp(0), node) = at(src.restp(0), slot);
     at(dst.restp(1), node) = at(src.restp(1), slot);
   }
+  if constexpr (S::kCShift) at(dst.cfr, node) = at(src.cfr, slot);
 }
 
 // ---------------------------------------------------------------------------
@@ -1235,7 +1331,10 @@ __global__ __launch_bounds__(kBlock) void k_init(const BoxDev *__restrict__ boxe
               zd = wrap_once(z - kCZ[i], B.nz);
     const uint32_t d = (uint32_t)B.base + (uint32_t)xd +
                        (uint32_t)B.nx * ((uint32_t)yd + (uint32_t)B.ny * (uint32_t)zd);
-    const float shr = pop_shift<S>(B, 0, i), shb = pop_shift<S>(B, 1, i);
+    // colour-fraction formats: the value is read back with the red fraction
+    // the node d stores (written below by d's own thread)
+    const float cd = S::kCShift ? S::dec(stored_fraction<S>(in_rr[d], in_rb[d])) : 0.f;
+    const float shr = pop_shift<S>(B, 0, i, cd), shb = pop_shift<S>(B, 1, i, cd);
     const typename S::T er = S::enc(vr - shr), eb = S::enc(vb - shb);
     st_rb(dst, i, d, er, eb);
     sr += (double)(S::dec(er) + shr);
@@ -1245,6 +1344,7 @@ __global__ __launch_bounds__(kBlock) void k_init(const BoxDev *__restrict__ boxe
     at(dst.restp(0), node) = tr - sr;
     at(dst.restp(1), node) = tb - sb;
   }
+  if constexpr (S::kCShift) at(dst.cfr, node) = stored_fraction<S>(rr, rb);
 }
 
 // ---------------------------------------------------------------------------
@@ -1664,6 +1764,7 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
           const double fr = d_rr, fb = d_rb;
           const Pops<S> dst(dst_, plane);
           PopWriter<S> w(dst, B, node, fluid && sd >= z0);
+          w.set_fraction(in.rr, in.rb);
           collide_node(B, in, w, [&] {
             if (kPipeD) load_d(s - 2, plane);
           });
@@ -1954,7 +2055,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(const BoxDev *__restrict__ boxe
     model_d_moments(rho, p, c[5], c[6], c[7], c[8], c[9], c[10], c[11], c[12], c[13], k);
   const Pops<S> dst(dst_, plane);
   PopWriter<S> w(dst, B, node);
-  emit_recoloured(B, k, c[2], c[3], c[4], c[0], c[1], irho, p, c[14], c[15], c[16], w);
+  emit_recoloured(B, k, c[2], c[3], c[4], div_refined(c[0], rho, irho), div_refined(c[1], rho, irho),
+                  p, c[14], c[15], c[16], w);
 }
 
 }  // namespace cglbm

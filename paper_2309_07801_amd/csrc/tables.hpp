@@ -19,7 +19,7 @@ namespace cglbm {
 using FusedFn = void (*)(const BoxDev *, const int32_t *, float *, void *, int64_t);
 struct FusedVariant {
   int tx, ty, zc, minw;
-  FusedFn fn[5][2];  // time step: [storage][any box with solid layers]
+  FusedFn fn[7][2];  // time step: [storage][any box with solid layers]
   FusedFn fx[2];     // field export (no population store): [solid layers]
   FusedFn fc[2];     // compact schedule: compact state out (FP32): [solid layers]
 };
@@ -29,7 +29,8 @@ struct FusedVariant {
   {TX, TY, ZC, MW,                                                                           \
    {CGLBM_FV_S(TX, TY, ZC, MW, StoreF32), CGLBM_FV_S(TX, TY, ZC, MW, StoreF16),               \
     CGLBM_FV_S(TX, TY, ZC, MW, StoreBF16), CGLBM_FV_S(TX, TY, ZC, MW, StoreF32X),             \
-    CGLBM_FV_S(TX, TY, ZC, MW, StoreF32P)},                                                  \
+    CGLBM_FV_S(TX, TY, ZC, MW, StoreF32P), CGLBM_FV_S(TX, TY, ZC, MW, StoreF16C),             \
+    CGLBM_FV_S(TX, TY, ZC, MW, StoreBF16C)},                                                 \
    {k_fused<TX, TY, ZC, MW, false, StoreF32, true>, k_fused<TX, TY, ZC, MW, true, StoreF32, true>}, \
    {k_fused<TX, TY, ZC, MW, false, StoreF32, false, true>,                                    \
     k_fused<TX, TY, ZC, MW, true, StoreF32, false, true>}}

@@ -68,8 +68,11 @@ def test_storage_buffer_sizes():
     assert popx == align(52 * total * 4) + 2 * total * 8
     assert aux16 == align(21 * total * 4) + 2 * total * 8 == auxx
     assert pkg.query_sizes(pb, pkg.FP32_PAIRS) == (pop32, aux32, total)
+    # colour-fraction shift: one 16-bit fraction per node after the rest planes
+    for st in (pkg.FP16_CSHIFT, pkg.BF16_CSHIFT):
+        assert pkg.query_sizes(pb, st) == (pop16 + 2 * total, aux16, total)
     with pytest.raises(pkg.CglbmError):
-        pkg.query_sizes(pb, 5)
+        pkg.query_sizes(pb, 7)
 
 
 def test_phase_validation_and_storage():
@@ -120,7 +123,10 @@ def test_d2q9_sizes_and_validation():
         pkg.query_sizes([q], pkg.FP32, lattice="d2q9")
     assert ei.value.code == -3
     with pytest.raises(pkg.CglbmError) as ei:
-        pkg.query_sizes(p, 5, lattice="d2q9")
+        pkg.query_sizes(p, pkg.FP16_CSHIFT, lattice="d2q9")   # D3Q27 only
+    assert ei.value.code == -3
+    with pytest.raises(pkg.CglbmError) as ei:
+        pkg.query_sizes(p, 7, lattice="d2q9")
     assert ei.value.code == -1
     with pytest.raises(ValueError):
         pkg.query_sizes(p, pkg.FP32, lattice="d3q19")

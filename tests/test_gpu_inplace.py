@@ -41,7 +41,7 @@ def _same(a, b):
             assert np.array_equal(x[name], y[name]), (k, name)
 
 
-@pytest.mark.parametrize("storage", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("storage", [0, 1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("schedule", [0, 1])
 def test_inplace_equals_two_buffers(storage, schedule):
     cases = _cases()

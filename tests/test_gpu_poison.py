@@ -3,7 +3,8 @@ with all-one bits (a NaN in every float format) before stepping — the
 alignment gaps between boxes and the plane tail of the stored state, all of
 the second population buffer and all of aux — and the fields after 21
 steps must equal, bit for bit, those of an unpoisoned run, with no
-non-finite value counted.  Every storage format, both layouts, a batch of
+non-finite value counted.  Every storage format (with the colour fractions
+of the colour-fraction-shifted formats), both layouts, a batch of
 four ragged boxes with every wall combination; D2Q9 batches as well."""
 import numpy as np
 import pytest
@@ -27,7 +28,10 @@ def _planes(storage, total):
     if storage == 4:
         return [(0, 8, 27)]
     w = 8 if storage == 3 else 4
-    return [(0, w, 26), (_align256(26 * total * w), 8, 2)]
+    planes = [(0, w, 26), (_align256(26 * total * w), 8, 2)]
+    if storage in (5, 6):  # the per-node colour fractions
+        planes.append((_align256(26 * total * w) + 2 * total * 8, 2, 1))
+    return planes
 
 
 def _sim(cases, storage, inplace):
@@ -48,7 +52,8 @@ def _poison(sim, storage):
     assert gap.numel() > 0
     state = sim.state_tensor()
     for off, es, count in _planes(storage, total):
-        seg = state[off:off + count * total * es].view(torch.int32 if es == 4 else torch.int64)
+        seg = state[off:off + count * total * es].view({2: torch.int16, 4: torch.int32,
+                                                         8: torch.int64}[es])
         seg.view(count, total)[:, gap] = -1
     if sim.pop_b is not None:
         other = sim.pop_b if state is sim.pop_a else sim.pop_a
@@ -57,7 +62,7 @@ def _poison(sim, storage):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("storage", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("storage", [0, 1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("inplace", [False, True])
 def test_poisoned_padding_is_never_read(storage, inplace):
     cases = []

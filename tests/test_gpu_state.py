@@ -42,7 +42,7 @@ def _same(a, b):
             assert np.array_equal(x[k], y[k]), k
 
 
-@pytest.mark.parametrize("storage", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("storage", [0, 1, 2, 3, 4, 5, 6])
 def test_checkpoint_resume_is_bitwise(storage):
     cases = _cases()
     ref = _sim(cases, storage)

@@ -31,10 +31,11 @@ def _case(shape=(17, 13, 11), gamma=10.0, tau=0.7, sigma=0.01, R=3.5, u=(0.02, -
 
 
 # (storage, e_rho, e_u, e_phi) bars after 50 steps
-BARS = {0: (1e-5, 1e-4, 1e-4), 3: (1e-5, 1e-4, 1e-4), 1: (2e-3, 5e-2, 2e-2), 2: (2e-2, 3e-1, 1.5e-1)}
+BARS = {0: (1e-5, 1e-4, 1e-4), 3: (1e-5, 1e-4, 1e-4), 1: (2e-3, 5e-2, 2e-2), 2: (2e-2, 3e-1, 1.5e-1),
+        5: (2e-3, 5e-2, 2e-2), 6: (2e-2, 3e-1, 1.5e-1)}
 
 
-@pytest.mark.parametrize("storage", [3, 1, 2])
+@pytest.mark.parametrize("storage", [3, 1, 2, 5, 6])
 @pytest.mark.parametrize("walls", [0, 3])
 def test_storage_parity_with_oracle(storage, walls):
     box, fl = _case(walls=walls)
@@ -46,7 +47,7 @@ def test_storage_parity_with_oracle(storage, walls):
     assert e["rho"] < br and e["u"] < bu and e["phi"] < bp
 
 
-@pytest.mark.parametrize("storage", [3, 1, 2])
+@pytest.mark.parametrize("storage", [3, 1, 2, 5, 6])
 def test_mass_exact_storage_conserves_colour_mass(storage):
     """Per-colour mass drift over 200 steps of a translating droplet at
     density ratio 10 (uniform carrier flow, where plain FP32 storage drifts
@@ -77,7 +78,7 @@ def test_fp32_exact_close_to_fp32():
         assert np.abs(out[0][k] - out[1][k]).max() <= 2e-5 * 0.02, k
 
 
-@pytest.mark.parametrize("storage", [1, 2, 3])
+@pytest.mark.parametrize("storage", [1, 2, 3, 5, 6])
 def test_storage_fused_equals_three_kernel_schedule(storage):
     box, fl = _case(shape=(37, 19, 23), R=5.0)
     out = []
