@@ -1,6 +1,6 @@
 """Benchmark of the colour-gradient LBM hot path on one MI355X.
 
-Default workload: the translating-droplet case -- 256^3 periodic box, red
+Main line (`value`): the translating-droplet case -- 256^3 periodic box, red
 droplet of radius 32 moving with u = 0.05 along x in a blue carrier, density
 ratio 10, equal dynamic viscosities, shear rate 1.6 and bulk rate 1.0,
 sigma = 0.005, beta = 0.7, +-1e-6 counter noise on the populations, FP32
@@ -8,25 +8,33 @@ storage and arithmetic.  A step is one full time update of every node
 (pull-streaming, moments, interface stencils, collision, recolouring).  The
 FP32 lines run the compact schedule (the state between the steps of a call
 held as each node's 17-value post-collision state); `--schedule 0` runs the
-population schedule.
+population schedule.  The K timed steps are one cglbm_step call with HIP
+events around every launch; `repeats` times four more calls of K steps and
+reports the median, `graph_mlups` the same update as replays of the
+captured graph cglbm_step uses by default.
 
 Prints ONE JSON line: MLUPS of the timed steps, the roofline of the dominant
 kernel (against HBM: algorithmic bytes per launch / average launch time from
-HIP events recorded on the launch stream during the timed region; against
-the FP32 vector issue rate: the committed SQ_INSTS_VALU count per launch x 64
-lanes / the same time; reported against the closer ceiling) and the FP64 CPU
-oracle timed on a bounded sample of the same workload.  `forms` reports, on
-the same workload and step counts, the FP16/BF16-shifted and mass-exact FP32
-storage (with their difference to the FP32 run as a proxy error), the
-96-box batched workload, the 32^3 static droplet, the Rayleigh-Taylor case
-at the paper's size (Models D and A), the translating droplet's
-deformation per equilibrium model, the two-dimensional model of App. A on a
-4096^2 droplet field (d2q9; d2q9_fp16 and d2q9_bf16 with 16-bit shifted
-storage), the main workload in the in-place layout (inplace) and Table II's
-surface tensions (table2).  The timed region
-launches every kernel directly (HIP events around each launch); after it,
-`graph_mlups` times the same update as replays of the captured two-step
-graph that cglbm_step uses by default.
+the HIP events; against the FP32 vector issue rate: the committed
+SQ_INSTS_VALU count per launch x 64 lanes / the same time; reported against
+the closer ceiling) and the FP64 CPU oracle timed on a bounded sample of the
+same workload (all host threads and one thread, with the host's CPU model).
+
+`forms` reports, beside the main line:
+  * the population schedule and the other storage formats on the same
+    workload (FP16 / BF16 with the constant or the colour-fraction-scaled
+    shift, FP32 mass-exact), each with its difference to the FP32 run after
+    the same steps and its per-colour mass drift after 5000 steps;
+  * the 512^3 density-ratio-1000 droplets (c3) in FP32, FP16 and BF16 with
+    either shift, and the walled 768x384x384 head-on collision (c5) in FP32
+    and FP16, at their own sizes;
+  * the 96-box batch, the 32^3 static droplet, the in-place layout, the
+    Rayleigh-Taylor case at the paper's size (Models D and A), the
+    translating droplet's deformation per equilibrium model, the D2Q9 model
+    of App. A on a 4096^2 droplet field (FP32, FP16, BF16) and Table II;
+  * `parity`: for every configuration a reduced-size run against the FP64
+    oracle on the same seeded inputs (e_rho, e_u, e_phi max and L2, with the
+    bar each format is held to and pass / fail).
 """
 import argparse
 import json
@@ -43,9 +51,17 @@ import workloads as WL  # noqa: E402  (seeded inputs; numpy only)
 
 HBM_PEAK_GBS = 8000.0
 GRAPH_STEPS = 500   # steps of the graph-replay run after the timed region
-STORAGES = {"fp32": 0, "fp16": 1, "bf16": 2, "fp32x": 3, "fp32p": 4}
+REPEATS = 5         # calls of K timed steps (the first is `value`)
+DRIFT_STEPS = 5000  # steps after which the C2 forms report per-colour mass drift
+BIG_STEPS = 500     # timed steps of each format at the 512^3 and 768x384x384 sizes
+STORAGES = {"fp32": 0, "fp16": 1, "bf16": 2, "fp32x": 3, "fp32p": 4, "fp16c": 5, "bf16c": 6}
 DTYPE = {"fp32": "f32", "fp16": "f16 storage, f32 arithmetic", "bf16": "bf16 storage, f32 arithmetic",
-         "fp32x": "f32", "fp32p": "f32"}
+         "fp32x": "f32", "fp32p": "f32", "fp16c": "f16 storage, f32 arithmetic",
+         "bf16c": "bf16 storage, f32 arithmetic"}
+SIXTEEN = ("fp16", "bf16", "fp16c", "bf16c")
+# unit roundoff of each storage format (round to nearest even)
+UNIT_ROUNDOFF = {"fp32": 2.0 ** -24, "fp32p": 2.0 ** -24, "fp32x": 2.0 ** -24,
+                 "fp16": 2.0 ** -11, "fp16c": 2.0 ** -11, "bf16": 2.0 ** -8, "bf16c": 2.0 ** -8}
 
 
 def kernel_bytes(storage: str):
@@ -55,6 +71,8 @@ def kernel_bytes(storage: str):
     else:
         s = 4 if storage == "fp32x" else 2
         pops, aux_rho = 52 * s + 2 * 8, 2 * 8      # moving populations + FP64 rest
+        if storage in ("fp16c", "bf16c"):
+            pops += 2                              # the node's stored colour fraction
     return {
         "pull": pops + 11 * 4 + aux_rho,           # populations in, 11 local moments out
         "interface": (2 + 3) * 4 + 9 * 4,          # rho_r, rho_b, j in; n, F, Q out
@@ -76,8 +94,9 @@ def d2q9_bytes(storage: str) -> int:
 # Compact schedule (FP32, periodic boxes): per node the pull reads the 17
 # floats of the compact post-collision state and writes the 11 moments; the
 # fused kernel reads the moments and writes the compact state; once per
-# call the emission reads the compact state and stores the populations.
-COMPACT_BYTES = {"pull": 17 * 4 + 11 * 4, "fused": 11 * 4 + 17 * 4, "collide": 17 * 4 + 54 * 4}
+# call the population pull starts it and the emission (17 in, 54 out) ends it.
+COMPACT_BYTES = {"pull": 17 * 4 + 11 * 4, "fused": 11 * 4 + 17 * 4,
+                 "pull_first": 54 * 4 + 11 * 4, "emit": 17 * 4 + 54 * 4}
 
 # storage format of the D2Q9 step kernel's template argument
 SNAMES = {"fp32": "StoreF32P", "fp32p": "StoreF32P", "fp16": "StoreF16", "bf16": "StoreBF16",
@@ -87,7 +106,7 @@ SNAMES = {"fp32": "StoreF32P", "fp32p": "StoreF32P", "fp16": "StoreF16", "bf16":
 def step_bytes(storage: str) -> int:
     """The whole step's algorithmic bytes: every population read and written
     once, 2 * 54 * (bytes per stored population)."""
-    return 2 * 54 * (2 if storage in ("fp16", "bf16") else 4)
+    return 2 * 54 * (2 if storage in SIXTEEN else 4)
 
 
 COUNTERS = os.path.join(ROOT, "profiles", "step_kernels_translating_droplet_256_counters.md")
@@ -133,6 +152,10 @@ def measured_valu(kernel: str):
     return None
 
 
+DEFAULT_FORMS = ("fp32_population,fp16,bf16,fp16c,bf16c,fp32x,c3,c5,batched,inplace,small,rti,"
+                 "galilean,d2q9,d2q9_fp16,d2q9_bf16,table2,parity")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,9 +163,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--size", type=int, default=256, help="box edge (default 256)")
     ap.add_argument("--storage", default="fp32", choices=sorted(STORAGES))
-    ap.add_argument("--forms", default="fp16,bf16,fp32x,batched,inplace,small,rti,galilean,d2q9,"
-                    "d2q9_fp16,d2q9_bf16,table2",
-                    help="extra forms on the same workload ('' for none)")
+    ap.add_argument("--forms", default=DEFAULT_FORMS, help="extra forms ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--schedule", type=int, default=None, choices=(0, 1, 2),
@@ -166,13 +187,32 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes_each_way": n * 4, "launches": 5}))
 
 
-def cpu_baseline(w, seconds):
-    """FP64 oracle on a 64^3 window of the same workload (centred on the
-    droplet's leading edge, noise keyed by the full box), stepped until about
-    `seconds` of CPU work has elapsed."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_params(box):
+    import oracle as O
+    return O.Params(nx=box.nx, ny=box.ny, nz=box.nz, rho0_r=box.rho0_r, rho0_b=box.rho0_b,
+                    alpha_r=box.alpha_r, alpha_b=box.alpha_b, nu_r=box.nu_r, nu_b=box.nu_b,
+                    sigma=box.sigma, beta=box.beta, walls=box.walls,
+                    body_force=tuple(box.body_force), model=box.model, use_q=box.use_q,
+                    gravity=tuple(box.gravity), rho_ref=box.rho_ref,
+                    omega=(box.omega_hi[0], 1.0, box.omega_bulk) + tuple(box.omega_hi[1:]))
+
+
+def _window_rate(w, n, seconds, max_steps):
+    """Oracle MLUPS on an n^3 window of workload w (noise keyed by the full
+    box), stepped until about `seconds` of CPU work has elapsed."""
     import oracle as O
     box = w.box
-    n = 64
     c = [int(v) for v in w.centres[0]]
     off = (c[0] + int(w.radii[0]) - n // 2, c[1] - n // 2, c[2] - n // 2)
     sl = [np.arange(o, o + n) % N for o, N in zip(off, (box.nx, box.ny, box.nz))]
@@ -180,27 +220,65 @@ def cpu_baseline(w, seconds):
     rr = w.rho_r[idx].astype(np.float64)
     rb = w.rho_b[idx].astype(np.float64)
     u = np.stack([w.u[a][idx] for a in range(3)]).astype(np.float64)
-    P = O.Params(nx=n, ny=n, nz=n, rho0_r=box.rho0_r, rho0_b=box.rho0_b, alpha_r=box.alpha_r,
-                 alpha_b=box.alpha_b, nu_r=box.nu_r, nu_b=box.nu_b, sigma=box.sigma,
-                 beta=box.beta, omega=(1.0, 1.0, box.omega_bulk) + (1.0,) * 8)
+    import dataclasses
+    P = _oracle_params(dataclasses.replace(box, nx=n, ny=n, nz=n))
     f = O.init_window(P, rr, rb, u, (box.nx, box.ny, box.nz), off, seed=w.seed, amp=w.noise)
     steps, t0 = 0, time.perf_counter()
     while True:
         O.step(P, f, 1)
         steps += 1
         el = time.perf_counter() - t0
-        if el >= seconds or steps >= 200:
+        if el >= seconds or steps >= max_steps:
             break
-    return {"value": n ** 3 * steps / el / 1e6, "unit": "MLUPS", "cores": O.num_threads(),
-            "kind": "oracle",
+    return n ** 3 * steps / el / 1e6, steps, el
+
+
+def cpu_baseline(w, seconds):
+    """FP64 oracle on a 64^3 window of the main workload (centred on the
+    droplet's leading edge, noise keyed by the full box): all host threads
+    for about `seconds`, one thread for about a third of that; and the full
+    32^3 static droplet of 200 steps on all threads."""
+    import oracle as O
+    threads = O.num_threads()
+    v, steps, el = _window_rate(w, 64, seconds, 200)
+    O.set_num_threads(1)
+    v1, steps1, el1 = _window_rate(w, 64, seconds / 3.0, 50)
+    O.set_num_threads(threads)
+    s = WL.static_droplet()
+    P = _oracle_params(s.box)
+    f = O.init(P, s.rho_r.astype(np.float64), s.rho_b.astype(np.float64), s.u.astype(np.float64))
+    t0 = time.perf_counter()
+    O.step(P, f, s.steps)
+    el_c1 = time.perf_counter() - t0
+    box = w.box
+    return {"value": v, "unit": "MLUPS", "cores": threads, "kind": "oracle",
             "sample": "%d steps of a 64^3 window of the %dx%dx%d workload (FP64, plain "
-                      "definitions), %.1f s" % (steps, box.nx, box.ny, box.nz, el)}
+                      "definitions), %.1f s on %d threads" % (steps, box.nx, box.ny, box.nz, el,
+                                                              threads),
+            "cpu_model": cpu_model(),
+            "one_thread": {"value": v1, "unit": "MLUPS", "steps": steps1, "seconds": round(el1, 2)},
+            "static_droplet_32_full": {"steps": s.steps, "seconds": round(el_c1, 3),
+                                       "mlups": s.box.nodes * s.steps / el_c1 / 1e6,
+                                       "threads": threads}}
 
 
-def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=False,
-             lattice="d3q27", inplace=False, schedule=None):
-    """Initialise, autotune, time `steps` steps; return throughput, per-kernel
-    event timings and (optionally) the final fields of box 0."""
+def _time_steps(sim, steps):
+    import torch
+    sim.profile_begin(8 * steps + 16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dt, sim.profile_end()
+
+
+def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=None,
+             lattice="d3q27", inplace=False, schedule=None, repeats=1, drift_steps=0):
+    """Initialise, autotune, time `steps` steps (and `repeats - 1` more calls
+    of as many); return throughput, per-kernel event timings, the per-colour
+    mass drift, and (keep_fields "host" or "device") the fields of box 0
+    after the timed steps."""
     import torch
     import paper_2309_07801_amd as pkg
     sim = pkg.Simulation([pkg.box_params_of(w.box) for w in workloads],
@@ -224,21 +302,36 @@ def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=False,
     sim.step(max(warmup - 2, 0))  # also captures the step graph
     torch.cuda.synchronize()
     # timed region: direct launches with HIP events around every kernel
-    sim.profile_begin(4 * steps)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = sim.profile_end()
-    dt = t1 - t0
+    dt, prof = _time_steps(sim, steps)
+    out_fields = None
+    if keep_fields:
+        names = ("rho_r", "rho_b", "phi", "ux", "uy", "uz")
+        f = sim.moments(0, names)
+        out_fields = {k: (v.clone() if keep_fields == "device" else v.cpu().numpy())
+                      for k, v in f.items()}
+        del f
+    mlups = [fluid * steps / dt / 1e6]
+    for _ in range(repeats - 1):
+        dtr, pr = _time_steps(sim, steps)
+        mlups.append(fluid * steps / dtr / 1e6)
+        for k, (ms, cnt) in pr.items():
+            prof[k] = (prof[k][0] + ms, prof[k][1] + cnt)
     # the same update as replays of the captured two-step graph
     ngraph = min(steps, GRAPH_STEPS)
     t2 = time.perf_counter()
     sim.step(ngraph)
     torch.cuda.synchronize()
     graph_mlups = fluid * ngraph / (time.perf_counter() - t2) / 1e6
+    done = 2 + max(warmup - 2, 0) + steps * repeats + ngraph
     d1 = sim.reduce()
+    drift_out = None
+    if drift_steps > done:
+        sim.step(drift_steps - done)
+        d2 = sim.reduce()
+        m0, m2 = d0[:, :2].sum(axis=0), d2[:, :2].sum(axis=0)
+        drift_out = {"steps": drift_steps,
+                     "red": float((m2[0] - m0[0]) / m0[0]), "blue": float((m2[1] - m0[1]) / m0[1]),
+                     "nonfinite": int(d2[:, 12].sum())}
     if lattice != "d3q27":
         kb = {"fused": d2q9_bytes(storage)}
     elif sim.schedule() == 2:
@@ -246,24 +339,97 @@ def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=False,
     else:
         kb = kernel_bytes(storage)
     kern = {}
+    tot = dt * repeats
     for k, (ms, cnt) in prof.items():
         if cnt:
             avg = ms / cnt / 1e3
-            kern[k] = {"avg_ms": avg * 1e3, "gbs": kb[k] * fluid / avg / 1e9, "share": ms / 1e3 / dt}
+            kern[k] = {"avg_ms": avg * 1e3, "gbs": kb[k] * fluid / avg / 1e9 if k in kb else None,
+                       "launches": cnt, "share": ms / 1e3 / tot}
     m0 = d0[:, :2].sum(axis=0)
     m1 = d1[:, :2].sum(axis=0)
-    out = {"mlups": fluid * steps / dt / 1e6, "ms_per_step": dt / steps * 1e3, "dt": dt,
-           "graph_mlups": graph_mlups,
+    out = {"mlups": mlups[0], "mlups_repeats": mlups, "mlups_median": float(np.median(mlups)),
+           "ms_per_step": dt / steps * 1e3, "dt": dt, "graph_mlups": graph_mlups,
            "fluid": fluid, "kernels": kern, "variant": var, "autotune_ms": tune_ms,
            "schedule": ("fused", "three kernels", "compact")[sim.schedule()],
            "mass_drift": [float((m1[0] - m0[0]) / m0[0]), float((m1[1] - m0[1]) / m0[1])],
+           "mass_drift_steps": done, "mass_drift_long": drift_out,
            "nonfinite": int(d1[:, 12].sum()), "steps": steps,
-           "pop_buffer_bytes": sim.pop_a.numel() * (1 if inplace else 2), "compact_variant": cvar}
-    if keep_fields:
-        out["fields"] = {k: v.cpu().numpy() for k, v in
-                         sim.moments(0, ("rho_r", "rho_b", "phi", "ux", "uy", "uz")).items()}
+           "pop_buffer_bytes": sim.pop_a.numel() * (1 if inplace else 2), "compact_variant": cvar,
+           "fields": out_fields}
     sim.close()
     del sim
+    torch.cuda.empty_cache()
+    return out
+
+
+def _kern_round(kern):
+    return {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+            for k, v in kern.items()}
+
+
+def proxy_errors(g, ref, u_ref):
+    """Difference of a run to the FP32 run after the same steps (the survey's
+    proxy for full-size runs the oracle cannot afford); fields as numpy
+    arrays or device tensors."""
+    def np_(x):
+        return x.double().cpu().numpy() if hasattr(x, "cpu") else np.asarray(x, np.float64)
+    if hasattr(g["rho_r"], "cpu"):
+        # device tensors: norms on the device, in FP64
+        rho_g = (g["rho_r"].double() + g["rho_b"].double())
+        rho_f = (ref["rho_r"].double() + ref["rho_b"].double())
+        rel = (rho_g - rho_f).abs() / rho_f
+        du = ((g["ux"].double() - ref["ux"].double()) ** 2 + (g["uy"].double() - ref["uy"].double()) ** 2
+              + (g["uz"].double() - ref["uz"].double()) ** 2).sqrt()
+        return {"e_rho": float(rel.max()), "e_u": float(du.max() / u_ref),
+                "e_phi": float((g["phi"].double() - ref["phi"].double()).abs().max()),
+                "e_rho_l2": float((rel ** 2).mean().sqrt()),
+                "e_u_l2": float((du ** 2).mean().sqrt() / u_ref)}
+    g = {k: np_(v) for k, v in g.items()}
+    ref = {k: np_(v) for k, v in ref.items()}
+    rho_g, rho_f = g["rho_r"] + g["rho_b"], ref["rho_r"] + ref["rho_b"]
+    du = np.sqrt((g["ux"] - ref["ux"]) ** 2 + (g["uy"] - ref["uy"]) ** 2 + (g["uz"] - ref["uz"]) ** 2)
+    return {"e_rho": float((np.abs(rho_g - rho_f) / rho_f).max()),
+            "e_u": float(du.max() / u_ref), "e_phi": float(np.abs(g["phi"] - ref["phi"]).max()),
+            "e_rho_l2": float(np.sqrt((((rho_g - rho_f) / rho_f) ** 2).mean())),
+            "e_u_l2": float(np.sqrt((du ** 2).mean()) / u_ref)}
+
+
+def storage_form(r, storage, ref_fields=None, u_ref=None):
+    """One storage form's throughput line."""
+    sbf = step_bytes(storage)
+    out = {"storage": storage, "mlups": round(r["mlups"], 1),
+           "mlups_median": round(r["mlups_median"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+           "graph_mlups": round(r["graph_mlups"], 1), "schedule": r["schedule"],
+           "step_roofline_frac": round(r["mlups"] * 1e6 * sbf / (HBM_PEAK_GBS * 1e9), 4),
+           "step_bytes_per_node": sbf, "kernels": _kern_round(r["kernels"]),
+           "mass_drift": r["mass_drift"], "mass_drift_steps": r["mass_drift_steps"],
+           "nonfinite": r["nonfinite"]}
+    if r["mass_drift_long"]:
+        out["mass_drift_5000"] = r["mass_drift_long"]
+    if ref_fields is not None and r["fields"] is not None:
+        out["vs_fp32_after_same_steps"] = proxy_errors(r["fields"], ref_fields, u_ref)
+    return out
+
+
+def big_form(label, w, storages, steps, warmup, u_ref):
+    """A configuration at its own size in several storage formats, each
+    compared with the FP32 run after the same steps (on the device)."""
+    import torch
+    box = w.box
+    out = {"workload": label, "nodes": box.fluid_nodes(), "steps": steps}
+    ref = None
+    for st in storages:
+        r = run_form([w], st, steps, warmup, keep_fields="device",
+                     schedule=2 if st in ("fp32", "fp32p") else None)
+        out[st] = storage_form(r, st, ref, u_ref)
+        if st == "fp32":
+            ref = r["fields"]
+        else:
+            del r["fields"]
+        torch.cuda.empty_cache()
+        print("bench:   %s %s %.1f MLUPS" % (label.split(",")[0], st, r["mlups"]), file=sys.stderr,
+              flush=True)
+    del ref
     torch.cuda.empty_cache()
     return out
 
@@ -386,15 +552,103 @@ def deformation(phi):
     return float((ev[-1] - ev[0]) / (ev[-1] + ev[0]))
 
 
-def proxy_errors(g, ref, u_ref):
-    """Difference of a run to the FP32 run after the same steps (the survey's
-    proxy for full-size runs the oracle cannot afford)."""
-    rho_g, rho_f = g["rho_r"] + g["rho_b"], ref["rho_r"] + ref["rho_b"]
-    du = np.sqrt((g["ux"] - ref["ux"]) ** 2 + (g["uy"] - ref["uy"]) ** 2 + (g["uz"] - ref["uz"]) ** 2)
-    return {"e_rho": float((np.abs(rho_g - rho_f) / rho_f).max()),
-            "e_u": float(du.max() / u_ref), "e_phi": float(np.abs(g["phi"] - ref["phi"]).max()),
-            "e_rho_l2": float(np.sqrt((((rho_g - rho_f) / rho_f) ** 2).mean())),
-            "e_u_l2": float(np.sqrt((du ** 2).mean()) / u_ref)}
+# ---------------------------------------------------------------------------
+# Parity against the FP64 oracle at reduced sizes, one run per configuration
+# ---------------------------------------------------------------------------
+
+# FP32 storage: 1e-5, or 2 gamma 2^-24 at a density ratio gamma where that
+# is larger (at a node of the light phase the heavy colour's FP32 values
+# carry rounding of 2^-24 of the heavy density).  16-bit storage: the error
+# its rounding alone produces is of the order of the unit roundoff u_s times
+# the stored deviations; the bar is 8 u_s (e_rho, e_phi) and 32 u_s (e_u,
+# which divides a momentum error by a velocity scale 10-25 times smaller
+# than the populations), independent of the step count.
+FP32_BAR = 1e-5
+
+
+def format_bar(storage, gamma=1.0):
+    if storage in ("fp32", "fp32p", "fp32x"):
+        b = max(FP32_BAR, 2.0 * max(gamma, 1.0 / gamma) * 2.0 ** -24)
+        return {"rho": b, "u": b, "phi": b}
+    us = UNIT_ROUNDOFF[storage]
+    return {"rho": 8 * us, "u": 32 * us, "phi": 8 * us}
+
+
+def _gpu_fields(ws, storage, steps, schedule, seed, noise):
+    import torch
+    import paper_2309_07801_amd as pkg
+    sim = pkg.Simulation([pkg.box_params_of(w.box) for w in ws], [w.rho_r for w in ws],
+                         [w.rho_b for w in ws], [w.u for w in ws], seed=seed, noise=noise,
+                         storage=STORAGES[storage])
+    if schedule is not None:
+        sim.set_schedule(schedule)
+    sim.step(steps)
+    out = [{k: v.double().cpu().numpy() for k, v in sim.moments(b).items()} for b in range(len(ws))]
+    torch.cuda.synchronize()
+    sim.close()
+    return out
+
+
+def _errors(g, o, box, u_ref):
+    m = np.ones(box.shape, bool)
+    if box.walls & 1:
+        m[:, 0, :] = m[:, -1, :] = False
+    if box.walls & 2:
+        m[0, :, :] = m[-1, :, :] = False
+    rho_g, rho_o = g["rho_r"] + g["rho_b"], o["rho_r"] + o["rho_b"]
+    rel = (np.abs(rho_g - rho_o) / rho_o)[m]
+    du = np.sqrt((g["ux"] - o["ux"]) ** 2 + (g["uy"] - o["uy"]) ** 2 + (g["uz"] - o["uz"]) ** 2)[m]
+    return {"e_rho": float(rel.max()), "e_u": float(du.max() / u_ref),
+            "e_phi": float(np.abs(g["phi"] - o["phi"])[m].max()),
+            "e_rho_l2": float(np.sqrt((rel ** 2).mean())), "e_u_l2": float(np.sqrt((du ** 2).mean()) / u_ref)}
+
+
+def parity_form():
+    """Every configuration at a reduced size against the FP64 oracle on the
+    same seeded inputs: e_rho (relative to the oracle's density), e_u
+    (relative to U_ref), e_phi (absolute), max and L2 over fluid nodes."""
+    import oracle as O
+    cases = [
+        ("c1", "32^3 static droplet (the configuration itself)", [WL.static_droplet()], 200, 0.01,
+         (("fp32", 2), ("fp32", 0))),
+        ("c2", "translating droplet at 64^3, R 8", [WL.translating_droplet(n=64, R=8.0)], 200, 0.05,
+         (("fp32", 2), ("fp32", 0), ("fp32x", None), ("fp16", None), ("fp16c", None))),
+        ("c3", "density-ratio-1000 droplets at 96^3, R U[4, 9]",
+         [WL.sheared_droplets(n=96, count=8, rmin=4.0, rmax=9.0)], 100, 0.04,
+         (("fp32", 2), ("fp16", None), ("bf16", None), ("fp16c", None), ("bf16c", None))),
+        ("c4", "the four smallest boxes of the 96-box batch",
+         sorted(WL.batched_boxes(), key=lambda x: x.box.nodes)[:4], 200, 0.01,
+         (("fp32p", 2),)),
+        ("c5", "walled head-on collision at 192x96x96, R 12 (We, Re kept)",
+         [WL.head_on_collision(nx=192, ny=96, nz=96, R=12.0)], 100, 0.05,
+         (("fp32", 2), ("fp16", None), ("fp16c", None))),
+    ]
+    out = {}
+    for key, label, ws, steps, u_ref, runs in cases:
+        t0 = time.perf_counter()
+        orc = []
+        for b, w in enumerate(ws):
+            P = _oracle_params(w.box)
+            f = O.init(P, w.rho_r.astype(np.float64), w.rho_b.astype(np.float64),
+                       w.u.astype(np.float64), seed=w.seed, amp=w.noise, box=b)
+            O.step(P, f, steps)
+            orc.append(O.fields(P, f))
+        t_orc = time.perf_counter() - t0
+        entry = {"workload": label, "steps": steps, "u_ref": u_ref, "oracle_seconds": round(t_orc, 1)}
+        for st, sched in runs:
+            g = _gpu_fields(ws, st, steps, sched, ws[0].seed, ws[0].noise)
+            errs = [_errors(gb, ob, w.box, u_ref) for gb, ob, w in zip(g, orc, ws)]
+            e = {k: max(x[k] for x in errs) for k in errs[0]}
+            bar = format_bar(st, max(max(w.box.rho0_r / w.box.rho0_b, w.box.rho0_b / w.box.rho0_r)
+                                     for w in ws))
+            e["bar"] = bar
+            e["status"] = "pass" if (e["e_rho"] <= bar["rho"] and e["e_u"] <= bar["u"]
+                                     and e["e_phi"] <= bar["phi"]) else "fail"
+            name = st + ("_" + ("population", "three_kernel", "compact")[sched] if sched is not None else "")
+            entry[name] = e
+        out[key] = entry
+        print("bench:   parity %s done (oracle %.1f s)" % (key, t_orc), file=sys.stderr, flush=True)
+    return out
 
 
 def main():
@@ -418,13 +672,15 @@ def main():
     sched = args.schedule
     if sched is None and args.storage in ("fp32", "fp32p"):
         sched = 2  # the compact schedule serves this periodic FP32 workload
+    want_fields = any(f in STORAGES for f in forms_req)
     main_r = run_form([w], args.storage, args.steps, args.warmup, args.variant,
-                      keep_fields=any(f in STORAGES for f in forms_req), schedule=sched)
+                      keep_fields="device" if want_fields else None, schedule=sched,
+                      repeats=REPEATS, drift_steps=DRIFT_STEPS if forms_req else 0)
     fluid = main_r["fluid"]
-    kern = {k: v for k, v in main_r["kernels"].items() if k != "collide" or main_r["schedule"] != "compact"}
+    compact = main_r["schedule"] == "compact"
+    kern = {k: v for k, v in main_r["kernels"].items() if k in ("pull", "fused")}
     dom = max(kern, key=lambda k: kern[k]["share"])
     var = main_r["variant"]
-    compact = main_r["schedule"] == "compact"
     geo = (var["tx"], var["ty"], var["zc"], var["min_waves"])
     if compact:
         cv = main_r["compact_variant"]
@@ -442,7 +698,8 @@ def main():
     hbm_frac = kern[dom]["gbs"] / HBM_PEAK_GBS
     roof = {"bound": "hbm", "achieved": round(kern[dom]["gbs"], 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(hbm_frac, 4), "traffic": traffic,
-            "traffic_unit": "bytes per launch", "algorithmic_bytes": kb[dom] * fluid, "kernel": kname}
+            "traffic_unit": "bytes per launch", "algorithmic_bytes": kb[dom] * fluid, "kernel": kname,
+            "launches_timed": kern[dom]["launches"]}
     if valu is not None:
         # VALU issue rate of the dominant kernel: its counted wave64 VALU
         # instructions per launch x 64 lanes / the live mean launch time
@@ -455,7 +712,7 @@ def main():
                     "hbm": {"achieved": round(kern[dom]["gbs"], 1), "peak": HBM_PEAK_GBS,
                             "unit": "GB/s", "frac": round(hbm_frac, 4),
                             "algorithmic_bytes": kb[dom] * fluid},
-                    "kernel": kname}
+                    "kernel": kname, "launches_timed": kern[dom]["launches"]}
         else:
             roof["valu_tops"] = round(tops, 2)
     line = {
@@ -476,50 +733,66 @@ def main():
                    "nodes": fluid, "storage": args.storage, "schedule": main_r["schedule"]},
         "roofline": roof,
         "step_roofline_frac": round(main_r["mlups"] * 1e6 * sb / (HBM_PEAK_GBS * 1e9), 4),
+        "repeats": {"calls": REPEATS, "steps_each": args.steps,
+                    "mlups": [round(v, 1) for v in main_r["mlups_repeats"]],
+                    "median_mlups": round(main_r["mlups_median"], 1)},
         "graph_mlups": round(main_r["graph_mlups"], 1),
         "step_bytes_per_node": sb,
         "step_bytes_moved_per_node": (COMPACT_BYTES["pull"] + COMPACT_BYTES["fused"]) if compact
                                      else kernel_bytes(args.storage)["pull"] + kernel_bytes(args.storage)["fused"],
-        "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()}
-                    for k, v in main_r["kernels"].items()},
+        "kernels": _kern_round(main_r["kernels"]),
         "fused_variant": var,
         "compact_variant": main_r["compact_variant"],
         "schedule": main_r["schedule"],
         "autotune_ms": [round(m, 4) for m in main_r["autotune_ms"]],
         "mass_drift": main_r["mass_drift"],
+        "mass_drift_steps": main_r["mass_drift_steps"],
         "nonfinite": main_r["nonfinite"],
     }
+    if main_r["mass_drift_long"]:
+        line["mass_drift_5000"] = main_r["mass_drift_long"]
     print("bench: main line %.1f MLUPS (%.1f s)" % (main_r["mlups"], time.perf_counter() - T0),
           file=sys.stderr, flush=True)
     forms = {}
     u_ref = 0.05
+    ref_fields = main_r["fields"]
     for f in forms_req:
         if f in STORAGES:
-            r = run_form([w], f, args.steps, args.warmup, args.variant, keep_fields=True)
-            sbf = step_bytes(f)
-            forms[f] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
-                        "graph_mlups": round(r["graph_mlups"], 1),
-                        "schedule": r["schedule"],
-                        "step_roofline_frac": round(r["mlups"] * 1e6 * sbf / (HBM_PEAK_GBS * 1e9), 4),
-                        "step_bytes_per_node": sbf,
-                        "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()}
-                                    for k, v in r["kernels"].items()},
-                        "mass_drift": r["mass_drift"], "nonfinite": r["nonfinite"],
-                        "vs_fp32_after_same_steps": proxy_errors(r["fields"], main_r["fields"], u_ref)}
+            r = run_form([w], f, args.steps, args.warmup, args.variant, keep_fields="device",
+                         drift_steps=DRIFT_STEPS)
+            forms[f] = storage_form(r, f, ref_fields, u_ref)
+            del r["fields"]
+        elif f == "fp32_population":
+            r = run_form([w], "fp32", args.steps, args.warmup, args.variant, schedule=0,
+                         drift_steps=DRIFT_STEPS)
+            forms[f] = storage_form(r, "fp32")
+        elif f == "c3":
+            w3 = WL.sheared_droplets()
+            forms["c3"] = big_form("512^3 periodic, 8 droplets R U[20,48], density ratio 1000, "
+                                   "sinusoidal shear 0.04", w3, ("fp32", "fp16", "bf16", "fp16c",
+                                                                 "bf16c"),
+                                   min(args.steps, BIG_STEPS), args.warmup, 0.04)
+            del w3
+        elif f == "c5":
+            w5 = WL.head_on_collision()
+            forms["c5"] = big_form("768x384x384, walls y/z, head-on collision of two R 48 droplets, "
+                                   "relative velocity 0.1, density ratio 10, Re 5000, We 50", w5,
+                                   ("fp32", "fp16", "fp16c"), min(args.steps, BIG_STEPS),
+                                   args.warmup, 0.05)
+            del w5
         elif f == "batched":
             boxes = WL.batched_boxes()
             steps_b = min(args.steps, 1000)
             r = run_form(boxes, "fp32p", steps_b, args.warmup, args.variant, schedule=2)
             forms["batched"] = {"workload": "96 periodic boxes, edges U{24..128}, density ratio "
                                             "in {1,10,100}, FP32 (colour-pair layout), compact schedule",
-                                "nodes": r["fluid"],
-                                "steps": steps_b, "mlups": round(r["mlups"], 1),
+                                "nodes": r["fluid"], "steps": steps_b, "mlups": round(r["mlups"], 1),
+                                "mlups_median": round(r["mlups_median"], 1),
                                 "ms_per_step": round(r["ms_per_step"], 4),
                                 "graph_mlups": round(r["graph_mlups"], 1),
-                                "schedule": r["schedule"],
+                                "schedule": r["schedule"], "compact_variant": r["compact_variant"],
                                 "step_roofline_frac": round(r["mlups"] * 1e6 * 432 / (HBM_PEAK_GBS * 1e9), 4),
-                                "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()}
-                                            for k, v in r["kernels"].items()},
+                                "kernels": _kern_round(r["kernels"]),
                                 "mass_drift": r["mass_drift"], "nonfinite": r["nonfinite"]}
         elif f == "inplace":
             r = run_form([w], args.storage, args.steps, args.warmup, args.variant, inplace=True)
@@ -530,8 +803,7 @@ def main():
                                 "ms_per_step": round(r["ms_per_step"], 4),
                                 "graph_mlups": round(r["graph_mlups"], 1),
                                 "schedule": r["schedule"],
-                                "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()}
-                                            for k, v in r["kernels"].items()},
+                                "kernels": _kern_round(r["kernels"]),
                                 "mass_drift": r["mass_drift"], "nonfinite": r["nonfinite"]}
         elif f == "small":
             ws = WL.static_droplet()
@@ -554,8 +826,31 @@ def main():
             forms[f] = d2q9_form(min(args.steps, 2000), args.warmup, f[5:])
         elif f == "table2":
             forms["table2"] = table2_form()
+        elif f == "parity":
+            forms["parity"] = parity_form()
         print("bench: form %s done (%.1f s)" % (f, time.perf_counter() - T0), file=sys.stderr,
               flush=True)
+    del ref_fields
+    main_r["fields"] = None
+    if "parity" in forms:
+        # each storage form carries the oracle verdict of its format on the
+        # reduced-size run of the same configuration
+        par = forms["parity"]
+        for key, st in (("fp16", "fp16"), ("bf16", "bf16"), ("fp16c", "fp16c"), ("bf16c", "bf16c"),
+                        ("fp32x", "fp32x")):
+            if key in forms:
+                for cfg in ("c2", "c3"):
+                    if st in par.get(cfg, {}):
+                        forms[key]["oracle_parity_" + cfg] = {
+                            k: par[cfg][st][k] for k in ("e_rho", "e_u", "e_phi", "status")}
+        for cfg in ("c3", "c5"):
+            for st in SIXTEEN + ("fp32",):
+                name = st if st != "fp32" else "fp32_compact"
+                if cfg in forms and st in forms[cfg] and name in par.get(cfg, {}):
+                    forms[cfg][st]["oracle_parity"] = {
+                        k: par[cfg][name][k] for k in ("e_rho", "e_u", "e_phi", "status")}
+        line["parity_status"] = {cfg: {k: v["status"] for k, v in e.items() if isinstance(v, dict)}
+                                 for cfg, e in par.items()}
     if forms:
         line["forms"] = forms
     if not args.no_cpu_baseline:

@@ -117,9 +117,14 @@ typedef struct {
  *   CGLBM_BF16_SHIFT  the same with bfloat16.
  *   CGLBM_FP32_EXACT  moving directions in float, rest populations in FP64.
  *   CGLBM_FP16_CSHIFT as CGLBM_FP16_SHIFT, with each moving population stored
- *                     as f^k_i - c_k s^k_i: the shift scaled by the colour
- *                     fraction c_k = rho_k / rho of the node that wrote it
- *                     (red c_r, blue 1 - c_r; s^k_i unrounded), which is
+ *                     as (f^k_i - c_k s^k_i) 2^-e_k: the shift scaled by the
+ *                     colour fraction c_k = rho_k / rho of the node that
+ *                     wrote it (red c_r, blue 1 - c_r; s^k_i unrounded), the
+ *                     difference scaled exactly by a power of two,
+ *                     e_k = floor(log2 rho_k^0) - 10, which keeps a colour's
+ *                     small values (a light phase, the other phase's tail at
+ *                     an interface) in the normal range of half down to about
+ *                     6e-8 rho_k^0; the fraction is
  *                     stored per node as one more 16-bit plane (c_r in half,
  *                     correctly rounded from rho_r / rho: 1 and 0 exactly in
  *                     the pure phases).  A pull decodes each population with
@@ -128,8 +133,7 @@ typedef struct {
  *                     colour exact zeros, as with the constant shift; at the
  *                     interface each colour stores its deviation from its
  *                     share of the equilibrium instead of a remainder of the
- *                     order of s (the colour-scaled reading of the "shifted
- *                     by their lattice weights" storage of Sec. II).  Solid
+ *                     order of s.  Solid
  *                     wall nodes re-encode the populations they reverse with
  *                     the fraction of their wall-normal fluid neighbour.
  *                     D3Q27 only.
@@ -295,11 +299,14 @@ int cglbm_load_state(cglbm_handle *h, const void *src, void *stream);
  *     diagnostics and checkpoints are those of schedule 0.  Results equal
  *     schedule 0 bit for bit for one step per call and to FP32 rounding
  *     otherwise (the moment sums run in another order).  Layouts: D3Q27,
- *     CGLBM_FP32 or CGLBM_FP32_PAIRS storage, two buffers, unit higher
- *     rates, any equilibrium family and Q switch (Model D with Q runs the
- *     fused kernel; the others the interface and collide kernels, writing
- *     compact states; one step per call then equals schedule 1 bit for
- *     bit); CGLBM_EUNSUPPORTED otherwise.  The compact state
+ *     two buffers, unit higher rates, and either CGLBM_FP32 or
+ *     CGLBM_FP32_PAIRS storage with any equilibrium family and Q switch
+ *     (Model D with Q runs the fused kernel; the others the interface and
+ *     collide kernels, writing compact states; one step per call then
+ *     equals schedule 1 bit for bit), or CGLBM_FP32_EXACT storage with
+ *     Model D and Q (the compact state then carries the FP64 colour
+ *     densities as well, 84 bytes per node, and per-colour mass stays
+ *     exact to FP64 rounding); CGLBM_EUNSUPPORTED otherwise.  The compact state
  *     lives in the population buffer that does not hold the state; solid
  *     wall nodes keep their (bounced) populations in two library-owned
  *     wall stashes allocated by cglbm_init.  cglbm_autotune chooses

@@ -98,6 +98,8 @@ const InitFn kInit[7] = {k_init<StoreF32>,  k_init<StoreF16>,  k_init<StoreBF16>
 // [FP32 pairs][general equilibrium family]
 const EmitFn kEmit[2][2] = {{k_emit<StoreF32, false>, k_emit<StoreF32, true>},
                             {k_emit<StoreF32P, false>, k_emit<StoreF32P, true>}};
+// the mass-exact storage (Model D with Q)
+const EmitFn kEmitX = k_emit<StoreF32X, false>;
 // the three-kernel schedule's collision writing compact states
 const CollideFn kCollideCompact = k_collide<StoreF32, true>;
 const WallCopyFn kWallCopy[7] = {k_wall_copy<StoreF32>,  k_wall_copy<StoreF16>,
@@ -296,6 +298,14 @@ void build_layout(int32_t n_boxes, const cglbm_box_params *boxes, Layout &L,
                             P.blue.rho0 * xi * (1.0 - P.blue.alpha)};
       for (int c = 0; c < 2; ++c)
         for (int k = 0; k < 4; ++k) B.shift[c][k] = (float)(w[k] * p0[c] * 3.0);
+      // power-of-two scale of each colour's stored values (colour-fraction
+      // formats): 2^(10 - floor(log2 rho_k^0))
+      const double r0[2] = {P.red.rho0, P.blue.rho0};
+      for (int c = 0; c < 2; ++c) {
+        const int e = std::max(-60, std::min(60, std::ilogb(r0[c]))) - 10;
+        B.pscale[c] = (float)std::ldexp(1.0, -e);
+        B.pinv[c] = (float)std::ldexp(1.0, e);
+      }
     }
     // solid nodes: the z-wall planes, then the y-wall rows of the other layers
     {
@@ -478,7 +488,9 @@ int launch_fused_compact(cglbm_handle *h, hipStream_t s) {
   void *dst = h->pop[1 - h->cur];
   int64_t plane = h->L.total;
   void *args[] = {(void *)&boxes, (void *)&cols, (void *)&aux, (void *)&dst, (void *)&plane};
-  HIP_TRY(hipLaunchKernel((const void *)F.fc[h->L.walls ? 1 : 0], dim3(h->L.ncol),
+  const FusedFn fn = h->storage == CGLBM_FP32_EXACT ? F.fcx[h->L.walls ? 1 : 0]
+                                                    : F.fc[h->L.walls ? 1 : 0];
+  HIP_TRY(hipLaunchKernel((const void *)fn, dim3(h->L.ncol),
                           dim3(F.tx * F.ty), args, 0, s));
   return CGLBM_OK;
 }
@@ -487,7 +499,8 @@ int launch_fused_compact(cglbm_handle *h, hipStream_t s) {
 int launch_cpull(cglbm_handle *h, hipStream_t s, int rd = 0) {
   const CPullVariant &C = cpull_variant(h->cvariant);
   const int wk = h->L.walls ? (h->storage == CGLBM_FP32_PAIRS ? 2 : 1) : 0;
-  const CPullFn fn = C.fn[h->L.general ? 1 : 0][wk];
+  const CPullFn fn = h->storage == CGLBM_FP32_EXACT ? C.fx[h->L.walls ? 1 : 0]
+                                                    : C.fn[h->L.general ? 1 : 0][wk];
   hipLaunchKernelGGL(fn, dim3((unsigned)h->L.ccol_box.size()), dim3(C.tx * C.ty), 0, s,
                      h->d_boxes, h->d_ccol_box, (const float *)h->pop[1 - h->cur], h->aux,
                      h->L.total, (const void *)h->cstash[rd], h->cstash[1 - rd], h->L.wtotal);
@@ -495,7 +508,9 @@ int launch_cpull(cglbm_handle *h, hipStream_t s, int rd = 0) {
 }
 // wi: the wall stash the last step wrote (the solid nodes' stored values)
 int launch_emit(cglbm_handle *h, hipStream_t s, int wi = 0) {
-  hipLaunchKernelGGL(kEmit[h->storage == CGLBM_FP32_PAIRS ? 1 : 0][h->L.general ? 1 : 0],
+  hipLaunchKernelGGL(h->storage == CGLBM_FP32_EXACT
+                         ? kEmitX
+                         : kEmit[h->storage == CGLBM_FP32_PAIRS ? 1 : 0][h->L.general ? 1 : 0],
                      dim3(h->L.nblk_pad), dim3(kBlock), 0, s, h->d_boxes, h->d_blk_box,
                      (const float *)h->pop[1 - h->cur], h->pop[h->cur], h->L.total);
   if (h->L.walls && !h->L.wblk_box.empty())
@@ -513,11 +528,13 @@ int launch_pull_compact(cglbm_handle *h, hipStream_t s) {
                      h->L.total, 1, stash, h->L.wtotal);
   return CGLBM_OK;
 }
-// Layouts the compact schedule serves: D3Q27, FP32 storage (either layout),
+// Layouts the compact schedule serves: D3Q27, FP32 storage (either layout,
+// any equilibrium family), or the mass-exact FP32 storage (Model D with Q),
 // two buffers, unit higher rates.
 bool compact_ok(const cglbm_handle *h) {
   return h->lattice == LATTICE_D3Q27 && !h->inplace && !h->L.full_rates &&
-         (h->storage == CGLBM_FP32 || h->storage == CGLBM_FP32_PAIRS);
+         (h->storage == CGLBM_FP32 || h->storage == CGLBM_FP32_PAIRS ||
+          (h->storage == CGLBM_FP32_EXACT && !h->L.general));
 }
 
 int launch_fused(cglbm_handle *h, hipStream_t s, int export_fields) {
@@ -995,7 +1012,8 @@ int init_handle(int lattice, cglbm_handle **out, int32_t n_boxes, const cglbm_bo
     size_t sb = 0, ab = 0;
     buffer_sizes(storage, h->L.wtotal, &sb, &ab, lattice);
     const bool cst = lattice == LATTICE_D3Q27 && !inplace &&
-                     (storage == CGLBM_FP32 || storage == CGLBM_FP32_PAIRS);
+                     (storage == CGLBM_FP32 || storage == CGLBM_FP32_PAIRS ||
+                      storage == CGLBM_FP32_EXACT);
     if ((e = hipMalloc(&h->d_wblk_box, sizeof(int32_t) * h->L.wblk_box.size())) != hipSuccess ||
         (e = hipMemcpyAsync(h->d_wblk_box, h->L.wblk_box.data(),
                             sizeof(int32_t) * h->L.wblk_box.size(), hipMemcpyHostToDevice, s)) !=
@@ -1103,8 +1121,8 @@ int cglbm_set_schedule(cglbm_handle *h, int32_t schedule) {
     return fail(CGLBM_EUNSUPPORTED, "D2Q9 steps have one schedule (0)");
   if (schedule == 2 && !compact_ok(h))
     return fail(CGLBM_EUNSUPPORTED,
-                "the compact schedule needs D3Q27, FP32 storage, two buffers and unit "
-                "higher-order rates");
+                "the compact schedule needs D3Q27, FP32 storage (or the mass-exact FP32 "
+                "storage with Model D and Q), two buffers and unit higher-order rates");
   if (schedule != h->schedule) drop_graphs(h);
   h->schedule = schedule;
   // the fused geometry preferred by the schedule (the autotuner's choices);

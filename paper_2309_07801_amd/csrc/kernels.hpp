@@ -60,6 +60,8 @@ struct BoxDev {
   float omega2;
   float Gx, Gy, Gz;
   float shift[2][4];    // storage shift by colour and speed class |c|^2
+  float pscale[2];      // colour-fraction formats: power-of-two scale of each colour's values
+  float pinv[2];        // and its inverse
   float bgx, bgy, bgz;  // g of the buoyancy force -(rho - rho_ref) g
   float rho_ref;
   float omh[9];         // omega_0, omega_3..omega_10 of Eq. (25)
@@ -381,6 +383,31 @@ __device__ __forceinline__ float pop_shift(const BoxDev &B, int c, int i, float 
     return S::dec(S::enc(B.shift[c][cls]));
   }
 }
+// Stored value of a population f of colour c whose shift is sh, and the
+// value read back.  The colour-fraction formats store (f - sh) times the
+// colour's power-of-two scale 2^(10 - e_c), e_c = floor(log2 rho_c^0): a
+// colour's values at its reference density then sit near 2^10, far below
+// half's largest finite value (65504), and its small values (the other
+// phase's tail near an interface, the light phase at a density ratio of
+// 1000) stay in half's normal range down to about 6e-8 rho_c^0 instead of
+// becoming subnormals with an absolute step of 6e-8.  The scaling is exact.
+template <class S>
+__device__ __forceinline__ typename S::T encode_pop(const BoxDev &B, int c, float f, float sh) {
+  if constexpr (S::kCShift) {
+    return S::enc((f - sh) * B.pscale[c]);
+  } else {
+    return S::enc(f - sh);
+  }
+}
+template <class S>
+__device__ __forceinline__ float decode_pop(const BoxDev &B, int c, typename S::T g, float sh) {
+  if constexpr (S::kCShift) {
+    const float v = S::dec(g) * B.pinv[c];
+    return v + sh;
+  } else {
+    return S::dec(g) + sh;
+  }
+}
 // Red fraction rho_r / rho of a node as the colour-fraction formats store it
 // (correctly rounded quotient: exactly 1 and 0 in the pure phases).
 template <class S>
@@ -503,10 +530,10 @@ __global__ __launch_bounds__(kBlock) void k_pull(const BoxDev *__restrict__ boxe
         const float cown = S::dec(craw);
 #pragma unroll
         for (int i = 1; i < kQ; ++i) {
-          const float fr = S::dec(gr[i]) + pop_shift<S>(B, 0, i, csrc[i]);
-          const float fb = S::dec(gb[i]) + pop_shift<S>(B, 1, i, csrc[i]);
-          st_rb(out, opposite(i), at_, S::enc(fr - pop_shift<S>(B, 0, i, cown)),
-                S::enc(fb - pop_shift<S>(B, 1, i, cown)));
+          const float fr = decode_pop<S>(B, 0, gr[i], pop_shift<S>(B, 0, i, csrc[i]));
+          const float fb = decode_pop<S>(B, 1, gb[i], pop_shift<S>(B, 1, i, csrc[i]));
+          st_rb(out, opposite(i), at_, encode_pop<S>(B, 0, fr, pop_shift<S>(B, 0, i, cown)),
+                encode_pop<S>(B, 1, fb, pop_shift<S>(B, 1, i, cown)));
         }
         at(out.cfr, at_) = craw;
       } else {
@@ -532,8 +559,8 @@ __global__ __launch_bounds__(kBlock) void k_pull(const BoxDev *__restrict__ boxe
   double drr = rr0, drb = rb0;
 #pragma unroll
   for (int i = i0; i < kQ; ++i) {
-    const float vr = S::dec(gr[i]) + pop_shift<S>(B, 0, i, csrc[i]);
-    const float vb = S::dec(gb[i]) + pop_shift<S>(B, 1, i, csrc[i]);
+    const float vr = decode_pop<S>(B, 0, gr[i], pop_shift<S>(B, 0, i, csrc[i]));
+    const float vb = decode_pop<S>(B, 1, gb[i], pop_shift<S>(B, 1, i, csrc[i]));
     if (S::kExact) {
       drr += (double)vr;
       drb += (double)vb;
@@ -904,6 +931,11 @@ __device__ __forceinline__ void collide_node(const BoxDev &B, const NodeIn &in, 
 // populations from them, bit for bit those collide_node emits.
 // ---------------------------------------------------------------------------
 constexpr int kCompact = 17;  // planes: rr rb ux uy uz Fx Fy Fz sxx syy szz sxy sxz syz nx ny nz
+// FP64 colour densities of the compact state (mass-exact storage), after its
+// 17 float planes.
+__device__ __forceinline__ double *compact_rho64(void *cst, int64_t plane) {
+  return (double *)((char *)cst + align256((int64_t)kCompact * plane * 4));
+}
 
 // GENERAL: the box's equilibrium family and correction switch (as
 // collide_node<true>); the relaxed second moments have the same form.
@@ -1119,7 +1151,8 @@ __device__ __forceinline__ void pull_total(const BoxDev &B, const void *src_, in
     typename S::T r, b;
     ld_rb(src, i, s, r, b);
     const float cs = S::kCShift ? S::dec(ld(&at(src.cfr, s))) : 0.f;
-    f[i] = (S::dec(r) + pop_shift<S>(B, 0, i, cs)) + (S::dec(b) + pop_shift<S>(B, 1, i, cs));
+    f[i] = decode_pop<S>(B, 0, r, pop_shift<S>(B, 0, i, cs)) +
+           decode_pop<S>(B, 1, b, pop_shift<S>(B, 1, i, cs));
   }
   if (S::kExact) f[0] = (float)(at(src.restp(0), node) + at(src.restp(1), node));
 }
@@ -1175,7 +1208,7 @@ struct PopWriter {
   __device__ __forceinline__ void operator()(int i, float fr, float fb) {
     if (S::kExact && i == 0) return;
     const float shr = pop_shift<S>(B, 0, i, cr), shb = pop_shift<S>(B, 1, i, cr);
-    const typename S::T er = S::enc(fr - shr), eb = S::enc(fb - shb);
+    const typename S::T er = encode_pop<S>(B, 0, fr, shr), eb = encode_pop<S>(B, 1, fb, shb);
     using W = typename S::W;
     const int64_t pb = dst.plane * (int64_t)sizeof(W);
     if constexpr (S::kPaired) {
@@ -1185,8 +1218,8 @@ struct PopWriter {
       buf_st(eb, plane_rsrc(dst.pw, pb, Pops<S>::slot(i, 1)), boff<W>(live, node));
     }
     if (S::kExact) {
-      sr += (double)(S::dec(er) + shr);
-      sb += (double)(S::dec(eb) + shb);
+      sr += (double)decode_pop<S>(B, 0, er, shr);
+      sb += (double)decode_pop<S>(B, 1, eb, shb);
     }
   }
   __device__ __forceinline__ void finish(double rho_r, double rho_b) {
@@ -1335,10 +1368,10 @@ __global__ __launch_bounds__(kBlock) void k_init(const BoxDev *__restrict__ boxe
     // the node d stores (written below by d's own thread)
     const float cd = S::kCShift ? S::dec(stored_fraction<S>(in_rr[d], in_rb[d])) : 0.f;
     const float shr = pop_shift<S>(B, 0, i, cd), shb = pop_shift<S>(B, 1, i, cd);
-    const typename S::T er = S::enc(vr - shr), eb = S::enc(vb - shb);
+    const typename S::T er = encode_pop<S>(B, 0, vr, shr), eb = encode_pop<S>(B, 1, vb, shb);
     st_rb(dst, i, d, er, eb);
-    sr += (double)(S::dec(er) + shr);
-    sb += (double)(S::dec(eb) + shb);
+    sr += (double)decode_pop<S>(B, 0, er, shr);
+    sb += (double)decode_pop<S>(B, 1, eb, shb);
   }
   if (S::kExact) {
     at(dst.restp(0), node) = tr - sr;
@@ -1523,6 +1556,11 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
 #pragma unroll
     for (int k = 0; k < kCompact; ++k)
       buf_st(0.f, plane_rsrc(dst_, plane_arg * 4, k), kDrop);
+    if (S::kExact) {
+      double *r64 = compact_rho64(dst_, plane_arg);
+      buf_st(0.0, plane_rsrc(r64, plane_arg * 8, 0), kDrop);
+      buf_st(0.0, plane_rsrc(r64, plane_arg * 8, 1), kDrop);
+    }
   } else if (!EXPORT) {
     const Pops<S> dst(dst_, plane_arg);
     PopWriter<S> w(dst, B, 0u, false);
@@ -1760,6 +1798,13 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
           const uint32_t off = boff<float>(fluid && sd >= z0, node);
 #pragma unroll
           for (int k = 0; k < kCompact; ++k) buf_st(c[k], plane_rsrc(dst_, plane * 4, k), off);
+          if (S::kExact) {
+            // mass-exact storage: the FP64 colour densities travel with it
+            double *r64 = compact_rho64(dst_, plane);
+            const uint32_t off64 = boff<double>(fluid && sd >= z0, node);
+            buf_st(d_rr, plane_rsrc(r64, plane * 8, 0), off64);
+            buf_st(d_rb, plane_rsrc(r64, plane * 8, 1), off64);
+          }
         } else {
           const double fr = d_rr, fb = d_rb;
           const Pops<S> dst(dst_, plane);
@@ -1802,17 +1847,43 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
 // through LDS, and every column node adds the 9 values arriving from its
 // neighbours to the moments of slab s + cz.  Slab s - 1 is then complete
 // (it received cz = +1 from s - 2, cz = 0 from s - 1 and cz = -1 from s, in
-// that order) and its 11 moments go to aux.
+// that order) and its 11 moments go to aux.  Each thread rebuilds its own
+// column node first (ring point k = 0), then one of the ring's halo points.
 // WALLS: solid nodes keep populations (full-way bounce-back): a solid ring
 // point emits what its slot of the wall stash wst_in holds (in storage
 // format S), and what arrives at a solid column node is stored reversed in
 // wst_out for the next step; its moments are zero.
+// Mass-exact storage (S::kExact): the compact state carries each node's
+// colour densities in FP64; a node's rest population is closed on them as
+// rho_k minus the FP64 sum of the 26 moving values it emits (which its own
+// thread computes as ring point k = 0), and the new colour densities are FP64
+// sums of the arrivals and that rest, so each colour's mass is conserved to
+// FP64 rounding; they go to the FP64 aux planes as well.
 // ---------------------------------------------------------------------------
 template <int TX, int TY>
 struct CPullGeom {
   static constexpr int NT = TX * TY;
   static constexpr int R1X = TX + 2, R1Y = TY + 2, R1 = R1X * R1Y;
   static constexpr int CP = (R1 + NT - 1) / NT;  // ring points per thread
+  // ring point j of the block: the column's own points first (thread j's
+  // column node), then the halo (top and bottom rows, then the two sides);
+  // (lx, ly) in the (TX + 2) x (TY + 2) ring, x fastest
+  __device__ static void point(int j, int &lx, int &ly) {
+    if (j < NT) {
+      lx = (j % TX) + 1;
+      ly = (j / TX) + 1;
+    } else {
+      const int h = j - NT;
+      if (h < 2 * R1X) {
+        lx = h % R1X;
+        ly = (h / R1X) * (R1Y - 1);
+      } else {
+        const int h2 = h - 2 * R1X;
+        lx = (h2 & 1) * (R1X - 1);
+        ly = (h2 >> 1) + 1;
+      }
+    }
+  }
 };
 
 template <int TX, int TY, int ZC, bool WALLS = false, class S = StoreF32, bool GENERAL = false>
@@ -1823,6 +1894,7 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
                                                   const void *__restrict__ wst_in,
                                                   void *__restrict__ wst_out, int64_t wplane) {
   using G = CPullGeom<TX, TY>;
+  constexpr bool EXACT = S::kExact;
   __shared__ float xb[18][G::R1];  // one z component: 9 directions x 2 colours
   const int tid = threadIdx.x;
   const uint32_t lb = xcd_block();
@@ -1838,17 +1910,19 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
   const int nx = B.nx, ny = B.ny, nz = B.nz;
   const int z1 = min(z0 + ZC, nz);
   const uint32_t nxy = (uint32_t)nx * (uint32_t)ny;
-  // ring points of this thread (column and one-node ring, row-major);
+  // ring points of this thread and their LDS slots (row-major in the ring);
   // lanes past the ring read point 0 and write nothing
   uint32_t roff[G::CP];
-  int rgx[G::CP], rgy[G::CP];
+  int rgx[G::CP], rgy[G::CP], rls[G::CP];
 #pragma unroll
   for (int k = 0; k < G::CP; ++k) {
     const int j = tid + k * G::NT;
     roff[k] = 0;
-    rgx[k] = rgy[k] = 0;
+    rgx[k] = rgy[k] = rls[k] = 0;
     if (j < G::R1) {
-      const int lx = j % G::R1X, ly = j / G::R1X;
+      int lx, ly;
+      G::point(j, lx, ly);
+      rls[k] = lx + G::R1X * ly;
       rgx[k] = wrap_any(x0 + lx - 1, nx);
       rgy[k] = wrap_any(y0 + ly - 1, ny);
       roff[k] = (uint32_t)rgx[k] + (uint32_t)nx * (uint32_t)rgy[k];
@@ -1864,6 +1938,19 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int m = 0; m < 11; ++m) acc[a][m] = 0.f;
+  double acc64[3][2];  // mass-exact storage: the colour densities in FP64
+#pragma unroll
+  for (int a = 0; a < 3; ++a) acc64[a][0] = acc64[a][1] = 0.0;
+  // Pressure p of the column node at slabs s, s - 1, s - 2 (zero at solid
+  // nodes).  The z momentum of the node at slab d is the sum of what arrives
+  // from slab d - 1 less the sum of what arrives from slab d + 1: two sums of
+  // nine populations each, of order rho / 6, whose difference is of order
+  // rho u.  Both are summed as deviations from 3 w_i p(d - 1), the same
+  // reference for the two, so that the large parts cancel before any
+  // rounding (rounded at the size of the large sums, the difference carries
+  // an error of order 1e-8 rho that repeats at every step of a steady flow
+  // and drifts the total momentum).
+  float ph0 = 0.f, ph1 = 0.f, ph2 = 0.f;
 
   for (int s = z0 - 1; s <= z1; ++s) {
     const int64_t plane = opaque_i64(plane_arg);
@@ -1876,6 +1963,13 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
       rsolid[k] = WALLS && tid + k * G::NT < G::R1 && is_solid(B, rgy[k], gz);
       rslot[k] = rsolid[k] ? (uint32_t)B.wbase + wall_slot(B, rgx[k], rgy[k], gz) : 0u;
     }
+    // the column node's FP64 colour densities at slab s (its ring point k = 0)
+    double own_r = 0.0, own_b = 0.0;
+    if constexpr (EXACT) {
+      const double *r64 = compact_rho64(const_cast<float *>(cst), plane);
+      own_r = buf_ld_f64(plane_rsrc(r64, plane * 8, 0), (zoff + oxy) * 8u);
+      own_b = buf_ld_f64(plane_rsrc(r64, plane * 8, 1), (zoff + oxy) * 8u);
+    }
     float h[G::CP][3][3][3];
     float pux[G::CP], pcr[G::CP], pcb[G::CP], pRx[G::CP], pRy[G::CP], pRz[G::CP];
 #pragma unroll
@@ -1885,6 +1979,11 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
       for (int m = 0; m < kCompact; ++m) c[m] = ldpl(cst, plane, m, zoff + roff[k]);
       CompactPost o;
       compact_post<GENERAL>(B, c, o);
+      if (k == 0) {
+        ph2 = ph1;
+        ph1 = ph0;
+        ph0 = (WALLS && rsolid[0]) ? 0.f : c[0] * B.cs2r + c[1] * B.cs2b;
+      }
       float g[3][3][3];
 #pragma unroll
       for (int a = 0; a < 3; ++a)
@@ -1905,6 +2004,8 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
       pRy[k] = o.Ry;
       pRz[k] = o.Rz;
     }
+    // mass-exact storage: FP64 sums of the moving values the column node emits
+    double emit_r = 0.0, emit_b = 0.0;
 #pragma unroll
     for (int pz = 0; pz < 3; ++pz) {
       // the x pass and the recolouring (Eqs. 18-19) of the directions with
@@ -1927,15 +2028,24 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
               const int q = 3 * cy + cx;
               float vr = fmaf(pcr[k], fx[cx], d), vb = fmaf(pcb[k], fx[cx], -d);
               if (WALLS && rsolid[k]) {
-                // a solid point emits what the bounce-back stored there
-                const Pops<S> win(const_cast<void *>(wst_in), wplane);
-                typename S::T er, eb;
-                ld_rb(win, i, rslot[k], er, eb);
-                vr = S::dec(er);
-                vb = S::dec(eb);
+                // a solid point emits what the bounce-back stored there (its
+                // rest population, which only it receives, stays in the stash)
+                if (!(EXACT && i == 0)) {
+                  const Pops<S> win(const_cast<void *>(wst_in), wplane);
+                  typename S::T er, eb;
+                  ld_rb(win, i, rslot[k], er, eb);
+                  vr = S::dec(er);
+                  vb = S::dec(eb);
+                } else {
+                  vr = vb = 0.f;
+                }
               }
-              xb[2 * q][j] = vr;
-              xb[2 * q + 1][j] = vb;
+              if (EXACT && k == 0 && i != 0) {
+                emit_r += (double)vr;
+                emit_b += (double)vb;
+              }
+              xb[2 * q][rls[k]] = vr;
+              xb[2 * q + 1][rls[k]] = vb;
             }
           }
         }
@@ -1963,6 +2073,19 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
           sr += fr[q];
           sb += fb[q];
         }
+        if constexpr (EXACT) {
+          // the arrivals in FP64; the node's own rest population is added
+          // below, closed on its FP64 density
+          double s64r = 0.0, s64b = 0.0;
+#pragma unroll
+          for (int q = 0; q < 9; ++q) {
+            if (pz == 1 && q == 4) continue;
+            s64r += (double)fr[q];
+            s64b += (double)fb[q];
+          }
+          acc64[pz][0] += s64r;
+          acc64[pz][1] += s64b;
+        }
         float r0[3], r1[3], r2[3];  // per row: sum, c_x-weighted, c_x^2-weighted
 #pragma unroll
         for (int cy = 0; cy < 3; ++cy) {
@@ -1970,9 +2093,26 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
           r1[cy] = f[3 * cy + 2] - f[3 * cy];
           r0[cy] = r2[cy] + f[3 * cy + 1];
         }
-        const float m02 = r0[2] + r0[0], m01 = r0[2] - r0[0], m00 = m02 + r0[1];
+        const float m02 = r0[2] + r0[0], m00 = m02 + r0[1];
+        // c_y-weighted: differences of opposite directions first
+        const float m01 = ((f[6] - f[0]) + (f[8] - f[2])) + (f[7] - f[1]);
         const float m11 = r1[2] - r1[0], m10 = (r1[2] + r1[0]) + r1[1];
         const float m20 = (r2[2] + r2[0]) + r2[1];
+        // z momentum: the nine arrivals as deviations from 3 w_i p(d - 1)
+        // (d: the destination slab; see ph0)
+        float m00d = 0.f;
+        if (pz != 1) {
+          const float pr = pz == 2 ? ph0 : ph2;
+          float e[9];
+#pragma unroll
+          for (int cy = 0; cy < 3; ++cy)
+#pragma unroll
+            for (int cx = 0; cx < 3; ++cx) {
+              const int q = 3 * cy + cx;
+              e[q] = fmaf(-3.0f * weight(dir_of(cx - 1, cy - 1, pz - 1)), pr, f[q]);
+            }
+          m00d = (((e[0] + e[2]) + (e[6] + e[8])) + ((e[1] + e[7]) + (e[3] + e[5]))) + e[4];
+        }
         if (WALLS) {
           // a solid column node keeps what arrives, reversed, for the next step
           const int d = s + pz - 1, gd = wrap_any(d, nz);
@@ -1984,8 +2124,15 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
 #pragma unroll
               for (int cx = 0; cx < 3; ++cx) {
                 const int q = 3 * cy + cx;
-                st_rb(wout, opposite(dir_of(cx - 1, cy - 1, pz - 1)), slot, S::enc(fr[q]),
-                      S::enc(fb[q]));
+                const int i = dir_of(cx - 1, cy - 1, pz - 1);
+                if (EXACT && i == 0) {
+                  // mass-exact storage: the rest populations stay as stored
+                  const Pops<S> win(const_cast<void *>(wst_in), wplane);
+                  at(wout.restp(0), slot) = at(win.restp(0), slot);
+                  at(wout.restp(1), slot) = at(win.restp(1), slot);
+                } else {
+                  st_rb(wout, opposite(i), slot, S::enc(fr[q]), S::enc(fb[q]));
+                }
               }
           }
         }
@@ -1999,7 +2146,7 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
         a[8] += m11;
         if (pz != 1) {
           const bool up = pz == 2;
-          a[4] += up ? m00 : -m00;
+          a[4] += up ? m00d : -m00d;
           a[7] += m00;
           a[9] += up ? m10 : -m10;
           a[10] += up ? m01 : -m01;
@@ -2007,11 +2154,30 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
       }
       __syncthreads();
     }
+    if constexpr (EXACT) {
+      // the rest populations of the column node at slab s
+      acc64[1][0] += own_r - emit_r;
+      acc64[1][1] += own_b - emit_b;
+    }
     // slab s - 1 is complete (solid nodes: zero moments)
     const int gzm = wrap_any(s - 1, nz);
     const uint32_t node = (uint32_t)B.base + oxy + nxy * (uint32_t)gzm;
     const uint32_t off = boff<float>(in_xy && s - 1 >= z0, node);
     const bool osolid = WALLS && is_solid(B, gyo, gzm);
+    if constexpr (EXACT) {
+      acc[0][0] = (float)acc64[0][0];
+      acc[0][1] = (float)acc64[0][1];
+      double *r64 = aux_rho64(aux, plane);
+      const uint32_t off64 = boff<double>(in_xy && s - 1 >= z0, node);
+      buf_st(osolid ? 0.0 : acc64[0][0], plane_rsrc(r64, plane * 8, 0), off64);
+      buf_st(osolid ? 0.0 : acc64[0][1], plane_rsrc(r64, plane * 8, 1), off64);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        acc64[0][c] = acc64[1][c];
+        acc64[1][c] = acc64[2][c];
+        acc64[2][c] = 0.0;
+      }
+    }
 #pragma unroll
     for (int m = 0; m < 11; ++m)
       buf_st(osolid ? 0.f : acc[0][m], plane_rsrc(aux, plane * 4, A_RR + m), off);
@@ -2057,6 +2223,11 @@ __global__ __launch_bounds__(kBlock) void k_emit(const BoxDev *__restrict__ boxe
   PopWriter<S> w(dst, B, node);
   emit_recoloured(B, k, c[2], c[3], c[4], div_refined(c[0], rho, irho), div_refined(c[1], rho, irho),
                   p, c[14], c[15], c[16], w);
+  if (S::kExact) {
+    // mass-exact storage: the rest populations closed on the FP64 densities
+    const double *r64 = compact_rho64(const_cast<float *>(cst), plane);
+    w.finish(at(r64, node), at(r64 + plane, node));
+  }
 }
 
 }  // namespace cglbm

@@ -22,6 +22,7 @@ struct FusedVariant {
   FusedFn fn[7][2];  // time step: [storage][any box with solid layers]
   FusedFn fx[2];     // field export (no population store): [solid layers]
   FusedFn fc[2];     // compact schedule: compact state out (FP32): [solid layers]
+  FusedFn fcx[2];    // compact schedule, mass-exact storage (FP64 densities): [solid layers]
 };
 #define CGLBM_FV_S(TX, TY, ZC, MW, S) \
   {k_fused<TX, TY, ZC, MW, false, S, false>, k_fused<TX, TY, ZC, MW, true, S, false>}
@@ -33,12 +34,14 @@ struct FusedVariant {
     CGLBM_FV_S(TX, TY, ZC, MW, StoreBF16C)},                                                 \
    {k_fused<TX, TY, ZC, MW, false, StoreF32, true>, k_fused<TX, TY, ZC, MW, true, StoreF32, true>}, \
    {k_fused<TX, TY, ZC, MW, false, StoreF32, false, true>,                                    \
-    k_fused<TX, TY, ZC, MW, true, StoreF32, false, true>}}
-// the eleven geometries, in three units
+    k_fused<TX, TY, ZC, MW, true, StoreF32, false, true>},                                    \
+   {k_fused<TX, TY, ZC, MW, false, StoreF32X, false, true>,                                   \
+    k_fused<TX, TY, ZC, MW, true, StoreF32X, false, true>}}
+// the thirteen geometries, in three units
 extern const FusedVariant kFusedPart0[4];
 extern const FusedVariant kFusedPart1[4];
-extern const FusedVariant kFusedPart2[3];
-constexpr int kNumFusedVariants = 11;
+extern const FusedVariant kFusedPart2[5];
+constexpr int kNumFusedVariants = 13;
 inline const FusedVariant &fused_variant(int v) {
   return v < 4 ? kFusedPart0[v] : (v < 8 ? kFusedPart1[v - 4] : kFusedPart2[v - 8]);
 }
@@ -51,6 +54,7 @@ struct CPullVariant {
   int tx, ty, zc;
   // [general equilibrium family][0 periodic, 1 walls with FP32 planes, 2 walls with FP32 pairs]
   CPullFn fn[2][3];
+  CPullFn fx[2];  // mass-exact storage, Model D with Q: [solid layers]
 };
 extern const CPullVariant kCPullTable[5];
 constexpr int kNumCPullVariants = 5;

@@ -167,7 +167,7 @@ def test_laplace_law_static_droplet():
     assert np.all(np.abs(m1 - m0) / m0 < 1e-13)
 
 
-def _layered(case, model, steps, a=12, b=24, nu=0.1):
+def _layered(case, model, steps, a=12, b=24, nu=0.1, margin=4):
     w, M = WL.layered_channel(case, a=a, b=b, nu=nu)
     box = w.box
     P = params_of(box, model=model, use_q=int(model >= O.MODEL_C))
@@ -179,8 +179,8 @@ def _layered(case, model, steps, a=12, b=24, nu=0.1):
     G = box.body_force[0]
     d2 = ux[2:] - 2 * ux[1:-1] + ux[:-2]
     yy = y[1:-1]
-    red = np.abs(yy) < a - 4
-    blue = (np.abs(yy) > a + 4) & (np.abs(yy) < b - 2)
+    red = np.abs(yy) < a - margin
+    blue = (np.abs(yy) > a + margin) & (np.abs(yy) < b - 2)
     mu_r, mu_b = box.nu_r * box.rho0_r, box.nu_b * box.rho0_b
     return d2[red].mean() / (-G / mu_r), d2[blue].mean() / (-G / mu_b)
 
@@ -195,6 +195,26 @@ def test_layered_poiseuille_pure_layer_curvature(case, steps, tol_r, tol_b):
     assert b == pytest.approx(1.0, abs=tol_b)
     ra, ba = _layered(case, O.MODEL_A, steps // 3)
     assert max(abs(ra - 1.0), abs(ba - 1.0)) > 0.3
+
+
+@pytest.mark.slow
+def test_layered_poiseuille_case_c_density_ratio_1000():
+    """Table III case C (light inner layer rho_r^0 = 0.008, heavy outer
+    layer rho_b^0 = 8, M = 1/40) at the paper's geometry, a = 25 and b = 50:
+    Model D gives u_x'' = -G/mu_k in each pure layer to 1e-3 (the layers
+    taken 12 nodes away from the interfaces: at a density ratio of 1000 the
+    heavy colour's tail raises the light layer's density several nodes into
+    it); Model A (no correction) diverges."""
+    threads = O.num_threads()
+    O.set_num_threads(1)  # 102 nodes: one thread runs the steps fastest
+    try:
+        r, b = _layered("C", O.MODEL_D, 40000, a=25, b=50, margin=12)
+        ra, ba = _layered("C", O.MODEL_A, 2000, a=25, b=50, margin=12)
+    finally:
+        O.set_num_threads(threads)
+    assert r == pytest.approx(1.0, abs=1e-3)
+    assert b == pytest.approx(1.0, abs=1e-3)
+    assert not (np.isfinite(ra) and np.isfinite(ba)) or max(abs(ra - 1.0), abs(ba - 1.0)) > 0.3
 
 
 def test_shear_wave_viscosity():

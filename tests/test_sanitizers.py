@@ -19,10 +19,11 @@ SAN = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-f
 
 def _env():
     env = dict(os.environ)
-    env["ASAN_OPTIONS"] = "detect_leaks=1:abort_on_error=0:halt_on_error=1"
+    # verify_asan_link_order=0: the process environment may preload another
+    # library ahead of the sanitizer runtime
+    env["ASAN_OPTIONS"] = "detect_leaks=1:abort_on_error=0:halt_on_error=1:verify_asan_link_order=0"
     env["UBSAN_OPTIONS"] = "halt_on_error=1:print_stacktrace=1"
     env["OMP_NUM_THREADS"] = "2"
-    env.pop("LD_PRELOAD", None)
     return env
 
 
