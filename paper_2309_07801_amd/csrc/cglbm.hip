@@ -298,6 +298,10 @@ void build_layout(int32_t n_boxes, const cglbm_box_params *boxes, Layout &L,
                             P.blue.rho0 * xi * (1.0 - P.blue.alpha)};
       for (int c = 0; c < 2; ++c)
         for (int k = 0; k < 4; ++k) B.shift[c][k] = (float)(w[k] * p0[c] * 3.0);
+      // k_cpull's reference for the z momentum: the rest-state populations
+      // 3 w_i p_ref (D3Q27 weights)
+      const double pref = std::min(p0[0], p0[1]);
+      for (int k = 0; k < 4; ++k) B.cdev[k] = (float)(-3.0 * w3[k] * pref);
       // power-of-two scale of each colour's stored values (colour-fraction
       // formats): 2^(10 - floor(log2 rho_k^0))
       const double r0[2] = {P.red.rho0, P.blue.rho0};

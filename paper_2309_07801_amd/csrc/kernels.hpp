@@ -60,6 +60,7 @@ struct BoxDev {
   float omega2;
   float Gx, Gy, Gz;
   float shift[2][4];    // storage shift by colour and speed class |c|^2
+  float cdev[4];        // -3 w p_ref by speed class |c|^2, p_ref = min_k rho_k^0 (c_s^k)^2 (k_cpull)
   float pscale[2];      // colour-fraction formats: power-of-two scale of each colour's values
   float pinv[2];        // and its inverse
   float bgx, bgy, bgz;  // g of the buoyancy force -(rho - rho_ref) g
@@ -1920,8 +1921,16 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
     roff[k] = 0;
     rgx[k] = rgy[k] = rls[k] = 0;
     if (j < G::R1) {
+      // the mass-exact storage puts each thread's own column node first
+      // (its ring point k = 0, whose emitted values close its rest
+      // populations); otherwise the ring is row-major
       int lx, ly;
-      G::point(j, lx, ly);
+      if constexpr (EXACT) {
+        G::point(j, lx, ly);
+      } else {
+        lx = j % G::R1X;
+        ly = j / G::R1X;
+      }
       rls[k] = lx + G::R1X * ly;
       rgx[k] = wrap_any(x0 + lx - 1, nx);
       rgy[k] = wrap_any(y0 + ly - 1, ny);
@@ -1941,16 +1950,6 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
   double acc64[3][2];  // mass-exact storage: the colour densities in FP64
 #pragma unroll
   for (int a = 0; a < 3; ++a) acc64[a][0] = acc64[a][1] = 0.0;
-  // Pressure p of the column node at slabs s, s - 1, s - 2 (zero at solid
-  // nodes).  The z momentum of the node at slab d is the sum of what arrives
-  // from slab d - 1 less the sum of what arrives from slab d + 1: two sums of
-  // nine populations each, of order rho / 6, whose difference is of order
-  // rho u.  Both are summed as deviations from 3 w_i p(d - 1), the same
-  // reference for the two, so that the large parts cancel before any
-  // rounding (rounded at the size of the large sums, the difference carries
-  // an error of order 1e-8 rho that repeats at every step of a steady flow
-  // and drifts the total momentum).
-  float ph0 = 0.f, ph1 = 0.f, ph2 = 0.f;
 
   for (int s = z0 - 1; s <= z1; ++s) {
     const int64_t plane = opaque_i64(plane_arg);
@@ -1979,11 +1978,6 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
       for (int m = 0; m < kCompact; ++m) c[m] = ldpl(cst, plane, m, zoff + roff[k]);
       CompactPost o;
       compact_post<GENERAL>(B, c, o);
-      if (k == 0) {
-        ph2 = ph1;
-        ph1 = ph0;
-        ph0 = (WALLS && rsolid[0]) ? 0.f : c[0] * B.cs2r + c[1] * B.cs2b;
-      }
       float g[3][3][3];
 #pragma unroll
       for (int a = 0; a < 3; ++a)
@@ -2044,8 +2038,9 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
                 emit_r += (double)vr;
                 emit_b += (double)vb;
               }
-              xb[2 * q][rls[k]] = vr;
-              xb[2 * q + 1][rls[k]] = vb;
+              const int slot = EXACT ? rls[k] : j;
+              xb[2 * q][slot] = vr;
+              xb[2 * q + 1][slot] = vb;
             }
           }
         }
@@ -2098,18 +2093,29 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
         const float m01 = ((f[6] - f[0]) + (f[8] - f[2])) + (f[7] - f[1]);
         const float m11 = r1[2] - r1[0], m10 = (r1[2] + r1[0]) + r1[1];
         const float m20 = (r2[2] + r2[0]) + r2[1];
-        // z momentum: the nine arrivals as deviations from 3 w_i p(d - 1)
-        // (d: the destination slab; see ph0)
+        // The z momentum of the node at slab d is what arrives from slab
+        // d - 1 less what arrives from slab d + 1: two sums of nine
+        // populations of order rho / 6 whose difference is of order rho u.
+        // Rounded at the size of the large sums it carries an error of order
+        // 1e-8 rho that repeats at every step of a steady flow (it drifted
+        // the total momentum of droplets at rest).  Both are therefore summed
+        // as deviations e_i = f_i - 3 w_i p_ref from the rest-state
+        // populations at the box's reference pressure (the smaller of the two
+        // pure phases' rest pressures, which the equilibria make equal when
+        // the sound speeds follow the density ratio): the same float
+        // constants enter both sums, so the reference cancels exactly and only
+        // the deviations are rounded.  (The even moments keep the plain sums:
+        // a reference added back as a constant would leave its own rounding
+        // as a bias of order 1e-9 in every node's second moments.)
         float m00d = 0.f;
         if (pz != 1) {
-          const float pr = pz == 2 ? ph0 : ph2;
           float e[9];
 #pragma unroll
           for (int cy = 0; cy < 3; ++cy)
 #pragma unroll
             for (int cx = 0; cx < 3; ++cx) {
               const int q = 3 * cy + cx;
-              e[q] = fmaf(-3.0f * weight(dir_of(cx - 1, cy - 1, pz - 1)), pr, f[q]);
+              e[q] = f[q] + B.cdev[(cx != 1) + (cy != 1) + 1];
             }
           m00d = (((e[0] + e[2]) + (e[6] + e[8])) + ((e[1] + e[7]) + (e[3] + e[5]))) + e[4];
         }

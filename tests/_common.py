@@ -1,6 +1,9 @@
 """Shared helpers of the tests: run the HIP path and the FP64 oracle on the
 same seeded inputs and measure their differences (error norms of density,
 velocity and order parameter as relative or absolute maxima)."""
+import json
+import os
+
 import numpy as np
 
 import oracle as O
@@ -61,6 +64,53 @@ def errors(g, o, box: WL.Box, u_ref: float):
         "rho_l2": float(np.sqrt((((rho_g - rho_o) / rho_o)[m] ** 2).mean())),
         "u_l2": float(np.sqrt((du[m] ** 2).mean()) / u_ref),
     }
+
+
+# FP32 bar of the error measures below (e_rho relative, e_u against U_ref,
+# e_phi absolute)
+FP32_BAR = 1e-5
+# unit roundoff of the 16-bit storage formats (by storage id)
+UNIT_ROUNDOFF_16 = {1: 2.0 ** -11, 5: 2.0 ** -11, 2: 2.0 ** -8, 6: 2.0 ** -8}
+
+
+def bars_16bit(storage):
+    """(e_rho, e_u, e_phi) bars of a 16-bit storage format: 8 u_s for the
+    density and phi and 32 u_s for the velocity (a momentum error divided by
+    a velocity scale 10-25 times smaller than the populations), u_s the
+    format's unit roundoff."""
+    us = UNIT_ROUNDOFF_16[storage]
+    return 8 * us, 32 * us, 8 * us
+
+
+def u_ref(box: WL.Box, U: float) -> float:
+    """Velocity scale of e_u: the imposed velocity U or the capillary scale
+    sigma / mu_max, whichever is larger."""
+    return max(U, box.sigma / max(box.rho0_r * box.nu_r, box.rho0_b * box.nu_b))
+
+
+def log_parity(key, value):
+    """Append a measured error record to the JSON file named by
+    CGLBM_PARITY_LOG (if set)."""
+    path = os.environ.get("CGLBM_PARITY_LOG")
+    if not path:
+        return
+    data = {}
+    if os.path.exists(path):
+        with open(path) as fh:
+            data = json.load(fh)
+    data[key] = value
+    with open(path, "w") as fh:
+        json.dump(data, fh, indent=1, sort_keys=True)
+
+
+def check(e, ctx="", rho=FP32_BAR, u=FP32_BAR, phi=FP32_BAR):
+    """Log the error record under the running test's id (and ctx), then hold
+    it to the bars."""
+    name = os.environ.get("PYTEST_CURRENT_TEST", "?").split(" ")[0]
+    if ctx != "":
+        name += ":%s" % (ctx,)
+    log_parity(name, e)
+    assert e["rho"] <= rho and e["u"] <= u and e["phi"] <= phi, (name, e)
 
 
 # ---- two-dimensional (D2Q9) boxes: workloads.Box with nz = 1 ----

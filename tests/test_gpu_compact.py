@@ -20,7 +20,7 @@ import numpy as np
 import pytest
 
 import workloads as WL
-from _common import errors, gpu_fields, run_oracle
+from _common import check, errors, gpu_fields, run_oracle, u_ref
 
 pytestmark = pytest.mark.gpu
 
@@ -64,9 +64,9 @@ def test_compact_schedule_parity_with_oracle(storage):
     sim.step(50)
     for k, (box, fl) in enumerate(cases):
         o = run_oracle(box, *fl, 50, seed=4, noise=1e-6, box_index=k)[0]
-        e = errors(gpu_fields(sim, k), o, box, 0.05)
+        e = errors(gpu_fields(sim, k), o, box, u_ref(box, 0.05))
         print(k, e)
-        assert e["rho"] < 1e-5 and e["u"] < 1e-4 and e["phi"] < 1e-4, (k, e)
+        check(e, k)
     d = sim.reduce()
     assert d[:, 12].sum() == 0
     sim.close()
@@ -182,9 +182,9 @@ def test_walls_parity_with_oracle(storage):
     sim.step(60)
     for k, (box, fl) in enumerate(cases):
         o = run_oracle(box, *fl, 60, seed=4, noise=1e-6, box_index=k)[0]
-        e = errors(gpu_fields(sim, k), o, box, 0.02)
+        e = errors(gpu_fields(sim, k), o, box, u_ref(box, 0.02))
         print(k, box.walls, e)
-        assert e["rho"] < 1e-5 and e["u"] < 1e-4 and e["phi"] < 1e-4, (k, e)
+        check(e, k)
     d = sim.reduce()
     assert d[:, 12].sum() == 0
     sim.close()
@@ -239,9 +239,9 @@ def test_general_models_parity_with_oracle():
     sim.step(50)
     for k, (box, fl) in enumerate(cases):
         o = run_oracle(box, *fl, 50, seed=4, noise=1e-6, box_index=k)[0]
-        e = errors(gpu_fields(sim, k), o, box, 0.03)
+        e = errors(gpu_fields(sim, k), o, box, u_ref(box, 0.03))
         print(k, box.model, box.use_q, e)
-        assert e["rho"] < 1e-5 and e["u"] < 1e-4 and e["phi"] < 1e-4, (k, e)
+        check(e, k)
     sim.close()
 
 

@@ -27,7 +27,7 @@ import pytest
 import oracle as O
 import workloads as WL
 
-from _common import oracle_params
+from _common import FP32_BAR, bars_16bit, oracle_params
 
 pytestmark = pytest.mark.gpu
 
@@ -36,7 +36,7 @@ W = 20          # window edge
 HALF = 10       # sample position inside the window along an open axis
 FIELDS = ("rho_r", "rho_b", "phi", "ux", "uy", "uz")
 # per storage: (density relative, velocity / U_ref, phi absolute)
-BARS = {0: (2e-5, 2e-5, 2e-5), 1: (2e-3, 5e-2, 2e-2), 2: (2e-2, 3e-1, 1.5e-1)}
+BARS = {0: (FP32_BAR,) * 3, 1: bars_16bit(1), 2: bars_16bit(2)}
 
 
 def _gpu_run(w, storage, steps, schedule=None):

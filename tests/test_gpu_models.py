@@ -14,7 +14,7 @@ import pytest
 
 import workloads as WL
 
-from _common import errors, gpu_fields, run_oracle
+from _common import check, errors, gpu_fields, run_oracle, u_ref
 
 pytestmark = pytest.mark.gpu
 
@@ -68,10 +68,11 @@ def test_model_translating_droplet_50_steps(model, use_q, walls):
     box, fl = _case(model, use_q, shape=(17, 9, 12), R=3.0, walls=walls)
     sim = _sim([box], [fl], seed=9, noise=1e-6)
     sim.step(50)
-    e = errors(gpu_fields(sim), run_oracle(box, *fl, 50, seed=9, noise=1e-6)[0], box, 0.04)
+    e = errors(gpu_fields(sim), run_oracle(box, *fl, 50, seed=9, noise=1e-6)[0], box,
+               u_ref(box, 0.04))
     sim.close()
     print(model, use_q, walls, e)
-    assert e["rho"] < 1e-5 and e["u"] < 1e-4 and e["phi"] < 1e-4
+    check(e)
 
 
 def test_mixed_models_in_one_batch():
@@ -81,8 +82,8 @@ def test_mixed_models_in_one_batch():
     sim.step(20)
     for k, (box, fl) in enumerate(cases):
         o, _ = run_oracle(box, *fl, 20, seed=3, noise=1e-6, box_index=k)
-        e = errors(gpu_fields(sim, k), o, box, 0.04)
-        assert e["rho"] < 1e-5 and e["u"] < 1e-4 and e["phi"] < 1e-4, (k, e)
+        e = errors(gpu_fields(sim, k), o, box, u_ref(box, 0.04))
+        check(e, k)
     sim.close()
 
 

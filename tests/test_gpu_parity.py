@@ -13,7 +13,7 @@ import pytest
 import oracle as O
 import workloads as WL
 
-from _common import errors, gpu_fields, oracle_params, run_oracle
+from _common import check, errors, gpu_fields, oracle_params, run_oracle, u_ref
 
 pytestmark = pytest.mark.gpu
 
@@ -67,9 +67,10 @@ def test_multi_step_translating_droplet():
     box, fl = _case(shape=(17, 9, 12), R=3.0)
     sim = _sim([box], [fl], seed=9, noise=1e-6)
     sim.step(50)
-    e = errors(gpu_fields(sim), run_oracle(box, *fl, 50, seed=9, noise=1e-6)[0], box, 0.02)
+    e = errors(gpu_fields(sim), run_oracle(box, *fl, 50, seed=9, noise=1e-6)[0], box,
+               u_ref(box, 0.02))
     print(e)
-    assert e["rho"] < 1e-5 and e["u"] < 1e-4 and e["phi"] < 1e-4
+    check(e)
 
 
 def test_static_droplet_32_cubed_200_steps_and_laplace():
@@ -81,9 +82,9 @@ def test_static_droplet_32_cubed_200_steps_and_laplace():
     sim.step(200)
     g = gpu_fields(sim)
     o, _ = run_oracle(w.box, w.rho_r, w.rho_b, w.u, 200)
-    e = errors(g, o, w.box, 2 * w.box.sigma / 8.0)
+    e = errors(g, o, w.box, u_ref(w.box, 0.0))
     print(e)
-    assert e["rho"] < 1e-5 and e["phi"] < 1e-4 and e["u"] < 1e-3
+    check(e)
     d = sim.reduce([w.centres[0]])[0]
     dp = d[5] - d[6]
     print("dp", dp, "R_eff", d[7], "theory", 2 * w.box.sigma / d[7])
@@ -96,10 +97,13 @@ def test_walls_droplet_and_channel():
     box, fl = _case(shape=(14, 12, 11), R=3.0, walls=3, u=(0.01, 0.0, 0.0))
     sim = _sim([box], [fl], seed=3, noise=1e-6)
     sim.step(30)
-    e = errors(gpu_fields(sim), run_oracle(box, *fl, 30, seed=3, noise=1e-6)[0], box, 0.01)
+    e = errors(gpu_fields(sim), run_oracle(box, *fl, 30, seed=3, noise=1e-6)[0], box,
+               u_ref(box, 0.01))
     print("walls droplet", e)
-    assert e["rho"] < 1e-5 and e["u"] < 1e-4 and e["phi"] < 1e-4
-    w, _ = WL.layered_channel("A", a=6, b=12, nu=0.1, G=1e-6)
+    check(e, "droplet")
+    # G 1e-5 rather than the paper's 1.5e-8: the per-step increment 3 w G of
+    # a population must be well above its FP32 resolution
+    w, _ = WL.layered_channel("A", a=6, b=12, nu=0.1, G=1e-5)
     w.box.nx = 3
     rr = np.repeat(w.rho_r, 3, axis=2)
     rb = np.repeat(w.rho_b, 3, axis=2)
@@ -110,11 +114,13 @@ def test_walls_droplet_and_channel():
     o, _ = run_oracle(w.box, rr, rb, uu, 300)
     # velocity reference max(U, sigma/mu_max) (creeping flow: FP32 resolves
     # u only to about 1e-7 absolute)
-    u_ref = max(np.abs(o["ux"]).max(), w.box.sigma / max(w.box.nu_r * w.box.rho0_r,
-                                                         w.box.nu_b * w.box.rho0_b))
-    e = errors(g, o, w.box, u_ref)
+    u_ref_l = u_ref(w.box, np.abs(o["ux"]).max())
+    e = errors(g, o, w.box, u_ref_l)
     print("layered", e)
-    assert e["rho"] < 1e-5 and e["u"] < 1e-4
+    # a flow uniform along x: every node of a layer rounds its update the
+    # same way at every step, so the velocity's rounding accumulates over
+    # the N steps (4 N 2^-24, measured 2.5e-5)
+    check(e, "layered", u=4 * 300 * 2.0 ** -24)
 
 
 def test_batched_boxes_match_solo_bitwise_and_oracle():
@@ -135,9 +141,9 @@ def test_batched_boxes_match_solo_bitwise_and_oracle():
         for k in g:
             assert np.array_equal(g[k], gs[k]), (b, k)
         o, _ = run_oracle(box, *fl, 20, seed=4, noise=1e-6, box_index=b)
-        e = errors(g, o, box, 0.02)
+        e = errors(g, o, box, u_ref(box, 0.02))
         print("box", b, e)
-        assert e["rho"] < 1e-5 and e["phi"] < 1e-4
+        check(e, b)
 
 
 def test_reduce_matches_oracle_fields():
@@ -241,9 +247,9 @@ def test_degenerate_boxes(schedule):
     for k, (b, fl) in enumerate(cases):
         o, _ = run_oracle(b, *fl, 20, seed=8, noise=1e-6, box_index=k)
         g = gpu_fields(sim, k)
-        e = errors(g, o, b, 0.02)
+        e = errors(g, o, b, u_ref(b, 0.02))
         print(k, (b.nx, b.ny, b.nz), e)
-        assert e["rho"] < 1e-5 and e["u"] < 1e-4 and e["phi"] < 1e-4, (k, e)
+        check(e, k)
         assert np.isfinite(g["kappa"]).all() and np.isfinite(g["Fx"]).all()
     assert np.all(sim.reduce()[:, 12] == 0)
     sim.close()
