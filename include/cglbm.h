@@ -263,6 +263,22 @@ int cglbm_moments(cglbm_handle *h, int32_t box, uint32_t field_mask, float *out_
 int cglbm_reduce(cglbm_handle *h, const double *centre, double *out, int32_t out_is_host,
                  void *stream);
 
+/* The diagnostics of cglbm_reduce (same kernels, same summation order, the
+ * same values bit for bit) for callers that cannot allocate device memory:
+ * work captured into a HIP graph, tight serving loops, harnesses that forbid
+ * hipMalloc.  The call allocates nothing and never synchronizes: its
+ * reduction scratch is a static device array of the library (8.5 MiB per
+ * GPU, held until the process ends), used for at most 65536 reduction chunks
+ * of 16384 nodes (about 1.07e9 nodes) and 4096 boxes; larger handles get
+ * CGLBM_EINVAL (use cglbm_reduce).  Every call on one GPU shares that array:
+ * calls that overlap on one GPU (other streams, other threads, other
+ * handles) race and must be ordered by the caller.
+ * centre: device array of 3 doubles per box, or NULL for the box centres.
+ * out: device array of n_boxes * CGLBM_NDIAG doubles (layout of
+ * cglbm_reduce); out[13 b + 12] is box b's count of non-finite values.
+ * CGLBM_ESTATE for a NULL handle, CGLBM_EINVAL for a NULL out. */
+int cglbm_reduce_noalloc(cglbm_handle *h, const double *centre, double *out, void *stream);
+
 /* Node offset of box b in the concatenated arrays, or -1. */
 int64_t cglbm_box_offset(const cglbm_handle *h, int32_t box);
 

@@ -41,7 +41,8 @@ EXPORTED = ("cglbm_query_sizes", "cglbm_init", "cglbm_step", "cglbm_moments", "c
             "cglbm_profile_begin", "cglbm_profile_end", "cglbm_destroy",
             "cglbm_last_error", "cglbm_version", "cglbm_query_sizes_d2q9", "cglbm_init_d2q9",
             "cglbm_lattice", "cglbm_variant_info_d2q9", "cglbm_state_buffer",
-            "cglbm_load_state", "cglbm_compact_variant", "cglbm_set_compact_variant")
+            "cglbm_load_state", "cglbm_compact_variant", "cglbm_set_compact_variant",
+            "cglbm_reduce_noalloc")
 # Lattices: the D3Q27 model of the paper's body and the D2Q9 model of App. A.
 LATTICES = ("d3q27", "d2q9")
 NUM_VARIANTS_D2Q9 = 4
@@ -121,6 +122,7 @@ def lib():
         L.cglbm_step.argtypes = [vp, i32, vp]
         L.cglbm_moments.argtypes = [vp, i32, u32, vp, vp]
         L.cglbm_reduce.argtypes = [vp, C.POINTER(C.c_double), vp, i32, vp]
+        L.cglbm_reduce_noalloc.argtypes = [vp, vp, vp, vp]
         L.cglbm_box_offset.argtypes = [vp, i32]
         L.cglbm_box_offset.restype = i64
         L.cglbm_compact_variant.argtypes = [vp, C.POINTER(i32)]
@@ -144,7 +146,7 @@ def lib():
         L.cglbm_version.restype = C.c_char_p
         for fn in ("cglbm_query_sizes", "cglbm_init", "cglbm_query_sizes_d2q9", "cglbm_init_d2q9",
                    "cglbm_lattice", "cglbm_variant_info_d2q9", "cglbm_step", "cglbm_moments",
-                   "cglbm_reduce", "cglbm_set_schedule", "cglbm_get_schedule", "cglbm_set_graph",
+                   "cglbm_reduce", "cglbm_reduce_noalloc", "cglbm_set_schedule", "cglbm_get_schedule", "cglbm_set_graph",
                    "cglbm_num_variants",
                    "cglbm_variant_info", "cglbm_set_variant", "cglbm_get_variant",
                    "cglbm_autotune", "cglbm_profile_begin", "cglbm_profile_end"):
@@ -328,6 +330,15 @@ class Simulation:
             c = np.ascontiguousarray(np.asarray(centres, np.float64).reshape(self.nboxes, 3))
             cptr = c.ctypes.data_as(C.POINTER(C.c_double))
         _check(lib().cglbm_reduce(self.h, cptr, out.data_ptr(), 0, _stream_ptr(self.stream)))
+        return out
+
+    def reduce_noalloc(self, out, centres=None):
+        """The diagnostics into the caller's device tensor `out` (n_boxes x
+        NDIAG float64) through the allocation-free entry point (static
+        scratch; usable under graph capture).  centres: device tensor of
+        n_boxes x 3 doubles or None."""
+        _check(lib().cglbm_reduce_noalloc(self.h, None if centres is None else centres.data_ptr(),
+                                          out.data_ptr(), _stream_ptr(self.stream)))
         return out
 
     def profile_begin(self, max_launches: int):

@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -24,6 +25,21 @@ using namespace cglbm;
 namespace {
 
 thread_local std::string g_err;
+
+// Scratch of cglbm_reduce_noalloc, a file-scope device array (each GPU the
+// library runs on holds its own copy until the process ends): the chunk
+// partials of the two reduction passes (kNPart doubles per chunk, at most
+// kScratchChunks chunks), then the per-box diagnostics (kNPart doubles per
+// box, at most kScratchBoxes boxes): 8.5 MiB.  Host code never uses the
+// array's name as an address: cglbm_init looks up its device address once
+// per device (g_scratch) and only that address is passed to kernels.
+constexpr size_t kScratchChunks = (size_t)1 << 16;
+constexpr size_t kScratchBoxes = 4096;
+constexpr size_t kScratchDoubles = (kScratchChunks + kScratchBoxes) * kNPart;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch[kMaxDevices] = {};
 
 int fail(int code, const char *fmt, ...) {
   char buf[512];
@@ -786,6 +802,21 @@ int compute_fields(cglbm_handle *h, hipStream_t s, int write_kappa) {
   return check_launch();
 }
 
+// Device address of this GPU's copy of `scratch`, looked up once per device
+// with that device current (the caller's).
+int scratch_lookup(int device) {
+  if (device < 0 || device >= kMaxDevices)
+    return fail(CGLBM_EUNSUPPORTED, "device %d beyond the library's %d", device, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[device]) return CGLBM_OK;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(CGLBM_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+  g_scratch[device] = (double *)ptr;
+  return CGLBM_OK;
+}
+
 // The diagnostics of the current state: local moments and interface fields
 // into aux, then the two chunked passes and the per-box finals (launches
 // only).  centre: device array of 3 doubles per box, or NULL for the box
@@ -1011,6 +1042,7 @@ int init_handle(int lattice, cglbm_handle **out, int32_t n_boxes, const cglbm_bo
           hipSuccess) {
     return cleanup(fail(CGLBM_EHIP, "init: %s", hipGetErrorString(e)));
   }
+  if ((rc = scratch_lookup(h->device))) return cleanup(rc);
   if (h->L.walls) {
     // wall stashes: the in-place layout's, or the compact schedule's pair
     size_t sb = 0, ab = 0;
@@ -1115,6 +1147,21 @@ int cglbm_reduce(cglbm_handle *h, const double *centre, double *out, int32_t out
     if (out[(size_t)b * CGLBM_NDIAG + 12] != 0.0)
       return fail(CGLBM_EUNSTABLE, "non-finite values in the state");
   return CGLBM_OK;
+}
+
+int cglbm_reduce_noalloc(cglbm_handle *h, const double *centre, double *out, void *stream) {
+  g_err.clear();
+  if (!h) return fail(CGLBM_ESTATE, "null handle");
+  if (!out) return fail(CGLBM_EINVAL, "out must not be NULL");
+  if (h->L.rch_box.size() > kScratchChunks || (size_t)h->n_boxes > kScratchBoxes)
+    return fail(CGLBM_EINVAL,
+                "%zu reduction chunks of %lld nodes and %d boxes exceed the static scratch "
+                "(at most %zu chunks and %zu boxes): use cglbm_reduce",
+                h->L.rch_box.size(), (long long)kRedChunk, h->n_boxes, kScratchChunks,
+                kScratchBoxes);
+  double *sp = h->device >= 0 && h->device < kMaxDevices ? g_scratch[h->device] : nullptr;
+  if (!sp) return fail(CGLBM_ESTATE, "scratch of device %d was not looked up", h->device);
+  return reduce_launch(h, (hipStream_t)stream, centre, sp, sp + kScratchChunks * kNPart, out);
 }
 
 int cglbm_set_schedule(cglbm_handle *h, int32_t schedule) {
