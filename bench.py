@@ -95,6 +95,11 @@ def d2q9_bytes(storage: str) -> int:
 # floats of the compact post-collision state and writes the 11 moments; the
 # fused kernel reads the moments and writes the compact state; once per
 # call the population pull starts it and the emission (17 in, 54 out) ends it.
+# With the mass-exact FP32 storage the compact state adds the two FP64 colour
+# densities (read by the pull for the node's own rest closure and written by
+# the fused kernel), and the pull writes them beside the 11 moments.
+COMPACT_BYTES_X = {"pull": 17 * 4 + 2 * 8 + 11 * 4 + 2 * 8, "fused": 11 * 4 + 2 * 8 + 17 * 4 + 2 * 8,
+                   "pull_first": 52 * 4 + 2 * 8 + 11 * 4 + 2 * 8, "emit": 17 * 4 + 2 * 8 + 52 * 4 + 2 * 8}
 COMPACT_BYTES = {"pull": 17 * 4 + 11 * 4, "fused": 11 * 4 + 17 * 4,
                  "pull_first": 54 * 4 + 11 * 4, "emit": 17 * 4 + 54 * 4}
 
@@ -152,8 +157,8 @@ def measured_valu(kernel: str):
     return None
 
 
-DEFAULT_FORMS = ("fp32_population,fp16,bf16,fp16c,bf16c,fp32x,c3,c5,batched,inplace,small,rti,"
-                 "galilean,d2q9,d2q9_fp16,d2q9_bf16,table2,parity")
+DEFAULT_FORMS = ("fp32_population,fp16,bf16,fp16c,bf16c,fp32x,fp32x_population,c3,c5,batched,"
+                 "inplace,small,rti,galilean,d2q9,d2q9_fp16,d2q9_bf16,table2,parity")
 
 
 def parse():
@@ -335,7 +340,7 @@ def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=None,
     if lattice != "d3q27":
         kb = {"fused": d2q9_bytes(storage)}
     elif sim.schedule() == 2:
-        kb = COMPACT_BYTES
+        kb = COMPACT_BYTES_X if storage == "fp32x" else COMPACT_BYTES
     else:
         kb = kernel_bytes(storage)
     kern = {}
@@ -377,20 +382,23 @@ def proxy_errors(g, ref, u_ref):
         # device tensors: norms on the device, in FP64
         rho_g = (g["rho_r"].double() + g["rho_b"].double())
         rho_f = (ref["rho_r"].double() + ref["rho_b"].double())
-        rel = (rho_g - rho_f).abs() / rho_f
+        fluid = rho_f > 0  # solid wall nodes hold zero moments
+        rel = ((rho_g - rho_f).abs() / rho_f)[fluid]
         du = ((g["ux"].double() - ref["ux"].double()) ** 2 + (g["uy"].double() - ref["uy"].double()) ** 2
-              + (g["uz"].double() - ref["uz"].double()) ** 2).sqrt()
+              + (g["uz"].double() - ref["uz"].double()) ** 2).sqrt()[fluid]
         return {"e_rho": float(rel.max()), "e_u": float(du.max() / u_ref),
-                "e_phi": float((g["phi"].double() - ref["phi"].double()).abs().max()),
+                "e_phi": float((g["phi"].double() - ref["phi"].double()).abs()[fluid].max()),
                 "e_rho_l2": float((rel ** 2).mean().sqrt()),
                 "e_u_l2": float((du ** 2).mean().sqrt() / u_ref)}
     g = {k: np_(v) for k, v in g.items()}
     ref = {k: np_(v) for k, v in ref.items()}
     rho_g, rho_f = g["rho_r"] + g["rho_b"], ref["rho_r"] + ref["rho_b"]
-    du = np.sqrt((g["ux"] - ref["ux"]) ** 2 + (g["uy"] - ref["uy"]) ** 2 + (g["uz"] - ref["uz"]) ** 2)
-    return {"e_rho": float((np.abs(rho_g - rho_f) / rho_f).max()),
-            "e_u": float(du.max() / u_ref), "e_phi": float(np.abs(g["phi"] - ref["phi"]).max()),
-            "e_rho_l2": float(np.sqrt((((rho_g - rho_f) / rho_f) ** 2).mean())),
+    m = rho_f > 0  # solid wall nodes hold zero moments
+    du = np.sqrt((g["ux"] - ref["ux"]) ** 2 + (g["uy"] - ref["uy"]) ** 2 + (g["uz"] - ref["uz"]) ** 2)[m]
+    rel = (np.abs(rho_g - rho_f)[m] / rho_f[m])
+    return {"e_rho": float(rel.max()),
+            "e_u": float(du.max() / u_ref), "e_phi": float(np.abs(g["phi"] - ref["phi"])[m].max()),
+            "e_rho_l2": float(np.sqrt((rel ** 2).mean())),
             "e_u_l2": float(np.sqrt((du ** 2).mean()) / u_ref)}
 
 
@@ -774,14 +782,19 @@ def main():
     ref_fields = main_r["fields"]
     for f in forms_req:
         if f in STORAGES:
+            # the FP32 formats run the compact schedule (the mass-exact one
+            # with its FP64 colour densities), the 16-bit ones the population
+            # schedule (the compact state would hold them in FP32)
             r = run_form([w], f, args.steps, args.warmup, args.variant, keep_fields="device",
-                         drift_steps=DRIFT_STEPS)
+                         drift_steps=DRIFT_STEPS,
+                         schedule=2 if f in ("fp32", "fp32p", "fp32x") else None)
             forms[f] = storage_form(r, f, ref_fields, u_ref)
             del r["fields"]
-        elif f == "fp32_population":
-            r = run_form([w], "fp32", args.steps, args.warmup, args.variant, schedule=0,
+        elif f in ("fp32_population", "fp32x_population"):
+            st = f.split("_")[0]
+            r = run_form([w], st, args.steps, args.warmup, args.variant, schedule=0,
                          drift_steps=DRIFT_STEPS)
-            forms[f] = storage_form(r, "fp32")
+            forms[f] = storage_form(r, st)
         elif f == "c3":
             w3 = WL.sheared_droplets()
             forms["c3"] = big_form("512^3 periodic, 8 droplets R U[20,48], density ratio 1000, "
