@@ -158,7 +158,8 @@ typedef struct cglbm_handle cglbm_handle;
 
 /* Bytes the caller must provide: pop_bytes for EACH of the two population
  * buffers, aux_bytes for the auxiliary field buffer.  Pure host computation;
- * validates the parameters.  Returns CGLBM_EINVAL on bad parameters. */
+ * validates the parameters.  Returns CGLBM_EINVAL on bad parameters
+ * (including more than 4096 boxes per handle). */
 int cglbm_query_sizes(int32_t n_boxes, const cglbm_box_params *boxes, int32_t storage,
                       size_t *pop_bytes, size_t *aux_bytes, int64_t *total_nodes);
 
@@ -269,8 +270,9 @@ int cglbm_reduce(cglbm_handle *h, const double *centre, double *out, int32_t out
  * hipMalloc.  The call allocates nothing and never synchronizes: its
  * reduction scratch is a static device array of the library (8.5 MiB per
  * GPU, held until the process ends), used for at most 65536 reduction chunks
- * of 16384 nodes (about 1.07e9 nodes) and 4096 boxes; larger handles get
- * CGLBM_EINVAL (use cglbm_reduce).  Every call on one GPU shares that array:
+ * of 16384 nodes (about 1.07e9 nodes) and 4096 boxes, which every handle
+ * fits (at most 2^29 - 2^20 nodes and 4096 boxes); the call still checks and
+ * returns CGLBM_EINVAL beyond.  Every call on one GPU shares that array:
  * calls that overlap on one GPU (other streams, other threads, other
  * handles) race and must be ordered by the caller.
  * centre: device array of 3 doubles per box, or NULL for the box centres.

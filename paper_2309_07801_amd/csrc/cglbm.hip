@@ -164,6 +164,10 @@ struct Layout {
   int64_t wtotal = 0;             // wall-node slots of all boxes (stash plane length)
   int64_t total = 0;  // plane length (nodes, all boxes, aligned)
   int32_t nblk = 0, ntile = 0, ncol = 0, nblk_pad = 0;
+  // D3Q27: col_box and ccol_box hold first the tiles that run the kernel
+  // without wall logic (ncol_plain, nccol_plain entries, padded to a
+  // multiple of 8), then those whose stencils or rings reach a solid layer
+  int32_t ncol_plain = 0, nccol_plain = 0;
   bool walls = false;
   bool general = false;  // a box with Model A, B or C or without Q: three-kernel schedule
   bool full_rates = false;  // a box with a higher-order rate other than 1
@@ -172,6 +176,8 @@ struct Layout {
 
 int validate(int32_t n_boxes, const cglbm_box_params *boxes, int32_t storage) {
   if (n_boxes <= 0 || !boxes) return fail(CGLBM_EINVAL, "n_boxes must be > 0 and boxes non-NULL");
+  if (n_boxes > kMaxTileBoxes)
+    return fail(CGLBM_EINVAL, "at most %d boxes per handle", (int)kMaxTileBoxes);
   if (storage < CGLBM_FP32 || storage > CGLBM_BF16_CSHIFT)
     return fail(CGLBM_EINVAL, "unknown storage format %d", storage);
   int64_t total = 0;
@@ -353,44 +359,76 @@ void build_layout(int32_t n_boxes, const cglbm_box_params *boxes, Layout &L,
   while ((int32_t)L.blk_box.size() < L.nblk_pad) L.blk_box.push_back(-1);
 }
 
-// Column table of k_cpull variant v: fills the per-box ccol fields.
+// Split of a box's tiles between the launch without wall logic and the one
+// with it: a tile goes to the latter if the y rows or z slabs it reads
+// (its extent widened by `halo`) come within one node of a solid layer.
+bool tile_near_walls(const BoxDev &B, int y0, int ty, int z0, int z1, int halo) {
+  const bool yw = (B.walls & 1u) && !(y0 - halo - 1 >= 1 && y0 + ty + halo <= B.ny - 2);
+  const bool zw = (B.walls & 2u) && !(z0 - halo - 1 >= 1 && z1 + halo <= B.nz - 2);
+  return yw || zw;
+}
+
+// Plain tiles first, then the tiles near walls, each list padded to a
+// multiple of 8 (the XCD remap); returns the length of the first list.
+int32_t pack_tiles(std::vector<int32_t> &out, std::vector<int32_t> &plain,
+                   std::vector<int32_t> &near) {
+  while (plain.size() % 8) plain.push_back(-1);
+  while (near.size() % 8) near.push_back(-1);
+  out = plain;
+  out.insert(out.end(), near.begin(), near.end());
+  return (int32_t)plain.size();
+}
+
+// Column table of k_cpull variant v: fills the per-box ccol fields.  Its
+// ring reaches one node around the column and one slab beyond the chunk.
 void build_ccolumns(Layout &L, int v) {
   const CPullVariant &C = cpull_variant(v);
-  L.ccol_box.clear();
-  int32_t ccol = 0;
+  std::vector<int32_t> plain, near;
   for (size_t b = 0; b < L.boxes.size(); ++b) {
     BoxDev &B = L.boxes[b];
-    B.ccol0 = ccol;
+    B.ccol0 = 0;
     B.cncx = (B.nx + C.tx - 1) / C.tx;
     B.cncy = (B.ny + C.ty - 1) / C.ty;
-    const int32_t nc = B.cncx * B.cncy * ((B.nz + C.zc - 1) / C.zc);
-    for (int32_t k = 0; k < nc; ++k) L.ccol_box.push_back((int32_t)b);
-    ccol += nc;
+    const int32_t ncz = (B.nz + C.zc - 1) / C.zc;
+    for (int32_t cz = 0; cz < ncz; ++cz)
+      for (int32_t cy = 0; cy < B.cncy; ++cy)
+        for (int32_t cx = 0; cx < B.cncx; ++cx) {
+          const int32_t t = cx + B.cncx * (cy + B.cncy * cz);
+          const int z0 = cz * C.zc, z1 = std::min(z0 + C.zc, B.nz);
+          (tile_near_walls(B, cy * C.ty, C.ty, z0, z1, 1) ? near : plain)
+              .push_back(tile_entry((int32_t)b, t));
+        }
     B.fccx = make_fastdiv((uint32_t)B.cncx);
     B.fccy = make_fastdiv((uint32_t)B.cncy);
   }
-  while ((int32_t)L.ccol_box.size() < align_up(ccol, 8)) L.ccol_box.push_back(-1);
+  L.nccol_plain = pack_tiles(L.ccol_box, plain, near);
 }
 
-// Column table of fused variant v: fills the per-box column fields.
+// Column table of fused variant v: fills the per-box column fields.  Its
+// stencils reach three nodes around the column and three slabs beyond the
+// chunk (plus the slab loaded ahead).
 void build_columns(Layout &L, int v) {
   const FusedVariant &F = fused_variant(v);
-  L.col_box.clear();
-  int32_t col = 0;
+  std::vector<int32_t> plain, near;
   for (size_t b = 0; b < L.boxes.size(); ++b) {
     BoxDev &B = L.boxes[b];
-    B.col0 = col;
+    B.col0 = 0;
     B.ncx = (B.nx + F.tx - 1) / F.tx;
     B.ncy = (B.ny + F.ty - 1) / F.ty;
     const int32_t ncz = (B.nz + F.zc - 1) / F.zc;
-    const int32_t nc = B.ncx * B.ncy * ncz;
-    for (int32_t k = 0; k < nc; ++k) L.col_box.push_back((int32_t)b);
-    col += nc;
+    for (int32_t cz = 0; cz < ncz; ++cz)
+      for (int32_t cy = 0; cy < B.ncy; ++cy)
+        for (int32_t cx = 0; cx < B.ncx; ++cx) {
+          const int32_t t = cx + B.ncx * (cy + B.ncy * cz);
+          const int z0 = cz * F.zc, z1 = std::min(z0 + F.zc, B.nz);
+          (tile_near_walls(B, cy * F.ty, F.ty, z0, z1, 4) ? near : plain)
+              .push_back(tile_entry((int32_t)b, t));
+        }
     B.fcx = make_fastdiv((uint32_t)B.ncx);
     B.fcy = make_fastdiv((uint32_t)B.ncy);
   }
-  L.ncol = (int32_t)align_up(col, 8);
-  while ((int32_t)L.col_box.size() < L.ncol) L.col_box.push_back(-1);
+  L.ncol_plain = pack_tiles(L.col_box, plain, near);
+  L.ncol = (int32_t)L.col_box.size();
 }
 
 // Tile table of the D2Q9 step kernel for variant v (kept in the column
@@ -495,6 +533,20 @@ int launch_iface(cglbm_handle *h, hipStream_t s, int write_kappa) {
   return CGLBM_OK;
 }
 
+// The fused kernel over the tiles away from walls (fn[0], the first
+// `nplain` column entries), then over those near them (fn[1], the rest).
+int launch_split(int32_t ncol, int32_t nplain, const FusedFn *fn, int nthreads, hipStream_t s,
+                 const BoxDev *boxes, const int32_t *cols, float *aux, void *dst, int64_t plane) {
+  const int32_t n[2] = {nplain, ncol - nplain};
+  for (int w = 0; w < 2; ++w) {
+    if (n[w] <= 0) continue;
+    const int32_t *c = cols + (w ? nplain : 0);
+    void *args[] = {(void *)&boxes, (void *)&c, (void *)&aux, (void *)&dst, (void *)&plane};
+    HIP_TRY(hipLaunchKernel((const void *)fn[w], dim3((unsigned)n[w]), dim3(nthreads), args, 0, s));
+  }
+  return CGLBM_OK;
+}
+
 // export == 0: interface stencils + collision of a time step; export != 0:
 // the interface fields n, F, Q, kappa into aux, populations untouched.
 // Compact schedule: the fused kernel writes the compact state into the
@@ -507,23 +559,25 @@ int launch_fused_compact(cglbm_handle *h, hipStream_t s) {
   float *aux = h->aux;
   void *dst = h->pop[1 - h->cur];
   int64_t plane = h->L.total;
-  void *args[] = {(void *)&boxes, (void *)&cols, (void *)&aux, (void *)&dst, (void *)&plane};
-  const FusedFn fn = h->storage == CGLBM_FP32_EXACT ? F.fcx[h->L.walls ? 1 : 0]
-                                                    : F.fc[h->L.walls ? 1 : 0];
-  HIP_TRY(hipLaunchKernel((const void *)fn, dim3(h->L.ncol),
-                          dim3(F.tx * F.ty), args, 0, s));
-  return CGLBM_OK;
+  const FusedFn *fn = h->storage == CGLBM_FP32_EXACT ? F.fcx : F.fc;
+  return launch_split(h->L.ncol, h->L.ncol_plain, fn, F.tx * F.ty, s, boxes, cols, aux, dst, plane);
 }
 // rd: the wall stash this step's solid points emit from; the arrivals at
 // solid nodes go to the other one
 int launch_cpull(cglbm_handle *h, hipStream_t s, int rd = 0) {
   const CPullVariant &C = cpull_variant(h->cvariant);
-  const int wk = h->L.walls ? (h->storage == CGLBM_FP32_PAIRS ? 2 : 1) : 0;
-  const CPullFn fn = h->storage == CGLBM_FP32_EXACT ? C.fx[h->L.walls ? 1 : 0]
-                                                    : C.fn[h->L.general ? 1 : 0][wk];
-  hipLaunchKernelGGL(fn, dim3((unsigned)h->L.ccol_box.size()), dim3(C.tx * C.ty), 0, s,
-                     h->d_boxes, h->d_ccol_box, (const float *)h->pop[1 - h->cur], h->aux,
-                     h->L.total, (const void *)h->cstash[rd], h->cstash[1 - rd], h->L.wtotal);
+  const bool x = h->storage == CGLBM_FP32_EXACT;
+  const int g = h->L.general ? 1 : 0;
+  // the tiles away from walls, then those near them
+  const CPullFn fn[2] = {x ? C.fx[0] : C.fn[g][0],
+                         x ? C.fx[1] : C.fn[g][h->storage == CGLBM_FP32_PAIRS ? 2 : 1]};
+  const int32_t n[2] = {h->L.nccol_plain, (int32_t)h->L.ccol_box.size() - h->L.nccol_plain};
+  for (int w = 0; w < 2; ++w)
+    if (n[w] > 0)
+      hipLaunchKernelGGL(fn[w], dim3((unsigned)n[w]), dim3(C.tx * C.ty), 0, s, h->d_boxes,
+                         h->d_ccol_box + (w ? n[0] : 0), (const float *)h->pop[1 - h->cur],
+                         h->aux, h->L.total, (const void *)h->cstash[rd], h->cstash[1 - rd],
+                         h->L.wtotal);
   return CGLBM_OK;
 }
 // wi: the wall stash the last step wrote (the solid nodes' stored values)
@@ -564,11 +618,8 @@ int launch_fused(cglbm_handle *h, hipStream_t s, int export_fields) {
   float *aux = h->aux;
   void *dst = h->pop[1 - h->cur];
   int64_t plane = h->L.total;
-  void *args[] = {(void *)&boxes, (void *)&cols, (void *)&aux, (void *)&dst, (void *)&plane};
-  const int w = h->L.walls ? 1 : 0;
-  const FusedFn fn = export_fields ? F.fx[w] : F.fn[h->storage][w];
-  HIP_TRY(hipLaunchKernel((const void *)fn, dim3(h->L.ncol), dim3(F.tx * F.ty), args, 0, s));
-  return CGLBM_OK;
+  const FusedFn *fn = export_fields ? F.fx : F.fn[h->storage];
+  return launch_split(h->L.ncol, h->L.ncol_plain, fn, F.tx * F.ty, s, boxes, cols, aux, dst, plane);
 }
 
 // Select fused variant v: rebuild and upload the column tables.

@@ -50,7 +50,7 @@ struct BoxDev {
   int32_t tnx, tny;     // tiles along x, y
   FastDiv fdx, fdy;     // division by nx, ny
   FastDiv ftx, fty;     // division by tnx, tny
-  int32_t col0;         // first column block of the box (k_fused)
+  int32_t col0;         // unused (column blocks carry their box and tile: tile_entry)
   int32_t ncx, ncy;     // columns along x, y
   FastDiv fcx, fcy;     // division by ncx, ncy
   float cs2r, cs2b;     // (c_s^k)^2 = xi (1 - alpha_k)
@@ -72,13 +72,24 @@ struct BoxDev {
   int32_t d2q9;         // 1: two-dimensional box of the D2Q9 lattice (App. A)
   int32_t wbase, wn;    // wall-node slots of the box in the in-place stash
   int32_t wblk0;        // first block of the box in k_wall_copy
-  int32_t ccol0;        // first column block of the box (k_cpull)
+  int32_t ccol0;        // unused (see col0)
   int32_t rch0;         // first reduction chunk of the box (k_reduce1, k_reduce2)
   int32_t cncx, cncy;   // k_cpull columns along x, y
   FastDiv fccx, fccy;   // division by cncx, cncy
 };
 
 constexpr int kBlock = 256;
+
+// Column-block entries of k_fused and k_cpull: the box in the low 12 bits,
+// the box's tile (column x chunk) index above them; -1 for padding blocks.
+// Each launch gets its own list, so that a box's tiles can be split between
+// launches (the tiles away from solid layers run the kernel without wall
+// logic).
+constexpr int kTileBoxBits = 12;
+constexpr int32_t kMaxTileBoxes = 1 << kTileBoxBits;
+__host__ __device__ constexpr int32_t tile_entry(int32_t box, int32_t tile) {
+  return (tile << kTileBoxBits) | box;
+}
 
 // Plane p of a SoA array: a uniform (scalar) base pointer.  Node offsets are
 // 32-bit (the host limits all boxes together to 2^30 nodes), so every access
@@ -839,19 +850,23 @@ __device__ __forceinline__ void emit_recoloured(const BoxDev &B, const float (&k
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int b = 0; b < 3; ++b)
-      cm_to_pop_1d(k[a + 3 * b], k[a + 3 * b + 9], k[a + 3 * b + 18], uz, g[a][b][0], g[a][b][1],
-                   g[a][b][2]);
+      cm_to_pop_1d_x2(k[a + 3 * b], k[a + 3 * b + 9], k[a + 3 * b + 18], uz, g[a][b][0],
+                      g[a][b][1], g[a][b][2]);
   float h[3][3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int cz = 0; cz < 3; ++cz)
-      cm_to_pop_1d(g[a][0][cz], g[a][1][cz], g[a][2][cz], uy, h[a][0][cz], h[a][1][cz],
-                   h[a][2][cz]);
+      cm_to_pop_1d_x2(g[a][0][cz], g[a][1][cz], g[a][2][cz], uy, h[a][0][cz], h[a][1][cz],
+                      h[a][2][cz]);
 #pragma unroll
   for (int cz = 0; cz < 3; ++cz)
 #pragma unroll
     for (int cy = 0; cy < 3; ++cy) {
+      // the z and y passes leave 2^(|c_y| + |c_z|) on this row: the colour
+      // fractions take its inverse (exact), the x pass keeps plain outputs
+      const float sc = 1.0f / (float)(1 << ((cy != 1) + (cz != 1)));
+      const float crs = sc * cr, cbs = sc * cb;
       float fx[3];
       cm_to_pop_1d(h[0][cy][cz], h[1][cy][cz], h[2][cy][cz], ux, fx[0], fx[1], fx[2]);
 #pragma unroll
@@ -861,7 +876,7 @@ __device__ __forceinline__ void emit_recoloured(const BoxDev &B, const float (&k
                          (kCY[i] ? (kCY[i] > 0 ? Ry : -Ry) : 0.f) +
                          (kCZ[i] ? (kCZ[i] > 0 ? Rz : -Rz) : 0.f);
         const float d = 3.0f * weight(i) * cR;
-        emit(i, fmaf(cr, fx[cx], d), fmaf(cb, fx[cx], -d));
+        emit(i, fmaf(crs, fx[cx], d), fmaf(cbs, fx[cx], -d));
       }
     }
 }
@@ -1413,10 +1428,11 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
 
   const int tid = threadIdx.x;
   const uint32_t lb = xcd_block();
-  const int b = col_box[lb];
-  if (b < 0) return;
+  const int32_t te = col_box[lb];
+  if (te < 0) return;
+  const int b = te & (kMaxTileBoxes - 1);
   const BoxDev B = boxes[b];
-  const uint32_t t = lb - B.col0;
+  const uint32_t t = (uint32_t)te >> kTileBoxBits;
   const uint32_t tyz = fdiv(t, B.fcx);
   const int cx = (int)(t - tyz * (uint32_t)B.ncx);
   const int cz = (int)fdiv(tyz, B.fcy);
@@ -1899,10 +1915,11 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
   __shared__ float xb[18][G::R1];  // one z component: 9 directions x 2 colours
   const int tid = threadIdx.x;
   const uint32_t lb = xcd_block();
-  const int b = ccol_box[lb];
-  if (b < 0) return;
+  const int32_t te = ccol_box[lb];
+  if (te < 0) return;
+  const int b = te & (kMaxTileBoxes - 1);
   const BoxDev B = boxes[b];
-  const uint32_t t = lb - (uint32_t)B.ccol0;
+  const uint32_t t = (uint32_t)te >> kTileBoxBits;
   const uint32_t tyz = fdiv(t, B.fccx);
   const int cxi = (int)(t - tyz * (uint32_t)B.cncx);
   const int czi = (int)fdiv(tyz, B.fccy);
@@ -1956,12 +1973,9 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
     const int gz = wrap_any(s, nz);
     const uint32_t zoff = (uint32_t)B.base + nxy * (uint32_t)gz;
     bool rsolid[G::CP];
-    uint32_t rslot[G::CP];
 #pragma unroll
-    for (int k = 0; k < G::CP; ++k) {
+    for (int k = 0; k < G::CP; ++k)
       rsolid[k] = WALLS && tid + k * G::NT < G::R1 && is_solid(B, rgy[k], gz);
-      rslot[k] = rsolid[k] ? (uint32_t)B.wbase + wall_slot(B, rgx[k], rgy[k], gz) : 0u;
-    }
     // the column node's FP64 colour densities at slab s (its ring point k = 0)
     double own_r = 0.0, own_b = 0.0;
     if constexpr (EXACT) {
@@ -1983,14 +1997,14 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
       for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int bb = 0; bb < 3; ++bb)
-          cm_to_pop_1d(o.k[a + 3 * bb], o.k[a + 3 * bb + 9], o.k[a + 3 * bb + 18], o.uz, g[a][bb][0],
-                       g[a][bb][1], g[a][bb][2]);
+          cm_to_pop_1d(o.k[a + 3 * bb], o.k[a + 3 * bb + 9], o.k[a + 3 * bb + 18], o.uz,
+                       g[a][bb][0], g[a][bb][1], g[a][bb][2]);
 #pragma unroll
       for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int cz = 0; cz < 3; ++cz)
-          cm_to_pop_1d(g[a][0][cz], g[a][1][cz], g[a][2][cz], o.uy, h[k][a][0][cz], h[k][a][1][cz],
-                       h[k][a][2][cz]);
+          cm_to_pop_1d(g[a][0][cz], g[a][1][cz], g[a][2][cz], o.uy, h[k][a][0][cz],
+                       h[k][a][1][cz], h[k][a][2][cz]);
       pux[k] = o.ux;
       pcr[k] = o.cr;
       pcb[k] = o.cb;
@@ -2010,8 +2024,11 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
         if (j < G::R1) {
 #pragma unroll
           for (int cy = 0; cy < 3; ++cy) {
+            // (the plain maps here: the doubled ones of emit_recoloured give
+            // the same bits but cost this kernel 8 VGPRs and an occupancy step)
             float fx[3];
-            cm_to_pop_1d(h[k][0][cy][pz], h[k][1][cy][pz], h[k][2][cy][pz], pux[k], fx[0], fx[1], fx[2]);
+            cm_to_pop_1d(h[k][0][cy][pz], h[k][1][cy][pz], h[k][2][cy][pz], pux[k], fx[0], fx[1],
+                         fx[2]);
 #pragma unroll
             for (int cx = 0; cx < 3; ++cx) {
               const int i = dir_of(cx - 1, cy - 1, pz - 1);
@@ -2020,20 +2037,7 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
                                (kCZ[i] ? (kCZ[i] > 0 ? pRz[k] : -pRz[k]) : 0.f);
               const float d = 3.0f * weight(i) * cR;
               const int q = 3 * cy + cx;
-              float vr = fmaf(pcr[k], fx[cx], d), vb = fmaf(pcb[k], fx[cx], -d);
-              if (WALLS && rsolid[k]) {
-                // a solid point emits what the bounce-back stored there (its
-                // rest population, which only it receives, stays in the stash)
-                if (!(EXACT && i == 0)) {
-                  const Pops<S> win(const_cast<void *>(wst_in), wplane);
-                  typename S::T er, eb;
-                  ld_rb(win, i, rslot[k], er, eb);
-                  vr = S::dec(er);
-                  vb = S::dec(eb);
-                } else {
-                  vr = vb = 0.f;
-                }
-              }
+              const float vr = fmaf(pcr[k], fx[cx], d), vb = fmaf(pcb[k], fx[cx], -d);
               if (EXACT && k == 0 && i != 0) {
                 emit_r += (double)vr;
                 emit_b += (double)vb;
@@ -2042,6 +2046,33 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
               xb[2 * q][slot] = vr;
               xb[2 * q + 1][slot] = vb;
             }
+          }
+          if (WALLS && rsolid[k]) {
+            // A solid point emits what the bounce-back stored there instead
+            // (its rest population, which only it receives, stays in the
+            // stash): one branch per point and z component, after the
+            // unbranched emission above, so that the hot loop stays one
+            // basic block.  (A solid column node's own sums above feed only
+            // its own moments, which are stored as zero.)
+            const Pops<S> win(const_cast<void *>(wst_in), wplane);
+            const uint32_t wslot = (uint32_t)B.wbase + wall_slot(B, rgx[k], rgy[k], gz);
+            const int slot = EXACT ? rls[k] : j;
+#pragma unroll
+            for (int cy = 0; cy < 3; ++cy)
+#pragma unroll
+              for (int cx = 0; cx < 3; ++cx) {
+                const int i = dir_of(cx - 1, cy - 1, pz - 1);
+                const int q = 3 * cy + cx;
+                float vr = 0.f, vb = 0.f;
+                if (!(EXACT && i == 0)) {
+                  typename S::T er, eb;
+                  ld_rb(win, i, wslot, er, eb);
+                  vr = S::dec(er);
+                  vb = S::dec(eb);
+                }
+                xb[2 * q][slot] = vr;
+                xb[2 * q + 1][slot] = vb;
+              }
           }
         }
       }

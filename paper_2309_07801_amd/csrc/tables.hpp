@@ -19,10 +19,10 @@ namespace cglbm {
 using FusedFn = void (*)(const BoxDev *, const int32_t *, float *, void *, int64_t);
 struct FusedVariant {
   int tx, ty, zc, minw;
-  FusedFn fn[7][2];  // time step: [storage][any box with solid layers]
-  FusedFn fx[2];     // field export (no population store): [solid layers]
-  FusedFn fc[2];     // compact schedule: compact state out (FP32): [solid layers]
-  FusedFn fcx[2];    // compact schedule, mass-exact storage (FP64 densities): [solid layers]
+  FusedFn fn[7][2];  // time step: [storage][0: tiles away from solid layers, 1: near them]
+  FusedFn fx[2];     // field export (no population store): [near solid layers]
+  FusedFn fc[2];     // compact schedule: compact state out (FP32): [near solid layers]
+  FusedFn fcx[2];    // compact schedule, mass-exact storage (FP64 densities): [near solid layers]
 };
 #define CGLBM_FV_S(TX, TY, ZC, MW, S) \
   {k_fused<TX, TY, ZC, MW, false, S, false>, k_fused<TX, TY, ZC, MW, true, S, false>}
@@ -52,9 +52,10 @@ using CPullFn = void (*)(const BoxDev *, const int32_t *, const float *, float *
                          const void *, void *, int64_t);
 struct CPullVariant {
   int tx, ty, zc;
-  // [general equilibrium family][0 periodic, 1 walls with FP32 planes, 2 walls with FP32 pairs]
+  // [general equilibrium family][0 tiles away from solid layers, 1 tiles near
+  // them with FP32 planes, 2 tiles near them with FP32 pairs]
   CPullFn fn[2][3];
-  CPullFn fx[2];  // mass-exact storage, Model D with Q: [solid layers]
+  CPullFn fx[2];  // mass-exact storage, Model D with Q: [near solid layers]
 };
 extern const CPullVariant kCPullTable[5];
 constexpr int kNumCPullVariants = 5;
