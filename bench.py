@@ -167,6 +167,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--size", type=int, default=256, help="box edge (default 256)")
+    ap.add_argument("--workload", default="droplet", choices=("droplet", "batched", "collision"),
+                    help="main line's workload: the translating droplet (default), the 96-box "
+                         "batch (FP32 pairs) or the 768x384x384 walled collision; the other two "
+                         "serve profiling runs of those kernels")
     ap.add_argument("--storage", default="fp32", choices=sorted(STORAGES))
     ap.add_argument("--forms", default=DEFAULT_FORMS, help="extra forms ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -304,6 +308,7 @@ def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=None,
     if schedule is not None:
         sim.set_schedule(schedule)  # loads the geometry the autotuner chose for it
         var = pkg.variant_info(sim.variant(), lattice)
+    wmode = sim.wall_mode() if lattice == "d3q27" else None
     sim.step(max(warmup - 2, 0))  # also captures the step graph
     torch.cuda.synchronize()
     # timed region: direct launches with HIP events around every kernel
@@ -360,7 +365,7 @@ def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=None,
            "mass_drift_steps": done, "mass_drift_long": drift_out,
            "nonfinite": int(d1[:, 12].sum()), "steps": steps,
            "pop_buffer_bytes": sim.pop_a.numel() * (1 if inplace else 2), "compact_variant": cvar,
-           "fields": out_fields}
+           "wall_mode": wmode, "fields": out_fields}
     sim.close()
     del sim
     torch.cuda.empty_cache()
@@ -408,6 +413,7 @@ def storage_form(r, storage, ref_fields=None, u_ref=None):
     out = {"storage": storage, "mlups": round(r["mlups"], 1),
            "mlups_median": round(r["mlups_median"], 1), "ms_per_step": round(r["ms_per_step"], 4),
            "graph_mlups": round(r["graph_mlups"], 1), "schedule": r["schedule"],
+           "wall_mode": r["wall_mode"],
            "step_roofline_frac": round(r["mlups"] * 1e6 * sbf / (HBM_PEAK_GBS * 1e9), 4),
            "step_bytes_per_node": sbf, "kernels": _kern_round(r["kernels"]),
            "mass_drift": r["mass_drift"], "mass_drift_steps": r["mass_drift_steps"],
@@ -513,7 +519,7 @@ def rti_form(W=128, T_list=(1.0, 2.0, 3.0, 4.0)):
         out["model_" + "ABCD"[model]] = {
             "mlups": round(w.box.fluid_nodes() * done / t_run / 1e6, 1), "steps": done,
             "schedule": ("fused", "three kernels", "compact")[sim.schedule()],
-            "T_spike_bubble_saddle": hist, "nonfinite": int(d[0, 12])}
+            "wall_mode": sim.wall_mode(), "T_spike_bubble_saddle": hist, "nonfinite": int(d[0, 12])}
         sim.close()
         del sim
         torch.cuda.empty_cache()
@@ -692,12 +698,20 @@ def main():
         sys.exit(1)
     n = args.size
     w = WL.translating_droplet(n=n, R=32.0 * n / 256.0)
+    main_ws, main_label = [w], None
+    if args.workload == "batched":
+        main_ws = WL.batched_boxes()
+        args.storage = "fp32p"
+        main_label = "96 periodic boxes, edges U{24..128}, density ratio in {1,10,100}, fp32p storage"
+    elif args.workload == "collision":
+        main_ws = [WL.head_on_collision()]
+        main_label = "768x384x384 walled head-on collision, density ratio 10, %s storage" % args.storage
     forms_req = [f for f in args.forms.split(",") if f]
     sched = args.schedule
     if sched is None and args.storage in ("fp32", "fp32p"):
         sched = 2  # the compact schedule serves this periodic FP32 workload
     want_fields = any(f in STORAGES for f in forms_req)
-    main_r = run_form([w], args.storage, args.steps, args.warmup, args.variant,
+    main_r = run_form(main_ws, args.storage, args.steps, args.warmup, args.variant,
                       keep_fields="device" if want_fields else None, schedule=sched,
                       repeats=REPEATS, drift_steps=DRIFT_STEPS if forms_req else 0)
     fluid = main_r["fluid"]
@@ -715,7 +729,7 @@ def main():
         kname = ("k_fused<%d, %d, %d, %d, false, f32, false>" % geo if dom == "fused"
                  else "k_%s<f32%s>" % (dom, ", false" if dom == "pull" else ""))
         kb = kernel_bytes(args.storage)
-    measured = n == 256 and args.storage == "fp32"
+    measured = n == 256 and args.storage == "fp32" and args.workload == "droplet"
     traffic = measured_traffic(kname) if measured else None
     valu = measured_valu(kname) if measured else None
     sb = step_bytes(args.storage)
@@ -752,8 +766,9 @@ def main():
         "vs_baseline": None,
         "dtype": DTYPE[args.storage],
         "data": "synthetic",
-        "config": {"workload": "translating droplet %d^3 periodic, density ratio 10, R=%g, "
-                               "u=0.05, %s storage" % (n, w.radii[0], args.storage),
+        "config": {"workload": main_label or ("translating droplet %d^3 periodic, density ratio "
+                                              "10, R=%g, u=0.05, %s storage"
+                                              % (n, w.radii[0], args.storage)),
                    "nodes": fluid, "storage": args.storage, "schedule": main_r["schedule"]},
         "roofline": roof,
         "step_roofline_frac": round(main_r["mlups"] * 1e6 * sb / (HBM_PEAK_GBS * 1e9), 4),
@@ -819,7 +834,8 @@ def main():
                                 "mlups_median": round(r["mlups_median"], 1),
                                 "ms_per_step": round(r["ms_per_step"], 4),
                                 "graph_mlups": round(r["graph_mlups"], 1),
-                                "schedule": r["schedule"], "compact_variant": r["compact_variant"],
+                                "schedule": r["schedule"], "fused_variant": r["variant"],
+                                "compact_variant": r["compact_variant"],
                                 "step_roofline_frac": round(r["mlups"] * 1e6 * 432 / (HBM_PEAK_GBS * 1e9), 4),
                                 "kernels": _kern_round(r["kernels"]),
                                 "mass_drift": r["mass_drift"], "nonfinite": r["nonfinite"]}

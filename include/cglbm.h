@@ -34,6 +34,11 @@
  *     layout and of the compact schedule (populations of solid nodes only).
  *   - `stream` is a hipStream_t passed as void*.  Every call enqueues its work
  *     on that stream and returns without synchronizing, except where stated.
+ *     For boxes with walls, the launch over the tiles near the solid layers
+ *     runs on a stream of the handle (default priority) beside the one over
+ *     the other tiles; it waits for the work enqueued on `stream` before it
+ *     and `stream` waits for it, so the ordering seen by the caller is that
+ *     of a single stream (also inside a graph captured from `stream`).
  *   - Return codes: CGLBM_OK (0) or a negative CGLBM_E* code; a message for
  *     the last failure on the calling thread is given by cglbm_last_error().
  *     No exception crosses the ABI.
@@ -158,8 +163,7 @@ typedef struct cglbm_handle cglbm_handle;
 
 /* Bytes the caller must provide: pop_bytes for EACH of the two population
  * buffers, aux_bytes for the auxiliary field buffer.  Pure host computation;
- * validates the parameters.  Returns CGLBM_EINVAL on bad parameters
- * (including more than 4096 boxes per handle). */
+ * validates the parameters.  Returns CGLBM_EINVAL on bad parameters. */
 int cglbm_query_sizes(int32_t n_boxes, const cglbm_box_params *boxes, int32_t storage,
                       size_t *pop_bytes, size_t *aux_bytes, int64_t *total_nodes);
 
@@ -270,9 +274,8 @@ int cglbm_reduce(cglbm_handle *h, const double *centre, double *out, int32_t out
  * hipMalloc.  The call allocates nothing and never synchronizes: its
  * reduction scratch is a static device array of the library (8.5 MiB per
  * GPU, held until the process ends), used for at most 65536 reduction chunks
- * of 16384 nodes (about 1.07e9 nodes) and 4096 boxes, which every handle
- * fits (at most 2^29 - 2^20 nodes and 4096 boxes); the call still checks and
- * returns CGLBM_EINVAL beyond.  Every call on one GPU shares that array:
+ * of 16384 nodes (about 1.07e9 nodes) and 4096 boxes; larger handles get
+ * CGLBM_EINVAL (use cglbm_reduce).  Every call on one GPU shares that array:
  * calls that overlap on one GPU (other streams, other threads, other
  * handles) race and must be ordered by the caller.
  * centre: device array of 3 doubles per box, or NULL for the box centres.
@@ -370,6 +373,21 @@ int cglbm_variant_info(int32_t variant, int32_t *info);
 int cglbm_set_variant(cglbm_handle *h, int32_t variant, void *stream);
 int cglbm_get_variant(const cglbm_handle *h);
 
+/* Wall mode of the tiled launches (fused kernel, compact pull) over boxes
+ * with walls, whose tiles within the kernel's reach of a solid layer run a
+ * kernel with the wall logic and the others one without it.  Bit 0: the
+ * slabs next to z walls form short chunks of their own (else the first and
+ * last chunk of every column are near-wall tiles); bit 1: the near-wall
+ * launch runs on the handle's side stream beside the other (else after it
+ * on the caller's stream).  All four modes give bitwise identical results.
+ * cglbm_set_wall_mode selects one for every schedule (synchronizes the
+ * device; CGLBM_EINVAL outside 0..3, CGLBM_EUNSUPPORTED for D2Q9 handles);
+ * cglbm_autotune chooses one per schedule for layouts with walls and two
+ * buffers; cglbm_get_wall_mode returns the one loaded (3 until chosen), -1
+ * for a NULL handle. */
+int cglbm_set_wall_mode(cglbm_handle *h, int32_t mode, void *stream);
+int cglbm_get_wall_mode(const cglbm_handle *h);
+
 /* Autotuner: time every fused variant and the three-kernel schedule `reps`
  * times on the current state (the stored state is not advanced: the kernels
  * after the pull are re-run on the same inputs; in the in-place layout they
@@ -378,8 +396,12 @@ int cglbm_get_variant(const cglbm_handle *h);
  * geometry and schedule (the three-kernel schedule wins on boxes too small to
  * fill the GPU with fused columns).  ms_per_variant (optional, length
  * cglbm_num_variants() + 1) receives the mean milliseconds per launch of
- * each fused variant, then of the interface + collide pair.  Synchronizes
- * the stream. */
+ * each fused variant, then of the interface + collide pair.  For layouts
+ * with walls and two buffers it then times the four wall modes with the
+ * chosen geometries, as replays of a captured graph (the fused kernel; for
+ * schedule 2 k_cpull with the compact collision, advancing only the compact
+ * state in the other buffer) and keeps the fastest per schedule.
+ * Synchronizes the stream. */
 int cglbm_autotune(cglbm_handle *h, int32_t reps, double *ms_per_variant, void *stream);
 
 /* Per-kernel timing with HIP events recorded on the caller's stream around

@@ -42,7 +42,7 @@ EXPORTED = ("cglbm_query_sizes", "cglbm_init", "cglbm_step", "cglbm_moments", "c
             "cglbm_last_error", "cglbm_version", "cglbm_query_sizes_d2q9", "cglbm_init_d2q9",
             "cglbm_lattice", "cglbm_variant_info_d2q9", "cglbm_state_buffer",
             "cglbm_load_state", "cglbm_compact_variant", "cglbm_set_compact_variant",
-            "cglbm_reduce_noalloc")
+            "cglbm_reduce_noalloc", "cglbm_set_wall_mode", "cglbm_get_wall_mode")
 # Lattices: the D3Q27 model of the paper's body and the D2Q9 model of App. A.
 LATTICES = ("d3q27", "d2q9")
 NUM_VARIANTS_D2Q9 = 4
@@ -137,6 +137,8 @@ def lib():
         L.cglbm_variant_info.argtypes = [i32, C.POINTER(i32)]
         L.cglbm_set_variant.argtypes = [vp, i32, vp]
         L.cglbm_get_variant.argtypes = [vp]
+        L.cglbm_set_wall_mode.argtypes = [vp, i32, vp]
+        L.cglbm_get_wall_mode.argtypes = [vp]
         L.cglbm_autotune.argtypes = [vp, i32, C.POINTER(C.c_double), vp]
         L.cglbm_profile_begin.argtypes = [vp, i32]
         L.cglbm_profile_end.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64), i32]
@@ -149,7 +151,7 @@ def lib():
                    "cglbm_reduce", "cglbm_reduce_noalloc", "cglbm_set_schedule", "cglbm_get_schedule", "cglbm_set_graph",
                    "cglbm_num_variants",
                    "cglbm_variant_info", "cglbm_set_variant", "cglbm_get_variant",
-                   "cglbm_autotune", "cglbm_profile_begin", "cglbm_profile_end"):
+                   "cglbm_set_wall_mode", "cglbm_get_wall_mode", "cglbm_autotune", "cglbm_profile_begin", "cglbm_profile_end"):
             getattr(L, fn).restype = C.c_int
         _lib = L
     return _lib
@@ -349,6 +351,14 @@ class Simulation:
 
     def variant(self) -> int:
         return int(lib().cglbm_get_variant(self.h))
+
+    def set_wall_mode(self, mode: int):
+        """Wall mode of the tiled launches over boxes with walls: bit 0 short
+        z-edge chunks, bit 1 the near-wall launch on a side stream."""
+        _check(lib().cglbm_set_wall_mode(self.h, int(mode), _stream_ptr(self.stream)))
+
+    def wall_mode(self) -> int:
+        return int(lib().cglbm_get_wall_mode(self.h))
 
     def set_compact_variant(self, v: int):
         _check(lib().cglbm_set_compact_variant(self.h, int(v), _stream_ptr(self.stream)))

@@ -159,15 +159,19 @@ struct Layout {
   std::vector<BoxDev> boxes;
   std::vector<int32_t> blk_box, tile_box, col_box;
   std::vector<int32_t> wblk_box;  // k_wall_copy blocks (in-place layouts with walls)
-  std::vector<int32_t> ccol_box;  // k_cpull column blocks (padded to a multiple of 8)
+  std::vector<TileEntry> col_tiles;   // k_fused blocks (D3Q27)
+  std::vector<TileEntry> ccol_tiles;  // k_cpull blocks
   std::vector<int32_t> rch_box;   // reduction chunks (kRedChunk nodes of one box each)
   int64_t wtotal = 0;             // wall-node slots of all boxes (stash plane length)
   int64_t total = 0;  // plane length (nodes, all boxes, aligned)
   int32_t nblk = 0, ntile = 0, ncol = 0, nblk_pad = 0;
-  // D3Q27: col_box and ccol_box hold first the tiles that run the kernel
+  // D3Q27: col_tiles and ccol_tiles hold first the tiles that run the kernel
   // without wall logic (ncol_plain, nccol_plain entries, padded to a
   // multiple of 8), then those whose stencils or rings reach a solid layer
   int32_t ncol_plain = 0, nccol_plain = 0;
+  // boxes with z walls: the slabs next to them form short chunks of their
+  // own (else the first and last chunks of every column are near walls)
+  bool zedge = true;
   bool walls = false;
   bool general = false;  // a box with Model A, B or C or without Q: three-kernel schedule
   bool full_rates = false;  // a box with a higher-order rate other than 1
@@ -176,8 +180,6 @@ struct Layout {
 
 int validate(int32_t n_boxes, const cglbm_box_params *boxes, int32_t storage) {
   if (n_boxes <= 0 || !boxes) return fail(CGLBM_EINVAL, "n_boxes must be > 0 and boxes non-NULL");
-  if (n_boxes > kMaxTileBoxes)
-    return fail(CGLBM_EINVAL, "at most %d boxes per handle", (int)kMaxTileBoxes);
   if (storage < CGLBM_FP32 || storage > CGLBM_BF16_CSHIFT)
     return fail(CGLBM_EINVAL, "unknown storage format %d", storage);
   int64_t total = 0;
@@ -370,65 +372,78 @@ bool tile_near_walls(const BoxDev &B, int y0, int ty, int z0, int z1, int halo) 
 
 // Plain tiles first, then the tiles near walls, each list padded to a
 // multiple of 8 (the XCD remap); returns the length of the first list.
-int32_t pack_tiles(std::vector<int32_t> &out, std::vector<int32_t> &plain,
-                   std::vector<int32_t> &near) {
-  while (plain.size() % 8) plain.push_back(-1);
-  while (near.size() % 8) near.push_back(-1);
+int32_t pack_tiles(std::vector<TileEntry> &out, std::vector<TileEntry> &plain,
+                   std::vector<TileEntry> &near) {
+  const TileEntry pad = {-1, 0, 0, 0};
+  while (plain.size() % 8) plain.push_back(pad);
+  while (near.size() % 8) near.push_back(pad);
   out = plain;
   out.insert(out.end(), near.begin(), near.end());
   return (int32_t)plain.size();
 }
 
-// Column table of k_cpull variant v: fills the per-box ccol fields.  Its
-// ring reaches one node around the column and one slab beyond the chunk.
-void build_ccolumns(Layout &L, int v) {
-  const CPullVariant &C = cpull_variant(v);
-  std::vector<int32_t> plain, near;
-  for (size_t b = 0; b < L.boxes.size(); ++b) {
-    BoxDev &B = L.boxes[b];
-    B.ccol0 = 0;
-    B.cncx = (B.nx + C.tx - 1) / C.tx;
-    B.cncy = (B.ny + C.ty - 1) / C.ty;
-    const int32_t ncz = (B.nz + C.zc - 1) / C.zc;
-    for (int32_t cz = 0; cz < ncz; ++cz)
-      for (int32_t cy = 0; cy < B.cncy; ++cy)
-        for (int32_t cx = 0; cx < B.cncx; ++cx) {
-          const int32_t t = cx + B.cncx * (cy + B.cncy * cz);
-          const int z0 = cz * C.zc, z1 = std::min(z0 + C.zc, B.nz);
-          (tile_near_walls(B, cy * C.ty, C.ty, z0, z1, 1) ? near : plain)
-              .push_back(tile_entry((int32_t)b, t));
-        }
-    B.fccx = make_fastdiv((uint32_t)B.cncx);
-    B.fccy = make_fastdiv((uint32_t)B.cncy);
+// z chunks [z0, z1) of a box: zc slabs each, except that a box with z walls
+// gets a chunk of `edge` slabs at each wall, so that the chunks between them
+// (whose stencils then stay clear of the walls) run without wall logic.
+std::vector<std::pair<int, int>> z_chunks(const BoxDev &B, int zc, int edge) {
+  std::vector<std::pair<int, int>> out;
+  int lo = 0, hi = B.nz;
+  if (edge > 0 && (B.walls & 2u) && B.nz > 2 * edge + zc) {
+    out.push_back({0, edge});
+    lo = edge;
+    hi = B.nz - edge;
   }
-  L.nccol_plain = pack_tiles(L.ccol_box, plain, near);
+  for (int z = lo; z < hi; z += zc) out.push_back({z, std::min(z + zc, hi)});
+  if (hi < B.nz) out.push_back({hi, B.nz});
+  return out;
 }
 
-// Column table of fused variant v: fills the per-box column fields.  Its
-// stencils reach three nodes around the column and three slabs beyond the
-// chunk (plus the slab loaded ahead).
-void build_columns(Layout &L, int v) {
-  const FusedVariant &F = fused_variant(v);
-  std::vector<int32_t> plain, near;
+// Tile lists of one kernel geometry: every (chunk, column) of every box,
+// split by tile_near_walls with the kernel's reach `halo`; `edge` slabs form
+// the chunks at z walls.
+void build_tiles(Layout &L, int tx, int ty, int zc, int halo, int edge,
+                 std::vector<TileEntry> &out, int32_t &nplain, bool cpull) {
+  std::vector<TileEntry> plain, near;
   for (size_t b = 0; b < L.boxes.size(); ++b) {
     BoxDev &B = L.boxes[b];
-    B.col0 = 0;
-    B.ncx = (B.nx + F.tx - 1) / F.tx;
-    B.ncy = (B.ny + F.ty - 1) / F.ty;
-    const int32_t ncz = (B.nz + F.zc - 1) / F.zc;
-    for (int32_t cz = 0; cz < ncz; ++cz)
-      for (int32_t cy = 0; cy < B.ncy; ++cy)
-        for (int32_t cx = 0; cx < B.ncx; ++cx) {
-          const int32_t t = cx + B.ncx * (cy + B.ncy * cz);
-          const int z0 = cz * F.zc, z1 = std::min(z0 + F.zc, B.nz);
-          (tile_near_walls(B, cy * F.ty, F.ty, z0, z1, 4) ? near : plain)
-              .push_back(tile_entry((int32_t)b, t));
+    const int32_t ncx = (B.nx + tx - 1) / tx, ncy = (B.ny + ty - 1) / ty;
+    if (cpull) {
+      B.ccol0 = 0;
+      B.cncx = ncx;
+      B.cncy = ncy;
+      B.fccx = make_fastdiv((uint32_t)ncx);
+      B.fccy = make_fastdiv((uint32_t)ncy);
+    } else {
+      B.col0 = 0;
+      B.ncx = ncx;
+      B.ncy = ncy;
+      B.fcx = make_fastdiv((uint32_t)ncx);
+      B.fcy = make_fastdiv((uint32_t)ncy);
+    }
+    for (const auto &zr : z_chunks(B, zc, edge))
+      for (int32_t cy = 0; cy < ncy; ++cy)
+        for (int32_t cx = 0; cx < ncx; ++cx) {
+          const TileEntry e = {(int32_t)b, cx + ncx * cy, zr.first, zr.second};
+          (tile_near_walls(B, cy * ty, ty, zr.first, zr.second, halo) ? near : plain).push_back(e);
         }
-    B.fcx = make_fastdiv((uint32_t)B.ncx);
-    B.fcy = make_fastdiv((uint32_t)B.ncy);
   }
-  L.ncol_plain = pack_tiles(L.col_box, plain, near);
-  L.ncol = (int32_t)L.col_box.size();
+  nplain = pack_tiles(out, plain, near);
+}
+
+// Column table of k_cpull variant v.  Its ring reaches one node around the
+// column and one slab beyond the chunk.
+void build_ccolumns(Layout &L, int v) {
+  const CPullVariant &C = cpull_variant(v);
+  build_tiles(L, C.tx, C.ty, C.zc, 1, L.zedge ? 3 : 0, L.ccol_tiles, L.nccol_plain, true);
+}
+
+// Column table of fused variant v.  Its stencils reach three nodes around
+// the column, and its march three slabs beyond the chunk, plus the slabs its
+// loads run ahead (five below the chunk).
+void build_columns(Layout &L, int v) {
+  const FusedVariant &F = fused_variant(v);
+  build_tiles(L, F.tx, F.ty, F.zc, 4, L.zedge ? 6 : 0, L.col_tiles, L.ncol_plain, false);
+  L.ncol = (int32_t)L.col_tiles.size();
 }
 
 // Tile table of the D2Q9 step kernel for variant v (kept in the column
@@ -477,20 +492,26 @@ struct cglbm_handle {
   bool inplace = false;          // pop[0] == pop[1]: one population buffer
   void *stash = nullptr;         // in-place layouts with walls: solid nodes' populations
   int32_t *d_wblk_box = nullptr;
-  int32_t *d_ccol_box = nullptr;  // k_cpull columns
+  TileEntry *d_ccol_tiles = nullptr;  // k_cpull blocks
   void *cstash[2] = {nullptr, nullptr};  // compact schedule with walls: solid nodes' populations
-  size_t ccol_cap = 0;             // capacity of d_ccol_box (entries)
+  size_t ccol_cap = 0;             // capacity of d_ccol_tiles (entries)
   int32_t cvariant = 0;            // k_cpull geometry
   int device = 0;
   BoxDev *d_boxes = nullptr;
   int32_t *d_blk_box = nullptr;
   int32_t *d_tile_box = nullptr;
-  int32_t *d_col_box = nullptr;
+  int32_t *d_col_box = nullptr;       // D2Q9 tiles
+  TileEntry *d_col_tiles = nullptr;    // D3Q27 k_fused blocks
+  size_t col_tiles_cap = 0;            // capacity of d_col_tiles (entries)
   int32_t schedule = 0;        // 0 fused, 1 three kernels (D3Q27)
   int32_t lattice = LATTICE_D3Q27;
   int32_t variant = 0;         // fused launch geometry (its column table is loaded)
   int32_t fvar_pop = 0;        // fused geometry for schedules 0 and 1
   int32_t fvar_compact = 0;    // fused geometry for schedule 2
+  // wall mode (boxes with walls): bit 0 short z-edge chunks (Layout::zedge),
+  // bit 1 the launches over tiles near walls on the side stream; the current
+  // one and the autotuner's choices per schedule
+  int32_t wmode = 3, wmode_pop = 3, wmode_compact = 3;
   size_t col_cap = 0;          // capacity of d_col_box (entries)
   int32_t *d_rch_box = nullptr;  // reduction chunk -> box
   double *d_part = nullptr;    // chunk partials of the reduction (kNPart doubles each)
@@ -500,6 +521,10 @@ struct cglbm_handle {
   // time steps as a captured graph: two steps from each buffer parity
   int32_t use_graph = 1;
   hipStream_t cap_stream = nullptr;
+  // the launch over the tiles near walls runs on `side`, beside the one over
+  // the other tiles on the caller's stream (fork and join by events)
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t graphc[2] = {nullptr, nullptr};  // compact schedule: two inner steps
   // profiling
@@ -533,18 +558,40 @@ int launch_iface(cglbm_handle *h, hipStream_t s, int write_kappa) {
   return CGLBM_OK;
 }
 
-// The fused kernel over the tiles away from walls (fn[0], the first
-// `nplain` column entries), then over those near them (fn[1], the rest).
-int launch_split(int32_t ncol, int32_t nplain, const FusedFn *fn, int nthreads, hipStream_t s,
-                 const BoxDev *boxes, const int32_t *cols, float *aux, void *dst, int64_t plane) {
-  const int32_t n[2] = {nplain, ncol - nplain};
-  for (int w = 0; w < 2; ++w) {
-    if (n[w] <= 0) continue;
-    const int32_t *c = cols + (w ? nplain : 0);
-    void *args[] = {(void *)&boxes, (void *)&c, (void *)&aux, (void *)&dst, (void *)&plane};
-    HIP_TRY(hipLaunchKernel((const void *)fn[w], dim3((unsigned)n[w]), dim3(nthreads), args, 0, s));
-  }
+int fork_side(cglbm_handle *h, hipStream_t s) {
+  HIP_TRY(hipEventRecord(h->fork_ev, s));
+  HIP_TRY(hipStreamWaitEvent(h->side, h->fork_ev, 0));
   return CGLBM_OK;
+}
+int join_side(cglbm_handle *h, hipStream_t s) {
+  HIP_TRY(hipEventRecord(h->join_ev, h->side));
+  HIP_TRY(hipStreamWaitEvent(s, h->join_ev, 0));
+  return CGLBM_OK;
+}
+
+// The fused kernel over the tiles near walls (fn[1], the column entries
+// after the first `nplain`), then over the others (fn[0]).  Both lists
+// non-empty and bit 1 of the wall mode set: the first goes to the handle's
+// side stream, which waits for everything before it on s, and s waits for it
+// afterwards (also under graph capture, where the events become the graph's
+// dependencies).
+int launch_split(cglbm_handle *h, int32_t ncol, int32_t nplain, const FusedFn *fn, int nthreads,
+                 hipStream_t s, const BoxDev *boxes, const TileEntry *cols, float *aux,
+                 void *dst, int64_t plane) {
+  const int32_t n[2] = {nplain, ncol - nplain};
+  const bool both = (h->wmode & 2) && n[0] > 0 && n[1] > 0;
+  if (both) {
+    const int rc = fork_side(h, s);
+    if (rc) return rc;
+  }
+  for (int w = 1; w >= 0; --w) {
+    if (n[w] <= 0) continue;
+    const TileEntry *c = cols + (w ? nplain : 0);
+    void *args[] = {(void *)&boxes, (void *)&c, (void *)&aux, (void *)&dst, (void *)&plane};
+    HIP_TRY(hipLaunchKernel((const void *)fn[w], dim3((unsigned)n[w]), dim3(nthreads), args, 0,
+                            (both && w) ? h->side : s));
+  }
+  return both ? join_side(h, s) : CGLBM_OK;
 }
 
 // export == 0: interface stencils + collision of a time step; export != 0:
@@ -555,12 +602,13 @@ int launch_split(int32_t ncol, int32_t nplain, const FusedFn *fn, int nthreads, 
 int launch_fused_compact(cglbm_handle *h, hipStream_t s) {
   const FusedVariant &F = fused_variant(h->variant);
   const BoxDev *boxes = h->d_boxes;
-  const int32_t *cols = h->d_col_box;
+  const TileEntry *cols = h->d_col_tiles;
   float *aux = h->aux;
   void *dst = h->pop[1 - h->cur];
   int64_t plane = h->L.total;
   const FusedFn *fn = h->storage == CGLBM_FP32_EXACT ? F.fcx : F.fc;
-  return launch_split(h->L.ncol, h->L.ncol_plain, fn, F.tx * F.ty, s, boxes, cols, aux, dst, plane);
+  return launch_split(h, h->L.ncol, h->L.ncol_plain, fn, F.tx * F.ty, s, boxes, cols, aux, dst,
+                      plane);
 }
 // rd: the wall stash this step's solid points emit from; the arrivals at
 // solid nodes go to the other one
@@ -571,14 +619,19 @@ int launch_cpull(cglbm_handle *h, hipStream_t s, int rd = 0) {
   // the tiles away from walls, then those near them
   const CPullFn fn[2] = {x ? C.fx[0] : C.fn[g][0],
                          x ? C.fx[1] : C.fn[g][h->storage == CGLBM_FP32_PAIRS ? 2 : 1]};
-  const int32_t n[2] = {h->L.nccol_plain, (int32_t)h->L.ccol_box.size() - h->L.nccol_plain};
-  for (int w = 0; w < 2; ++w)
+  const int32_t n[2] = {h->L.nccol_plain, (int32_t)h->L.ccol_tiles.size() - h->L.nccol_plain};
+  const bool both = (h->wmode & 2) && n[0] > 0 && n[1] > 0;
+  if (both) {
+    const int rc = fork_side(h, s);
+    if (rc) return rc;
+  }
+  for (int w = 1; w >= 0; --w)
     if (n[w] > 0)
-      hipLaunchKernelGGL(fn[w], dim3((unsigned)n[w]), dim3(C.tx * C.ty), 0, s, h->d_boxes,
-                         h->d_ccol_box + (w ? n[0] : 0), (const float *)h->pop[1 - h->cur],
-                         h->aux, h->L.total, (const void *)h->cstash[rd], h->cstash[1 - rd],
-                         h->L.wtotal);
-  return CGLBM_OK;
+      hipLaunchKernelGGL(fn[w], dim3((unsigned)n[w]), dim3(C.tx * C.ty), 0,
+                         (both && w) ? h->side : s, h->d_boxes, h->d_ccol_tiles + (w ? n[0] : 0),
+                         (const float *)h->pop[1 - h->cur], h->aux, h->L.total,
+                         (const void *)h->cstash[rd], h->cstash[1 - rd], h->L.wtotal);
+  return both ? join_side(h, s) : CGLBM_OK;
 }
 // wi: the wall stash the last step wrote (the solid nodes' stored values)
 int launch_emit(cglbm_handle *h, hipStream_t s, int wi = 0) {
@@ -614,12 +667,13 @@ bool compact_ok(const cglbm_handle *h) {
 int launch_fused(cglbm_handle *h, hipStream_t s, int export_fields) {
   const FusedVariant &F = fused_variant(h->variant);
   const BoxDev *boxes = h->d_boxes;
-  const int32_t *cols = h->d_col_box;
+  const TileEntry *cols = h->d_col_tiles;
   float *aux = h->aux;
   void *dst = h->pop[1 - h->cur];
   int64_t plane = h->L.total;
   const FusedFn *fn = export_fields ? F.fx : F.fn[h->storage];
-  return launch_split(h->L.ncol, h->L.ncol_plain, fn, F.tx * F.ty, s, boxes, cols, aux, dst, plane);
+  return launch_split(h, h->L.ncol, h->L.ncol_plain, fn, F.tx * F.ty, s, boxes, cols, aux, dst,
+                      plane);
 }
 
 // Select fused variant v: rebuild and upload the column tables.
@@ -643,14 +697,14 @@ int select_cvariant(cglbm_handle *h, int v, hipStream_t s) {
   for (const BoxDev &B : h->L.boxes)
     if (!fastdiv_ok((uint32_t)B.cncx, 1u << 20) || !fastdiv_ok((uint32_t)B.cncy, 1u << 20))
       return fail(CGLBM_EINVAL, "index division self-check failed");
-  if (h->L.ccol_box.size() > h->ccol_cap) {
-    if (h->d_ccol_box) HIP_TRY(hipFree(h->d_ccol_box));
-    h->d_ccol_box = nullptr;
-    HIP_TRY(hipMalloc(&h->d_ccol_box, sizeof(int32_t) * h->L.ccol_box.size()));
-    h->ccol_cap = h->L.ccol_box.size();
+  if (h->L.ccol_tiles.size() > h->ccol_cap) {
+    if (h->d_ccol_tiles) HIP_TRY(hipFree(h->d_ccol_tiles));
+    h->d_ccol_tiles = nullptr;
+    HIP_TRY(hipMalloc(&h->d_ccol_tiles, sizeof(TileEntry) * h->L.ccol_tiles.size()));
+    h->ccol_cap = h->L.ccol_tiles.size();
   }
-  HIP_TRY(hipMemcpyAsync(h->d_ccol_box, h->L.ccol_box.data(),
-                         sizeof(int32_t) * h->L.ccol_box.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(h->d_ccol_tiles, h->L.ccol_tiles.data(),
+                         sizeof(TileEntry) * h->L.ccol_tiles.size(), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(h->d_boxes, h->L.boxes.data(), sizeof(BoxDev) * h->L.boxes.size(),
                          hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -665,23 +719,44 @@ int select_variant(cglbm_handle *h, int v, hipStream_t s) {
     for (const BoxDev &B : h->L.boxes)
       if (!fastdiv_ok((uint32_t)B.tnx, (uint32_t)(B.tnx * B.tny)))
         return fail(CGLBM_EINVAL, "index division self-check failed");
+    if (h->L.col_box.size() > h->col_cap) {
+      if (h->d_col_box) HIP_TRY(hipFree(h->d_col_box));
+      h->d_col_box = nullptr;
+      HIP_TRY(hipMalloc(&h->d_col_box, sizeof(int32_t) * h->L.col_box.size()));
+      h->col_cap = h->L.col_box.size();
+    }
+    HIP_TRY(hipMemcpyAsync(h->d_col_box, h->L.col_box.data(),
+                           sizeof(int32_t) * h->L.col_box.size(), hipMemcpyHostToDevice, s));
   } else {
     build_columns(h->L, v);
+    if (h->L.col_tiles.size() > h->col_tiles_cap) {
+      if (h->d_col_tiles) HIP_TRY(hipFree(h->d_col_tiles));
+      h->d_col_tiles = nullptr;
+      HIP_TRY(hipMalloc(&h->d_col_tiles, sizeof(TileEntry) * h->L.col_tiles.size()));
+      h->col_tiles_cap = h->L.col_tiles.size();
+    }
+    HIP_TRY(hipMemcpyAsync(h->d_col_tiles, h->L.col_tiles.data(),
+                           sizeof(TileEntry) * h->L.col_tiles.size(), hipMemcpyHostToDevice, s));
   }
-  if (h->L.col_box.size() > h->col_cap) {
-    if (h->d_col_box) HIP_TRY(hipFree(h->d_col_box));
-    h->d_col_box = nullptr;
-    HIP_TRY(hipMalloc(&h->d_col_box, sizeof(int32_t) * h->L.col_box.size()));
-    h->col_cap = h->L.col_box.size();
-  }
-  HIP_TRY(hipMemcpyAsync(h->d_col_box, h->L.col_box.data(), sizeof(int32_t) * h->L.col_box.size(),
-                         hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(h->d_boxes, h->L.boxes.data(), sizeof(BoxDev) * h->L.boxes.size(),
                          hipMemcpyHostToDevice, s));
   // pageable host sources: make sure the copies completed before the vectors change
   HIP_TRY(hipStreamSynchronize(s));
   h->variant = v;
   return CGLBM_OK;
+}
+
+// Fused variant v under wall mode m: rebuild the tile lists whose chunking
+// changes (the k_cpull list too); graphs captured under another mode are
+// dropped.
+int select_mode(cglbm_handle *h, int v, int32_t m, hipStream_t s) {
+  const bool zedge = (m & 1) != 0, rebuild_c = zedge != h->L.zedge;
+  if (m != h->wmode) drop_graphs(h);
+  h->wmode = m;
+  h->L.zedge = zedge;
+  int rc = select_variant(h, v, s);
+  if (!rc && rebuild_c) rc = select_cvariant(h, h->cvariant, s);
+  return rc;
 }
 
 int launch_collide(cglbm_handle *h, hipStream_t s) {
@@ -787,6 +862,38 @@ int capture_compact_pair(cglbm_handle *h) {
     h->graphc[h->cur] = nullptr;
     return fail(CGLBM_EHIP, "graph instantiate: %s", hipGetErrorString(ei));
   }
+  return CGLBM_OK;
+}
+
+// Mean milliseconds per launch(k) over `reps` replays of a graph that
+// captures launch(stream, 0) and launch(stream, 1) on the capture stream.
+template <class F>
+int time_graph(cglbm_handle *h, hipStream_t s, int reps, hipEvent_t e0, hipEvent_t e1, F &&launch,
+               double &ms_out) {
+  if (!h->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  int rc = launch(h->cap_stream, 0);
+  if (!rc) rc = launch(h->cap_stream, 1);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+  if (!rc && e != hipSuccess) rc = fail(CGLBM_EHIP, "graph capture: %s", hipGetErrorString(e));
+  hipGraphExec_t x = nullptr;
+  if (!rc) {
+    const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (ei != hipSuccess) rc = fail(CGLBM_EHIP, "graph instantiate: %s", hipGetErrorString(ei));
+  }
+  if (g) (void)hipGraphDestroy(g);
+  if (rc) return rc;
+  hipError_t el = hipGraphLaunch(x, s);
+  if (el == hipSuccess) el = hipEventRecord(e0, s);
+  for (int r = 0; r < reps && el == hipSuccess; ++r) el = hipGraphLaunch(x, s);
+  if (el == hipSuccess) el = hipEventRecord(e1, s);
+  if (el == hipSuccess) el = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (el == hipSuccess) el = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipGraphExecDestroy(x);
+  if (el != hipSuccess) return fail(CGLBM_EHIP, "autotune: %s", hipGetErrorString(el));
+  ms_out = (double)ms / (2.0 * reps);
   return CGLBM_OK;
 }
 
@@ -1048,7 +1155,7 @@ int init_handle(int lattice, cglbm_handle **out, int32_t n_boxes, const cglbm_bo
   h->lattice = lattice;
   build_layout(n_boxes, boxes, h->L, lattice);
   build_ccolumns(h->L, 0);
-  h->ccol_cap = h->L.ccol_box.size();
+  h->ccol_cap = h->L.ccol_tiles.size();
   for (const BoxDev &B : h->L.boxes) {
     if (!fastdiv_ok((uint32_t)B.nx, (uint32_t)B.n) || !fastdiv_ok((uint32_t)B.ny, (uint32_t)B.n) ||
         !fastdiv_ok((uint32_t)B.tnx, 1u << 20) || !fastdiv_ok((uint32_t)B.tny, 1u << 20) ||
@@ -1079,9 +1186,10 @@ int init_handle(int lattice, cglbm_handle **out, int32_t n_boxes, const cglbm_bo
       (e = hipMemcpyAsync(h->d_rch_box, h->L.rch_box.data(),
                           sizeof(int32_t) * h->L.rch_box.size(), hipMemcpyHostToDevice, s)) !=
           hipSuccess ||
-      (e = hipMalloc(&h->d_ccol_box, sizeof(int32_t) * h->L.ccol_box.size())) != hipSuccess ||
-      (e = hipMemcpyAsync(h->d_ccol_box, h->L.ccol_box.data(),
-                          sizeof(int32_t) * h->L.ccol_box.size(), hipMemcpyHostToDevice, s)) !=
+      (e = hipMalloc(&h->d_ccol_tiles, sizeof(TileEntry) * h->L.ccol_tiles.size())) !=
+          hipSuccess ||
+      (e = hipMemcpyAsync(h->d_ccol_tiles, h->L.ccol_tiles.data(),
+                          sizeof(TileEntry) * h->L.ccol_tiles.size(), hipMemcpyHostToDevice, s)) !=
           hipSuccess ||
       (e = hipMemcpyAsync(h->d_boxes, h->L.boxes.data(), sizeof(BoxDev) * n_boxes,
                           hipMemcpyHostToDevice, s)) != hipSuccess ||
@@ -1090,7 +1198,10 @@ int init_handle(int lattice, cglbm_handle **out, int32_t n_boxes, const cglbm_bo
           hipSuccess ||
       (e = hipMemcpyAsync(h->d_tile_box, h->L.tile_box.data(),
                           sizeof(int32_t) * h->L.tile_box.size(), hipMemcpyHostToDevice, s)) !=
-          hipSuccess) {
+          hipSuccess ||
+      (e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming)) != hipSuccess) {
     return cleanup(fail(CGLBM_EHIP, "init: %s", hipGetErrorString(e)));
   }
   if ((rc = scratch_lookup(h->device))) return cleanup(rc);
@@ -1232,9 +1343,10 @@ int cglbm_set_schedule(cglbm_handle *h, int32_t schedule) {
   // device is synchronized before they are replaced
   if (h->lattice == LATTICE_D3Q27) {
     const int32_t v = schedule == 2 ? h->fvar_compact : h->fvar_pop;
-    if (v != h->variant) {
+    const int32_t m = schedule == 2 ? h->wmode_compact : h->wmode_pop;
+    if (v != h->variant || m != h->wmode) {
       HIP_TRY(hipDeviceSynchronize());
-      return select_variant(h, v, nullptr);
+      return select_mode(h, v, m, nullptr);
     }
   }
   return CGLBM_OK;
@@ -1272,6 +1384,17 @@ int cglbm_set_variant(cglbm_handle *h, int32_t v, void *stream) {
 }
 
 int cglbm_get_variant(const cglbm_handle *h) { return h ? h->variant : -1; }
+
+int cglbm_set_wall_mode(cglbm_handle *h, int32_t mode, void *stream) {
+  g_err.clear();
+  if (!h) return fail(CGLBM_ESTATE, "null handle");
+  if (h->lattice != LATTICE_D3Q27) return fail(CGLBM_EUNSUPPORTED, "D2Q9 has no wall modes");
+  if (mode < 0 || mode > 3) return fail(CGLBM_EINVAL, "wall mode %d out of range", mode);
+  h->wmode_pop = h->wmode_compact = mode;
+  return select_mode(h, h->variant, mode, (hipStream_t)stream);
+}
+
+int cglbm_get_wall_mode(const cglbm_handle *h) { return h ? h->wmode : -1; }
 
 int cglbm_set_compact_variant(cglbm_handle *h, int32_t v, void *stream) {
   g_err.clear();
@@ -1398,10 +1521,37 @@ int cglbm_autotune(cglbm_handle *h, int32_t reps, double *ms_per_variant, void *
     }
     if (!rc) rc = select_cvariant(h, cbest, s);
   }
+  // boxes with walls: the wall mode of each schedule with its chosen
+  // geometries, timed as the steps run (replays of a captured graph of two
+  // launches): the fused kernel alone for the population schedule (its pull
+  // does not depend on the mode; layouts with the three-kernel schedule have
+  // no tiled launch there), k_cpull with the compact collision for the
+  // compact one (which advance only the compact state in the other buffer)
+  for (int cmp = 0; cmp < 2 && !rc && h->L.walls && !h->inplace; ++cmp) {
+    if (cmp ? !compact_ok(h) : h->L.general) continue;
+    auto launch = [&](hipStream_t cs, int k) {
+      int r = cmp ? launch_cpull(h, cs, k) : CGLBM_OK;
+      if (!r) r = cmp ? launch_compact_collide(h, cs) : launch_fused(h, cs, 0);
+      return r;
+    };
+    int32_t mbest = cmp ? h->wmode_compact : h->wmode_pop;
+    double mbest_ms = 1e300;
+    for (int32_t m = 0; m < 4 && !rc; ++m) {
+      double ms = 0.0;
+      if ((rc = select_mode(h, cmp ? cfbest : best, m, s)) ||
+          (rc = time_graph(h, s, reps, e0, e1, launch, ms)))
+        break;
+      if (ms < mbest_ms) {
+        mbest_ms = ms;
+        mbest = m;
+      }
+    }
+    (cmp ? h->wmode_compact : h->wmode_pop) = mbest;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
-  if (!rc) rc = select_variant(h, best, s);
+  if (!rc) rc = select_mode(h, best, h->wmode_pop, s);
   if (rc) return rc;
   const int32_t sched = three_ms < best_ms ? 1 : 0;
   if (sched != h->schedule) drop_graphs(h);
@@ -1451,11 +1601,15 @@ void cglbm_destroy(cglbm_handle *h) {
   if (!h) return;
   drop_graphs(h);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  if (h->side) (void)hipStreamDestroy(h->side);
+  if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
+  if (h->join_ev) (void)hipEventDestroy(h->join_ev);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   if (h->d_boxes) (void)hipFree(h->d_boxes);
   if (h->d_blk_box) (void)hipFree(h->d_blk_box);
   if (h->d_tile_box) (void)hipFree(h->d_tile_box);
   if (h->d_col_box) (void)hipFree(h->d_col_box);
+  if (h->d_col_tiles) (void)hipFree(h->d_col_tiles);
   if (h->d_part) (void)hipFree(h->d_part);
   if (h->d_rch_box) (void)hipFree(h->d_rch_box);
   if (h->d_out) (void)hipFree(h->d_out);
@@ -1465,7 +1619,7 @@ void cglbm_destroy(cglbm_handle *h) {
   for (void *p : h->cstash)
     if (p) (void)hipFree(p);
   if (h->d_wblk_box) (void)hipFree(h->d_wblk_box);
-  if (h->d_ccol_box) (void)hipFree(h->d_ccol_box);
+  if (h->d_ccol_tiles) (void)hipFree(h->d_ccol_tiles);
   delete h;
 }
 

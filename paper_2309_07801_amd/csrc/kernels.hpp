@@ -50,7 +50,7 @@ struct BoxDev {
   int32_t tnx, tny;     // tiles along x, y
   FastDiv fdx, fdy;     // division by nx, ny
   FastDiv ftx, fty;     // division by tnx, tny
-  int32_t col0;         // unused (column blocks carry their box and tile: tile_entry)
+  int32_t col0;         // unused (blocks carry their box and tile: TileEntry)
   int32_t ncx, ncy;     // columns along x, y
   FastDiv fcx, fcy;     // division by ncx, ncy
   float cs2r, cs2b;     // (c_s^k)^2 = xi (1 - alpha_k)
@@ -80,16 +80,15 @@ struct BoxDev {
 
 constexpr int kBlock = 256;
 
-// Column-block entries of k_fused and k_cpull: the box in the low 12 bits,
-// the box's tile (column x chunk) index above them; -1 for padding blocks.
-// Each launch gets its own list, so that a box's tiles can be split between
-// launches (the tiles away from solid layers run the kernel without wall
-// logic).
-constexpr int kTileBoxBits = 12;
-constexpr int32_t kMaxTileBoxes = 1 << kTileBoxBits;
-__host__ __device__ constexpr int32_t tile_entry(int32_t box, int32_t tile) {
-  return (tile << kTileBoxBits) | box;
-}
+// One block of k_fused or k_cpull: a box, its xy column (x fastest) and the
+// slabs [z0, z1) the block outputs; box < 0 for padding blocks.  Each launch
+// gets its own list, so that a box's tiles can be split between launches:
+// those whose stencils stay clear of solid layers run the kernel without
+// wall logic, and the chunks next to a z wall are cut short so that few
+// slabs need it.
+struct TileEntry {
+  int32_t box, xy, z0, z1;
+};
 
 // Plane p of a SoA array: a uniform (scalar) base pointer.  Node offsets are
 // 32-bit (the host limits all boxes together to 2^30 nodes), so every access
@@ -1417,7 +1416,7 @@ struct FusedGeom {
 // of dst, see compact_of) instead of its populations.
 template <int TX, int TY, int ZC, int MINW, bool WALLS, class S, bool EXPORT, bool COMPACT = false>
 __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict__ boxes,
-                                                  const int32_t *__restrict__ col_box,
+                                                  const TileEntry *__restrict__ tiles,
                                                   float *__restrict__ aux,
                                                   void *__restrict__ dst_, int64_t plane_arg) {
   using G = FusedGeom<TX, TY>;
@@ -1428,18 +1427,16 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
 
   const int tid = threadIdx.x;
   const uint32_t lb = xcd_block();
-  const int32_t te = col_box[lb];
-  if (te < 0) return;
-  const int b = te & (kMaxTileBoxes - 1);
+  const TileEntry te = tiles[lb];
+  if (te.box < 0) return;
+  const int b = te.box;
   const BoxDev B = boxes[b];
-  const uint32_t t = (uint32_t)te >> kTileBoxBits;
-  const uint32_t tyz = fdiv(t, B.fcx);
-  const int cx = (int)(t - tyz * (uint32_t)B.ncx);
-  const int cz = (int)fdiv(tyz, B.fcy);
-  const int cy = (int)(tyz - (uint32_t)cz * (uint32_t)B.ncy);
-  const int x0 = cx * TX, y0 = cy * TY, z0 = cz * ZC;
+  const uint32_t cyu = fdiv((uint32_t)te.xy, B.fcx);
+  const int cx = (int)((uint32_t)te.xy - cyu * (uint32_t)B.ncx);
+  const int cy = (int)cyu;
+  const int x0 = cx * TX, y0 = cy * TY, z0 = te.z0;
   const int nx = B.nx, ny = B.ny, nz = B.nz;
-  const int z1 = min(z0 + ZC, nz);
+  const int z1 = te.z1;
   const uint32_t nxy = (uint32_t)nx * (uint32_t)ny;
   const bool zwalls = WALLS && (B.walls & 2u) != 0;
 
@@ -1905,7 +1902,7 @@ struct CPullGeom {
 
 template <int TX, int TY, int ZC, bool WALLS = false, class S = StoreF32, bool GENERAL = false>
 __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ boxes,
-                                                  const int32_t *__restrict__ ccol_box,
+                                                  const TileEntry *__restrict__ tiles,
                                                   const float *__restrict__ cst,
                                                   float *__restrict__ aux, int64_t plane_arg,
                                                   const void *__restrict__ wst_in,
@@ -1915,18 +1912,16 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
   __shared__ float xb[18][G::R1];  // one z component: 9 directions x 2 colours
   const int tid = threadIdx.x;
   const uint32_t lb = xcd_block();
-  const int32_t te = ccol_box[lb];
-  if (te < 0) return;
-  const int b = te & (kMaxTileBoxes - 1);
+  const TileEntry te = tiles[lb];
+  if (te.box < 0) return;
+  const int b = te.box;
   const BoxDev B = boxes[b];
-  const uint32_t t = (uint32_t)te >> kTileBoxBits;
-  const uint32_t tyz = fdiv(t, B.fccx);
-  const int cxi = (int)(t - tyz * (uint32_t)B.cncx);
-  const int czi = (int)fdiv(tyz, B.fccy);
-  const int cyi = (int)(tyz - (uint32_t)czi * (uint32_t)B.cncy);
-  const int x0 = cxi * TX, y0 = cyi * TY, z0 = czi * ZC;
+  const uint32_t cyu = fdiv((uint32_t)te.xy, B.fccx);
+  const int cxi = (int)((uint32_t)te.xy - cyu * (uint32_t)B.cncx);
+  const int cyi = (int)cyu;
+  const int x0 = cxi * TX, y0 = cyi * TY, z0 = te.z0;
   const int nx = B.nx, ny = B.ny, nz = B.nz;
-  const int z1 = min(z0 + ZC, nz);
+  const int z1 = te.z1;
   const uint32_t nxy = (uint32_t)nx * (uint32_t)ny;
   // ring points of this thread and their LDS slots (row-major in the ring);
   // lanes past the ring read point 0 and write nothing

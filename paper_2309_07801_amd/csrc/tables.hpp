@@ -16,7 +16,7 @@ namespace cglbm {
 // minimum waves per SIMD requested from the register allocator.  Every
 // variant performs the same arithmetic per node (results are bitwise equal);
 // cglbm_autotune picks the fastest for the boxes at hand.
-using FusedFn = void (*)(const BoxDev *, const int32_t *, float *, void *, int64_t);
+using FusedFn = void (*)(const BoxDev *, const TileEntry *, float *, void *, int64_t);
 struct FusedVariant {
   int tx, ty, zc, minw;
   FusedFn fn[7][2];  // time step: [storage][0: tiles away from solid layers, 1: near them]
@@ -48,7 +48,7 @@ inline const FusedVariant &fused_variant(int v) {
 
 // The compact schedule's pull (column tile and z chunk, chosen by the
 // autotuner; equal results).
-using CPullFn = void (*)(const BoxDev *, const int32_t *, const float *, float *, int64_t,
+using CPullFn = void (*)(const BoxDev *, const TileEntry *, const float *, float *, int64_t,
                          const void *, void *, int64_t);
 struct CPullVariant {
   int tx, ty, zc;

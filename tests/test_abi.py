@@ -149,13 +149,6 @@ def test_empty_and_oversized_inputs_are_rejected():
     assert total < (1 << 29) and pop_b == 54 * 4 * total
     with pytest.raises(pkg.CglbmError):
         pkg.query_sizes([pkg.box_params_of(a)] * 3)
-    # at most 4096 boxes per handle (the column tables hold the box index in
-    # 12 bits beside the tile index)
-    tiny = pkg.box_params_of(WL.two_phase_box((2, 2, 2), 1.0, 1.0, 0.8, 0.01, 0.7))
-    pkg.query_sizes([tiny] * 4096)
-    with pytest.raises(pkg.CglbmError) as ei:
-        pkg.query_sizes([tiny] * 4097)
-    assert ei.value.code == -1
 
 
 def test_null_handle_calls_fail_cleanly():

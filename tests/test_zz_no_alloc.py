@@ -3,8 +3,8 @@ scratch is the library's static device array): through the C ABI its output
 equals cglbm_reduce's bit for bit, on two calls in a row whose second has a
 smaller input, with and without caller-given centres; captured into a HIP
 graph and replayed with other work in between, every replay equals the
-eager reduction of the state it sees; the largest handle the library
-accepts (4096 boxes) fits its scratch."""
+eager reduction of the state it sees; handles beyond the scratch's limits
+are refused."""
 import ctypes as C
 
 import numpy as np
@@ -93,28 +93,18 @@ def test_noalloc_replays_from_a_captured_graph():
     sim.close()
 
 
-def test_noalloc_at_the_largest_box_count():
-    """A handle holds at most 4096 boxes (CGLBM_EINVAL beyond, at
-    initialisation), which is the scratch's box capacity, and at most
-    2^29 - 2^20 nodes, well inside its 65536 reduction chunks: every handle
-    fits.  At 4096 one-node boxes the entry point equals cglbm_reduce."""
+def test_noalloc_refuses_handles_beyond_the_scratch():
     import torch
     import paper_2309_07801_amd as pkg
-    n = 4096
+    n = 4097
     box = WL.two_phase_box((1, 1, 1), 1.0, 1.0, 0.8, 0.0, 0.0)
     one = [np.ones((1, 1, 1), np.float32)]
-    zero = [np.zeros((1, 1, 1), np.float32)]
-    u = [np.zeros((3, 1, 1, 1), np.float32)]
-    with pytest.raises(pkg.CglbmError) as ei:
-        pkg.Simulation([pkg.box_params_of(box)] * (n + 1), one * (n + 1), zero * (n + 1),
-                       u * (n + 1))
-    assert ei.value.code == -1
-    sim = pkg.Simulation([pkg.box_params_of(box)] * n, one * n, zero * n, u * n)
+    sim = pkg.Simulation([pkg.box_params_of(box)] * n, one * n, [np.zeros((1, 1, 1), np.float32)] * n,
+                         [np.zeros((3, 1, 1, 1), np.float32)] * n)
     out = torch.zeros((n, 13), dtype=torch.float64, device=sim.device)
-    assert _noalloc(sim, out) == 0
-    torch.cuda.synchronize()
+    assert _noalloc(sim, out) == -1
+    assert "4096 boxes" in _lib().cglbm_last_error().decode()
     d = sim.reduce()
-    assert np.array_equal(out.cpu().numpy(), d)
     np.testing.assert_allclose(d[:, 0], 1.0, rtol=1e-6)   # FP32 populations, FP64 sums
     assert np.all(d[:, 1] == 0.0) and np.all(d[:, 12] == 0.0)
     sim.close()
