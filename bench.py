@@ -157,7 +157,8 @@ def measured_valu(kernel: str):
     return None
 
 
-DEFAULT_FORMS = ("fp32_population,fp16,bf16,fp16c,bf16c,fp32x,fp32x_population,c3,c5,batched,"
+DEFAULT_FORMS = ("fp32_population,fp16,bf16,fp16c,bf16c,fp16c_population,fp32x,fp32x_population,"
+                 "c3,c5,batched,"
                  "inplace,small,rti,galilean,d2q9,d2q9_fp16,d2q9_bf16,table2,parity")
 
 
@@ -432,16 +433,18 @@ def big_form(label, w, storages, steps, warmup, u_ref):
     box = w.box
     out = {"workload": label, "nodes": box.fluid_nodes(), "steps": steps}
     ref = None
-    for st in storages:
+    for name in storages:
+        # the compact schedule, or (a "_population" suffix) the population one
+        st = name.split("_")[0]
         r = run_form([w], st, steps, warmup, keep_fields="device",
-                     schedule=2 if st in ("fp32", "fp32p") else None)
-        out[st] = storage_form(r, st, ref, u_ref)
-        if st == "fp32":
+                     schedule=0 if name.endswith("_population") else 2)
+        out[name] = storage_form(r, st, ref, u_ref)
+        if name == "fp32":
             ref = r["fields"]
         else:
             del r["fields"]
         torch.cuda.empty_cache()
-        print("bench:   %s %s %.1f MLUPS" % (label.split(",")[0], st, r["mlups"]), file=sys.stderr,
+        print("bench:   %s %s %.1f MLUPS" % (label.split(",")[0], name, r["mlups"]), file=sys.stderr,
               flush=True)
     del ref
     torch.cuda.empty_cache()
@@ -635,22 +638,26 @@ def parity_form():
     same seeded inputs: e_rho (relative to the oracle's density), e_u
     (relative to U_ref = max(U, sigma / mu_max); e_u_vs_U against the
     imposed velocity U alone), e_phi (absolute), max and L2 over fluid
-    nodes."""
+    nodes.  The 16-bit formats run the population schedule (rounded to the
+    format at every step) and, marked _compact, the compact schedule (one
+    call: rounded when it stores the populations)."""
     import oracle as O
     cases = [
         ("c1", "32^3 static droplet (the configuration itself)", [WL.static_droplet()], 200, 0.01,
          (("fp32", 2), ("fp32", 0))),
         ("c2", "translating droplet at 64^3, R 8", [WL.translating_droplet(n=64, R=8.0)], 200, 0.05,
-         (("fp32", 2), ("fp32", 0), ("fp32x", None), ("fp16", None), ("fp16c", None))),
+         (("fp32", 2), ("fp32", 0), ("fp32x", None), ("fp16", None), ("fp16c", None),
+          ("fp16", 2), ("fp16c", 2))),
         ("c3", "density-ratio-1000 droplets at 96^3, R U[4, 9]",
          [WL.sheared_droplets(n=96, count=8, rmin=4.0, rmax=9.0)], 100, 0.04,
-         (("fp32", 2), ("fp16", None), ("bf16", None), ("fp16c", None), ("bf16c", None))),
+         (("fp32", 2), ("fp16", None), ("bf16", None), ("fp16c", None), ("bf16c", None),
+          ("fp16c", 2), ("bf16c", 2))),
         ("c4", "the four smallest boxes of the 96-box batch",
          sorted(WL.batched_boxes(), key=lambda x: x.box.nodes)[:4], 200, 0.01,
          (("fp32p", 2),)),
         ("c5", "walled head-on collision at 192x96x96, R 12 (We, Re kept)",
          [WL.head_on_collision(nx=192, ny=96, nz=96, R=12.0)], 100, 0.05,
-         (("fp32", 2), ("fp16", None), ("fp16c", None))),
+         (("fp32", 2), ("fp16", None), ("fp16c", None), ("fp16c", 2))),
     ]
     out = {}
     for key, label, ws, steps, u_ref, runs in cases:
@@ -797,19 +804,23 @@ def main():
     ref_fields = main_r["fields"]
     for f in forms_req:
         if f in STORAGES:
-            # the FP32 formats run the compact schedule (the mass-exact one
-            # with its FP64 colour densities), the 16-bit ones the population
-            # schedule (the compact state would hold them in FP32)
+            # every format runs the compact schedule (the mass-exact and
+            # 16-bit ones with FP64 colour densities in the compact state;
+            # the 16-bit populations are decoded and encoded at the ends of
+            # each call)
             r = run_form([w], f, args.steps, args.warmup, args.variant, keep_fields="device",
-                         drift_steps=DRIFT_STEPS,
-                         schedule=2 if f in ("fp32", "fp32p", "fp32x") else None)
+                         drift_steps=DRIFT_STEPS, schedule=2)
             forms[f] = storage_form(r, f, ref_fields, u_ref)
             del r["fields"]
-        elif f in ("fp32_population", "fp32x_population"):
+        elif f.endswith("_population") and f.split("_")[0] in STORAGES:
+            # the population schedule: the stored format between every two
+            # steps
             st = f.split("_")[0]
+            sixteen = st in SIXTEEN
             r = run_form([w], st, args.steps, args.warmup, args.variant, schedule=0,
-                         drift_steps=DRIFT_STEPS)
-            forms[f] = storage_form(r, st)
+                         drift_steps=DRIFT_STEPS, keep_fields="device" if sixteen else None)
+            forms[f] = storage_form(r, st, ref_fields if sixteen else None, u_ref)
+            r.pop("fields", None)
         elif f == "c3":
             w3 = WL.sheared_droplets()
             forms["c3"] = big_form("512^3 periodic, 8 droplets R U[20,48], density ratio 1000, "
@@ -821,7 +832,8 @@ def main():
             w5 = WL.head_on_collision()
             forms["c5"] = big_form("768x384x384, walls y/z, head-on collision of two R 48 droplets, "
                                    "relative velocity 0.1, density ratio 10, Re 5000, We 50", w5,
-                                   ("fp32", "fp16", "fp16c"), min(args.steps, BIG_STEPS),
+                                   ("fp32", "fp16", "fp16c", "fp16c_population"),
+                                   min(args.steps, BIG_STEPS),
                                    args.warmup, 0.05)
             del w5
         elif f == "batched":

@@ -327,7 +327,13 @@ int cglbm_load_state(cglbm_handle *h, const void *src, void *stream);
  *     equals schedule 1 bit for bit), or CGLBM_FP32_EXACT storage with
  *     Model D and Q (the compact state then carries the FP64 colour
  *     densities as well, 84 bytes per node, and per-colour mass stays
- *     exact to FP64 rounding); CGLBM_EUNSUPPORTED otherwise.  The compact state
+ *     exact to FP64 rounding), or one of the 16-bit storages with Model D
+ *     and Q: the same compact state, so that within a call the state is
+ *     held in FP32 and FP64 and rounded to the 16-bit format only when the
+ *     call stores the populations (a call of n steps rounds once, not n
+ *     times; one step per call equals schedule 0 bit for bit on boxes
+ *     without walls; the solid nodes' populations are re-encoded once per
+ *     call); CGLBM_EUNSUPPORTED otherwise.  The compact state
  *     lives in the population buffer that does not hold the state; solid
  *     wall nodes keep their (bounced) populations in two library-owned
  *     wall stashes allocated by cglbm_init.  cglbm_autotune chooses

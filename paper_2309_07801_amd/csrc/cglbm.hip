@@ -114,8 +114,32 @@ const InitFn kInit[7] = {k_init<StoreF32>,  k_init<StoreF16>,  k_init<StoreBF16>
 // [FP32 pairs][general equilibrium family]
 const EmitFn kEmit[2][2] = {{k_emit<StoreF32, false>, k_emit<StoreF32, true>},
                             {k_emit<StoreF32P, false>, k_emit<StoreF32P, true>}};
-// the mass-exact storage (Model D with Q)
-const EmitFn kEmitX = k_emit<StoreF32X, false>;
+// the mass-exact storages (Model D with Q), by storage (none for the plain
+// FP32 layouts)
+const EmitFn kEmitX[7] = {nullptr,
+                          k_emit<StoreF16, false>,
+                          k_emit<StoreBF16, false>,
+                          k_emit<StoreF32X, false>,
+                          nullptr,
+                          k_emit<StoreF16C, false>,
+                          k_emit<StoreBF16C, false>};
+// the compact schedule of the 16-bit formats: the first pull writes the
+// solid nodes' reversed populations decoded into a mass-exact FP32 stash,
+// and the call's end encodes the last stash into the stored format
+const PullFn kPullDec[7] = {nullptr,
+                            k_pull<StoreF16, true, StoreF32X>,
+                            k_pull<StoreBF16, true, StoreF32X>,
+                            nullptr,
+                            nullptr,
+                            k_pull<StoreF16C, true, StoreF32X>,
+                            k_pull<StoreBF16C, true, StoreF32X>};
+const WallCopyFn kWallEncode[7] = {nullptr,
+                                   k_wall_encode<StoreF16>,
+                                   k_wall_encode<StoreBF16>,
+                                   nullptr,
+                                   nullptr,
+                                   k_wall_encode<StoreF16C>,
+                                   k_wall_encode<StoreBF16C>};
 // the three-kernel schedule's collision writing compact states
 const CollideFn kCollideCompact = k_collide<StoreF32, true>;
 const WallCopyFn kWallCopy[7] = {k_wall_copy<StoreF32>,  k_wall_copy<StoreF16>,
@@ -126,6 +150,7 @@ const WallCopyFn kWallCopy[7] = {k_wall_copy<StoreF32>,  k_wall_copy<StoreF16>,
 // D2Q9 keeps FP32 in colour pairs in either FP32 format
 int storage2_slot(int32_t st) { return st == CGLBM_FP32_PAIRS ? 0 : st; }
 bool storage_exact(int32_t st) { return st != CGLBM_FP32 && st != CGLBM_FP32_PAIRS; }
+bool storage_16bit(int32_t st) { return storage_exact(st) && st != CGLBM_FP32_EXACT; }
 size_t storage_bytes(int32_t st) {
   return (st == CGLBM_FP16_SHIFT || st == CGLBM_BF16_SHIFT || st == CGLBM_FP16_CSHIFT ||
           st == CGLBM_BF16_CSHIFT)
@@ -606,7 +631,7 @@ int launch_fused_compact(cglbm_handle *h, hipStream_t s) {
   float *aux = h->aux;
   void *dst = h->pop[1 - h->cur];
   int64_t plane = h->L.total;
-  const FusedFn *fn = h->storage == CGLBM_FP32_EXACT ? F.fcx : F.fc;
+  const FusedFn *fn = storage_exact(h->storage) ? F.fcx : F.fc;
   return launch_split(h, h->L.ncol, h->L.ncol_plain, fn, F.tx * F.ty, s, boxes, cols, aux, dst,
                       plane);
 }
@@ -614,7 +639,7 @@ int launch_fused_compact(cglbm_handle *h, hipStream_t s) {
 // solid nodes go to the other one
 int launch_cpull(cglbm_handle *h, hipStream_t s, int rd = 0) {
   const CPullVariant &C = cpull_variant(h->cvariant);
-  const bool x = h->storage == CGLBM_FP32_EXACT;
+  const bool x = storage_exact(h->storage);
   const int g = h->L.general ? 1 : 0;
   // the tiles away from walls, then those near them
   const CPullFn fn[2] = {x ? C.fx[0] : C.fn[g][0],
@@ -635,33 +660,40 @@ int launch_cpull(cglbm_handle *h, hipStream_t s, int rd = 0) {
 }
 // wi: the wall stash the last step wrote (the solid nodes' stored values)
 int launch_emit(cglbm_handle *h, hipStream_t s, int wi = 0) {
-  hipLaunchKernelGGL(h->storage == CGLBM_FP32_EXACT
-                         ? kEmitX
+  hipLaunchKernelGGL(storage_exact(h->storage)
+                         ? kEmitX[h->storage]
                          : kEmit[h->storage == CGLBM_FP32_PAIRS ? 1 : 0][h->L.general ? 1 : 0],
                      dim3(h->L.nblk_pad), dim3(kBlock), 0, s, h->d_boxes, h->d_blk_box,
                      (const float *)h->pop[1 - h->cur], h->pop[h->cur], h->L.total);
   if (h->L.walls && !h->L.wblk_box.empty())
-    hipLaunchKernelGGL(kWallCopy[h->storage], dim3((unsigned)h->L.wblk_box.size()), dim3(kBlock),
+    hipLaunchKernelGGL(storage_16bit(h->storage) ? kWallEncode[h->storage]
+                                                 : kWallCopy[h->storage],
+                       dim3((unsigned)h->L.wblk_box.size()), dim3(kBlock),
                        0, s, h->d_boxes, h->d_wblk_box, (const void *)h->cstash[wi],
                        h->pop[h->cur], h->L.total, h->L.wtotal);
   return CGLBM_OK;
 }
 // The first step of a compact call: the population pull, with the solid
-// nodes' reversed populations going to wall stash 0.
+// nodes' reversed populations going to wall stash 0 (decoded to the
+// mass-exact FP32 format for the 16-bit storages).
 int launch_pull_compact(cglbm_handle *h, hipStream_t s) {
   void *stash = h->L.walls ? h->cstash[0] : nullptr;
-  hipLaunchKernelGGL(kPull[stash ? 1 : 0][h->storage], dim3(h->L.nblk_pad), dim3(kBlock), 0, s,
+  hipLaunchKernelGGL(stash && storage_16bit(h->storage) ? kPullDec[h->storage]
+                                                        : kPull[stash ? 1 : 0][h->storage],
+                     dim3(h->L.nblk_pad), dim3(kBlock), 0, s,
                      h->d_boxes, h->d_blk_box, h->pop[h->cur], h->pop[1 - h->cur], h->aux,
                      h->L.total, 1, stash, h->L.wtotal);
   return CGLBM_OK;
 }
 // Layouts the compact schedule serves: D3Q27, FP32 storage (either layout,
-// any equilibrium family), or the mass-exact FP32 storage (Model D with Q),
-// two buffers, unit higher rates.
+// any equilibrium family), or a mass-exact storage (FP32 or 16-bit; Model D
+// with Q), two buffers, unit higher rates.  With a 16-bit storage the
+// compact state (17 floats and the FP64 colour densities, 84 bytes a node)
+// fits the other population buffer (at least 120 bytes a node).
 bool compact_ok(const cglbm_handle *h) {
   return h->lattice == LATTICE_D3Q27 && !h->inplace && !h->L.full_rates &&
          (h->storage == CGLBM_FP32 || h->storage == CGLBM_FP32_PAIRS ||
-          (h->storage == CGLBM_FP32_EXACT && !h->L.general));
+          (storage_exact(h->storage) && !h->L.general));
 }
 
 int launch_fused(cglbm_handle *h, hipStream_t s, int export_fields) {
@@ -1207,18 +1239,20 @@ int init_handle(int lattice, cglbm_handle **out, int32_t n_boxes, const cglbm_bo
   if ((rc = scratch_lookup(h->device))) return cleanup(rc);
   if (h->L.walls) {
     // wall stashes: the in-place layout's, or the compact schedule's pair
-    size_t sb = 0, ab = 0;
+    // (the compact schedule of the 16-bit storages keeps its stashes in the
+    // mass-exact FP32 format)
+    size_t sb = 0, ab = 0, csb = 0;
     buffer_sizes(storage, h->L.wtotal, &sb, &ab, lattice);
-    const bool cst = lattice == LATTICE_D3Q27 && !inplace &&
-                     (storage == CGLBM_FP32 || storage == CGLBM_FP32_PAIRS ||
-                      storage == CGLBM_FP32_EXACT);
+    buffer_sizes(storage_16bit(storage) ? CGLBM_FP32_EXACT : storage, h->L.wtotal, &csb, &ab,
+                 lattice);
+    const bool cst = lattice == LATTICE_D3Q27 && !inplace;
     if ((e = hipMalloc(&h->d_wblk_box, sizeof(int32_t) * h->L.wblk_box.size())) != hipSuccess ||
         (e = hipMemcpyAsync(h->d_wblk_box, h->L.wblk_box.data(),
                             sizeof(int32_t) * h->L.wblk_box.size(), hipMemcpyHostToDevice, s)) !=
             hipSuccess ||
         (inplace && (e = hipMalloc(&h->stash, sb)) != hipSuccess) ||
-        (cst && ((e = hipMalloc(&h->cstash[0], sb)) != hipSuccess ||
-                 (e = hipMalloc(&h->cstash[1], sb)) != hipSuccess)))
+        (cst && ((e = hipMalloc(&h->cstash[0], csb)) != hipSuccess ||
+                 (e = hipMalloc(&h->cstash[1], csb)) != hipSuccess)))
       return cleanup(fail(CGLBM_EHIP, "init: %s", hipGetErrorString(e)));
   }
   if ((rc = select_variant(h, 0, s))) return cleanup(rc);
@@ -1334,8 +1368,8 @@ int cglbm_set_schedule(cglbm_handle *h, int32_t schedule) {
     return fail(CGLBM_EUNSUPPORTED, "D2Q9 steps have one schedule (0)");
   if (schedule == 2 && !compact_ok(h))
     return fail(CGLBM_EUNSUPPORTED,
-                "the compact schedule needs D3Q27, FP32 storage (or the mass-exact FP32 "
-                "storage with Model D and Q), two buffers and unit higher-order rates");
+                "the compact schedule needs D3Q27, FP32 storage (or a mass-exact FP32 or "
+                "16-bit storage with Model D and Q), two buffers and unit higher-order rates");
   if (schedule != h->schedule) drop_graphs(h);
   h->schedule = schedule;
   // the fused geometry preferred by the schedule (the autotuner's choices);

@@ -28,6 +28,8 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_bf16.h>
 
+#include <type_traits>
+
 #include "lattice.hpp"
 
 namespace cglbm {
@@ -467,9 +469,12 @@ __device__ __forceinline__ void st_rb(const Pops<S> &p, int i, uint32_t d, typen
 // other nodes of this launch still read what the solid node holds;
 // k_wall_copy moves them into place once the pull has completed.  STASH
 // selects that path at compile time, so the two-buffer pull carries none of
-// it (measured 4 % faster than one kernel with a run-time switch).
+// it (measured 4 % faster than one kernel with a run-time switch).  SS is
+// the stash's format: the storage's own, or (the compact schedule of the
+// 16-bit formats) the mass-exact FP32 one, into which the reversed
+// populations go decoded.
 // ---------------------------------------------------------------------------
-template <class S, bool STASH>
+template <class S, bool STASH, class SS = S>
 __global__ __launch_bounds__(kBlock) void k_pull(const BoxDev *__restrict__ boxes,
                                                  const int32_t *__restrict__ blk_box,
                                                  void *__restrict__ src_, void *__restrict__ dst_,
@@ -523,7 +528,20 @@ __global__ __launch_bounds__(kBlock) void k_pull(const BoxDev *__restrict__ boxe
     rb0 = at(src.restp(1), node);
   }
   if (is_solid(B, y, z)) {
-    if (bounce) {
+    if constexpr (!std::is_same<SS, S>::value) {
+      // decoded into the mass-exact FP32 stash (rest populations as stored)
+      static_assert(STASH && SS::kExact && S::kExact, "decoded stash of a mass-exact format");
+      if (bounce) {
+        const Pops<SS> out(stash_, wplane);
+        const uint32_t at_ = (uint32_t)B.wbase + wall_slot(B, x, y, z);
+#pragma unroll
+        for (int i = 1; i < kQ; ++i)
+          st_rb(out, opposite(i), at_, decode_pop<S>(B, 0, gr[i], pop_shift<S>(B, 0, i, csrc[i])),
+                decode_pop<S>(B, 1, gb[i], pop_shift<S>(B, 1, i, csrc[i])));
+        at(out.restp(0), at_) = rr0;
+        at(out.restp(1), at_) = rb0;
+      }
+    } else if (bounce) {
       // the shift of direction i equals that of its opposite: copy raw pairs
       const Pops<S> out(STASH ? stash_ : dst_, STASH ? wplane : plane);
       const uint32_t at_ = STASH ? (uint32_t)B.wbase + wall_slot(B, x, y, z) : node;
@@ -1330,6 +1348,51 @@ __global__ __launch_bounds__(kBlock) void k_wall_copy(const BoxDev *__restrict__
     at(dst.restp(1), node) = at(src.restp(1), slot);
   }
   if constexpr (S::kCShift) at(dst.cfr, node) = at(src.cfr, slot);
+}
+
+// The compact schedule of the 16-bit formats: the solid nodes' populations
+// from a decoded (mass-exact FP32) wall stash, encoded into the stored
+// format (after k_emit, whose red fractions of the fluid nodes the
+// colour-fraction formats read: a solid node takes that of its wall-normal
+// fluid neighbour, as the pull does).
+template <class S>
+__global__ __launch_bounds__(kBlock) void k_wall_encode(const BoxDev *__restrict__ boxes,
+                                                        const int32_t *__restrict__ wblk_box,
+                                                        const void *__restrict__ stash_,
+                                                        void *__restrict__ pop_, int64_t plane,
+                                                        int64_t wplane) {
+  const int b = wblk_box[blockIdx.x];
+  if (b < 0) return;
+  const BoxDev B = boxes[b];
+  const int32_t local = (int32_t)(blockIdx.x - (uint32_t)B.wblk0) * kBlock + (int32_t)threadIdx.x;
+  if (local >= B.wn) return;
+  int x, y, z;
+  wall_node(B, (uint32_t)local, x, y, z);
+  const int nx = B.nx, ny = B.ny, nz = B.nz;
+  const uint32_t node = (uint32_t)B.base + (uint32_t)x +
+                        (uint32_t)nx * ((uint32_t)y + (uint32_t)ny * (uint32_t)z);
+  const uint32_t slot = (uint32_t)(B.wbase + local);
+  const Pops<StoreF32X> src(const_cast<void *>(stash_), wplane);
+  const Pops<S> dst(pop_, plane);
+  float cown = 0.f;
+  if constexpr (S::kCShift) {
+    const int dy = (B.walls & 1u) ? (y == 0 ? -1 : (y == ny - 1 ? 1 : 0)) : 0;
+    const int dz = (B.walls & 2u) ? (z == 0 ? -1 : (z == nz - 1 ? 1 : 0)) : 0;
+    const uint32_t nb = (uint32_t)B.base + (uint32_t)x +
+                        (uint32_t)nx * ((uint32_t)(y - dy) + (uint32_t)ny * (uint32_t)(z - dz));
+    const typename S::T craw = ld(&at(dst.cfr, nb));
+    cown = S::dec(craw);
+    at(dst.cfr, node) = craw;
+  }
+#pragma unroll
+  for (int i = 1; i < kQ; ++i) {
+    float fr, fb;
+    ld_rb(src, i, slot, fr, fb);
+    st_rb(dst, i, node, encode_pop<S>(B, 0, fr, pop_shift<S>(B, 0, i, cown)),
+          encode_pop<S>(B, 1, fb, pop_shift<S>(B, 1, i, cown)));
+  }
+  at(dst.restp(0), node) = at(src.restp(0), slot);
+  at(dst.restp(1), node) = at(src.restp(1), slot);
 }
 
 // ---------------------------------------------------------------------------
@@ -2253,6 +2316,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(const BoxDev *__restrict__ boxe
     model_d_moments(rho, p, c[5], c[6], c[7], c[8], c[9], c[10], c[11], c[12], c[13], k);
   const Pops<S> dst(dst_, plane);
   PopWriter<S> w(dst, B, node);
+  w.set_fraction(c[0], c[1]);
   emit_recoloured(B, k, c[2], c[3], c[4], div_refined(c[0], rho, irho), div_refined(c[1], rho, irho),
                   p, c[14], c[15], c[16], w);
   if (S::kExact) {

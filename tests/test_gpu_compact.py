@@ -97,9 +97,10 @@ def test_compact_schedule_refuses_other_layouts():
     import paper_2309_07801_amd as pkg
     b, f = _case()
     refused = [
-        ([(b, f)], {"storage": 1}),
-        ([(b, f)], {"storage": 5}),
+        ([(dataclasses.replace(b, model=0), f)], {"storage": 1}),
+        ([(dataclasses.replace(b, use_q=0), f)], {"storage": 5}),
         ([(b, f)], {"inplace": True}),
+        ([(b, f)], {"storage": 2, "inplace": True}),
         ([(dataclasses.replace(b, omega_hi=(1.0, 1.2) + (1.0,) * 7), f)], {}),
         ([(dataclasses.replace(b, model=0), f)], {"storage": 3}),
     ]

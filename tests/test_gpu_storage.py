@@ -110,3 +110,64 @@ def test_fp32_pair_layout_equals_fp32_bitwise(walls, schedule):
     for a, b in zip(out[0], out[1]):
         for k in a:
             assert np.array_equal(a[k], b[k]), k
+
+
+# The compact schedule of the 16-bit formats: inside a call the state is the
+# compact FP32 state with FP64 colour densities; the populations are decoded
+# when the call starts and encoded when it ends.
+@pytest.mark.parametrize("storage", [1, 2, 5, 6])
+def test_compact_16bit_single_step_calls_equal_population_schedule(storage):
+    """One step per call: the compact call's emission encodes the same
+    values, with the same colour fractions, as the population schedule's
+    collision (periodic boxes: without walls no population is re-encoded)."""
+    cases = [_case(), _case(shape=(40, 33, 21), R=6.0)]
+    out = []
+    for sched in (0, 2):
+        sim = _sim([b for b, _ in cases], [f for _, f in cases], storage, seed=4, noise=1e-6)
+        sim.set_schedule(sched)
+        assert sim.schedule() == sched
+        for _ in range(5):
+            sim.step(1)
+        out.append([gpu_fields(sim, k) for k in range(2)])
+        sim.close()
+    for a, b in zip(out[0], out[1]):
+        for k in a:
+            assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("storage", [1, 2, 5, 6])
+@pytest.mark.parametrize("walls", [0, 3])
+def test_compact_16bit_parity_with_oracle(storage, walls):
+    """50 steps in seven calls (graph pairs inside each, the state rounded
+    to the 16-bit format at each call's end) against the FP64 oracle, with
+    the bars of the population schedule, which rounds at every step."""
+    box, fl = _case(walls=walls)
+    sim = _sim([box], [fl], storage, seed=3, noise=1e-6)
+    sim.set_schedule(2)
+    for n in (7, 7, 7, 7, 7, 7, 8):
+        sim.step(n)
+    e = errors(gpu_fields(sim), run_oracle(box, *fl, 50, seed=3, noise=1e-6)[0], box,
+               u_ref(box, 0.02))
+    print("compact storage", storage, "walls", walls, e)
+    br, bu, bp = _bars(storage)
+    check(e, rho=br, u=bu, phi=bp)
+    assert sim.reduce()[0, 12] == 0
+    sim.close()
+
+
+@pytest.mark.parametrize("storage", [1, 5])
+def test_compact_16bit_conserves_colour_mass(storage):
+    """200 steps in four calls of the compact schedule: the FP64 densities
+    inside a call and the rest populations closed on them when a call stores
+    the 16-bit populations keep each colour's mass to FP64 rounding."""
+    box, fl = _case(shape=(24, 20, 18), R=5.0, u=(0.05, 0.0, 0.0))
+    sim = _sim([box], [fl], storage, seed=5, noise=1e-6)
+    sim.set_schedule(2)
+    d0 = sim.reduce()[0]
+    for _ in range(4):
+        sim.step(50)
+    d1 = sim.reduce()[0]
+    drift = [(d1[k] - d0[k]) / d0[k] for k in (0, 1)]
+    print("compact storage", storage, "mass drift", drift)
+    assert abs(drift[0]) < 1e-12 and abs(drift[1]) < 1e-12
+    sim.close()
