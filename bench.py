@@ -103,6 +103,22 @@ COMPACT_BYTES_X = {"pull": 17 * 4 + 2 * 8 + 11 * 4 + 2 * 8, "fused": 11 * 4 + 2 
 COMPACT_BYTES = {"pull": 17 * 4 + 11 * 4, "fused": 11 * 4 + 17 * 4,
                  "pull_first": 54 * 4 + 11 * 4, "emit": 17 * 4 + 54 * 4}
 
+
+
+def compact_bytes(storage: str):
+    """Algorithmic bytes per node of the compact schedule's kernels.  The
+    mass-exact and 16-bit formats carry FP64 colour densities in the compact
+    state and the moments; the 16-bit ones decode (pull_first) and encode
+    (emit) their own populations: 26 pairs of 16-bit values, the FP64 rest
+    populations and, with the colour-fraction shift, a 16-bit fraction."""
+    if storage in ("fp32", "fp32p"):
+        return COMPACT_BYTES
+    if storage == "fp32x":
+        return COMPACT_BYTES_X
+    pops = 26 * 2 * 2 + 2 * 8 + (2 if storage in ("fp16c", "bf16c") else 0)
+    return dict(COMPACT_BYTES_X, pull_first=pops + 11 * 4 + 2 * 8, emit=17 * 4 + 2 * 8 + pops)
+
+
 # storage format of the D2Q9 step kernel's template argument
 SNAMES = {"fp32": "StoreF32P", "fp32p": "StoreF32P", "fp16": "StoreF16", "bf16": "StoreBF16",
           "fp32x": "StoreF32X"}
@@ -346,7 +362,7 @@ def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=None,
     if lattice != "d3q27":
         kb = {"fused": d2q9_bytes(storage)}
     elif sim.schedule() == 2:
-        kb = COMPACT_BYTES_X if storage == "fp32x" else COMPACT_BYTES
+        kb = compact_bytes(storage)
     else:
         kb = kernel_bytes(storage)
     kern = {}
@@ -734,7 +750,7 @@ def main():
         kb = COMPACT_BYTES
     else:
         kname = ("k_fused<%d, %d, %d, %d, false, f32, false>" % geo if dom == "fused"
-                 else "k_%s<f32%s>" % (dom, ", false" if dom == "pull" else ""))
+                 else "k_%s<f32%s>" % (dom, ", false, f32" if dom == "pull" else ""))
         kb = kernel_bytes(args.storage)
     measured = n == 256 and args.storage == "fp32" and args.workload == "droplet"
     traffic = measured_traffic(kname) if measured else None

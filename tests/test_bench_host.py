@@ -16,7 +16,7 @@ def test_counter_summary_matches_sources_and_kernels():
     assert rows is not None, "profiles summary missing or taken for other device sources"
     for k in ("k_cpull<64, 8, 64, false, f32, false>",
               "k_fused<64, 8, 64, 4, false, f32, false, true>",
-              "k_fused<64, 8, 32, 4, false, f32, false, false>", "k_pull<f32, false>"):
+              "k_fused<64, 8, 32, 4, false, f32, false, false>", "k_pull<f32, false, f32>"):
         t = bench.measured_traffic(k)
         assert t is not None and t > 0, k
     for k in ("k_cpull<64, 8, 64, false, f32, false>",
