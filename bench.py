@@ -8,10 +8,12 @@ storage and arithmetic.  A step is one full time update of every node
 (pull-streaming, moments, interface stencils, collision, recolouring).  The
 FP32 lines run the compact schedule (the state between the steps of a call
 held as each node's 17-value post-collision state); `--schedule 0` runs the
-population schedule.  The K timed steps are one cglbm_step call with HIP
-events around every launch; `repeats` times four more calls of K steps and
-reports the median, `graph_mlups` the same update as replays of the
-captured graph cglbm_step uses by default.
+population schedule.  The K timed steps are one cglbm_step call as the
+library runs it by default (replays of its captured two-step graph), timed
+between two device synchronizations; `repeats` times four more such calls
+and reports the median; one more call of K steps launches every kernel
+directly between HIP events for the per-kernel times (`kernels`, the
+roofline) and `events_mlups`.
 
 Prints ONE JSON line: MLUPS of the timed steps, the roofline of the dominant
 kernel (against HBM: algorithmic bytes per launch / average launch time from
@@ -50,7 +52,6 @@ sys.path.insert(0, ROOT)
 import workloads as WL  # noqa: E402  (seeded inputs; numpy only)
 
 HBM_PEAK_GBS = 8000.0
-GRAPH_STEPS = 500   # steps of the graph-replay run after the timed region
 REPEATS = 5         # calls of K timed steps (the first is `value`)
 DRIFT_STEPS = 5000  # steps after which the C2 forms report per-colour mass drift
 BIG_STEPS = 500     # timed steps of each format at the 512^3 and 768x384x384 sizes
@@ -196,21 +197,35 @@ def parse():
                     help="step schedule (default: the autotuner's choice)")
     ap.add_argument("--variant", type=int, default=-1,
                     help="fused launch geometry (default: autotune)")
+    ap.add_argument("--copy-probe-check", action="store_true",
+                    help="run only a 256 MiB copy and a 2 GiB fill (counter calibration check: also a fill and a sum of 2 GiB)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 2 GiB device copy (counter calibration)")
     return ap.parse_args()
 
 
-def copy_probe():
-    """A plain copy kernel of known size: 2 GiB read, 2 GiB written, 5 times."""
+def copy_probe(check=False):
+    """A plain copy kernel of known size: 2 GiB read, 2 GiB written, 5 times
+    (the calibration of the HBM counters).  check: a copy of 256 MiB, a fill
+    of 2 GiB and a sum over 2 GiB, 5 times each, to check that the
+    calibration scales with the size and holds for kernels that only write
+    or only read."""
     import torch
-    n = 2 ** 29
+    n = 2 ** 26 if check else 2 ** 29
     a = torch.ones(n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     for _ in range(5):
         b.copy_(a)
+    out = {"copy_probe_bytes_each_way": n * 4, "launches": 5}
+    if check:
+        c = torch.empty(2 ** 29, dtype=torch.float32, device="cuda")
+        for _ in range(5):
+            c.fill_(2.0)
+        for _ in range(5):
+            c.sum()
+        out["fill_bytes_written"] = out["sum_bytes_read"] = c.numel() * 4
     torch.cuda.synchronize()
-    print(json.dumps({"copy_probe_bytes_each_way": n * 4, "launches": 5}))
+    print(json.dumps(out))
 
 
 def cpu_model():
@@ -328,28 +343,29 @@ def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=None,
     wmode = sim.wall_mode() if lattice == "d3q27" else None
     sim.step(max(warmup - 2, 0))  # also captures the step graph
     torch.cuda.synchronize()
-    # timed region: direct launches with HIP events around every kernel
-    dt, prof = _time_steps(sim, steps)
-    out_fields = None
-    if keep_fields:
-        names = ("rho_r", "rho_b", "phi", "ux", "uy", "uz")
-        f = sim.moments(0, names)
-        out_fields = {k: (v.clone() if keep_fields == "device" else v.cpu().numpy())
-                      for k, v in f.items()}
-        del f
-    mlups = [fluid * steps / dt / 1e6]
-    for _ in range(repeats - 1):
-        dtr, pr = _time_steps(sim, steps)
+    # timed region: `repeats` calls of K steps as the library runs them by
+    # default (replays of the captured two-step graph)
+    mlups, out_fields, dt = [], None, None
+    for rep in range(repeats):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        dtr = time.perf_counter() - t0
         mlups.append(fluid * steps / dtr / 1e6)
-        for k, (ms, cnt) in pr.items():
-            prof[k] = (prof[k][0] + ms, prof[k][1] + cnt)
-    # the same update as replays of the captured two-step graph
-    ngraph = min(steps, GRAPH_STEPS)
-    t2 = time.perf_counter()
-    sim.step(ngraph)
-    torch.cuda.synchronize()
-    graph_mlups = fluid * ngraph / (time.perf_counter() - t2) / 1e6
-    done = 2 + max(warmup - 2, 0) + steps * repeats + ngraph
+        if rep == 0:
+            dt = dtr
+            if keep_fields:
+                names = ("rho_r", "rho_b", "phi", "ux", "uy", "uz")
+                f = sim.moments(0, names)
+                out_fields = {k: (v.clone() if keep_fields == "device" else v.cpu().numpy())
+                              for k, v in f.items()}
+                del f
+    # one more call of K steps with every kernel launched directly between
+    # HIP events: the per-kernel times
+    dte, prof = _time_steps(sim, steps)
+    events_mlups = fluid * steps / dte / 1e6
+    done = 2 + max(warmup - 2, 0) + steps * repeats + steps
     d1 = sim.reduce()
     drift_out = None
     if drift_steps > done:
@@ -366,16 +382,15 @@ def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=None,
     else:
         kb = kernel_bytes(storage)
     kern = {}
-    tot = dt * repeats
     for k, (ms, cnt) in prof.items():
         if cnt:
             avg = ms / cnt / 1e3
             kern[k] = {"avg_ms": avg * 1e3, "gbs": kb[k] * fluid / avg / 1e9 if k in kb else None,
-                       "launches": cnt, "share": ms / 1e3 / tot}
+                       "launches": cnt, "share": ms / 1e3 / dte}
     m0 = d0[:, :2].sum(axis=0)
     m1 = d1[:, :2].sum(axis=0)
     out = {"mlups": mlups[0], "mlups_repeats": mlups, "mlups_median": float(np.median(mlups)),
-           "ms_per_step": dt / steps * 1e3, "dt": dt, "graph_mlups": graph_mlups,
+           "ms_per_step": dt / steps * 1e3, "dt": dt, "events_mlups": events_mlups,
            "fluid": fluid, "kernels": kern, "variant": var, "autotune_ms": tune_ms,
            "schedule": ("fused", "three kernels", "compact")[sim.schedule()],
            "mass_drift": [float((m1[0] - m0[0]) / m0[0]), float((m1[1] - m0[1]) / m0[1])],
@@ -429,7 +444,7 @@ def storage_form(r, storage, ref_fields=None, u_ref=None):
     sbf = step_bytes(storage)
     out = {"storage": storage, "mlups": round(r["mlups"], 1),
            "mlups_median": round(r["mlups_median"], 1), "ms_per_step": round(r["ms_per_step"], 4),
-           "graph_mlups": round(r["graph_mlups"], 1), "schedule": r["schedule"],
+           "events_mlups": round(r["events_mlups"], 1), "schedule": r["schedule"],
            "wall_mode": r["wall_mode"],
            "step_roofline_frac": round(r["mlups"] * 1e6 * sbf / (HBM_PEAK_GBS * 1e9), 4),
            "step_bytes_per_node": sbf, "kernels": _kern_round(r["kernels"]),
@@ -476,7 +491,7 @@ def d2q9_form(steps, warmup, storage="fp32"):
     out = {"workload": "4096^2 periodic, 16 x 16 droplets R=48, density ratio 10, U=0.05, %s"
                        % storage.upper(),
            "nodes": r["fluid"], "steps": steps, "mlups": round(r["mlups"], 1),
-           "graph_mlups": round(r["graph_mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+           "events_mlups": round(r["events_mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
            "kernel": {"name": "k2_step<%s, %d, %d, 256, false>"
                               % (SNAMES[storage], r["variant"]["tx"], r["variant"]["ty"]),
                       "avg_ms": round(k["avg_ms"], 4), "gbs": round(k["gbs"], 1),
@@ -713,8 +728,8 @@ def main():
         sys.exit(2)
     import torch
 
-    if args.copy_probe:
-        copy_probe()
+    if args.copy_probe or args.copy_probe_check:
+        copy_probe(check=args.copy_probe_check)
         return
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -798,7 +813,7 @@ def main():
         "repeats": {"calls": REPEATS, "steps_each": args.steps,
                     "mlups": [round(v, 1) for v in main_r["mlups_repeats"]],
                     "median_mlups": round(main_r["mlups_median"], 1)},
-        "graph_mlups": round(main_r["graph_mlups"], 1),
+        "events_mlups": round(main_r["events_mlups"], 1),
         "step_bytes_per_node": sb,
         "step_bytes_moved_per_node": (COMPACT_BYTES["pull"] + COMPACT_BYTES["fused"]) if compact
                                      else kernel_bytes(args.storage)["pull"] + kernel_bytes(args.storage)["fused"],
@@ -861,7 +876,7 @@ def main():
                                 "nodes": r["fluid"], "steps": steps_b, "mlups": round(r["mlups"], 1),
                                 "mlups_median": round(r["mlups_median"], 1),
                                 "ms_per_step": round(r["ms_per_step"], 4),
-                                "graph_mlups": round(r["graph_mlups"], 1),
+                                "events_mlups": round(r["events_mlups"], 1),
                                 "schedule": r["schedule"], "fused_variant": r["variant"],
                                 "compact_variant": r["compact_variant"],
                                 "step_roofline_frac": round(r["mlups"] * 1e6 * 432 / (HBM_PEAK_GBS * 1e9), 4),
@@ -874,7 +889,7 @@ def main():
                                 "two_buffer_bytes": main_r["pop_buffer_bytes"],
                                 "mlups": round(r["mlups"], 1),
                                 "ms_per_step": round(r["ms_per_step"], 4),
-                                "graph_mlups": round(r["graph_mlups"], 1),
+                                "events_mlups": round(r["events_mlups"], 1),
                                 "schedule": r["schedule"],
                                 "kernels": _kern_round(r["kernels"]),
                                 "mass_drift": r["mass_drift"], "nonfinite": r["nonfinite"]}
@@ -884,8 +899,8 @@ def main():
             r = run_form([ws], "fp32", steps_s, args.warmup, args.variant)
             forms["small"] = {"workload": "static droplet 32^3 (density ratio 1, R=8), FP32",
                               "nodes": r["fluid"], "steps": steps_s,
-                              "mlups_direct_launches": round(r["mlups"], 1),
-                              "graph_mlups": round(r["graph_mlups"], 1),
+                              "mlups": round(r["mlups"], 1),
+                              "events_mlups": round(r["events_mlups"], 1),
                               "schedule": r["schedule"],
                               "ms_per_step": round(r["ms_per_step"], 4),
                               "mass_drift": r["mass_drift"], "nonfinite": r["nonfinite"]}
