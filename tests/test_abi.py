@@ -163,6 +163,8 @@ def test_null_handle_calls_fail_cleanly():
     assert L.cglbm_box_offset(None, 0) == -1
     out = (C.c_double * 13)()
     assert L.cglbm_reduce(None, None, out, 1, None) == -5
+    assert L.cglbm_set_wall_mode(None, 0, None) == -5
+    assert L.cglbm_get_wall_mode(None) == -1
 
 
 def test_inplace_layout_restrictions():

@@ -102,3 +102,26 @@ def test_autotuned_wall_modes():
     _same(_fields(ref, len(cases)), _fields(sim, len(cases)), "autotuned")
     sim.close()
     ref.close()
+
+
+def test_wall_mode_argument_checks():
+    """Modes outside 0..3 are refused with CGLBM_EINVAL and leave the mode as
+    it was; a D2Q9 handle has no wall modes (CGLBM_EUNSUPPORTED)."""
+    import paper_2309_07801_amd as pkg
+    cases = _cases()[2:]
+    sim = _sim(cases)
+    sim.set_wall_mode(1)
+    for bad in (-1, 4):
+        with pytest.raises(pkg.CglbmError) as ei:
+            sim.set_wall_mode(bad)
+        assert ei.value.code == -1
+    assert sim.wall_mode() == 1
+    sim.close()
+    box = WL.Box(nx=40, ny=30, nz=1, rho0_r=10.0, rho0_b=1.0, alpha_r=WL.alpha_heavy_2d(10.0),
+                 alpha_b=WL.ALPHA_LIGHT_2D, nu_r=0.1, nu_b=0.1, sigma=0.01, beta=0.7, walls=1)
+    rr, rb, u = WL.droplet_fields(box, [(19.5, 14.5, 0.0)], [6.0])
+    sim2 = pkg.Simulation([pkg.box_params_of(box)], [rr], [rb], [u], lattice="d2q9")
+    with pytest.raises(pkg.CglbmError) as ei:
+        sim2.set_wall_mode(0)
+    assert ei.value.code == -3
+    sim2.close()
