@@ -122,6 +122,14 @@ __device__ __forceinline__ int64_t opaque_i64(int64_t v) {
 // the correctly rounded division and square root sequences.
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+// The wall rule of the stencils (a solid neighbour takes the centre node's
+// value).  The neighbour's value v is an argument, so its (in-bounds) LDS
+// load is issued whatever the flag and the choice is one select: written as
+// `solid ? centre : array[...]`, the conditional load had become a branch
+// per stencil point in the walled kernels (450 branches in one of them).
+__device__ __forceinline__ float wall_rule(bool solid, float centre, float v) {
+  return solid ? centre : v;
+}
 // num / den from r, the hardware reciprocal of den, refined by one
 // Newton-Raphson step on the residual num - den q (formed exactly by an
 // FMA): within about half an ulp, exactly 1 for num == den and 0 for
@@ -157,6 +165,15 @@ __device__ __forceinline__ float buf_ld_f32(__amdgpu_buffer_rsrc_t r, uint32_t o
 }
 __device__ __forceinline__ double buf_ld_f64(__amdgpu_buffer_rsrc_t r, uint32_t off) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+// A 4- or 8-byte word (a plane element of a population array).
+template <class W>
+__device__ __forceinline__ W buf_ld_w(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  if constexpr (sizeof(W) == 8) {
+    return __builtin_bit_cast(W, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+  } else {
+    return __builtin_bit_cast(W, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+  }
 }
 __device__ __forceinline__ void buf_st(float v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, 0,
@@ -461,6 +478,50 @@ __device__ __forceinline__ void st_rb(const Pops<S> &p, int i, uint32_t d, typen
   }
 }
 
+// A wall stash of the compact pull through one buffer descriptor over all
+// its planes, with each access's plane in the lane offset (a stash holds
+// solid nodes only; the host keeps it below 4 GiB).  The z march then holds
+// one scalar descriptor per stash: with a pointer or a descriptor per plane
+// the 54 plane addresses had been hoisted into scalar registers and spilled
+// to vector lanes (627 v_readlane / v_writelane in one instantiation).
+template <class S>
+struct StashBuf {
+  using W = typename S::W;
+  __amdgpu_buffer_rsrc_t r;
+  uint32_t pb;    // bytes per plane
+  uint32_t rest;  // byte offset of the FP64 rest planes (mass-exact formats)
+  __device__ StashBuf(const void *base, int64_t plane) {
+    pb = (uint32_t)plane * (uint32_t)sizeof(W);
+    rest = (uint32_t)align256(Pops<S>::kPlanes * plane * (int64_t)sizeof(W));
+    const uint32_t bytes = rest + (S::kExact ? 16u * (uint32_t)plane : 0u);
+    r = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, 0x00020000);
+  }
+  __device__ uint32_t off(int i, int c, uint32_t s) const {
+    return (uint32_t)Pops<S>::slot(i, c) * pb + s * (uint32_t)sizeof(W);
+  }
+  // both colours of direction i at slot s, as stored
+  __device__ void ld(int i, uint32_t s, typename S::T &rv, typename S::T &bv) const {
+    if constexpr (S::kPaired) {
+      const W w = buf_ld_w<W>(r, off(i, 0, s));
+      rv = S::lo(w);
+      bv = S::hi(w);
+    } else {
+      rv = buf_ld_w<W>(r, off(i, 0, s));
+      bv = buf_ld_w<W>(r, off(i, 1, s));
+    }
+  }
+  __device__ void st(int i, uint32_t d, typename S::T rv, typename S::T bv) const {
+    if constexpr (S::kPaired) {
+      buf_st(S::pack(rv, bv), r, off(i, 0, d));
+    } else {
+      buf_st(rv, r, off(i, 0, d));
+      buf_st(bv, r, off(i, 1, d));
+    }
+  }
+  __device__ uint32_t rest_off(int c, uint32_t s) const {
+    return rest + (uint32_t)c * (pb / (uint32_t)sizeof(W)) * 8u + s * 8u;
+  }
+};
 // ---------------------------------------------------------------------------
 // k_pull: f^k_i(x) = stored_i(x - c_i); local moments; bounce-back at solid
 // nodes (the pulled populations are reversed and stored for the next step).
@@ -674,7 +735,7 @@ __device__ __forceinline__ void lds_gradient(const float *f, int c, Solid solid,
       const bool s = solid(dy, dz);
 #pragma unroll
       for (int dx = -1; dx <= 1; ++dx)
-        v[dz + 1][dy + 1][dx + 1] = s ? vc : f[c + dx + SY * dy + SZ * dz];
+        v[dz + 1][dy + 1][dx + 1] = wall_rule(s, vc, f[c + dx + SY * dy + SZ * dz]);
     }
   // (1/c_s^2) w_i c_i = 3 * w(dx) w(dy) w(dz) * c_i; for the pair along one
   // axis the factor is 3 * (1/6) * w(.) w(.) = w(.) w(.) / 2.
@@ -1693,7 +1754,7 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
               const bool sd = szd | sy(ly + 1 + dy);
 #pragma unroll
               for (int dx = -1; dx <= 1; ++dx)
-                v[dz + 1][dy + 1][dx + 1] = sd ? vc : pl[c3 + dx + G::R3X * dy];
+                v[dz + 1][dy + 1][dx + 1] = wall_rule(sd, vc, pl[c3 + dx + G::R3X * dy]);
             }
           }
           float gx = 0.f, gy = 0.f, gz = 0.f;
@@ -1758,7 +1819,7 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
                 const bool sd = szd | sy(ly + 2 + dy);
 #pragma unroll
                 for (int dx = -1; dx <= 1; ++dx)
-                  v[dz + 1][dy + 1][dx + 1] = sd ? vc : pl[c2 + dx + G::R2X * dy];
+                  v[dz + 1][dy + 1][dx + 1] = wall_rule(sd, vc, pl[c2 + dx + G::R2X * dy]);
               }
             }
             float gx = 0.f, gy = 0.f, gz = 0.f;
@@ -1834,23 +1895,23 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
             const float *pl = b2 < 0 ? qm[0] : (b2 > 0 ? qp[0] : qc[0]);
             const bool sdd = (b2 < 0 ? sz_m : (b2 > 0 ? sz_p : false)) | sy(oy + 3 + a2);
             const float vc = qc[0][c1];
-            const float vp = sdd ? vc : pl[c1 + 1 + G::R1X * a2];
-            const float vm = sdd ? vc : pl[c1 - 1 + G::R1X * a2];
+            const float vp = wall_rule(sdd, vc, pl[c1 + 1 + G::R1X * a2]);
+            const float vm = wall_rule(sdd, vc, pl[c1 - 1 + G::R1X * a2]);
             Qx = fmaf(w, vp - vm, Qx);
           }
           {  // y: a2 = dx, b2 = dz
             const float *pl = b2 < 0 ? qm[1] : (b2 > 0 ? qp[1] : qc[1]);
             const bool szd = b2 < 0 ? sz_m : (b2 > 0 ? sz_p : false);
             const float vc = qc[1][c1];
-            const float vp = (szd | sy(oy + 4)) ? vc : pl[c1 + a2 + G::R1X];
-            const float vm = (szd | sy(oy + 2)) ? vc : pl[c1 + a2 - G::R1X];
+            const float vp = wall_rule(szd | sy(oy + 4), vc, pl[c1 + a2 + G::R1X]);
+            const float vm = wall_rule(szd | sy(oy + 2), vc, pl[c1 + a2 - G::R1X]);
             Qy = fmaf(w, vp - vm, Qy);
           }
           {  // z: a2 = dx, b2 = dy
             const bool syd = sy(oy + 3 + b2);
             const float vc = qc[2][c1];
-            const float vp = (sz_p | syd) ? vc : qp[2][c1 + a2 + G::R1X * b2];
-            const float vm = (sz_m | syd) ? vc : qm[2][c1 + a2 + G::R1X * b2];
+            const float vp = wall_rule(sz_p | syd, vc, qp[2][c1 + a2 + G::R1X * b2]);
+            const float vm = wall_rule(sz_m | syd, vc, qm[2][c1 + a2 + G::R1X * b2]);
             Qz = fmaf(w, vp - vm, Qz);
           }
         }
@@ -2028,6 +2089,10 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
 
   for (int s = z0 - 1; s <= z1; ++s) {
     const int64_t plane = opaque_i64(plane_arg);
+    // the wall stashes (one descriptor each, rebuilt per slab from an
+    // opaque plane length so that nothing of them is hoisted)
+    const int64_t wpl = WALLS ? opaque_i64(wplane) : wplane;
+    const StashBuf<S> win(wst_in, wpl), wout(wst_out, wpl);
     const int gz = wrap_any(s, nz);
     const uint32_t zoff = (uint32_t)B.base + nxy * (uint32_t)gz;
     bool rsolid[G::CP];
@@ -2080,6 +2145,22 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
       for (int k = 0; k < G::CP; ++k) {
         const int j = tid + k * G::NT;
         if (j < G::R1) {
+          // a solid ring point: what the bounce-back stored for these
+          // directions, loaded before the emission so that the loads'
+          // latency passes behind it
+          typename S::T stv[9][2];
+          if (WALLS && rsolid[k]) {
+            const uint32_t wslot = (uint32_t)B.wbase + wall_slot(B, rgx[k], rgy[k], gz);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+              const int i = dir_of(q % 3 - 1, q / 3 - 1, pz - 1);
+              if (EXACT && i == 0) {
+                stv[q][0] = stv[q][1] = S::enc(0.f);
+              } else {
+                win.ld(i, wslot, stv[q][0], stv[q][1]);
+              }
+            }
+          }
 #pragma unroll
           for (int cy = 0; cy < 3; ++cy) {
             // (the plain maps here: the doubled ones of emit_recoloured give
@@ -2112,25 +2193,12 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
             // unbranched emission above, so that the hot loop stays one
             // basic block.  (A solid column node's own sums above feed only
             // its own moments, which are stored as zero.)
-            const Pops<S> win(const_cast<void *>(wst_in), wplane);
-            const uint32_t wslot = (uint32_t)B.wbase + wall_slot(B, rgx[k], rgy[k], gz);
             const int slot = EXACT ? rls[k] : j;
 #pragma unroll
-            for (int cy = 0; cy < 3; ++cy)
-#pragma unroll
-              for (int cx = 0; cx < 3; ++cx) {
-                const int i = dir_of(cx - 1, cy - 1, pz - 1);
-                const int q = 3 * cy + cx;
-                float vr = 0.f, vb = 0.f;
-                if (!(EXACT && i == 0)) {
-                  typename S::T er, eb;
-                  ld_rb(win, i, wslot, er, eb);
-                  vr = S::dec(er);
-                  vb = S::dec(eb);
-                }
-                xb[2 * q][slot] = vr;
-                xb[2 * q + 1][slot] = vb;
-              }
+            for (int q = 0; q < 9; ++q) {
+              xb[2 * q][slot] = S::dec(stv[q][0]);
+              xb[2 * q + 1][slot] = S::dec(stv[q][1]);
+            }
           }
         }
       }
@@ -2212,7 +2280,6 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
           // a solid column node keeps what arrives, reversed, for the next step
           const int d = s + pz - 1, gd = wrap_any(d, nz);
           if (in_xy && d >= z0 && d < z1 && is_solid(B, gyo, gd)) {
-            const Pops<S> wout(wst_out, wplane);
             const uint32_t slot = (uint32_t)B.wbase + wall_slot(B, gxo, gyo, gd);
 #pragma unroll
             for (int cy = 0; cy < 3; ++cy)
@@ -2222,11 +2289,11 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
                 const int i = dir_of(cx - 1, cy - 1, pz - 1);
                 if (EXACT && i == 0) {
                   // mass-exact storage: the rest populations stay as stored
-                  const Pops<S> win(const_cast<void *>(wst_in), wplane);
-                  at(wout.restp(0), slot) = at(win.restp(0), slot);
-                  at(wout.restp(1), slot) = at(win.restp(1), slot);
+#pragma unroll
+                  for (int c = 0; c < 2; ++c)
+                    buf_st(buf_ld_f64(win.r, win.rest_off(c, slot)), wout.r, wout.rest_off(c, slot));
                 } else {
-                  st_rb(wout, opposite(i), slot, S::enc(fr[q]), S::enc(fb[q]));
+                  wout.st(opposite(i), slot, S::enc(fr[q]), S::enc(fb[q]));
                 }
               }
           }
