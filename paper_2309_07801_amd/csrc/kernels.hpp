@@ -142,6 +142,17 @@ __device__ __forceinline__ float div_refined(float num, float den, float r) {
   return fmaf(r, fmaf(-den, q, num), q);
 }
 
+// Order parameter phi = (rr - rb) / (rr + rb) of the stencils (Eq. 14, the
+// densities already divided by their reference densities): the refined
+// quotient, exactly +-1 in a pure phase (num = +-den), so that the bulk
+// gradient is exactly zero, at half the instructions of the correctly
+// rounded division it replaced (measured 0.027 ms of the 0.48 ms compact
+// fused kernel at 256^3, where it runs on 1.9x the column's points).
+__device__ __forceinline__ float phase_field(float rr, float rb) {
+  const float den = rr + rb;
+  return den > 0.f ? div_refined(rr - rb, den, rcp(den)) : 0.f;
+}
+
 // Scalar buffer descriptor of plane p of an SoA array whose planes are
 // plane_bytes apart.  The host keeps every plane below 4 GiB, so a lane
 // addresses it with one 32-bit byte offset and no vector address arithmetic.
@@ -790,10 +801,7 @@ __global__ __launch_bounds__(kBlock) void k_interface(const BoxDev *__restrict__
         (uint32_t)B.base + (uint32_t)gx + (uint32_t)nx * ((uint32_t)gy + (uint32_t)ny * (uint32_t)gz);
     const float rr = at(PL(aux, A_RR), node) * B.ir0r;
     const float rb = at(PL(aux, A_RB), node) * B.ir0b;
-    const float den = rr + rb;
-    // correctly rounded: phi is exactly +-1 in a pure phase, so the bulk
-    // gradient is exactly zero
-    s_phi[i] = den > 0.f ? (rr - rb) / den : 0.f;
+    s_phi[i] = phase_field(rr, rb);
   }
   __syncthreads();
 
@@ -1724,8 +1732,7 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
         if (i < G::R3) {
           const float rr = a_rr[k] * B.ir0r;
           const float rb = a_rb[k] * B.ir0b;
-          const float den = rr + rb;
-          ph[i] = den > 0.f ? (rr - rb) / den : 0.f;
+          ph[i] = phase_field(rr, rb);
         }
       }
     }
