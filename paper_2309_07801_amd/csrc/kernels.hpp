@@ -2010,22 +2010,26 @@ struct CPullGeom {
   static constexpr int NT = TX * TY;
   static constexpr int R1X = TX + 2, R1Y = TY + 2, R1 = R1X * R1Y;
   static constexpr int CP = (R1 + NT - 1) / NT;  // ring points per thread
+  // the halo fills whole wavefronts: those of the rows first, then one or
+  // more of the columns
+  static_assert(CP == 2 && NT % 64 == 0 && (2 * TX) % 64 == 0, "ring layout");
   // ring point j of the block: the column's own points first (thread j's
-  // column node), then the halo (top and bottom rows, then the two sides);
-  // (lx, ly) in the (TX + 2) x (TY + 2) ring, x fastest
+  // column node), then the halo: the rows below and above the tile (without
+  // the corners), then the columns beside it (corners included); (lx, ly) in
+  // the (TX + 2) x (TY + 2) ring
   __device__ static void point(int j, int &lx, int &ly) {
     if (j < NT) {
       lx = (j % TX) + 1;
       ly = (j / TX) + 1;
     } else {
       const int h = j - NT;
-      if (h < 2 * R1X) {
-        lx = h % R1X;
-        ly = (h / R1X) * (R1Y - 1);
+      if (h < 2 * TX) {
+        lx = h % TX + 1;
+        ly = (h / TX) * (R1Y - 1);
       } else {
-        const int h2 = h - 2 * R1X;
+        const int h2 = h - 2 * TX;
         lx = (h2 & 1) * (R1X - 1);
-        ly = (h2 >> 1) + 1;
+        ly = h2 >> 1;
       }
     }
   }
@@ -2054,26 +2058,25 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
   const int nx = B.nx, ny = B.ny, nz = B.nz;
   const int z1 = te.z1;
   const uint32_t nxy = (uint32_t)nx * (uint32_t)ny;
-  // ring points of this thread and their LDS slots (row-major in the ring);
-  // lanes past the ring read point 0 and write nothing
+  // ring points of this thread (its own column node first, then a halo
+  // point or none) and their LDS slots (row-major in the ring); lanes past
+  // the ring read point 0 and write nothing
   uint32_t roff[G::CP];
   int rgx[G::CP], rgy[G::CP], rls[G::CP];
+  // a halo point's one c_y row (above or below the tile) or c_x column
+  // (beside it) that reaches the tile: c = +1 (true) or -1
+  bool rfwd = false;
+  // a wavefront of halo points holds rows only or columns only
+  const bool rowwave = (int)__builtin_amdgcn_readfirstlane(tid) < 2 * TX;
 #pragma unroll
   for (int k = 0; k < G::CP; ++k) {
     const int j = tid + k * G::NT;
     roff[k] = 0;
     rgx[k] = rgy[k] = rls[k] = 0;
     if (j < G::R1) {
-      // the mass-exact storage puts each thread's own column node first
-      // (its ring point k = 0, whose emitted values close its rest
-      // populations); otherwise the ring is row-major
       int lx, ly;
-      if constexpr (EXACT) {
-        G::point(j, lx, ly);
-      } else {
-        lx = j % G::R1X;
-        ly = j / G::R1X;
-      }
+      G::point(j, lx, ly);
+      if (k > 0) rfwd = rowwave ? ly == 0 : lx == 0;
       rls[k] = lx + G::R1X * ly;
       rgx[k] = wrap_any(x0 + lx - 1, nx);
       rgy[k] = wrap_any(y0 + ly - 1, ny);
@@ -2168,39 +2171,78 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
               }
             }
           }
+          const int slot = rls[k];
+          if (k == 0) {
+            // the column node: all nine directions
 #pragma unroll
-          for (int cy = 0; cy < 3; ++cy) {
-            // (the plain maps here: the doubled ones of emit_recoloured give
-            // the same bits but cost this kernel 8 VGPRs and an occupancy step)
+            for (int cy = 0; cy < 3; ++cy) {
+              // (the plain maps here: the doubled ones of emit_recoloured
+              // give the same bits but cost this kernel 8 VGPRs and an
+              // occupancy step)
+              float fx[3];
+              cm_to_pop_1d(h[k][0][cy][pz], h[k][1][cy][pz], h[k][2][cy][pz], pux[k], fx[0], fx[1],
+                           fx[2]);
+#pragma unroll
+              for (int cx = 0; cx < 3; ++cx) {
+                const int i = dir_of(cx - 1, cy - 1, pz - 1);
+                const float cR = (kCX[i] ? (kCX[i] > 0 ? pRx[k] : -pRx[k]) : 0.f) +
+                                 (kCY[i] ? (kCY[i] > 0 ? pRy[k] : -pRy[k]) : 0.f) +
+                                 (kCZ[i] ? (kCZ[i] > 0 ? pRz[k] : -pRz[k]) : 0.f);
+                const float d = 3.0f * weight(i) * cR;
+                const int q = 3 * cy + cx;
+                const float vr = fmaf(pcr[k], fx[cx], d), vb = fmaf(pcb[k], fx[cx], -d);
+                if (EXACT && i != 0) {
+                  emit_r += (double)vr;
+                  emit_b += (double)vb;
+                }
+                xb[2 * q][slot] = vr;
+                xb[2 * q + 1][slot] = vb;
+              }
+            }
+          } else if (rowwave) {
+            // a halo point below (c_y = +1) or above (c_y = -1) the tile:
+            // the three directions of that row, the same values as above
+            const bool fw = rfwd;
             float fx[3];
-            cm_to_pop_1d(h[k][0][cy][pz], h[k][1][cy][pz], h[k][2][cy][pz], pux[k], fx[0], fx[1],
-                         fx[2]);
+            cm_to_pop_1d(fw ? h[k][0][2][pz] : h[k][0][0][pz], fw ? h[k][1][2][pz] : h[k][1][0][pz],
+                         fw ? h[k][2][2][pz] : h[k][2][0][pz], pux[k], fx[0], fx[1], fx[2]);
+            const float yR = fw ? pRy[k] : -pRy[k];
 #pragma unroll
             for (int cx = 0; cx < 3; ++cx) {
-              const int i = dir_of(cx - 1, cy - 1, pz - 1);
-              const float cR = (kCX[i] ? (kCX[i] > 0 ? pRx[k] : -pRx[k]) : 0.f) +
-                               (kCY[i] ? (kCY[i] > 0 ? pRy[k] : -pRy[k]) : 0.f) +
+              const int i = dir_of(cx - 1, 1, pz - 1);  // |c|, c_x, c_z as in either row
+              const float cR = (kCX[i] ? (kCX[i] > 0 ? pRx[k] : -pRx[k]) : 0.f) + yR +
                                (kCZ[i] ? (kCZ[i] > 0 ? pRz[k] : -pRz[k]) : 0.f);
               const float d = 3.0f * weight(i) * cR;
-              const int q = 3 * cy + cx;
-              const float vr = fmaf(pcr[k], fx[cx], d), vb = fmaf(pcb[k], fx[cx], -d);
-              if (EXACT && k == 0 && i != 0) {
-                emit_r += (double)vr;
-                emit_b += (double)vb;
-              }
-              const int slot = EXACT ? rls[k] : j;
-              xb[2 * q][slot] = vr;
-              xb[2 * q + 1][slot] = vb;
+              const int q = (fw ? 6 : 0) + cx;
+              xb[2 * q][slot] = fmaf(pcr[k], fx[cx], d);
+              xb[2 * q + 1][slot] = fmaf(pcb[k], fx[cx], -d);
+            }
+          } else {
+            // a halo point left (c_x = +1) or right (c_x = -1) of the tile:
+            // the three directions of that column
+            const bool fw = rfwd;
+            const float xR = fw ? pRx[k] : -pRx[k];
+#pragma unroll
+            for (int cy = 0; cy < 3; ++cy) {
+              float fx[3];
+              cm_to_pop_1d(h[k][0][cy][pz], h[k][1][cy][pz], h[k][2][cy][pz], pux[k], fx[0], fx[1],
+                           fx[2]);
+              const float fv = fw ? fx[2] : fx[0];
+              const int i = dir_of(1, cy - 1, pz - 1);  // |c|, c_y, c_z as in either column
+              const float cR = xR + (kCY[i] ? (kCY[i] > 0 ? pRy[k] : -pRy[k]) : 0.f) +
+                               (kCZ[i] ? (kCZ[i] > 0 ? pRz[k] : -pRz[k]) : 0.f);
+              const float d = 3.0f * weight(i) * cR;
+              const int q = 3 * cy + (fw ? 2 : 0);
+              xb[2 * q][slot] = fmaf(pcr[k], fv, d);
+              xb[2 * q + 1][slot] = fmaf(pcb[k], fv, -d);
             }
           }
           if (WALLS && rsolid[k]) {
             // A solid point emits what the bounce-back stored there instead
             // (its rest population, which only it receives, stays in the
             // stash): one branch per point and z component, after the
-            // unbranched emission above, so that the hot loop stays one
-            // basic block.  (A solid column node's own sums above feed only
-            // its own moments, which are stored as zero.)
-            const int slot = EXACT ? rls[k] : j;
+            // emission above.  (A solid column node's own sums above feed
+            // only its own moments, which are stored as zero.)
 #pragma unroll
             for (int q = 0; q < 9; ++q) {
               xb[2 * q][slot] = S::dec(stv[q][0]);
