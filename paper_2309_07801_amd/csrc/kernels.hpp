@@ -2059,15 +2059,18 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
   const int z1 = te.z1;
   const uint32_t nxy = (uint32_t)nx * (uint32_t)ny;
   // ring points of this thread (its own column node first, then a halo
-  // point or none) and their LDS slots (row-major in the ring); lanes past
-  // the ring read point 0 and write nothing
+  // point or none) and their LDS slots (row-major in the ring); wavefronts
+  // with no halo point skip the second pass, and the lanes past the ring in
+  // the last halo wavefront read point 0 and write nothing
   uint32_t roff[G::CP];
   int rgx[G::CP], rgy[G::CP], rls[G::CP];
   // a halo point's one c_y row (above or below the tile) or c_x column
   // (beside it) that reaches the tile: c = +1 (true) or -1
   bool rfwd = false;
-  // a wavefront of halo points holds rows only or columns only
-  const bool rowwave = (int)__builtin_amdgcn_readfirstlane(tid) < 2 * TX;
+  // a wavefront of halo points holds rows only or columns only; the
+  // wavefronts past the halo have no second point
+  const int wave0 = (int)__builtin_amdgcn_readfirstlane(tid);
+  const bool rowwave = wave0 < 2 * TX, halowave = wave0 + G::NT < G::R1;
 #pragma unroll
   for (int k = 0; k < G::CP; ++k) {
     const int j = tid + k * G::NT;
@@ -2120,6 +2123,17 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
     float pux[G::CP], pcr[G::CP], pcb[G::CP], pRx[G::CP], pRy[G::CP], pRz[G::CP];
 #pragma unroll
     for (int k = 0; k < G::CP; ++k) {
+      if (k > 0 && !halowave) {
+        // (defined values here keep the register use of the others down)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int cy = 0; cy < 3; ++cy)
+#pragma unroll
+            for (int cz = 0; cz < 3; ++cz) h[k][a][cy][cz] = 0.f;
+        pux[k] = pcr[k] = pcb[k] = pRx[k] = pRy[k] = pRz[k] = 0.f;
+        continue;
+      }
       float c[kCompact];
 #pragma unroll
       for (int m = 0; m < kCompact; ++m) c[m] = ldpl(cst, plane, m, zoff + roff[k]);
@@ -2154,7 +2168,7 @@ __global__ __launch_bounds__(TX *TY) void k_cpull(const BoxDev *__restrict__ box
 #pragma unroll
       for (int k = 0; k < G::CP; ++k) {
         const int j = tid + k * G::NT;
-        if (j < G::R1) {
+        if ((k == 0 || halowave) && j < G::R1) {
           // a solid ring point: what the bounce-back stored for these
           // directions, loaded before the emission so that the loads'
           // latency passes behind it
