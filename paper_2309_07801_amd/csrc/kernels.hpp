@@ -1640,12 +1640,20 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
   // ahead, before the stores of the collision.  The waits for them then
   // never include those stores, which share the in-order vector memory
   // counter with the loads.
+  // (except the loads of a wavefront's later points when none of its lanes
+  // has one, e.g. the second R1 point in five of the eight wavefronts of a
+  // 64x8 column: their values are set to zero instead)
   float a_rr[G::A_PER], a_rb[G::A_PER];
   float pc_[C_PER][5];
+  const int wave0 = (int)__builtin_amdgcn_readfirstlane(tid);
   auto load_a = [&](int sl, int64_t pl) {
     const uint32_t zoff = (uint32_t)B.base + nxy * (uint32_t)wrap_any(sl, nz);
 #pragma unroll
     for (int k = 0; k < G::A_PER; ++k) {
+      if (k > 0 && wave0 + k * G::NT >= G::R3) {
+        a_rr[k] = a_rb[k] = 0.f;
+        continue;
+      }
       const uint32_t node = zoff + (uint32_t)a_off[k];
       a_rr[k] = ldpl(aux, pl, A_RR, node);
       a_rb[k] = ldpl(aux, pl, A_RB, node);
@@ -1655,6 +1663,11 @@ __global__ __launch_bounds__(TX *TY, MINW) void k_fused(const BoxDev *__restrict
     const uint32_t zoff = (uint32_t)B.base + nxy * (uint32_t)wrap_any(sl, nz);
 #pragma unroll
     for (int kk = 0; kk < C_PER; ++kk) {
+      if (kk > 0 && wave0 + kk * G::NT >= G::R1) {
+#pragma unroll
+        for (int m = 0; m < 5; ++m) pc_[kk][m] = 0.f;
+        continue;
+      }
       const uint32_t node = zoff + c_off[kk];
       pc_[kk][0] = ldpl(aux, pl, A_RR, node);
       pc_[kk][1] = ldpl(aux, pl, A_RB, node);
