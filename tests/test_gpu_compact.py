@@ -85,11 +85,16 @@ def test_compact_schedule_close_to_fused_and_conserves_mass():
         out.append(gpu_fields(sim))
         sim.close()
     print("mass drift fused / compact", drift)
+    # The schedules differ only in the FP32 order of the moment sums; after
+    # 300 steps the fields were measured 1.2e-6 apart in density and 4.4e-6 U
+    # in velocity, and the compact run's colour masses 5e-8 from the start.
     for name in ("rho_r", "rho_b"):
-        assert np.abs(out[0][name] - out[1][name]).max() <= 5e-5 * np.abs(out[0][name]).max(), name
+        print(name, np.abs(out[0][name] - out[1][name]).max() / np.abs(out[0][name]).max())
+        assert np.abs(out[0][name] - out[1][name]).max() <= 5e-6 * np.abs(out[0][name]).max(), name
     for name in ("ux", "uy", "uz"):
-        assert np.abs(out[0][name] - out[1][name]).max() <= 5e-4 * 0.05, name
-    assert max(abs(x) for x in drift[1]) < 1e-4
+        print(name, np.abs(out[0][name] - out[1][name]).max() / 0.05)
+        assert np.abs(out[0][name] - out[1][name]).max() <= 2e-5 * 0.05, name
+    assert max(abs(x) for x in drift[1]) < 1e-6
 
 
 def test_compact_schedule_refuses_other_layouts():
@@ -201,9 +206,11 @@ def test_walls_close_to_fused_over_many_steps():
         out.append(gpu_fields(sim))
         sim.close()
     for name in ("rho_r", "rho_b"):
-        assert np.abs(out[0][name] - out[1][name]).max() <= 5e-5 * np.abs(out[0][name]).max(), name
+        print(name, np.abs(out[0][name] - out[1][name]).max() / np.abs(out[0][name]).max())
+        assert np.abs(out[0][name] - out[1][name]).max() <= 5e-6 * np.abs(out[0][name]).max(), name
     for name in ("ux", "uy", "uz"):
-        assert np.abs(out[0][name] - out[1][name]).max() <= 5e-4 * 0.04, name
+        print(name, np.abs(out[0][name] - out[1][name]).max() / 0.04)
+        assert np.abs(out[0][name] - out[1][name]).max() <= 2e-5 * 0.04, name
 
 
 def _general_cases():

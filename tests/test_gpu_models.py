@@ -59,7 +59,8 @@ def test_model_fields_match_oracle(model, use_q, steps):
         m = band if name == "kappa" else np.ones_like(band)
         scale = max(np.abs(o[name]).max(), 1e-30)
         err = np.abs(g[name] - o[name])[m].max()
-        assert err <= 2e-5 * scale + 1e-12, (name, err, scale)
+        print(model, use_q, steps, name, "relative", err / scale)
+        assert err <= 1e-5 * scale + 1e-12, (name, err, scale)
 
 
 @pytest.mark.parametrize("model,use_q", CASES)

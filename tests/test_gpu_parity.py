@@ -46,6 +46,8 @@ def test_fields_match_oracle_on_ragged_box(steps):
     sim.step(steps)
     g = gpu_fields(sim)
     o, _ = run_oracle(box, *fl, steps, seed=5, noise=1e-5)
+    # Measured: at most 6.4e-6 of the field's scale (the curvature after one
+    # step), 1.5e-6 for the moments, and 3.6e-7 for n in the band.
     for name in ALL:
         scale = max(np.abs(o[name]).max(), 1e-30)
         err = np.abs(g[name] - o[name]).max()
@@ -58,9 +60,10 @@ def test_fields_match_oracle_on_ragged_box(steps):
                 band = (o["nx"] ** 2 + o["ny"] ** 2 + o["nz"] ** 2) > 0.5
             assert band.any()
             err = np.abs(g[name] - o[name])[band].max()
-            assert err < 1e-4, name
+            print(steps, name, "in the interface band", err)
+            assert err < 1e-6, name
         else:
-            assert err <= 2e-5 * scale + 1e-12, name
+            assert err <= 1e-5 * scale + 1e-12, name
 
 
 def test_multi_step_translating_droplet():
@@ -155,7 +158,9 @@ def test_reduce_matches_oracle_fields():
     rho = o["rho_r"] + o["rho_b"]
     assert d[0] == pytest.approx(o["rho_r"].sum(), rel=1e-6)
     assert d[1] == pytest.approx(o["rho_b"].sum(), rel=1e-6)
-    assert d[2] == pytest.approx((rho * o["ux"]).sum(), rel=1e-4)
+    jx = (rho * o["ux"]).sum()
+    print("x momentum", d[2], jx, abs(d[2] - jx) / abs(jx))
+    assert d[2] == pytest.approx(jx, rel=1e-6)
     V = ((1 + o["phi"]) / 2).sum()
     assert d[7] == pytest.approx((3 * V / (4 * np.pi)) ** (1 / 3), rel=1e-6)
     assert d[12] == 0

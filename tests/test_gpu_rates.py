@@ -50,7 +50,8 @@ def test_rates_fields_after_one_step(k, model, use_q):
                  "Qz"):
         scale = max(np.abs(o[name]).max(), 1e-30)
         err = np.abs(g[name] - o[name]).max()
-        assert err <= 2e-5 * scale + 1e-12, (name, err, scale)
+        print(k, model, use_q, name, "relative", err / scale)
+        assert err <= 1e-5 * scale + 1e-12, (name, err, scale)
 
 
 @pytest.mark.parametrize("k", range(len(RATES)))
