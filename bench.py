@@ -192,6 +192,8 @@ def parse():
     ap.add_argument("--storage", default="fp32", choices=sorted(STORAGES))
     ap.add_argument("--forms", default=DEFAULT_FORMS, help="extra forms ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-resident", action="store_true",
+                    help="compact schedule: store the populations at the end of every call")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--schedule", type=int, default=None, choices=(0, 1, 2),
                     help="step schedule (default: the autotuner's choice)")
@@ -315,7 +317,8 @@ def _time_steps(sim, steps):
 
 
 def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=None,
-             lattice="d3q27", inplace=False, schedule=None, repeats=1, drift_steps=0):
+             lattice="d3q27", inplace=False, schedule=None, repeats=1, drift_steps=0,
+             resident=False):
     """Initialise, autotune, time `steps` steps (and `repeats - 1` more calls
     of as many); return throughput, per-kernel event timings, the per-colour
     mass drift, and (keep_fields "host" or "device") the fields of box 0
@@ -341,6 +344,10 @@ def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=None,
         sim.set_schedule(schedule)  # loads the geometry the autotuner chose for it
         var = pkg.variant_info(sim.variant(), lattice)
     wmode = sim.wall_mode() if lattice == "d3q27" else None
+    # compact schedule: keep the compact state resident between calls (the
+    # populations are stored when the state is read)
+    resident = bool(resident) and sim.schedule() == 2
+    sim.set_resident(resident)
     sim.step(max(warmup - 2, 0))  # also captures the step graph
     torch.cuda.synchronize()
     # timed region: `repeats` calls of K steps as the library runs them by
@@ -387,9 +394,19 @@ def run_form(workloads, storage, steps, warmup, variant=-1, keep_fields=None,
             avg = ms / cnt / 1e3
             kern[k] = {"avg_ms": avg * 1e3, "gbs": kb[k] * fluid / avg / 1e9 if k in kb else None,
                        "launches": cnt, "share": ms / 1e3 / dte}
+    nonres = None
+    if resident:
+        # the same K steps as one call that pulls the stored populations
+        # first and stores them again at its end
+        sim.set_resident(False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        nonres = fluid * steps / (time.perf_counter() - t0) / 1e6
     m0 = d0[:, :2].sum(axis=0)
     m1 = d1[:, :2].sum(axis=0)
-    out = {"mlups": mlups[0], "mlups_repeats": mlups, "mlups_median": float(np.median(mlups)),
+    out = {"mlups": mlups[0], "resident": resident, "nonresident_mlups": nonres, "mlups_repeats": mlups, "mlups_median": float(np.median(mlups)),
            "ms_per_step": dt / steps * 1e3, "dt": dt, "events_mlups": events_mlups,
            "fluid": fluid, "kernels": kern, "variant": var, "autotune_ms": tune_ms,
            "schedule": ("fused", "three kernels", "compact")[sim.schedule()],
@@ -445,6 +462,7 @@ def storage_form(r, storage, ref_fields=None, u_ref=None):
     out = {"storage": storage, "mlups": round(r["mlups"], 1),
            "mlups_median": round(r["mlups_median"], 1), "ms_per_step": round(r["ms_per_step"], 4),
            "events_mlups": round(r["events_mlups"], 1), "schedule": r["schedule"],
+           "resident": r["resident"],
            "wall_mode": r["wall_mode"],
            "step_roofline_frac": round(r["mlups"] * 1e6 * sbf / (HBM_PEAK_GBS * 1e9), 4),
            "step_bytes_per_node": sbf, "kernels": _kern_round(r["kernels"]),
@@ -468,7 +486,7 @@ def big_form(label, w, storages, steps, warmup, u_ref):
         # the compact schedule, or (a "_population" suffix) the population one
         st = name.split("_")[0]
         r = run_form([w], st, steps, warmup, keep_fields="device",
-                     schedule=0 if name.endswith("_population") else 2)
+                     schedule=0 if name.endswith("_population") else 2, resident=name == "fp32")
         out[name] = storage_form(r, st, ref, u_ref)
         if name == "fp32":
             ref = r["fields"]
@@ -751,7 +769,8 @@ def main():
     want_fields = any(f in STORAGES for f in forms_req)
     main_r = run_form(main_ws, args.storage, args.steps, args.warmup, args.variant,
                       keep_fields="device" if want_fields else None, schedule=sched,
-                      repeats=REPEATS, drift_steps=DRIFT_STEPS if forms_req else 0)
+                      repeats=REPEATS, drift_steps=DRIFT_STEPS if forms_req else 0,
+                      resident=not args.no_resident and args.storage in ("fp32", "fp32p"))
     fluid = main_r["fluid"]
     compact = main_r["schedule"] == "compact"
     kern = {k: v for k, v in main_r["kernels"].items() if k in ("pull", "fused")}
@@ -821,6 +840,9 @@ def main():
         "fused_variant": var,
         "compact_variant": main_r["compact_variant"],
         "schedule": main_r["schedule"],
+        "resident": main_r["resident"],
+        "nonresident_mlups": (round(main_r["nonresident_mlups"], 1)
+                              if main_r["nonresident_mlups"] else None),
         "autotune_ms": [round(m, 4) for m in main_r["autotune_ms"]],
         "mass_drift": main_r["mass_drift"],
         "mass_drift_steps": main_r["mass_drift_steps"],
@@ -870,11 +892,14 @@ def main():
         elif f == "batched":
             boxes = WL.batched_boxes()
             steps_b = min(args.steps, 1000)
-            r = run_form(boxes, "fp32p", steps_b, args.warmup, args.variant, schedule=2)
+            r = run_form(boxes, "fp32p", steps_b, args.warmup, args.variant, schedule=2,
+                         resident=True)
             forms["batched"] = {"workload": "96 periodic boxes, edges U{24..128}, density ratio "
                                             "in {1,10,100}, FP32 (colour-pair layout), compact schedule",
                                 "nodes": r["fluid"], "steps": steps_b, "mlups": round(r["mlups"], 1),
                                 "mlups_median": round(r["mlups_median"], 1),
+                                "resident": r["resident"],
+                                "nonresident_mlups": round(r["nonresident_mlups"], 1),
                                 "ms_per_step": round(r["ms_per_step"], 4),
                                 "events_mlups": round(r["events_mlups"], 1),
                                 "schedule": r["schedule"], "fused_variant": r["variant"],

@@ -291,8 +291,9 @@ int64_t cglbm_box_offset(const cglbm_handle *h, int32_t box);
  * the two population buffers (which one alternates with the step parity);
  * aux holds only fields derived from it, and the initial noise enters only
  * through it.  cglbm_state_buffer returns that buffer (pop_a or pop_b, a
- * device pointer to pop_bytes), valid until the next cglbm_step; NULL for a
- * NULL handle.  A copy of it ordered after the work enqueued so far is a
+ * device pointer to pop_bytes), valid until the next cglbm_step (and, with a
+ * resident compact state, only after cglbm_sync_state); NULL for a NULL
+ * handle.  A copy of it ordered after the work enqueued so far is a
  * checkpoint.  cglbm_load_state copies pop_bytes from the device buffer src
  * into the state buffer of h, on stream (asynchronous); h must have been
  * created with the same boxes, storage and lattice as the run that wrote the
@@ -349,6 +350,30 @@ int cglbm_set_schedule(cglbm_handle *h, int32_t schedule);
 /* Schedule the next step runs: 0, 1 or 2 as above (1 whenever a box needs
  * the three-kernel schedule), -1 for a NULL handle. */
 int cglbm_get_schedule(const cglbm_handle *h);
+
+/* Resident compact state (schedule 2 only; the moment-representation variant
+ * of the update, Sec. II with Eqs. 66-67, kept across calls).  With enable =
+ * 1, a schedule-2 call of cglbm_step no longer stores the populations at its
+ * end: the compact state of its last step stays in the other population
+ * buffer (and the wall stashes), and the next schedule-2 call continues from
+ * it without the population pull.  A sequence of calls then gives bit for
+ * bit the results of one call of as many steps.  Until the state is stored,
+ * the buffer cglbm_state_buffer returns is stale.  It is stored (one launch
+ * on the given stream, after which the next call starts from the
+ * populations again) by cglbm_sync_state, by cglbm_set_resident with enable
+ * = 0, and, before they read the state, by cglbm_moments, cglbm_reduce,
+ * cglbm_reduce_noalloc, cglbm_autotune and a cglbm_step in another schedule;
+ * cglbm_set_schedule, cglbm_set_variant, cglbm_set_wall_mode and
+ * cglbm_set_compact_variant store it on the stream of the last step first.
+ * cglbm_load_state discards it.  The caller keeps these calls on the stream
+ * of the steps (or orders the streams), as for every other reader.  Has no
+ * effect in schedules 0 and 1 and for D2Q9.  Default 0.  CGLBM_ESTATE for a
+ * NULL handle, CGLBM_EINVAL for enable other than 0 or 1.
+ * cglbm_get_resident returns 1 or 0, -1 for a NULL handle; cglbm_sync_state
+ * returns CGLBM_OK when there is nothing to store. */
+int cglbm_set_resident(cglbm_handle *h, int32_t enable, void *stream);
+int cglbm_get_resident(const cglbm_handle *h);
+int cglbm_sync_state(cglbm_handle *h, void *stream);
 
 /* Geometry of the compact schedule's pull: returns its index (-1 for a NULL
  * handle) and, if info is not NULL, writes info[0] = x extent, info[1] =

@@ -42,7 +42,8 @@ EXPORTED = ("cglbm_query_sizes", "cglbm_init", "cglbm_step", "cglbm_moments", "c
             "cglbm_last_error", "cglbm_version", "cglbm_query_sizes_d2q9", "cglbm_init_d2q9",
             "cglbm_lattice", "cglbm_variant_info_d2q9", "cglbm_state_buffer",
             "cglbm_load_state", "cglbm_compact_variant", "cglbm_set_compact_variant",
-            "cglbm_reduce_noalloc", "cglbm_set_wall_mode", "cglbm_get_wall_mode")
+            "cglbm_reduce_noalloc", "cglbm_set_wall_mode", "cglbm_get_wall_mode",
+            "cglbm_set_resident", "cglbm_get_resident", "cglbm_sync_state")
 # Lattices: the D3Q27 model of the paper's body and the D2Q9 model of App. A.
 LATTICES = ("d3q27", "d2q9")
 NUM_VARIANTS_D2Q9 = 4
@@ -131,6 +132,9 @@ def lib():
         L.cglbm_state_buffer.restype = vp
         L.cglbm_load_state.argtypes = [vp, vp, vp]
         L.cglbm_set_schedule.argtypes = [vp, i32]
+        L.cglbm_set_resident.argtypes = [vp, i32, vp]
+        L.cglbm_get_resident.argtypes = [vp]
+        L.cglbm_sync_state.argtypes = [vp, vp]
         L.cglbm_get_schedule.argtypes = [vp]
         L.cglbm_set_graph.argtypes = [vp, i32]
         L.cglbm_num_variants.argtypes = []
@@ -270,7 +274,8 @@ class Simulation:
 
     def state_tensor(self):
         """The population buffer that holds the current state (a view, valid
-        until the next step)."""
+        until the next step); a resident compact state is stored first."""
+        self.sync_state()
         ptr = lib().cglbm_state_buffer(self.h)
         if ptr == self.pop_a.data_ptr():
             return self.pop_a
@@ -383,6 +388,18 @@ class Simulation:
 
     def set_schedule(self, schedule: int):
         _check(lib().cglbm_set_schedule(self.h, int(schedule)))
+
+    def set_resident(self, enable: bool):
+        """Keep the compact schedule's state resident between step calls
+        (True) or store it as populations after each call (False, default)."""
+        _check(lib().cglbm_set_resident(self.h, 1 if enable else 0, _stream_ptr(self.stream)))
+
+    def resident(self) -> bool:
+        return int(lib().cglbm_get_resident(self.h)) == 1
+
+    def sync_state(self):
+        """Store a resident compact state as populations in the state buffer."""
+        _check(lib().cglbm_sync_state(self.h, _stream_ptr(self.stream)))
 
     def schedule(self) -> int:
         """Schedule in use: 0 fused, 1 three kernels, 2 compact."""

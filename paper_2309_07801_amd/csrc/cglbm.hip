@@ -552,6 +552,13 @@ struct cglbm_handle {
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t graphc[2] = {nullptr, nullptr};  // compact schedule: two inner steps
+  // compact schedule with the state resident between calls
+  // (cglbm_set_resident): clive is set while the other population buffer
+  // holds the compact state of the last step and the state buffer is stale;
+  // cwi is the wall stash that step wrote, cstream the stream it ran on
+  bool resident = false, clive = false;
+  int32_t cwi = 0;
+  hipStream_t cstream = nullptr;
   // profiling
   bool prof = false;
   std::vector<hipEvent_t> ev;
@@ -929,16 +936,42 @@ int time_graph(cglbm_handle *h, hipStream_t s, int reps, hipEvent_t e0, hipEvent
   return CGLBM_OK;
 }
 
+// Resident compact state (cglbm_set_resident): store it as populations in the
+// state buffer if the last call left it in compact form.  The next compact
+// call then starts from the populations again.
+int flush_compact(cglbm_handle *h, hipStream_t s) {
+  if (!h->clive) return CGLBM_OK;
+  h->clive = false;
+  const int rc = timed(h, s, KIND_EMIT, [&] { return launch_emit(h, s, h->cwi); });
+  return rc ? rc : check_launch();
+}
+
 int step_compact(cglbm_handle *h, int32_t n, hipStream_t s) {
   if (n == 0) return CGLBM_OK;
   // wall stashes (boxes with solid layers): step k's solid points emit from
   // stash wi, its arrivals at solid nodes go to 1 - wi; the first step
   // (the population pull) writes stash 0
   int wi = 0;
-  int rc = timed(h, s, KIND_PULL_FIRST, [&] { return launch_pull_compact(h, s); });
-  if (!rc) rc = timed(h, s, KIND_FUSED, [&] { return launch_compact_collide(h, s); });
-  int32_t k = 1;
-  if (!rc && h->use_graph && !h->prof && n >= 3) {
+  int rc = CGLBM_OK;
+  int32_t k = 0;
+  if (h->clive) {
+    // resident: continue from the compact state of the last call, with one
+    // direct step first if it left the stashes at odd parity (the captured
+    // pair starts from stash 0)
+    wi = h->cwi;
+    h->clive = false;
+    if (wi == 1) {
+      rc = timed(h, s, KIND_PULL, [&] { return launch_cpull(h, s, 1); });
+      if (!rc) rc = timed(h, s, KIND_FUSED, [&] { return launch_compact_collide(h, s); });
+      wi = 0;
+      k = 1;
+    }
+  } else {
+    rc = timed(h, s, KIND_PULL_FIRST, [&] { return launch_pull_compact(h, s); });
+    if (!rc) rc = timed(h, s, KIND_FUSED, [&] { return launch_compact_collide(h, s); });
+    k = 1;
+  }
+  if (!rc && h->use_graph && !h->prof && n - k >= 2) {
     if (!h->graphc[h->cur]) rc = capture_compact_pair(h);
     for (; !rc && k + 1 < n; k += 2) HIP_TRY(hipGraphLaunch(h->graphc[h->cur], s));
   }
@@ -947,7 +980,14 @@ int step_compact(cglbm_handle *h, int32_t n, hipStream_t s) {
     if (!rc) rc = timed(h, s, KIND_FUSED, [&] { return launch_compact_collide(h, s); });
     wi = 1 - wi;
   }
-  if (!rc) rc = timed(h, s, KIND_EMIT, [&] { return launch_emit(h, s, wi); });
+  if (rc) return rc;
+  if (h->resident) {
+    h->clive = true;
+    h->cwi = wi;
+    h->cstream = s;
+  } else {
+    rc = timed(h, s, KIND_EMIT, [&] { return launch_emit(h, s, wi); });
+  }
   if (!rc) rc = check_launch();
   return rc;
 }
@@ -978,6 +1018,10 @@ int capture_pair(cglbm_handle *h) {
 }
 
 int compute_fields(cglbm_handle *h, hipStream_t s, int write_kappa) {
+  if (h->clive) {
+    const int rc = flush_compact(h, s);
+    if (rc) return rc;
+  }
   if (h->lattice == LATTICE_D2Q9) {
     const int rc = launch_step2(h, s, 1);
     return rc ? rc : check_launch();
@@ -1144,6 +1188,7 @@ int cglbm_load_state(cglbm_handle *h, const void *src, void *stream) {
   if (!src) return fail(CGLBM_EINVAL, "src must not be NULL");
   size_t pop = 0, aux = 0;
   buffer_sizes(h->storage, h->L.total, &pop, &aux, h->lattice);
+  h->clive = false;  // a resident compact state is replaced by the loaded one
   if (src == h->pop[h->cur]) return CGLBM_OK;
   HIP_TRY(hipMemcpyAsync(h->pop[h->cur], src, pop, hipMemcpyDeviceToDevice, (hipStream_t)stream));
   return CGLBM_OK;
@@ -1281,6 +1326,10 @@ int cglbm_step(cglbm_handle *h, int32_t n_steps, void *stream) {
   if (n_steps < 0) return fail(CGLBM_EINVAL, "n_steps must be >= 0");
   hipStream_t s = (hipStream_t)stream;
   if (effective_schedule(h) == 2) return step_compact(h, n_steps, s);
+  if (h->clive) {
+    const int rc = flush_compact(h, s);
+    if (rc) return rc;
+  }
   int32_t k = 0;
   if (h->use_graph && !h->prof && n_steps >= 2) {
     if (!h->graph[h->cur]) {
@@ -1370,6 +1419,10 @@ int cglbm_set_schedule(cglbm_handle *h, int32_t schedule) {
     return fail(CGLBM_EUNSUPPORTED,
                 "the compact schedule needs D3Q27, FP32 storage (or a mass-exact FP32 or "
                 "16-bit storage with Model D and Q), two buffers and unit higher-order rates");
+  if (h->clive) {
+    const int rc = flush_compact(h, h->cstream);
+    if (rc) return rc;
+  }
   if (schedule != h->schedule) drop_graphs(h);
   h->schedule = schedule;
   // the fused geometry preferred by the schedule (the autotuner's choices);
@@ -1413,6 +1466,10 @@ int cglbm_set_variant(cglbm_handle *h, int32_t v, void *stream) {
   if (!h) return fail(CGLBM_ESTATE, "null handle");
   const int nv = h->lattice == LATTICE_D2Q9 ? kNumV2 : kNumFused;
   if (v < 0 || v >= nv) return fail(CGLBM_EINVAL, "variant %d out of range", v);
+  if (h->clive) {
+    const int rc = flush_compact(h, h->cstream);
+    if (rc) return rc;
+  }
   h->fvar_pop = h->fvar_compact = v;
   return select_variant(h, v, (hipStream_t)stream);
 }
@@ -1424,6 +1481,10 @@ int cglbm_set_wall_mode(cglbm_handle *h, int32_t mode, void *stream) {
   if (!h) return fail(CGLBM_ESTATE, "null handle");
   if (h->lattice != LATTICE_D3Q27) return fail(CGLBM_EUNSUPPORTED, "D2Q9 has no wall modes");
   if (mode < 0 || mode > 3) return fail(CGLBM_EINVAL, "wall mode %d out of range", mode);
+  if (h->clive) {
+    const int rc = flush_compact(h, h->cstream);
+    if (rc) return rc;
+  }
   h->wmode_pop = h->wmode_compact = mode;
   return select_mode(h, h->variant, mode, (hipStream_t)stream);
 }
@@ -1434,7 +1495,27 @@ int cglbm_set_compact_variant(cglbm_handle *h, int32_t v, void *stream) {
   g_err.clear();
   if (!h) return fail(CGLBM_ESTATE, "null handle");
   if (v < 0 || v >= kNumCPull) return fail(CGLBM_EINVAL, "compact variant %d out of range", v);
+  if (h->clive) {
+    const int rc = flush_compact(h, h->cstream);
+    if (rc) return rc;
+  }
   return select_cvariant(h, v, (hipStream_t)stream);
+}
+
+int cglbm_set_resident(cglbm_handle *h, int32_t enable, void *stream) {
+  g_err.clear();
+  if (!h) return fail(CGLBM_ESTATE, "null handle");
+  if (enable != 0 && enable != 1) return fail(CGLBM_EINVAL, "enable must be 0 or 1, not %d", enable);
+  h->resident = enable == 1;
+  return enable ? CGLBM_OK : flush_compact(h, (hipStream_t)stream);
+}
+
+int cglbm_get_resident(const cglbm_handle *h) { return h ? (h->resident ? 1 : 0) : -1; }
+
+int cglbm_sync_state(cglbm_handle *h, void *stream) {
+  g_err.clear();
+  if (!h) return fail(CGLBM_ESTATE, "null handle");
+  return flush_compact(h, (hipStream_t)stream);
 }
 
 int cglbm_compact_variant(const cglbm_handle *h, int32_t *info) {
@@ -1454,6 +1535,10 @@ int cglbm_autotune(cglbm_handle *h, int32_t reps, double *ms_per_variant, void *
   if (reps < 1) return fail(CGLBM_EINVAL, "reps must be >= 1");
   hipStream_t s = (hipStream_t)stream;
   if (h->lattice == LATTICE_D2Q9) return autotune2(h, reps, ms_per_variant, s);
+  if (h->clive) {
+    const int rc = flush_compact(h, s);
+    if (rc) return rc;
+  }
   // the fused kernel is idempotent for a fixed pull: time every variant on
   // the same inputs; the stored state is unchanged afterwards (in place, the
   // variants all write the next state into the one buffer: the call then
