@@ -165,6 +165,9 @@ def test_null_handle_calls_fail_cleanly():
     assert L.cglbm_reduce(None, None, out, 1, None) == -5
     assert L.cglbm_set_wall_mode(None, 0, None) == -5
     assert L.cglbm_get_wall_mode(None) == -1
+    assert L.cglbm_set_resident(None, 1, None) == -5
+    assert L.cglbm_get_resident(None) == -1
+    assert L.cglbm_sync_state(None, None) == -5
 
 
 def test_inplace_layout_restrictions():
