@@ -8,7 +8,8 @@ run without residency:
   the wall stashes at both parities between calls), periodic and walled, in
   the FP32, colour-pair, mass-exact FP32 and 16-bit colour-fraction storages,
   with graph replays and with direct launches: fields, the stored
-  populations (checkpoint) and the FP64 diagnostics;
+  populations (checkpoint) and the FP64 diagnostics; and for a batch of
+  Models A, B, C and Model D without Q;
 * the state is stored before a reader, before a step in another schedule and
   by cglbm_set_resident(0), and a loaded checkpoint replaces it;
 * argument checks of the new entry points."""
@@ -72,6 +73,26 @@ def test_calls_equal_one_long_call(storage, walls, graph):
     assert np.array_equal(s_ref.numpy(), s_res.numpy())
     _same(f_ref, f_res)
     assert np.array_equal(d_ref, d_res)
+
+
+def test_general_models_calls_equal_one_long_call():
+    """Models A, B, C and Model D without Q run schedule 2 through the
+    interface and collide kernels writing compact states."""
+    import dataclasses
+    cases = []
+    for k, (model, use_q) in enumerate(((0, 1), (1, 1), (2, 1), (3, 0))):
+        b, f = _case((17 + 2 * k, 13, 11), R=3.0, u=(0.03, 0.0, 0.01), walls=k % 2)
+        cases.append((dataclasses.replace(b, model=model, use_q=use_q), f))
+    ref = _sim(cases)
+    ref.step(6)
+    f_ref = [gpu_fields(ref, k) for k in range(len(cases))]
+    ref.close()
+    res = _sim(cases, resident=True)
+    for n in (3, 1, 2):
+        res.step(n)
+    f_res = [gpu_fields(res, k) for k in range(len(cases))]
+    res.close()
+    _same(f_ref, f_res)
 
 
 def test_readers_and_other_schedules_store_the_state_first():
