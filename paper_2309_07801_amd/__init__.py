@@ -228,8 +228,10 @@ class Simulation:
         self.stream = stream
         dev = self.device
         self.inplace = bool(inplace)
-        self.pop_a = torch.empty(pop_bytes, dtype=torch.uint8, device=dev)
-        self.pop_b = None if self.inplace else torch.empty(pop_bytes, dtype=torch.uint8, device=dev)
+        # zeroed, so that the padding between boxes (never read or written by
+        # the kernels) is the same in every run and checkpoints compare bytewise
+        self.pop_a = torch.zeros(pop_bytes, dtype=torch.uint8, device=dev)
+        self.pop_b = None if self.inplace else torch.zeros(pop_bytes, dtype=torch.uint8, device=dev)
         self.aux = torch.empty(aux_bytes, dtype=torch.uint8, device=dev)
         self.offsets = self._offsets_host()
         rr = self.pack([np.asarray(a, np.float32) for a in rho_r])

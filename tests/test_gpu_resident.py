@@ -157,3 +157,34 @@ def test_argument_checks():
     assert lib.cglbm_set_resident(sim.h, 2, None) == einval
     assert lib.cglbm_sync_state(sim.h, None) == pkg.CGLBM_OK  # nothing to store
     sim.close()
+
+
+def test_full_size_droplet_256_in_the_bench_geometry():
+    """The 256^3 translating droplet in the autotuned geometry the benchmark
+    times: resident calls of 999, 1 and 1000 steps equal one call of 2000
+    steps bit for bit (stored populations compared on the device)."""
+    import torch
+    import paper_2309_07801_amd as pkg
+    w = WL.translating_droplet()
+    states, geometry = [], None
+    for resident in (False, True):
+        sim = pkg.Simulation([pkg.box_params_of(w.box)], [w.rho_r], [w.rho_b], [w.u],
+                             seed=w.seed, noise=w.noise)
+        if geometry is None:
+            sim.autotune(reps=1)
+            sim.set_schedule(2)
+            geometry = (sim.variant(), sim.compact_variant()["index"])
+        else:
+            sim.set_schedule(2)
+            sim.set_variant(geometry[0])
+            sim.set_compact_variant(geometry[1])
+        assert (sim.variant(), sim.compact_variant()["index"]) == geometry
+        sim.set_resident(resident)
+        for n in ((999, 1, 1000) if resident else (2000,)):
+            sim.step(n)
+        states.append(sim.checkpoint())
+        assert sim.reduce()[0, 12] == 0  # no non-finite values
+        torch.cuda.synchronize()
+        sim.close()
+    print("geometry", geometry)
+    assert torch.equal(states[0], states[1])
